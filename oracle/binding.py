@@ -1,0 +1,247 @@
+"""ctypes binding of the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import ensure_built
+
+__all__ = ["lib", "OracleScene", "philox", "u01", "fresnel", "slab", "snell_cos_t",
+           "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir"]
+
+_lib = None
+
+
+class _Material(C.Structure):
+    _fields_ = [("type", C.c_int32), ("thick_mm", C.c_double), ("bubble_density", C.c_double),
+                ("bubble_rmin_um", C.c_double), ("bubble_rmax_um", C.c_double),
+                ("pane_id", C.c_int32),
+                ("albedo", C.POINTER(C.c_double)), ("n", C.POINTER(C.c_double)),
+                ("k", C.POINTER(C.c_double)), ("alpha_tint", C.POINTER(C.c_double))]
+
+
+class _SceneDesc(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("pos", C.POINTER(C.c_double)),
+                ("vthick_mm", C.POINTER(C.c_double)), ("nt", C.c_int32),
+                ("idx", C.POINTER(C.c_int32)), ("mat", C.POINTER(C.c_int32)),
+                ("n_mat", C.c_int32), ("mats", C.POINTER(_Material)), ("n_tab", C.c_int32),
+                ("tab_lambda_nm", C.POINTER(C.c_double)), ("sun_dir", C.c_double * 3),
+                ("sun_E", C.POINTER(C.c_double)), ("sky_L", C.POINTER(C.c_double))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("spp", C.c_int32), ("max_depth", C.c_int32),
+                ("projection", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
+                ("up", C.c_double * 3), ("vfov_deg", C.c_double), ("ortho_height", C.c_double),
+                ("seed", C.c_uint64), ("job_id", C.c_uint32), ("n_lambda", C.c_int32),
+                ("lambda_nm", C.POINTER(C.c_double)), ("cmf_xyz", C.POINTER(C.c_double)),
+                ("n_bands", C.c_int32), ("tile", C.c_int32), ("beta_threshold", C.c_double),
+                ("use_bvh", C.c_int32), ("n_threads", C.c_int32)]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        so = ensure_built()
+        L = C.CDLL(so)
+        L.orc_philox_batch.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_u01.restype = C.c_double
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_fresnel.argtypes = [C.c_double] * 3 + [C.POINTER(C.c_double)] * 2
+        L.orc_slab_batch.argtypes = [C.c_int64] + [C.c_void_p] * 8
+        L.orc_snell_cos_t.restype = C.c_double
+        L.orc_snell_cos_t.argtypes = [C.c_double, C.c_double]
+        L.orc_scene_create.restype = C.c_void_p
+        L.orc_scene_create.argtypes = [C.POINTER(_SceneDesc)]
+        L.orc_scene_destroy.argtypes = [C.c_void_p]
+        L.orc_scene_teps.restype = C.c_double
+        L.orc_scene_teps.argtypes = [C.c_void_p]
+        L.orc_bvh_depth.restype = C.c_int32
+        L.orc_bvh_depth.argtypes = [C.c_void_p]
+        L.orc_intersect.argtypes = [C.c_void_p, C.c_int32, C.c_int64] + [C.c_void_p] * 7
+        L.orc_shadow.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                 C.c_double, C.c_void_p]
+        L.orc_render.restype = C.c_int
+        L.orc_render.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_void_p, C.c_void_p]
+        L.orc_render_pixels.restype = C.c_int
+        L.orc_render_pixels.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int64, C.c_void_p,
+                                        C.c_void_p]
+        L.orc_camera_ray.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_double,
+                                     C.c_double, C.c_void_p, C.c_void_p]
+        L.orc_cosine_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_void_p]
+        L.orc_spec_to_xyz.argtypes = [C.c_int64, C.c_int32] + [C.c_void_p] * 4
+        _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------------------
+def philox(ctr, key):
+    """ctr: (n, 4) uint32, key: (n, 2) uint32 -> (n, 4) uint32."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(len(ctr), ctr.ctypes.data, key.ctypes.data, out.ctypes.data)
+    return out
+
+
+def u01(x):
+    return lib().orc_u01(int(x))
+
+
+def fresnel(cos_i, n, k):
+    rs, rp = C.c_double(), C.c_double()
+    lib().orc_fresnel(float(cos_i), float(n), float(k), C.byref(rs), C.byref(rp))
+    return rs.value, rp.value
+
+
+def snell_cos_t(cos_i, n):
+    return lib().orc_snell_cos_t(float(cos_i), float(n))
+
+
+def slab(cos_i, lambda_nm, d_mm, n, k, alpha_tint):
+    """Vectorised thin-slab (R, T); arguments broadcast."""
+    arrs = np.broadcast_arrays(*[np.asarray(a, dtype=np.float64) for a in
+                                 (cos_i, lambda_nm, d_mm, n, k, alpha_tint)])
+    shape = arrs[0].shape
+    flat = [np.ascontiguousarray(a.reshape(-1)) for a in arrs]
+    R = np.empty(flat[0].size)
+    T = np.empty(flat[0].size)
+    lib().orc_slab_batch(flat[0].size, *[a.ctypes.data for a in flat], R.ctypes.data, T.ctypes.data)
+    return R.reshape(shape), T.reshape(shape)
+
+
+class OracleScene:
+    """Owns the C scene; arrays are converted to float64 (exact for float32)."""
+
+    def __init__(self, scene):
+        self._keep = []
+        f64 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        pos = f64(scene.pos.reshape(-1))
+        vth = f64(scene.vthick)
+        idx = np.ascontiguousarray(scene.idx.reshape(-1), dtype=np.int32)
+        mat = np.ascontiguousarray(scene.mat, dtype=np.int32)
+        tab = f64(scene.tab_lambda)
+        mats = (_Material * max(1, len(scene.materials)))()
+        for i, m in enumerate(scene.materials):
+            arrs = [f64(m.albedo), f64(m.n), f64(m.k), f64(m.alpha_tint)]
+            self._keep += arrs
+            mats[i] = _Material(m.type, float(m.thick_mm), float(m.bubble_density),
+                                float(m.bubble_rmin_um), float(m.bubble_rmax_um), int(m.pane_id),
+                                *[_dp(a) for a in arrs])
+        sunE, skyL = f64(scene.sun_E), f64(scene.sky_L)
+        self._keep += [pos, vth, idx, mat, tab, mats, sunE, skyL]
+        d = _SceneDesc(len(scene.pos), _dp(pos), _dp(vth), int(scene.idx.shape[0]), _ip(idx),
+                       _ip(mat), len(scene.materials), mats, len(tab), _dp(tab),
+                       (C.c_double * 3)(*[float(x) for x in scene.sun_dir]), _dp(sunE), _dp(skyL))
+        self.ptr = lib().orc_scene_create(C.byref(d))
+        if not self.ptr:
+            raise ValueError("oracle rejected the scene description")
+        self.nt = int(scene.idx.shape[0])
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().orc_scene_destroy(self.ptr)
+            self.ptr = None
+
+    @property
+    def teps(self):
+        return lib().orc_scene_teps(self.ptr)
+
+    @property
+    def bvh_depth(self):
+        return lib().orc_bvh_depth(self.ptr)
+
+    def intersect(self, o, d, skip=None, use_bvh=True):
+        o = np.ascontiguousarray(o, dtype=np.float64).reshape(-1, 3)
+        d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
+        m = len(o)
+        sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.int32)
+        t = np.empty(m)
+        tri = np.empty(m, dtype=np.int32)
+        u = np.empty(m)
+        v = np.empty(m)
+        lib().orc_intersect(self.ptr, int(use_bvh), m, o.ctypes.data, d.ctypes.data,
+                            None if sk is None else sk.ctypes.data, t.ctypes.data,
+                            tri.ctypes.data, u.ctypes.data, v.ctypes.data)
+        return t, tri, u, v
+
+    def shadow(self, o, lambda_nm, skip=None, use_bvh=True):
+        o = np.ascontiguousarray(o, dtype=np.float64).reshape(-1, 3)
+        sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.int32)
+        T = np.empty(len(o))
+        lib().orc_shadow(self.ptr, int(use_bvh), len(o), o.ctypes.data,
+                         None if sk is None else sk.ctypes.data, float(lambda_nm), T.ctypes.data)
+        return T
+
+
+def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None):
+    cam = settings.camera
+    lam = np.ascontiguousarray(settings.lambda_nm, dtype=np.float64)
+    cmf = np.ascontiguousarray(settings.cmf, dtype=np.float64).reshape(-1)
+    p = _Params(cam.W, cam.H, settings.spp, settings.max_depth, cam.projection,
+                (C.c_double * 3)(*cam.eye), (C.c_double * 3)(*cam.target),
+                (C.c_double * 3)(*cam.up), float(cam.vfov_deg), float(cam.ortho_height),
+                int(settings.seed), int(settings.job_id), len(lam), _dp(lam), _dp(cmf),
+                int(settings.n_bands if n_bands is None else n_bands), int(tile),
+                float(settings.beta_threshold), int(use_bvh), int(n_threads))
+    return p, (lam, cmf)
+
+
+def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None):
+    """Full image -> (spec (H, W, nl) float64, xyz (H, W, 3) float64)."""
+    p, keep = _params(settings, use_bvh, tile, n_threads, n_bands)
+    W, H, nl = settings.camera.W, settings.camera.H, len(settings.lambda_nm)
+    spec = np.empty((H, W, nl))
+    xyz = np.empty((H, W, 3))
+    rc = lib().orc_render(oscene.ptr, C.byref(p), spec.ctypes.data, xyz.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle render rejected the parameters")
+    return spec, xyz
+
+
+def render_pixels(oscene, settings, pixels, use_bvh=True, n_threads=0):
+    """Selected linear pixel indices -> spec (m, nl) float64."""
+    p, keep = _params(settings, use_bvh, 16, n_threads)
+    px = np.ascontiguousarray(pixels, dtype=np.int32)
+    spec = np.empty((len(px), len(settings.lambda_nm)))
+    rc = lib().orc_render_pixels(oscene.ptr, C.byref(p), len(px), px.ctypes.data, spec.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle render rejected the parameters")
+    return spec
+
+
+def camera_ray(settings, i, j, u0, u1):
+    p, keep = _params(settings)
+    o = np.empty(3)
+    d = np.empty(3)
+    lib().orc_camera_ray(C.byref(p), int(i), int(j), float(u0), float(u1), o.ctypes.data,
+                         d.ctypes.data)
+    return o, d
+
+
+def cosine_dir(n, u1, u2):
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    d = np.empty(3)
+    lib().orc_cosine_dir(n.ctypes.data, float(u1), float(u2), d.ctypes.data)
+    return d
+
+
+def spec_to_xyz(spec, lambda_nm, cmf):
+    spec = np.ascontiguousarray(spec, dtype=np.float64)
+    nl = spec.shape[-1]
+    lam = np.ascontiguousarray(lambda_nm, dtype=np.float64)
+    cm = np.ascontiguousarray(cmf, dtype=np.float64).reshape(-1)
+    out = np.empty(spec.shape[:-1] + (3,))
+    lib().orc_spec_to_xyz(spec.size // nl, nl, lam.ctypes.data, cm.ctypes.data, spec.ctypes.data,
+                          out.ctypes.data)
+    return out

@@ -1,0 +1,802 @@
+/*
+ * sdm_oracle.c -- plain FP64 CPU oracle of the spectral path tracer.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no code
+ * with the HIP library.
+ *
+ * Structure follows the paper:
+ *   Sec. 3.1  inverse ray tracing: a ray per pixel, closest hit, a shadow ray
+ *             toward each light, reflected/refracted secondaries, stop after a
+ *             fixed number of bounces or below an energy threshold;
+ *   eq. (3)   light sum over the directional sun;
+ *   eq. (1)   glass optical constants n + ik, Fresnel at the interfaces;
+ *   Sec. 6    per-location thickness (per-vertex map);
+ *   Sec. 4/5  every pixel and every wavelength is computed on its own; work
+ *             items are (pixel tile x spectral band) pulled dynamically.
+ * Monte Carlo conventions (random-number mapping, camera, sampling, depth)
+ * are readings; each one is stated where it is used.
+ */
+#include "sdm_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box with two */
+/* 32x32->64 multiplies; the key is bumped by the Weyl constants each round.  */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void orc_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
+}
+
+/* Reading: uniform in [0, 1) from the top 24 bits, exact in float and double. */
+double orc_u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+/* Reading: counter = (pixel, sample, (vertex + 1) << 16 | call, job), key =
+ * the 64-bit seed; the wavelength is not part of the counter, so all
+ * wavelengths of a (pixel, sample) draw the same numbers. */
+static void draw4(uint64_t seed, uint32_t job, uint32_t pixel, uint32_t sample, int vertex,
+                  uint32_t call, double u[4])
+{
+    uint32_t ctr[4] = {pixel, sample, ((uint32_t)(vertex + 1) << 16) | call, job};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    for (int i = 0; i < 4; ++i) u[i] = orc_u01(x[i]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Glass optics                                                               */
+/* ------------------------------------------------------------------------- */
+/* Fresnel amplitude coefficients air -> n~ = n + ik (eq. (1)); cos of the
+ * complex refraction angle from Snell's law on the principal branch. */
+void orc_fresnel(double cos_i, double n, double k, double *Rs, double *Rp)
+{
+    if (cos_i > 1.0) cos_i = 1.0;
+    if (cos_i < 0.0) cos_i = 0.0;
+    double complex nt = n + I * k;
+    double sin2 = 1.0 - cos_i * cos_i;
+    double complex ct = csqrt(1.0 - sin2 / (nt * nt));
+    double complex rs = (cos_i - nt * ct) / (cos_i + nt * ct);
+    double complex rp = (nt * cos_i - ct) / (nt * cos_i + ct);
+    *Rs = creal(rs * conj(rs));
+    *Rp = creal(rp * conj(rp));
+}
+
+/* Reading: the in-glass path length uses the real Snell angle. */
+double orc_snell_cos_t(double cos_i, double n)
+{
+    double s2 = 1.0 - cos_i * cos_i;
+    if (s2 < 0.0) s2 = 0.0;
+    double st = sqrt(s2) / n;
+    double c2 = 1.0 - st * st;
+    return c2 > 0.0 ? sqrt(c2) : 0.0;
+}
+
+/* One polarisation of a slab with interface reflectance r and one-pass
+ * internal transmittance tau: sum of the incoherent bounce series. */
+static void slab_pol(double r, double tau, double *R, double *T)
+{
+    if (r >= 1.0) { *R = 1.0; *T = 0.0; return; }
+    double den = 1.0 - r * r * tau * tau;
+    *R = r + (1.0 - r) * (1.0 - r) * r * tau * tau / den;
+    *T = (1.0 - r) * (1.0 - r) * tau / den;
+}
+
+/* Reading: Beer-Lambert absorption alpha = 4 pi k / lambda + alpha_tint, path
+ * d / cos(theta_t); the exit face reflects with the entry-face reflectance;
+ * the reported slab R, T are the averages of the s and p polarisations. */
+void orc_slab(double cos_i, double lambda_nm, double d_mm, double n, double k,
+              double alpha_tint, double *R, double *T)
+{
+    double Rs, Rp;
+    orc_fresnel(cos_i, n, k, &Rs, &Rp);
+    double ct = orc_snell_cos_t(cos_i, n);
+    double alpha = 4.0 * PI * k / (lambda_nm * 1e-6) + alpha_tint;
+    double ad = alpha * d_mm;
+    double tau = (ad == 0.0) ? 1.0 : (ct > 0.0 ? exp(-ad / ct) : 0.0);
+    double Rs_, Ts_, Rp_, Tp_;
+    slab_pol(Rs, tau, &Rs_, &Ts_);
+    slab_pol(Rp, tau, &Rp_, &Tp_);
+    *R = 0.5 * (Rs_ + Rp_);
+    *T = 0.5 * (Ts_ + Tp_);
+}
+
+void orc_slab_batch(int64_t m, const double *cos_i, const double *lambda_nm, const double *d_mm,
+                    const double *n, const double *k, const double *alpha_tint, double *R,
+                    double *T)
+{
+    for (int64_t i = 0; i < m; ++i)
+        orc_slab(cos_i[i], lambda_nm[i], d_mm[i], n[i], k[i], alpha_tint[i], R + i, T + i);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scene                                                                      */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t left, right; /* children, or -1 for a leaf */
+    int32_t first, count;
+} onode;
+
+typedef struct {
+    int32_t type;
+    double thick_mm;
+    double *albedo, *n, *k, *tint; /* owned copies [n_tab] */
+} omat;
+
+struct orc_scene {
+    int32_t nv, nt, n_mat, n_tab;
+    double *pos, *vthick, *ng;
+    int32_t *idx, *mat;
+    omat *mats;
+    double *tab_lambda, *sun_E, *sky_L;
+    double sun[3];
+    double teps;
+    onode *nodes;
+    int32_t n_nodes;
+    int32_t *order; /* triangle ids in leaf order */
+    int32_t depth;
+};
+
+static double *dup_d(const double *p, int64_t n)
+{
+    if (!p || n <= 0) return NULL;
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    memcpy(q, p, sizeof(double) * (size_t)n);
+    return q;
+}
+
+static void sub3(const double *a, const double *b, double *r) { for (int i = 0; i < 3; ++i) r[i] = a[i] - b[i]; }
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *r)
+{
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static void normalize3(double *a)
+{
+    double l = sqrt(dot3(a, a));
+    if (l > 0) { a[0] /= l; a[1] /= l; a[2] /= l; }
+}
+
+/* Median-split BVH (leaves of at most 4 triangles).  Any acceleration
+ * structure gives the same closest hit under the tie rule below; this one is
+ * kept simple and is checked against brute force. */
+typedef struct { double key; int32_t id; } keyed;
+static int cmp_keyed(const void *a, const void *b)
+{
+    const keyed *x = (const keyed *)a, *y = (const keyed *)b;
+    if (x->key < y->key) return -1;
+    if (x->key > y->key) return 1;
+    return (x->id < y->id) ? -1 : (x->id > y->id);
+}
+
+static int32_t bvh_build(orc_scene *s, int32_t first, int32_t count, double pad, int depth)
+{
+    int32_t me = s->n_nodes++;
+    onode *nd = &s->nodes[me];
+    for (int a = 0; a < 3; ++a) { nd->lo[a] = INFINITY; nd->hi[a] = -INFINITY; }
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t i = first; i < first + count; ++i) {
+        int32_t t = s->order[i];
+        for (int c = 0; c < 3; ++c) {
+            const double *p = s->pos + 3 * s->idx[3 * t + c];
+            for (int a = 0; a < 3; ++a) {
+                if (p[a] < nd->lo[a]) nd->lo[a] = p[a];
+                if (p[a] > nd->hi[a]) nd->hi[a] = p[a];
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            double cen = (s->pos[3 * s->idx[3 * t] + a] + s->pos[3 * s->idx[3 * t + 1] + a] +
+                          s->pos[3 * s->idx[3 * t + 2] + a]) / 3.0;
+            if (cen < clo[a]) clo[a] = cen;
+            if (cen > chi[a]) chi[a] = cen;
+        }
+    }
+    for (int a = 0; a < 3; ++a) { nd->lo[a] -= pad; nd->hi[a] += pad; }
+    if (depth + 1 > s->depth) s->depth = depth + 1;
+    if (count <= 4) {
+        nd->left = nd->right = -1;
+        nd->first = first;
+        nd->count = count;
+        return me;
+    }
+    int axis = 0;
+    for (int a = 1; a < 3; ++a) if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+    keyed *tmp = (keyed *)malloc(sizeof(keyed) * (size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        int32_t t = s->order[first + i];
+        tmp[i].key = s->pos[3 * s->idx[3 * t] + axis] + s->pos[3 * s->idx[3 * t + 1] + axis] +
+                     s->pos[3 * s->idx[3 * t + 2] + axis];
+        tmp[i].id = t;
+    }
+    qsort(tmp, (size_t)count, sizeof(keyed), cmp_keyed);
+    for (int32_t i = 0; i < count; ++i) s->order[first + i] = tmp[i].id;
+    free(tmp);
+    int32_t half = count / 2;
+    nd->first = nd->count = 0;
+    int32_t l = bvh_build(s, first, half, pad, depth + 1);
+    int32_t r = bvh_build(s, first + half, count - half, pad, depth + 1);
+    s->nodes[me].left = l;
+    s->nodes[me].right = r;
+    return me;
+}
+
+orc_scene *orc_scene_create(const orc_scene_desc *d)
+{
+    if (!d || d->nv < 0 || d->nt < 0 || d->n_tab < 1 || !d->tab_lambda_nm || !d->sun_E || !d->sky_L)
+        return NULL;
+    if (d->nt > 0 && (!d->pos || !d->idx || !d->mat || !d->mats || d->n_mat < 1)) return NULL;
+    for (int32_t t = 0; t < d->nt; ++t) {
+        for (int c = 0; c < 3; ++c)
+            if (d->idx[3 * t + c] < 0 || d->idx[3 * t + c] >= d->nv) return NULL;
+        if (d->mat[t] < 0 || d->mat[t] >= d->n_mat) return NULL;
+    }
+    for (int32_t m = 0; m < d->n_mat; ++m) {
+        const orc_material *mm = &d->mats[m];
+        if (mm->type == ORC_LAMBERT && !mm->albedo) return NULL;
+        if (mm->type != ORC_LAMBERT && (!mm->n || !mm->k)) return NULL;
+    }
+    orc_scene *s = (orc_scene *)calloc(1, sizeof(orc_scene));
+    s->nv = d->nv; s->nt = d->nt; s->n_mat = d->n_mat; s->n_tab = d->n_tab;
+    s->pos = dup_d(d->pos, 3 * (int64_t)d->nv);
+    s->vthick = dup_d(d->vthick_mm, d->nv);
+    s->idx = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(d->nt + 1));
+    s->mat = (int32_t *)malloc(sizeof(int32_t) * (size_t)(d->nt + 1));
+    if (d->nt) {
+        memcpy(s->idx, d->idx, sizeof(int32_t) * 3 * (size_t)d->nt);
+        memcpy(s->mat, d->mat, sizeof(int32_t) * (size_t)d->nt);
+    }
+    s->mats = (omat *)calloc((size_t)(d->n_mat + 1), sizeof(omat));
+    for (int32_t m = 0; m < d->n_mat; ++m) {
+        const orc_material *mm = &d->mats[m];
+        s->mats[m].type = mm->type;
+        s->mats[m].thick_mm = mm->thick_mm;
+        s->mats[m].albedo = dup_d(mm->albedo, d->n_tab);
+        s->mats[m].n = dup_d(mm->n, d->n_tab);
+        s->mats[m].k = dup_d(mm->k, d->n_tab);
+        s->mats[m].tint = dup_d(mm->alpha_tint, d->n_tab);
+    }
+    s->tab_lambda = dup_d(d->tab_lambda_nm, d->n_tab);
+    s->sun_E = dup_d(d->sun_E, d->n_tab);
+    s->sky_L = dup_d(d->sky_L, d->n_tab);
+    for (int a = 0; a < 3; ++a) s->sun[a] = d->sun_dir[a];
+    /* geometric normals and the self-intersection epsilon */
+    s->ng = (double *)malloc(sizeof(double) * 3 * (size_t)(d->nt + 1));
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t t = 0; t < d->nt; ++t) {
+        const double *p0 = s->pos + 3 * s->idx[3 * t], *p1 = s->pos + 3 * s->idx[3 * t + 1],
+                     *p2 = s->pos + 3 * s->idx[3 * t + 2];
+        double e1[3], e2[3];
+        sub3(p1, p0, e1);
+        sub3(p2, p0, e2);
+        cross3(e1, e2, s->ng + 3 * t);
+        normalize3(s->ng + 3 * t);
+    }
+    for (int32_t v = 0; v < d->nv; ++v)
+        for (int a = 0; a < 3; ++a) {
+            if (s->pos[3 * v + a] < lo[a]) lo[a] = s->pos[3 * v + a];
+            if (s->pos[3 * v + a] > hi[a]) hi[a] = s->pos[3 * v + a];
+        }
+    double diag = 0.0;
+    if (d->nv > 0) {
+        double e[3];
+        sub3(hi, lo, e);
+        diag = sqrt(dot3(e, e));
+    }
+    /* Reading: hits are accepted for t > 1e-6 x scene diagonal. */
+    s->teps = 1e-6 * diag;
+    s->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(d->nt + 1));
+    for (int32_t t = 0; t < d->nt; ++t) s->order[t] = t;
+    s->nodes = (onode *)calloc((size_t)(2 * d->nt + 2), sizeof(onode));
+    s->n_nodes = 0;
+    if (d->nt > 0) bvh_build(s, 0, d->nt, 1e-9 * (diag + 1.0), 0);
+    return s;
+}
+
+void orc_scene_destroy(orc_scene *s)
+{
+    if (!s) return;
+    for (int32_t m = 0; m < s->n_mat; ++m) {
+        free(s->mats[m].albedo); free(s->mats[m].n); free(s->mats[m].k); free(s->mats[m].tint);
+    }
+    free(s->mats); free(s->pos); free(s->vthick); free(s->ng); free(s->idx); free(s->mat);
+    free(s->tab_lambda); free(s->sun_E); free(s->sky_L); free(s->nodes); free(s->order);
+    free(s);
+}
+
+double orc_scene_teps(const orc_scene *s) { return s->teps; }
+int32_t orc_bvh_depth(const orc_scene *s) { return s->depth; }
+
+/* ------------------------------------------------------------------------- */
+/* Intersection                                                               */
+/* ------------------------------------------------------------------------- */
+/* Moeller-Trumbore (1997): two-sided, edges inclusive (u, v >= 0, u + v <= 1). */
+static int tri_hit(const orc_scene *s, int32_t t, const double *o, const double *d, double *tt,
+                   double *uu, double *vv)
+{
+    const double *p0 = s->pos + 3 * s->idx[3 * t], *p1 = s->pos + 3 * s->idx[3 * t + 1],
+                 *p2 = s->pos + 3 * s->idx[3 * t + 2];
+    double e1[3], e2[3], pv[3], sv[3], qv[3];
+    sub3(p1, p0, e1);
+    sub3(p2, p0, e2);
+    cross3(d, e2, pv);
+    double det = dot3(e1, pv);
+    if (det == 0.0) return 0;
+    double inv = 1.0 / det;
+    sub3(o, p0, sv);
+    double u = dot3(sv, pv) * inv;
+    if (u < 0.0 || u > 1.0) return 0;
+    cross3(sv, e1, qv);
+    double v = dot3(d, qv) * inv;
+    if (v < 0.0 || u + v > 1.0) return 0;
+    *tt = dot3(e2, qv) * inv;
+    *uu = u;
+    *vv = v;
+    return 1;
+}
+
+typedef struct { double t, u, v; int32_t tri; } ohit;
+
+/* Reading: the closest accepted hit wins; an exact tie in t goes to the
+ * smaller triangle index, which makes the result independent of the
+ * acceleration structure. */
+static void consider(const orc_scene *s, int32_t t, const double *o, const double *d, int32_t skip,
+                     ohit *h)
+{
+    if (t == skip) return;
+    double tt, u, v;
+    if (!tri_hit(s, t, o, d, &tt, &u, &v)) return;
+    if (!(tt > s->teps)) return;
+    if (tt < h->t || (tt == h->t && t < h->tri)) { h->t = tt; h->u = u; h->v = v; h->tri = t; }
+}
+
+static int box_overlap(const onode *n, const double *o, const double *d, double tlo, double thi)
+{
+    double a = -INFINITY, b = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] == 0.0) {
+            if (o[i] < n->lo[i] || o[i] > n->hi[i]) return 0;
+            continue;
+        }
+        double t1 = (n->lo[i] - o[i]) / d[i], t2 = (n->hi[i] - o[i]) / d[i];
+        double mn = t1 < t2 ? t1 : t2, mx = t1 < t2 ? t2 : t1;
+        if (mn > a) a = mn;
+        if (mx < b) b = mx;
+    }
+    return a <= b && b >= tlo && a <= thi;
+}
+
+static ohit closest(const orc_scene *s, int use_bvh, const double *o, const double *d, int32_t skip)
+{
+    ohit h = {INFINITY, 0, 0, -1};
+    if (s->nt == 0) return h;
+    if (!use_bvh) {
+        for (int32_t t = 0; t < s->nt; ++t) consider(s, t, o, d, skip, &h);
+        return h;
+    }
+    int32_t stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const onode *n = &s->nodes[stack[--sp]];
+        if (!box_overlap(n, o, d, s->teps, h.t)) continue;
+        if (n->left < 0) {
+            for (int32_t i = n->first; i < n->first + n->count; ++i) consider(s, s->order[i], o, d, skip, &h);
+        } else {
+            stack[sp++] = n->left;
+            stack[sp++] = n->right;
+        }
+    }
+    return h;
+}
+
+static double interp_tab(const orc_scene *s, const double *ys, double x);
+
+/* Glass thickness at barycentric (u, v): the per-vertex distribution map. */
+static double thickness_at(const orc_scene *s, int32_t t, double u, double v)
+{
+    const omat *m = &s->mats[s->mat[t]];
+    if (!s->vthick) return m->thick_mm;
+    return (1.0 - u - v) * s->vthick[s->idx[3 * t]] + u * s->vthick[s->idx[3 * t + 1]] +
+           v * s->vthick[s->idx[3 * t + 2]];
+}
+
+/* Per-render material values at the render wavelengths. */
+typedef struct {
+    int32_t nl;
+    double *lam, *rho, *n, *k, *tint, *E, *Lsky; /* rho/n/k/tint are [n_mat][nl] */
+} spectra;
+
+/* Sun transmittance along x + t * sun (t > teps, t unbounded): zero if any
+ * opaque triangle is crossed, else the product of the slab transmittances of
+ * every pane crossed (Sec. 3.1 shadow rays; eq. (3)). */
+static double shadow_T(const orc_scene *s, const spectra *sp, int use_bvh, const double *x,
+                       int32_t skip, int li, double lambda_nm)
+{
+    double T = 1.0;
+    const double *d = s->sun;
+    int32_t stack[256];
+    int top = 0;
+    if (s->nt == 0) return 1.0;
+    if (use_bvh) stack[top++] = 0;
+    int32_t brute = use_bvh ? -1 : 0;
+    for (;;) {
+        int32_t first, count;
+        if (brute >= 0) {
+            if (brute >= s->nt) break;
+            first = brute; count = 1; brute++;
+        } else {
+            if (top == 0) break;
+            const onode *n = &s->nodes[stack[--top]];
+            if (!box_overlap(n, x, d, s->teps, INFINITY)) continue;
+            if (n->left >= 0) { stack[top++] = n->left; stack[top++] = n->right; continue; }
+            first = n->first; count = n->count;
+        }
+        for (int32_t i = first; i < first + count; ++i) {
+            int32_t t = use_bvh ? s->order[i] : i;
+            if (t == skip) continue;
+            double tt, u, v;
+            if (!tri_hit(s, t, x, d, &tt, &u, &v) || !(tt > s->teps)) continue;
+            const omat *m = &s->mats[s->mat[t]];
+            if (m->type == ORC_LAMBERT) return 0.0;
+            double R, Tr;
+            double c = fabs(dot3(d, s->ng + 3 * t));
+            int32_t mi = s->mat[t];
+            orc_slab(c, lambda_nm, thickness_at(s, t, u, v), sp->n[mi * sp->nl + li],
+                     sp->k[mi * sp->nl + li], sp->tint[mi * sp->nl + li], &R, &Tr);
+            T *= Tr;
+        }
+    }
+    return T;
+}
+
+void orc_intersect(const orc_scene *s, int32_t use_bvh, int64_t m, const double *o, const double *dir,
+                   const int32_t *skip, double *t, int32_t *tri, double *u, double *v)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+        ohit h = closest(s, use_bvh, o + 3 * i, dir + 3 * i, skip ? skip[i] : -1);
+        t[i] = h.t; tri[i] = h.tri; u[i] = h.u; v[i] = h.v;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tables                                                                     */
+/* ------------------------------------------------------------------------- */
+/* Reading: tables are linearly interpolated to the render wavelengths and
+ * held constant beyond their ends. */
+static double interp_tab(const orc_scene *s, const double *ys, double x)
+{
+    const double *xs = s->tab_lambda;
+    int n = s->n_tab;
+    if (n == 1 || x <= xs[0]) return ys[0];
+    if (x >= xs[n - 1]) return ys[n - 1];
+    int i = 0;
+    while (xs[i + 1] < x) ++i;
+    double w = (x - xs[i]) / (xs[i + 1] - xs[i]);
+    return (1.0 - w) * ys[i] + w * ys[i + 1];
+}
+
+static void spectra_make(const orc_scene *s, const orc_render_params *p, spectra *sp)
+{
+    int nl = p->n_lambda, nm = s->n_mat;
+    sp->nl = nl;
+    sp->lam = (double *)malloc(sizeof(double) * (size_t)nl);
+    sp->rho = (double *)calloc((size_t)(nm * nl + 1), sizeof(double));
+    sp->n = (double *)calloc((size_t)(nm * nl + 1), sizeof(double));
+    sp->k = (double *)calloc((size_t)(nm * nl + 1), sizeof(double));
+    sp->tint = (double *)calloc((size_t)(nm * nl + 1), sizeof(double));
+    sp->E = (double *)malloc(sizeof(double) * (size_t)nl);
+    sp->Lsky = (double *)malloc(sizeof(double) * (size_t)nl);
+    for (int i = 0; i < nl; ++i) {
+        double x = p->lambda_nm[i];
+        sp->lam[i] = x;
+        sp->E[i] = interp_tab(s, s->sun_E, x);
+        sp->Lsky[i] = interp_tab(s, s->sky_L, x);
+        for (int m = 0; m < nm; ++m) {
+            const omat *mm = &s->mats[m];
+            if (mm->albedo) sp->rho[m * nl + i] = interp_tab(s, mm->albedo, x);
+            if (mm->n) sp->n[m * nl + i] = interp_tab(s, mm->n, x);
+            if (mm->k) sp->k[m * nl + i] = interp_tab(s, mm->k, x);
+            if (mm->tint) sp->tint[m * nl + i] = interp_tab(s, mm->tint, x);
+        }
+    }
+}
+
+static void spectra_free(spectra *sp)
+{
+    free(sp->lam); free(sp->rho); free(sp->n); free(sp->k); free(sp->tint); free(sp->E); free(sp->Lsky);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Path tracing                                                               */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double eye[3], f[3], r[3], u[3];
+    double th, aspect, oh;
+} camera;
+
+static void camera_make(const orc_render_params *p, camera *c)
+{
+    for (int a = 0; a < 3; ++a) c->eye[a] = p->eye[a];
+    sub3(p->target, p->eye, c->f);
+    normalize3(c->f);
+    cross3(c->f, p->up, c->r);
+    normalize3(c->r);
+    cross3(c->r, c->f, c->u);
+    c->th = tan(0.5 * p->vfov_deg * PI / 180.0);
+    c->aspect = (double)p->W / (double)p->H;
+    c->oh = 0.5 * p->ortho_height;
+}
+
+/* Reading: image point (x, y) = ((i + u0) / W, (j + u1) / H), row j counted
+ * from the top.  Pinhole: from the eye through the image plane at unit
+ * distance; orthographic: rays orthogonal to the image plane (Sec. 3.1). */
+static void camera_ray(const orc_render_params *p, const camera *c, int i, int j, const double *u,
+                       double *o, double *d)
+{
+    double x = (i + u[0]) / p->W, y = (j + u[1]) / p->H;
+    double a = 2.0 * x - 1.0, b = 1.0 - 2.0 * y;
+    if (p->projection == 1) {
+        for (int k = 0; k < 3; ++k) {
+            o[k] = c->eye[k] + a * c->oh * c->aspect * c->r[k] + b * c->oh * c->u[k];
+            d[k] = c->f[k];
+        }
+        return;
+    }
+    for (int k = 0; k < 3; ++k) {
+        o[k] = c->eye[k];
+        d[k] = c->f[k] + a * c->th * c->aspect * c->r[k] + b * c->th * c->u[k];
+    }
+    normalize3(d);
+}
+
+/* Orthonormal basis around unit n (Duff et al., JCGT 2017). */
+static void onb(const double *n, double *t1, double *t2)
+{
+    double sign = copysign(1.0, n[2]);
+    double a = -1.0 / (sign + n[2]);
+    double b = n[0] * n[1] * a;
+    t1[0] = 1.0 + sign * n[0] * n[0] * a; t1[1] = sign * b; t1[2] = -sign * n[0];
+    t2[0] = b; t2[1] = sign + n[1] * n[1] * a; t2[2] = -n[1];
+}
+
+typedef struct {
+    const orc_scene *s;
+    const orc_render_params *p;
+    const spectra *sp;
+    camera cam;
+} rctx;
+
+void orc_camera_ray(const orc_render_params *p, int32_t i, int32_t j, double u0, double u1,
+                    double o[3], double d[3])
+{
+    camera c;
+    camera_make(p, &c);
+    double u[2] = {u0, u1};
+    camera_ray(p, &c, i, j, u, o, d);
+}
+
+/* Reading: cosine-weighted bounce (Malley's method: uniform disk point
+ * lifted to the hemisphere) in the basis of onb(). */
+static void cosine_dir(const double *ns, double u1, double u2, double *d)
+{
+    double t1[3], t2[3];
+    onb(ns, t1, t2);
+    double rr = sqrt(u1), phi = 2.0 * PI * u2, lz = sqrt(1.0 - u1);
+    double lx = rr * cos(phi), ly = rr * sin(phi);
+    for (int a = 0; a < 3; ++a) d[a] = lx * t1[a] + ly * t2[a] + lz * ns[a];
+}
+
+void orc_cosine_dir(const double n[3], double u1, double u2, double d[3]) { cosine_dir(n, u1, u2, d); }
+
+/* One (pixel, sample, wavelength) path estimate. */
+static double path_radiance(const rctx *c, int i, int j, int smp, int li)
+{
+    const orc_scene *s = c->s;
+    const orc_render_params *p = c->p;
+    const spectra *sp = c->sp;
+    uint32_t pixel = (uint32_t)(j * p->W + i);
+    double u[4], o[3], d[3];
+    draw4(p->seed, p->job_id, pixel, (uint32_t)smp, -1, 0, u);
+    camera_ray(p, &c->cam, i, j, u, o, d);
+    double lambda = sp->lam[li];
+    double beta = 1.0, L = 0.0;
+    int32_t skip = -1;
+    /* Reading: vertices 0 .. max_depth-1 are shaded; the last one does its
+     * light sum but traces no continuation; no Russian roulette. */
+    for (int vtx = 0; vtx < p->max_depth; ++vtx) {
+        ohit h = closest(s, p->use_bvh, o, d, skip);
+        if (h.tri < 0) {
+            /* Reading: every escaping ray sees the uniform sky; the sun is a
+             * delta light reached only through the shadow rays. */
+            L += beta * sp->Lsky[li];
+            break;
+        }
+        double x[3];
+        for (int a = 0; a < 3; ++a) x[a] = o[a] + h.t * d[a];
+        draw4(p->seed, p->job_id, pixel, (uint32_t)smp, vtx, 0, u);
+        int32_t mi = s->mat[h.tri];
+        const double *ng = s->ng + 3 * h.tri;
+        if (s->mats[mi].type == ORC_LAMBERT) {
+            double ns[3] = {ng[0], ng[1], ng[2]};
+            if (dot3(ns, d) > 0.0) { ns[0] = -ns[0]; ns[1] = -ns[1]; ns[2] = -ns[2]; }
+            double rho = sp->rho[mi * sp->nl + li];
+            double cs = dot3(ns, s->sun);
+            if (cs > 0.0) {
+                double T = shadow_T(s, sp, p->use_bvh, x, h.tri, li, lambda);
+                /* eq. (3): Lambert BRDF rho / pi times E_sun cos(theta). */
+                L += beta * rho / PI * sp->E[li] * cs * T;
+            }
+            if (vtx == p->max_depth - 1) break;
+            /* The cosine/pdf ratio of the bounce cancels pi, so the path
+             * weight is multiplied by the albedo. */
+            cosine_dir(ns, u[1], u[2], d);
+            beta *= rho;
+        } else {
+            /* Glass pane as a thin slab (Sec. 6 thickness map): the path
+             * reflects with probability R/(R+T), else passes straight
+             * through; the weight is R + T. */
+            double cos_i = fabs(dot3(d, ng));
+            double thick = thickness_at(s, h.tri, h.u, h.v);
+            double R, T;
+            orc_slab(cos_i, lambda, thick, sp->n[mi * sp->nl + li], sp->k[mi * sp->nl + li],
+                     sp->tint[mi * sp->nl + li], &R, &T);
+            if (vtx == p->max_depth - 1) break;
+            if (R + T > 0.0 && u[0] < R / (R + T)) {
+                double dn = dot3(d, ng);
+                for (int a = 0; a < 3; ++a) d[a] -= 2.0 * dn * ng[a];
+            }
+            beta *= R + T;
+        }
+        /* Energy threshold of Sec. 3.1 (off when 0). */
+        if (beta < p->beta_threshold) break;
+        for (int a = 0; a < 3; ++a) o[a] = x[a];
+        skip = h.tri;
+    }
+    return L;
+}
+
+static int params_ok(const orc_scene *s, const orc_render_params *p)
+{
+    if (!s || !p || p->W < 1 || p->H < 1 || p->spp < 1 || p->max_depth < 1 || p->n_lambda < 1 ||
+        !p->lambda_nm)
+        return 0;
+    return 1;
+}
+
+/* Reading: trapezoid weights in nm over the render grid (1 for a single
+ * wavelength), no normalising constant. */
+static void trapezoid(int nl, const double *lam, double *w)
+{
+    if (nl == 1) { w[0] = 1.0; return; }
+    for (int i = 0; i < nl; ++i) {
+        double a = lam[i > 0 ? i - 1 : 0], b = lam[i < nl - 1 ? i + 1 : nl - 1];
+        w[i] = 0.5 * (b - a);
+    }
+}
+
+void orc_spec_to_xyz(int64_t npix, int32_t nl, const double *lam, const double *cmf,
+                     const double *spec, double *xyz)
+{
+    double *w = (double *)malloc(sizeof(double) * (size_t)nl);
+    trapezoid(nl, lam, w);
+    for (int64_t q = 0; q < npix; ++q)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int i = 0; i < nl; ++i) acc += w[i] * spec[q * nl + i] * cmf[3 * i + c];
+            xyz[3 * q + c] = acc;
+        }
+    free(w);
+}
+
+static void pixel_spectrum(const rctx *c, int i, int j, int l0, int l1, double *out)
+{
+    for (int li = l0; li < l1; ++li) {
+        double sum = 0.0;
+        for (int smp = 0; smp < c->p->spp; ++smp) sum += path_radiance(c, i, j, smp, li);
+        out[li] = sum / c->p->spp;
+    }
+}
+
+int orc_render(const orc_scene *s, const orc_render_params *p, double *spec, double *xyz)
+{
+    if (!params_ok(s, p) || !spec) return -1;
+    spectra sp;
+    spectra_make(s, p, &sp);
+    rctx c = {s, p, &sp, {{0}}};
+    camera_make(p, &c.cam);
+    int nl = p->n_lambda;
+    int B = p->n_bands < 1 ? 1 : (p->n_bands > nl ? nl : p->n_bands);
+    int tile = p->tile > 0 ? p->tile : 16;
+    int tx = (p->W + tile - 1) / tile, ty = (p->H + tile - 1) / tile;
+    int64_t items = (int64_t)tx * ty * B;
+#ifdef _OPENMP
+    if (p->n_threads > 0) omp_set_num_threads(p->n_threads);
+#endif
+    /* Work items = pixel tile x spectral band (Sec. 4, Sec. 5), pulled
+     * dynamically by the threads (dynamic job balancing, Sec. 4).  Bands are
+     * contiguous, the first nl mod B one wavelength larger. */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t it = 0; it < items; ++it) {
+        int band = (int)(it % B);
+        int64_t tile_id = it / B;
+        int bx = (int)(tile_id % tx), by = (int)(tile_id / tx);
+        int base = nl / B, extra = nl % B;
+        int l0 = band * base + (band < extra ? band : extra);
+        int l1 = l0 + base + (band < extra ? 1 : 0);
+        for (int j = by * tile; j < (by + 1) * tile && j < p->H; ++j)
+            for (int i = bx * tile; i < (bx + 1) * tile && i < p->W; ++i)
+                pixel_spectrum(&c, i, j, l0, l1, spec + ((int64_t)j * p->W + i) * nl);
+    }
+    if (xyz && p->cmf_xyz) orc_spec_to_xyz((int64_t)p->W * p->H, nl, p->lambda_nm, p->cmf_xyz, spec, xyz);
+    spectra_free(&sp);
+    return 0;
+}
+
+int orc_render_pixels(const orc_scene *s, const orc_render_params *p, int64_t m, const int32_t *pixels,
+                      double *spec)
+{
+    if (!params_ok(s, p) || !spec || !pixels) return -1;
+    spectra sp;
+    spectra_make(s, p, &sp);
+    rctx c = {s, p, &sp, {{0}}};
+    camera_make(p, &c.cam);
+#ifdef _OPENMP
+    if (p->n_threads > 0) omp_set_num_threads(p->n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < m; ++q) {
+        int pix = pixels[q];
+        pixel_spectrum(&c, pix % p->W, pix / p->W, 0, p->n_lambda, spec + q * p->n_lambda);
+    }
+    spectra_free(&sp);
+    return 0;
+}
+
+void orc_shadow(const orc_scene *s, int32_t use_bvh, int64_t m, const double *o, const int32_t *skip,
+                double lambda_nm, double *T)
+{
+    orc_render_params p;
+    memset(&p, 0, sizeof(p));
+    p.n_lambda = 1;
+    p.lambda_nm = &lambda_nm;
+    spectra sp;
+    spectra_make(s, &p, &sp);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) T[i] = shadow_T(s, &sp, use_bvh, o + 3 * i, skip ? skip[i] : -1, 0, lambda_nm);
+    spectra_free(&sp);
+}

@@ -1,0 +1,126 @@
+/*
+ * sdm_oracle.h -- plain FP64 CPU oracle of the spectral path tracer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the HIP path.
+ *
+ * What it computes (paper: "Spectral Domain Decomposition Method for Natural
+ * Lighting and Medieval Glass Rendering"):
+ *   - inverse ray tracing from each pixel, closest hit, shadow rays toward the
+ *     light, secondary rays by reflection/refraction, stop after a fixed
+ *     number of bounces or below an energy threshold (Sec. 3.1);
+ *   - the light sum of eq. (3) for the directional sun, the uniform sky as
+ *     the escape radiance;
+ *   - glass described by optical constants n + ik (eq. (1)) with thickness
+ *     maps (Sec. 6);
+ *   - each wavelength of the 81-sample grid handled on its own (Sec. 4), each
+ *     pixel on its own (Sec. 4, Sec. 5), so any split into spectral bands and
+ *     pixel tiles gives the same image.
+ * Every other convention is a reading stated next to the code that uses it.
+ */
+#ifndef SDM_ORACLE_H
+#define SDM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_LAMBERT = 0, ORC_GLASS = 1, ORC_GLASS_BUBBLY = 2 };
+
+typedef struct {
+    int32_t type;
+    double thick_mm;          /* pane thickness when there is no per-vertex map */
+    double bubble_density;    /* bubbles per mm^3 (bubbly glass) */
+    double bubble_rmin_um, bubble_rmax_um;
+    int32_t pane_id;
+    const double *albedo;     /* [n_tab] or NULL */
+    const double *n;          /* [n_tab] or NULL */
+    const double *k;          /* [n_tab] or NULL */
+    const double *alpha_tint; /* [n_tab] mm^-1 or NULL */
+} orc_material;
+
+typedef struct {
+    int32_t nv;
+    const double *pos;        /* [nv*3] metres */
+    const double *vthick_mm;  /* [nv] or NULL */
+    int32_t nt;
+    const int32_t *idx;       /* [nt*3] */
+    const int32_t *mat;       /* [nt] */
+    int32_t n_mat;
+    const orc_material *mats;
+    int32_t n_tab;
+    const double *tab_lambda_nm; /* [n_tab], increasing */
+    double sun_dir[3];        /* unit vector toward the sun */
+    const double *sun_E;      /* [n_tab] */
+    const double *sky_L;      /* [n_tab] */
+} orc_scene_desc;
+
+typedef struct {
+    int32_t W, H, spp, max_depth;
+    int32_t projection;       /* 0 pinhole, 1 orthographic */
+    double eye[3], target[3], up[3];
+    double vfov_deg, ortho_height;
+    uint64_t seed;
+    uint32_t job_id;
+    int32_t n_lambda;
+    const double *lambda_nm;  /* [n_lambda] */
+    const double *cmf_xyz;    /* [n_lambda*3] */
+    int32_t n_bands;          /* spectral subdomains (result is independent) */
+    int32_t tile;             /* pixel-tile side of the work items */
+    double beta_threshold;    /* energy threshold of Sec. 3.1 (0 = off) */
+    int32_t use_bvh;          /* 1: BVH, 0: brute force */
+    int32_t n_threads;        /* 0 = OpenMP default */
+} orc_render_params;
+
+typedef struct orc_scene orc_scene;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
+double orc_u01(uint32_t x);
+
+/* Interface Fresnel reflectance, air -> n + ik, per polarisation. */
+void orc_fresnel(double cos_i, double n, double k, double *Rs, double *Rp);
+/* Thin slab: incoherent multiple reflection with Beer-Lambert attenuation. */
+void orc_slab(double cos_i, double lambda_nm, double d_mm, double n, double k,
+              double alpha_tint, double *R, double *T);
+void orc_slab_batch(int64_t m, const double *cos_i, const double *lambda_nm,
+                    const double *d_mm, const double *n, const double *k,
+                    const double *alpha_tint, double *R, double *T);
+/* Refraction angle used for the path length (real Snell). */
+double orc_snell_cos_t(double cos_i, double n);
+
+orc_scene *orc_scene_create(const orc_scene_desc *d);
+void orc_scene_destroy(orc_scene *s);
+double orc_scene_teps(const orc_scene *s);
+int32_t orc_bvh_depth(const orc_scene *s);
+
+/* Closest hit of m rays; tri = -1 on a miss.  skip[i] is a triangle to ignore. */
+void orc_intersect(const orc_scene *s, int32_t use_bvh, int64_t m, const double *o,
+                   const double *dir, const int32_t *skip, double *t, int32_t *tri,
+                   double *u, double *v);
+/* Sun transmittance from m points (0 if an opaque triangle is in the way). */
+void orc_shadow(const orc_scene *s, int32_t use_bvh, int64_t m, const double *o,
+                const int32_t *skip, double lambda_nm, double *T);
+
+/* Whole image: spec[H*W*n_lambda] (lambda fastest) and xyz[H*W*3]. */
+int orc_render(const orc_scene *s, const orc_render_params *p, double *spec, double *xyz);
+/* Selected pixels only: spec[m*n_lambda]. */
+int orc_render_pixels(const orc_scene *s, const orc_render_params *p, int64_t m,
+                      const int32_t *pixels, double *spec);
+/* Camera ray for image point (i + u0, j + u1) (exposed for the pin tests). */
+void orc_camera_ray(const orc_render_params *p, int32_t i, int32_t j, double u0, double u1,
+                    double o[3], double d[3]);
+/* Cosine-weighted direction about unit n from (u1, u2) (exposed for tests). */
+void orc_cosine_dir(const double n[3], double u1, double u2, double d[3]);
+
+/* Spectral image -> XYZ with trapezoid weights in nm. */
+void orc_spec_to_xyz(int64_t npix, int32_t n_lambda, const double *lambda_nm,
+                     const double *cmf_xyz, const double *spec, double *xyz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,193 @@
+/*
+ * sdm.h -- C ABI of the MI355X spectral path tracer (libsdm.so).
+ *
+ * The library renders naturally lit scenes with glass panes, per pixel and
+ * per wavelength, as in "Spectral Domain Decomposition Method for Natural
+ * Lighting and Medieval Glass Rendering":
+ *   - inverse ray tracing from the pixels, closest hit, a shadow ray to the
+ *     light, reflected/refracted secondaries, stop after a fixed number of
+ *     bounces or below an energy threshold (Sec. 3.1);
+ *   - the light sum of eq. (3) over the directional sun, a uniform sky as the
+ *     radiance of escaping rays;
+ *   - glass panes described by optical constants n + ik (eq. (1)) with
+ *     per-vertex thickness maps (Sec. 6), as thin slabs with Fresnel
+ *     interfaces and Beer-Lambert absorption;
+ *   - the spectral (wavelength-band) and ray-set (pixel-tile) sub-domains of
+ *     Sec. 4 and Sec. 5 become work items of one GPU; the result does not
+ *     depend on how they are cut;
+ *   - spectral radiance is accumulated in FP64 and converted to CIE XYZ with
+ *     a caller-supplied observer table.
+ *
+ * Conventions for every function:
+ *   - returns SDM_OK (0) or a negative SDM_E_* code; sdm_last_error() then
+ *     describes the failure.  Nothing is written to outputs on SDM_E_INVALID.
+ *   - scene and parameter arrays are HOST pointers and are copied during the
+ *     call (the caller may free them on return), unless stated otherwise.
+ *   - output buffers are owned by the caller; their memory kind (host or
+ *     device) is given per buffer.
+ *   - work is enqueued on the caller's HIP stream (hip_stream, may be NULL for
+ *     the null stream).  Device outputs are valid once that stream is
+ *     synchronised; host outputs are valid on return.
+ *   - a context is not thread-safe: use one context per host thread.  Scenes
+ *     belong to the context that created them; destroy them before it.
+ */
+#ifndef SDM_H
+#define SDM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDM_OK 0
+#define SDM_E_INVALID (-1)     /* bad argument (null pointer, size, index)   */
+#define SDM_E_NOMEM (-2)       /* device or host allocation failed            */
+#define SDM_E_DEVICE (-3)      /* HIP error or a device-side error flag       */
+#define SDM_E_UNSUPPORTED (-4) /* valid request this build does not handle    */
+
+enum { SDM_LAMBERT = 0, SDM_GLASS = 1, SDM_GLASS_BUBBLY = 2 };
+enum { SDM_MEM_HOST = 0, SDM_MEM_DEVICE = 1 };
+enum { SDM_PREC_FP32 = 0, SDM_PREC_FP64 = 1 };
+enum { SDM_PINHOLE = 0, SDM_ORTHO = 1 };
+
+/* Largest number of wavelengths one spectral band (sub-domain) may hold. */
+#define SDM_MAX_BAND 128
+
+typedef struct sdm_context sdm_context;
+typedef struct sdm_scene sdm_scene;
+
+/* Material.  Tables are host arrays sampled at the scene's tab_lambda_nm and
+ * linearly interpolated to the render wavelengths (held constant beyond the
+ * table ends).  Lambert needs albedo; glass needs n and k (eq. (1));
+ * alpha_tint (mm^-1, extra absorption) may be NULL for zero. */
+typedef struct {
+    int32_t type;               /* SDM_LAMBERT or SDM_GLASS                    */
+    const float *albedo;        /* [n_tab] or NULL                             */
+    const float *n;             /* [n_tab] real index, >= 1                    */
+    const float *k;             /* [n_tab] absorption index, >= 0              */
+    const float *alpha_tint;    /* [n_tab] mm^-1, or NULL                      */
+    float thick_mm;             /* pane thickness when vthick_mm is NULL        */
+    float bubble_density_mm3;   /* heterogeneous glass (reserved)               */
+    float bubble_rmin_um, bubble_rmax_um;
+    int32_t pane_id;
+} sdm_material;
+
+/* Scene.  Triangles are two-sided.  Units: metres, thickness in mm. */
+typedef struct {
+    int32_t nv;
+    const float *pos;           /* [nv*3]                                      */
+    const float *vthick_mm;     /* [nv] per-vertex pane thickness, or NULL      */
+    int32_t nt;
+    const int32_t *idx;         /* [nt*3] vertex indices in [0, nv)             */
+    const int32_t *mat;         /* [nt] material indices in [0, n_mat)          */
+    int32_t n_mat;
+    const sdm_material *mats;   /* [n_mat]                                      */
+    int32_t n_tab;
+    const float *tab_lambda_nm; /* [n_tab], strictly increasing                 */
+    float sun_dir[3];           /* unit vector toward the sun                   */
+    const float *sun_E;         /* [n_tab] sun irradiance                       */
+    const float *sky_L;         /* [n_tab] uniform sky radiance                 */
+} sdm_scene_desc;
+
+typedef struct {
+    float eye[3], target[3], up[3];
+    float vfov_deg;             /* pinhole vertical field of view              */
+    float ortho_height;         /* orthographic view height (metres)           */
+    int32_t W, H;
+    int32_t projection;         /* SDM_PINHOLE or SDM_ORTHO                    */
+} sdm_camera;
+
+typedef struct {
+    sdm_camera camera;
+    int32_t n_lambda;           /* render wavelengths                          */
+    const float *lambda_nm;     /* [n_lambda] host                             */
+    const float *cmf_xyz;       /* [n_lambda*3] host observer table            */
+    int32_t spp;                /* samples per pixel (>= 1)                    */
+    int32_t max_depth;          /* shaded vertices per path (>= 1)             */
+    uint64_t seed;              /* Philox key                                  */
+    uint32_t job_id;            /* fourth Philox counter word                  */
+    int32_t n_bands;            /* spectral sub-domains (>= 1), even split     */
+    const int32_t *band_edges;  /* [n_bands+1] host, or NULL for an even split */
+    int32_t tile_w, tile_h;     /* pixel-tile work items (0 = library default) */
+    float beta_threshold;       /* path-weight threshold (0 = off)             */
+    int32_t precision;          /* SDM_PREC_FP32 (default) or SDM_PREC_FP64    */
+    int64_t chunk_paths;        /* in-flight primary paths (0 = default)       */
+    int32_t timing;             /* 1: time every kernel with HIP events        */
+} sdm_render_params;
+
+/* Kernel classes reported in sdm_stats. */
+enum { SDM_K_GENERATE = 0, SDM_K_TRACE = 1, SDM_K_SHADE = 2, SDM_K_SHADOW = 3,
+       SDM_K_FINALIZE = 4, SDM_K_COUNT = 5 };
+
+typedef struct {
+    uint64_t spectral_samples;  /* W*H*spp*n_lambda                            */
+    uint64_t paths;             /* primary rays: pixels x spp x bands          */
+    uint64_t closest_segments;  /* closest-hit traversals                      */
+    uint64_t shadow_segments;   /* shadow (any-hit) traversals                 */
+    uint64_t forks;             /* paths split at glass by wavelength          */
+    uint64_t chunks;            /* wavefront chunks                            */
+    uint64_t nodes_visited[2];  /* BVH node fetches [closest-hit, shadow]      */
+    uint64_t tris_tested[2];    /* ray-triangle tests [closest-hit, shadow]    */
+    double ms_render;          /* wall time of the render on the stream       */
+    double kernel_ms[SDM_K_COUNT];     /* summed kernel durations (timing=1)   */
+    uint64_t kernel_launches[SDM_K_COUNT];
+} sdm_stats;
+
+typedef struct {
+    float *spectral;            /* [H*W*n_lambda], wavelength fastest, or NULL */
+    double *xyz;                /* [H*W*3], or NULL                            */
+    int32_t spectral_mem;       /* SDM_MEM_HOST or SDM_MEM_DEVICE              */
+    int32_t xyz_mem;
+    sdm_stats *stats;           /* host struct, may be NULL                     */
+} sdm_outputs;
+
+/* Context on HIP device `device`.  Owns the work buffers of renders. */
+int sdm_context_create(int device, sdm_context **out);
+int sdm_context_destroy(sdm_context *ctx);
+/* Description of the last failure of a call on ctx (context-owned string). */
+const char *sdm_last_error(const sdm_context *ctx);
+
+/* Copies the scene, builds its BVH on the host (binned SAH) and uploads it. */
+int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *desc, sdm_scene **out);
+int sdm_scene_destroy(sdm_scene *scene);
+
+/* Renders one image: spectral radiance (mean over spp) per pixel and
+ * wavelength, and XYZ = sum_i w_i L(lambda_i) cmf(lambda_i) with trapezoid
+ * weights w_i in nm.  Geometry and shading run in the requested precision;
+ * the per-pixel spectral accumulation and XYZ are FP64.  The call
+ * synchronises the stream before it returns: it checks the device flag that
+ * reports a full path pool (more glass forks than the pool holds), and in
+ * that case renders again with a larger pool (the result is deterministic),
+ * returning SDM_E_DEVICE only if the pool cannot grow further. */
+int sdm_render(sdm_context *ctx, const sdm_scene *scene, const sdm_render_params *params,
+               const sdm_outputs *out, void *hip_stream);
+
+/* Thin-slab optics for m independent inputs (DEVICE arrays of length m):
+ * interface Fresnel for n + ik at incidence cos_i, real-Snell path length,
+ * Beer-Lambert absorption 4 pi k / lambda + alpha_tint over d_mm, incoherent
+ * multiple reflection, s/p averaged.  Writes R and T (DEVICE, length m). */
+int sdm_slab_eval(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm,
+                  const float *d_mm, const float *n, const float *k, const float *alpha_tint,
+                  float *R, float *T, void *hip_stream);
+
+/* Closest hit of m rays against a scene (DEVICE arrays): o, d [m*3], skip [m]
+ * (triangle index to ignore, -1 for none) -> t [m], tri [m] (-1 = miss),
+ * uv [m*2] barycentrics.  Hits need t > 1e-6 x scene diagonal; ties in t go
+ * to the smaller triangle index. */
+int sdm_debug_intersect(sdm_context *ctx, const sdm_scene *scene, int64_t m, const float *o,
+                        const float *d, const int32_t *skip, float *t, int32_t *tri, float *uv,
+                        void *hip_stream);
+
+/* Sun transmittance from m points (DEVICE arrays o [m*3], skip [m]) at one
+ * wavelength: 0 if an opaque triangle lies toward the sun, else the product
+ * of the slab transmittances of the panes crossed.  Writes T [m] (DEVICE). */
+int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *scene, int64_t m, const float *o,
+                     const int32_t *skip, float lambda_nm, float *T, void *hip_stream);
+
+/* BVH shape of a scene (for tests and tuning): node count and depth. */
+int sdm_scene_info(const sdm_scene *scene, int32_t *n_nodes, int32_t *depth);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -584,14 +584,17 @@ static void camera_ray(const orc_render_params *p, const camera *c, int i, int j
     normalize3(d);
 }
 
-/* Orthonormal basis around unit n (Duff et al., JCGT 2017). */
+/* Reading: tangent basis about unit n from a fixed generic axis h = (1, 2,
+ * 3) / sqrt(14): t1 = normalize(h x n), t2 = n x t1.  It is continuous for
+ * every normal except +-h, so axis-aligned and vertical faces (the common
+ * case in architecture) never sit on the switch of a branch-based basis,
+ * where the choice would hang on the sign of a rounding residue. */
 static void onb(const double *n, double *t1, double *t2)
 {
-    double sign = copysign(1.0, n[2]);
-    double a = -1.0 / (sign + n[2]);
-    double b = n[0] * n[1] * a;
-    t1[0] = 1.0 + sign * n[0] * n[0] * a; t1[1] = sign * b; t1[2] = -sign * n[0];
-    t2[0] = b; t2[1] = sign + n[1] * n[1] * a; t2[2] = -n[1];
+    const double h[3] = {0.2672612419124244, 0.5345224838248488, 0.8017837257372732};
+    cross3(h, n, t1);
+    normalize3(t1);
+    cross3(n, t1, t2);
 }
 
 typedef struct {

@@ -1,0 +1,698 @@
+// api.cpp -- C ABI of the spectral wavefront path tracer (see include/sdm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sdm.h"
+#include "bvh_build.hpp"
+#include "sdm_types.hpp"
+#include "wavefront.hpp"
+
+using namespace sdm;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t b)
+    {
+        if (b <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
+        if (e != hipSuccess) { p = nullptr; bytes = 0; return e; }
+        bytes = std::max<size_t>(b, 256);
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+    ~DevBuf() { release(); }
+};
+
+}  // namespace
+
+struct sdm_context {
+    int device = 0;
+    int num_cu = 0;
+    std::string err;
+    DevBuf gstack;
+    // render work buffers (one set; reallocated when a render needs more)
+    DevBuf pool, queue0, queue1, hits, shadowq, acc, counters, jobs, bands, items, tables, outs;
+    Counters *host_counters = nullptr;
+    std::vector<hipEvent_t> events;
+    DevBuf slab_tmp;
+};
+
+struct sdm_scene {
+    sdm_context *ctx = nullptr;
+    SceneDev dev{};
+    DevBuf nodes, tris, thick, mat_type, mat_thick, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
+    int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
+};
+
+namespace {
+
+int fail(sdm_context *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, x)                                                                            \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? SDM_E_NOMEM : SDM_E_DEVICE, "%s: %s",    \
+                        #x, hipGetErrorString(e_));                                               \
+    } while (0)
+
+template <class T>
+hipError_t upload(DevBuf &b, const T *src, size_t n, hipStream_t s = nullptr)
+{
+    hipError_t e = b.ensure(n * sizeof(T));
+    if (e != hipSuccess || n == 0) return e;
+    return hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+bool ptr_is_device(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdm_context_create(int device, sdm_context **out)
+{
+    if (!out) return SDM_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SDM_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return SDM_E_DEVICE;
+    auto *ctx = new sdm_context();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete ctx;
+        return SDM_E_DEVICE;
+    }
+    ctx->num_cu = prop.multiProcessorCount;
+    if (hipHostMalloc((void **)&ctx->host_counters, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return SDM_E_NOMEM;
+    }
+    *out = ctx;
+    return SDM_OK;
+}
+
+int sdm_context_destroy(sdm_context *ctx)
+{
+    if (!ctx) return SDM_E_INVALID;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+    delete ctx;
+    return SDM_OK;
+}
+
+const char *sdm_last_error(const sdm_context *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sdm_scene_info(const sdm_scene *sc, int32_t *n_nodes, int32_t *depth)
+{
+    if (!sc) return SDM_E_INVALID;
+    if (n_nodes) *n_nodes = sc->n_nodes;
+    if (depth) *depth = sc->depth;
+    return SDM_OK;
+}
+
+int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!d || !out) return fail(ctx, SDM_E_INVALID, "null scene description or output");
+    *out = nullptr;
+    if (d->nv < 0 || d->nt < 0) return fail(ctx, SDM_E_INVALID, "negative vertex/triangle count");
+    if (d->nt > 0 && (!d->pos || !d->idx || !d->mat || !d->mats || d->n_mat < 1))
+        return fail(ctx, SDM_E_INVALID, "triangles need pos, idx, mat and materials");
+    if (d->n_tab < 1 || !d->tab_lambda_nm || !d->sun_E || !d->sky_L)
+        return fail(ctx, SDM_E_INVALID, "scene needs tab_lambda_nm, sun_E and sky_L tables");
+    for (int i = 1; i < d->n_tab; ++i)
+        if (!(d->tab_lambda_nm[i] > d->tab_lambda_nm[i - 1]))
+            return fail(ctx, SDM_E_INVALID, "tab_lambda_nm must be strictly increasing");
+    if ((int64_t)d->nt >= (1ll << 30)) return fail(ctx, SDM_E_UNSUPPORTED, "too many triangles");
+    for (int32_t t = 0; t < d->nt; ++t) {
+        for (int c = 0; c < 3; ++c)
+            if (d->idx[3 * (size_t)t + c] < 0 || d->idx[3 * (size_t)t + c] >= d->nv)
+                return fail(ctx, SDM_E_INVALID, "triangle %d has a vertex index out of range", t);
+        if (d->mat[t] < 0 || d->mat[t] >= d->n_mat)
+            return fail(ctx, SDM_E_INVALID, "triangle %d has a material index out of range", t);
+    }
+    for (int32_t m = 0; m < d->n_mat; ++m) {
+        const sdm_material &mm = d->mats[m];
+        if (mm.type == SDM_LAMBERT) {
+            if (!mm.albedo) return fail(ctx, SDM_E_INVALID, "Lambert material %d needs albedo", m);
+        } else if (mm.type == SDM_GLASS || mm.type == SDM_GLASS_BUBBLY) {
+            if (!mm.n || !mm.k) return fail(ctx, SDM_E_INVALID, "glass material %d needs n and k", m);
+            for (int i = 0; i < d->n_tab; ++i)
+                if (!(mm.n[i] >= 1.0f) || !(mm.k[i] >= 0.0f))
+                    return fail(ctx, SDM_E_INVALID, "glass material %d needs n >= 1 and k >= 0", m);
+        } else {
+            return fail(ctx, SDM_E_INVALID, "material %d has an unknown type %d", m, mm.type);
+        }
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    auto *sc = new sdm_scene();
+    sc->ctx = ctx;
+    sc->n_tab = d->n_tab;
+    sc->n_mat = d->n_mat;
+    sc->nt = d->nt;
+    BvhResult bvh = build_bvh(d->pos, d->nv, d->idx, d->nt);
+    sc->depth = bvh.depth;
+    sc->n_nodes = (int32_t)bvh.nodes.size();
+    std::vector<TriDev> tris(d->nt);
+    std::vector<float4> thick(d->nt);
+    std::vector<int32_t> o2l(std::max(1, d->nt));
+    for (int32_t l = 0; l < d->nt; ++l) {
+        const int32_t t = bvh.order[l];
+        o2l[t] = l;
+        const float *p0 = d->pos + 3 * (size_t)d->idx[3 * (size_t)t];
+        const float *p1 = d->pos + 3 * (size_t)d->idx[3 * (size_t)t + 1];
+        const float *p2 = d->pos + 3 * (size_t)d->idx[3 * (size_t)t + 2];
+        int32_t tt = t, mm = d->mat[t];
+        float ft, fm;
+        std::memcpy(&ft, &tt, 4);
+        std::memcpy(&fm, &mm, 4);
+        tris[l].a = make_float4(p0[0], p0[1], p0[2], ft);
+        tris[l].b = make_float4(p1[0], p1[1], p1[2], fm);
+        tris[l].c = make_float4(p2[0], p2[1], p2[2], 0.0f);
+        if (d->vthick_mm)
+            thick[l] = make_float4(d->vthick_mm[d->idx[3 * (size_t)t]], d->vthick_mm[d->idx[3 * (size_t)t + 1]],
+                                   d->vthick_mm[d->idx[3 * (size_t)t + 2]], 0.0f);
+        else
+            thick[l] = make_float4(0, 0, 0, 0);
+    }
+    // self-intersection epsilon: 1e-6 x diagonal of the vertex bounding box
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t v = 0; v < d->nv; ++v)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], (double)d->pos[3 * (size_t)v + a]);
+            hi[a] = std::max(hi[a], (double)d->pos[3 * (size_t)v + a]);
+        }
+    double diag = 0.0;
+    if (d->nv > 0)
+        diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                         (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    std::vector<int32_t> mtype(d->n_mat);
+    std::vector<float> mthick(d->n_mat);
+    std::vector<float> tabm(4 * (size_t)d->n_mat * d->n_tab, 0.0f);
+    for (int32_t m = 0; m < d->n_mat; ++m) {
+        const sdm_material &mm = d->mats[m];
+        mtype[m] = mm.type == SDM_LAMBERT ? 0 : 1;
+        mthick[m] = mm.thick_mm;
+        const float *src[4] = {mm.albedo, mm.n, mm.k, mm.alpha_tint};
+        for (int q = 0; q < 4; ++q)
+            if (src[q])
+                std::memcpy(&tabm[((size_t)q * d->n_mat + m) * d->n_tab], src[q], sizeof(float) * d->n_tab);
+    }
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(upload(sc->nodes, bvh.nodes.data(), bvh.nodes.size()));
+    chk(upload(sc->tris, tris.data(), tris.size()));
+    chk(upload(sc->thick, thick.data(), thick.size()));
+    chk(upload(sc->orig_to_leaf, o2l.data(), o2l.size()));
+    chk(upload(sc->mat_type, mtype.data(), mtype.size()));
+    chk(upload(sc->mat_thick, mthick.data(), mthick.size()));
+    chk(upload(sc->tab_x, d->tab_lambda_nm, (size_t)d->n_tab));
+    chk(upload(sc->tab_mat, tabm.data(), tabm.size()));
+    chk(upload(sc->tab_sun, d->sun_E, (size_t)d->n_tab));
+    chk(upload(sc->tab_sky, d->sky_L, (size_t)d->n_tab));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete sc;
+        return fail(ctx, e == hipErrorOutOfMemory ? SDM_E_NOMEM : SDM_E_DEVICE, "scene upload: %s",
+                    hipGetErrorString(e));
+    }
+    SceneDev &sd = sc->dev;
+    sd.nodes = sc->nodes.as<BvhNode>();
+    sd.tris = sc->tris.as<TriDev>();
+    sd.thick = sc->thick.as<float4>();
+    sd.mat_type = sc->mat_type.as<int32_t>();
+    sd.mat_thick = sc->mat_thick.as<float>();
+    sd.n_nodes = sc->n_nodes;
+    sd.nt = d->nt;
+    sd.n_mat = d->n_mat;
+    sd.has_vthick = d->vthick_mm ? 1 : 0;
+    for (int a = 0; a < 3; ++a) sd.sun[a] = d->sun_dir[a];
+    sd.teps_d = 1e-6 * diag;
+    sd.teps_f = (float)sd.teps_d;
+    *out = sc;
+    return SDM_OK;
+}
+
+int sdm_scene_destroy(sdm_scene *sc)
+{
+    if (!sc) return SDM_E_INVALID;
+    (void)hipSetDevice(sc->ctx->device);
+    (void)hipDeviceSynchronize();
+    delete sc;
+    return SDM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Render
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Plan {
+    std::vector<BandDev> bands;
+    std::vector<ItemDev> items;
+    uint64_t total_rays = 0;
+    int nbmax = 0;
+};
+
+int plan_work(sdm_context *ctx, const sdm_render_params *p, int job, Plan &plan)
+{
+    const int nl = p->n_lambda;
+    std::vector<int> edges;
+    if (p->band_edges) {
+        edges.assign(p->band_edges, p->band_edges + p->n_bands + 1);
+        if (edges.front() != 0 || edges.back() != nl)
+            return fail(ctx, SDM_E_INVALID, "band_edges must start at 0 and end at n_lambda");
+        for (int b = 0; b < p->n_bands; ++b)
+            if (edges[b + 1] <= edges[b]) return fail(ctx, SDM_E_INVALID, "band_edges must increase");
+    } else {
+        // contiguous bands, the first nl mod B one wavelength larger
+        const int B = p->n_bands, base = nl / B, extra = nl % B;
+        edges.push_back(0);
+        for (int b = 0; b < B; ++b) edges.push_back(edges.back() + base + (b < extra ? 1 : 0));
+    }
+    const int b0 = (int)plan.bands.size();
+    for (size_t b = 0; b + 1 < edges.size(); ++b) {
+        const int nb = edges[b + 1] - edges[b];
+        if (nb > kMaxBand) return fail(ctx, SDM_E_UNSUPPORTED, "a band holds %d > %d wavelengths", nb, kMaxBand);
+        plan.bands.push_back(BandDev{job, edges[b], nb, 0});
+        plan.nbmax = std::max(plan.nbmax, nb);
+    }
+    if ((int)plan.bands.size() >= (1 << kAuxBandBits)) return fail(ctx, SDM_E_UNSUPPORTED, "too many bands");
+    const int tw = p->tile_w > 0 ? p->tile_w : 16, th = p->tile_h > 0 ? p->tile_h : 16;
+    const int W = p->camera.W, H = p->camera.H;
+    for (int y0 = 0; y0 < H; y0 += th)
+        for (int x0 = 0; x0 < W; x0 += tw)
+            for (int b = b0; b < (int)plan.bands.size(); ++b) {
+                ItemDev it{};
+                it.band = b;
+                it.x0 = x0;
+                it.y0 = y0;
+                it.tw = std::min(tw, W - x0);
+                it.th = std::min(th, H - y0);
+                it.s0 = 0;
+                it.ns = p->spp;
+                it.first = plan.total_rays;
+                plan.total_rays += (uint64_t)it.tw * it.th * it.ns;
+                plan.items.push_back(it);
+            }
+    return SDM_OK;
+}
+
+int validate_params(sdm_context *ctx, const sdm_render_params *p)
+{
+    if (!p) return fail(ctx, SDM_E_INVALID, "null render parameters");
+    const sdm_camera &c = p->camera;
+    if (c.W < 1 || c.H < 1 || (int64_t)c.W * c.H > (1ll << 31))
+        return fail(ctx, SDM_E_INVALID, "image size %d x %d out of range", c.W, c.H);
+    if (p->spp < 1 || p->spp > 65535) return fail(ctx, SDM_E_INVALID, "spp must be in [1, 65535]");
+    if (p->max_depth < 1 || p->max_depth > 255) return fail(ctx, SDM_E_INVALID, "max_depth must be in [1, 255]");
+    if (p->n_lambda < 1 || !p->lambda_nm) return fail(ctx, SDM_E_INVALID, "need n_lambda >= 1 wavelengths");
+    if (p->n_bands < 1 || p->n_bands > p->n_lambda)
+        return fail(ctx, SDM_E_INVALID, "n_bands must be in [1, n_lambda]");
+    if (c.projection != SDM_PINHOLE && c.projection != SDM_ORTHO)
+        return fail(ctx, SDM_E_INVALID, "unknown projection");
+    if (p->precision != SDM_PREC_FP32 && p->precision != SDM_PREC_FP64)
+        return fail(ctx, SDM_E_INVALID, "unknown precision");
+    return SDM_OK;
+}
+
+void camera_basis(const sdm_camera &c, JobDev &jb)
+{
+    double f[3], r[3], u[3];
+    for (int a = 0; a < 3; ++a) f[a] = (double)c.target[a] - c.eye[a];
+    auto nrm = [](double *v) {
+        double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (l > 0) for (int a = 0; a < 3; ++a) v[a] /= l;
+    };
+    nrm(f);
+    const double up[3] = {c.up[0], c.up[1], c.up[2]};
+    r[0] = f[1] * up[2] - f[2] * up[1];
+    r[1] = f[2] * up[0] - f[0] * up[2];
+    r[2] = f[0] * up[1] - f[1] * up[0];
+    nrm(r);
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    for (int a = 0; a < 3; ++a) {
+        jb.eye[a] = c.eye[a];
+        jb.f[a] = f[a];
+        jb.r[a] = r[a];
+        jb.u[a] = u[a];
+    }
+    jb.th = std::tan(0.5 * (double)c.vfov_deg * M_PI / 180.0);
+    jb.aspect = (double)c.W / (double)c.H;
+    jb.oh = 0.5 * (double)c.ortho_height;
+    jb.projection = c.projection;
+    jb.W = c.W;
+    jb.H = c.H;
+}
+
+struct Timer {
+    sdm_context *ctx;
+    hipStream_t s;
+    bool on;
+    size_t next = 0;
+    std::vector<std::pair<int, size_t>> marks;  // (kernel class, event index of start)
+    hipError_t begin(int cls)
+    {
+        if (!on) return hipSuccess;
+        if (next + 2 > ctx->events.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                ctx->events.push_back(e);
+            }
+        }
+        marks.push_back({cls, next});
+        hipError_t r = hipEventRecord(ctx->events[next], s);
+        next += 2;
+        return r;
+    }
+    hipError_t end()
+    {
+        if (!on) return hipSuccess;
+        return hipEventRecord(ctx->events[marks.back().second + 1], s);
+    }
+};
+
+template <class R>
+int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p, const sdm_outputs *out,
+                hipStream_t s)
+{
+    const int nl = p->n_lambda, W = p->camera.W, H = p->camera.H;
+    const int64_t npix = (int64_t)W * H;
+    Plan plan;
+    int rc = plan_work(ctx, p, 0, plan);
+    if (rc) return rc;
+    // per-render tables at the render wavelengths
+    const int nm = sc->n_mat;
+    const size_t tab_elems = 4 * (size_t)nm * nl + 3 * (size_t)nl;  // rho,n,k,tint | E, Lsky, lambda
+    std::vector<double> wts(nl), cmf(3 * (size_t)nl, 0.0);
+    if (nl == 1) wts[0] = 1.0;
+    else
+        for (int i = 0; i < nl; ++i)
+            wts[i] = 0.5 * ((double)p->lambda_nm[std::min(i + 1, nl - 1)] - p->lambda_nm[std::max(i - 1, 0)]);
+    if (p->cmf_xyz)
+        for (size_t i = 0; i < 3 * (size_t)nl; ++i) cmf[i] = p->cmf_xyz[i];
+    // device layout of `tables`: [R tables][lambda float][wts double][cmf double]
+    const size_t off_lamf = ((tab_elems * sizeof(R) + 255) / 256) * 256;
+    const size_t off_w = off_lamf + ((nl * sizeof(float) + 255) / 256) * 256;
+    const size_t off_c = off_w + ((nl * sizeof(double) + 255) / 256) * 256;
+    const size_t tab_bytes = off_c + 3 * nl * sizeof(double);
+    HIPCHK(ctx, ctx->tables.ensure(tab_bytes));
+    char *tb = ctx->tables.as<char>();
+    R *tR = reinterpret_cast<R *>(tb);
+    float *lamf = reinterpret_cast<float *>(tb + off_lamf);
+    double *wts_d = reinterpret_cast<double *>(tb + off_w);
+    double *cmf_d = reinterpret_cast<double *>(tb + off_c);
+    HIPCHK(ctx, hipMemcpyAsync(lamf, p->lambda_nm, nl * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(wts_d, wts.data(), nl * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(cmf_d, cmf.data(), 3 * nl * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lamf, nl, tR, s);
+    launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sun.as<float>(), 1, lamf, nl,
+                       tR + 4 * (size_t)nm * nl, s);
+    launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sky.as<float>(), 1, lamf, nl,
+                       tR + 4 * (size_t)nm * nl + nl, s);
+    // lambda itself in R (identity resample of the wavelength grid)
+    launch_resample<R>(lamf, nl, lamf, 1, lamf, nl, tR + 4 * (size_t)nm * nl + 2 * nl, s);
+    HIPCHK(ctx, hipGetLastError());
+
+    JobDev jb{};
+    jb.sc = sc->dev;
+    camera_basis(p->camera, jb);
+    jb.spp = p->spp;
+    jb.nl = nl;
+    jb.max_depth = p->max_depth;
+    jb.seed = p->seed;
+    jb.job_word = p->job_id;
+    jb.acc_off = 0;
+    jb.rho = tR;
+    jb.n = tR + (size_t)nm * nl;
+    jb.k = tR + 2 * (size_t)nm * nl;
+    jb.tint = tR + 3 * (size_t)nm * nl;
+    jb.E = tR + 4 * (size_t)nm * nl;
+    jb.Lsky = tR + 4 * (size_t)nm * nl + nl;
+    jb.lam = tR + 4 * (size_t)nm * nl + 2 * nl;
+    jb.beta_thr = p->beta_threshold;
+    HIPCHK(ctx, upload(ctx->jobs, &jb, 1, s));
+    HIPCHK(ctx, upload(ctx->bands, plan.bands.data(), plan.bands.size(), s));
+    HIPCHK(ctx, upload(ctx->items, plan.items.data(), plan.items.size(), s));
+
+    // work buffers
+    const uint64_t total = plan.total_rays;
+    uint64_t chunk = p->chunk_paths > 0 ? (uint64_t)p->chunk_paths : (uint64_t)1 << 21;
+    chunk = std::min<uint64_t>(chunk, total);
+    chunk = std::max<uint64_t>(chunk, 1);
+    int attempt = 0;
+    for (;;) {
+        const uint64_t cap64 = chunk * (2ull << attempt);
+        if (cap64 >= (1ull << 31)) return fail(ctx, SDM_E_NOMEM, "path pool would exceed 2^31 slots");
+        const uint32_t cap = (uint32_t)cap64;
+        const int nb = plan.nbmax;
+        const size_t pool_b = cap * (6 * sizeof(R) + 4 * 4 + (size_t)nb * sizeof(R));
+        const size_t hit_b = (size_t)cap * (3 * sizeof(R) + 4);
+        const size_t sh_b = (size_t)cap * (3 * sizeof(R) + 12 + (size_t)nb * sizeof(R));
+        HIPCHK(ctx, ctx->pool.ensure(pool_b));
+        HIPCHK(ctx, ctx->queue0.ensure((size_t)cap * 4));
+        HIPCHK(ctx, ctx->queue1.ensure((size_t)cap * 4));
+        HIPCHK(ctx, ctx->hits.ensure(hit_b));
+        HIPCHK(ctx, ctx->shadowq.ensure(sh_b));
+        HIPCHK(ctx, ctx->acc.ensure((size_t)npix * nl * sizeof(double)));
+        HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
+        const int grid_t = ctx->num_cu * occupancy_trace<R>();
+        const int grid_s = ctx->num_cu * occupancy_shade<R>();
+        const int grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
+        const size_t gthreads = (size_t)std::max(grid_t, grid_s) * block_size();
+        HIPCHK(ctx, ctx->gstack.ensure(gthreads * kGlobalStack * sizeof(int32_t)));
+        Work<R> w{};
+        char *pb = ctx->pool.as<char>();
+        auto take = [&](size_t bytes) { char *r = pb; pb += bytes; return r; };
+        w.ox = (R *)take(cap * sizeof(R)); w.oy = (R *)take(cap * sizeof(R)); w.oz = (R *)take(cap * sizeof(R));
+        w.dx = (R *)take(cap * sizeof(R)); w.dy = (R *)take(cap * sizeof(R)); w.dz = (R *)take(cap * sizeof(R));
+        w.pix = (uint32_t *)take(cap * 4); w.smp = (uint32_t *)take(cap * 4); w.aux = (uint32_t *)take(cap * 4);
+        w.skip = (int32_t *)take(cap * 4);
+        w.beta = (R *)take((size_t)cap * nb * sizeof(R));
+        w.q[0] = ctx->queue0.as<uint32_t>();
+        w.q[1] = ctx->queue1.as<uint32_t>();
+        pb = ctx->hits.as<char>();
+        w.ht = (R *)take(cap * sizeof(R)); w.hu = (R *)take(cap * sizeof(R)); w.hv = (R *)take(cap * sizeof(R));
+        w.htri = (int32_t *)take(cap * 4);
+        pb = ctx->shadowq.as<char>();
+        w.sx = (R *)take(cap * sizeof(R)); w.sy = (R *)take(cap * sizeof(R)); w.sz = (R *)take(cap * sizeof(R));
+        w.sskip = (int32_t *)take(cap * 4); w.spix = (uint32_t *)take(cap * 4); w.saux = (uint32_t *)take(cap * 4);
+        w.contrib = (R *)take((size_t)cap * nb * sizeof(R));
+        w.acc = ctx->acc.as<double>();
+        w.cnt = ctx->counters.as<Counters>();
+        w.cap = cap;
+        w.primary_cap = (uint32_t)chunk;
+        w.gstack = ctx->gstack.as<int32_t>();
+        w.gstack_threads = (uint32_t)gthreads;
+
+        Timer tm{ctx, s, p->timing != 0};
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        HIPCHK(ctx, hipEventCreate(&ev0));
+        HIPCHK(ctx, hipEventCreate(&ev1));
+        HIPCHK(ctx, hipEventRecord(ev0, s));
+        launch_zero_f64(w.acc, npix * nl, s);
+        launch_zero_counters(w.cnt, s);
+        const JobDev *jobs_d = ctx->jobs.as<JobDev>();
+        const BandDev *bands_d = ctx->bands.as<BandDev>();
+        uint64_t n_chunks = 0;
+        for (uint64_t r0 = 0; r0 < total; r0 += chunk) {
+            const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, total - r0);
+            int cur = 0;
+            HIPCHK(ctx, tm.begin(SDM_K_GENERATE));
+            launch_generate<R>(jobs_d, bands_d, ctx->items.as<ItemDev>(), (int)plan.items.size(), w, r0, n, cur,
+                               grid_g, s);
+            HIPCHK(ctx, tm.end());
+            for (int dpt = 0; dpt < p->max_depth; ++dpt) {
+                HIPCHK(ctx, tm.begin(SDM_K_TRACE));
+                launch_trace<R>(jobs_d, w, cur, 0, grid_t, s);
+                HIPCHK(ctx, tm.end());
+                HIPCHK(ctx, tm.begin(SDM_K_SHADE));
+                launch_shade<R>(jobs_d, bands_d, w, cur, grid_s, s);
+                HIPCHK(ctx, tm.end());
+                HIPCHK(ctx, tm.begin(SDM_K_SHADOW));
+                launch_shadow<R>(jobs_d, bands_d, w, 0, grid_t, s);
+                HIPCHK(ctx, tm.end());
+                cur ^= 1;
+            }
+            ++n_chunks;
+        }
+        HIPCHK(ctx, hipGetLastError());
+        // finalize into device outputs (or staging for host outputs)
+        float *spec_d = nullptr;
+        double *xyz_d = nullptr;
+        const bool spec_host = out->spectral && out->spectral_mem == SDM_MEM_HOST;
+        const bool xyz_host = out->xyz && out->xyz_mem == SDM_MEM_HOST;
+        const size_t spec_b = (size_t)npix * nl * sizeof(float), xyz_b = (size_t)npix * 3 * sizeof(double);
+        if (spec_host || xyz_host) HIPCHK(ctx, ctx->outs.ensure(spec_b + xyz_b + 256));
+        if (out->spectral) spec_d = spec_host ? ctx->outs.as<float>() : out->spectral;
+        if (out->xyz)
+            xyz_d = xyz_host ? reinterpret_cast<double *>(ctx->outs.as<char>() + ((spec_b + 255) / 256) * 256)
+                             : out->xyz;
+        HIPCHK(ctx, tm.begin(SDM_K_FINALIZE));
+        launch_finalize(w.acc, npix, nl, p->spp, wts_d, cmf_d, spec_d, p->cmf_xyz ? xyz_d : nullptr, s);
+        HIPCHK(ctx, tm.end());
+        HIPCHK(ctx, hipEventRecord(ev1, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        if (spec_host) HIPCHK(ctx, hipMemcpyAsync(out->spectral, spec_d, spec_b, hipMemcpyDeviceToHost, s));
+        if (xyz_host && p->cmf_xyz) HIPCHK(ctx, hipMemcpyAsync(out->xyz, xyz_d, xyz_b, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        const Counters c = *ctx->host_counters;
+        if (c.overflow) {
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
+            if (++attempt > 4)
+                return fail(ctx, SDM_E_DEVICE, "path pool overflow: more than %llu forks per chunk",
+                            (unsigned long long)(cap64 - chunk));
+            continue;  // deterministic: render again with a larger fork region
+        }
+        if (out->stats) {
+            sdm_stats &st = *out->stats;
+            std::memset(&st, 0, sizeof(st));
+            st.spectral_samples = (uint64_t)npix * p->spp * nl;
+            st.paths = total;
+            st.closest_segments = c.closest;
+            st.shadow_segments = c.shadow;
+            st.forks = c.forks;
+            st.chunks = n_chunks;
+            for (int q = 0; q < 2; ++q) {
+                st.nodes_visited[q] = c.nodes[q];
+                st.tris_tested[q] = c.tris[q];
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev0, ev1);
+            st.ms_render = ms;
+            if (tm.on)
+                for (auto &mk : tm.marks) {
+                    float km = 0;
+                    (void)hipEventElapsedTime(&km, ctx->events[mk.second], ctx->events[mk.second + 1]);
+                    st.kernel_ms[mk.first] += km;
+                    st.kernel_launches[mk.first] += 1;
+                }
+        }
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        return SDM_OK;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdm_render(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p, const sdm_outputs *out,
+               void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!sc || !out) return fail(ctx, SDM_E_INVALID, "null scene or outputs");
+    if (sc->ctx != ctx) return fail(ctx, SDM_E_INVALID, "scene belongs to another context");
+    int rc = validate_params(ctx, p);
+    if (rc) return rc;
+    if (out->spectral && out->spectral_mem == SDM_MEM_DEVICE && !ptr_is_device(out->spectral))
+        return fail(ctx, SDM_E_INVALID, "spectral output is not device memory");
+    if (out->xyz && out->xyz_mem == SDM_MEM_DEVICE && !ptr_is_device(out->xyz))
+        return fail(ctx, SDM_E_INVALID, "xyz output is not device memory");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (p->precision == SDM_PREC_FP64) return render_impl<double>(ctx, sc, p, out, s);
+    return render_impl<float>(ctx, sc, p, out, s);
+}
+
+int sdm_slab_eval(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm, const float *d_mm,
+                  const float *n, const float *k, const float *alpha_tint, float *R, float *T, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (m < 0) return fail(ctx, SDM_E_INVALID, "negative size");
+    if (m == 0) return SDM_OK;
+    if (!cos_i || !lambda_nm || !d_mm || !n || !k || !R || !T)
+        return fail(ctx, SDM_E_INVALID, "null array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    launch_slab_eval(m, cos_i, lambda_nm, d_mm, n, k, alpha_tint, R, T, (hipStream_t)hip_stream);
+    HIPCHK(ctx, hipGetLastError());
+    return SDM_OK;
+}
+
+int sdm_debug_intersect(sdm_context *ctx, const sdm_scene *sc, int64_t m, const float *o, const float *d,
+                        const int32_t *skip, float *t, int32_t *tri, float *uv, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!sc || m < 0) return fail(ctx, SDM_E_INVALID, "bad scene or size");
+    if (m == 0) return SDM_OK;
+    if (!o || !d || !t || !tri || !uv) return fail(ctx, SDM_E_INVALID, "null array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
+    HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * kGlobalStack * sizeof(int32_t)));
+    launch_debug_intersect(sc->dev, m, o, d, skip, sc->orig_to_leaf.as<int32_t>(), t, tri, uv,
+                           ctx->gstack.as<int32_t>(), grid, (hipStream_t)hip_stream);
+    HIPCHK(ctx, hipGetLastError());
+    return SDM_OK;
+}
+
+int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const float *o, const int32_t *skip,
+                     float lambda_nm, float *T, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!sc || m < 0) return fail(ctx, SDM_E_INVALID, "bad scene or size");
+    if (m == 0) return SDM_OK;
+    if (!o || !T) return fail(ctx, SDM_E_INVALID, "null array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nm = sc->n_mat;
+    HIPCHK(ctx, ctx->slab_tmp.ensure(256 + 4 * (size_t)nm * sizeof(float)));
+    float *lam = ctx->slab_tmp.as<float>();
+    float *tabs = lam + 64;  // [4][nm] : rho, n, k, tint at lambda
+    HIPCHK(ctx, hipMemcpyAsync(lam, &lambda_nm, sizeof(float), hipMemcpyHostToDevice, s));
+    launch_resample<float>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lam, 1, tabs, s);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
+    HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * kGlobalStack * sizeof(int32_t)));
+    launch_debug_shadow(sc->dev, m, o, skip, sc->orig_to_leaf.as<int32_t>(), lambda_nm, tabs + nm, tabs + 2 * nm,
+                        tabs + 3 * nm, T, ctx->gstack.as<int32_t>(), grid, s);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return SDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// sdm_dev.hpp -- device-side building blocks of the spectral wavefront tracer
+// (gfx950, wave64).  Templated on the geometry/shading precision R (float for
+// production, double for the validation build of the same kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sdm_types.hpp"
+
+namespace sdm {
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+// SC'11).  Each round multiplies words 0 and 2 by the round constants, mixes
+// the high halves with words 1 and 3 and the key, and bumps the key by the
+// Weyl increments.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint2 k)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Uniform in [0, 1) from the top 24 bits: exact in float and double.
+template <class R>
+__device__ __forceinline__ R u01(uint32_t x)
+{
+    return R(x >> 8) * R(1.0 / 16777216.0);
+}
+
+// Draws of one path vertex: counter (pixel, sample, (vertex+1) << 16 | call,
+// job word), key = seed.  Vertex -1 is the camera.  The wavelength is not in
+// the counter: every wavelength of a (pixel, sample) sees the same numbers,
+// which is what lets one ray carry a whole spectral band.
+__device__ __forceinline__ uint4 vertex_draws(uint64_t seed, uint32_t job_word, uint32_t pixel,
+                                              uint32_t sample, int vertex, uint32_t call)
+{
+    return philox10(make_uint4(pixel, sample, ((uint32_t)(vertex + 1) << 16) | call, job_word),
+                    make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+}
+
+// ---------------------------------------------------------------------------
+// Small vector type
+// ---------------------------------------------------------------------------
+template <class R>
+struct V3 {
+    R x, y, z;
+};
+template <class R> __device__ __forceinline__ V3<R> mk(R x, R y, R z) { return V3<R>{x, y, z}; }
+template <class R> __device__ __forceinline__ V3<R> operator+(V3<R> a, V3<R> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class R> __device__ __forceinline__ V3<R> operator-(V3<R> a, V3<R> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class R> __device__ __forceinline__ V3<R> operator*(R s, V3<R> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class R> __device__ __forceinline__ R dot(V3<R> a, V3<R> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class R> __device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class R> __device__ __forceinline__ V3<R> normalize(V3<R> a)
+{
+    R l = sqrt(dot(a, a));
+    return l > R(0) ? V3<R>{a.x / l, a.y / l, a.z / l} : a;
+}
+template <class R> __device__ __forceinline__ V3<R> from4(float4 f) { return {R(f.x), R(f.y), R(f.z)}; }
+
+// Tangent basis about unit n from the fixed axis h = (1, 2, 3) / sqrt(14):
+// t1 = normalize(h x n), t2 = n x t1.  Continuous for every normal but +-h,
+// so vertical and axis-aligned faces get the same basis whatever the sign of
+// the rounding residue in their normal's zero components.
+template <class R>
+__device__ __forceinline__ void onb(V3<R> n, V3<R> &t1, V3<R> &t2)
+{
+    const V3<R> h = {R(0.2672612419124244), R(0.5345224838248488), R(0.8017837257372732)};
+    t1 = normalize(cross(h, n));
+    t2 = cross(n, t1);
+}
+
+// Cosine-weighted direction about n: uniform disk point (r = sqrt(u1),
+// phi = 2 pi u2) lifted to the hemisphere.
+template <class R>
+__device__ __forceinline__ V3<R> cosine_dir(V3<R> n, R u1, R u2)
+{
+    V3<R> t1, t2;
+    onb(n, t1, t2);
+    const R r = sqrt(u1), phi = R(6.283185307179586) * u2, lz = sqrt(R(1) - u1);
+    R s, c;
+    if constexpr (sizeof(R) == 4) sincosf(phi, &s, &c);
+    else sincos(phi, &s, &c);
+    return (r * c) * t1 + (r * s) * t2 + lz * n;
+}
+
+// ---------------------------------------------------------------------------
+// Glass: thin slab with Fresnel interfaces for n~ = n + ik (eq. (1)).
+// ---------------------------------------------------------------------------
+// Principal square root of a complex number (re >= 0), written to avoid
+// cancellation in the smaller component.
+template <class R>
+__device__ __forceinline__ void csqrt_p(R zr, R zi, R &sr, R &si)
+{
+    const R m = hypot(zr, zi);
+    if (m == R(0)) { sr = R(0); si = R(0); return; }
+    if (zr >= R(0)) {
+        sr = sqrt(R(0.5) * (m + zr));
+        si = zi / (R(2) * sr);
+    } else {
+        R t = sqrt(R(0.5) * (m - zr));
+        si = copysign(t, zi);
+        sr = fabs(zi) / (R(2) * t);
+    }
+}
+
+// Interface reflectances air -> n + ik at incidence cosine c, s and p.
+template <class R>
+__device__ __forceinline__ void fresnel_sp(R c, R n, R k, R &Rs, R &Rp)
+{
+    c = fmin(fmax(c, R(0)), R(1));
+    const R s2 = R(1) - c * c;
+    const R a = n * n - k * k, b = R(2) * n * k;     // n~^2
+    const R m = a * a + b * b;
+    // cos(theta_t) = sqrt(1 - s2 / n~^2) on the principal branch
+    R cr, ci;
+    csqrt_p(R(1) - s2 * a / m, s2 * b / m, cr, ci);
+    const R x = n * cr - k * ci, y = n * ci + k * cr; // n~ cos(theta_t)
+    Rs = ((c - x) * (c - x) + y * y) / ((c + x) * (c + x) + y * y);
+    const R px = n * c, py = k * c;                  // n~ cos(theta_i)
+    Rp = ((px - cr) * (px - cr) + (py - ci) * (py - ci)) /
+         ((px + cr) * (px + cr) + (py + ci) * (py + ci));
+}
+
+template <class R>
+__device__ __forceinline__ void slab_pol(R r, R tau, R &Rr, R &Tt)
+{
+    if (r >= R(1)) { Rr = R(1); Tt = R(0); return; }
+    const R q = R(1) - r;
+    const R den = R(1) - r * r * tau * tau;
+    Rr = r + q * q * r * tau * tau / den;
+    Tt = q * q * tau / den;
+}
+
+// Slab reflectance/transmittance: Fresnel per polarisation at both faces,
+// Beer-Lambert attenuation exp(-alpha d / cos(theta_t)) with alpha = 4 pi k /
+// lambda + alpha_tint and the real Snell angle, incoherent multiple
+// reflections summed in closed form, s and p averaged.
+template <class R>
+__device__ __forceinline__ void slab_RT(R c, R lambda_nm, R d_mm, R n, R k, R tint, R &Rout, R &Tout)
+{
+    R Rs, Rp;
+    fresnel_sp(c, n, k, Rs, Rp);
+    c = fmin(fmax(c, R(0)), R(1));
+    const R st = sqrt(fmax(R(1) - c * c, R(0))) / n;
+    const R ct2 = R(1) - st * st;
+    const R ct = ct2 > R(0) ? sqrt(ct2) : R(0);
+    const R alpha = R(12.566370614359172) * k / (lambda_nm * R(1e-6)) + tint;
+    const R ad = alpha * d_mm;
+    const R tau = (ad == R(0)) ? R(1) : (ct > R(0) ? exp(-ad / ct) : R(0));
+    R R1, T1, R2, T2;
+    slab_pol(Rs, tau, R1, T1);
+    slab_pol(Rp, tau, R2, T2);
+    Rout = R(0.5) * (R1 + R2);
+    Tout = R(0.5) * (T1 + T2);
+}
+
+// ---------------------------------------------------------------------------
+// Ray-triangle (Moeller-Trumbore 1997): two-sided, edges inclusive.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ bool tri_hit(V3<R> o, V3<R> d, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u, R &v)
+{
+    const V3<R> e1 = p1 - p0, e2 = p2 - p0;
+    const V3<R> pv = cross(d, e2);
+    const R det = dot(e1, pv);
+    if (det == R(0)) return false;
+    const R inv = R(1) / det;
+    const V3<R> sv = o - p0;
+    u = dot(sv, pv) * inv;
+    if (u < R(0) || u > R(1)) return false;
+    const V3<R> qv = cross(sv, e1);
+    v = dot(d, qv) * inv;
+    if (v < R(0) || u + v > R(1)) return false;
+    t = dot(e2, qv) * inv;
+    return true;
+}
+
+// Slab test against an axis-aligned box given the reciprocal direction; the
+// boxes are padded at build time, so rounding never loses a hit.
+template <class R>
+__device__ __forceinline__ bool box_hit(const float lo[3], const float hi[3], V3<R> o, V3<R> inv,
+                                        R tlo, R thi, R &tnear)
+{
+    R t1 = (R(lo[0]) - o.x) * inv.x, t2 = (R(hi[0]) - o.x) * inv.x;
+    R a = fmin(t1, t2), b = fmax(t1, t2);
+    t1 = (R(lo[1]) - o.y) * inv.y; t2 = (R(hi[1]) - o.y) * inv.y;
+    a = fmax(a, fmin(t1, t2)); b = fmin(b, fmax(t1, t2));
+    t1 = (R(lo[2]) - o.z) * inv.z; t2 = (R(hi[2]) - o.z) * inv.z;
+    a = fmax(a, fmin(t1, t2)); b = fmin(b, fmax(t1, t2));
+    tnear = a;
+    return a <= b && b >= tlo && a <= thi;
+}
+
+template <class R>
+__device__ __forceinline__ V3<R> safe_inv(V3<R> d)
+{
+    const R tiny = sizeof(R) == 4 ? R(1e-20) : R(1e-200);
+    auto f = [&](R x) -> R { return R(1) / (fabs(x) < tiny ? (x < R(0) ? -tiny : tiny) : x); };
+    return V3<R>{f(d.x), f(d.y), f(d.z)};
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level compaction: one atomic per wave per queue.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// All lanes of the wave must call this together.  Returns the slot of each
+// lane with pred set (undefined for the others).
+__device__ __forceinline__ uint32_t wave_reserve(bool pred, uint32_t *counter)
+{
+    const uint64_t m = __ballot(pred);
+    const uint32_t lane = lane_id();
+    const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    uint32_t base = 0;
+    if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        if ((int)lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+    }
+    return base + before;
+}
+
+}  // namespace sdm

@@ -1,0 +1,116 @@
+// sdm_types.hpp -- data layouts shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdm {
+
+// BVH2 node: the boxes of both children (so one node fetch tests two boxes)
+// and, per child, either an inner-node index (count 0), a leaf (first
+// triangle, count > 0) or nothing (index -1, count 0, empty box).  Nodes are
+// stored breadth-first so the top levels are a prefix that kernels stage in
+// LDS.  64 bytes = four 16-byte loads.
+struct alignas(16) BvhNode {
+    float lo0[3], hi0[3], lo1[3], hi1[3];
+    int32_t c0, c1, n0, n1;
+};
+static_assert(sizeof(BvhNode) == 64, "node layout");
+
+// Triangle in BVH leaf order: the three vertices (exact float inputs, edges
+// are formed in the kernel's precision); a.w holds the caller's triangle
+// index, b.w the material index (integer bits).
+struct alignas(16) TriDev {
+    float4 a, b, c;
+};
+
+// Scene data resident on the device.
+struct SceneDev {
+    const BvhNode *nodes;
+    const TriDev *tris;
+    const float4 *thick;        // per leaf-order triangle: vertex thickness (mm)
+    const int32_t *mat_type;    // [n_mat]
+    const float *mat_thick;     // [n_mat] default thickness
+    int32_t n_nodes, nt, n_mat, has_vthick;
+    float sun[3];
+    float teps_f;
+    double teps_d;
+};
+
+// One render job (an image of one scene).  Spectral tables are in the
+// kernel precision at the job's render wavelengths, [n_mat][nl] row-major.
+struct JobDev {
+    SceneDev sc;
+    double eye[3], f[3], r[3], u[3];
+    double th, aspect, oh;
+    int32_t projection, W, H, spp, nl, max_depth;
+    uint64_t seed;
+    uint32_t job_word;
+    uint32_t pad0;
+    uint64_t acc_off;           // offset of this job's accumulator (doubles)
+    const void *rho, *n, *k, *tint, *E, *Lsky, *lam;
+    double beta_thr;
+};
+
+// Spectral band (sub-domain): wavelengths [l0, l0 + nb) of a job.
+struct BandDev {
+    int32_t job, l0, nb, pad;
+};
+
+// Work item: a band x pixel tile x sample range; rays of an item are
+// numbered pixel-major, sample-minor, starting at `first`.
+struct ItemDev {
+    int32_t band, x0, y0, tw, th, s0, ns, pad;
+    uint64_t first;
+};
+
+// Device counters (zeroed by kernels, never by memset, so a captured graph
+// replays cleanly).
+struct Counters {
+    uint32_t qcount[2];         // ray queues
+    uint32_t scount;            // shadow queue
+    uint32_t fork_next;         // next free fork slot in the path pool
+    uint32_t overflow;          // set when a fork found the pool full
+    uint32_t pad[3];
+    unsigned long long closest, shadow, forks;
+    unsigned long long nodes[2], tris[2];  // traversal work [closest, shadow]: node fetches, triangle tests
+};
+
+// Wavefront state.  Path pool (SoA, stable slots), index queues, hit records
+// (by queue position) and the shadow queue (SoA).  Per-wavelength arrays are
+// [j][slot] so consecutive slots of one wavelength are contiguous.
+template <class R>
+struct Work {
+    R *ox, *oy, *oz, *dx, *dy, *dz;
+    uint32_t *pix, *smp, *aux;  // aux = depth | band << 8 | job << 20
+    int32_t *skip;
+    R *beta;
+    uint32_t *q[2];
+    R *ht, *hu, *hv;
+    int32_t *htri;
+    R *sx, *sy, *sz;
+    int32_t *sskip;
+    uint32_t *spix, *saux;
+    R *contrib;
+    double *acc;
+    Counters *cnt;
+    uint32_t cap;               // pool slots = queue capacity
+    uint32_t primary_cap;       // slots reserved for primary rays of a chunk
+    int32_t *gstack;            // traversal stack overflow (global)
+    uint32_t gstack_threads;    // threads the overflow stack is sized for
+};
+
+constexpr int kAuxDepthBits = 8;
+constexpr int kAuxBandShift = 8;
+constexpr int kAuxBandBits = 12;
+constexpr int kAuxJobShift = 20;
+constexpr int kMaxBand = 128;
+constexpr int kLdsStack = 16;      // traversal stack levels held in LDS
+constexpr int kGlobalStack = 48;   // further levels in global memory
+constexpr int kMaxBvhDepth = kLdsStack + kGlobalStack - 2;
+
+__host__ __device__ inline uint32_t pack_aux(int depth, int band, int job)
+{
+    return (uint32_t)depth | ((uint32_t)band << kAuxBandShift) | ((uint32_t)job << kAuxJobShift);
+}
+
+}  // namespace sdm

@@ -1,0 +1,281 @@
+"""Python binding of ``libsdm.so`` (include/sdm.h): argument marshalling only.
+
+PyTorch provides device memory and streams; every step of the render runs in
+the library's HIP kernels.  There is no CPU fallback: if the library or a GPU
+is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdm.so")
+
+SDM_OK = 0
+SDM_MEM_HOST, SDM_MEM_DEVICE = 0, 1
+SDM_PREC_FP32, SDM_PREC_FP64 = 0, 1
+KERNELS = ("generate", "trace", "shade", "shadow", "finalize")
+
+_FP = C.POINTER(C.c_float)
+
+
+class Material(C.Structure):
+    _fields_ = [("type", C.c_int32), ("albedo", _FP), ("n", _FP), ("k", _FP), ("alpha_tint", _FP),
+                ("thick_mm", C.c_float), ("bubble_density_mm3", C.c_float),
+                ("bubble_rmin_um", C.c_float), ("bubble_rmax_um", C.c_float),
+                ("pane_id", C.c_int32)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("pos", _FP), ("vthick_mm", _FP), ("nt", C.c_int32),
+                ("idx", C.POINTER(C.c_int32)), ("mat", C.POINTER(C.c_int32)),
+                ("n_mat", C.c_int32), ("mats", C.POINTER(Material)), ("n_tab", C.c_int32),
+                ("tab_lambda_nm", _FP), ("sun_dir", C.c_float * 3), ("sun_E", _FP),
+                ("sky_L", _FP)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float), ("ortho_height", C.c_float), ("W", C.c_int32),
+                ("H", C.c_int32), ("projection", C.c_int32)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("camera", Camera), ("n_lambda", C.c_int32), ("lambda_nm", _FP),
+                ("cmf_xyz", _FP), ("spp", C.c_int32), ("max_depth", C.c_int32),
+                ("seed", C.c_uint64), ("job_id", C.c_uint32), ("n_bands", C.c_int32),
+                ("band_edges", C.POINTER(C.c_int32)), ("tile_w", C.c_int32),
+                ("tile_h", C.c_int32), ("beta_threshold", C.c_float), ("precision", C.c_int32),
+                ("chunk_paths", C.c_int64), ("timing", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("spectral_samples", C.c_uint64), ("paths", C.c_uint64),
+                ("closest_segments", C.c_uint64), ("shadow_segments", C.c_uint64),
+                ("forks", C.c_uint64), ("chunks", C.c_uint64), ("nodes_visited", C.c_uint64 * 2),
+                ("tris_tested", C.c_uint64 * 2), ("ms_render", C.c_double),
+                ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_uint64 * 5)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_[:6]}
+        d["ms_render"] = self.ms_render
+        d["nodes_visited"] = {"closest": int(self.nodes_visited[0]), "shadow": int(self.nodes_visited[1])}
+        d["tris_tested"] = {"closest": int(self.tris_tested[0]), "shadow": int(self.tris_tested[1])}
+        d["kernel_ms"] = {k: self.kernel_ms[i] for i, k in enumerate(KERNELS)}
+        d["kernel_launches"] = {k: int(self.kernel_launches[i]) for i, k in enumerate(KERNELS)}
+        return d
+
+
+class Outputs(C.Structure):
+    _fields_ = [("spectral", C.c_void_p), ("xyz", C.c_void_p), ("spectral_mem", C.c_int32),
+                ("xyz_mem", C.c_int32), ("stats", C.POINTER(Stats))]
+
+
+class SdmError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libsdm.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SdmError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.sdm_context_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.sdm_context_destroy.argtypes = [vp]
+        L.sdm_last_error.restype = C.c_char_p
+        L.sdm_last_error.argtypes = [vp]
+        L.sdm_scene_create.argtypes = [vp, C.POINTER(SceneDesc), C.POINTER(vp)]
+        L.sdm_scene_destroy.argtypes = [vp]
+        L.sdm_scene_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sdm_render.argtypes = [vp, vp, C.POINTER(RenderParams), C.POINTER(Outputs), vp]
+        L.sdm_slab_eval.argtypes = [vp, C.c_int64] + [vp] * 9
+        L.sdm_debug_intersect.argtypes = [vp, vp, C.c_int64] + [vp] * 7
+        L.sdm_debug_shadow.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_float, vp, vp]
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_scene_create",
+            "sdm_scene_destroy", "sdm_scene_info", "sdm_render", "sdm_slab_eval",
+            "sdm_debug_intersect", "sdm_debug_shadow")
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _f32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+class Context:
+    def __init__(self, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise SdmError("no GPU available")
+        self.device = device
+        self.ptr = C.c_void_p()
+        rc = lib().sdm_context_create(device, C.byref(self.ptr))
+        if rc != SDM_OK:
+            raise SdmError(f"sdm_context_create failed ({rc})")
+
+    def check(self, rc, what):
+        if rc != SDM_OK:
+            msg = lib().sdm_last_error(self.ptr).decode(errors="replace")
+            raise SdmError(f"{what} failed ({rc}): {msg}")
+
+    def close(self):
+        if self.ptr:
+            lib().sdm_context_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scene:
+    """Uploads a ``synth.Scene``-like object (pos, idx, mat, materials, tables)."""
+
+    def __init__(self, ctx: Context, scene):
+        self.ctx = ctx
+        keep = []
+        pos = _f32(scene.pos.reshape(-1))
+        vth = _f32(scene.vthick)
+        idx = np.ascontiguousarray(scene.idx.reshape(-1), dtype=np.int32)
+        mat = np.ascontiguousarray(scene.mat, dtype=np.int32)
+        tab = _f32(scene.tab_lambda)
+        fp = lambda a: a.ctypes.data_as(_FP) if a is not None else None
+        mats = (Material * max(1, len(scene.materials)))()
+        for i, m in enumerate(scene.materials):
+            arrs = [_f32(m.albedo), _f32(m.n), _f32(m.k), _f32(m.alpha_tint)]
+            keep += arrs
+            mats[i] = Material(int(m.type), *[fp(a) for a in arrs], float(m.thick_mm),
+                               float(m.bubble_density), float(m.bubble_rmin_um),
+                               float(m.bubble_rmax_um), int(m.pane_id))
+        sE, sL = _f32(scene.sun_E), _f32(scene.sky_L)
+        keep += [pos, vth, idx, mat, tab, sE, sL]
+        d = SceneDesc(len(scene.pos), fp(pos), fp(vth), int(scene.idx.shape[0]),
+                      idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                      mat.ctypes.data_as(C.POINTER(C.c_int32)), len(scene.materials), mats,
+                      len(tab), fp(tab), (C.c_float * 3)(*[float(x) for x in scene.sun_dir]),
+                      fp(sE), fp(sL))
+        self.ptr = C.c_void_p()
+        ctx.check(lib().sdm_scene_create(ctx.ptr, C.byref(d), C.byref(self.ptr)), "sdm_scene_create")
+        self.nt = int(scene.idx.shape[0])
+
+    def info(self):
+        n, dep = C.c_int32(), C.c_int32()
+        lib().sdm_scene_info(self.ptr, C.byref(n), C.byref(dep))
+        return {"n_nodes": n.value, "depth": dep.value}
+
+    def close(self):
+        if self.ptr:
+            lib().sdm_scene_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision="fp32",
+                chunk_paths=0, timing=False):
+    cam = settings.camera
+    lam = _f32(settings.lambda_nm)
+    cmf = _f32(np.asarray(settings.cmf).reshape(-1))
+    keep = [lam, cmf]
+    be = None
+    nb = int(settings.n_bands if n_bands is None else n_bands)
+    if band_edges is not None:
+        be = np.ascontiguousarray(band_edges, dtype=np.int32)
+        keep.append(be)
+        nb = len(be) - 1
+    p = RenderParams(
+        Camera((C.c_float * 3)(*cam.eye), (C.c_float * 3)(*cam.target), (C.c_float * 3)(*cam.up),
+               float(cam.vfov_deg), float(cam.ortho_height), int(cam.W), int(cam.H),
+               int(cam.projection)),
+        len(lam), lam.ctypes.data_as(_FP), cmf.ctypes.data_as(_FP), int(settings.spp),
+        int(settings.max_depth), int(settings.seed), int(settings.job_id), nb,
+        be.ctypes.data_as(C.POINTER(C.c_int32)) if be is not None else None,
+        int(tile[0]), int(tile[1]), float(settings.beta_threshold),
+        SDM_PREC_FP64 if precision == "fp64" else SDM_PREC_FP32, int(chunk_paths), int(timing))
+    return p, keep
+
+
+def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, tile=(0, 0),
+           precision="fp32", chunk_paths=0, timing=False, stream=None, spectral=True, xyz=True):
+    """Render into new device tensors: (spectral (H, W, nl) float32, xyz (H, W, 3) float64,
+    stats dict)."""
+    import torch
+    cam = settings.camera
+    nl = len(settings.lambda_nm)
+    dev = torch.device("cuda", ctx.device)
+    spec_t = torch.empty((cam.H, cam.W, nl), dtype=torch.float32, device=dev) if spectral else None
+    xyz_t = torch.empty((cam.H, cam.W, 3), dtype=torch.float64, device=dev) if xyz else None
+    p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing)
+    st = Stats()
+    out = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, C.pointer(st))
+    ctx.check(lib().sdm_render(ctx.ptr, scene.ptr, C.byref(p), C.byref(out), _stream(stream)),
+              "sdm_render")
+    return spec_t, xyz_t, st.as_dict()
+
+
+def render_into(ctx: Context, scene: Scene, params, spec_t, xyz_t, stream=None):
+    """Render with prepared params into existing device tensors; returns stats."""
+    st = Stats()
+    out = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, C.pointer(st))
+    ctx.check(lib().sdm_render(ctx.ptr, scene.ptr, C.byref(params), C.byref(out), _stream(stream)),
+              "sdm_render")
+    return st.as_dict()
+
+
+def slab_eval(ctx: Context, cos_i, lambda_nm, d_mm, n, k, alpha_tint, stream=None):
+    """Device float32 tensors of equal length -> (R, T) device tensors."""
+    import torch
+    m = cos_i.numel()
+    R = torch.empty_like(cos_i)
+    T = torch.empty_like(cos_i)
+    ctx.check(lib().sdm_slab_eval(ctx.ptr, m, _ptr(cos_i), _ptr(lambda_nm), _ptr(d_mm), _ptr(n),
+                                  _ptr(k), _ptr(alpha_tint), _ptr(R), _ptr(T), _stream(stream)),
+              "sdm_slab_eval")
+    return R, T
+
+
+def debug_intersect(ctx: Context, scene: Scene, o, d, skip=None, stream=None):
+    import torch
+    m = o.shape[0]
+    t = torch.empty(m, dtype=torch.float32, device=o.device)
+    tri = torch.empty(m, dtype=torch.int32, device=o.device)
+    uv = torch.empty((m, 2), dtype=torch.float32, device=o.device)
+    ctx.check(lib().sdm_debug_intersect(ctx.ptr, scene.ptr, m, _ptr(o), _ptr(d), _ptr(skip), _ptr(t),
+                                        _ptr(tri), _ptr(uv), _stream(stream)), "sdm_debug_intersect")
+    return t, tri, uv
+
+
+def debug_shadow(ctx: Context, scene: Scene, o, lambda_nm, skip=None, stream=None):
+    import torch
+    m = o.shape[0]
+    T = torch.empty(m, dtype=torch.float32, device=o.device)
+    ctx.check(lib().sdm_debug_shadow(ctx.ptr, scene.ptr, m, _ptr(o), _ptr(skip), float(lambda_nm),
+                                     _ptr(T), _stream(stream)), "sdm_debug_shadow")
+    return T

@@ -36,12 +36,49 @@ def kernel_models(stats, nb, npix, nl):
         "generate": ("hbm", Ng * (44 + 4 * nb)),
         "trace": ("alu", stats["nodes_visited"]["closest"] * FLOPS_PER_NODE
                   + stats["tris_tested"]["closest"] * FLOPS_PER_TRI),
-        "shade": ("hbm", Nc * (92 + 8 * nb) + Ns * (24 + 4 * nb) + F * (44 + 8 * nb)),
+        "shade": ("hbm", Nc * (84 + 8 * nb) + Ns * (24 + 4 * nb) + F * (40 + 4 * nb)),
         "shadow": ("alu", stats["nodes_visited"]["shadow"] * FLOPS_PER_NODE
                    + stats["tris_tested"]["shadow"] * FLOPS_PER_TRI),
+        "shadow_accum": ("hbm", Ns * (16 + 4 * nb)),
+        "shade_glass": ("alu", 0),
         "finalize": ("hbm", npix * nl * 12 + npix * 24),
     }
     return m
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel factors),
+    or None when the kernel source has changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "nave512_pmc_traffic.json")
+    src = os.path.join(ROOT, "paper_1912_05494_amd", "csrc", "wavefront.hip")
+    try:
+        meta = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if meta.get("kernel_source_sha256") != sha or kernel not in meta.get("kernels", {}):
+        return None
+    return meta["kernels"][kernel]["bytes_per_launch"]
+
+
+def profile_once():
+    """One render of the workload, then a 256 MiB device-to-device copy whose
+    FETCH_SIZE / WRITE_SIZE calibrate the traffic counters."""
+    import torch
+    from paper_1912_05494_amd import sdm, synth
+    ctx = sdm.Context(0)
+    gs = sdm.Scene(ctx, synth.nave_scene(seed=1))
+    spec, xyz, stats = sdm.render(ctx, gs, synth.nave_settings())
+    torch.cuda.synchronize()
+    a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"closest": stats["closest_segments"], "shadow": stats["shadow_segments"],
+                      "copy_bytes": a.numel() * 4}), flush=True)
+    ctx.close()
 
 
 def cpu_baseline(scene, settings, budget_s=12.0, max_pixels=4096):
@@ -83,7 +120,12 @@ def main():
     ap.add_argument("--bands", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-once", action="store_true",
+                    help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
+    if args.profile_once:
+        profile_once()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the spectral and pixel sub-domains are work items of a single device)",
@@ -158,7 +200,7 @@ def main():
                    "W": W, "H": H, "spp": st.spp, "n_lambda": nl, "max_depth": st.max_depth,
                    "triangles": scene.nt, "bands": args.bands, "accumulation": "f64"},
         "roofline": {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
-                     "unit": kd["unit"], "frac": kd["frac"], "traffic": None},
+                     "unit": kd["unit"], "frac": kd["frac"], "traffic": measured_traffic(dom)},
         "kernels": kernels,
         "segments_per_s": (s["closest_segments"] + s["shadow_segments"]) * args.steps / dt,
         "distinct_rays_per_step": {"closest": s["closest_segments"], "shadow": s["shadow_segments"],

@@ -117,7 +117,7 @@ typedef struct {
 
 /* Kernel classes reported in sdm_stats. */
 enum { SDM_K_GENERATE = 0, SDM_K_TRACE = 1, SDM_K_SHADE = 2, SDM_K_SHADOW = 3,
-       SDM_K_FINALIZE = 4, SDM_K_COUNT = 5 };
+       SDM_K_FINALIZE = 4, SDM_K_SHADOW_ACCUM = 5, SDM_K_SHADE_GLASS = 6, SDM_K_COUNT = 7 };
 
 typedef struct {
     uint64_t spectral_samples;  /* W*H*spp*n_lambda                            */

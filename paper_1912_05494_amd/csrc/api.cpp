@@ -48,7 +48,7 @@ struct sdm_context {
     std::string err;
     DevBuf gstack;
     // render work buffers (one set; reallocated when a render needs more)
-    DevBuf pool, queue0, queue1, hits, shadowq, acc, counters, jobs, bands, items, tables, outs;
+    DevBuf pool, hits, shadowq, acc, counters, jobs, bands, items, tables, outs;
     Counters *host_counters = nullptr;
     std::vector<hipEvent_t> events;
     DevBuf slab_tmp;
@@ -161,7 +161,7 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     for (int i = 1; i < d->n_tab; ++i)
         if (!(d->tab_lambda_nm[i] > d->tab_lambda_nm[i - 1]))
             return fail(ctx, SDM_E_INVALID, "tab_lambda_nm must be strictly increasing");
-    if ((int64_t)d->nt >= (1ll << 30)) return fail(ctx, SDM_E_UNSUPPORTED, "too many triangles");
+    if ((int64_t)d->nt >= (int64_t)kMaxTris - 1) return fail(ctx, SDM_E_UNSUPPORTED, "too many triangles");
     for (int32_t t = 0; t < d->nt; ++t) {
         for (int c = 0; c < 3; ++c)
             if (d->idx[3 * (size_t)t + c] < 0 || d->idx[3 * (size_t)t + c] >= d->nv)
@@ -189,6 +189,11 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     sc->n_mat = d->n_mat;
     sc->nt = d->nt;
     BvhResult bvh = build_bvh(d->pos, d->nv, d->idx, d->nt);
+    if (!bvh.ok) {
+        delete sc;
+        return fail(ctx, SDM_E_UNSUPPORTED, "scene too degenerate: a BVH leaf at the depth limit holds > %d triangles",
+                    kMaxLeafTris);
+    }
     sc->depth = bvh.depth;
     sc->n_nodes = (int32_t)bvh.nodes.size();
     std::vector<TriDev> tris(d->nt);
@@ -486,48 +491,56 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
     chunk = std::max<uint64_t>(chunk, 1);
     int attempt = 0;
     for (;;) {
-        const uint64_t cap64 = chunk * (2ull << attempt);
+        // pool capacity: the chunk plus headroom for forks (doubled on overflow)
+        const uint64_t cap64 = ((chunk + (chunk >> 2) * (1ull << attempt) + 1024 + 63) / 64) * 64;
         if (cap64 >= (1ull << 31)) return fail(ctx, SDM_E_NOMEM, "path pool would exceed 2^31 slots");
         const uint32_t cap = (uint32_t)cap64;
         const int nb = plan.nbmax;
-        const size_t pool_b = cap * (6 * sizeof(R) + 4 * 4 + (size_t)nb * sizeof(R));
-        const size_t hit_b = (size_t)cap * (3 * sizeof(R) + 4);
-        const size_t sh_b = (size_t)cap * (3 * sizeof(R) + 12 + (size_t)nb * sizeof(R));
-        HIPCHK(ctx, ctx->pool.ensure(pool_b));
-        HIPCHK(ctx, ctx->queue0.ensure((size_t)cap * 4));
-        HIPCHK(ctx, ctx->queue1.ensure((size_t)cap * 4));
-        HIPCHK(ctx, ctx->hits.ensure(hit_b));
-        HIPCHK(ctx, ctx->shadowq.ensure(sh_b));
+        const size_t plane = (size_t)cap * sizeof(R);
+        const size_t pool_b = 6 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R);
+        const size_t hit_b = 3 * plane + 2 * (size_t)cap * 4;
+        const size_t sh_b = 3 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
+                            (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R));
+        HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
+        HIPCHK(ctx, ctx->hits.ensure(hit_b + 2048));
+        HIPCHK(ctx, ctx->shadowq.ensure(sh_b + 2048));
         HIPCHK(ctx, ctx->acc.ensure((size_t)npix * nl * sizeof(double)));
         HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
         const int grid_t = ctx->num_cu * occupancy_trace<R>();
+        const int grid_st = ctx->num_cu * occupancy_shadow<R>();
         const int grid_s = ctx->num_cu * occupancy_shade<R>();
         const int grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
-        const size_t gthreads = (size_t)std::max(grid_t, grid_s) * block_size();
+        const size_t gthreads = (size_t)std::max(grid_t, grid_st) * block_size();
         HIPCHK(ctx, ctx->gstack.ensure(gthreads * kGlobalStack * sizeof(int32_t)));
         Work<R> w{};
-        char *pb = ctx->pool.as<char>();
-        auto take = [&](size_t bytes) { char *r = pb; pb += bytes; return r; };
-        w.ox = (R *)take(cap * sizeof(R)); w.oy = (R *)take(cap * sizeof(R)); w.oz = (R *)take(cap * sizeof(R));
-        w.dx = (R *)take(cap * sizeof(R)); w.dy = (R *)take(cap * sizeof(R)); w.dz = (R *)take(cap * sizeof(R));
-        w.pix = (uint32_t *)take(cap * 4); w.smp = (uint32_t *)take(cap * 4); w.aux = (uint32_t *)take(cap * 4);
-        w.skip = (int32_t *)take(cap * 4);
-        w.beta = (R *)take((size_t)cap * nb * sizeof(R));
-        w.q[0] = ctx->queue0.as<uint32_t>();
-        w.q[1] = ctx->queue1.as<uint32_t>();
+        char *pb = nullptr;
+        auto take = [&](size_t bytes) { char *r = pb; pb += (bytes + 255) / 256 * 256; return r; };
+        pb = ctx->pool.as<char>();
+        for (int q = 0; q < 2; ++q) {
+            Pool<R> &P = w.p[q];
+            P.ox = (R *)take(plane); P.oy = (R *)take(plane); P.oz = (R *)take(plane);
+            P.dx = (R *)take(plane); P.dy = (R *)take(plane); P.dz = (R *)take(plane);
+            P.pix = (uint32_t *)take((size_t)cap * 4); P.smp = (uint32_t *)take((size_t)cap * 4);
+            P.aux = (uint32_t *)take((size_t)cap * 4); P.skip = (int32_t *)take((size_t)cap * 4);
+            P.beta = (R *)take((size_t)cap * nb * sizeof(R));
+        }
         pb = ctx->hits.as<char>();
-        w.ht = (R *)take(cap * sizeof(R)); w.hu = (R *)take(cap * sizeof(R)); w.hv = (R *)take(cap * sizeof(R));
-        w.htri = (int32_t *)take(cap * 4);
+        w.ht = (R *)take(plane); w.hu = (R *)take(plane); w.hv = (R *)take(plane);
+        w.htri = (int32_t *)take((size_t)cap * 4);
+        w.gidx = (uint32_t *)take((size_t)cap * 4);
         pb = ctx->shadowq.as<char>();
-        w.sx = (R *)take(cap * sizeof(R)); w.sy = (R *)take(cap * sizeof(R)); w.sz = (R *)take(cap * sizeof(R));
-        w.sskip = (int32_t *)take(cap * 4); w.spix = (uint32_t *)take(cap * 4); w.saux = (uint32_t *)take(cap * 4);
+        w.sx = (R *)take(plane); w.sy = (R *)take(plane); w.sz = (R *)take(plane);
+        w.sskip = (int32_t *)take((size_t)cap * 4); w.spix = (uint32_t *)take((size_t)cap * 4);
+        w.saux = (uint32_t *)take((size_t)cap * 4); w.socc = (int32_t *)take((size_t)cap * 4);
         w.contrib = (R *)take((size_t)cap * nb * sizeof(R));
+        w.sg_leaf = (int32_t *)take((size_t)cap * kMaxGlass * 4);
+        w.sg_u = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
+        w.sg_v = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
         w.acc = ctx->acc.as<double>();
         w.cnt = ctx->counters.as<Counters>();
         w.cap = cap;
-        w.primary_cap = (uint32_t)chunk;
+        w.nbmax = nb;
         w.gstack = ctx->gstack.as<int32_t>();
-        w.gstack_threads = (uint32_t)gthreads;
 
         Timer tm{ctx, s, p->timing != 0};
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -543,8 +556,7 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
             const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, total - r0);
             int cur = 0;
             HIPCHK(ctx, tm.begin(SDM_K_GENERATE));
-            launch_generate<R>(jobs_d, bands_d, ctx->items.as<ItemDev>(), (int)plan.items.size(), w, r0, n, cur,
-                               grid_g, s);
+            launch_generate<R>(jobs_d, bands_d, ctx->items.as<ItemDev>(), (int)plan.items.size(), w, r0, n, grid_g, s);
             HIPCHK(ctx, tm.end());
             for (int dpt = 0; dpt < p->max_depth; ++dpt) {
                 HIPCHK(ctx, tm.begin(SDM_K_TRACE));
@@ -553,8 +565,14 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
                 HIPCHK(ctx, tm.begin(SDM_K_SHADE));
                 launch_shade<R>(jobs_d, bands_d, w, cur, grid_s, s);
                 HIPCHK(ctx, tm.end());
+                HIPCHK(ctx, tm.begin(SDM_K_SHADE_GLASS));
+                launch_shade_glass<R>(jobs_d, bands_d, w, cur, grid_s, s);
+                HIPCHK(ctx, tm.end());
                 HIPCHK(ctx, tm.begin(SDM_K_SHADOW));
-                launch_shadow<R>(jobs_d, bands_d, w, 0, grid_t, s);
+                launch_shadow_trace<R>(jobs_d, bands_d, w, 0, grid_st, s);
+                HIPCHK(ctx, tm.end());
+                HIPCHK(ctx, tm.begin(SDM_K_SHADOW_ACCUM));
+                launch_shadow_accum<R>(jobs_d, bands_d, w, grid_s, s);
                 HIPCHK(ctx, tm.end());
                 cur ^= 1;
             }
@@ -581,13 +599,18 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
         if (xyz_host && p->cmf_xyz) HIPCHK(ctx, hipMemcpyAsync(out->xyz, xyz_d, xyz_b, hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
         const Counters c = *ctx->host_counters;
+        if (c.overflow & 2u) {
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
+            return fail(ctx, SDM_E_UNSUPPORTED, "a shadow ray crossed more than %d glass panes", kMaxGlass);
+        }
         if (c.overflow) {
             (void)hipEventDestroy(ev0);
             (void)hipEventDestroy(ev1);
-            if (++attempt > 4)
-                return fail(ctx, SDM_E_DEVICE, "path pool overflow: more than %llu forks per chunk",
-                            (unsigned long long)(cap64 - chunk));
-            continue;  // deterministic: render again with a larger fork region
+            if (++attempt > 8)
+                return fail(ctx, SDM_E_DEVICE, "path pool overflow: glass forks exceed %llu slots",
+                            (unsigned long long)cap64);
+            continue;  // deterministic: render again with a larger pool
         }
         if (out->stats) {
             sdm_stats &st = *out->stats;
@@ -659,14 +682,17 @@ int sdm_debug_intersect(sdm_context *ctx, const sdm_scene *sc, int64_t m, const 
                         const int32_t *skip, float *t, int32_t *tri, float *uv, void *hip_stream)
 {
     if (!ctx) return SDM_E_INVALID;
-    if (!sc || m < 0) return fail(ctx, SDM_E_INVALID, "bad scene or size");
+    if (!sc || m < 0 || m >= (1ll << 31)) return fail(ctx, SDM_E_INVALID, "bad scene or size");
     if (m == 0) return SDM_OK;
     if (!o || !d || !t || !tri || !uv) return fail(ctx, SDM_E_INVALID, "null array");
     HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
     HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * kGlobalStack * sizeof(int32_t)));
-    launch_debug_intersect(sc->dev, m, o, d, skip, sc->orig_to_leaf.as<int32_t>(), t, tri, uv,
-                           ctx->gstack.as<int32_t>(), grid, (hipStream_t)hip_stream);
+    HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
+    launch_zero_counters(ctx->counters.as<Counters>(), s);
+    launch_debug_intersect(sc->dev, (uint32_t)m, o, d, skip, sc->orig_to_leaf.as<int32_t>(), t, tri, uv,
+                           &ctx->counters.as<Counters>()->tfetch, ctx->gstack.as<int32_t>(), grid, s);
     HIPCHK(ctx, hipGetLastError());
     return SDM_OK;
 }
@@ -675,7 +701,7 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const flo
                      float lambda_nm, float *T, void *hip_stream)
 {
     if (!ctx) return SDM_E_INVALID;
-    if (!sc || m < 0) return fail(ctx, SDM_E_INVALID, "bad scene or size");
+    if (!sc || m < 0 || m >= (1ll << 31)) return fail(ctx, SDM_E_INVALID, "bad scene or size");
     if (m == 0) return SDM_OK;
     if (!o || !T) return fail(ctx, SDM_E_INVALID, "null array");
     HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -688,8 +714,11 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const flo
     launch_resample<float>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lam, 1, tabs, s);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
     HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * kGlobalStack * sizeof(int32_t)));
-    launch_debug_shadow(sc->dev, m, o, skip, sc->orig_to_leaf.as<int32_t>(), lambda_nm, tabs + nm, tabs + 2 * nm,
-                        tabs + 3 * nm, T, ctx->gstack.as<int32_t>(), grid, s);
+    HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
+    launch_zero_counters(ctx->counters.as<Counters>(), s);
+    launch_debug_shadow(sc->dev, (uint32_t)m, o, skip, sc->orig_to_leaf.as<int32_t>(), lambda_nm, tabs + nm,
+                        tabs + 2 * nm, tabs + 3 * nm, T, &ctx->counters.as<Counters>()->sfetch,
+                        ctx->gstack.as<int32_t>(), grid, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
     return SDM_OK;

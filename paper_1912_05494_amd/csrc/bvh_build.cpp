@@ -60,6 +60,7 @@ struct Builder {
     std::vector<int32_t> prims;
     std::vector<TNode> nodes;
     int max_depth = 0;
+    bool too_big = false;   // a depth-capped leaf exceeds kMaxLeafTris
 
     int32_t make_leaf(const Box &b, int32_t first, int32_t count)
     {
@@ -140,7 +141,10 @@ struct Builder {
             mid = (int32_t)(it - prims.begin());
             if (mid == first || mid == first + count) mid = first + count / 2;
         }
-        if (depth + 1 >= kMaxBvhDepth) return make_leaf(b, first, count);
+        if (depth + 1 >= kMaxBvhDepth) {
+            if (count > kMaxLeafTris) too_big = true;
+            return make_leaf(b, first, count);
+        }
         TNode n;
         n.box = b;
         nodes.push_back(n);
@@ -197,6 +201,7 @@ BvhResult build_bvh(const float *pos, int32_t nv, const int32_t *idx, int32_t nt
     (void)nv;
     B.nodes.reserve(2 * (size_t)nt);
     const int32_t root = B.build(0, nt, 0);
+    out.ok = !B.too_big;
     double diag = 0.0;
     for (int a = 0; a < 3; ++a) diag += double(scene.hi[a] - scene.lo[a]) * (scene.hi[a] - scene.lo[a]);
     diag = std::sqrt(diag);

@@ -12,6 +12,7 @@ struct BvhResult {
     std::vector<BvhNode> nodes;   // breadth-first; empty for an empty scene
     std::vector<int32_t> order;   // leaf slot -> caller's triangle index
     int depth = 0;                // levels of inner nodes plus leaves
+    bool ok = true;               // false: a leaf at the depth cap is too large
 };
 
 BvhResult build_bvh(const float *pos, int32_t nv, const int32_t *idx, int32_t nt);

@@ -63,40 +63,59 @@ struct ItemDev {
     uint64_t first;
 };
 
-// Device counters (zeroed by kernels, never by memset, so a captured graph
-// replays cleanly).
+// Device counters.  Kernels clear the counters the next kernel needs (never
+// a memset), so a captured launch sequence replays cleanly.
 struct Counters {
-    uint32_t qcount[2];         // ray queues
-    uint32_t scount;            // shadow queue
-    uint32_t fork_next;         // next free fork slot in the path pool
-    uint32_t overflow;          // set when a fork found the pool full
-    uint32_t pad[3];
+    uint32_t count[2];          // paths in pool 0 / pool 1
+    uint32_t scount;            // shadow records
+    uint32_t tfetch, sfetch;    // work cursors of the two traversal kernels
+    uint32_t overflow;          // bit 0: a pool or record buffer was full;
+                                // bit 1: a shadow ray crossed more than kMaxGlass panes
+    uint32_t gcount;            // glass vertices queued for the glass shading pass
+    uint32_t pad;
     unsigned long long closest, shadow, forks;
-    unsigned long long nodes[2], tris[2];  // traversal work [closest, shadow]: node fetches, triangle tests
+    unsigned long long nodes[2], tris[2];   // traversal work [closest, shadow]
 };
 
-// Wavefront state.  Path pool (SoA, stable slots), index queues, hit records
-// (by queue position) and the shadow queue (SoA).  Per-wavelength arrays are
-// [j][slot] so consecutive slots of one wavelength are contiguous.
+// Per-wavelength arrays use an AoSoA layout: the values of wavelength j for
+// the 64 paths of block b = slot / 64 are contiguous, and a block holds all
+// nb_max wavelengths, so a wave that works on 64 consecutive slots touches one
+// contiguous region.
+__host__ __device__ __forceinline__ size_t aosoa(uint32_t slot, int j, int nbmax)
+{
+    return ((size_t)(slot >> 6) * (size_t)nbmax + (size_t)j) * 64u + (slot & 63u);
+}
+
+// Path pool (SoA).  Two pools alternate: shade reads one and writes the
+// survivors, compacted, into the other.
 template <class R>
-struct Work {
+struct Pool {
     R *ox, *oy, *oz, *dx, *dy, *dz;
     uint32_t *pix, *smp, *aux;  // aux = depth | band << 8 | job << 20
-    int32_t *skip;
-    R *beta;
-    uint32_t *q[2];
-    R *ht, *hu, *hv;
+    int32_t *skip;              // leaf-order index of the last hit triangle
+    R *beta;                    // AoSoA [slot][j] path weights
+};
+
+constexpr int kMaxGlass = 8;    // panes a shadow ray may cross (more: SDM_E_UNSUPPORTED)
+
+template <class R>
+struct Work {
+    Pool<R> p[2];
+    R *ht, *hu, *hv;            // closest hit per slot of the current pool
     int32_t *htri;
-    R *sx, *sy, *sz;
+    uint32_t *gidx;             // slots of the current pool at a glass vertex
+    R *sx, *sy, *sz;            // shadow records
     int32_t *sskip;
     uint32_t *spix, *saux;
-    R *contrib;
+    R *contrib;                 // AoSoA [record][j]
+    int32_t *socc;              // panes crossed (0..kMaxGlass), -1 occluded
+    int32_t *sg_leaf;           // [record][kMaxGlass]
+    R *sg_u, *sg_v;
     double *acc;
     Counters *cnt;
-    uint32_t cap;               // pool slots = queue capacity
-    uint32_t primary_cap;       // slots reserved for primary rays of a chunk
+    uint32_t cap;               // slots of each pool and of the record buffer
+    int32_t nbmax;              // per-wavelength stride of the AoSoA arrays
     int32_t *gstack;            // traversal stack overflow (global)
-    uint32_t gstack_threads;    // threads the overflow stack is sized for
 };
 
 constexpr int kAuxDepthBits = 8;
@@ -104,9 +123,11 @@ constexpr int kAuxBandShift = 8;
 constexpr int kAuxBandBits = 12;
 constexpr int kAuxJobShift = 20;
 constexpr int kMaxBand = 128;
-constexpr int kLdsStack = 16;      // traversal stack levels held in LDS
-constexpr int kGlobalStack = 48;   // further levels in global memory
+constexpr int kLdsStack = 12;      // traversal stack levels held in LDS
+constexpr int kGlobalStack = 52;   // further levels in global memory
 constexpr int kMaxBvhDepth = kLdsStack + kGlobalStack - 2;
+constexpr int kMaxLeafTris = 255;  // leaf size bound of the stack encoding
+constexpr int kMaxTris = 1 << 23;  // triangles per scene (stack encoding)
 
 __host__ __device__ inline uint32_t pack_aux(int depth, int band, int job)
 {

@@ -5,10 +5,16 @@
 // bends no wavelength differently, so they follow one ray until a glass
 // vertex sends some wavelengths to reflection and others to transmission;
 // then the path forks (wavelengths are still independent, so the image is
-// the same as tracing each wavelength alone).  Per-wavelength path weights
-// live in the path pool; queues hold pool slots.  One step of the loop of
-// Sec. 3.1 is: closest hit -> shade (light sum of eq. (3) via a shadow
-// record, reflect/refract, compaction) -> shadow rays.
+// the same as tracing each wavelength alone).
+//
+// One step of the loop of Sec. 3.1 over a pool of paths:
+//   k_trace         closest hit of every path (persistent, lanes refilled)
+//   k_shade         sky for escaping paths, a shadow record per Lambert
+//                   vertex (eq. (3)), reflect/refract, survivors compacted
+//                   with their per-wavelength weights into the other pool
+//   k_shadow_trace  any-hit walk of the shadow records toward the sun
+//   k_shadow_accum  per wavelength: slab transmittance of the panes crossed,
+//                   wave-level segmented sums, FP64 atomics per pixel
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -18,15 +24,35 @@
 
 namespace sdm {
 
-// ---------------------------------------------------------------------------
-// Traversal
-// ---------------------------------------------------------------------------
-constexpr int kLdsNodes = 256;    // BVH prefix staged in LDS (16 KB)
+constexpr int kLdsNodes = 128;    // BVH prefix staged in LDS (8 KB)
 constexpr int kBlock = 256;
+constexpr uint32_t kFetch = 256;  // rays a traversal wave claims at a time
+constexpr int32_t kDone = INT_MIN;
 
+// ---------------------------------------------------------------------------
+// Explicit global-memory loads (pointers read from structs would otherwise
+// be generic and compile to flat loads).
+// ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 gld4(const float4 *p)
+{
+    const f4v v = *(const __attribute__((address_space(1))) f4v *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+template <class T>
+__device__ __forceinline__ T gld(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// ---------------------------------------------------------------------------
+// Traversal stack: kLdsStack levels per lane in LDS, deeper levels in a
+// per-thread global region.  Entries are inner-node indices (>= 0) or leaves
+// encoded as -1 - (first << 8 | count).
+// ---------------------------------------------------------------------------
 struct Stack {
     int32_t *lds;       // [kLdsStack][kBlock]
-    int32_t *glob;      // overflow, [(level - kLdsStack) * gstride + gtid]
+    int32_t *glob;      // [(level - kLdsStack) * gstride + gtid]
     uint32_t gtid, gstride;
     int sp;
     __device__ __forceinline__ void push(int32_t v)
@@ -38,163 +64,9 @@ struct Stack {
     __device__ __forceinline__ int32_t pop()
     {
         --sp;
-        return sp < kLdsStack ? lds[sp * kBlock + threadIdx.x]
-                              : glob[(size_t)(sp - kLdsStack) * gstride + gtid];
+        return sp < kLdsStack ? lds[sp * kBlock + threadIdx.x] : glob[(size_t)(sp - kLdsStack) * gstride + gtid];
     }
 };
-
-struct NodeView {
-    float lo0[3], hi0[3], lo1[3], hi1[3];
-    int32_t c0, c1, n0, n1;
-};
-
-__device__ __forceinline__ NodeView load_node(const float4 *lds_nodes, int n_lds, const BvhNode *nodes, int i)
-{
-    const float4 *p = (i < n_lds) ? lds_nodes + 4 * i : reinterpret_cast<const float4 *>(nodes) + 4 * (size_t)i;
-    const float4 a = p[0], b = p[1], c = p[2], d = p[3];
-    NodeView v;
-    v.lo0[0] = a.x; v.lo0[1] = a.y; v.lo0[2] = a.z; v.hi0[0] = a.w;
-    v.hi0[1] = b.x; v.hi0[2] = b.y; v.lo1[0] = b.z; v.lo1[1] = b.w;
-    v.lo1[2] = c.x; v.hi1[0] = c.y; v.hi1[1] = c.z; v.hi1[2] = c.w;
-    v.c0 = __float_as_int(d.x); v.c1 = __float_as_int(d.y);
-    v.n0 = __float_as_int(d.z); v.n1 = __float_as_int(d.w);
-    return v;
-}
-
-// Stage the BVH prefix of `sc` in LDS (whole block participates).
-__device__ __forceinline__ int stage_nodes(float4 *lds_nodes, const SceneDev &sc)
-{
-    const int n = min(sc.n_nodes, kLdsNodes);
-    const float4 *src = reinterpret_cast<const float4 *>(sc.nodes);
-    for (int i = threadIdx.x; i < 4 * n; i += blockDim.x) lds_nodes[i] = src[i];
-    __syncthreads();
-    return n;
-}
-
-template <class R>
-__device__ __forceinline__ R teps_of(const SceneDev &sc)
-{
-    return sizeof(R) == 4 ? R(sc.teps_f) : R(sc.teps_d);
-}
-
-// Closest hit.  Ties in t go to the smaller caller triangle index, so the
-// result does not depend on the tree.  `skip` is a leaf-order index.
-template <class R>
-__device__ void closest_hit(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st, V3<R> o,
-                            V3<R> d, int32_t skip, R &tb, int32_t &trib, R &ub, R &vb, uint32_t &nodes,
-                            uint32_t &tests)
-{
-    tb = R(INFINITY);
-    trib = -1;
-    ub = vb = R(0);
-    if (sc.n_nodes == 0) return;
-    int32_t orig_b = INT_MAX;
-    const V3<R> inv = safe_inv(d);
-    const R teps = teps_of<R>(sc);
-    st.sp = 0;
-    int cur = 0;
-    auto leaf = [&](int first, int cnt) {
-        tests += (uint32_t)cnt;
-        for (int i = first; i < first + cnt; ++i) {
-            if (i == skip) continue;
-            const TriDev tr = sc.tris[i];
-            R t, u, v;
-            if (!tri_hit(o, d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
-            if (!(t > teps)) continue;
-            const int32_t orig = __float_as_int(tr.a.w);
-            if (t < tb || (t == tb && orig < orig_b)) {
-                tb = t; trib = i; ub = u; vb = v; orig_b = orig;
-            }
-        }
-    };
-    for (;;) {
-        const NodeView nv = load_node(lds_nodes, n_lds, sc.nodes, cur);
-        ++nodes;
-        R tn0, tn1;
-        bool h0 = (nv.n0 > 0 || nv.c0 > 0) && box_hit(nv.lo0, nv.hi0, o, inv, teps, tb, tn0);
-        bool h1 = (nv.n1 > 0 || nv.c1 > 0) && box_hit(nv.lo1, nv.hi1, o, inv, teps, tb, tn1);
-        if (h0 && nv.n0 > 0) { leaf(nv.c0, nv.n0); h0 = false; }
-        if (h1 && nv.n1 > 0) { leaf(nv.c1, nv.n1); h1 = false; }
-        if (h0 && h1) {
-            const bool first0 = tn0 <= tn1;
-            st.push(first0 ? nv.c1 : nv.c0);
-            cur = first0 ? nv.c0 : nv.c1;
-        } else if (h0) {
-            cur = nv.c0;
-        } else if (h1) {
-            cur = nv.c1;
-        } else {
-            if (st.sp == 0) break;
-            cur = st.pop();
-        }
-    }
-}
-
-// Any-hit walk toward +infinity.  Returns true when an opaque triangle is
-// crossed; calls on_glass(leaf_index, u, v) for every pane crossed.
-template <class R, class F>
-__device__ bool shadow_walk(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st, V3<R> o,
-                            V3<R> d, int32_t skip, F &&on_glass, uint32_t &nodes, uint32_t &tests)
-{
-    if (sc.n_nodes == 0) return false;
-    const V3<R> inv = safe_inv(d);
-    const R teps = teps_of<R>(sc);
-    const R tinf = R(INFINITY);
-    st.sp = 0;
-    int cur = 0;
-    for (;;) {
-        const NodeView nv = load_node(lds_nodes, n_lds, sc.nodes, cur);
-        ++nodes;
-        R tn0, tn1;
-        bool h0 = (nv.n0 > 0 || nv.c0 > 0) && box_hit(nv.lo0, nv.hi0, o, inv, teps, tinf, tn0);
-        bool h1 = (nv.n1 > 0 || nv.c1 > 0) && box_hit(nv.lo1, nv.hi1, o, inv, teps, tinf, tn1);
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            const int cnt = w ? nv.n1 : nv.n0;
-            const bool hh = w ? h1 : h0;
-            if (!(hh && cnt > 0)) continue;
-            const int first = w ? nv.c1 : nv.c0;
-            tests += (uint32_t)cnt;
-            for (int i = first; i < first + cnt; ++i) {
-                if (i == skip) continue;
-                const TriDev tr = sc.tris[i];
-                R t, u, v;
-                if (!tri_hit(o, d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
-                if (!(t > teps)) continue;
-                if (sc.mat_type[__float_as_int(tr.b.w)] == 0) return true;
-                on_glass(i, u, v);
-            }
-            if (w) h1 = false; else h0 = false;
-        }
-        if (h0 && h1) {
-            st.push(nv.c1);
-            cur = nv.c0;
-        } else if (h0) {
-            cur = nv.c0;
-        } else if (h1) {
-            cur = nv.c1;
-        } else {
-            if (st.sp == 0) break;
-            cur = st.pop();
-        }
-    }
-    return false;
-}
-
-template <class R>
-__device__ __forceinline__ V3<R> tri_normal(const TriDev &tr)
-{
-    const V3<R> p0 = from4<R>(tr.a), p1 = from4<R>(tr.b), p2 = from4<R>(tr.c);
-    return normalize(cross(p1 - p0, p2 - p0));
-}
-
-template <class R>
-__device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, R u, R v)
-{
-    if (!sc.has_vthick) return R(sc.mat_thick[__float_as_int(sc.tris[leaf].b.w)]);
-    const float4 th = sc.thick[leaf];
-    return (R(1) - u - v) * R(th.x) + u * R(th.y) + v * R(th.z);
-}
 
 __device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
 {
@@ -207,6 +79,257 @@ __device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
     return st;
 }
 
+__device__ __forceinline__ int32_t leaf_code(int32_t first, int32_t cnt) { return -1 - ((first << 8) | cnt); }
+
+struct NodeView {
+    float lo0[3], hi0[3], lo1[3], hi1[3];
+    int32_t e0, e1;      // stack entries of the children (-1 - code for leaves)
+    bool v0, v1;         // child present
+};
+
+__device__ __forceinline__ NodeView load_node(const float4 *lds_nodes, int n_lds, const BvhNode *nodes, int i)
+{
+    float4 a, b, c, d;
+    if (i < n_lds) {
+        a = lds_nodes[4 * i]; b = lds_nodes[4 * i + 1]; c = lds_nodes[4 * i + 2]; d = lds_nodes[4 * i + 3];
+    } else {
+        const float4 *p = reinterpret_cast<const float4 *>(nodes) + 4 * (size_t)i;
+        a = gld4(p); b = gld4(p + 1); c = gld4(p + 2); d = gld4(p + 3);
+    }
+    NodeView v;
+    v.lo0[0] = a.x; v.lo0[1] = a.y; v.lo0[2] = a.z; v.hi0[0] = a.w;
+    v.hi0[1] = b.x; v.hi0[2] = b.y; v.lo1[0] = b.z; v.lo1[1] = b.w;
+    v.lo1[2] = c.x; v.hi1[0] = c.y; v.hi1[1] = c.z; v.hi1[2] = c.w;
+    const int32_t c0 = __float_as_int(d.x), c1 = __float_as_int(d.y);
+    const int32_t n0 = __float_as_int(d.z), n1 = __float_as_int(d.w);
+    v.v0 = n0 > 0 || c0 > 0;
+    v.v1 = n1 > 0 || c1 > 0;
+    v.e0 = n0 > 0 ? leaf_code(c0, n0) : c0;
+    v.e1 = n1 > 0 ? leaf_code(c1, n1) : c1;
+    return v;
+}
+
+__device__ __forceinline__ int stage_nodes(float4 *lds_nodes, const SceneDev &sc)
+{
+    const int n = min(sc.n_nodes, kLdsNodes);
+    const float4 *src = reinterpret_cast<const float4 *>(sc.nodes);
+    for (int i = threadIdx.x; i < 4 * n; i += blockDim.x) lds_nodes[i] = gld4(src + i);
+    __syncthreads();
+    return n;
+}
+
+template <class R>
+__device__ __forceinline__ R teps_of(const SceneDev &sc)
+{
+    return sizeof(R) == 4 ? R(sc.teps_f) : R(sc.teps_d);
+}
+
+__device__ __forceinline__ TriDev load_tri(const TriDev *tris, int i)
+{
+    const float4 *p = reinterpret_cast<const float4 *>(tris) + 3 * (size_t)i;
+    TriDev t;
+    t.a = gld4(p);
+    t.b = gld4(p + 1);
+    t.c = gld4(p + 2);
+    return t;
+}
+
+template <class R>
+struct Ray {
+    V3<R> o, d, inv;
+    int32_t skip, cur;
+};
+
+template <class R>
+struct Closest {
+    R tb, ub, vb;
+    int32_t trib, orig_b;
+};
+
+// One step of a closest-hit search: visit inner nodes nearest-first until a
+// leaf is due, test that leaf, and report whether the search is complete.
+// Ties in t go to the smaller caller triangle index, so the result does not
+// depend on the tree.
+template <class R>
+__device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
+                                             Ray<R> &ry, Closest<R> &h, R teps, uint32_t &nodes, uint32_t &tests)
+{
+    int32_t cur = ry.cur;
+    while (cur >= 0) {
+        const NodeView nv = load_node(lds_nodes, n_lds, sc.nodes, cur);
+        ++nodes;
+        R tn0, tn1;
+        const bool h0 = nv.v0 && box_hit(nv.lo0, nv.hi0, ry.o, ry.inv, teps, h.tb, tn0);
+        const bool h1 = nv.v1 && box_hit(nv.lo1, nv.hi1, ry.o, ry.inv, teps, h.tb, tn1);
+        if (h0 && h1) {
+            const bool f0 = tn0 <= tn1;
+            st.push(f0 ? nv.e1 : nv.e0);
+            cur = f0 ? nv.e0 : nv.e1;
+        } else if (h0) {
+            cur = nv.e0;
+        } else if (h1) {
+            cur = nv.e1;
+        } else {
+            cur = st.sp ? st.pop() : kDone;
+        }
+    }
+    if (cur != kDone) {
+        const int32_t code = -1 - cur;
+        const int first = code >> 8, cnt = code & 255;
+        tests += (uint32_t)cnt;
+        for (int i = first; i < first + cnt; ++i) {
+            if (i == ry.skip) continue;
+            const TriDev tr = load_tri(sc.tris, i);
+            R t, u, v;
+            if (!tri_hit(ry.o, ry.d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
+            if (!(t > teps)) continue;
+            const int32_t orig = __float_as_int(tr.a.w);
+            if (t < h.tb || (t == h.tb && orig < h.orig_b)) {
+                h.tb = t; h.trib = i; h.ub = u; h.vb = v; h.orig_b = orig;
+            }
+        }
+        cur = st.sp ? st.pop() : kDone;
+    }
+    ry.cur = cur;
+    return cur == kDone;
+}
+
+// One step of an any-hit walk toward +infinity: visit inner nodes until a leaf
+// is due and test it.  An opaque triangle ends the walk (occluded); each pane
+// crossed is reported to on_glass(leaf, u, v).
+template <class R, class F>
+__device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
+                                            Ray<R> &ry, bool &occluded, R teps, F &&on_glass, uint32_t &nodes,
+                                            uint32_t &tests)
+{
+    const R tinf = R(INFINITY);
+    int32_t cur = ry.cur;
+    while (cur >= 0) {
+        const NodeView nv = load_node(lds_nodes, n_lds, sc.nodes, cur);
+        ++nodes;
+        R tn0, tn1;
+        const bool h0 = nv.v0 && box_hit(nv.lo0, nv.hi0, ry.o, ry.inv, teps, tinf, tn0);
+        const bool h1 = nv.v1 && box_hit(nv.lo1, nv.hi1, ry.o, ry.inv, teps, tinf, tn1);
+        if (h0 && h1) {
+            st.push(nv.e1);
+            cur = nv.e0;
+        } else if (h0) {
+            cur = nv.e0;
+        } else if (h1) {
+            cur = nv.e1;
+        } else {
+            cur = st.sp ? st.pop() : kDone;
+        }
+    }
+    if (cur != kDone) {
+        const int32_t code = -1 - cur;
+        const int first = code >> 8, cnt = code & 255;
+        tests += (uint32_t)cnt;
+        for (int i = first; i < first + cnt; ++i) {
+            if (i == ry.skip) continue;
+            const TriDev tr = load_tri(sc.tris, i);
+            R t, u, v;
+            if (!tri_hit(ry.o, ry.d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
+            if (!(t > teps)) continue;
+            if (gld(sc.mat_type + __float_as_int(tr.b.w)) == 0) {
+                occluded = true;
+                ry.cur = kDone;
+                return true;
+            }
+            on_glass(i, u, v);
+        }
+        cur = st.sp ? st.pop() : kDone;
+    }
+    ry.cur = cur;
+    return cur == kDone;
+}
+
+// Work distribution of the persistent traversal kernels: a wave claims
+// kFetch consecutive items with one atomic and hands them to idle lanes.
+struct WaveFeed {
+    uint32_t beg, end;
+    bool done;
+    // All lanes call this together; returns the item of an idle lane or -1.
+    __device__ __forceinline__ int64_t next(bool idle, uint32_t *cursor, uint32_t count)
+    {
+        const uint64_t m = __ballot(idle);
+        if (!m || done) return -1;
+        if (beg >= end) {
+            uint32_t base = 0;
+            if (lane_id() == 0) base = atomicAdd(cursor, kFetch);
+            base = __shfl(base, 0);
+            if (base >= count) {
+                done = true;
+                return -1;
+            }
+            beg = base;
+            end = min(base + kFetch, count);
+        }
+        const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
+        const int64_t item = (idle && beg + before < end) ? (int64_t)(beg + before) : -1;
+        beg = min(end, beg + (uint32_t)__popcll(m));
+        return item;
+    }
+};
+
+template <class R>
+__device__ __forceinline__ V3<R> tri_normal(const TriDev &tr)
+{
+    const V3<R> p0 = from4<R>(tr.a), p1 = from4<R>(tr.b), p2 = from4<R>(tr.c);
+    return normalize(cross(p1 - p0, p2 - p0));
+}
+
+template <class R>
+__device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, R u, R v)
+{
+    if (!sc.has_vthick) return R(gld(sc.mat_thick + __float_as_int(load_tri(sc.tris, leaf).b.w)));
+    const float4 th = gld4(sc.thick + leaf);
+    return (R(1) - u - v) * R(th.x) + u * R(th.y) + v * R(th.z);
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level segmented sum over runs of lanes with equal keys, then one FP64
+// atomic per run.  All lanes call it; lanes with key ~0 add nothing.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t run_start(uint64_t key)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t prev = __shfl_up(key, 1);
+    uint32_t start = (lane == 0 || prev != key) ? lane : 0u;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(start, off);
+        if ((int)lane >= off) start = max(start, o);
+    }
+    return start;
+}
+
+__device__ __forceinline__ bool run_last(uint64_t key)
+{
+    const uint64_t next = __shfl_down(key, 1);
+    return lane_id() == 63 || next != key;
+}
+
+// K wavelengths j .. j+K-1 at once (independent shuffle chains); a lane of
+// run base `key0` adds v[q] to acc[key0 + j + q] when j + q < nb.
+template <int K>
+__device__ __forceinline__ void run_add_k(double *acc, uint64_t key0, int j, int nb, uint32_t start, bool last,
+                                          double (&v)[K])
+{
+    const uint32_t lane = lane_id();
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double o = __shfl_up(v[q], off);
+            if (lane >= start + (uint32_t)off) v[q] += o;
+        }
+    }
+    if (last && key0 != ~0ull) {
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (j + q < nb && v[q] != 0.0) unsafeAtomicAdd(acc + key0 + j + q, v[q]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Camera rays (Sec. 3.1: a ray from each pixel).  Image point ((i + u0) / W,
 // (j + u1) / H), row j from the top; pinhole through the unit-distance image
@@ -215,12 +338,15 @@ __device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const BandDev *bands,
                                                      const ItemDev *items, int32_t n_items, Work<R> w,
-                                                     uint64_t r0, uint32_t n, int cur)
+                                                     uint64_t r0, uint32_t n)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        w.cnt->qcount[cur] = n;
-        w.cnt->fork_next = w.primary_cap;
+        w.cnt->count[0] = n;
+        w.cnt->count[1] = 0;
+        w.cnt->tfetch = 0;
+        w.cnt->scount = 0;
     }
+    const Pool<R> P = w.p[0];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t r = r0 + i;
@@ -252,44 +378,71 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const B
             o = eye;
             d = normalize(f + (a * R(jb.th) * R(jb.aspect)) * rv + (b * R(jb.th)) * uv);
         }
-        w.ox[i] = o.x; w.oy[i] = o.y; w.oz[i] = o.z;
-        w.dx[i] = d.x; w.dy[i] = d.y; w.dz[i] = d.z;
-        w.pix[i] = pixel;
-        w.smp[i] = smp;
-        w.aux[i] = pack_aux(0, it.band, bd.job);
-        w.skip[i] = -1;
-        for (int j = 0; j < bd.nb; ++j) w.beta[(size_t)j * w.cap + i] = R(1);
-        w.q[cur][i] = i;
+        P.ox[i] = o.x; P.oy[i] = o.y; P.oz[i] = o.z;
+        P.dx[i] = d.x; P.dy[i] = d.y; P.dz[i] = d.z;
+        P.pix[i] = pixel;
+        P.smp[i] = smp;
+        P.aux[i] = pack_aux(0, it.band, bd.job);
+        P.skip[i] = -1;
+        for (int j = 0; j < bd.nb; ++j) P.beta[aosoa(i, j, w.nbmax)] = R(1);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Closest-hit traversal of the current queue.
+// Closest hit of every path of pool `cur`.
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w, int cur, int lds_job)
 {
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
-    const uint32_t count = w.cnt->qcount[cur];
+    const uint32_t count = w.cnt->count[cur];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        w.cnt->qcount[cur ^ 1] = 0;
+        w.cnt->count[cur ^ 1] = 0;
         w.cnt->scount = 0;
+        w.cnt->sfetch = 0;
+        w.cnt->gcount = 0;
         w.cnt->closest += count;
     }
     const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
     Stack st = make_stack(s_stack, w.gstack);
-    const uint32_t stride = gridDim.x * blockDim.x;
+    const Pool<R> P = w.p[cur];
+    WaveFeed feed{0, 0, false};
+    Ray<R> ry;
+    Closest<R> h;
+    int64_t item = -1;
+    int job = 0;
+    R teps = R(0);
     uint32_t n_nodes = 0, n_tests = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        const uint32_t s = w.q[cur][i];
-        const int job = (int)(w.aux[s] >> kAuxJobShift);
-        const SceneDev &sc = jobs[job].sc;
-        const V3<R> o = {w.ox[s], w.oy[s], w.oz[s]}, d = {w.dx[s], w.dy[s], w.dz[s]};
-        R t, u, v;
-        int32_t tri;
-        closest_hit(sc, s_nodes, job == lds_job ? n_lds : 0, st, o, d, w.skip[s], t, tri, u, v, n_nodes, n_tests);
-        w.ht[i] = t; w.htri[i] = tri; w.hu[i] = u; w.hv[i] = v;
+    for (;;) {
+        const int64_t got = feed.next(item < 0, &w.cnt->tfetch, count);
+        if (got >= 0) {
+            item = got;
+            const uint32_t s = (uint32_t)got;
+            job = (int)(P.aux[s] >> kAuxJobShift);
+            const SceneDev &sc = jobs[job].sc;
+            ry.o = {P.ox[s], P.oy[s], P.oz[s]};
+            ry.d = {P.dx[s], P.dy[s], P.dz[s]};
+            ry.inv = safe_inv(ry.d);
+            ry.skip = P.skip[s];
+            ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+            teps = teps_of<R>(sc);
+            h.tb = R(INFINITY); h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
+            st.sp = 0;
+        }
+        if (!__ballot(item >= 0)) {
+            if (feed.done) break;
+            continue;
+        }
+        if (item >= 0) {
+            const bool fin = ry.cur == kDone ||
+                             closest_step(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, h, teps, n_nodes,
+                                          n_tests);
+            if (fin) {
+                w.ht[item] = h.tb; w.htri[item] = h.trib; w.hu[item] = h.ub; w.hv[item] = h.vb;
+                item = -1;
+            }
+        }
     }
     if (n_nodes) {
         atomicAdd(&w.cnt->nodes[0], (unsigned long long)n_nodes);
@@ -299,16 +452,17 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
 
 // ---------------------------------------------------------------------------
 // Shade: misses add the sky, Lambert vertices emit a shadow record (eq. (3))
-// and bounce, glass vertices reflect or pass per wavelength; survivors are
-// compacted into the next queue.
+// and bounce; survivors are compacted with their weights into the other
+// pool.  Glass vertices are queued for k_shade_glass so that the costly
+// per-wavelength slab optics run in dense waves.
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
 {
-    const uint32_t count = w.cnt->qcount[cur];
-    const uint32_t *qin = w.q[cur];
-    uint32_t *qout = w.q[cur ^ 1];
-    const size_t cap = w.cap;
+    const uint32_t count = w.cnt->count[cur];
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->tfetch = 0;
+    const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
+    const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -316,176 +470,257 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
     for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
         const uint32_t i = base + lane;
         const bool active = i < count;
-        uint32_t s = 0, aux = 0, pix = 0;
+        uint32_t aux = 0, pix = 0, smp = 0;
         int32_t tri = -1;
-        int kind = -1;            // 0 miss, 1 lambert, 2 glass
-        bool last = true, want_shadow = false;
-        V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x, ns = x;
-        R cs = R(0), cos_i = R(0), thick = R(0), u0 = R(0);
-        int mat = 0, job = 0, band = 0, depth = 0;
+        int kind = -1;            // 0 miss, 1 Lambert, 2 glass (queued)
+        bool want_shadow = false, keep = false;
+        V3<R> x = {R(0), R(0), R(0)}, dnew = x;
+        R cs = R(0);
+        int mat = 0;
         const JobDev *jb = nullptr;
         BandDev bd = {0, 0, 0, 0};
         if (active) {
-            s = qin[i];
-            aux = w.aux[s];
-            pix = w.pix[s];
-            depth = (int)(aux & 0xffu);
-            band = (int)((aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u));
-            job = (int)(aux >> kAuxJobShift);
-            jb = &jobs[job];
-            bd = bands[band];
+            aux = Pi.aux[i];
+            pix = Pi.pix[i];
+            smp = Pi.smp[i];
+            const int depth = (int)(aux & 0xffu);
+            jb = &jobs[aux >> kAuxJobShift];
+            bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
             tri = w.htri[i];
-            last = depth >= jb->max_depth - 1;
+            const bool last = depth >= jb->max_depth - 1;
             if (tri < 0) {
                 kind = 0;
             } else {
-                const V3<R> o = {w.ox[s], w.oy[s], w.oz[s]}, d = {w.dx[s], w.dy[s], w.dz[s]};
-                const R t = w.ht[i];
-                x = o + t * d;
-                const TriDev tr = jb->sc.tris[tri];
+                const TriDev tr = load_tri(jb->sc.tris, tri);
                 mat = __float_as_int(tr.b.w);
-                const V3<R> ng = tri_normal<R>(tr);
-                const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, w.smp[s], depth, 0);
-                u0 = u01<R>(rr.x);
-                if (jb->sc.mat_type[mat] == 0) {
+                if (gld(jb->sc.mat_type + mat) == 0) {
                     kind = 1;
-                    ns = dot(ng, d) > R(0) ? R(-1) * ng : ng;
+                    const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
+                    x = o + w.ht[i] * d;
+                    const V3<R> ng = tri_normal<R>(tr);
+                    const V3<R> ns = dot(ng, d) > R(0) ? R(-1) * ng : ng;
                     const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
                     cs = dot(ns, sun);
                     want_shadow = cs > R(0);
-                    if (!last) dnew = cosine_dir(ns, u01<R>(rr.y), u01<R>(rr.z));
-                } else {
-                    kind = 2;
-                    cos_i = fabs(dot(d, ng));
-                    thick = pane_thickness<R>(jb->sc, tri, w.hu[i], w.hv[i]);
-                    dnew = d;
-                    drefl = d - (R(2) * dot(d, ng)) * ng;
-                }
-            }
-        }
-        // shadow records (one atomic per wave)
-        const uint32_t sslot = wave_reserve(want_shadow, &w.cnt->scount);
-        bool keep = false, fork = false;
-        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;   // reflected-wavelength mask
-        if (active) {
-            const int nl = jb->nl;
-            const R *E = (const R *)jb->E;
-            const R thr = R(jb->beta_thr);
-            if (kind == 0) {
-                const R *Ls = (const R *)jb->Lsky;
-                double *acc = w.acc + jb->acc_off + (size_t)pix * nl + bd.l0;
-                for (int j = 0; j < bd.nb; ++j) {
-                    const R b = w.beta[(size_t)j * cap + s];
-                    if (b != R(0)) unsafeAtomicAdd(acc + j, (double)(b * Ls[bd.l0 + j]));
-                }
-            } else if (kind == 1) {
-                const R *rho = (const R *)jb->rho + (size_t)mat * nl + bd.l0;
-                bool any = false;
-                if (want_shadow) {
-                    w.sx[sslot] = x.x; w.sy[sslot] = x.y; w.sz[sslot] = x.z;
-                    w.sskip[sslot] = tri;
-                    w.spix[sslot] = pix;
-                    w.saux[sslot] = aux;
-                }
-                for (int j = 0; j < bd.nb; ++j) {
-                    const R b = w.beta[(size_t)j * cap + s];
-                    const R rj = rho[j];
-                    if (want_shadow) w.contrib[(size_t)j * cap + sslot] = b * rj * inv_pi * E[bd.l0 + j] * cs;
+                    keep = !last;
                     if (!last) {
-                        R bn = b * rj;
-                        if (bn < thr) bn = R(0);
-                        w.beta[(size_t)j * cap + s] = bn;
-                        any |= bn != R(0);
+                        const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp, depth, 0);
+                        dnew = cosine_dir(ns, u01<R>(rr.y), u01<R>(rr.z));
                     }
+                } else if (!last) {
+                    kind = 2;   // no light sum at glass; a glass vertex at the depth limit ends the path
                 }
-                keep = !last && any;
-            } else if (kind == 2 && !last) {
-                const R *nn = (const R *)jb->n + (size_t)mat * nl + bd.l0;
-                const R *kk = (const R *)jb->k + (size_t)mat * nl + bd.l0;
-                const R *tt = (const R *)jb->tint + (size_t)mat * nl + bd.l0;
-                const R *lam = (const R *)jb->lam + bd.l0;
-                bool anyR = false, anyT = false;
-                for (int j = 0; j < bd.nb; ++j) {
-                    const R b = w.beta[(size_t)j * cap + s];
-                    R Rr = R(0), Tt = R(0), bn = R(0);
-                    bool refl = false;
-                    if (b != R(0)) {
-                        slab_RT<R>(cos_i, lam[j], thick, nn[j], kk[j], tt[j], Rr, Tt);
-                        const R rt = Rr + Tt;
-                        refl = rt > R(0) && u0 < Rr / rt;
-                        bn = b * rt;
-                        if (bn < thr) bn = R(0);
-                    }
-                    w.beta[(size_t)j * cap + s] = bn;
-                    if (bn != R(0)) {
-                        if (refl) {
-                            anyR = true;
-                            const uint32_t bit = 1u << (j & 31);
-                            if (j < 32) m0 |= bit; else if (j < 64) m1 |= bit; else if (j < 96) m2 |= bit; else m3 |= bit;
-                        } else {
-                            anyT = true;
-                        }
-                    }
-                }
-                keep = anyR || anyT;
-                fork = anyR && anyT;
-                if (anyR && !anyT) dnew = drefl;   // whole band reflects: no fork
             }
         }
-        // fork slots in the pool
-        uint32_t fslot = wave_reserve(fork, &w.cnt->fork_next);
-        {
-            const uint64_t mfk = __ballot(fork);
-            if (mfk && (int)lane == __ffsll((unsigned long long)mfk) - 1)
-                atomicAdd(&w.cnt->forks, (unsigned long long)__popcll(mfk));
-        }
-        if (fork && fslot >= w.cap) {
-            w.cnt->overflow = 1;
-            fork = false;
-        }
-        if (active && fork) {
-            for (int j = 0; j < bd.nb; ++j) {
-                const uint32_t word = j < 32 ? m0 : j < 64 ? m1 : j < 96 ? m2 : m3;
-                const R b = w.beta[(size_t)j * cap + s];
-                const bool refl = (word >> (j & 31)) & 1u;
-                w.beta[(size_t)j * cap + fslot] = refl ? b : R(0);
-                if (refl) w.beta[(size_t)j * cap + s] = R(0);
+        // glass queue, shadow records and pool slots: one atomic per wave and buffer
+        const uint32_t gslot = wave_reserve(kind == 2, &w.cnt->gcount);
+        if (kind == 2) w.gidx[gslot] = i;
+        uint32_t sslot = wave_reserve(want_shadow, &w.cnt->scount);
+        if (want_shadow && sslot >= w.cap) { w.cnt->overflow |= 1u; want_shadow = false; }
+        uint32_t om = wave_reserve(keep, &w.cnt->count[cur ^ 1]);
+        if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
+        if (kind == 1) {
+            const int nl = jb->nl;
+            if (want_shadow) {
+                w.sx[sslot] = x.x; w.sy[sslot] = x.y; w.sz[sslot] = x.z;
+                w.sskip[sslot] = tri;
+                w.spix[sslot] = pix;
+                w.saux[sslot] = aux;
             }
-            w.ox[fslot] = x.x; w.oy[fslot] = x.y; w.oz[fslot] = x.z;
-            w.dx[fslot] = drefl.x; w.dy[fslot] = drefl.y; w.dz[fslot] = drefl.z;
-            w.pix[fslot] = pix;
-            w.smp[fslot] = w.smp[s];
-            w.aux[fslot] = aux + 1u;
-            w.skip[fslot] = tri;
+            if (keep) {
+                Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
+                Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
+                Po.pix[om] = pix; Po.smp[om] = smp; Po.aux[om] = aux + 1u; Po.skip[om] = tri;
+            }
+            const R thr = R(jb->beta_thr);
+            const R *rho = (const R *)jb->rho + (size_t)mat * nl + bd.l0;
+            const R *E = (const R *)jb->E + bd.l0;
+            const R *__restrict__ bin = Pi.beta;
+            R *__restrict__ bout = Po.beta;
+            R *__restrict__ cout = w.contrib;
+            const R ncs = inv_pi * cs;
+            // eight wavelengths per round: all loads issued before the stores
+            int j = 0;
+            for (; j + 8 <= bd.nb; j += 8) {
+                R b[8], r[8], e[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    b[q] = bin[aosoa(i, j + q, nbm)];
+                    r[q] = gld(rho + j + q);
+                    e[q] = gld(E + j + q);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (want_shadow) cout[aosoa(sslot, j + q, nbm)] = b[q] * r[q] * ncs * e[q];
+                    if (keep) {
+                        R bn = b[q] * r[q];
+                        if (bn < thr) bn = R(0);
+                        bout[aosoa(om, j + q, nbm)] = bn;
+                    }
+                }
+            }
+            for (; j < bd.nb; ++j) {
+                const R b = bin[aosoa(i, j, nbm)];
+                const R rj = gld(rho + j);
+                if (want_shadow) cout[aosoa(sslot, j, nbm)] = b * rj * ncs * gld(E + j);
+                if (keep) {
+                    R bn = b * rj;
+                    if (bn < thr) bn = R(0);
+                    bout[aosoa(om, j, nbm)] = bn;
+                }
+            }
         }
-        if (active && keep) {
-            w.ox[s] = x.x; w.oy[s] = x.y; w.oz[s] = x.z;
-            w.dx[s] = dnew.x; w.dy[s] = dnew.y; w.dz[s] = dnew.z;
-            w.aux[s] = aux + 1u;
-            w.skip[s] = tri;
+        // escaping paths: sky radiance, summed per pixel across the wave
+        if (__ballot(kind == 0)) {
+            const int nb = kind == 0 ? bd.nb : 0;
+            int jmax = nb;
+            for (int off = 32; off > 0; off >>= 1) jmax = max(jmax, __shfl_xor(jmax, off));
+            const uint64_t key0 = kind == 0 ? jb->acc_off + (uint64_t)pix * jb->nl + bd.l0 : ~0ull;
+            const uint32_t start = run_start(key0);
+            const bool lst = run_last(key0);
+            for (int j = 0; j < jmax; j += 4) {
+                double v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    v[q] = j + q < nb ? (double)(Pi.beta[aosoa(i, j + q, nbm)] *
+                                                 gld((const R *)jb->Lsky + bd.l0 + j + q))
+                                      : 0.0;
+                run_add_k<4>(w.acc, key0, j, nb, start, lst, v);
+            }
         }
-        // compaction of survivors and forks into the next queue
-        const uint64_t mk = __ballot(keep), mf = __ballot(fork);
-        const uint32_t nk = (uint32_t)__popcll(mk), nf = (uint32_t)__popcll(mf);
-        const uint64_t lt = (1ull << lane) - 1ull;
-        uint32_t qbase = 0;
-        if (nk + nf) {
-            const int leader = __ffsll((unsigned long long)(mk | mf)) - 1;
-            if ((int)lane == leader) qbase = atomicAdd(&w.cnt->qcount[cur ^ 1], nk + nf);
-            qbase = __shfl(qbase, leader);
-        }
-        if (keep) qout[qbase + (uint32_t)__popcll(mk & lt)] = s;
-        if (fork) qout[qbase + nk + (uint32_t)__popcll(mf & lt)] = fslot;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Shadow rays toward the sun: an opaque hit ends the record; every pane
-// crossed multiplies in its slab transmittance at the sun angle.  The
-// product is accumulated in FP64.
+// Glass vertices (thin slab, Sec. 6 thickness map): per wavelength the path
+// reflects with probability R/(R+T) and otherwise passes straight through,
+// its weight multiplied by R + T.  When a band splits, the path forks: the
+// reflected wavelengths continue in a new pool slot.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_shadow(const JobDev *jobs, const BandDev *bands, Work<R> w, int lds_job)
+__global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
+{
+    const uint32_t count = w.cnt->gcount;
+    const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
+    const int nbm = w.nbmax;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
+        const bool active = base + lane < count;
+        uint32_t i = 0, aux = 0, pix = 0, smp = 0;
+        int32_t tri = -1;
+        V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x;
+        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;   // reflected wavelengths
+        bool keep = false, fork = false;
+        BandDev bd = {0, 0, 0, 0};
+        if (active) {
+            i = w.gidx[base + lane];
+            aux = Pi.aux[i];
+            pix = Pi.pix[i];
+            smp = Pi.smp[i];
+            const int depth = (int)(aux & 0xffu);
+            const JobDev *jb = &jobs[aux >> kAuxJobShift];
+            bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+            tri = w.htri[i];
+            const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
+            x = o + w.ht[i] * d;
+            const TriDev tr = load_tri(jb->sc.tris, tri);
+            const int mat = __float_as_int(tr.b.w);
+            const V3<R> ng = tri_normal<R>(tr);
+            const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp, depth, 0);
+            const R u0 = u01<R>(rr.x);
+            const R cos_i = fabs(dot(d, ng));
+            const R thick = pane_thickness<R>(jb->sc, tri, w.hu[i], w.hv[i]);
+            dnew = d;
+            drefl = d - (R(2) * dot(d, ng)) * ng;
+            const int nl = jb->nl;
+            const R *nn = (const R *)jb->n + (size_t)mat * nl + bd.l0;
+            const R *kk = (const R *)jb->k + (size_t)mat * nl + bd.l0;
+            const R *tt = (const R *)jb->tint + (size_t)mat * nl + bd.l0;
+            const R *lam = (const R *)jb->lam + bd.l0;
+            const R thr = R(jb->beta_thr);
+            bool anyR = false, anyT = false;
+            // the new weights stay in the input slot until the output slots are known
+            for (int j = 0; j < bd.nb; ++j) {
+                const size_t q = aosoa(i, j, nbm);
+                const R b = Pi.beta[q];
+                if (b == R(0)) continue;
+                R Rr, Tt;
+                slab_RT<R>(cos_i, gld(lam + j), thick, gld(nn + j), gld(kk + j), gld(tt + j), Rr, Tt);
+                const R rt = Rr + Tt;
+                R bn = b * rt;
+                if (bn < thr) bn = R(0);
+                Pi.beta[q] = bn;
+                if (bn == R(0)) continue;
+                if (rt > R(0) && u0 < Rr / rt) {
+                    anyR = true;
+                    const uint32_t bit = 1u << (j & 31);
+                    if (j < 32) m0 |= bit; else if (j < 64) m1 |= bit; else if (j < 96) m2 |= bit; else m3 |= bit;
+                } else {
+                    anyT = true;
+                }
+            }
+            keep = anyR || anyT;
+            fork = anyR && anyT;
+            if (anyR && !anyT) dnew = drefl;
+        }
+        const uint64_t mk = __ballot(keep), mf = __ballot(fork);
+        const uint32_t nk = (uint32_t)__popcll(mk), nf = (uint32_t)__popcll(mf);
+        const uint64_t lt = (1ull << lane) - 1ull;
+        uint32_t obase = 0;
+        if (nk + nf) {
+            const int leader = __ffsll((unsigned long long)(mk | mf)) - 1;
+            if ((int)lane == leader) {
+                obase = atomicAdd(&w.cnt->count[cur ^ 1], nk + nf);
+                if (nf) atomicAdd(&w.cnt->forks, (unsigned long long)nf);
+            }
+            obase = __shfl(obase, leader);
+        }
+        const uint32_t om = obase + (uint32_t)__popcll(mk & lt);
+        const uint32_t of = obase + nk + (uint32_t)__popcll(mf & lt);
+        if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
+        if (fork && of >= w.cap) { w.cnt->overflow |= 1u; fork = false; }
+        if (keep) {
+            Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
+            Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
+            Po.pix[om] = pix; Po.smp[om] = smp; Po.aux[om] = aux + 1u; Po.skip[om] = tri;
+        }
+        if (fork) {
+            Po.ox[of] = x.x; Po.oy[of] = x.y; Po.oz[of] = x.z;
+            Po.dx[of] = drefl.x; Po.dy[of] = drefl.y; Po.dz[of] = drefl.z;
+            Po.pix[of] = pix; Po.smp[of] = smp; Po.aux[of] = aux + 1u; Po.skip[of] = tri;
+        }
+        if (keep) {
+            const R *__restrict__ bin = Pi.beta;
+            R *__restrict__ bout = Po.beta;
+            for (int j = 0; j < bd.nb; j += 8) {
+                R bn[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) bn[q] = j + q < bd.nb ? bin[aosoa(i, j + q, nbm)] : R(0);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int jj = j + q;
+                    if (jj >= bd.nb) break;
+                    const uint32_t word = jj < 32 ? m0 : jj < 64 ? m1 : jj < 96 ? m2 : m3;
+                    const bool refl = (word >> (jj & 31)) & 1u;
+                    bout[aosoa(om, jj, nbm)] = (fork && refl) ? R(0) : bn[q];
+                    if (fork) bout[aosoa(of, jj, nbm)] = refl ? bn[q] : R(0);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shadow records: any-hit walk toward the sun.  socc = -1 when an opaque
+// triangle is in the way, else the number of panes crossed, kept for the
+// transmittance pass.  A walk that crosses more than kMaxGlass panes sets
+// bit 1 of the overflow word and the render reports it.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, const BandDev *bands, Work<R> w,
+                                                         int lds_job)
 {
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
@@ -493,63 +728,155 @@ __global__ void __launch_bounds__(kBlock) k_shadow(const JobDev *jobs, const Ban
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->shadow += count;
     const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
     Stack st = make_stack(s_stack, w.gstack);
-    const size_t cap = w.cap;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    constexpr int G = 4;
+    WaveFeed feed{0, 0, false};
+    Ray<R> ry;
+    int64_t item = -1;
+    int job = 0, ng = 0;
+    bool occ = false;
+    R teps = R(0);
     uint32_t n_nodes = 0, n_tests = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        const uint32_t aux = w.saux[i];
-        const int job = (int)(aux >> kAuxJobShift);
-        const int band = (int)((aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u));
-        const JobDev &jb = jobs[job];
-        const BandDev bd = bands[band];
-        const int nl = jb.nl;
-        const R *nn_t = (const R *)jb.n, *kk_t = (const R *)jb.k, *tt_t = (const R *)jb.tint;
-        const R *lam = (const R *)jb.lam + bd.l0;
-        const V3<R> o = {w.sx[i], w.sy[i], w.sz[i]};
-        const V3<R> sun = {R(jb.sc.sun[0]), R(jb.sc.sun[1]), R(jb.sc.sun[2])};
-        // panes crossed, kept in registers; folded into contrib when full
-        R gc[G], gd[G];
-        int gm[G];
-        int ng = 0;
-        auto fold = [&]() {
-            for (int j = 0; j < bd.nb; ++j) {
-                R T = w.contrib[(size_t)j * cap + i];
-                for (int g = 0; g < ng; ++g) {
-                    R Rr, Tt;
-                    const size_t mo = (size_t)gm[g] * nl + bd.l0 + j;
-                    slab_RT<R>(gc[g], lam[j], gd[g], nn_t[mo], kk_t[mo], tt_t[mo], Rr, Tt);
-                    T *= Tt;
-                }
-                w.contrib[(size_t)j * cap + i] = T;
-            }
+    for (;;) {
+        const int64_t got = feed.next(item < 0, &w.cnt->sfetch, count);
+        if (got >= 0) {
+            item = got;
+            const uint32_t s = (uint32_t)got;
+            job = (int)(w.saux[s] >> kAuxJobShift);
+            const SceneDev &sc = jobs[job].sc;
+            ry.o = {w.sx[s], w.sy[s], w.sz[s]};
+            ry.d = {R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])};
+            ry.inv = safe_inv(ry.d);
+            ry.skip = w.sskip[s];
+            ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+            teps = teps_of<R>(sc);
             ng = 0;
-        };
-        const bool occluded = shadow_walk<R>(jb.sc, s_nodes, job == lds_job ? n_lds : 0, st, o, sun, w.sskip[i],
-                                             [&](int leaf, R u, R v) {
-                                                 const TriDev tr = jb.sc.tris[leaf];
-                                                 if (ng == G) fold();
-                                                 gc[ng] = fabs(dot(sun, tri_normal<R>(tr)));
-                                                 gd[ng] = pane_thickness<R>(jb.sc, leaf, u, v);
-                                                 gm[ng] = __float_as_int(tr.b.w);
-                                                 ++ng;
-                                             }, n_nodes, n_tests);
-        if (occluded) continue;
-        double *acc = w.acc + jb.acc_off + (size_t)w.spix[i] * nl + bd.l0;
-        for (int j = 0; j < bd.nb; ++j) {
-            R T = w.contrib[(size_t)j * cap + i];
-            for (int g = 0; g < ng; ++g) {
-                R Rr, Tt;
-                const size_t mo = (size_t)gm[g] * nl + bd.l0 + j;
-                slab_RT<R>(gc[g], lam[j], gd[g], nn_t[mo], kk_t[mo], tt_t[mo], Rr, Tt);
-                T *= Tt;
+            occ = false;
+            st.sp = 0;
+        }
+        if (!__ballot(item >= 0)) {
+            if (feed.done) break;
+            continue;
+        }
+        if (item >= 0) {
+            const uint32_t rec = (uint32_t)item;
+            const bool fin = ry.cur == kDone ||
+                             shadow_step(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, occ, teps,
+                                         [&](int leaf, R u, R v) {
+                                             if (ng == kMaxGlass) {
+                                                 atomicOr(&w.cnt->overflow, 2u);
+                                                 return;
+                                             }
+                                             w.sg_leaf[(size_t)rec * kMaxGlass + ng] = leaf;
+                                             w.sg_u[(size_t)rec * kMaxGlass + ng] = u;
+                                             w.sg_v[(size_t)rec * kMaxGlass + ng] = v;
+                                             ++ng;
+                                         },
+                                         n_nodes, n_tests);
+            if (fin) {
+                w.socc[rec] = occ ? -1 : ng;
+                item = -1;
             }
-            if (T != R(0)) unsafeAtomicAdd(acc + j, (double)T);
         }
     }
     if (n_nodes) {
         atomicAdd(&w.cnt->nodes[1], (unsigned long long)n_nodes);
         atomicAdd(&w.cnt->tris[1], (unsigned long long)n_tests);
+    }
+}
+
+// Per wavelength: the record's contribution times the slab transmittance of
+// each pane crossed (at the sun angle, thickness at the crossing), summed
+// over runs of lanes of the same pixel, added to the FP64 accumulator.  Each
+// wave walks a contiguous range of records and compacts the unoccluded ones
+// in LDS (order kept, so runs of one pixel stay together) before the
+// per-wavelength loop, which then runs on full waves.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, const BandDev *bands, Work<R> w)
+{
+    __shared__ uint32_t s_buf[kBlock / 64][128];
+    const uint32_t count = w.cnt->scount;
+    const int nbm = w.nbmax;
+    const uint32_t lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint32_t *buf = s_buf[threadIdx.x >> 6];
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t per = ((count + nwaves - 1) / nwaves + 63) / 64 * 64;
+    const uint32_t r0 = min(count, wave * per), r1 = min(count, r0 + per);
+    uint32_t base = r0, nbuf = 0;
+    for (;;) {
+        while (nbuf < 64 && base < r1) {
+            const uint32_t i = base + lane;
+            const bool ok = i < r1 && w.socc[i] >= 0;
+            const uint64_t m = __ballot(ok);
+            if (ok) buf[nbuf + (uint32_t)__popcll(m & lt)] = i;
+            nbuf += (uint32_t)__popcll(m);
+            base += 64;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (nbuf == 0) break;
+        const uint32_t take = min(nbuf, 64u);
+        const bool act = lane < take;
+        const uint32_t rec = act ? buf[lane] : 0u;
+        int ng = -1, nb = 0;
+        uint64_t key0 = ~0ull;
+        const JobDev *jb = nullptr;
+        BandDev bd = {0, 0, 0, 0};
+        R gc[kMaxGlass], gd[kMaxGlass];
+        int gm[kMaxGlass];
+        if (act) {
+            ng = w.socc[rec];
+            const uint32_t aux = w.saux[rec];
+            jb = &jobs[aux >> kAuxJobShift];
+            bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+            nb = bd.nb;
+            key0 = jb->acc_off + (uint64_t)w.spix[rec] * jb->nl + bd.l0;
+            const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
+#pragma unroll
+            for (int g = 0; g < kMaxGlass; ++g) {
+                if (g < ng) {
+                    const int leaf = w.sg_leaf[(size_t)rec * kMaxGlass + g];
+                    const TriDev tr = load_tri(jb->sc.tris, leaf);
+                    gc[g] = fabs(dot(sun, tri_normal<R>(tr)));
+                    gd[g] = pane_thickness<R>(jb->sc, leaf, w.sg_u[(size_t)rec * kMaxGlass + g],
+                                              w.sg_v[(size_t)rec * kMaxGlass + g]);
+                    gm[g] = __float_as_int(tr.b.w);
+                } else {
+                    gc[g] = gd[g] = R(0);
+                    gm[g] = 0;
+                }
+            }
+        }
+        int jmax = nb;
+        for (int off = 32; off > 0; off >>= 1) jmax = max(jmax, __shfl_xor(jmax, off));
+        const uint32_t start = run_start(key0);
+        const bool lst = run_last(key0);
+        for (int j = 0; j < jmax; j += 4) {
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[q] = 0.0;
+                if (j + q < nb) {
+                    R T = w.contrib[aosoa(rec, j + q, nbm)];
+                    for (int g = 0; g < ng; ++g) {
+                        const size_t mo = (size_t)gm[g] * jb->nl + bd.l0 + j + q;
+                        R Rr, Tt;
+                        slab_RT<R>(gc[g], gld((const R *)jb->lam + bd.l0 + j + q), gd[g],
+                                   gld((const R *)jb->n + mo), gld((const R *)jb->k + mo),
+                                   gld((const R *)jb->tint + mo), Rr, Tt);
+                        T *= Tt;
+                    }
+                    v[q] = (double)T;
+                }
+            }
+            run_add_k<4>(w.acc, key0, j, nb, start, lst, v);
+        }
+        // keep the records not processed yet at the front of the buffer
+        const uint32_t rem = nbuf - take;
+        const uint32_t nxt = lane < rem ? buf[take + lane] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rem) buf[lane] = nxt;
+        __builtin_amdgcn_wave_barrier();
+        nbuf = rem;
     }
 }
 
@@ -590,10 +917,11 @@ __global__ void k_zero_f64(double *a, int64_t n)
 __global__ void k_zero_counters(Counters *c)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        c->qcount[0] = c->qcount[1] = 0;
+        c->count[0] = c->count[1] = 0;
         c->scount = 0;
-        c->fork_next = 0;
+        c->tfetch = c->sfetch = 0;
         c->overflow = 0;
+        c->gcount = 0;
         c->closest = c->shadow = c->forks = 0;
         c->nodes[0] = c->nodes[1] = c->tris[0] = c->tris[1] = 0;
     }
@@ -602,8 +930,8 @@ __global__ void k_zero_counters(Counters *c)
 // Linear interpolation of a table (tab_x[n_tab], tab_y[n_tab]) at xs[nl],
 // held constant beyond the ends; rows of `rows` tables.
 template <class R>
-__global__ void k_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs,
-                           int nl, R *out)
+__global__ void k_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl,
+                           R *out)
 {
     const int total = rows * nl;
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
@@ -640,55 +968,100 @@ __global__ void k_slab_eval(int64_t m, const float *c, const float *lam, const f
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_debug_intersect(SceneDev sc, int64_t m, const float *o, const float *d,
+__global__ void __launch_bounds__(kBlock) k_debug_intersect(SceneDev sc, uint32_t m, const float *o, const float *d,
                                                             const int32_t *skip, const int32_t *orig_to_leaf,
-                                                            float *t, int32_t *tri, float *uv,
+                                                            float *t, int32_t *tri, float *uv, uint32_t *cursor,
                                                             int32_t *gstack)
 {
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const int n_lds = stage_nodes(s_nodes, sc);
     Stack st = make_stack(s_stack, gstack);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
-        const V3<float> oo = {o[3 * i], o[3 * i + 1], o[3 * i + 2]}, dd = {d[3 * i], d[3 * i + 1], d[3 * i + 2]};
-        const int32_t sk = (skip && skip[i] >= 0 && skip[i] < sc.nt) ? orig_to_leaf[skip[i]] : -1;
-        float tt, u, v;
-        int32_t leaf;
-        uint32_t nn = 0, nt = 0;
-        closest_hit<float>(sc, s_nodes, n_lds, st, oo, dd, sk, tt, leaf, u, v, nn, nt);
-        t[i] = tt;
-        tri[i] = leaf >= 0 ? __float_as_int(sc.tris[leaf].a.w) : -1;
-        uv[2 * i] = u;
-        uv[2 * i + 1] = v;
+    WaveFeed feed{0, 0, false};
+    Ray<float> ry;
+    Closest<float> h;
+    int64_t item = -1;
+    uint32_t nn = 0, nt = 0;
+    for (;;) {
+        const int64_t got = feed.next(item < 0, cursor, m);
+        if (got >= 0) {
+            item = got;
+            ry.o = {o[3 * got], o[3 * got + 1], o[3 * got + 2]};
+            ry.d = {d[3 * got], d[3 * got + 1], d[3 * got + 2]};
+            ry.inv = safe_inv(ry.d);
+            ry.skip = (skip && skip[got] >= 0 && skip[got] < sc.nt) ? orig_to_leaf[skip[got]] : -1;
+            ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+            h.tb = INFINITY; h.ub = h.vb = 0.0f; h.trib = -1; h.orig_b = INT_MAX;
+            st.sp = 0;
+        }
+        if (!__ballot(item >= 0)) {
+            if (feed.done) break;
+            continue;
+        }
+        if (item >= 0) {
+            const bool fin = ry.cur == kDone || closest_step<float>(sc, s_nodes, n_lds, st, ry, h, sc.teps_f, nn, nt);
+            if (fin) {
+                t[item] = h.tb;
+                tri[item] = h.trib >= 0 ? __float_as_int(sc.tris[h.trib].a.w) : -1;
+                uv[2 * item] = h.ub;
+                uv[2 * item + 1] = h.vb;
+                item = -1;
+            }
+        }
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, int64_t m, const float *o, const int32_t *skip,
+__global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m, const float *o, const int32_t *skip,
                                                          const int32_t *orig_to_leaf, float lambda_nm,
                                                          const float *n_at, const float *k_at, const float *t_at,
-                                                         float *T, int32_t *gstack)
+                                                         float *T, uint32_t *cursor, int32_t *gstack)
 {
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const int n_lds = stage_nodes(s_nodes, sc);
     Stack st = make_stack(s_stack, gstack);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    WaveFeed feed{0, 0, false};
+    Ray<float> ry;
+    int64_t item = -1;
+    bool occ = false;
+    float prod = 1.0f;
+    uint32_t nn = 0, nt = 0;
     const V3<float> sun = {sc.sun[0], sc.sun[1], sc.sun[2]};
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
-        const V3<float> oo = {o[3 * i], o[3 * i + 1], o[3 * i + 2]};
-        const int32_t sk = (skip && skip[i] >= 0 && skip[i] < sc.nt) ? orig_to_leaf[skip[i]] : -1;
-        float prod = 1.0f;
-        uint32_t nn = 0, nt = 0;
-        const bool occ = shadow_walk<float>(sc, s_nodes, n_lds, st, oo, sun, sk, [&](int leaf, float u, float v) {
-            const TriDev tr = sc.tris[leaf];
-            const int mt = __float_as_int(tr.b.w);
-            float Rr, Tt;
-            slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm, pane_thickness<float>(sc, leaf, u, v),
-                           n_at[mt], k_at[mt], t_at[mt], Rr, Tt);
-            prod *= Tt;
-        }, nn, nt);
-        T[i] = occ ? 0.0f : prod;
+    for (;;) {
+        const int64_t got = feed.next(item < 0, cursor, m);
+        if (got >= 0) {
+            item = got;
+            ry.o = {o[3 * got], o[3 * got + 1], o[3 * got + 2]};
+            ry.d = sun;
+            ry.inv = safe_inv(ry.d);
+            ry.skip = (skip && skip[got] >= 0 && skip[got] < sc.nt) ? orig_to_leaf[skip[got]] : -1;
+            ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+            occ = false;
+            prod = 1.0f;
+            st.sp = 0;
+        }
+        if (!__ballot(item >= 0)) {
+            if (feed.done) break;
+            continue;
+        }
+        if (item >= 0) {
+            const bool fin = ry.cur == kDone ||
+                             shadow_step<float>(sc, s_nodes, n_lds, st, ry, occ, sc.teps_f,
+                                                [&](int leaf, float u, float v) {
+                                                    const TriDev tr = load_tri(sc.tris, leaf);
+                                                    const int mt = __float_as_int(tr.b.w);
+                                                    float Rr, Tt;
+                                                    slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm,
+                                                                   pane_thickness<float>(sc, leaf, u, v), n_at[mt],
+                                                                   k_at[mt], t_at[mt], Rr, Tt);
+                                                    prod *= Tt;
+                                                },
+                                                nn, nt);
+            if (fin) {
+                T[item] = occ ? 0.0f : prod;
+                item = -1;
+            }
+        }
     }
 }
 
@@ -697,9 +1070,9 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, int64_t m,
 // ---------------------------------------------------------------------------
 template <class R>
 void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *items, int n_items, const Work<R> &w,
-                     uint64_t r0, uint32_t n, int cur, int grid, hipStream_t s)
+                     uint64_t r0, uint32_t n, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_generate<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, items, n_items, w, r0, n, cur);
+    hipLaunchKernelGGL(k_generate<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, items, n_items, w, r0, n);
 }
 template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, int grid, hipStream_t s)
@@ -712,9 +1085,20 @@ void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, in
     hipLaunchKernelGGL(k_shade<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
 }
 template <class R>
-void launch_shadow(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid, hipStream_t s)
+void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shadow<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, lds_job);
+    hipLaunchKernelGGL(k_shade_glass<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+}
+template <class R>
+void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shadow_trace<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, lds_job);
+}
+template <class R>
+void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shadow_accum<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w);
 }
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
@@ -746,19 +1130,19 @@ void launch_slab_eval(int64_t m, const float *c, const float *lam, const float *
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (m + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(k_slab_eval, dim3(grid), dim3(kBlock), 0, s, m, c, lam, d, n, k, tint, R, T);
 }
-void launch_debug_intersect(const SceneDev &sc, int64_t m, const float *o, const float *d, const int32_t *skip,
-                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv, int32_t *gstack,
-                            int grid, hipStream_t s)
+void launch_debug_intersect(const SceneDev &sc, uint32_t m, const float *o, const float *d, const int32_t *skip,
+                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv, uint32_t *cursor,
+                            int32_t *gstack, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_debug_intersect, dim3(grid), dim3(kBlock), 0, s, sc, m, o, d, skip, orig_to_leaf, t, tri,
-                       uv, gstack);
+                       uv, cursor, gstack);
 }
-void launch_debug_shadow(const SceneDev &sc, int64_t m, const float *o, const int32_t *skip,
+void launch_debug_shadow(const SceneDev &sc, uint32_t m, const float *o, const int32_t *skip,
                          const int32_t *orig_to_leaf, float lambda_nm, const float *n_at, const float *k_at,
-                         const float *t_at, float *T, int32_t *gstack, int grid, hipStream_t s)
+                         const float *t_at, float *T, uint32_t *cursor, int32_t *gstack, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_debug_shadow, dim3(grid), dim3(kBlock), 0, s, sc, m, o, skip, orig_to_leaf, lambda_nm, n_at,
-                       k_at, t_at, T, gstack);
+                       k_at, t_at, T, cursor, gstack);
 }
 
 int block_size() { return kBlock; }
@@ -771,6 +1155,13 @@ int occupancy_trace()
     return std::max(1, b);
 }
 template <class R>
+int occupancy_shadow()
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_shadow_trace<R>, kBlock, 0) != hipSuccess) return 1;
+    return std::max(1, b);
+}
+template <class R>
 int occupancy_shade()
 {
     int b = 0;
@@ -778,15 +1169,18 @@ int occupancy_shade()
     return std::max(1, b);
 }
 
-#define SDM_INSTANTIATE(R)                                                                                        \
-    template void launch_generate<R>(const JobDev *, const BandDev *, const ItemDev *, int, const Work<R> &,      \
-                                     uint64_t, uint32_t, int, int, hipStream_t);                                  \
-    template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, int, hipStream_t);                   \
-    template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);       \
-    template void launch_shadow<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);      \
-    template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,             \
-                                     hipStream_t);                                                                \
-    template int occupancy_trace<R>();                                                                            \
+#define SDM_INSTANTIATE(R)                                                                                         \
+    template void launch_generate<R>(const JobDev *, const BandDev *, const ItemDev *, int, const Work<R> &,       \
+                                     uint64_t, uint32_t, int, hipStream_t);                                        \
+    template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, int, hipStream_t);                    \
+    template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);        \
+    template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);  \
+    template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
+    template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, int, hipStream_t);      \
+    template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,              \
+                                     hipStream_t);                                                                 \
+    template int occupancy_trace<R>();                                                                             \
+    template int occupancy_shadow<R>();                                                                            \
     template int occupancy_shade<R>();
 
 SDM_INSTANTIATE(float)

@@ -10,18 +10,25 @@ namespace sdm {
 
 template <class R>
 void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *items, int n_items, const Work<R> &w,
-                     uint64_t r0, uint32_t n, int cur, int grid, hipStream_t s);
+                     uint64_t r0, uint32_t n, int grid, hipStream_t s);
 template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, int grid, hipStream_t s);
 template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
 template <class R>
-void launch_shadow(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid, hipStream_t s);
+void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
+template <class R>
+void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid,
+                         hipStream_t s);
+template <class R>
+void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s);
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
                      hipStream_t s);
 template <class R>
 int occupancy_trace();
+template <class R>
+int occupancy_shadow();
 template <class R>
 int occupancy_shade();
 
@@ -31,12 +38,12 @@ void launch_zero_f64(double *a, int64_t n, hipStream_t s);
 void launch_zero_counters(Counters *c, hipStream_t s);
 void launch_slab_eval(int64_t m, const float *c, const float *lam, const float *d, const float *n, const float *k,
                       const float *tint, float *R, float *T, hipStream_t s);
-void launch_debug_intersect(const SceneDev &sc, int64_t m, const float *o, const float *d, const int32_t *skip,
-                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv, int32_t *gstack,
-                            int grid, hipStream_t s);
-void launch_debug_shadow(const SceneDev &sc, int64_t m, const float *o, const int32_t *skip,
+void launch_debug_intersect(const SceneDev &sc, uint32_t m, const float *o, const float *d, const int32_t *skip,
+                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv, uint32_t *cursor,
+                            int32_t *gstack, int grid, hipStream_t s);
+void launch_debug_shadow(const SceneDev &sc, uint32_t m, const float *o, const int32_t *skip,
                          const int32_t *orig_to_leaf, float lambda_nm, const float *n_at, const float *k_at,
-                         const float *t_at, float *T, int32_t *gstack, int grid, hipStream_t s);
+                         const float *t_at, float *T, uint32_t *cursor, int32_t *gstack, int grid, hipStream_t s);
 int block_size();
 
 }  // namespace sdm

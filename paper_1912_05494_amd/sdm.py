@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsdm.so")
 SDM_OK = 0
 SDM_MEM_HOST, SDM_MEM_DEVICE = 0, 1
 SDM_PREC_FP32, SDM_PREC_FP64 = 0, 1
-KERNELS = ("generate", "trace", "shade", "shadow", "finalize")
+KERNELS = ("generate", "trace", "shade", "shadow", "finalize", "shadow_accum", "shade_glass")
 
 _FP = C.POINTER(C.c_float)
 
@@ -57,7 +57,7 @@ class Stats(C.Structure):
                 ("closest_segments", C.c_uint64), ("shadow_segments", C.c_uint64),
                 ("forks", C.c_uint64), ("chunks", C.c_uint64), ("nodes_visited", C.c_uint64 * 2),
                 ("tris_tested", C.c_uint64 * 2), ("ms_render", C.c_double),
-                ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_uint64 * 5)]
+                ("kernel_ms", C.c_double * 7), ("kernel_launches", C.c_uint64 * 7)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_[:6]}

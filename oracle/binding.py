@@ -9,7 +9,8 @@ import numpy as np
 from .build import ensure_built
 
 __all__ = ["lib", "OracleScene", "philox", "u01", "fresnel", "slab", "snell_cos_t",
-           "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir"]
+           "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir", "slab_mc",
+           "fresnel_real", "bubble_dir", "mlp_nparams", "mlp_forward", "mlp_loss_grad"]
 
 _lib = None
 
@@ -80,6 +81,16 @@ def lib():
                                      C.c_double, C.c_void_p, C.c_void_p]
         L.orc_cosine_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_void_p]
         L.orc_spec_to_xyz.argtypes = [C.c_int64, C.c_int32] + [C.c_void_p] * 4
+        L.orc_slab_mc.argtypes = ([C.c_int64] + [C.c_void_p] * 4 + [C.c_double] * 2 + [C.c_void_p] * 3
+                                  + [C.c_uint64, C.c_uint32, C.c_int32] + [C.c_void_p] * 4)
+        L.orc_fresnel_real.restype = C.c_double
+        L.orc_fresnel_real.argtypes = [C.c_double] * 3 + [C.c_int]
+        L.orc_bubble_dir.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_void_p]
+        L.orc_mlp_nparams.restype = C.c_int64
+        L.orc_mlp_nparams.argtypes = [C.c_int32]
+        L.orc_mlp_forward.argtypes = [C.c_void_p, C.c_int32, C.c_int64] + [C.c_void_p] * 3
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_mlp_loss_grad.argtypes = [C.c_void_p, C.c_int32, C.c_int64] + [C.c_void_p] * 4
         _lib = L
     return _lib
 
@@ -234,6 +245,58 @@ def cosine_dir(n, u1, u2):
     d = np.empty(3)
     lib().orc_cosine_dir(n.ctypes.data, float(u1), float(u2), d.ctypes.data)
     return d
+
+
+def slab_mc(cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint, seed=0, tuple0=0, n_photons=64,
+            rmin_um=10.0, rmax_um=200.0):
+    """Bubbly-slab Monte Carlo per tuple -> (R, T, A, w_lobe) float64 arrays."""
+    arrs = np.broadcast_arrays(*[np.asarray(a, dtype=np.float64) for a in
+                                 (cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint)])
+    flat = [np.ascontiguousarray(a.reshape(-1)) for a in arrs]
+    m = flat[0].size
+    R, T, A, W = (np.empty(m) for _ in range(4))
+    lib().orc_slab_mc(m, *[a.ctypes.data for a in flat[:4]], float(rmin_um), float(rmax_um),
+                      *[a.ctypes.data for a in flat[4:]], int(seed), int(tuple0), int(n_photons),
+                      R.ctypes.data, T.ctypes.data, A.ctypes.data, W.ctypes.data)
+    return R, T, A, W
+
+
+def fresnel_real(n1, n2, c, pol):
+    return lib().orc_fresnel_real(float(n1), float(n2), float(c), int(pol))
+
+
+def bubble_dir(d, e_perp, sin_i, n, p):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    e = np.ascontiguousarray(e_perp, dtype=np.float64)
+    out = np.empty(3)
+    lib().orc_bubble_dir(d.ctypes.data, e.ctypes.data, float(sin_i), float(n), int(p), out.ctypes.data)
+    return out
+
+
+def mlp_nparams(n_panes):
+    return int(lib().orc_mlp_nparams(int(n_panes)))
+
+
+def mlp_forward(params, n_panes, tuples, panes):
+    """tuples (m, 4): cos, lambda_nm, d_mm, rho_b -> (m, 3): R, T, w."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(tuples, dtype=np.float64).reshape(-1, 4)
+    pn = np.ascontiguousarray(panes, dtype=np.int32)
+    out = np.empty((len(x), 3))
+    lib().orc_mlp_forward(p.ctypes.data, int(n_panes), len(x), x.ctypes.data, pn.ctypes.data,
+                          out.ctypes.data)
+    return out
+
+
+def mlp_loss_grad(params, n_panes, tuples, panes, target):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(tuples, dtype=np.float64).reshape(-1, 4)
+    pn = np.ascontiguousarray(panes, dtype=np.int32)
+    t = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, 3)
+    g = np.empty_like(p)
+    loss = lib().orc_mlp_loss_grad(p.ctypes.data, int(n_panes), len(x), x.ctypes.data, pn.ctypes.data,
+                                   t.ctypes.data, g.ctypes.data)
+    return loss, g
 
 
 def spec_to_xyz(spec, lambda_nm, cmf):

@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "libsdm_oracle.so")
-SOURCES = ["sdm_oracle.c"]
+SOURCES = ["sdm_oracle.c", "slab_mc.c", "mlp.c"]
 
 
 def build(verbose=False):

@@ -120,6 +120,22 @@ void orc_cosine_dir(const double n[3], double u1, double u2, double d[3]);
 void orc_spec_to_xyz(int64_t npix, int32_t n_lambda, const double *lambda_nm,
                      const double *cmf_xyz, const double *spec, double *xyz);
 
+/* Bubbly slab Monte Carlo (reading; see slab_mc.c): m tuples of n_photons
+ * photons; outputs R, T, A (absorbed) and the transmitted-lobe width. */
+void orc_slab_mc(int64_t m, const double *cos_i, const double *lambda_nm, const double *d_mm,
+                 const double *rho_b, double rmin_um, double rmax_um, const double *n, const double *k,
+                 const double *alpha_tint, uint64_t seed, uint32_t tuple0, int32_t n_photons, double *R,
+                 double *T, double *A, double *w_lobe);
+double orc_fresnel_real(double n1, double n2, double c, int pol);
+void orc_bubble_dir(const double dir[3], const double e_perp[3], double sin_i, double n, int p, double out[3]);
+
+/* Surrogate network (reading; see mlp.c). */
+int64_t orc_mlp_nparams(int32_t n_panes);
+void orc_mlp_forward(const double *params, int32_t n_panes, int64_t m, const double *tuples,
+                     const int32_t *panes, double *out);
+double orc_mlp_loss_grad(const double *params, int32_t n_panes, int64_t m, const double *tuples,
+                         const int32_t *panes, const double *target, double *grad);
+
 #ifdef __cplusplus
 }
 #endif

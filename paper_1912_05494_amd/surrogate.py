@@ -1,0 +1,61 @@
+"""Surrogate BTDF of bubbly glass: parameter layout and seeded initial
+weights (inputs of the training), plus thin wrappers of the library's
+training and inference entry points.
+
+Network: 12 -> 64 -> 64 -> 64 -> 3 with ReLU; inputs (cos(theta), lambda,
+thickness, bubble density, 8-value pane embedding); outputs (R, T, lobe width).
+The forward/backward passes, the loss and the optimiser run in the HIP
+library (BF16 MFMA with FP32 accumulation); this module only lays out and
+initialises parameters and marshals arguments.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_IN, N_HID, N_OUT, N_EMB = 12, 64, 3, 8
+#: (name, shape) in the order of the flat parameter vector
+LAYOUT = [("W1", (N_HID, N_IN)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
+          ("W3", (N_HID, N_HID)), ("b3", (N_HID,)), ("W4", (N_OUT, N_HID)), ("b4", (N_OUT,))]
+RHO_MAX = 34.0   # bubbles per mm^3 at a volume fraction of 0.3 for r in [10, 200] um
+
+
+def n_params(n_panes):
+    return sum(int(np.prod(s)) for _, s in LAYOUT) + N_EMB * n_panes
+
+
+def init_params(n_panes, seed=0):
+    """He-uniform weights, zero biases, N(0, 0.1) embeddings (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in LAYOUT:
+        if name.startswith("W"):
+            lim = np.sqrt(6.0 / shape[1]) * (0.1 if name == "W4" else 1.0)
+            parts.append(rng.uniform(-lim, lim, size=shape).reshape(-1))
+        else:
+            parts.append(np.zeros(shape).reshape(-1))
+    parts.append(rng.normal(0.0, 0.1, size=N_EMB * n_panes))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def split(params, n_panes):
+    """Views of the flat vector by name (plus 'E' for the embeddings)."""
+    out, o = {}, 0
+    for name, shape in LAYOUT:
+        k = int(np.prod(shape))
+        out[name] = params[o:o + k].reshape(shape)
+        o += k
+    out["E"] = params[o:o + N_EMB * n_panes].reshape(n_panes, N_EMB)
+    return out
+
+
+def random_tuples(n, n_panes, lambdas, seed=0, rho_max=RHO_MAX, d_range=(2.0, 5.0)):
+    """Training inputs: cos(theta) ~ U(0, 1], lambda on the grid, thickness ~
+    U(2, 5) mm, bubble density ~ U(0, rho_max), pane ~ U{0..n_panes-1}."""
+    rng = np.random.default_rng(seed)
+    tup = np.empty((n, 4), dtype=np.float32)
+    tup[:, 0] = 1.0 - rng.random(n)
+    tup[:, 1] = rng.choice(np.asarray(lambdas, dtype=np.float32), n)
+    tup[:, 2] = rng.uniform(*d_range, n)
+    tup[:, 3] = rng.uniform(0.0, rho_max, n)
+    pane = rng.integers(0, n_panes, n).astype(np.int32)
+    return tup, pane

@@ -187,6 +187,84 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *scene, int64_t m, const 
 /* BVH shape of a scene (for tests and tuning): node count and depth. */
 int sdm_scene_info(const sdm_scene *scene, int32_t *n_nodes, int32_t *depth);
 
+/* ---------------------------------------------------------------------------
+ * Bubbly glass (air micro-particles in the glass body, Sec. 1; light
+ * scattering as the next material feature, Sec. 6) and its learned surrogate.
+ * ------------------------------------------------------------------------- */
+
+/* Monte Carlo of a glass slab holding spherical air bubbles, for m tuples of
+ * n_photons photon walks each.  Inputs are DEVICE float arrays of length m:
+ * cos_i (incidence cosine, (0, 1]), lambda_nm, d_mm (thickness), rho_b
+ * (bubbles per mm^3, >= 0), n, k (optical constants of eq. (1) at lambda),
+ * alpha_tint (per mm, may be NULL for 0).  Bubble radii are uniform in
+ * [rmin_um, rmax_um] micrometres.  The walk: complex-index Fresnel at entry,
+ * Beer-Lambert weight in glass, Poisson bubbles with extinction rho_b pi <r^2>
+ * acting at the collision point with exact sphere optics for the new
+ * direction (outer reflection or p internal reflections), Fresnel / total
+ * reflection at the faces; a fresh s/p label per bubble.  Random numbers are
+ * Philox4x32-10 with counter (tuple0 + i, photon, event, 0x5EB10000 | sub)
+ * and key seed.  precision: SDM_PREC_FP32 or SDM_PREC_FP64 (the walk's
+ * arithmetic; sums are FP64 either way).  Outputs (DEVICE float, length m):
+ * R, T (fractions leaving the top / bottom face), A (absorbed, may be NULL),
+ * w_lobe (RMS angle in radians between the transmitted and the incident
+ * direction, weighted by transmitted energy, divided by sqrt(2); 0 when
+ * nothing is transmitted).  Uses a context-owned FP64 work buffer of 32 m
+ * bytes and synchronises the stream before it returns. */
+int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm,
+                const float *d_mm, const float *rho_b, const float *n, const float *k,
+                const float *alpha_tint, float rmin_um, float rmax_um, int32_t n_photons,
+                uint64_t seed, uint32_t tuple0, int32_t precision, float *R, float *T, float *A,
+                float *w_lobe, void *hip_stream);
+
+/* Surrogate network of the bubbly slab: 12 -> 64 -> 64 -> 64 -> 3 with ReLU.
+ * Input of a tuple (cos_i, lambda_nm, d_mm, rho_b) on pane type p:
+ * (cos_i, (lambda - 580) / 200, (d - 3.5) / 1.5, rho_b / 34, E[p][0..7]);
+ * outputs o -> R = e^o0 / (e^o0 + e^o1 + 1), T = e^o1 / (same),
+ * w = log(1 + e^o2).  Loss: mean over samples of the squared errors of
+ * (R, T, w).  Parameters (FP32 master copy, this order):
+ *   W1[64][12] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]
+ *   E[n_panes][8]
+ * i.e. sdm_mlp_nparams(n_panes) = 9347 + 8 n_panes floats.  Products run on
+ * BF16 matrix cores with FP32 accumulation; heads, loss and Adam in FP32. */
+typedef struct sdm_mlp sdm_mlp;
+
+typedef struct {
+    int32_t steps;      /* Adam steps                                          */
+    int32_t batch;      /* samples per step; step s uses rows
+                           [(s mod nb) batch, +batch), nb = floor(m / batch)   */
+    float lr, beta1, beta2, eps;
+} sdm_train_params;
+
+int64_t sdm_mlp_nparams(int32_t n_panes);
+/* params: HOST, sdm_mlp_nparams(n_panes) floats; 1 <= n_panes <= 64. */
+int sdm_mlp_create(sdm_context *ctx, int32_t n_panes, const float *params, sdm_mlp **out);
+int sdm_mlp_destroy(sdm_mlp *mlp);
+/* Copies the FP32 master parameters to params (HOST). */
+int sdm_mlp_get_params(const sdm_mlp *mlp, float *params);
+/* Gradient of the mean loss over m samples with respect to every parameter.
+ * tuples [m][4] (cos_i, lambda_nm, d_mm, rho_b), panes [m] (0..n_panes-1),
+ * target [m][3] (R, T, w): DEVICE.  grad: DEVICE, nparams floats.  loss:
+ * HOST, may be NULL.  Synchronises the stream. */
+int sdm_mlp_grad(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *panes,
+                 const float *target, float *grad, float *loss, void *hip_stream);
+/* Adam training on m samples (DEVICE arrays as for sdm_mlp_grad); the
+ * optimiser state and its step count persist across calls.  loss_curve:
+ * HOST, tp->steps floats (mean batch loss before each step), may be NULL.
+ * Synchronises the stream. */
+int sdm_mlp_train(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *panes,
+                  const float *target, const sdm_train_params *tp, float *loss_curve,
+                  void *hip_stream);
+/* (R, T, w) for m tuples: out [m][3] DEVICE. */
+int sdm_mlp_infer(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *panes, float *out,
+                  void *hip_stream);
+
+/* Matrix-core lane layout check: C32 = A32 B32 with A32 [16][32], B32
+ * [32][16] (v_mfma_f32_16x16x32_bf16), C16 = A16 B16 with A16 [16][16],
+ * B16 [16][16] (v_mfma_f32_16x16x16_bf16); inputs rounded to BF16; all
+ * DEVICE row-major FP32.  Synchronises the stream. */
+int sdm_debug_mfma(sdm_context *ctx, const float *A32, const float *B32, float *C32, const float *A16,
+                   const float *B16, float *C16, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

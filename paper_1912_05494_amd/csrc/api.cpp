@@ -12,6 +12,7 @@
 #include "../../include/sdm.h"
 #include "bvh_build.hpp"
 #include "sdm_types.hpp"
+#include "surrogate.hpp"
 #include "wavefront.hpp"
 
 using namespace sdm;
@@ -52,6 +53,15 @@ struct sdm_context {
     Counters *host_counters = nullptr;
     std::vector<hipEvent_t> events;
     DevBuf slab_tmp;
+    DevBuf mc_acc, flag;
+};
+
+struct sdm_mlp {
+    sdm_context *ctx = nullptr;
+    int32_t n_panes = 0;
+    int64_t P = 0;
+    int64_t t = 0;   // Adam steps taken
+    DevBuf params, m1, m2, grad, wb, bb, partial, loss_partial, loss;
 };
 
 struct sdm_scene {
@@ -98,6 +108,50 @@ bool ptr_is_device(const void *p)
         return false;
     }
     return a.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+namespace {
+
+int mlp_check(sdm_mlp *net, int64_t m, const void *tuples, const void *panes)
+{
+    if (m < 0 || m > (1LL << 30)) return fail(net->ctx, SDM_E_INVALID, "sample count %lld out of range", (long long)m);
+    if (m > 0 && (!tuples || !panes)) return fail(net->ctx, SDM_E_INVALID, "null array");
+    return SDM_OK;
+}
+
+int mlp_grad_blocks(const sdm_mlp *net, int64_t m)
+{
+    const int64_t waves = (m + 15) / 16;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(net->ctx->num_cu, (waves + 3) / 4));
+}
+
+// Enqueues pack + gradient + reduce for m samples; loss_dst receives the mean
+// loss (device float).
+int mlp_enqueue_grad(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *panes, const float *target,
+                     float *grad, float *loss_dst, hipStream_t s)
+{
+    sdm_context *ctx = net->ctx;
+    const int nblk = mlp_grad_blocks(net, m);
+    HIPCHK(ctx, net->partial.ensure((size_t)nblk * net->P * sizeof(float)));
+    HIPCHK(ctx, net->loss_partial.ensure((size_t)nblk * sizeof(float)));
+    launch_mlp_pack(net->params.as<float>(), net->wb.p, net->bb.as<float>(), s);
+    launch_mlp_grad((uint32_t)m, net->n_panes, tuples, panes, target, net->wb.p, net->bb.as<float>(),
+                    net->params.as<float>() + mlp_net_params(), 1.0f / (float)m, net->partial.as<float>(),
+                    net->loss_partial.as<float>(), ctx->flag.as<int>(), nblk, s);
+    launch_mlp_reduce(nblk, (int)net->P, net->partial.as<float>(), net->loss_partial.as<float>(), 1.0f / (float)m, grad,
+                      loss_dst, s);
+    return SDM_OK;
+}
+
+int check_flag(sdm_context *ctx, hipStream_t s, const char *what)
+{
+    int bad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (bad) return fail(ctx, SDM_E_INVALID, "%s: pane index out of range", what);
+    return SDM_OK;
 }
 
 }  // namespace
@@ -719,6 +773,176 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const flo
     launch_debug_shadow(sc->dev, (uint32_t)m, o, skip, sc->orig_to_leaf.as<int32_t>(), lambda_nm, tabs + nm,
                         tabs + 2 * nm, tabs + 3 * nm, T, &ctx->counters.as<Counters>()->sfetch,
                         ctx->gstack.as<int32_t>(), grid, s);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return SDM_OK;
+}
+
+int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm, const float *d_mm,
+                const float *rho_b, const float *n, const float *k, const float *alpha_tint, float rmin_um,
+                float rmax_um, int32_t n_photons, uint64_t seed, uint32_t tuple0, int32_t precision, float *R,
+                float *T, float *A, float *w_lobe, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (m < 0 || m > 0xffffffffLL) return fail(ctx, SDM_E_INVALID, "tuple count %lld out of range", (long long)m);
+    if (n_photons < 1) return fail(ctx, SDM_E_INVALID, "n_photons must be >= 1");
+    if ((uint64_t)tuple0 + (uint64_t)m > 0x100000000ULL)
+        return fail(ctx, SDM_E_INVALID, "tuple0 + m exceeds the 32-bit counter word");
+    if (!(rmin_um >= 0.0f) || !(rmax_um >= rmin_um)) return fail(ctx, SDM_E_INVALID, "bad bubble radius range");
+    if (precision != SDM_PREC_FP32 && precision != SDM_PREC_FP64) return fail(ctx, SDM_E_INVALID, "bad precision");
+    if (m == 0) return SDM_OK;
+    if (!cos_i || !lambda_nm || !d_mm || !rho_b || !n || !k || !R || !T || !w_lobe)
+        return fail(ctx, SDM_E_INVALID, "null array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(ctx, ctx->mc_acc.ensure(4 * (size_t)m * sizeof(double)));
+    const double a = (double)rmin_um * 1e-3, b = (double)rmax_um * 1e-3;
+    const double r2 = (a * a + a * b + b * b) / 3.0;   // <r^2> in mm^2, r ~ U(a, b)
+    if (precision == SDM_PREC_FP64)
+        launch_slab_mc<double>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint, r2,
+                               seed, tuple0, ctx->mc_acc.as<double>(), R, T, A, w_lobe, ctx->num_cu, s);
+    else
+        launch_slab_mc<float>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint, r2,
+                              seed, tuple0, ctx->mc_acc.as<double>(), R, T, A, w_lobe, ctx->num_cu, s);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return SDM_OK;
+}
+
+int64_t sdm_mlp_nparams(int32_t n_panes) { return n_panes < 0 ? -1 : (int64_t)mlp_net_params() + 8LL * n_panes; }
+
+int sdm_mlp_create(sdm_context *ctx, int32_t n_panes, const float *params, sdm_mlp **out)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!out || !params) return fail(ctx, SDM_E_INVALID, "null argument");
+    *out = nullptr;
+    if (n_panes < 1 || n_panes > kMaxPanes)
+        return fail(ctx, SDM_E_INVALID, "n_panes must be in [1, %d]", kMaxPanes);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    sdm_mlp *net = new sdm_mlp;
+    net->ctx = ctx;
+    net->n_panes = n_panes;
+    net->P = sdm_mlp_nparams(n_panes);
+    const size_t pb = (size_t)net->P * sizeof(float);
+    hipError_t e = upload(net->params, params, (size_t)net->P);
+    if (e == hipSuccess) e = net->m1.ensure(pb);
+    if (e == hipSuccess) e = net->m2.ensure(pb);
+    if (e == hipSuccess) e = net->grad.ensure(pb);
+    if (e == hipSuccess) e = net->wb.ensure((size_t)mlp_wb_elems() * 2);
+    if (e == hipSuccess) e = net->bb.ensure((size_t)mlp_bb_elems() * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(net->m1.p, 0, pb);
+    if (e == hipSuccess) e = hipMemset(net->m2.p, 0, pb);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete net;
+        return fail(ctx, e == hipErrorOutOfMemory ? SDM_E_NOMEM : SDM_E_DEVICE, "mlp create: %s",
+                    hipGetErrorString(e));
+    }
+    *out = net;
+    return SDM_OK;
+}
+
+int sdm_mlp_destroy(sdm_mlp *net)
+{
+    if (!net) return SDM_E_INVALID;
+    (void)hipSetDevice(net->ctx->device);
+    delete net;
+    return SDM_OK;
+}
+
+int sdm_mlp_get_params(const sdm_mlp *net, float *params)
+{
+    if (!net) return SDM_E_INVALID;
+    if (!params) return fail(net->ctx, SDM_E_INVALID, "null params");
+    HIPCHK(net->ctx, hipSetDevice(net->ctx->device));
+    HIPCHK(net->ctx, hipMemcpy(params, net->params.p, (size_t)net->P * sizeof(float), hipMemcpyDeviceToHost));
+    return SDM_OK;
+}
+
+
+int sdm_mlp_grad(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *panes, const float *target,
+                 float *grad, float *loss, void *hip_stream)
+{
+    if (!net) return SDM_E_INVALID;
+    sdm_context *ctx = net->ctx;
+    if (int rc = mlp_check(net, m, tuples, panes)) return rc;
+    if (m == 0) return fail(ctx, SDM_E_INVALID, "empty batch");
+    if (!target || !grad) return fail(ctx, SDM_E_INVALID, "null array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(ctx, ctx->flag.ensure(sizeof(int)));
+    HIPCHK(ctx, net->loss.ensure(sizeof(float)));
+    launch_zero_i32(ctx->flag.as<int>(), 1, s);
+    if (int rc = mlp_enqueue_grad(net, m, tuples, panes, target, grad, net->loss.as<float>(), s)) return rc;
+    HIPCHK(ctx, hipGetLastError());
+    if (int rc = check_flag(ctx, s, "sdm_mlp_grad")) return rc;
+    if (loss) HIPCHK(ctx, hipMemcpy(loss, net->loss.p, sizeof(float), hipMemcpyDeviceToHost));
+    return SDM_OK;
+}
+
+int sdm_mlp_train(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *panes, const float *target,
+                  const sdm_train_params *tp, float *loss_curve, void *hip_stream)
+{
+    if (!net) return SDM_E_INVALID;
+    sdm_context *ctx = net->ctx;
+    if (int rc = mlp_check(net, m, tuples, panes)) return rc;
+    if (!tp || !target) return fail(ctx, SDM_E_INVALID, "null argument");
+    if (tp->steps < 0 || tp->batch < 1 || tp->batch > m)
+        return fail(ctx, SDM_E_INVALID, "need 0 <= steps and 1 <= batch <= m");
+    if (!(tp->lr > 0.0f) || !(tp->beta1 >= 0.0f && tp->beta1 < 1.0f) || !(tp->beta2 >= 0.0f && tp->beta2 < 1.0f) ||
+        !(tp->eps > 0.0f))
+        return fail(ctx, SDM_E_INVALID, "bad optimiser constants");
+    if (tp->steps == 0) return SDM_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(ctx, ctx->flag.ensure(sizeof(int)));
+    HIPCHK(ctx, net->loss.ensure((size_t)tp->steps * sizeof(float)));
+    launch_zero_i32(ctx->flag.as<int>(), 1, s);
+    const int64_t nb = m / tp->batch;
+    for (int32_t step = 0; step < tp->steps; ++step) {
+        const int64_t off = (step % nb) * (int64_t)tp->batch;
+        if (int rc = mlp_enqueue_grad(net, tp->batch, tuples + 4 * off, panes + off, target + 3 * off,
+                                      net->grad.as<float>(), net->loss.as<float>() + step, s))
+            return rc;
+        ++net->t;
+        const float c1 = (float)(1.0 - std::pow((double)tp->beta1, (double)net->t));
+        const float c2 = (float)(1.0 - std::pow((double)tp->beta2, (double)net->t));
+        launch_mlp_adam((int)net->P, net->grad.as<float>(), net->params.as<float>(), net->m1.as<float>(),
+                        net->m2.as<float>(), tp->lr, tp->beta1, tp->beta2, tp->eps, c1, c2, s);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    if (int rc = check_flag(ctx, s, "sdm_mlp_train")) return rc;
+    if (loss_curve)
+        HIPCHK(ctx, hipMemcpy(loss_curve, net->loss.p, (size_t)tp->steps * sizeof(float), hipMemcpyDeviceToHost));
+    return SDM_OK;
+}
+
+int sdm_mlp_infer(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *panes, float *out, void *hip_stream)
+{
+    if (!net) return SDM_E_INVALID;
+    sdm_context *ctx = net->ctx;
+    if (int rc = mlp_check(net, m, tuples, panes)) return rc;
+    if (m == 0) return SDM_OK;
+    if (!out) return fail(ctx, SDM_E_INVALID, "null output");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(ctx, ctx->flag.ensure(sizeof(int)));
+    launch_zero_i32(ctx->flag.as<int>(), 1, s);
+    launch_mlp_pack(net->params.as<float>(), net->wb.p, net->bb.as<float>(), s);
+    launch_mlp_infer((uint32_t)m, net->n_panes, tuples, panes, net->wb.p, net->bb.as<float>(),
+                     net->params.as<float>() + mlp_net_params(), out, ctx->flag.as<int>(), ctx->num_cu, s);
+    HIPCHK(ctx, hipGetLastError());
+    return check_flag(ctx, s, "sdm_mlp_infer");
+}
+
+int sdm_debug_mfma(sdm_context *ctx, const float *A32, const float *B32, float *C32, const float *A16,
+                   const float *B16, float *C16, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!A32 || !B32 || !C32 || !A16 || !B16 || !C16) return fail(ctx, SDM_E_INVALID, "null array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    launch_mfma_probe(A32, B32, C32, A16, B16, C16, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
     return SDM_OK;

@@ -74,6 +74,11 @@ class Outputs(C.Structure):
                 ("xyz_mem", C.c_int32), ("stats", C.POINTER(Stats))]
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float)]
+
+
 class SdmError(RuntimeError):
     pass
 
@@ -100,13 +105,26 @@ def lib():
         L.sdm_slab_eval.argtypes = [vp, C.c_int64] + [vp] * 9
         L.sdm_debug_intersect.argtypes = [vp, vp, C.c_int64] + [vp] * 7
         L.sdm_debug_shadow.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_float, vp, vp]
+        L.sdm_slab_mc.argtypes = ([vp, C.c_int64] + [vp] * 7 + [C.c_float, C.c_float, C.c_int32, C.c_uint64,
+                                                                 C.c_uint32, C.c_int32] + [vp] * 5)
+        L.sdm_mlp_nparams.restype = C.c_int64
+        L.sdm_mlp_nparams.argtypes = [C.c_int32]
+        L.sdm_mlp_create.argtypes = [vp, C.c_int32, vp, C.POINTER(vp)]
+        L.sdm_mlp_destroy.argtypes = [vp]
+        L.sdm_mlp_get_params.argtypes = [vp, vp]
+        L.sdm_mlp_grad.argtypes = [vp, C.c_int64] + [vp] * 6
+        L.sdm_mlp_train.argtypes = [vp, C.c_int64] + [vp] * 3 + [C.POINTER(TrainParams), vp, vp]
+        L.sdm_mlp_infer.argtypes = [vp, C.c_int64] + [vp] * 4
+        L.sdm_debug_mfma.argtypes = [vp] * 8
         _lib = L
     return _lib
 
 
 EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_scene_create",
             "sdm_scene_destroy", "sdm_scene_info", "sdm_render", "sdm_slab_eval",
-            "sdm_debug_intersect", "sdm_debug_shadow")
+            "sdm_debug_intersect", "sdm_debug_shadow", "sdm_slab_mc", "sdm_mlp_nparams",
+            "sdm_mlp_create", "sdm_mlp_destroy", "sdm_mlp_get_params", "sdm_mlp_grad",
+            "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma")
 
 
 def _stream(stream=None):
@@ -279,3 +297,92 @@ def debug_shadow(ctx: Context, scene: Scene, o, lambda_nm, skip=None, stream=Non
     ctx.check(lib().sdm_debug_shadow(ctx.ptr, scene.ptr, m, _ptr(o), _ptr(skip), float(lambda_nm),
                                      _ptr(T), _stream(stream)), "sdm_debug_shadow")
     return T
+
+
+PRECISION = {"fp32": 0, "fp64": 1}
+
+
+def slab_mc(ctx: Context, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint=None, rmin_um=10.0,
+            rmax_um=200.0, n_photons=64, seed=0, tuple0=0, precision="fp32", stream=None):
+    """Bubbly-slab Monte Carlo on device float32 tensors of length m ->
+    (R, T, A, w_lobe) device tensors."""
+    import torch
+    m = cos_i.numel()
+    out = [torch.empty_like(cos_i) for _ in range(4)]
+    ctx.check(lib().sdm_slab_mc(ctx.ptr, m, _ptr(cos_i), _ptr(lambda_nm), _ptr(d_mm), _ptr(rho_b), _ptr(n),
+                                _ptr(k), _ptr(alpha_tint), float(rmin_um), float(rmax_um), int(n_photons),
+                                int(seed), int(tuple0), PRECISION[precision], *[_ptr(o) for o in out],
+                                _stream(stream)), "sdm_slab_mc")
+    return tuple(out)
+
+
+def mlp_nparams(n_panes):
+    return int(lib().sdm_mlp_nparams(int(n_panes)))
+
+
+class MLP:
+    """Surrogate network held by the library (FP32 master weights, BF16 copy,
+    Adam state)."""
+
+    def __init__(self, ctx: Context, n_panes, params):
+        self.ctx = ctx
+        self.n_panes = int(n_panes)
+        p = _f32(params).reshape(-1)
+        if p.size != mlp_nparams(n_panes):
+            raise SdmError(f"expected {mlp_nparams(n_panes)} parameters, got {p.size}")
+        h = C.c_void_p()
+        ctx.check(lib().sdm_mlp_create(ctx.ptr, self.n_panes, p.ctypes.data, C.byref(h)), "sdm_mlp_create")
+        self.ptr = h
+
+    def params(self):
+        p = np.empty(mlp_nparams(self.n_panes), dtype=np.float32)
+        self.ctx.check(lib().sdm_mlp_get_params(self.ptr, p.ctypes.data), "sdm_mlp_get_params")
+        return p
+
+    def grad(self, tuples, panes, target, stream=None):
+        """Device tensors tuples [m,4] f32, panes [m] i32, target [m,3] f32 ->
+        (gradient device tensor, mean loss)."""
+        import torch
+        g = torch.empty(mlp_nparams(self.n_panes), dtype=torch.float32, device=tuples.device)
+        loss = C.c_float()
+        self.ctx.check(lib().sdm_mlp_grad(self.ptr, tuples.shape[0], _ptr(tuples), _ptr(panes), _ptr(target),
+                                          _ptr(g), C.byref(loss), _stream(stream)), "sdm_mlp_grad")
+        return g, float(loss.value)
+
+    def train(self, tuples, panes, target, steps, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              stream=None):
+        """Adam steps; returns the loss before each step (numpy)."""
+        tp = TrainParams(int(steps), int(batch), float(lr), float(beta1), float(beta2), float(eps))
+        curve = np.zeros(max(int(steps), 1), dtype=np.float32)
+        self.ctx.check(lib().sdm_mlp_train(self.ptr, tuples.shape[0], _ptr(tuples), _ptr(panes), _ptr(target),
+                                           C.byref(tp), curve.ctypes.data, _stream(stream)), "sdm_mlp_train")
+        return curve[:int(steps)]
+
+    def infer(self, tuples, panes, stream=None):
+        import torch
+        out = torch.empty((tuples.shape[0], 3), dtype=torch.float32, device=tuples.device)
+        self.ctx.check(lib().sdm_mlp_infer(self.ptr, tuples.shape[0], _ptr(tuples), _ptr(panes), _ptr(out),
+                                           _stream(stream)), "sdm_mlp_infer")
+        return out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().sdm_mlp_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def debug_mfma(ctx: Context, A32, B32, A16, B16, stream=None):
+    """Device float32 [16,32] x [32,16] and [16,16] x [16,16] products on the
+    matrix cores (inputs rounded to BF16)."""
+    import torch
+    C32 = torch.empty((16, 16), dtype=torch.float32, device=A32.device)
+    C16 = torch.empty((16, 16), dtype=torch.float32, device=A32.device)
+    ctx.check(lib().sdm_debug_mfma(ctx.ptr, _ptr(A32), _ptr(B32), _ptr(C32), _ptr(A16), _ptr(B16), _ptr(C16),
+                                   _stream(stream)), "sdm_debug_mfma")
+    return C32, C16

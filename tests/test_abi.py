@@ -19,7 +19,7 @@ def declared_functions():
     for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
         text = open(h).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names |= set(re.findall(r"^\s*(?:int|const\s+char\s*\*|void)\s*\**\s*(sdm_\w+)\s*\(", text, re.M))
+        names |= set(re.findall(r"^\s*(?:int64_t|int|const\s+char\s*\*|void)\s*\**\s*(sdm_\w+)\s*\(", text, re.M))
     return sorted(names)
 
 
@@ -33,11 +33,34 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = declared_functions()
-    assert len(names) >= 9
+    assert len(names) >= 19
     for n in names:
         assert hasattr(lib, n), n
     from paper_1912_05494_amd import sdm
     assert set(sdm.EXPORTED) <= set(names)
+
+
+def declared_arity():
+    """Parameter count of every prototype in the public headers."""
+    out = {}
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for m in re.finditer(r"^\s*(?:int64_t|int|const\s+char\s*\*|void)\s*\**\s*(sdm_\w+)\s*\(([^)]*)\)\s*;",
+                             text, re.M):
+            args = [a for a in m.group(2).split(",") if a.strip() and a.strip() != "void"]
+            out[m.group(1)] = len(args)
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    from paper_1912_05494_amd import sdm
+    if not os.path.exists(sdm.LIB_PATH):
+        pytest.skip("library not built")
+    L = sdm.lib()
+    arity = declared_arity()
+    assert set(sdm.EXPORTED) <= set(arity)
+    for name in sdm.EXPORTED:
+        assert len(getattr(L, name).argtypes) == arity[name], name
 
 
 def test_binding_layouts_match_header():
@@ -54,6 +77,8 @@ int main(void) {
   printf("sdm_render_params %zu\n", sizeof(sdm_render_params));
   printf("sdm_stats %zu\n", sizeof(sdm_stats));
   printf("sdm_outputs %zu\n", sizeof(sdm_outputs));
+  printf("sdm_train_params %zu\n", sizeof(sdm_train_params));
+  P(sdm_train_params, lr); P(sdm_train_params, eps);
   P(sdm_material, thick_mm); P(sdm_material, pane_id);
   P(sdm_scene_desc, mats); P(sdm_scene_desc, sun_dir); P(sdm_scene_desc, sky_L);
   P(sdm_render_params, seed); P(sdm_render_params, band_edges);
@@ -71,7 +96,8 @@ int main(void) {
         out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
     got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     m = {"sdm_material": sdm.Material, "sdm_scene_desc": sdm.SceneDesc, "sdm_camera": sdm.Camera,
-         "sdm_render_params": sdm.RenderParams, "sdm_stats": sdm.Stats, "sdm_outputs": sdm.Outputs}
+         "sdm_render_params": sdm.RenderParams, "sdm_stats": sdm.Stats, "sdm_outputs": sdm.Outputs,
+         "sdm_train_params": sdm.TrainParams}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")

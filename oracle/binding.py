@@ -10,7 +10,9 @@ from .build import ensure_built
 
 __all__ = ["lib", "OracleScene", "philox", "u01", "fresnel", "slab", "snell_cos_t",
            "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir", "slab_mc",
-           "fresnel_real", "bubble_dir", "mlp_nparams", "mlp_forward", "mlp_loss_grad"]
+           "fresnel_real", "bubble_dir", "mlp_nparams", "mlp_forward", "mlp_loss_grad", "walk_draw",
+           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "slab_to_world",
+           "BTDF_MODES"]
 
 _lib = None
 
@@ -39,7 +41,22 @@ class _Params(C.Structure):
                 ("seed", C.c_uint64), ("job_id", C.c_uint32), ("n_lambda", C.c_int32),
                 ("lambda_nm", C.POINTER(C.c_double)), ("cmf_xyz", C.POINTER(C.c_double)),
                 ("n_bands", C.c_int32), ("tile", C.c_int32), ("beta_threshold", C.c_double),
-                ("use_bvh", C.c_int32), ("n_threads", C.c_int32)]
+                ("use_bvh", C.c_int32), ("n_threads", C.c_int32),
+                ("btdf_mode", C.c_int32), ("mlp_n_panes", C.c_int32), ("mlp_bf16", C.c_int32),
+                ("err_dims", C.c_int32 * 3), ("mlp_params", C.POINTER(C.c_double)),
+                ("err_table", C.POINTER(C.c_double)), ("err_bound", C.c_double)]
+
+
+class _WalkStream(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("c0", C.c_uint32), ("c1", C.c_uint32), ("c3", C.c_uint32),
+                ("vertex", C.c_uint32), ("render", C.c_int32)]
+
+
+class _WalkOut(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dir", C.c_double * 3), ("L", C.c_double)]
+
+
+BTDF_MODES = {"exact": 0, "surrogate": 1, "fallback": 2}
 
 
 def _dp(a):
@@ -81,8 +98,18 @@ def lib():
                                      C.c_double, C.c_void_p, C.c_void_p]
         L.orc_cosine_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_void_p]
         L.orc_spec_to_xyz.argtypes = [C.c_int64, C.c_int32] + [C.c_void_p] * 4
-        L.orc_slab_mc.argtypes = ([C.c_int64] + [C.c_void_p] * 4 + [C.c_double] * 2 + [C.c_void_p] * 3
+        L.orc_slab_mc.argtypes = ([C.c_int64] + [C.c_void_p] * 4 + [C.c_double] * 2 + [C.c_void_p] * 4
                                   + [C.c_uint64, C.c_uint32, C.c_int32] + [C.c_void_p] * 4)
+        L.orc_walk_draw.argtypes = [C.POINTER(_WalkStream), C.c_uint32, C.c_uint32, C.c_void_p]
+        L.orc_bubbly_walk.argtypes = [C.POINTER(_WalkStream)] + [C.c_double] * 4 + [C.c_int,
+                                                                                  C.POINTER(_WalkOut)]
+        L.orc_bubble_sigma.restype = C.c_double
+        L.orc_bubble_sigma.argtypes = [C.c_double] * 3
+        L.orc_mlp_forward_bf16.argtypes = [C.c_void_p, C.c_int32, C.c_int64] + [C.c_void_p] * 3
+        L.orc_bf16.restype = C.c_double
+        L.orc_bf16.argtypes = [C.c_double]
+        L.orc_lobe_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.orc_slab_to_world.argtypes = [C.c_void_p] * 4
         L.orc_fresnel_real.restype = C.c_double
         L.orc_fresnel_real.argtypes = [C.c_double] * 3 + [C.c_int]
         L.orc_bubble_dir.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_void_p]
@@ -195,7 +222,10 @@ class OracleScene:
         return T
 
 
-def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None):
+def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=None):
+    """btdf: None (exact walks on bubbly panes) or a dict with keys mode
+    ("exact" / "surrogate" / "fallback"), params, n_panes, bf16 (bool) and,
+    for "fallback", err_table (n_panes, n_cos, n_d, n_rho) and bound."""
     cam = settings.camera
     lam = np.ascontiguousarray(settings.lambda_nm, dtype=np.float64)
     cmf = np.ascontiguousarray(settings.cmf, dtype=np.float64).reshape(-1)
@@ -205,12 +235,27 @@ def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None):
                 int(settings.seed), int(settings.job_id), len(lam), _dp(lam), _dp(cmf),
                 int(settings.n_bands if n_bands is None else n_bands), int(tile),
                 float(settings.beta_threshold), int(use_bvh), int(n_threads))
-    return p, (lam, cmf)
+    keep = [lam, cmf]
+    if btdf is not None:
+        p.btdf_mode = BTDF_MODES[btdf.get("mode", "exact")]
+        if btdf.get("params") is not None:
+            prm = np.ascontiguousarray(btdf["params"], dtype=np.float64)
+            keep.append(prm)
+            p.mlp_params = _dp(prm)
+            p.mlp_n_panes = int(btdf["n_panes"])
+            p.mlp_bf16 = int(bool(btdf.get("bf16", False)))
+        if btdf.get("err_table") is not None:
+            tab = np.ascontiguousarray(btdf["err_table"], dtype=np.float64)
+            keep.append(tab)
+            p.err_table = _dp(tab)
+            p.err_dims = (C.c_int32 * 3)(*tab.shape[1:4])
+            p.err_bound = float(btdf.get("bound", 1e-3))
+    return p, keep
 
 
-def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None):
+def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=None):
     """Full image -> (spec (H, W, nl) float64, xyz (H, W, 3) float64)."""
-    p, keep = _params(settings, use_bvh, tile, n_threads, n_bands)
+    p, keep = _params(settings, use_bvh, tile, n_threads, n_bands, btdf)
     W, H, nl = settings.camera.W, settings.camera.H, len(settings.lambda_nm)
     spec = np.empty((H, W, nl))
     xyz = np.empty((H, W, 3))
@@ -220,9 +265,9 @@ def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None):
     return spec, xyz
 
 
-def render_pixels(oscene, settings, pixels, use_bvh=True, n_threads=0):
+def render_pixels(oscene, settings, pixels, use_bvh=True, n_threads=0, btdf=None):
     """Selected linear pixel indices -> spec (m, nl) float64."""
-    p, keep = _params(settings, use_bvh, 16, n_threads)
+    p, keep = _params(settings, use_bvh, 16, n_threads, btdf=btdf)
     px = np.ascontiguousarray(pixels, dtype=np.int32)
     spec = np.empty((len(px), len(settings.lambda_nm)))
     rc = lib().orc_render_pixels(oscene.ptr, C.byref(p), len(px), px.ctypes.data, spec.ctypes.data)
@@ -248,10 +293,12 @@ def cosine_dir(n, u1, u2):
 
 
 def slab_mc(cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint, seed=0, tuple0=0, n_photons=64,
-            rmin_um=10.0, rmax_um=200.0):
-    """Bubbly-slab Monte Carlo per tuple -> (R, T, A, w_lobe) float64 arrays."""
+            rmin_um=10.0, rmax_um=200.0, n_ref=None):
+    """Bubbly-slab Monte Carlo per tuple -> (R, T, A, w_lobe) float64 arrays.
+    n_ref: index used inside the slab (default: n)."""
     arrs = np.broadcast_arrays(*[np.asarray(a, dtype=np.float64) for a in
-                                 (cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint)])
+                                 (cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint,
+                                  n if n_ref is None else n_ref)])
     flat = [np.ascontiguousarray(a.reshape(-1)) for a in arrs]
     m = flat[0].size
     R, T, A, W = (np.empty(m) for _ in range(4))
@@ -259,6 +306,57 @@ def slab_mc(cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint, seed=0, tuple0=0, n
                       *[a.ctypes.data for a in flat[4:]], int(seed), int(tuple0), int(n_photons),
                       R.ctypes.data, T.ctypes.data, A.ctypes.data, W.ctypes.data)
     return R, T, A, W
+
+
+def walk_draw(seed, c0, c1, event, sub, render=False, vertex=0, c3=0):
+    st = _WalkStream(int(seed), int(c0), int(c1), int(c3), int(vertex), int(bool(render)))
+    u = np.empty(4)
+    lib().orc_walk_draw(C.byref(st), int(event), int(sub), u.ctypes.data)
+    return u
+
+
+def bubbly_walk(cos_i, d_mm, sigma, n_ref, pol, seed=0, c0=0, c1=0, render=False, vertex=0, c3=0):
+    """One walk inside a bubbly slab -> (kind, direction (3,), length in glass)."""
+    st = _WalkStream(int(seed), int(c0), int(c1), int(c3), int(vertex), int(bool(render)))
+    out = _WalkOut()
+    lib().orc_bubbly_walk(C.byref(st), float(cos_i), float(d_mm), float(sigma), float(n_ref), int(pol),
+                          C.byref(out))
+    return out.kind, np.array(out.dir[:]), out.L
+
+
+def bubble_sigma(rho_b, rmin_um=10.0, rmax_um=200.0):
+    return lib().orc_bubble_sigma(float(rho_b), float(rmin_um), float(rmax_um))
+
+
+def bf16(x):
+    return np.array([lib().orc_bf16(float(v)) for v in np.asarray(x, dtype=np.float64).reshape(-1)])
+
+
+def mlp_forward_bf16(params, n_panes, tuples, panes):
+    """The network with BF16 operands (inputs, weights, hidden activations)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(tuples, dtype=np.float64).reshape(-1, 4)
+    pn = np.ascontiguousarray(panes, dtype=np.int32)
+    out = np.empty((len(x), 3))
+    lib().orc_mlp_forward_bf16(p.ctypes.data, int(n_panes), len(x), x.ctypes.data, pn.ctypes.data,
+                               out.ctypes.data)
+    return out
+
+
+def lobe_dir(d, w, u1, u2):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.empty(3)
+    lib().orc_lobe_dir(d.ctypes.data, float(w), float(u1), float(u2), out.ctypes.data)
+    return out
+
+
+def slab_to_world(d, ng, a):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    ng = np.ascontiguousarray(ng, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.empty(3)
+    lib().orc_slab_to_world(d.ctypes.data, ng.ctypes.data, a.ctypes.data, out.ctypes.data)
+    return out
 
 
 def fresnel_real(n1, n2, c, pol):

@@ -84,6 +84,56 @@ static void heads(const double *o, double *out)
     out[2] = softplus(o[2]);
 }
 
+/* Round to the nearest bfloat16 (8-bit significand), ties to even, through
+ * float32 as the matrix-core operands are formed. */
+double orc_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7f800000u) == 0x7f800000u) return x;   /* inf / nan unchanged */
+    b = (b + 0x7fffu + ((b >> 16) & 1u)) & 0xffff0000u;
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+/* Layer with BF16 operands: y = b + sum bf16(W) bf16(x), summed in double;
+ * biases and sums stay wide. */
+static void dense_bf16(const double *W, const double *b, const double *xb, int nin, int nout, double *y)
+{
+    for (int o = 0; o < nout; ++o) {
+        double s = 0.0;
+        for (int i = 0; i < nin; ++i) s += orc_bf16(W[o * nin + i]) * xb[i];
+        y[o] = (double)(float)s + (double)(float)b[o];
+    }
+}
+
+/* Network evaluated with BF16 operands (inputs, weights and hidden
+ * activations rounded to bfloat16), the arithmetic of the matrix-core path. */
+void orc_mlp_forward_bf16(const double *params, int32_t n_panes, int64_t m, const double *tuples,
+                          const int32_t *panes, double *out)
+{
+    (void)n_panes;
+    view v = make_view(params);
+    for (int64_t s = 0; s < m; ++s) {
+        const double *t = tuples + 4 * s;
+        double x[NIN], z1[NH], h1[NH], z2[NH], h2[NH], z3[NH], h3[NH], o[NOUT];
+        x[0] = orc_bf16((float)t[0]);
+        x[1] = orc_bf16(((float)t[1] - 580.0f) / 200.0f);
+        x[2] = orc_bf16(((float)t[2] - 3.5f) / 1.5f);
+        x[3] = orc_bf16((float)t[3] / 34.0f);
+        for (int e = 0; e < NEMB; ++e) x[4 + e] = orc_bf16(v.E[panes[s] * NEMB + e]);
+        dense_bf16(v.W1, v.b1, x, NIN, NH, z1); relu(z1, NH, h1);
+        for (int i = 0; i < NH; ++i) h1[i] = orc_bf16(h1[i]);
+        dense_bf16(v.W2, v.b2, h1, NH, NH, z2); relu(z2, NH, h2);
+        for (int i = 0; i < NH; ++i) h2[i] = orc_bf16(h2[i]);
+        dense_bf16(v.W3, v.b3, h2, NH, NH, z3); relu(z3, NH, h3);
+        for (int i = 0; i < NH; ++i) h3[i] = orc_bf16(h3[i]);
+        dense_bf16(v.W4, v.b4, h3, NH, NOUT, o);
+        heads(o, out + 3 * s);
+    }
+}
+
 /* tuples: m x 4 (cos, lambda_nm, d_mm, rho_b); panes: m; out: m x 3 (R, T, w) */
 void orc_mlp_forward(const double *params, int32_t n_panes, int64_t m, const double *tuples,
                      const int32_t *panes, double *out)

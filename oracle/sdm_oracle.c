@@ -153,6 +153,8 @@ typedef struct {
     int32_t type;
     double thick_mm;
     double *albedo, *n, *k, *tint; /* owned copies [n_tab] */
+    double density, rmin_um, rmax_um; /* bubbly glass */
+    int32_t pane_id;
 } omat;
 
 struct orc_scene {
@@ -288,6 +290,10 @@ orc_scene *orc_scene_create(const orc_scene_desc *d)
         s->mats[m].n = dup_d(mm->n, d->n_tab);
         s->mats[m].k = dup_d(mm->k, d->n_tab);
         s->mats[m].tint = dup_d(mm->alpha_tint, d->n_tab);
+        s->mats[m].density = mm->bubble_density;
+        s->mats[m].rmin_um = mm->bubble_rmin_um;
+        s->mats[m].rmax_um = mm->bubble_rmax_um;
+        s->mats[m].pane_id = mm->pane_id;
     }
     s->tab_lambda = dup_d(d->tab_lambda_nm, d->n_tab);
     s->sun_E = dup_d(d->sun_E, d->n_tab);
@@ -438,6 +444,7 @@ static double thickness_at(const orc_scene *s, int32_t t, double u, double v)
 typedef struct {
     int32_t nl;
     double *lam, *rho, *n, *k, *tint, *E, *Lsky; /* rho/n/k/tint are [n_mat][nl] */
+    double *nref, *sigma;                        /* [n_mat]: bubbly panes */
 } spectra;
 
 /* Sun transmittance along x + t * sun (t > teps, t unbounded): zero if any
@@ -475,8 +482,11 @@ static double shadow_T(const orc_scene *s, const spectra *sp, int use_bvh, const
             double R, Tr;
             double c = fabs(dot3(d, s->ng + 3 * t));
             int32_t mi = s->mat[t];
+            /* Reading: toward the delta sun only the unscattered (ballistic)
+             * light of a bubbly pane counts, so the bubbles' extinction adds
+             * to the absorption of the slab. */
             orc_slab(c, lambda_nm, thickness_at(s, t, u, v), sp->n[mi * sp->nl + li],
-                     sp->k[mi * sp->nl + li], sp->tint[mi * sp->nl + li], &R, &Tr);
+                     sp->k[mi * sp->nl + li], sp->tint[mi * sp->nl + li] + sp->sigma[mi], &R, &Tr);
             T *= Tr;
         }
     }
@@ -521,6 +531,15 @@ static void spectra_make(const orc_scene *s, const orc_render_params *p, spectra
     sp->tint = (double *)calloc((size_t)(nm * nl + 1), sizeof(double));
     sp->E = (double *)malloc(sizeof(double) * (size_t)nl);
     sp->Lsky = (double *)malloc(sizeof(double) * (size_t)nl);
+    sp->nref = (double *)calloc((size_t)(nm + 1), sizeof(double));
+    sp->sigma = (double *)calloc((size_t)(nm + 1), sizeof(double));
+    for (int m = 0; m < nm; ++m) {
+        const omat *mm = &s->mats[m];
+        /* Reading: inside a bubbly pane the walk uses the pane's index at
+         * 560 nm (R1 interpolation of its table). */
+        sp->nref[m] = mm->n ? interp_tab(s, mm->n, 560.0) : 1.0;
+        if (mm->type == ORC_GLASS_BUBBLY) sp->sigma[m] = orc_bubble_sigma(mm->density, mm->rmin_um, mm->rmax_um);
+    }
     for (int i = 0; i < nl; ++i) {
         double x = p->lambda_nm[i];
         sp->lam[i] = x;
@@ -539,6 +558,7 @@ static void spectra_make(const orc_scene *s, const orc_render_params *p, spectra
 static void spectra_free(spectra *sp)
 {
     free(sp->lam); free(sp->rho); free(sp->n); free(sp->k); free(sp->tint); free(sp->E); free(sp->Lsky);
+    free(sp->nref); free(sp->sigma);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -626,6 +646,65 @@ static void cosine_dir(const double *ns, double u1, double u2, double *d)
 
 void orc_cosine_dir(const double n[3], double u1, double u2, double d[3]) { cosine_dir(n, u1, u2, d); }
 
+/* Reading: the surrogate's transmitted direction is d plus a 2-D Gaussian
+ * offset of standard deviation w per tangent axis (Box-Muller on u1, u2) in
+ * the basis of onb(d), normalised. */
+void orc_lobe_dir(const double d[3], double w, double u1, double u2, double out[3])
+{
+    double t1[3], t2[3];
+    onb(d, t1, t2);
+    double g = sqrt(-2.0 * log1p(-u1)), phi = 2.0 * PI * u2;
+    double g1 = g * cos(phi), g2 = g * sin(phi);
+    for (int a = 0; a < 3; ++a) out[a] = d[a] + w * (g1 * t1[a] + g2 * t2[a]);
+    normalize3(out);
+}
+
+/* Slab frame of a hit: z along the face normal on the far side of the
+ * incoming ray, x along the ray's component in the face (the onb() axis
+ * when the ray meets the face head-on), y = z x x. */
+void orc_slab_to_world(const double d[3], const double ng[3], const double a[3], double out[3])
+{
+    double nz[3], ex[3], ey[3], t2[3];
+    double dn = dot3(d, ng);
+    for (int i = 0; i < 3; ++i) nz[i] = dn > 0.0 ? ng[i] : -ng[i];
+    double c = fabs(dn);
+    for (int i = 0; i < 3; ++i) ex[i] = d[i] - c * nz[i];
+    double len = sqrt(dot3(ex, ex));
+    if (len > 1e-7) {
+        for (int i = 0; i < 3; ++i) ex[i] /= len;
+    } else {
+        onb(nz, ex, t2);
+    }
+    cross3(nz, ex, ey);
+    for (int i = 0; i < 3; ++i) out[i] = a[0] * ex[i] + a[1] * ey[i] + a[2] * nz[i];
+    normalize3(out);
+}
+
+/* Evaluation of a bubbly-pane vertex: the mode, after the error-table check
+ * of the fallback mode (cell value above the bound -> exact walk). */
+static int bubbly_mode(const orc_render_params *p, const omat *mm, double cos_i, double d)
+{
+    if (p->btdf_mode != ORC_BTDF_FALLBACK) return p->btdf_mode;
+    const int nc = p->err_dims[0], nd = p->err_dims[1], nr = p->err_dims[2];
+    int ic = (int)(cos_i * nc);
+    int id = (int)((d - ORC_ERR_D_LO) / (ORC_ERR_D_HI - ORC_ERR_D_LO) * nd);
+    int ir = (int)(mm->density / ORC_ERR_RHO_HI * nr);
+    ic = ic < 0 ? 0 : (ic >= nc ? nc - 1 : ic);
+    id = id < 0 ? 0 : (id >= nd ? nd - 1 : id);
+    ir = ir < 0 ? 0 : (ir >= nr ? nr - 1 : ir);
+    double e = p->err_table[(((int64_t)mm->pane_id * nc + ic) * nd + id) * nr + ir];
+    return e > p->err_bound ? ORC_BTDF_EXACT : ORC_BTDF_SURROGATE;
+}
+
+static void surrogate_eval(const orc_render_params *p, const omat *mm, double cos_i, double lambda, double d,
+                           double out[3])
+{
+    double tup[4] = {cos_i, lambda, d, mm->density};
+    int32_t pane = mm->pane_id;
+    if (p->mlp_bf16) orc_mlp_forward_bf16(p->mlp_params, p->mlp_n_panes, 1, tup, &pane, out);
+    else orc_mlp_forward(p->mlp_params, p->mlp_n_panes, 1, tup, &pane, out);
+}
+
 /* One (pixel, sample, wavelength) path estimate. */
 static double path_radiance(const rctx *c, int i, int j, int smp, int li)
 {
@@ -669,6 +748,52 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li)
              * weight is multiplied by the albedo. */
             cosine_dir(ns, u[1], u[2], d);
             beta *= rho;
+        } else if (s->mats[mi].type == ORC_GLASS_BUBBLY) {
+            /* Bubbly pane (air micro-particles, Sec. 1; scattering, Sec. 6). */
+            if (vtx == p->max_depth - 1) break;
+            const omat *mm = &s->mats[mi];
+            double cos_i = fabs(dot3(d, ng));
+            double thick = thickness_at(s, h.tri, h.u, h.v);
+            if (bubbly_mode(p, mm, cos_i, thick) == ORC_BTDF_EXACT) {
+                /* Exact walk: entry interface at this wavelength (eq. (1)),
+                 * then the wavelength-independent walk inside; the weight is
+                 * the absorption along the walk's length in glass. */
+                orc_walk_stream st = {p->seed, pixel, (uint32_t)smp, p->job_id, (uint32_t)vtx, 1};
+                double ue[4], Rs, Rp;
+                orc_walk_draw(&st, 0, 0, ue);
+                int pol = ue[1] < 0.5 ? 0 : 1;
+                orc_fresnel(cos_i, sp->n[mi * sp->nl + li], sp->k[mi * sp->nl + li], &Rs, &Rp);
+                if (ue[0] < (pol == 0 ? Rs : Rp)) {
+                    double dn = dot3(d, ng);
+                    for (int a = 0; a < 3; ++a) d[a] -= 2.0 * dn * ng[a];
+                } else {
+                    orc_walk_out wo;
+                    orc_bubbly_walk(&st, cos_i, thick, sp->sigma[mi], sp->nref[mi], pol, &wo);
+                    if (wo.kind == 0) break;
+                    double alpha = 4.0 * PI * sp->k[mi * sp->nl + li] / (lambda * 1e-6) + sp->tint[mi * sp->nl + li];
+                    double nd[3];
+                    orc_slab_to_world(d, ng, wo.dir, nd);
+                    for (int a = 0; a < 3; ++a) d[a] = nd[a];
+                    beta *= exp(-alpha * wo.L);
+                }
+            } else {
+                /* Surrogate: (R, T) at this wavelength; reflect with
+                 * probability R / (R + T), else leave through the
+                 * transmitted lobe, whose width is taken at 560 nm so that
+                 * every wavelength of the path keeps one direction. */
+                double y[3], yr[3];
+                surrogate_eval(p, mm, cos_i, lambda, thick, y);
+                surrogate_eval(p, mm, cos_i, 560.0, thick, yr);
+                if (u[0] < y[0] / (y[0] + y[1])) {
+                    double dn = dot3(d, ng);
+                    for (int a = 0; a < 3; ++a) d[a] -= 2.0 * dn * ng[a];
+                } else {
+                    double nd[3];
+                    orc_lobe_dir(d, yr[2], u[1], u[2], nd);
+                    for (int a = 0; a < 3; ++a) d[a] = nd[a];
+                }
+                beta *= y[0] + y[1];
+            }
         } else {
             /* Glass pane as a thin slab (Sec. 6 thickness map): the path
              * reflects with probability R/(R+T), else passes straight
@@ -698,6 +823,15 @@ static int params_ok(const orc_scene *s, const orc_render_params *p)
     if (!s || !p || p->W < 1 || p->H < 1 || p->spp < 1 || p->max_depth < 1 || p->n_lambda < 1 ||
         !p->lambda_nm)
         return 0;
+    if (p->btdf_mode < ORC_BTDF_EXACT || p->btdf_mode > ORC_BTDF_FALLBACK) return 0;
+    for (int m = 0; m < s->n_mat; ++m) {
+        const omat *mm = &s->mats[m];
+        if (mm->type != ORC_GLASS_BUBBLY || p->btdf_mode == ORC_BTDF_EXACT) continue;
+        if (!p->mlp_params || mm->pane_id < 0 || mm->pane_id >= p->mlp_n_panes) return 0;
+        if (p->btdf_mode == ORC_BTDF_FALLBACK &&
+            (!p->err_table || p->err_dims[0] < 1 || p->err_dims[1] < 1 || p->err_dims[2] < 1))
+            return 0;
+    }
     return 1;
 }
 

@@ -28,6 +28,14 @@ extern "C" {
 #endif
 
 enum { ORC_LAMBERT = 0, ORC_GLASS = 1, ORC_GLASS_BUBBLY = 2 };
+/* How a path vertex on a bubbly pane is evaluated: the exact walk, the
+ * surrogate network, or the network unless the error table flags the cell. */
+enum { ORC_BTDF_EXACT = 0, ORC_BTDF_SURROGATE = 1, ORC_BTDF_FALLBACK = 2 };
+/* Error-table cells: cos(theta) in [0, 1], thickness in [2, 5] mm, bubble
+ * density in [0, 34] per mm^3, each split evenly (values outside clamp). */
+#define ORC_ERR_D_LO 2.0
+#define ORC_ERR_D_HI 5.0
+#define ORC_ERR_RHO_HI 34.0
 
 typedef struct {
     int32_t type;
@@ -72,6 +80,14 @@ typedef struct {
     double beta_threshold;    /* energy threshold of Sec. 3.1 (0 = off) */
     int32_t use_bvh;          /* 1: BVH, 0: brute force */
     int32_t n_threads;        /* 0 = OpenMP default */
+    /* bubbly panes */
+    int32_t btdf_mode;        /* ORC_BTDF_* */
+    int32_t mlp_n_panes;      /* embedding rows of the network */
+    int32_t mlp_bf16;         /* 1: network with BF16 operands */
+    int32_t err_dims[3];      /* cells along cos, thickness, density */
+    const double *mlp_params; /* network parameters (ORC_BTDF_SURROGATE / _FALLBACK) */
+    const double *err_table;  /* [mlp_n_panes][err_dims[0]][err_dims[1]][err_dims[2]] */
+    double err_bound;         /* a cell above this uses the exact walk */
 } orc_render_params;
 
 typedef struct orc_scene orc_scene;
@@ -115,17 +131,45 @@ void orc_camera_ray(const orc_render_params *p, int32_t i, int32_t j, double u0,
                     double o[3], double d[3]);
 /* Cosine-weighted direction about unit n from (u1, u2) (exposed for tests). */
 void orc_cosine_dir(const double n[3], double u1, double u2, double d[3]);
+/* Transmitted direction of the surrogate: d tilted by a 2-D Gaussian of
+ * standard deviation w (radians, per tangent axis) from (u1, u2). */
+void orc_lobe_dir(const double d[3], double w, double u1, double u2, double out[3]);
+/* Direction a (slab frame of orc_bubbly_walk) in world space for a ray d
+ * hitting a face of geometric normal ng. */
+void orc_slab_to_world(const double d[3], const double ng[3], const double a[3], double out[3]);
 
 /* Spectral image -> XYZ with trapezoid weights in nm. */
 void orc_spec_to_xyz(int64_t npix, int32_t n_lambda, const double *lambda_nm,
                      const double *cmf_xyz, const double *spec, double *xyz);
 
 /* Bubbly slab Monte Carlo (reading; see slab_mc.c): m tuples of n_photons
- * photons; outputs R, T, A (absorbed) and the transmitted-lobe width. */
+ * photons; outputs R, T, A (absorbed) and the transmitted-lobe width.
+ * n_ref: the real index used inside the slab (NULL = n). */
 void orc_slab_mc(int64_t m, const double *cos_i, const double *lambda_nm, const double *d_mm,
                  const double *rho_b, double rmin_um, double rmax_um, const double *n, const double *k,
-                 const double *alpha_tint, uint64_t seed, uint32_t tuple0, int32_t n_photons, double *R,
-                 double *T, double *A, double *w_lobe);
+                 const double *alpha_tint, const double *n_ref, uint64_t seed, uint32_t tuple0,
+                 int32_t n_photons, double *R, double *T, double *A, double *w_lobe);
+
+/* Draw stream of one walk: render = 0 -> dataset counters (c0 = tuple,
+ * c1 = photon); render = 1 -> (c0 = pixel, c1 = sample, vertex, c3 = job). */
+typedef struct {
+    uint64_t seed;
+    uint32_t c0, c1, c3, vertex;
+    int32_t render;
+} orc_walk_stream;
+
+typedef struct {
+    int32_t kind;   /* 0 absorbed (event cap), 1 out through the entry face, 2 through the far face */
+    double dir[3];  /* direction in air, slab frame (x in the plane of incidence, z into the slab) */
+    double L;       /* geometric length travelled in glass (mm) */
+} orc_walk_out;
+
+/* The four uniforms of draw (event, sub) of a walk stream. */
+void orc_walk_draw(const orc_walk_stream *st, uint32_t event, uint32_t sub, double u[4]);
+void orc_bubbly_walk(const orc_walk_stream *st, double cos_i, double d_mm, double sigma, double n_ref,
+                     int pol, orc_walk_out *out);
+/* Extinction of the bubbles, rho_b pi <r^2> with r ~ U(rmin, rmax) (per mm). */
+double orc_bubble_sigma(double rho_b, double rmin_um, double rmax_um);
 double orc_fresnel_real(double n1, double n2, double c, int pol);
 void orc_bubble_dir(const double dir[3], const double e_perp[3], double sin_i, double n, int p, double out[3]);
 
@@ -135,6 +179,10 @@ void orc_mlp_forward(const double *params, int32_t n_panes, int64_t m, const dou
                      const int32_t *panes, double *out);
 double orc_mlp_loss_grad(const double *params, int32_t n_panes, int64_t m, const double *tuples,
                          const int32_t *panes, const double *target, double *grad);
+/* The same network with BF16 operands (matrix-core arithmetic). */
+void orc_mlp_forward_bf16(const double *params, int32_t n_panes, int64_t m, const double *tuples,
+                          const int32_t *panes, double *out);
+double orc_bf16(double x);
 
 #ifdef __cplusplus
 }

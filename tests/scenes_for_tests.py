@@ -56,3 +56,25 @@ def settings(cam, lam=None, spp=4, max_depth=4, n_bands=1, seed=0, thr=0.0):
 def ortho_down(z, height, W=32, H=32):
     return Camera(eye=(0.0, 0.0, z), target=(0.0, 0.0, z - 1.0), up=(0.0, 1.0, 0.0),
                   W=W, H=H, projection=1, ortho_height=height)
+
+
+def bubbly(n=1.52, k=1e-7, tint=0.0, thick=3.0, density=20.0, rmin=10.0, rmax=200.0, pane_id=0,
+           dispersive=False):
+    g = glass(n, k, tint, thick, dispersive)
+    g.type = synth.GLASS_BUBBLY
+    g.bubble_density = density
+    g.bubble_rmin_um = rmin
+    g.bubble_rmax_um = rmax
+    g.pane_id = pane_id
+    return g
+
+
+def constant_net(n_panes, R, T, w):
+    """Network parameters whose output is (R, T, w) for every input: zero
+    weights and the output biases that give those heads."""
+    from paper_1912_05494_amd import surrogate
+    p = np.zeros(surrogate.n_params(n_panes), dtype=np.float64)
+    s = surrogate.split(p, n_panes)
+    rest = 1.0 - R - T
+    s["b4"][:] = [np.log(R / rest), np.log(T / rest), np.log(np.expm1(w))]
+    return p

@@ -49,27 +49,30 @@ enum { SDM_LAMBERT = 0, SDM_GLASS = 1, SDM_GLASS_BUBBLY = 2 };
 enum { SDM_MEM_HOST = 0, SDM_MEM_DEVICE = 1 };
 enum { SDM_PREC_FP32 = 0, SDM_PREC_FP64 = 1 };
 enum { SDM_PINHOLE = 0, SDM_ORTHO = 1 };
+/* Evaluation of path vertices on bubbly panes (SDM_GLASS_BUBBLY). */
+enum { SDM_BTDF_EXACT = 0, SDM_BTDF_SURROGATE = 1, SDM_BTDF_FALLBACK = 2 };
 
 /* Largest number of wavelengths one spectral band (sub-domain) may hold. */
 #define SDM_MAX_BAND 128
 
 typedef struct sdm_context sdm_context;
 typedef struct sdm_scene sdm_scene;
+typedef struct sdm_mlp sdm_mlp;
 
 /* Material.  Tables are host arrays sampled at the scene's tab_lambda_nm and
  * linearly interpolated to the render wavelengths (held constant beyond the
  * table ends).  Lambert needs albedo; glass needs n and k (eq. (1));
  * alpha_tint (mm^-1, extra absorption) may be NULL for zero. */
 typedef struct {
-    int32_t type;               /* SDM_LAMBERT or SDM_GLASS                    */
+    int32_t type;               /* SDM_LAMBERT, SDM_GLASS or SDM_GLASS_BUBBLY  */
     const float *albedo;        /* [n_tab] or NULL                             */
     const float *n;             /* [n_tab] real index, >= 1                    */
     const float *k;             /* [n_tab] absorption index, >= 0              */
     const float *alpha_tint;    /* [n_tab] mm^-1, or NULL                      */
     float thick_mm;             /* pane thickness when vthick_mm is NULL        */
-    float bubble_density_mm3;   /* heterogeneous glass (reserved)               */
-    float bubble_rmin_um, bubble_rmax_um;
-    int32_t pane_id;
+    float bubble_density_mm3;   /* bubbly glass: air bubbles per mm^3, >= 0     */
+    float bubble_rmin_um, bubble_rmax_um;   /* radius range (micrometres)      */
+    int32_t pane_id;            /* bubbly glass: the network's pane type       */
 } sdm_material;
 
 /* Scene.  Triangles are two-sided.  Units: metres, thickness in mm. */
@@ -113,11 +116,28 @@ typedef struct {
     int32_t precision;          /* SDM_PREC_FP32 (default) or SDM_PREC_FP64    */
     int64_t chunk_paths;        /* in-flight primary paths (0 = default)       */
     int32_t timing;             /* 1: time every kernel with HIP events        */
+    /* Bubbly panes.  SDM_BTDF_EXACT: the photon walk of sdm_slab_mc at each
+     * vertex (entry interface per wavelength with n + ik, walk inside at the
+     * pane's index at 560 nm shared by every wavelength, weight
+     * exp(-alpha L)).  SDM_BTDF_SURROGATE: the network's (R, T) per
+     * wavelength, reflect with probability R / (R + T) else a Gaussian lobe
+     * of the network's width at 560 nm, weight R + T.  SDM_BTDF_FALLBACK: the
+     * surrogate, except where err_table[pane][c][t][r] > err_bound for the
+     * vertex's cell (c: cos theta in [0, 1], t: thickness in [2, 5] mm, r:
+     * density in [0, 34] per mm^3, err_dims cells each, clamped), which take
+     * the exact walk.  Shadow rays through bubbly panes see the slab
+     * transmittance with the bubbles' extinction added to the absorption. */
+    int32_t btdf_mode;
+    int32_t err_dims[3];        /* cells along cos, thickness, density          */
+    const sdm_mlp *mlp;         /* network (surrogate modes), same context      */
+    const float *err_table;     /* host [n_panes * err_dims product] (fallback) */
+    float err_bound;
 } sdm_render_params;
 
 /* Kernel classes reported in sdm_stats. */
 enum { SDM_K_GENERATE = 0, SDM_K_TRACE = 1, SDM_K_SHADE = 2, SDM_K_SHADOW = 3,
-       SDM_K_FINALIZE = 4, SDM_K_SHADOW_ACCUM = 5, SDM_K_SHADE_GLASS = 6, SDM_K_COUNT = 7 };
+       SDM_K_FINALIZE = 4, SDM_K_SHADOW_ACCUM = 5, SDM_K_SHADE_GLASS = 6, SDM_K_BUBBLY_EVAL = 7,
+       SDM_K_SHADE_BUBBLY = 8, SDM_K_COUNT = 9 };
 
 typedef struct {
     uint64_t spectral_samples;  /* W*H*spp*n_lambda                            */
@@ -128,6 +148,7 @@ typedef struct {
     uint64_t chunks;            /* wavefront chunks                            */
     uint64_t nodes_visited[2];  /* BVH node fetches [closest-hit, shadow]      */
     uint64_t tris_tested[2];    /* ray-triangle tests [closest-hit, shadow]    */
+    uint64_t bubbly_vertices;   /* path vertices shaded on bubbly panes         */
     double ms_render;          /* wall time of the render on the stream       */
     double kernel_ms[SDM_K_COUNT];     /* summed kernel durations (timing=1)   */
     uint64_t kernel_launches[SDM_K_COUNT];
@@ -196,25 +217,28 @@ int sdm_scene_info(const sdm_scene *scene, int32_t *n_nodes, int32_t *depth);
  * n_photons photon walks each.  Inputs are DEVICE float arrays of length m:
  * cos_i (incidence cosine, (0, 1]), lambda_nm, d_mm (thickness), rho_b
  * (bubbles per mm^3, >= 0), n, k (optical constants of eq. (1) at lambda),
- * alpha_tint (per mm, may be NULL for 0).  Bubble radii are uniform in
- * [rmin_um, rmax_um] micrometres.  The walk: complex-index Fresnel at entry,
- * Beer-Lambert weight in glass, Poisson bubbles with extinction rho_b pi <r^2>
- * acting at the collision point with exact sphere optics for the new
- * direction (outer reflection or p internal reflections), Fresnel / total
- * reflection at the faces; a fresh s/p label per bubble.  Random numbers are
- * Philox4x32-10 with counter (tuple0 + i, photon, event, 0x5EB10000 | sub)
- * and key seed.  precision: SDM_PREC_FP32 or SDM_PREC_FP64 (the walk's
- * arithmetic; sums are FP64 either way).  Outputs (DEVICE float, length m):
- * R, T (fractions leaving the top / bottom face), A (absorbed, may be NULL),
- * w_lobe (RMS angle in radians between the transmitted and the incident
- * direction, weighted by transmitted energy, divided by sqrt(2); 0 when
- * nothing is transmitted).  Uses a context-owned FP64 work buffer of 32 m
- * bytes and synchronises the stream before it returns. */
+ * alpha_tint (per mm, may be NULL for 0), n_ref (the real index used inside
+ * the slab, may be NULL for n).  Bubble radii are uniform in
+ * [rmin_um, rmax_um] micrometres.  A photon meets the entry interface with
+ * the complex index (s or p label drawn per photon); inside, directions and
+ * decisions use n_ref: Fresnel / total reflection at the faces, Poisson
+ * bubbles with extinction rho_b pi <r^2> acting at the collision point with
+ * exact sphere optics (outer reflection or p internal reflections, a fresh
+ * label per bubble); its weight is exp(-(4 pi k / lambda + alpha_tint) L)
+ * over the length L travelled in glass.  Random numbers are Philox4x32-10
+ * with counter (tuple0 + i, photon, event, 0x5EB10000 | sub) and key seed.
+ * precision: SDM_PREC_FP32 or SDM_PREC_FP64 (the walk's arithmetic; sums are
+ * FP64 either way).  Outputs (DEVICE float, length m): R, T (fractions
+ * leaving the entry / far face), A (absorbed, may be NULL), w_lobe (RMS angle
+ * in radians between the transmitted and the incident direction, weighted
+ * by transmitted energy, divided by sqrt(2); 0 when nothing is transmitted).
+ * Uses a context-owned FP64 work buffer of 32 m bytes and synchronises the
+ * stream before it returns. */
 int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm,
                 const float *d_mm, const float *rho_b, const float *n, const float *k,
-                const float *alpha_tint, float rmin_um, float rmax_um, int32_t n_photons,
-                uint64_t seed, uint32_t tuple0, int32_t precision, float *R, float *T, float *A,
-                float *w_lobe, void *hip_stream);
+                const float *alpha_tint, const float *n_ref, float rmin_um, float rmax_um,
+                int32_t n_photons, uint64_t seed, uint32_t tuple0, int32_t precision, float *R,
+                float *T, float *A, float *w_lobe, void *hip_stream);
 
 /* Surrogate network of the bubbly slab: 12 -> 64 -> 64 -> 64 -> 3 with ReLU.
  * Input of a tuple (cos_i, lambda_nm, d_mm, rho_b) on pane type p:
@@ -226,7 +250,6 @@ int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *la
  *   E[n_panes][8]
  * i.e. sdm_mlp_nparams(n_panes) = 9347 + 8 n_panes floats.  Products run on
  * BF16 matrix cores with FP32 accumulation; heads, loss and Adam in FP32. */
-typedef struct sdm_mlp sdm_mlp;
 
 typedef struct {
     int32_t steps;      /* Adam steps                                          */

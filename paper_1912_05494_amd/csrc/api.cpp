@@ -54,6 +54,7 @@ struct sdm_context {
     std::vector<hipEvent_t> events;
     DevBuf slab_tmp;
     DevBuf mc_acc, flag;
+    DevBuf bubq, errtab;        // surrogate branch ratios and lobe widths; error table
 };
 
 struct sdm_mlp {
@@ -67,8 +68,9 @@ struct sdm_mlp {
 struct sdm_scene {
     sdm_context *ctx = nullptr;
     SceneDev dev{};
-    DevBuf nodes, tris, thick, mat_type, mat_thick, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
+    DevBuf nodes, tris, thick, mat_type, mat_thick, mat_bub, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
     int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
+    int32_t max_pane = -1;      // largest pane type of a bubbly material (-1: none)
 };
 
 namespace {
@@ -232,6 +234,12 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
             for (int i = 0; i < d->n_tab; ++i)
                 if (!(mm.n[i] >= 1.0f) || !(mm.k[i] >= 0.0f))
                     return fail(ctx, SDM_E_INVALID, "glass material %d needs n >= 1 and k >= 0", m);
+            if (mm.type == SDM_GLASS_BUBBLY &&
+                (!(mm.bubble_density_mm3 >= 0.0f) || !(mm.bubble_rmin_um >= 0.0f) ||
+                 !(mm.bubble_rmax_um >= mm.bubble_rmin_um) || mm.pane_id < 0 || mm.pane_id >= kMaxPanes))
+                return fail(ctx, SDM_E_INVALID,
+                            "bubbly material %d needs density >= 0, 0 <= rmin <= rmax and pane_id in [0, %d)", m,
+                            kMaxPanes);
         } else {
             return fail(ctx, SDM_E_INVALID, "material %d has an unknown type %d", m, mm.type);
         }
@@ -286,10 +294,34 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     std::vector<int32_t> mtype(d->n_mat);
     std::vector<float> mthick(d->n_mat);
     std::vector<float> tabm(4 * (size_t)d->n_mat * d->n_tab, 0.0f);
+    std::vector<double> mbub(4 * (size_t)std::max(1, d->n_mat), 0.0);
     for (int32_t m = 0; m < d->n_mat; ++m) {
         const sdm_material &mm = d->mats[m];
-        mtype[m] = mm.type == SDM_LAMBERT ? 0 : 1;
+        mtype[m] = mm.type == SDM_LAMBERT ? 0 : (mm.type == SDM_GLASS ? 1 : 2);
         mthick[m] = mm.thick_mm;
+        if (mm.type == SDM_GLASS_BUBBLY) {
+            // extinction rho_b pi <r^2> (r ~ U(rmin, rmax), mm) and the inner index:
+            // the material's n at kLambdaRef, interpolated linearly in its table
+            const double a = (double)mm.bubble_rmin_um * 1e-3, b = (double)mm.bubble_rmax_um * 1e-3;
+            mbub[4 * (size_t)m] = (double)mm.bubble_density_mm3 * M_PI * ((a * a + a * b + b * b) / 3.0);
+            const double x = kLambdaRef;
+            const float *tx = d->tab_lambda_nm, *ty = mm.n;
+            double nref;
+            if (d->n_tab == 1 || x <= tx[0]) {
+                nref = ty[0];
+            } else if (x >= tx[d->n_tab - 1]) {
+                nref = ty[d->n_tab - 1];
+            } else {
+                int i = 0;
+                while ((double)tx[i + 1] < x) ++i;
+                const double wgt = (x - tx[i]) / ((double)tx[i + 1] - tx[i]);
+                nref = (1.0 - wgt) * ty[i] + wgt * ty[i + 1];
+            }
+            mbub[4 * (size_t)m + 1] = nref;
+            mbub[4 * (size_t)m + 2] = mm.bubble_density_mm3;
+            mbub[4 * (size_t)m + 3] = mm.pane_id;
+            sc->max_pane = std::max(sc->max_pane, mm.pane_id);
+        }
         const float *src[4] = {mm.albedo, mm.n, mm.k, mm.alpha_tint};
         for (int q = 0; q < 4; ++q)
             if (src[q])
@@ -303,6 +335,7 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     chk(upload(sc->orig_to_leaf, o2l.data(), o2l.size()));
     chk(upload(sc->mat_type, mtype.data(), mtype.size()));
     chk(upload(sc->mat_thick, mthick.data(), mthick.size()));
+    chk(upload(sc->mat_bub, mbub.data(), mbub.size()));
     chk(upload(sc->tab_x, d->tab_lambda_nm, (size_t)d->n_tab));
     chk(upload(sc->tab_mat, tabm.data(), tabm.size()));
     chk(upload(sc->tab_sun, d->sun_E, (size_t)d->n_tab));
@@ -319,6 +352,7 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     sd.thick = sc->thick.as<float4>();
     sd.mat_type = sc->mat_type.as<int32_t>();
     sd.mat_thick = sc->mat_thick.as<float>();
+    sd.mat_bub = sc->mat_bub.as<double>();
     sd.n_nodes = sc->n_nodes;
     sd.nt = d->nt;
     sd.n_mat = d->n_mat;
@@ -412,6 +446,29 @@ int validate_params(sdm_context *ctx, const sdm_render_params *p)
         return fail(ctx, SDM_E_INVALID, "unknown projection");
     if (p->precision != SDM_PREC_FP32 && p->precision != SDM_PREC_FP64)
         return fail(ctx, SDM_E_INVALID, "unknown precision");
+    if (p->btdf_mode != SDM_BTDF_EXACT && p->btdf_mode != SDM_BTDF_SURROGATE && p->btdf_mode != SDM_BTDF_FALLBACK)
+        return fail(ctx, SDM_E_INVALID, "unknown btdf_mode");
+    return SDM_OK;
+}
+
+// Network and error table of the bubbly panes of a scene (none needed for
+// exact walks or scenes without bubbly panes).
+int validate_btdf(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p)
+{
+    if (sc->max_pane < 0 || p->btdf_mode == SDM_BTDF_EXACT) return SDM_OK;
+    if (!p->mlp) return fail(ctx, SDM_E_INVALID, "surrogate modes need a network (mlp)");
+    if (p->mlp->ctx != ctx) return fail(ctx, SDM_E_INVALID, "the network belongs to another context");
+    if (sc->max_pane >= p->mlp->n_panes)
+        return fail(ctx, SDM_E_INVALID, "pane type %d is beyond the network's %d embeddings", sc->max_pane,
+                    p->mlp->n_panes);
+    if (p->btdf_mode == SDM_BTDF_FALLBACK) {
+        if (!p->err_table) return fail(ctx, SDM_E_INVALID, "fallback mode needs an error table");
+        for (int a = 0; a < 3; ++a)
+            if (p->err_dims[a] < 1 || p->err_dims[a] > 1024)
+                return fail(ctx, SDM_E_INVALID, "err_dims must be in [1, 1024]");
+        if ((int64_t)p->err_dims[0] * p->err_dims[1] * p->err_dims[2] > (1 << 20))
+            return fail(ctx, SDM_E_INVALID, "error table too large");
+    }
     return SDM_OK;
 }
 
@@ -534,6 +591,18 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
     jb.Lsky = tR + 4 * (size_t)nm * nl + nl;
     jb.lam = tR + 4 * (size_t)nm * nl + 2 * nl;
     jb.beta_thr = p->beta_threshold;
+    // bubbly panes: mode, error table, network weights in the kernels' layout
+    const bool bubbly = sc->max_pane >= 0;
+    const bool surr = bubbly && p->btdf_mode != SDM_BTDF_EXACT;
+    jb.btdf_mode = p->btdf_mode;
+    jb.err_bound = p->err_bound;
+    if (bubbly && p->btdf_mode == SDM_BTDF_FALLBACK) {
+        const size_t ncell = (size_t)p->mlp->n_panes * p->err_dims[0] * p->err_dims[1] * p->err_dims[2];
+        HIPCHK(ctx, upload(ctx->errtab, p->err_table, ncell, s));
+        for (int a = 0; a < 3; ++a) jb.err_dims[a] = p->err_dims[a];
+        jb.err_table = ctx->errtab.as<float>();
+    }
+    if (surr) launch_mlp_pack(p->mlp->params.as<float>(), p->mlp->wb.p, p->mlp->bb.as<float>(), s);
     HIPCHK(ctx, upload(ctx->jobs, &jb, 1, s));
     HIPCHK(ctx, upload(ctx->bands, plan.bands.data(), plan.bands.size(), s));
     HIPCHK(ctx, upload(ctx->items, plan.items.data(), plan.items.size(), s));
@@ -582,6 +651,12 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
         w.ht = (R *)take(plane); w.hu = (R *)take(plane); w.hv = (R *)take(plane);
         w.htri = (int32_t *)take((size_t)cap * 4);
         w.gidx = (uint32_t *)take((size_t)cap * 4);
+        if (surr) {
+            HIPCHK(ctx, ctx->bubq.ensure((size_t)cap * nb * sizeof(R) + plane + 1024));
+            pb = ctx->bubq.as<char>();
+            w.bratio = (R *)take((size_t)cap * nb * sizeof(R));
+            w.bw = (R *)take(plane);
+        }
         pb = ctx->shadowq.as<char>();
         w.sx = (R *)take(plane); w.sy = (R *)take(plane); w.sz = (R *)take(plane);
         w.sskip = (int32_t *)take((size_t)cap * 4); w.spix = (uint32_t *)take((size_t)cap * 4);
@@ -622,6 +697,19 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
                 HIPCHK(ctx, tm.begin(SDM_K_SHADE_GLASS));
                 launch_shade_glass<R>(jobs_d, bands_d, w, cur, grid_s, s);
                 HIPCHK(ctx, tm.end());
+                if (surr) {
+                    HIPCHK(ctx, tm.begin(SDM_K_BUBBLY_EVAL));
+                    launch_bubbly_eval<R>(jobs_d, bands_d, w, cur, p->mlp->wb.p, p->mlp->bb.as<float>(),
+                                          p->mlp->params.as<float>(),
+                                          p->mlp->params.as<float>() + mlp_net_params(),
+                                          ctx->num_cu * (sizeof(R) == 4 ? 2 : 4), s);
+                    HIPCHK(ctx, tm.end());
+                }
+                if (bubbly) {
+                    HIPCHK(ctx, tm.begin(SDM_K_SHADE_BUBBLY));
+                    launch_shade_bubbly<R>(jobs_d, bands_d, w, cur, grid_s, s);
+                    HIPCHK(ctx, tm.end());
+                }
                 HIPCHK(ctx, tm.begin(SDM_K_SHADOW));
                 launch_shadow_trace<R>(jobs_d, bands_d, w, 0, grid_st, s);
                 HIPCHK(ctx, tm.end());
@@ -674,6 +762,7 @@ int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *
             st.closest_segments = c.closest;
             st.shadow_segments = c.shadow;
             st.forks = c.forks;
+            st.bubbly_vertices = c.bubbly;
             st.chunks = n_chunks;
             for (int q = 0; q < 2; ++q) {
                 st.nodes_visited[q] = c.nodes[q];
@@ -707,6 +796,8 @@ int sdm_render(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p
     if (!sc || !out) return fail(ctx, SDM_E_INVALID, "null scene or outputs");
     if (sc->ctx != ctx) return fail(ctx, SDM_E_INVALID, "scene belongs to another context");
     int rc = validate_params(ctx, p);
+    if (rc) return rc;
+    rc = validate_btdf(ctx, sc, p);
     if (rc) return rc;
     if (out->spectral && out->spectral_mem == SDM_MEM_DEVICE && !ptr_is_device(out->spectral))
         return fail(ctx, SDM_E_INVALID, "spectral output is not device memory");
@@ -779,9 +870,9 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const flo
 }
 
 int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm, const float *d_mm,
-                const float *rho_b, const float *n, const float *k, const float *alpha_tint, float rmin_um,
-                float rmax_um, int32_t n_photons, uint64_t seed, uint32_t tuple0, int32_t precision, float *R,
-                float *T, float *A, float *w_lobe, void *hip_stream)
+                const float *rho_b, const float *n, const float *k, const float *alpha_tint, const float *n_ref,
+                float rmin_um, float rmax_um, int32_t n_photons, uint64_t seed, uint32_t tuple0, int32_t precision,
+                float *R, float *T, float *A, float *w_lobe, void *hip_stream)
 {
     if (!ctx) return SDM_E_INVALID;
     if (m < 0 || m > 0xffffffffLL) return fail(ctx, SDM_E_INVALID, "tuple count %lld out of range", (long long)m);
@@ -799,11 +890,11 @@ int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *la
     const double a = (double)rmin_um * 1e-3, b = (double)rmax_um * 1e-3;
     const double r2 = (a * a + a * b + b * b) / 3.0;   // <r^2> in mm^2, r ~ U(a, b)
     if (precision == SDM_PREC_FP64)
-        launch_slab_mc<double>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint, r2,
-                               seed, tuple0, ctx->mc_acc.as<double>(), R, T, A, w_lobe, ctx->num_cu, s);
+        launch_slab_mc<double>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint,
+                               n_ref, r2, seed, tuple0, ctx->mc_acc.as<double>(), R, T, A, w_lobe, ctx->num_cu, s);
     else
-        launch_slab_mc<float>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint, r2,
-                              seed, tuple0, ctx->mc_acc.as<double>(), R, T, A, w_lobe, ctx->num_cu, s);
+        launch_slab_mc<float>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint,
+                              n_ref, r2, seed, tuple0, ctx->mc_acc.as<double>(), R, T, A, w_lobe, ctx->num_cu, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
     return SDM_OK;

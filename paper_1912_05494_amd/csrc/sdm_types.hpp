@@ -28,8 +28,10 @@ struct SceneDev {
     const BvhNode *nodes;
     const TriDev *tris;
     const float4 *thick;        // per leaf-order triangle: vertex thickness (mm)
-    const int32_t *mat_type;    // [n_mat]
+    const int32_t *mat_type;    // [n_mat]: 0 Lambert, 1 glass, 2 bubbly glass
     const float *mat_thick;     // [n_mat] default thickness
+    const double *mat_bub;      // [n_mat][4]: bubble extinction (per mm), inner index n_ref,
+                                // density (per mm^3), pane type; zeros for other materials
     int32_t n_nodes, nt, n_mat, has_vthick;
     float sun[3];
     float teps_f;
@@ -49,7 +51,16 @@ struct JobDev {
     uint64_t acc_off;           // offset of this job's accumulator (doubles)
     const void *rho, *n, *k, *tint, *E, *Lsky, *lam;
     double beta_thr;
+    // bubbly panes
+    int32_t btdf_mode;          // kBtdfExact, kBtdfSurrogate or kBtdfFallback
+    int32_t err_dims[3];        // error-table cells along cos, thickness, density
+    const float *err_table;     // [n_panes][err_dims] (fallback mode)
+    float err_bound;            // a cell above this uses the exact walk
+    int32_t pad1;
 };
+
+constexpr int kBtdfExact = 0, kBtdfSurrogate = 1, kBtdfFallback = 2;
+constexpr float kLambdaRef = 560.0f;   // wavelength of a bubbly pane's inner index and lobe width
 
 // Spectral band (sub-domain): wavelengths [l0, l0 + nb) of a job.
 struct BandDev {
@@ -72,8 +83,8 @@ struct Counters {
     uint32_t overflow;          // bit 0: a pool or record buffer was full;
                                 // bit 1: a shadow ray crossed more than kMaxGlass panes
     uint32_t gcount;            // glass vertices queued for the glass shading pass
-    uint32_t pad;
-    unsigned long long closest, shadow, forks;
+    uint32_t bcount;            // bubbly-glass vertices, queued from the back of gidx
+    unsigned long long closest, shadow, forks, bubbly;
     unsigned long long nodes[2], tris[2];   // traversal work [closest, shadow]
 };
 
@@ -103,7 +114,10 @@ struct Work {
     Pool<R> p[2];
     R *ht, *hu, *hv;            // closest hit per slot of the current pool
     int32_t *htri;
-    uint32_t *gidx;             // slots of the current pool at a glass vertex
+    uint32_t *gidx;             // slots of the current pool at a glass vertex (clear glass from
+                                // the front, bubbly glass from the back: gidx[cap - 1 - b])
+    R *bratio;                  // AoSoA [slot][j]: surrogate R / (R + T) at bubbly vertices
+    R *bw;                      // [slot]: surrogate lobe width at kLambdaRef
     R *sx, *sy, *sz;            // shadow records
     int32_t *sskip;
     uint32_t *spix, *saux;

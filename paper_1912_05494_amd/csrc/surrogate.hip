@@ -1,40 +1,20 @@
-// surrogate.hip -- bubbly-glass slab Monte Carlo and the BF16-MFMA surrogate
-// network (gfx950).
+// surrogate.hip -- tables of the bubbly-glass slab by Monte Carlo and the
+// BF16-MFMA surrogate network (gfx950).
 //
-// Slab walk: glass of thickness d with optical constants n + ik (eq. (1)),
-// Fresnel per polarisation at the faces, Beer-Lambert in glass, Poisson air
-// bubbles (density rho_b, radii uniform in [rmin, rmax]) acting as point
-// scatterers with exact sphere geometric optics for the direction.  Random
-// numbers: Philox4x32-10, counter (tuple, photon, event, 0x5EB10000 | sub).
+// Slab walk: see bubbly_dev.hpp (entry interface with n + ik of eq. (1),
+// walk inside at the pane's real index, Beer-Lambert over the glass length,
+// Poisson air bubbles with exact sphere optics for the direction).
 //
 // Network: 12 -> 64 -> 64 -> 64 -> 3, ReLU, heads R, T = softmax over
 // (o0, o1, 0), w = softplus(o2); loss = mean squared error over (R, T, w).
 // Operands BF16, accumulation FP32, master weights FP32 (Adam).
 #include <hip/hip_runtime.h>
 
-#include "sdm_dev.hpp"
+#include "bubbly_dev.hpp"
+#include "mlp_dev.hpp"
 #include "surrogate.hpp"
 
 namespace sdm {
-
-// ---------------------------------------------------------------------------
-// MFMA fragments (gfx950).  For a lane l, g = l / 16, c = l % 16:
-//   v_mfma_f32_16x16x32_bf16:  A[c][8g .. 8g+7], B[8g .. 8g+7][c], D[4g .. 4g+3][c]
-//   v_mfma_f32_16x16x16_bf16:  A[c][4g .. 4g+3], B[4g .. 4g+3][c], D[4g .. 4g+3][c]
-// ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short s16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma16(s16x4 a, s16x4 b, f32x4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ short bits(__bf16 x) { return __builtin_bit_cast(short, x); }
 
 __global__ void k_mfma_probe(const float *A32, const float *B32, float *C32, const float *A16, const float *B16,
                              float *C16)
@@ -61,109 +41,44 @@ __global__ void k_mfma_probe(const float *A32, const float *B32, float *C32, con
 // ---------------------------------------------------------------------------
 // Bubbly slab Monte Carlo
 // ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ R fresnel_real(R n1, R n2, R c, int pol)
-{
-    c = fmin(c, R(1));
-    const R st2 = (n1 / n2) * (n1 / n2) * (R(1) - c * c);
-    if (st2 >= R(1)) return R(1);
-    const R ct = sqrt(R(1) - st2);
-    const R r = pol == 0 ? (n1 * c - n2 * ct) / (n1 * c + n2 * ct) : (n2 * c - n1 * ct) / (n2 * c + n1 * ct);
-    return r * r;
-}
-
-template <class R>
-__device__ __forceinline__ void mc_u(uint64_t seed, uint32_t tuple, uint32_t ph, uint32_t e, uint32_t sub, R u[4])
-{
-    const uint4 x = philox10(make_uint4(tuple, ph, e, 0x5EB10000u | sub),
-                             make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
-    u[0] = u01<R>(x.x); u[1] = u01<R>(x.y); u[2] = u01<R>(x.z); u[3] = u01<R>(x.w);
-}
-
 struct McOut {
     double R, T, A, dev2;
 };
 
+// One photon of a table tuple: entry interface with the complex index at
+// lambda (eq. (1)) and the label s/p, then the walk inside.
 template <class R>
-__device__ McOut mc_photon(R cos_i, R lam, R d, R sigma, R n, R k, R tint, uint64_t seed, uint32_t tuple, uint32_t ph)
+__device__ McOut mc_photon(R cos_i, R lam, R d, R sigma, R n, R k, R tint, R n_ref, uint64_t seed, uint32_t tuple,
+                           uint32_t ph)
 {
     McOut o = {0, 0, 0, 0};
-    R u[4], v[4];
-    const R sin_i = sqrt(fmax(R(1) - cos_i * cos_i, R(0)));
-    mc_u<R>(seed, tuple, ph, 0, 0, u);
-    int pol = u[1] < R(0.5) ? 0 : 1;
+    const WalkStream ws = {seed, tuple, ph, 0, 0, false};
+    R u[4];
+    walk_draw<R>(ws, 0, 0, u);
+    const int pol = u[1] < R(0.5) ? 0 : 1;
     R Rs, Rp;
     fresnel_sp<R>(cos_i, n, k, Rs, Rp);
     if (u[0] < (pol == 0 ? Rs : Rp)) {
         o.R = 1.0;
         return o;
     }
-    const R alpha = R(12.566370614359172) * k / (lam * R(1e-6)) + tint;
-    const R st = sin_i / n;
-    V3<R> dir = {st, R(0), sqrt(fmax(R(1) - st * st, R(0)))};
-    R z = R(0), w = R(1);
-    for (uint32_t e = 1; e <= 10000u; ++e) {
-        mc_u<R>(seed, tuple, ph, e, 0, u);
-        const R sb = dir.z > R(0) ? (d - z) / dir.z : (dir.z < R(0) ? -z / dir.z : R(INFINITY));
-        const R l = sigma > R(0) ? -log1p(-u[0]) / sigma : R(INFINITY);
-        if (l >= sb) {
-            w *= exp(-alpha * sb);
-            const bool bottom = dir.z > R(0);
-            z = bottom ? d : R(0);
-            if (u[1] < fresnel_real<R>(n, R(1), fabs(dir.z), pol)) {
-                dir.z = -dir.z;
-                continue;
-            }
-            if (bottom) {
-                o.T = (double)w;
-                const R tx = n * dir.x, ty = n * dir.y;
-                const R tz = sqrt(fmax(R(1) - tx * tx - ty * ty, R(0)));
-                const R c = fmin(fmax(tx * sin_i + tz * cos_i, R(-1)), R(1));
-                const R dev = acos(c);
-                o.dev2 = (double)(w * dev * dev);
-            } else {
-                o.R = (double)w;
-            }
-            o.A = 1.0 - (double)w;
-            return o;
-        }
-        w *= exp(-alpha * l);
-        z += l * dir.z;
-        V3<R> t1, t2;
-        onb(dir, t1, t2);
-        R sphi, cphi;
-        if constexpr (sizeof(R) == 4) sincosf(R(6.283185307179586) * u[3], &sphi, &cphi);
-        else sincos(R(6.283185307179586) * u[3], &sphi, &cphi);
-        const V3<R> ep = cphi * t1 + sphi * t2;
-        uint32_t sub = 1;
-        mc_u<R>(seed, tuple, ph, e, sub, v);
-        pol = v[1] < R(0.5) ? 0 : 1;
-        const R sin_b = sqrt(u[2]), cos_b = sqrt(R(1) - u[2]);
-        if (v[0] < fresnel_real<R>(n, R(1), cos_b, pol)) {
-            const V3<R> nh = (-cos_b) * dir + sin_b * ep;
-            dir = dir - (R(2) * dot(dir, nh)) * nh;
-        } else {
-            const R sr = n * sin_b;
-            const R R2 = fresnel_real<R>(R(1), n, sqrt(fmax(R(1) - sr * sr, R(0))), pol);
-            int q = 2, p = 0;
-            while (p < 64) {
-                if (q == 4) {
-                    mc_u<R>(seed, tuple, ph, e, ++sub, v);
-                    q = 0;
-                }
-                if (v[q++] < R2) ++p;
-                else break;
-            }
-            const R ri = asin(fmin(sin_b, R(1))), rr = asin(fmin(sr, R(1)));
-            const R D = R(2) * (ri - rr) + R(p) * (R(3.141592653589793) - R(2) * rr);
-            R sD, cD;
-            if constexpr (sizeof(R) == 4) sincosf(D, &sD, &cD);
-            else sincos(D, &sD, &cD);
-            dir = cD * dir - sD * ep;
-        }
-        dir = normalize(dir);
+    const WalkOut<R> w = bubbly_walk<R>(ws, cos_i, d, sigma, n_ref, pol);
+    if (w.kind == 0) {
+        o.A = 1.0;
+        return o;
     }
-    o.A = 1.0;
+    const R alpha = R(12.566370614359172) * k / (lam * R(1e-6)) + tint;
+    const R wt = exp(-alpha * w.L);
+    if (w.kind == 2) {
+        o.T = (double)wt;
+        const R sin_i = sqrt(fmax(R(1) - cos_i * cos_i, R(0)));
+        const R c = fmin(fmax(w.a.x * sin_i + w.a.z * cos_i, R(-1)), R(1));
+        const R dev = acos(c);
+        o.dev2 = (double)(wt * dev * dev);
+    } else {
+        o.R = (double)wt;
+    }
+    o.A = 1.0 - (double)wt;
     return o;
 }
 
@@ -173,7 +88,7 @@ __device__ McOut mc_photon(R cos_i, R lam, R d, R sigma, R n, R k, R tint, uint6
 template <class R>
 __global__ void __launch_bounds__(256) k_slab_mc(uint32_t m, uint32_t nph, const float *cos_i, const float *lam,
                                                  const float *d, const float *rho, const float *n, const float *k,
-                                                 const float *tint, double r2_mm, uint64_t seed,
+                                                 const float *tint, const float *n_ref, double r2_mm, uint64_t seed,
                                                  uint32_t tuple0, double *acc)
 {
     const uint64_t total = (uint64_t)m * nph;
@@ -189,7 +104,7 @@ __global__ void __launch_bounds__(256) k_slab_mc(uint32_t m, uint32_t nph, const
             const uint32_t ph = (uint32_t)(i % nph);
             const R sigma = R((double)rho[t] * 3.14159265358979323846 * r2_mm);   // rho pi <r^2>
             o = mc_photon<R>(R(cos_i[t]), R(lam[t]), R(d[t]), sigma, R(n[t]), R(k[t]), tint ? R(tint[t]) : R(0),
-                             seed, tuple0 + t, ph);
+                             n_ref ? R(n_ref[t]) : R(n[t]), seed, tuple0 + t, ph);
         }
         // runs of lanes of the same tuple: segmented sums, one atomic per run
         const uint32_t prev = __shfl_up(t, 1);
@@ -226,105 +141,6 @@ __global__ void k_slab_mc_out(uint32_t m, uint32_t nph, const double *acc, float
 __global__ void k_zero_f64s(double *a, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// Surrogate network
-// ---------------------------------------------------------------------------
-// Kernel weight layout (BF16): W1p[64][32] (inputs 12..31 zero), W2[64][64],
-// W3[64][64], W4p[16][64] (outputs 3..15 zero); biases FP32 b1[64] b2[64]
-// b3[64] b4p[16].  Canonical FP32 parameter vector: W1[64][12] b1 W2 b2 W3 b3
-// W4[3][64] b4 E[n_panes][8].
-constexpr int kNetParams = 64 * 12 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 3 * 64 + 3;   // 9347
-constexpr int kOffW1 = 0, kOffB1 = 768, kOffW2 = 832, kOffB2 = 4928, kOffW3 = 4992, kOffB3 = 9088,
-              kOffW4 = 9152, kOffB4 = 9344, kOffE = 9347;
-constexpr int kWb = 64 * 32 + 64 * 64 + 64 * 64 + 16 * 64;   // 11264 BF16
-constexpr int kBb = 64 + 64 + 64 + 16;                       // 208 FP32
-
-struct alignas(16) NetLds {
-    __bf16 W1[64 * 32], W2[64 * 64], W3[64 * 64], W4[16 * 64];
-    float b1[64], b2[64], b3[64], b4[16];
-};
-
-struct alignas(16) WaveBuf {   // per wave, 16 samples
-    __bf16 X0[16 * 32], H1[16 * 64], H2[16 * 64], H3[16 * 64], Z0[16 * 64], Z1[16 * 64], dO[16 * 16];
-    float O[16 * 16];
-};
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ void load_net(NetLds &net, const __bf16 *wb, const float *bb)
-{
-    const __bf16 *src = wb;
-    __bf16 *dst = net.W1;
-    for (int i = threadIdx.x; i < kWb; i += blockDim.x) dst[i] = src[i];
-    float *bd = net.b1;
-    for (int i = threadIdx.x; i < kBb; i += blockDim.x) bd[i] = bb[i];
-    __syncthreads();
-}
-
-// Inputs of one sample: cos, (lambda - 580) / 200, (d - 3.5) / 1.5,
-// rho_b / 34, then the pane's 8 embedding values.
-__device__ __forceinline__ void features(float cosv, float lam, float d, float rho, const float *E, __bf16 *row)
-{
-    row[0] = (__bf16)cosv;
-    row[1] = (__bf16)((lam - 580.0f) / 200.0f);
-    row[2] = (__bf16)((d - 3.5f) / 1.5f);
-    row[3] = (__bf16)(rho / 34.0f);
-    for (int e = 0; e < 8; ++e) row[4 + e] = (__bf16)E[e];
-    for (int e = 12; e < 32; ++e) row[e] = (__bf16)0.0f;
-}
-
-// Y[16][64] = relu(X[16][K] W[64][K]^T + b), K = 32 * ksteps, stored BF16.
-__device__ __forceinline__ void dense_relu(const __bf16 *X, int ldx, const __bf16 *W, int ldw, const float *b,
-                                           int ksteps, __bf16 *Y)
-{
-    const int l = lane_id(), g = l / 16, c = l % 16;
-    for (int t = 0; t < 4; ++t) {
-        f32x4 acc = {0, 0, 0, 0};
-        for (int ks = 0; ks < ksteps; ++ks) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(X + c * ldx + 32 * ks + 8 * g);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(W + (16 * t + c) * ldw + 32 * ks + 8 * g);
-            acc = mfma32(a, bv, acc);
-        }
-        for (int r = 0; r < 4; ++r) {
-            const float z = acc[r] + b[16 * t + c];
-            Y[(4 * g + r) * 64 + 16 * t + c] = (__bf16)(z > 0.0f ? z : 0.0f);
-        }
-    }
-}
-
-__device__ __forceinline__ void forward_tile(const NetLds &net, WaveBuf &wb)
-{
-    dense_relu(wb.X0, 32, net.W1, 32, net.b1, 1, wb.H1);
-    wave_sync();
-    dense_relu(wb.H1, 64, net.W2, 64, net.b2, 2, wb.H2);
-    wave_sync();
-    dense_relu(wb.H2, 64, net.W3, 64, net.b3, 2, wb.H3);
-    wave_sync();
-    const int l = lane_id(), g = l / 16, c = l % 16;
-    f32x4 acc = {0, 0, 0, 0};
-    for (int ks = 0; ks < 2; ++ks) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(wb.H3 + c * 64 + 32 * ks + 8 * g);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(net.W4 + c * 64 + 32 * ks + 8 * g);
-        acc = mfma32(a, bv, acc);
-    }
-    for (int r = 0; r < 4; ++r) wb.O[(4 * g + r) * 16 + c] = acc[r] + net.b4[c];
-    wave_sync();
-}
-
-__device__ __forceinline__ void heads(float o0, float o1, float o2, float &R, float &T, float &w)
-{
-    const float m = fmaxf(fmaxf(o0, o1), 0.0f);
-    const float a = expf(o0 - m), b = expf(o1 - m), c = expf(-m);
-    const float s = a + b + c;
-    R = a / s;
-    T = b / s;
-    w = o2 > 30.0f ? o2 : log1pf(expf(o2));
 }
 
 // dW[out][in] += sum_s dZ[s][out] H[s][in] over the 16 samples (k = 16),
@@ -579,22 +395,23 @@ void launch_mfma_probe(const float *A32, const float *B32, float *C32, const flo
 
 template <class R>
 void launch_slab_mc(uint32_t m, uint32_t nph, const float *cos_i, const float *lam, const float *d, const float *rho,
-                    const float *n, const float *k, const float *tint, double r2_mm, uint64_t seed,
-                    uint32_t tuple0, double *acc, float *Rr, float *Tt, float *A, float *W, int num_cu, hipStream_t s)
+                    const float *n, const float *k, const float *tint, const float *n_ref, double r2_mm,
+                    uint64_t seed, uint32_t tuple0, double *acc, float *Rr, float *Tt, float *A, float *W, int num_cu,
+                    hipStream_t s)
 {
     const size_t n4 = 4 * (size_t)m;
     hipLaunchKernelGGL(k_zero_f64s, dim3((unsigned)std::min<size_t>(4096, (n4 + 255) / 256)), dim3(256), 0, s, acc, n4);
     const uint64_t total = (uint64_t)m * nph;
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16ull * num_cu));
-    hipLaunchKernelGGL(k_slab_mc<R>, dim3(grid), dim3(256), 0, s, m, nph, cos_i, lam, d, rho, n, k, tint,
+    hipLaunchKernelGGL(k_slab_mc<R>, dim3(grid), dim3(256), 0, s, m, nph, cos_i, lam, d, rho, n, k, tint, n_ref,
                        r2_mm, seed, tuple0, acc);
     hipLaunchKernelGGL(k_slab_mc_out, dim3((unsigned)std::max<uint32_t>(1, std::min<uint32_t>(4096, (m + 255) / 256))),
                        dim3(256), 0, s, m, nph, acc, Rr, Tt, A, W);
 }
 #define SDM_INST_MC(R)                                                                                              \
     template void launch_slab_mc<R>(uint32_t, uint32_t, const float *, const float *, const float *, const float *, \
-                                    const float *, const float *, const float *, double, uint64_t, uint32_t,        \
-                                    double *, float *, float *, float *, float *, int, hipStream_t);
+                                    const float *, const float *, const float *, const float *, double, uint64_t,  \
+                                    uint32_t, double *, float *, float *, float *, float *, int, hipStream_t);
 SDM_INST_MC(float)
 SDM_INST_MC(double)
 #undef SDM_INST_MC

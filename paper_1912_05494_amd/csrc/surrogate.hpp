@@ -13,8 +13,9 @@ void launch_mfma_probe(const float *A32, const float *B32, float *C32, const flo
 
 template <class R>
 void launch_slab_mc(uint32_t m, uint32_t nph, const float *cos_i, const float *lam, const float *d, const float *rho,
-                    const float *n, const float *k, const float *tint, double r2_mm, uint64_t seed,
-                    uint32_t tuple0, double *acc, float *Rr, float *Tt, float *A, float *W, int num_cu, hipStream_t s);
+                    const float *n, const float *k, const float *tint, const float *n_ref, double r2_mm,
+                    uint64_t seed, uint32_t tuple0, double *acc, float *Rr, float *Tt, float *A, float *W, int num_cu,
+                    hipStream_t s);
 
 void launch_mlp_pack(const float *params, void *wb, float *bb, hipStream_t s);
 void launch_mlp_grad(uint32_t m, int n_panes, const float *tup, const int32_t *pane, const float *target,

@@ -19,6 +19,8 @@
 
 #include <climits>
 
+#include "bubbly_dev.hpp"
+#include "mlp_dev.hpp"
 #include "sdm_dev.hpp"
 #include "wavefront.hpp"
 
@@ -396,12 +398,13 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
 {
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
-    const uint32_t count = w.cnt->count[cur];
+    const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.cnt->count[cur ^ 1] = 0;
         w.cnt->scount = 0;
         w.cnt->sfetch = 0;
         w.cnt->gcount = 0;
+        w.cnt->bcount = 0;
         w.cnt->closest += count;
     }
     const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
@@ -459,7 +462,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
 {
-    const uint32_t count = w.cnt->count[cur];
+    const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->tfetch = 0;
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
     const int nbm = w.nbmax;
@@ -472,7 +475,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
         const bool active = i < count;
         uint32_t aux = 0, pix = 0, smp = 0;
         int32_t tri = -1;
-        int kind = -1;            // 0 miss, 1 Lambert, 2 glass (queued)
+        int kind = -1;            // 0 miss, 1 Lambert, 2 glass, 3 bubbly glass (both queued)
         bool want_shadow = false, keep = false;
         V3<R> x = {R(0), R(0), R(0)}, dnew = x;
         R cs = R(0);
@@ -508,13 +511,16 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
                         dnew = cosine_dir(ns, u01<R>(rr.y), u01<R>(rr.z));
                     }
                 } else if (!last) {
-                    kind = 2;   // no light sum at glass; a glass vertex at the depth limit ends the path
+                    // no light sum at glass; a glass vertex at the depth limit ends the path
+                    kind = gld(jb->sc.mat_type + mat) == 2 ? 3 : 2;
                 }
             }
         }
         // glass queue, shadow records and pool slots: one atomic per wave and buffer
         const uint32_t gslot = wave_reserve(kind == 2, &w.cnt->gcount);
         if (kind == 2) w.gidx[gslot] = i;
+        const uint32_t bslot = wave_reserve(kind == 3, &w.cnt->bcount);
+        if (kind == 3) w.gidx[w.cap - 1u - bslot] = i;
         uint32_t sslot = wave_reserve(want_shadow, &w.cnt->scount);
         if (want_shadow && sslot >= w.cap) { w.cnt->overflow |= 1u; want_shadow = false; }
         uint32_t om = wave_reserve(keep, &w.cnt->count[cur ^ 1]);
@@ -591,6 +597,64 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
     }
 }
 
+// Outputs of a split vertex: the kept path (direction dnew, the wavelengths
+// whose reflect bit is clear, or all of them when there is no fork) and, when
+// both branches occur, a forked path (direction drefl, the wavelengths whose
+// bit is set).  The new weights sit in Pi.beta at slot i.  One atomic per wave.
+template <class R>
+__device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, const Pool<R> &Po, int cur, bool keep,
+                                           bool fork, uint32_t i, V3<R> x, V3<R> dnew, V3<R> drefl, uint32_t pix,
+                                           uint32_t smp, uint32_t aux, int32_t tri, int nb, uint32_t m0, uint32_t m1,
+                                           uint32_t m2, uint32_t m3)
+{
+    const int nbm = w.nbmax;
+    const uint32_t lane = lane_id();
+    const uint64_t mk = __ballot(keep), mf = __ballot(fork);
+    const uint32_t nk = (uint32_t)__popcll(mk), nf = (uint32_t)__popcll(mf);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint32_t obase = 0;
+    if (nk + nf) {
+        const int leader = __ffsll((unsigned long long)(mk | mf)) - 1;
+        if ((int)lane == leader) {
+            obase = atomicAdd(&w.cnt->count[cur ^ 1], nk + nf);
+            if (nf) atomicAdd(&w.cnt->forks, (unsigned long long)nf);
+        }
+        obase = __shfl(obase, leader);
+    }
+    const uint32_t om = obase + (uint32_t)__popcll(mk & lt);
+    const uint32_t of = obase + nk + (uint32_t)__popcll(mf & lt);
+    if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
+    if (fork && of >= w.cap) { w.cnt->overflow |= 1u; fork = false; }
+    if (keep) {
+        Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
+        Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
+        Po.pix[om] = pix; Po.smp[om] = smp; Po.aux[om] = aux + 1u; Po.skip[om] = tri;
+    }
+    if (fork) {
+        Po.ox[of] = x.x; Po.oy[of] = x.y; Po.oz[of] = x.z;
+        Po.dx[of] = drefl.x; Po.dy[of] = drefl.y; Po.dz[of] = drefl.z;
+        Po.pix[of] = pix; Po.smp[of] = smp; Po.aux[of] = aux + 1u; Po.skip[of] = tri;
+    }
+    if (keep) {
+        const R *__restrict__ bin = Pi.beta;
+        R *__restrict__ bout = Po.beta;
+        for (int j = 0; j < nb; j += 8) {
+            R bn[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) bn[q] = j + q < nb ? bin[aosoa(i, j + q, nbm)] : R(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int jj = j + q;
+                if (jj >= nb) break;
+                const uint32_t word = jj < 32 ? m0 : jj < 64 ? m1 : jj < 96 ? m2 : m3;
+                const bool refl = (word >> (jj & 31)) & 1u;
+                bout[aosoa(om, jj, nbm)] = (fork && refl) ? R(0) : bn[q];
+                if (fork) bout[aosoa(of, jj, nbm)] = refl ? bn[q] : R(0);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Glass vertices (thin slab, Sec. 6 thickness map): per wavelength the path
 // reflects with probability R/(R+T) and otherwise passes straight through,
@@ -600,7 +664,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
 {
-    const uint32_t count = w.cnt->gcount;
+    const uint32_t count = min(w.cnt->gcount, w.cap);
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
@@ -665,50 +729,292 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, cons
             fork = anyR && anyT;
             if (anyR && !anyT) dnew = drefl;
         }
-        const uint64_t mk = __ballot(keep), mf = __ballot(fork);
-        const uint32_t nk = (uint32_t)__popcll(mk), nf = (uint32_t)__popcll(mf);
-        const uint64_t lt = (1ull << lane) - 1ull;
-        uint32_t obase = 0;
-        if (nk + nf) {
-            const int leader = __ffsll((unsigned long long)(mk | mf)) - 1;
-            if ((int)lane == leader) {
-                obase = atomicAdd(&w.cnt->count[cur ^ 1], nk + nf);
-                if (nf) atomicAdd(&w.cnt->forks, (unsigned long long)nf);
-            }
-            obase = __shfl(obase, leader);
-        }
-        const uint32_t om = obase + (uint32_t)__popcll(mk & lt);
-        const uint32_t of = obase + nk + (uint32_t)__popcll(mf & lt);
-        if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
-        if (fork && of >= w.cap) { w.cnt->overflow |= 1u; fork = false; }
-        if (keep) {
-            Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
-            Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
-            Po.pix[om] = pix; Po.smp[om] = smp; Po.aux[om] = aux + 1u; Po.skip[om] = tri;
-        }
-        if (fork) {
-            Po.ox[of] = x.x; Po.oy[of] = x.y; Po.oz[of] = x.z;
-            Po.dx[of] = drefl.x; Po.dy[of] = drefl.y; Po.dz[of] = drefl.z;
-            Po.pix[of] = pix; Po.smp[of] = smp; Po.aux[of] = aux + 1u; Po.skip[of] = tri;
-        }
-        if (keep) {
-            const R *__restrict__ bin = Pi.beta;
-            R *__restrict__ bout = Po.beta;
-            for (int j = 0; j < bd.nb; j += 8) {
-                R bn[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) bn[q] = j + q < bd.nb ? bin[aosoa(i, j + q, nbm)] : R(0);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int jj = j + q;
-                    if (jj >= bd.nb) break;
-                    const uint32_t word = jj < 32 ? m0 : jj < 64 ? m1 : jj < 96 ? m2 : m3;
-                    const bool refl = (word >> (jj & 31)) & 1u;
-                    bout[aosoa(om, jj, nbm)] = (fork && refl) ? R(0) : bn[q];
-                    if (fork) bout[aosoa(of, jj, nbm)] = refl ? bn[q] : R(0);
+        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bubbly panes (air micro-particles in the glass, Sec. 1; volume scattering,
+// Sec. 6).  A vertex is evaluated by the exact walk or by the surrogate
+// network; the fallback mode takes the walk where the error table flags the
+// vertex's cell.
+// ---------------------------------------------------------------------------
+struct BubblyVertex {
+    uint32_t i;                 // pool slot
+    const JobDev *jb;
+    BandDev bd;
+    int32_t tri, mat, pane;
+    int mode;                   // kBtdfExact or kBtdfSurrogate after the table check
+    double sigma, n_ref, rho;
+};
+
+template <class R>
+__device__ __forceinline__ BubblyVertex bubbly_vertex(const JobDev *jobs, const BandDev *bands, const Work<R> &w,
+                                                      const Pool<R> &Pi, uint32_t e, V3<R> &d, V3<R> &ng, R &cos_i,
+                                                      R &thick)
+{
+    BubblyVertex v;
+    v.i = w.gidx[w.cap - 1u - e];
+    const uint32_t aux = Pi.aux[v.i];
+    v.jb = &jobs[aux >> kAuxJobShift];
+    v.bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+    v.tri = w.htri[v.i];
+    const TriDev tr = load_tri(v.jb->sc.tris, v.tri);
+    v.mat = __float_as_int(tr.b.w);
+    d = {Pi.dx[v.i], Pi.dy[v.i], Pi.dz[v.i]};
+    ng = tri_normal<R>(tr);
+    cos_i = fabs(dot(d, ng));
+    thick = pane_thickness<R>(v.jb->sc, v.tri, w.hu[v.i], w.hv[v.i]);
+    const double *b = v.jb->sc.mat_bub + 4 * (size_t)v.mat;
+    v.sigma = gld(b);
+    v.n_ref = gld(b + 1);
+    v.rho = gld(b + 2);
+    v.pane = (int)gld(b + 3);
+    v.mode = v.jb->btdf_mode;
+    if (v.mode == kBtdfFallback) {
+        const int c = err_cell<R>(v.jb->err_dims, v.pane, cos_i, thick, R(v.rho));
+        v.mode = gld(v.jb->err_table + c) > v.jb->err_bound ? kBtdfExact : kBtdfSurrogate;
+    }
+    return v;
+}
+
+// Surrogate at the bubbly vertices: for each vertex the network's (R, T) at
+// every wavelength of its band and its lobe width w at kLambdaRef.  The
+// weights are multiplied by R + T in place; R / (R + T) and w are kept for
+// k_shade_bubbly.  FP32 build: 16-tuple tiles on the matrix cores (BF16
+// operands, FP32 sums), tuples enumerated (vertex, j) with j = nb_max for
+// the reference wavelength.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *jobs, const BandDev *bands, Work<R> w,
+                                                            int cur, const __bf16 *wb, const float *bb,
+                                                            const float *E)
+{
+    __shared__ NetLds net;
+    __shared__ WaveBuf wbuf[kBlock / 64];
+    load_net(net, wb, bb);
+    const Pool<R> Pi = w.p[cur];
+    WaveBuf &wv = wbuf[threadIdx.x >> 6];
+    const uint32_t l = lane_id();
+    const uint32_t stride = (uint32_t)w.nbmax + 1u;
+    const uint64_t ntup = (uint64_t)min(w.cnt->bcount, w.cap) * stride;
+    const uint64_t ntile = (ntup + 15) / 16;
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t tile = wave; tile < ntile; tile += nw) {
+        bool valid = false;
+        uint32_t slot = 0, j = 0;
+        if (l < 16) {
+            const uint64_t tu = tile * 16 + l;
+            if (tu < ntup) {
+                const uint32_t e = (uint32_t)(tu / stride);
+                j = (uint32_t)(tu % stride);
+                V3<R> d, ng;
+                R cos_i, thick;
+                const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, e, d, ng, cos_i, thick);
+                slot = v.i;
+                valid = v.mode == kBtdfSurrogate && (j < (uint32_t)v.bd.nb || j == stride - 1u);
+                if (valid) {
+                    const float lam = j == stride - 1u ? kLambdaRef : (float)gld((const R *)v.jb->lam + v.bd.l0 + j);
+                    features((float)cos_i, lam, (float)thick, (float)v.rho, E + 8 * v.pane, wv.X0 + l * 32);
                 }
             }
+            if (!valid)
+                for (int q = 0; q < 32; ++q) wv.X0[l * 32 + q] = (__bf16)0.0f;
         }
+        wave_sync();
+        forward_tile(net, wv);
+        if (valid) {
+            float Rr, Tt, wl;
+            heads(wv.O[l * 16], wv.O[l * 16 + 1], wv.O[l * 16 + 2], Rr, Tt, wl);
+            if (j == stride - 1u) {
+                w.bw[slot] = R(wl);
+            } else {
+                const size_t q = aosoa(slot, (int)j, w.nbmax);
+                Pi.beta[q] = Pi.beta[q] * R(Rr + Tt);
+                w.bratio[q] = R(Rr / (Rr + Tt));
+            }
+        }
+        wave_sync();
+    }
+}
+
+// FP64 build: the same network evaluated in double, one tuple per thread
+// (the arithmetic of the FP64 reference network).
+__device__ double net_fp64(const float *p, const float *E, int pane, double cos_i, double lam, double d, double rho,
+                           double out[3])
+{
+    double x[12], h1[64], h2[64];
+    x[0] = cos_i;
+    x[1] = (lam - 580.0) / 200.0;
+    x[2] = (d - 3.5) / 1.5;
+    x[3] = rho / 34.0;
+    for (int e = 0; e < 8; ++e) x[4 + e] = (double)E[8 * pane + e];
+    const float *W1 = p, *b1 = p + 768, *W2 = p + 832, *b2 = p + 4928, *W3 = p + 4992, *b3 = p + 9088,
+                *W4 = p + 9152, *b4 = p + 9344;
+    for (int o = 0; o < 64; ++o) {
+        double s = b1[o];
+        for (int i = 0; i < 12; ++i) s += (double)W1[o * 12 + i] * x[i];
+        h1[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < 64; ++o) {
+        double s = b2[o];
+        for (int i = 0; i < 64; ++i) s += (double)W2[o * 64 + i] * h1[i];
+        h2[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < 64; ++o) {
+        double s = b3[o];
+        for (int i = 0; i < 64; ++i) s += (double)W3[o * 64 + i] * h2[i];
+        h1[o] = s > 0.0 ? s : 0.0;   // h3
+    }
+    double o3[3];
+    for (int o = 0; o < 3; ++o) {
+        double s = b4[o];
+        for (int i = 0; i < 64; ++i) s += (double)W4[o * 64 + i] * h1[i];
+        o3[o] = s;
+    }
+    const double m = fmax(fmax(o3[0], o3[1]), 0.0);
+    const double a = exp(o3[0] - m), b = exp(o3[1] - m), c = exp(-m);
+    out[0] = a / (a + b + c);
+    out[1] = b / (a + b + c);
+    out[2] = o3[2] > 30.0 ? o3[2] : log1p(exp(o3[2]));
+    return out[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *jobs, const BandDev *bands, Work<double> w,
+                                                            int cur, const float *params, const float *E)
+{
+    const Pool<double> Pi = w.p[cur];
+    const uint32_t stride = (uint32_t)w.nbmax + 1u;
+    const uint64_t ntup = (uint64_t)min(w.cnt->bcount, w.cap) * stride;
+    for (uint64_t tu = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; tu < ntup;
+         tu += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = (uint32_t)(tu / stride), j = (uint32_t)(tu % stride);
+        V3<double> d, ng;
+        double cos_i, thick;
+        const BubblyVertex v = bubbly_vertex<double>(jobs, bands, w, Pi, e, d, ng, cos_i, thick);
+        if (v.mode != kBtdfSurrogate || (j >= (uint32_t)v.bd.nb && j != stride - 1u)) continue;
+        const double lam = j == stride - 1u ? (double)kLambdaRef : gld((const double *)v.jb->lam + v.bd.l0 + j);
+        double y[3];
+        net_fp64(params, E, v.pane, cos_i, lam, thick, v.rho, y);
+        if (j == stride - 1u) {
+            w.bw[v.i] = y[2];
+        } else {
+            const size_t q = aosoa(v.i, (int)j, w.nbmax);
+            Pi.beta[q] = Pi.beta[q] * (y[0] + y[1]);
+            w.bratio[q] = y[0] / (y[0] + y[1]);
+        }
+    }
+}
+
+// Bubbly vertex shading.  Exact walk: the entry interface decides per
+// wavelength (complex index, shared draw); the wavelengths that enter share
+// one walk inside (the pane's index at kLambdaRef) and are weighted by
+// exp(-alpha L).  Surrogate: reflect where u0 < R / (R + T), else the
+// transmitted lobe of width w.  Either way a band splits into at most a
+// reflected and a continuing packet.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
+{
+    const uint32_t count = min(w.cnt->bcount, w.cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->bubbly += count;
+    const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
+    const int nbm = w.nbmax;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
+        const bool active = base + lane < count;
+        uint32_t i = 0, aux = 0, pix = 0, smp = 0;
+        int32_t tri = -1;
+        V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x;
+        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+        bool keep = false, fork = false;
+        BandDev bd = {0, 0, 0, 0};
+        if (active) {
+            V3<R> d, ng;
+            R cos_i, thick;
+            const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, base + lane, d, ng, cos_i, thick);
+            i = v.i;
+            bd = v.bd;
+            tri = v.tri;
+            aux = Pi.aux[i];
+            pix = Pi.pix[i];
+            smp = Pi.smp[i];
+            const int depth = (int)(aux & 0xffu);
+            const JobDev *jb = v.jb;
+            x = V3<R>{Pi.ox[i], Pi.oy[i], Pi.oz[i]} + w.ht[i] * d;
+            dnew = d;
+            drefl = d - (R(2) * dot(d, ng)) * ng;
+            const int nl = jb->nl;
+            const R *nn = (const R *)jb->n + (size_t)v.mat * nl + bd.l0;
+            const R *kk = (const R *)jb->k + (size_t)v.mat * nl + bd.l0;
+            const R *tt = (const R *)jb->tint + (size_t)v.mat * nl + bd.l0;
+            const R *lam = (const R *)jb->lam + bd.l0;
+            const R thr = R(jb->beta_thr);
+            bool anyR = false, anyT = false;
+            auto set_bit = [&](int j) {
+                const uint32_t bit = 1u << (j & 31);
+                if (j < 32) m0 |= bit; else if (j < 64) m1 |= bit; else if (j < 96) m2 |= bit; else m3 |= bit;
+            };
+            if (v.mode == kBtdfExact) {
+                const WalkStream ws = {jb->seed, pix, smp, jb->job_word, (uint32_t)depth, true};
+                R ue[4];
+                walk_draw<R>(ws, 0, 0, ue);
+                const int pol = ue[1] < R(0.5) ? 0 : 1;
+                bool enter = false;
+                for (int j = 0; j < bd.nb; ++j) {
+                    if (Pi.beta[aosoa(i, j, nbm)] == R(0)) continue;
+                    R Rs, Rp;
+                    fresnel_sp<R>(cos_i, gld(nn + j), gld(kk + j), Rs, Rp);
+                    if (ue[0] < (pol == 0 ? Rs : Rp)) set_bit(j);
+                    else enter = true;
+                }
+                WalkOut<R> wo;
+                wo.kind = 0;
+                wo.L = R(0);
+                if (enter) {
+                    wo = bubbly_walk<R>(ws, cos_i, thick, R(v.sigma), R(v.n_ref), pol);
+                    if (wo.kind != 0) dnew = slab_to_world<R>(d, ng, wo.a);
+                }
+                const uint32_t r0 = m0, r1 = m1, r2 = m2, r3 = m3;
+                m0 = m1 = m2 = m3 = 0;
+                for (int j = 0; j < bd.nb; ++j) {
+                    const size_t q = aosoa(i, j, nbm);
+                    const R b = Pi.beta[q];
+                    if (b == R(0)) continue;
+                    const uint32_t word = j < 32 ? r0 : j < 64 ? r1 : j < 96 ? r2 : r3;
+                    const bool refl = (word >> (j & 31)) & 1u;
+                    R bn = R(0);
+                    if (refl) {
+                        bn = b;
+                    } else if (wo.kind != 0) {
+                        const R alpha = R(12.566370614359172) * gld(kk + j) / (gld(lam + j) * R(1e-6)) + gld(tt + j);
+                        bn = b * exp(-alpha * wo.L);
+                    }
+                    if (bn < thr) bn = R(0);
+                    Pi.beta[q] = bn;
+                    if (bn == R(0)) continue;
+                    if (refl) { anyR = true; set_bit(j); }
+                    else anyT = true;
+                }
+            } else {
+                const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp, depth, 0);
+                const R u0 = u01<R>(rr.x);
+                dnew = lobe_dir<R>(d, w.bw[i], u01<R>(rr.y), u01<R>(rr.z));
+                for (int j = 0; j < bd.nb; ++j) {
+                    const size_t q = aosoa(i, j, nbm);
+                    R bn = Pi.beta[q];
+                    if (bn == R(0)) continue;
+                    if (bn < thr) { Pi.beta[q] = R(0); continue; }
+                    if (u0 < w.bratio[q]) { anyR = true; set_bit(j); }
+                    else anyT = true;
+                }
+            }
+            keep = anyR || anyT;
+            fork = anyR && anyT;
+            if (anyR && !anyT) dnew = drefl;
+        }
+        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3);
     }
 }
 
@@ -724,7 +1030,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
 {
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
-    const uint32_t count = w.cnt->scount;
+    const uint32_t count = min(w.cnt->scount, w.cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->shadow += count;
     const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
     Stack st = make_stack(s_stack, w.gstack);
@@ -793,7 +1099,7 @@ template <class R>
 __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, const BandDev *bands, Work<R> w)
 {
     __shared__ uint32_t s_buf[kBlock / 64][128];
-    const uint32_t count = w.cnt->scount;
+    const uint32_t count = min(w.cnt->scount, w.cap);
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -821,7 +1127,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, con
         uint64_t key0 = ~0ull;
         const JobDev *jb = nullptr;
         BandDev bd = {0, 0, 0, 0};
-        R gc[kMaxGlass], gd[kMaxGlass];
+        R gc[kMaxGlass], gd[kMaxGlass], gs[kMaxGlass];
         int gm[kMaxGlass];
         if (act) {
             ng = w.socc[rec];
@@ -840,8 +1146,11 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, con
                     gd[g] = pane_thickness<R>(jb->sc, leaf, w.sg_u[(size_t)rec * kMaxGlass + g],
                                               w.sg_v[(size_t)rec * kMaxGlass + g]);
                     gm[g] = __float_as_int(tr.b.w);
+                    // toward the delta sun a bubbly pane passes its unscattered light:
+                    // the bubbles' extinction adds to the absorption
+                    gs[g] = R(gld(jb->sc.mat_bub + 4 * gm[g]));
                 } else {
-                    gc[g] = gd[g] = R(0);
+                    gc[g] = gd[g] = gs[g] = R(0);
                     gm[g] = 0;
                 }
             }
@@ -862,7 +1171,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, con
                         R Rr, Tt;
                         slab_RT<R>(gc[g], gld((const R *)jb->lam + bd.l0 + j + q), gd[g],
                                    gld((const R *)jb->n + mo), gld((const R *)jb->k + mo),
-                                   gld((const R *)jb->tint + mo), Rr, Tt);
+                                   gld((const R *)jb->tint + mo) + gs[g], Rr, Tt);
                         T *= Tt;
                     }
                     v[q] = (double)T;
@@ -921,8 +1230,8 @@ __global__ void k_zero_counters(Counters *c)
         c->scount = 0;
         c->tfetch = c->sfetch = 0;
         c->overflow = 0;
-        c->gcount = 0;
-        c->closest = c->shadow = c->forks = 0;
+        c->gcount = c->bcount = 0;
+        c->closest = c->shadow = c->forks = c->bubbly = 0;
         c->nodes[0] = c->nodes[1] = c->tris[0] = c->tris[1] = 0;
     }
 }
@@ -1053,7 +1362,9 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
                                                     float Rr, Tt;
                                                     slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm,
                                                                    pane_thickness<float>(sc, leaf, u, v), n_at[mt],
-                                                                   k_at[mt], t_at[mt], Rr, Tt);
+                                                                   k_at[mt],
+                                                                   t_at[mt] + (float)gld(sc.mat_bub + 4 * mt),
+                                                                   Rr, Tt);
                                                     prod *= Tt;
                                                 },
                                                 nn, nt);
@@ -1088,6 +1399,21 @@ template <class R>
 void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_shade_glass<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+}
+template <class R>
+void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const void *wb,
+                        const float *bb, const float *params, const float *E, int grid, hipStream_t s)
+{
+    if constexpr (sizeof(R) == 4)
+        hipLaunchKernelGGL(k_bubbly_eval_mfma<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur,
+                           (const __bf16 *)wb, bb, E);
+    else
+        hipLaunchKernelGGL(k_bubbly_eval_fp64, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur, params, E);
+}
+template <class R>
+void launch_shade_bubbly(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shade_bubbly<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
 }
 template <class R>
 void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid,
@@ -1175,6 +1501,9 @@ int occupancy_shade()
     template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, int, hipStream_t);                    \
     template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);        \
     template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);  \
+    template void launch_bubbly_eval<R>(const JobDev *, const BandDev *, const Work<R> &, int, const void *,       \
+                                        const float *, const float *, const float *, int, hipStream_t);            \
+    template void launch_shade_bubbly<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
     template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
     template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, int, hipStream_t);      \
     template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,              \

@@ -18,6 +18,11 @@ void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, in
 template <class R>
 void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
 template <class R>
+void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const void *wb,
+                        const float *bb, const float *params, const float *E, int grid, hipStream_t s);
+template <class R>
+void launch_shade_bubbly(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
+template <class R>
 void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid,
                          hipStream_t s);
 template <class R>

@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(HERE, "libsdm.so")
 SDM_OK = 0
 SDM_MEM_HOST, SDM_MEM_DEVICE = 0, 1
 SDM_PREC_FP32, SDM_PREC_FP64 = 0, 1
-KERNELS = ("generate", "trace", "shade", "shadow", "finalize", "shadow_accum", "shade_glass")
+KERNELS = ("generate", "trace", "shade", "shadow", "finalize", "shadow_accum", "shade_glass", "bubbly_eval",
+           "shade_bubbly")
+BTDF_MODES = {"exact": 0, "surrogate": 1, "fallback": 2}
 
 _FP = C.POINTER(C.c_float)
 
@@ -49,21 +51,25 @@ class RenderParams(C.Structure):
                 ("seed", C.c_uint64), ("job_id", C.c_uint32), ("n_bands", C.c_int32),
                 ("band_edges", C.POINTER(C.c_int32)), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("beta_threshold", C.c_float), ("precision", C.c_int32),
-                ("chunk_paths", C.c_int64), ("timing", C.c_int32)]
+                ("chunk_paths", C.c_int64), ("timing", C.c_int32), ("btdf_mode", C.c_int32),
+                ("err_dims", C.c_int32 * 3), ("mlp", C.c_void_p), ("err_table", _FP),
+                ("err_bound", C.c_float)]
 
 
 class Stats(C.Structure):
     _fields_ = [("spectral_samples", C.c_uint64), ("paths", C.c_uint64),
                 ("closest_segments", C.c_uint64), ("shadow_segments", C.c_uint64),
                 ("forks", C.c_uint64), ("chunks", C.c_uint64), ("nodes_visited", C.c_uint64 * 2),
-                ("tris_tested", C.c_uint64 * 2), ("ms_render", C.c_double),
-                ("kernel_ms", C.c_double * 7), ("kernel_launches", C.c_uint64 * 7)]
+                ("tris_tested", C.c_uint64 * 2), ("bubbly_vertices", C.c_uint64),
+                ("ms_render", C.c_double), ("kernel_ms", C.c_double * 9),
+                ("kernel_launches", C.c_uint64 * 9)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_[:6]}
         d["ms_render"] = self.ms_render
         d["nodes_visited"] = {"closest": int(self.nodes_visited[0]), "shadow": int(self.nodes_visited[1])}
         d["tris_tested"] = {"closest": int(self.tris_tested[0]), "shadow": int(self.tris_tested[1])}
+        d["bubbly_vertices"] = int(self.bubbly_vertices)
         d["kernel_ms"] = {k: self.kernel_ms[i] for i, k in enumerate(KERNELS)}
         d["kernel_launches"] = {k: int(self.kernel_launches[i]) for i, k in enumerate(KERNELS)}
         return d
@@ -105,7 +111,7 @@ def lib():
         L.sdm_slab_eval.argtypes = [vp, C.c_int64] + [vp] * 9
         L.sdm_debug_intersect.argtypes = [vp, vp, C.c_int64] + [vp] * 7
         L.sdm_debug_shadow.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_float, vp, vp]
-        L.sdm_slab_mc.argtypes = ([vp, C.c_int64] + [vp] * 7 + [C.c_float, C.c_float, C.c_int32, C.c_uint64,
+        L.sdm_slab_mc.argtypes = ([vp, C.c_int64] + [vp] * 8 + [C.c_float, C.c_float, C.c_int32, C.c_uint64,
                                                                  C.c_uint32, C.c_int32] + [vp] * 5)
         L.sdm_mlp_nparams.restype = C.c_int64
         L.sdm_mlp_nparams.argtypes = [C.c_int32]
@@ -217,7 +223,10 @@ class Scene:
 
 
 def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision="fp32",
-                chunk_paths=0, timing=False):
+                chunk_paths=0, timing=False, btdf=None):
+    """btdf: None (exact walks on bubbly panes) or a dict with mode ("exact",
+    "surrogate", "fallback"), mlp (an MLP) and, for "fallback", err_table
+    (array (n_panes, n_cos, n_d, n_rho)) and bound."""
     cam = settings.camera
     lam = _f32(settings.lambda_nm)
     cmf = _f32(np.asarray(settings.cmf).reshape(-1))
@@ -237,11 +246,23 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
         be.ctypes.data_as(C.POINTER(C.c_int32)) if be is not None else None,
         int(tile[0]), int(tile[1]), float(settings.beta_threshold),
         SDM_PREC_FP64 if precision == "fp64" else SDM_PREC_FP32, int(chunk_paths), int(timing))
+    if btdf is not None:
+        p.btdf_mode = BTDF_MODES[btdf.get("mode", "exact")]
+        if btdf.get("mlp") is not None:
+            p.mlp = btdf["mlp"].ptr
+            keep.append(btdf["mlp"])
+        if btdf.get("err_table") is not None:
+            tab = _f32(btdf["err_table"])
+            keep.append(tab)
+            p.err_table = tab.ctypes.data_as(_FP)
+            p.err_dims = (C.c_int32 * 3)(*tab.shape[1:4])
+            p.err_bound = float(btdf.get("bound", 1e-3))
     return p, keep
 
 
 def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, tile=(0, 0),
-           precision="fp32", chunk_paths=0, timing=False, stream=None, spectral=True, xyz=True):
+           precision="fp32", chunk_paths=0, timing=False, stream=None, spectral=True, xyz=True,
+           btdf=None):
     """Render into new device tensors: (spectral (H, W, nl) float32, xyz (H, W, 3) float64,
     stats dict)."""
     import torch
@@ -250,7 +271,7 @@ def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, 
     dev = torch.device("cuda", ctx.device)
     spec_t = torch.empty((cam.H, cam.W, nl), dtype=torch.float32, device=dev) if spectral else None
     xyz_t = torch.empty((cam.H, cam.W, 3), dtype=torch.float64, device=dev) if xyz else None
-    p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing)
+    p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing, btdf)
     st = Stats()
     out = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, C.pointer(st))
     ctx.check(lib().sdm_render(ctx.ptr, scene.ptr, C.byref(p), C.byref(out), _stream(stream)),
@@ -303,14 +324,15 @@ PRECISION = {"fp32": 0, "fp64": 1}
 
 
 def slab_mc(ctx: Context, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint=None, rmin_um=10.0,
-            rmax_um=200.0, n_photons=64, seed=0, tuple0=0, precision="fp32", stream=None):
+            rmax_um=200.0, n_photons=64, seed=0, tuple0=0, precision="fp32", n_ref=None, stream=None):
     """Bubbly-slab Monte Carlo on device float32 tensors of length m ->
     (R, T, A, w_lobe) device tensors."""
     import torch
     m = cos_i.numel()
     out = [torch.empty_like(cos_i) for _ in range(4)]
     ctx.check(lib().sdm_slab_mc(ctx.ptr, m, _ptr(cos_i), _ptr(lambda_nm), _ptr(d_mm), _ptr(rho_b), _ptr(n),
-                                _ptr(k), _ptr(alpha_tint), float(rmin_um), float(rmax_um), int(n_photons),
+                                _ptr(k), _ptr(alpha_tint), _ptr(n_ref), float(rmin_um), float(rmax_um),
+                                int(n_photons),
                                 int(seed), int(tuple0), PRECISION[precision], *[_ptr(o) for o in out],
                                 _stream(stream)), "sdm_slab_mc")
     return tuple(out)

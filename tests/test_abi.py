@@ -83,6 +83,9 @@ int main(void) {
   P(sdm_scene_desc, mats); P(sdm_scene_desc, sun_dir); P(sdm_scene_desc, sky_L);
   P(sdm_render_params, seed); P(sdm_render_params, band_edges);
   P(sdm_render_params, chunk_paths); P(sdm_render_params, timing);
+  P(sdm_render_params, btdf_mode); P(sdm_render_params, err_dims); P(sdm_render_params, mlp);
+  P(sdm_render_params, err_table); P(sdm_render_params, err_bound);
+  P(sdm_stats, bubbly_vertices); P(sdm_stats, kernel_ms);
   P(sdm_stats, ms_render); P(sdm_stats, kernel_launches);
   P(sdm_outputs, stats);
   return 0;

@@ -22,6 +22,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 # Plain VALU issue rate of FP32 arithmetic without packed math:
 # 256 CUs x 64 lanes x 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s.
 ALU_PEAK_TFLOPS = 78.6
@@ -42,6 +43,10 @@ def kernel_models(stats, nb, npix, nl):
         "shadow_accum": ("hbm", Ns * (16 + 4 * nb)),
         "shade_glass": ("alu", 0),
         "finalize": ("hbm", npix * nl * 12 + npix * 24),
+        # network on the matrix cores: 2 x 9216 multiply-adds per (vertex, wavelength) tuple,
+        # nb wavelengths plus the reference one per bubbly vertex
+        "bubbly_eval": ("mfma", stats.get("bubbly_vertices", 0) * (nb + 1) * 2 * 9216),
+        "shade_bubbly": ("alu", 0),
     }
     return m
 
@@ -112,6 +117,131 @@ def cpu_baseline(scene, settings, budget_s=12.0, max_pixels=4096):
                       f"wavelengths, FP64, {dt:.1f} s on {threads} threads of {cpu}"}
 
 
+def bubbly_bench(args):
+    """Bubbly panes on the nave: MC tables of the slab (GPU), network training
+    (matrix cores), error table, then the exact, surrogate and fallback forms
+    of the render, with their rates and CIEDE2000 against the exact form."""
+    import torch
+    from paper_1912_05494_amd import color, sdm, surrogate, synth
+
+    scene = synth.nave_scene(seed=1, bubbly=True)
+    st = synth.nave_settings(W=512, H=512, spp=args.bubbly_spp, max_depth=8)
+    W, H, nl = st.camera.W, st.camera.H, len(st.lambda_nm)
+    ctx = sdm.Context(0)
+    gs = sdm.Scene(ctx, scene)
+    dev = torch.device("cuda", 0)
+    panes = [m for m in scene.materials if m.type == synth.GLASS_BUBBLY]
+    n_panes = len(panes)
+    lam_tab = scene.tab_lambda.astype(np.float64)
+
+    def tuples_for(n, seed):
+        tup, pane = surrogate.random_tuples(n, n_panes, st.lambda_nm, seed=seed)
+        nk = np.empty((n, 4), dtype=np.float32)
+        for q, m in enumerate(panes):
+            sel = pane == q
+            lam = tup[sel, 1].astype(np.float64)
+            nk[sel, 0] = np.interp(lam, lam_tab, m.n)
+            nk[sel, 1] = np.interp(lam, lam_tab, m.k)
+            nk[sel, 2] = np.interp(lam, lam_tab, m.alpha_tint)
+            nk[sel, 3] = np.interp(560.0, lam_tab, m.n)
+        return tup, pane, nk
+
+    def mc(tup, nk, nph, seed):
+        t = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+             (tup[:, 0], tup[:, 1], tup[:, 2], tup[:, 3], nk[:, 0], nk[:, 1], nk[:, 2], nk[:, 3])]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R, T, A, Wl = sdm.slab_mc(ctx, *t[:7], n_ref=t[7], n_photons=nph, seed=seed)
+        torch.cuda.synchronize()
+        return torch.stack([R, T, Wl], 1).contiguous(), time.perf_counter() - t0
+
+    tup, pane, nk = tuples_for(args.bubbly_train, seed=101)
+    target, t_mc = mc(tup, nk, 64, 7)
+    print(f"MC tables: {len(tup)} tuples x 64 photons in {t_mc:.2f} s", file=sys.stderr, flush=True)
+    net = sdm.MLP(ctx, n_panes, surrogate.init_params(n_panes, seed=0))
+    tt = torch.from_numpy(tup).to(dev)
+    tp = torch.from_numpy(pane).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    curve = net.train(tt, tp, target, steps=args.bubbly_steps, batch=8192, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"training: {args.bubbly_steps} steps in {t_train:.2f} s, loss {curve[0]:.4g} -> "
+          f"{curve[-50:].mean():.4g}", file=sys.stderr, flush=True)
+    vt, vp, vnk = tuples_for(8192, seed=202)
+    vtarget, _ = mc(vt, vnk, 16384, 9)
+    table = net.error_table(torch.from_numpy(vt).to(dev), torch.from_numpy(vp).to(dev), vtarget,
+                            dims=(8, 3, 4)).cpu().numpy()
+
+    forms = {}
+    images = {}
+    for form, btdf in (("exact", {"mode": "exact"}), ("surrogate", {"mode": "surrogate", "mlp": net}),
+                       ("fallback", {"mode": "fallback", "mlp": net, "err_table": table,
+                                     "bound": args.bubbly_bound})):
+        params, keep = sdm.make_params(st, timing=True, btdf=btdf)
+        spec = torch.empty((H, W, nl), dtype=torch.float32, device=dev)
+        xyz = torch.empty((H, W, 3), dtype=torch.float64, device=dev)
+        sdm.render_into(ctx, gs, params, spec, xyz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        images[form] = xyz.cpu().numpy()
+        forms[form] = {"value": W * H * st.spp * nl / dt, "ms_per_step": dt * 1e3,
+                       "bubbly_vertices": s_["bubbly_vertices"],
+                       "kernel_ms": {k: v for k, v in s_["kernel_ms"].items() if v > 0}}
+        print(f"{form}: {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    # sampling noise: each form against itself at another seed
+    st2 = synth.nave_settings(W=512, H=512, spp=args.bubbly_spp, max_depth=8, seed=1)
+    other = {}
+    for form, btdf in (("exact", {"mode": "exact"}), ("surrogate", {"mode": "surrogate", "mlp": net})):
+        p2, keep2 = sdm.make_params(st2, btdf=btdf)
+        spec = torch.empty((H, W, nl), dtype=torch.float32, device=dev)
+        xyz = torch.empty((H, W, 3), dtype=torch.float64, device=dev)
+        sdm.render_into(ctx, gs, p2, spec, xyz)
+        other[form] = xyz.cpu().numpy()
+    de = {f: float(np.mean(color.image_delta_e(images["exact"], images[f], st.cmf, st.lambda_nm)))
+          for f in ("surrogate", "fallback")}
+    for f in ("exact", "surrogate"):
+        de[f + "_vs_own_other_seed"] = float(np.mean(color.image_delta_e(images[f], other[f], st.cmf,
+                                                                          st.lambda_nm)))
+
+    def blocks(x, b=16):
+        return x.reshape(H // b, b, W // b, b, 3).mean((1, 3))
+
+    # the same on 16 x 16 pixel block means, where sampling noise is 16x lower
+    de_blocks = {f: float(np.mean(color.image_delta_e(blocks(images["exact"]), blocks(images[f]), st.cmf,
+                                                      st.lambda_nm))) for f in ("surrogate", "fallback")}
+    de_blocks["exact_vs_own_other_seed"] = float(np.mean(color.image_delta_e(
+        blocks(images["exact"]), blocks(other["exact"]), st.cmf, st.lambda_nm)))
+    out = {
+        "metric": "spectral ray samples/sec (bubbly panes, fallback form)",
+        "value": forms["fallback"]["value"],
+        "unit": "spectral ray samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": forms["fallback"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"procedural church nave with {n_panes} bubbly panes (density <= 34 per mm^3, "
+                               f"radii 10-200 um), {W}x{H}, {st.spp} spp, {nl} wavelengths, depth 8",
+                   "surrogate": f"12-64-64-64-3 trained {args.bubbly_steps} Adam steps of 8192 on "
+                                f"{args.bubbly_train} MC tuples (64 photons)",
+                   "error_table": f"8x3x4 cells per pane from 8192 tuples x 16384 photons, bound "
+                                  f"{args.bubbly_bound}"},
+        "forms": forms,
+        "mean_delta_e2000_vs_exact": de,
+        "mean_delta_e2000_vs_exact_16x16_blocks": de_blocks,
+        "flagged_cells": float((table > args.bubbly_bound).mean()),
+        "mc_tuple_photons_per_s": len(tup) * 64 / t_mc,
+        "train_samples_per_s": args.bubbly_steps * 8192 / t_train,
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +252,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--form", default="plain", choices=["plain", "bubbly"],
+                    help="plain: the clear-glass nave (default); bubbly: bubbly panes in three forms")
+    ap.add_argument("--bubbly-spp", type=int, default=64)
+    ap.add_argument("--bubbly-train", type=int, default=10_000_000)
+    ap.add_argument("--bubbly-steps", type=int, default=10000)
+    # the validation tables carry MC noise of ~2e-3 per tuple (16384 photons),
+    # so a bound below ~1e-2 flags nearly every cell
+    ap.add_argument("--bubbly-bound", type=float, default=2e-2)
     args = ap.parse_args()
     if args.profile_once:
         profile_once()
@@ -131,6 +269,10 @@ def main():
               "(the spectral and pixel sub-domains are work items of a single device)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.form == "bubbly":
+        bubbly_bench(args)
+        return
 
     import torch
     from paper_1912_05494_amd import sdm, synth
@@ -174,6 +316,8 @@ def main():
         per_launch = work / (kl[k] / args.steps)
         if bound == "hbm":
             ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+        elif bound == "mfma":
+            ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, MFMA_BF16_PEAK_TFLOPS, "TFLOP/s"
         else:
             ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, ALU_PEAK_TFLOPS, "TFLOP/s"
         kernels[k] = {"ms_per_step": kms[k] / args.steps, "launches_per_step": kl[k] // args.steps,

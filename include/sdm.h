@@ -281,6 +281,16 @@ int sdm_mlp_train(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *p
 int sdm_mlp_infer(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *panes, float *out,
                   void *hip_stream);
 
+/* Error table of the fallback mode: table[pane][c][t][r] (DEVICE float,
+ * n_panes * dims[0] * dims[1] * dims[2]) = the largest max(|R - R*|,
+ * |T - T*|) between the network and the targets (R*, T*, w*) over the m
+ * validation tuples that fall in the cell (0 for empty cells); cells as in
+ * sdm_render_params: cos theta in [0, 1], thickness in [2, 5] mm, density in
+ * [0, 34] per mm^3, dims[] (HOST) cells each, clamped.  tuples, panes,
+ * target: DEVICE as for sdm_mlp_grad.  Synchronises the stream. */
+int sdm_mlp_error_table(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *panes,
+                        const float *target, const int32_t *dims, float *table, void *hip_stream);
+
 /* Matrix-core lane layout check: C32 = A32 B32 with A32 [16][32], B32
  * [32][16] (v_mfma_f32_16x16x32_bf16), C16 = A16 B16 with A16 [16][16],
  * B16 [16][16] (v_mfma_f32_16x16x16_bf16); inputs rounded to BF16; all

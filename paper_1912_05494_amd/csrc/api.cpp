@@ -1026,6 +1026,34 @@ int sdm_mlp_infer(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *p
     return check_flag(ctx, s, "sdm_mlp_infer");
 }
 
+int sdm_mlp_error_table(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *panes, const float *target,
+                        const int32_t *dims, float *table, void *hip_stream)
+{
+    if (!net) return SDM_E_INVALID;
+    sdm_context *ctx = net->ctx;
+    if (int rc = mlp_check(net, m, tuples, panes)) return rc;
+    if (!dims || !table || (m > 0 && !target)) return fail(ctx, SDM_E_INVALID, "null argument");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > 1024) return fail(ctx, SDM_E_INVALID, "dims must be in [1, 1024]");
+    if ((int64_t)net->n_panes * dims[0] * dims[1] * dims[2] > (1 << 24))
+        return fail(ctx, SDM_E_INVALID, "error table too large");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(ctx, ctx->flag.ensure(sizeof(int)));
+    HIPCHK(ctx, ctx->mc_acc.ensure(3 * (size_t)std::max<int64_t>(m, 1) * sizeof(float)));
+    launch_zero_i32(ctx->flag.as<int>(), 1, s);
+    float *y = ctx->mc_acc.as<float>();
+    if (m > 0) {
+        launch_mlp_pack(net->params.as<float>(), net->wb.p, net->bb.as<float>(), s);
+        launch_mlp_infer((uint32_t)m, net->n_panes, tuples, panes, net->wb.p, net->bb.as<float>(),
+                         net->params.as<float>() + mlp_net_params(), y, ctx->flag.as<int>(), ctx->num_cu, s);
+    }
+    const int d[3] = {dims[0], dims[1], dims[2]};
+    launch_err_cells((uint32_t)m, tuples, panes, y, target, net->n_panes, d, table, ctx->flag.as<int>(), s);
+    HIPCHK(ctx, hipGetLastError());
+    return check_flag(ctx, s, "sdm_mlp_error_table");
+}
+
 int sdm_debug_mfma(sdm_context *ctx, const float *A32, const float *B32, float *C32, const float *A16,
                    const float *B16, float *C16, void *hip_stream)
 {

@@ -384,6 +384,25 @@ __global__ void __launch_bounds__(256) k_mlp_infer(uint32_t m, int n_panes, cons
     }
 }
 
+// Error table of the surrogate: per cell (pane, cos, thickness, density) the
+// largest |R - R*| or |T - T*| over the validation tuples in it (atomic max
+// on the bits of non-negative floats).  y: network outputs [m][3].
+__global__ void k_err_cells(uint32_t m, const float *tup, const int32_t *pane, const float *y, const float *target,
+                            int n_panes, int d0, int d1, int d2, uint32_t *table, int *bad)
+{
+    const int dims[3] = {d0, d1, d2};
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < m; s += gridDim.x * blockDim.x) {
+        const int p = pane[s];
+        if ((unsigned)p >= (unsigned)n_panes) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        const float e = fmaxf(fabsf(y[3 * s] - target[3 * s]), fabsf(y[3 * s + 1] - target[3 * s + 1]));
+        const int c = err_cell<float>(dims, p, tup[4 * s], tup[4 * s + 2], tup[4 * s + 3]);
+        atomicMax(table + c, __float_as_uint(e));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -458,6 +477,17 @@ __global__ void k_zero_i32(int *p, int n)
 void launch_zero_i32(int *p, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+}
+
+void launch_err_cells(uint32_t m, const float *tup, const int32_t *pane, const float *y, const float *target,
+                      int n_panes, const int dims[3], float *table, int *bad, hipStream_t s)
+{
+    const int ncell = n_panes * dims[0] * dims[1] * dims[2];
+    hipLaunchKernelGGL(k_zero_i32, dim3((ncell + 255) / 256), dim3(256), 0, s, (int *)table, ncell);
+    if (m == 0) return;
+    const int grid = (int)std::min<uint32_t>(4096, (m + 255) / 256);
+    hipLaunchKernelGGL(k_err_cells, dim3(grid), dim3(256), 0, s, m, tup, pane, y, target, n_panes, dims[0], dims[1],
+                       dims[2], (uint32_t *)table, bad);
 }
 
 int mlp_net_params() { return kNetParams; }

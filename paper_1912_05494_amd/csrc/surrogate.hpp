@@ -28,6 +28,8 @@ void launch_mlp_adam(int P, const float *grad, float *params, float *m1, float *
 void launch_mlp_infer(uint32_t m, int n_panes, const float *tup, const int32_t *pane, const void *wb, const float *bb,
                       const float *E, float *out, int *bad, int num_cu, hipStream_t s);
 void launch_zero_i32(int *p, int n, hipStream_t s);
+void launch_err_cells(uint32_t m, const float *tup, const int32_t *pane, const float *y, const float *target,
+                      int n_panes, const int dims[3], float *table, int *bad, hipStream_t s);
 int mlp_net_params();
 int mlp_wb_elems();
 int mlp_bb_elems();

@@ -782,8 +782,8 @@ __device__ __forceinline__ BubblyVertex bubbly_vertex(const JobDev *jobs, const 
 // every wavelength of its band and its lobe width w at kLambdaRef.  The
 // weights are multiplied by R + T in place; R / (R + T) and w are kept for
 // k_shade_bubbly.  FP32 build: 16-tuple tiles on the matrix cores (BF16
-// operands, FP32 sums), tuples enumerated (vertex, j) with j = nb_max for
-// the reference wavelength.
+// operands, FP32 sums); tuple j of a vertex is its band's wavelength j, and
+// j = nb_max the reference wavelength.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *jobs, const BandDev *bands, Work<R> w,
                                                             int cur, const __bf16 *wb, const float *bb,
@@ -795,31 +795,29 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *jobs,
     const Pool<R> Pi = w.p[cur];
     WaveBuf &wv = wbuf[threadIdx.x >> 6];
     const uint32_t l = lane_id();
-    const uint32_t stride = (uint32_t)w.nbmax + 1u;
-    const uint64_t ntup = (uint64_t)min(w.cnt->bcount, w.cap) * stride;
-    const uint64_t ntile = (ntup + 15) / 16;
+    const uint32_t stride = (uint32_t)w.nbmax + 1u;          // band wavelengths + the reference one
+    const uint32_t per_v = (stride + 15u) / 16u;              // tiles per vertex
+    const uint64_t ntile = (uint64_t)min(w.cnt->bcount, w.cap) * per_v;
     const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
     const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     for (uint64_t tile = wave; tile < ntile; tile += nw) {
-        bool valid = false;
-        uint32_t slot = 0, j = 0;
+        // one tile = 16 consecutive wavelengths of one vertex, so the mode
+        // check is uniform across the wave and exact-walk vertices cost no
+        // matrix work
+        const uint32_t e = (uint32_t)(tile / per_v);
+        const uint32_t j = (uint32_t)(tile % per_v) * 16u + (l & 15u);
+        V3<R> d, ng;
+        R cos_i, thick;
+        const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, e, d, ng, cos_i, thick);
+        if (v.mode != kBtdfSurrogate) continue;
+        const bool valid = l < 16 && (j < (uint32_t)v.bd.nb || j == stride - 1u);
         if (l < 16) {
-            const uint64_t tu = tile * 16 + l;
-            if (tu < ntup) {
-                const uint32_t e = (uint32_t)(tu / stride);
-                j = (uint32_t)(tu % stride);
-                V3<R> d, ng;
-                R cos_i, thick;
-                const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, e, d, ng, cos_i, thick);
-                slot = v.i;
-                valid = v.mode == kBtdfSurrogate && (j < (uint32_t)v.bd.nb || j == stride - 1u);
-                if (valid) {
-                    const float lam = j == stride - 1u ? kLambdaRef : (float)gld((const R *)v.jb->lam + v.bd.l0 + j);
-                    features((float)cos_i, lam, (float)thick, (float)v.rho, E + 8 * v.pane, wv.X0 + l * 32);
-                }
-            }
-            if (!valid)
+            if (valid) {
+                const float lam = j == stride - 1u ? kLambdaRef : (float)gld((const R *)v.jb->lam + v.bd.l0 + j);
+                features((float)cos_i, lam, (float)thick, (float)v.rho, E + 8 * v.pane, wv.X0 + l * 32);
+            } else {
                 for (int q = 0; q < 32; ++q) wv.X0[l * 32 + q] = (__bf16)0.0f;
+            }
         }
         wave_sync();
         forward_tile(net, wv);
@@ -827,9 +825,9 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *jobs,
             float Rr, Tt, wl;
             heads(wv.O[l * 16], wv.O[l * 16 + 1], wv.O[l * 16 + 2], Rr, Tt, wl);
             if (j == stride - 1u) {
-                w.bw[slot] = R(wl);
+                w.bw[v.i] = R(wl);
             } else {
-                const size_t q = aosoa(slot, (int)j, w.nbmax);
+                const size_t q = aosoa(v.i, (int)j, w.nbmax);
                 Pi.beta[q] = Pi.beta[q] * R(Rr + Tt);
                 w.bratio[q] = R(Rr / (Rr + Tt));
             }

@@ -122,6 +122,7 @@ def lib():
         L.sdm_mlp_train.argtypes = [vp, C.c_int64] + [vp] * 3 + [C.POINTER(TrainParams), vp, vp]
         L.sdm_mlp_infer.argtypes = [vp, C.c_int64] + [vp] * 4
         L.sdm_debug_mfma.argtypes = [vp] * 8
+        L.sdm_mlp_error_table.argtypes = [vp, C.c_int64] + [vp] * 6
         _lib = L
     return _lib
 
@@ -130,7 +131,7 @@ EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_
             "sdm_scene_destroy", "sdm_scene_info", "sdm_render", "sdm_slab_eval",
             "sdm_debug_intersect", "sdm_debug_shadow", "sdm_slab_mc", "sdm_mlp_nparams",
             "sdm_mlp_create", "sdm_mlp_destroy", "sdm_mlp_get_params", "sdm_mlp_grad",
-            "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma")
+            "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table")
 
 
 def _stream(stream=None):
@@ -386,6 +387,17 @@ class MLP:
         self.ctx.check(lib().sdm_mlp_infer(self.ptr, tuples.shape[0], _ptr(tuples), _ptr(panes), _ptr(out),
                                            _stream(stream)), "sdm_mlp_infer")
         return out
+
+    def error_table(self, tuples, panes, target, dims=(8, 3, 4), stream=None):
+        """Largest |R - R*| or |T - T*| per cell -> device tensor
+        (n_panes, *dims)."""
+        import torch
+        d = np.ascontiguousarray(dims, dtype=np.int32)
+        tab = torch.empty((self.n_panes, *[int(x) for x in dims]), dtype=torch.float32, device=tuples.device)
+        self.ctx.check(lib().sdm_mlp_error_table(self.ptr, tuples.shape[0], _ptr(tuples), _ptr(panes),
+                                                 _ptr(target), d.ctypes.data, _ptr(tab), _stream(stream)),
+                       "sdm_mlp_error_table")
+        return tab
 
     def close(self):
         if getattr(self, "ptr", None):

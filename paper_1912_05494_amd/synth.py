@@ -247,7 +247,7 @@ def random_glass(rng, lam):
 
 
 def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=1,
-               pane_grid=10, bubbly=False, rho_max=50.0, sun_elev=35.0, sun_azim=15.0):
+               pane_grid=10, bubbly=False, rho_max=34.0, sun_elev=35.0, sun_azim=15.0):
     """Procedural church nave, 60 x 12 x 20 m: floor, side walls with window
     openings (1.5 x 4 m), semicircular barrel vault, end walls and two rows of
     ten cylindrical columns; glass panes fill the openings.  Opaque parts are

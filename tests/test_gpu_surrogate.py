@@ -268,3 +268,31 @@ def test_mlp_invalid_inputs(gpu):
     with pytest.raises(sdm.SdmError):
         net.train(t, pn, tg, steps=1, batch=41)
     net.close()
+
+
+def test_mlp_error_table_matches_oracle(gpu, orc):
+    """Per-cell largest |R - R*| or |T - T*|: the GPU network against targets,
+    compared with the oracle's BF16-operand network binned the same way."""
+    sdm, ctx, torch = gpu
+    n_panes, m, dims = 3, 6000, (8, 3, 4)
+    p, tup, pane, _ = net_case(31, m, n_panes)
+    y = orc.mlp_forward_bf16(p.astype(np.float64), n_panes, tup.astype(np.float64), pane)
+    rng = np.random.default_rng(5)
+    target = (y + rng.normal(0, 0.01, y.shape)).astype(np.float32)
+    net = sdm.MLP(ctx, n_panes, p)
+    t, pn, tg = to_dev(torch, tup, pane, target)
+    tab = net.error_table(t, pn, tg, dims=dims).cpu().numpy()
+    f = np.float32
+    ic = np.clip((tup[:, 0] * f(dims[0])).astype(np.int64), 0, dims[0] - 1)
+    idd = np.clip(((tup[:, 2] - f(2)) / f(3) * f(dims[1])).astype(np.int64), 0, dims[1] - 1)
+    ir = np.clip((tup[:, 3] / f(34) * f(dims[2])).astype(np.int64), 0, dims[2] - 1)
+    e = np.maximum(np.abs(y[:, 0] - target[:, 0]), np.abs(y[:, 1] - target[:, 1]))
+    ref = np.zeros((n_panes,) + dims)
+    np.maximum.at(ref, (pane, ic, idd, ir), e)
+    assert np.array_equal(tab > 0, ref > 0)
+    assert np.allclose(tab, ref, atol=1e-3)
+    pane[0] = n_panes
+    t, pn = to_dev(torch, tup, pane)
+    with pytest.raises(sdm.SdmError):
+        net.error_table(t, pn, tg, dims=dims)
+    net.close()

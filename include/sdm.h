@@ -132,6 +132,8 @@ typedef struct {
     const sdm_mlp *mlp;         /* network (surrogate modes), same context      */
     const float *err_table;     /* host [n_panes * err_dims product] (fallback) */
     float err_bound;
+    int32_t graph;              /* 1: replay each chunk's kernel sequence as a
+                                   HIP graph (ignored when timing = 1)         */
 } sdm_render_params;
 
 /* Kernel classes reported in sdm_stats. */
@@ -182,6 +184,43 @@ int sdm_scene_destroy(sdm_scene *scene);
  * returning SDM_E_DEVICE only if the pool cannot grow further. */
 int sdm_render(sdm_context *ctx, const sdm_scene *scene, const sdm_render_params *params,
                const sdm_outputs *out, void *hip_stream);
+
+/* One job of a batch: a scene, its parameters and its outputs. */
+typedef struct {
+    const sdm_scene *scene;
+    const sdm_render_params *params;
+    const sdm_outputs *out;
+} sdm_job;
+
+/* Renders n_jobs images in one wavefront: the (job x band x tile) work items
+ * of every job share one path pool and one kernel sequence per chunk, with a
+ * job table giving each path its scene, camera, spectra and accumulator
+ * (Sec. 4: dynamic balancing of sub-domains).  Each image equals what
+ * sdm_render gives for its job alone.  All jobs must use the same precision,
+ * and the jobs that need a network must share one.  Chunking, graph replay
+ * and the pool headroom follow jobs[0].params.  The per-job outputs are as
+ * for sdm_render; job statistics are not filled; stats (host, may be NULL)
+ * receives the totals.  Synchronises the stream. */
+int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_stats *stats,
+                     void *hip_stream);
+
+/* Tuning of the wavefront for a scene and parameters: renders at reduced
+ * samples per pixel with candidate chunk sizes (2^20, 2^21, 2^22 paths) and
+ * pixel tiles (8x8, 16x16, 32x32), keeps the fastest, and uses it in later
+ * renders of this context with the same scene, image size, wavelength
+ * count, depth and precision whose chunk_paths, tile_w and tile_h are 0.
+ * cache_path (may be NULL): a text file of earlier results; a matching entry
+ * is taken without measuring, a new result is appended.  The image does not
+ * depend on the choice. */
+typedef struct {
+    int64_t chunk_paths;
+    int32_t tile_w, tile_h;
+    double ms;                  /* measured time of the reduced render         */
+    int32_t from_cache;         /* 1: taken from cache_path                    */
+} sdm_tune_result;
+
+int sdm_autotune(sdm_context *ctx, const sdm_scene *scene, const sdm_render_params *params,
+                 const char *cache_path, sdm_tune_result *out, void *hip_stream);
 
 /* Thin-slab optics for m independent inputs (DEVICE arrays of length m):
  * interface Fresnel for n + ik at incidence cos_i, real-Snell path length,

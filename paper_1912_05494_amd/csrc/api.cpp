@@ -17,63 +17,11 @@
 
 using namespace sdm;
 
-namespace {
+#include "runtime.hpp"
 
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t b)
-    {
-        if (b <= bytes && p) return hipSuccess;
-        release();
-        hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
-        if (e != hipSuccess) { p = nullptr; bytes = 0; return e; }
-        bytes = std::max<size_t>(b, 256);
-        return hipSuccess;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
-    ~DevBuf() { release(); }
-};
+using namespace sdm_rt;
 
-}  // namespace
-
-struct sdm_context {
-    int device = 0;
-    int num_cu = 0;
-    std::string err;
-    DevBuf gstack;
-    // render work buffers (one set; reallocated when a render needs more)
-    DevBuf pool, hits, shadowq, acc, counters, jobs, bands, items, tables, outs;
-    Counters *host_counters = nullptr;
-    std::vector<hipEvent_t> events;
-    DevBuf slab_tmp;
-    DevBuf mc_acc, flag;
-    DevBuf bubq, errtab;        // surrogate branch ratios and lobe widths; error table
-};
-
-struct sdm_mlp {
-    sdm_context *ctx = nullptr;
-    int32_t n_panes = 0;
-    int64_t P = 0;
-    int64_t t = 0;   // Adam steps taken
-    DevBuf params, m1, m2, grad, wb, bb, partial, loss_partial, loss;
-};
-
-struct sdm_scene {
-    sdm_context *ctx = nullptr;
-    SceneDev dev{};
-    DevBuf nodes, tris, thick, mat_type, mat_thick, mat_bub, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
-    int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
-    int32_t max_pane = -1;      // largest pane type of a bubbly material (-1: none)
-};
-
-namespace {
+namespace sdm_rt {
 
 int fail(sdm_context *ctx, int code, const char *fmt, ...)
 {
@@ -86,22 +34,6 @@ int fail(sdm_context *ctx, int code, const char *fmt, ...)
     return code;
 }
 
-#define HIPCHK(ctx, x)                                                                            \
-    do {                                                                                          \
-        hipError_t e_ = (x);                                                                      \
-        if (e_ != hipSuccess)                                                                     \
-            return fail(ctx, e_ == hipErrorOutOfMemory ? SDM_E_NOMEM : SDM_E_DEVICE, "%s: %s",    \
-                        #x, hipGetErrorString(e_));                                               \
-    } while (0)
-
-template <class T>
-hipError_t upload(DevBuf &b, const T *src, size_t n, hipStream_t s = nullptr)
-{
-    hipError_t e = b.ensure(n * sizeof(T));
-    if (e != hipSuccess || n == 0) return e;
-    return hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, s);
-}
-
 bool ptr_is_device(const void *p)
 {
     hipPointerAttribute_t a;
@@ -112,7 +44,7 @@ bool ptr_is_device(const void *p)
     return a.type == hipMemoryTypeDevice;
 }
 
-}  // namespace
+}  // namespace sdm_rt
 
 namespace {
 
@@ -179,6 +111,14 @@ int sdm_context_create(int device, sdm_context **out)
         delete ctx;
         return SDM_E_NOMEM;
     }
+    // the stream graphs are captured on and replayed from (default priority)
+    if (hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(ctx->host_counters);
+        delete ctx;
+        return SDM_E_DEVICE;
+    }
     *out = ctx;
     return SDM_OK;
 }
@@ -189,6 +129,10 @@ int sdm_context_destroy(sdm_context *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (auto e : ctx->join)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
     if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
     delete ctx;
     return SDM_OK;
@@ -375,439 +319,7 @@ int sdm_scene_destroy(sdm_scene *sc)
 
 }  // extern "C"
 
-// ---------------------------------------------------------------------------
-// Render
-// ---------------------------------------------------------------------------
-namespace {
-
-struct Plan {
-    std::vector<BandDev> bands;
-    std::vector<ItemDev> items;
-    uint64_t total_rays = 0;
-    int nbmax = 0;
-};
-
-int plan_work(sdm_context *ctx, const sdm_render_params *p, int job, Plan &plan)
-{
-    const int nl = p->n_lambda;
-    std::vector<int> edges;
-    if (p->band_edges) {
-        edges.assign(p->band_edges, p->band_edges + p->n_bands + 1);
-        if (edges.front() != 0 || edges.back() != nl)
-            return fail(ctx, SDM_E_INVALID, "band_edges must start at 0 and end at n_lambda");
-        for (int b = 0; b < p->n_bands; ++b)
-            if (edges[b + 1] <= edges[b]) return fail(ctx, SDM_E_INVALID, "band_edges must increase");
-    } else {
-        // contiguous bands, the first nl mod B one wavelength larger
-        const int B = p->n_bands, base = nl / B, extra = nl % B;
-        edges.push_back(0);
-        for (int b = 0; b < B; ++b) edges.push_back(edges.back() + base + (b < extra ? 1 : 0));
-    }
-    const int b0 = (int)plan.bands.size();
-    for (size_t b = 0; b + 1 < edges.size(); ++b) {
-        const int nb = edges[b + 1] - edges[b];
-        if (nb > kMaxBand) return fail(ctx, SDM_E_UNSUPPORTED, "a band holds %d > %d wavelengths", nb, kMaxBand);
-        plan.bands.push_back(BandDev{job, edges[b], nb, 0});
-        plan.nbmax = std::max(plan.nbmax, nb);
-    }
-    if ((int)plan.bands.size() >= (1 << kAuxBandBits)) return fail(ctx, SDM_E_UNSUPPORTED, "too many bands");
-    const int tw = p->tile_w > 0 ? p->tile_w : 16, th = p->tile_h > 0 ? p->tile_h : 16;
-    const int W = p->camera.W, H = p->camera.H;
-    for (int y0 = 0; y0 < H; y0 += th)
-        for (int x0 = 0; x0 < W; x0 += tw)
-            for (int b = b0; b < (int)plan.bands.size(); ++b) {
-                ItemDev it{};
-                it.band = b;
-                it.x0 = x0;
-                it.y0 = y0;
-                it.tw = std::min(tw, W - x0);
-                it.th = std::min(th, H - y0);
-                it.s0 = 0;
-                it.ns = p->spp;
-                it.first = plan.total_rays;
-                plan.total_rays += (uint64_t)it.tw * it.th * it.ns;
-                plan.items.push_back(it);
-            }
-    return SDM_OK;
-}
-
-int validate_params(sdm_context *ctx, const sdm_render_params *p)
-{
-    if (!p) return fail(ctx, SDM_E_INVALID, "null render parameters");
-    const sdm_camera &c = p->camera;
-    if (c.W < 1 || c.H < 1 || (int64_t)c.W * c.H > (1ll << 31))
-        return fail(ctx, SDM_E_INVALID, "image size %d x %d out of range", c.W, c.H);
-    if (p->spp < 1 || p->spp > 65535) return fail(ctx, SDM_E_INVALID, "spp must be in [1, 65535]");
-    if (p->max_depth < 1 || p->max_depth > 255) return fail(ctx, SDM_E_INVALID, "max_depth must be in [1, 255]");
-    if (p->n_lambda < 1 || !p->lambda_nm) return fail(ctx, SDM_E_INVALID, "need n_lambda >= 1 wavelengths");
-    if (p->n_bands < 1 || p->n_bands > p->n_lambda)
-        return fail(ctx, SDM_E_INVALID, "n_bands must be in [1, n_lambda]");
-    if (c.projection != SDM_PINHOLE && c.projection != SDM_ORTHO)
-        return fail(ctx, SDM_E_INVALID, "unknown projection");
-    if (p->precision != SDM_PREC_FP32 && p->precision != SDM_PREC_FP64)
-        return fail(ctx, SDM_E_INVALID, "unknown precision");
-    if (p->btdf_mode != SDM_BTDF_EXACT && p->btdf_mode != SDM_BTDF_SURROGATE && p->btdf_mode != SDM_BTDF_FALLBACK)
-        return fail(ctx, SDM_E_INVALID, "unknown btdf_mode");
-    return SDM_OK;
-}
-
-// Network and error table of the bubbly panes of a scene (none needed for
-// exact walks or scenes without bubbly panes).
-int validate_btdf(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p)
-{
-    if (sc->max_pane < 0 || p->btdf_mode == SDM_BTDF_EXACT) return SDM_OK;
-    if (!p->mlp) return fail(ctx, SDM_E_INVALID, "surrogate modes need a network (mlp)");
-    if (p->mlp->ctx != ctx) return fail(ctx, SDM_E_INVALID, "the network belongs to another context");
-    if (sc->max_pane >= p->mlp->n_panes)
-        return fail(ctx, SDM_E_INVALID, "pane type %d is beyond the network's %d embeddings", sc->max_pane,
-                    p->mlp->n_panes);
-    if (p->btdf_mode == SDM_BTDF_FALLBACK) {
-        if (!p->err_table) return fail(ctx, SDM_E_INVALID, "fallback mode needs an error table");
-        for (int a = 0; a < 3; ++a)
-            if (p->err_dims[a] < 1 || p->err_dims[a] > 1024)
-                return fail(ctx, SDM_E_INVALID, "err_dims must be in [1, 1024]");
-        if ((int64_t)p->err_dims[0] * p->err_dims[1] * p->err_dims[2] > (1 << 20))
-            return fail(ctx, SDM_E_INVALID, "error table too large");
-    }
-    return SDM_OK;
-}
-
-void camera_basis(const sdm_camera &c, JobDev &jb)
-{
-    double f[3], r[3], u[3];
-    for (int a = 0; a < 3; ++a) f[a] = (double)c.target[a] - c.eye[a];
-    auto nrm = [](double *v) {
-        double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        if (l > 0) for (int a = 0; a < 3; ++a) v[a] /= l;
-    };
-    nrm(f);
-    const double up[3] = {c.up[0], c.up[1], c.up[2]};
-    r[0] = f[1] * up[2] - f[2] * up[1];
-    r[1] = f[2] * up[0] - f[0] * up[2];
-    r[2] = f[0] * up[1] - f[1] * up[0];
-    nrm(r);
-    u[0] = r[1] * f[2] - r[2] * f[1];
-    u[1] = r[2] * f[0] - r[0] * f[2];
-    u[2] = r[0] * f[1] - r[1] * f[0];
-    for (int a = 0; a < 3; ++a) {
-        jb.eye[a] = c.eye[a];
-        jb.f[a] = f[a];
-        jb.r[a] = r[a];
-        jb.u[a] = u[a];
-    }
-    jb.th = std::tan(0.5 * (double)c.vfov_deg * M_PI / 180.0);
-    jb.aspect = (double)c.W / (double)c.H;
-    jb.oh = 0.5 * (double)c.ortho_height;
-    jb.projection = c.projection;
-    jb.W = c.W;
-    jb.H = c.H;
-}
-
-struct Timer {
-    sdm_context *ctx;
-    hipStream_t s;
-    bool on;
-    size_t next = 0;
-    std::vector<std::pair<int, size_t>> marks;  // (kernel class, event index of start)
-    hipError_t begin(int cls)
-    {
-        if (!on) return hipSuccess;
-        if (next + 2 > ctx->events.size()) {
-            for (int i = 0; i < 64; ++i) {
-                hipEvent_t e;
-                hipError_t r = hipEventCreate(&e);
-                if (r != hipSuccess) return r;
-                ctx->events.push_back(e);
-            }
-        }
-        marks.push_back({cls, next});
-        hipError_t r = hipEventRecord(ctx->events[next], s);
-        next += 2;
-        return r;
-    }
-    hipError_t end()
-    {
-        if (!on) return hipSuccess;
-        return hipEventRecord(ctx->events[marks.back().second + 1], s);
-    }
-};
-
-template <class R>
-int render_impl(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p, const sdm_outputs *out,
-                hipStream_t s)
-{
-    const int nl = p->n_lambda, W = p->camera.W, H = p->camera.H;
-    const int64_t npix = (int64_t)W * H;
-    Plan plan;
-    int rc = plan_work(ctx, p, 0, plan);
-    if (rc) return rc;
-    // per-render tables at the render wavelengths
-    const int nm = sc->n_mat;
-    const size_t tab_elems = 4 * (size_t)nm * nl + 3 * (size_t)nl;  // rho,n,k,tint | E, Lsky, lambda
-    std::vector<double> wts(nl), cmf(3 * (size_t)nl, 0.0);
-    if (nl == 1) wts[0] = 1.0;
-    else
-        for (int i = 0; i < nl; ++i)
-            wts[i] = 0.5 * ((double)p->lambda_nm[std::min(i + 1, nl - 1)] - p->lambda_nm[std::max(i - 1, 0)]);
-    if (p->cmf_xyz)
-        for (size_t i = 0; i < 3 * (size_t)nl; ++i) cmf[i] = p->cmf_xyz[i];
-    // device layout of `tables`: [R tables][lambda float][wts double][cmf double]
-    const size_t off_lamf = ((tab_elems * sizeof(R) + 255) / 256) * 256;
-    const size_t off_w = off_lamf + ((nl * sizeof(float) + 255) / 256) * 256;
-    const size_t off_c = off_w + ((nl * sizeof(double) + 255) / 256) * 256;
-    const size_t tab_bytes = off_c + 3 * nl * sizeof(double);
-    HIPCHK(ctx, ctx->tables.ensure(tab_bytes));
-    char *tb = ctx->tables.as<char>();
-    R *tR = reinterpret_cast<R *>(tb);
-    float *lamf = reinterpret_cast<float *>(tb + off_lamf);
-    double *wts_d = reinterpret_cast<double *>(tb + off_w);
-    double *cmf_d = reinterpret_cast<double *>(tb + off_c);
-    HIPCHK(ctx, hipMemcpyAsync(lamf, p->lambda_nm, nl * sizeof(float), hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, hipMemcpyAsync(wts_d, wts.data(), nl * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, hipMemcpyAsync(cmf_d, cmf.data(), 3 * nl * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lamf, nl, tR, s);
-    launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sun.as<float>(), 1, lamf, nl,
-                       tR + 4 * (size_t)nm * nl, s);
-    launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sky.as<float>(), 1, lamf, nl,
-                       tR + 4 * (size_t)nm * nl + nl, s);
-    // lambda itself in R (identity resample of the wavelength grid)
-    launch_resample<R>(lamf, nl, lamf, 1, lamf, nl, tR + 4 * (size_t)nm * nl + 2 * nl, s);
-    HIPCHK(ctx, hipGetLastError());
-
-    JobDev jb{};
-    jb.sc = sc->dev;
-    camera_basis(p->camera, jb);
-    jb.spp = p->spp;
-    jb.nl = nl;
-    jb.max_depth = p->max_depth;
-    jb.seed = p->seed;
-    jb.job_word = p->job_id;
-    jb.acc_off = 0;
-    jb.rho = tR;
-    jb.n = tR + (size_t)nm * nl;
-    jb.k = tR + 2 * (size_t)nm * nl;
-    jb.tint = tR + 3 * (size_t)nm * nl;
-    jb.E = tR + 4 * (size_t)nm * nl;
-    jb.Lsky = tR + 4 * (size_t)nm * nl + nl;
-    jb.lam = tR + 4 * (size_t)nm * nl + 2 * nl;
-    jb.beta_thr = p->beta_threshold;
-    // bubbly panes: mode, error table, network weights in the kernels' layout
-    const bool bubbly = sc->max_pane >= 0;
-    const bool surr = bubbly && p->btdf_mode != SDM_BTDF_EXACT;
-    jb.btdf_mode = p->btdf_mode;
-    jb.err_bound = p->err_bound;
-    if (bubbly && p->btdf_mode == SDM_BTDF_FALLBACK) {
-        const size_t ncell = (size_t)p->mlp->n_panes * p->err_dims[0] * p->err_dims[1] * p->err_dims[2];
-        HIPCHK(ctx, upload(ctx->errtab, p->err_table, ncell, s));
-        for (int a = 0; a < 3; ++a) jb.err_dims[a] = p->err_dims[a];
-        jb.err_table = ctx->errtab.as<float>();
-    }
-    if (surr) launch_mlp_pack(p->mlp->params.as<float>(), p->mlp->wb.p, p->mlp->bb.as<float>(), s);
-    HIPCHK(ctx, upload(ctx->jobs, &jb, 1, s));
-    HIPCHK(ctx, upload(ctx->bands, plan.bands.data(), plan.bands.size(), s));
-    HIPCHK(ctx, upload(ctx->items, plan.items.data(), plan.items.size(), s));
-
-    // work buffers
-    const uint64_t total = plan.total_rays;
-    uint64_t chunk = p->chunk_paths > 0 ? (uint64_t)p->chunk_paths : (uint64_t)1 << 21;
-    chunk = std::min<uint64_t>(chunk, total);
-    chunk = std::max<uint64_t>(chunk, 1);
-    int attempt = 0;
-    for (;;) {
-        // pool capacity: the chunk plus headroom for forks (doubled on overflow)
-        const uint64_t cap64 = ((chunk + (chunk >> 2) * (1ull << attempt) + 1024 + 63) / 64) * 64;
-        if (cap64 >= (1ull << 31)) return fail(ctx, SDM_E_NOMEM, "path pool would exceed 2^31 slots");
-        const uint32_t cap = (uint32_t)cap64;
-        const int nb = plan.nbmax;
-        const size_t plane = (size_t)cap * sizeof(R);
-        const size_t pool_b = 6 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R);
-        const size_t hit_b = 3 * plane + 2 * (size_t)cap * 4;
-        const size_t sh_b = 3 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
-                            (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R));
-        HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
-        HIPCHK(ctx, ctx->hits.ensure(hit_b + 2048));
-        HIPCHK(ctx, ctx->shadowq.ensure(sh_b + 2048));
-        HIPCHK(ctx, ctx->acc.ensure((size_t)npix * nl * sizeof(double)));
-        HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
-        const int grid_t = ctx->num_cu * occupancy_trace<R>();
-        const int grid_st = ctx->num_cu * occupancy_shadow<R>();
-        const int grid_s = ctx->num_cu * occupancy_shade<R>();
-        const int grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
-        const size_t gthreads = (size_t)std::max(grid_t, grid_st) * block_size();
-        HIPCHK(ctx, ctx->gstack.ensure(gthreads * kGlobalStack * sizeof(int32_t)));
-        Work<R> w{};
-        char *pb = nullptr;
-        auto take = [&](size_t bytes) { char *r = pb; pb += (bytes + 255) / 256 * 256; return r; };
-        pb = ctx->pool.as<char>();
-        for (int q = 0; q < 2; ++q) {
-            Pool<R> &P = w.p[q];
-            P.ox = (R *)take(plane); P.oy = (R *)take(plane); P.oz = (R *)take(plane);
-            P.dx = (R *)take(plane); P.dy = (R *)take(plane); P.dz = (R *)take(plane);
-            P.pix = (uint32_t *)take((size_t)cap * 4); P.smp = (uint32_t *)take((size_t)cap * 4);
-            P.aux = (uint32_t *)take((size_t)cap * 4); P.skip = (int32_t *)take((size_t)cap * 4);
-            P.beta = (R *)take((size_t)cap * nb * sizeof(R));
-        }
-        pb = ctx->hits.as<char>();
-        w.ht = (R *)take(plane); w.hu = (R *)take(plane); w.hv = (R *)take(plane);
-        w.htri = (int32_t *)take((size_t)cap * 4);
-        w.gidx = (uint32_t *)take((size_t)cap * 4);
-        if (surr) {
-            HIPCHK(ctx, ctx->bubq.ensure((size_t)cap * nb * sizeof(R) + plane + 1024));
-            pb = ctx->bubq.as<char>();
-            w.bratio = (R *)take((size_t)cap * nb * sizeof(R));
-            w.bw = (R *)take(plane);
-        }
-        pb = ctx->shadowq.as<char>();
-        w.sx = (R *)take(plane); w.sy = (R *)take(plane); w.sz = (R *)take(plane);
-        w.sskip = (int32_t *)take((size_t)cap * 4); w.spix = (uint32_t *)take((size_t)cap * 4);
-        w.saux = (uint32_t *)take((size_t)cap * 4); w.socc = (int32_t *)take((size_t)cap * 4);
-        w.contrib = (R *)take((size_t)cap * nb * sizeof(R));
-        w.sg_leaf = (int32_t *)take((size_t)cap * kMaxGlass * 4);
-        w.sg_u = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
-        w.sg_v = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
-        w.acc = ctx->acc.as<double>();
-        w.cnt = ctx->counters.as<Counters>();
-        w.cap = cap;
-        w.nbmax = nb;
-        w.gstack = ctx->gstack.as<int32_t>();
-
-        Timer tm{ctx, s, p->timing != 0};
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        HIPCHK(ctx, hipEventCreate(&ev0));
-        HIPCHK(ctx, hipEventCreate(&ev1));
-        HIPCHK(ctx, hipEventRecord(ev0, s));
-        launch_zero_f64(w.acc, npix * nl, s);
-        launch_zero_counters(w.cnt, s);
-        const JobDev *jobs_d = ctx->jobs.as<JobDev>();
-        const BandDev *bands_d = ctx->bands.as<BandDev>();
-        uint64_t n_chunks = 0;
-        for (uint64_t r0 = 0; r0 < total; r0 += chunk) {
-            const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, total - r0);
-            int cur = 0;
-            HIPCHK(ctx, tm.begin(SDM_K_GENERATE));
-            launch_generate<R>(jobs_d, bands_d, ctx->items.as<ItemDev>(), (int)plan.items.size(), w, r0, n, grid_g, s);
-            HIPCHK(ctx, tm.end());
-            for (int dpt = 0; dpt < p->max_depth; ++dpt) {
-                HIPCHK(ctx, tm.begin(SDM_K_TRACE));
-                launch_trace<R>(jobs_d, w, cur, 0, grid_t, s);
-                HIPCHK(ctx, tm.end());
-                HIPCHK(ctx, tm.begin(SDM_K_SHADE));
-                launch_shade<R>(jobs_d, bands_d, w, cur, grid_s, s);
-                HIPCHK(ctx, tm.end());
-                HIPCHK(ctx, tm.begin(SDM_K_SHADE_GLASS));
-                launch_shade_glass<R>(jobs_d, bands_d, w, cur, grid_s, s);
-                HIPCHK(ctx, tm.end());
-                if (surr) {
-                    HIPCHK(ctx, tm.begin(SDM_K_BUBBLY_EVAL));
-                    launch_bubbly_eval<R>(jobs_d, bands_d, w, cur, p->mlp->wb.p, p->mlp->bb.as<float>(),
-                                          p->mlp->params.as<float>(),
-                                          p->mlp->params.as<float>() + mlp_net_params(),
-                                          ctx->num_cu * (sizeof(R) == 4 ? 2 : 4), s);
-                    HIPCHK(ctx, tm.end());
-                }
-                if (bubbly) {
-                    HIPCHK(ctx, tm.begin(SDM_K_SHADE_BUBBLY));
-                    launch_shade_bubbly<R>(jobs_d, bands_d, w, cur, grid_s, s);
-                    HIPCHK(ctx, tm.end());
-                }
-                HIPCHK(ctx, tm.begin(SDM_K_SHADOW));
-                launch_shadow_trace<R>(jobs_d, bands_d, w, 0, grid_st, s);
-                HIPCHK(ctx, tm.end());
-                HIPCHK(ctx, tm.begin(SDM_K_SHADOW_ACCUM));
-                launch_shadow_accum<R>(jobs_d, bands_d, w, grid_s, s);
-                HIPCHK(ctx, tm.end());
-                cur ^= 1;
-            }
-            ++n_chunks;
-        }
-        HIPCHK(ctx, hipGetLastError());
-        // finalize into device outputs (or staging for host outputs)
-        float *spec_d = nullptr;
-        double *xyz_d = nullptr;
-        const bool spec_host = out->spectral && out->spectral_mem == SDM_MEM_HOST;
-        const bool xyz_host = out->xyz && out->xyz_mem == SDM_MEM_HOST;
-        const size_t spec_b = (size_t)npix * nl * sizeof(float), xyz_b = (size_t)npix * 3 * sizeof(double);
-        if (spec_host || xyz_host) HIPCHK(ctx, ctx->outs.ensure(spec_b + xyz_b + 256));
-        if (out->spectral) spec_d = spec_host ? ctx->outs.as<float>() : out->spectral;
-        if (out->xyz)
-            xyz_d = xyz_host ? reinterpret_cast<double *>(ctx->outs.as<char>() + ((spec_b + 255) / 256) * 256)
-                             : out->xyz;
-        HIPCHK(ctx, tm.begin(SDM_K_FINALIZE));
-        launch_finalize(w.acc, npix, nl, p->spp, wts_d, cmf_d, spec_d, p->cmf_xyz ? xyz_d : nullptr, s);
-        HIPCHK(ctx, tm.end());
-        HIPCHK(ctx, hipEventRecord(ev1, s));
-        HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        if (spec_host) HIPCHK(ctx, hipMemcpyAsync(out->spectral, spec_d, spec_b, hipMemcpyDeviceToHost, s));
-        if (xyz_host && p->cmf_xyz) HIPCHK(ctx, hipMemcpyAsync(out->xyz, xyz_d, xyz_b, hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        const Counters c = *ctx->host_counters;
-        if (c.overflow & 2u) {
-            (void)hipEventDestroy(ev0);
-            (void)hipEventDestroy(ev1);
-            return fail(ctx, SDM_E_UNSUPPORTED, "a shadow ray crossed more than %d glass panes", kMaxGlass);
-        }
-        if (c.overflow) {
-            (void)hipEventDestroy(ev0);
-            (void)hipEventDestroy(ev1);
-            if (++attempt > 8)
-                return fail(ctx, SDM_E_DEVICE, "path pool overflow: glass forks exceed %llu slots",
-                            (unsigned long long)cap64);
-            continue;  // deterministic: render again with a larger pool
-        }
-        if (out->stats) {
-            sdm_stats &st = *out->stats;
-            std::memset(&st, 0, sizeof(st));
-            st.spectral_samples = (uint64_t)npix * p->spp * nl;
-            st.paths = total;
-            st.closest_segments = c.closest;
-            st.shadow_segments = c.shadow;
-            st.forks = c.forks;
-            st.bubbly_vertices = c.bubbly;
-            st.chunks = n_chunks;
-            for (int q = 0; q < 2; ++q) {
-                st.nodes_visited[q] = c.nodes[q];
-                st.tris_tested[q] = c.tris[q];
-            }
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, ev0, ev1);
-            st.ms_render = ms;
-            if (tm.on)
-                for (auto &mk : tm.marks) {
-                    float km = 0;
-                    (void)hipEventElapsedTime(&km, ctx->events[mk.second], ctx->events[mk.second + 1]);
-                    st.kernel_ms[mk.first] += km;
-                    st.kernel_launches[mk.first] += 1;
-                }
-        }
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
-        return SDM_OK;
-    }
-}
-
-}  // namespace
-
 extern "C" {
-
-int sdm_render(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p, const sdm_outputs *out,
-               void *hip_stream)
-{
-    if (!ctx) return SDM_E_INVALID;
-    if (!sc || !out) return fail(ctx, SDM_E_INVALID, "null scene or outputs");
-    if (sc->ctx != ctx) return fail(ctx, SDM_E_INVALID, "scene belongs to another context");
-    int rc = validate_params(ctx, p);
-    if (rc) return rc;
-    rc = validate_btdf(ctx, sc, p);
-    if (rc) return rc;
-    if (out->spectral && out->spectral_mem == SDM_MEM_DEVICE && !ptr_is_device(out->spectral))
-        return fail(ctx, SDM_E_INVALID, "spectral output is not device memory");
-    if (out->xyz && out->xyz_mem == SDM_MEM_DEVICE && !ptr_is_device(out->xyz))
-        return fail(ctx, SDM_E_INVALID, "xyz output is not device memory");
-    HIPCHK(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)hip_stream;
-    if (p->precision == SDM_PREC_FP64) return render_impl<double>(ctx, sc, p, out, s);
-    return render_impl<float>(ctx, sc, p, out, s);
-}
 
 int sdm_slab_eval(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm, const float *d_mm,
                   const float *n, const float *k, const float *alpha_tint, float *R, float *T, void *hip_stream)

@@ -1,0 +1,740 @@
+// render.cpp -- the render runtime behind sdm_render: work planning (spectral
+// bands x pixel tiles, Sec. 4 and 5), per-render tables, the wavefront chunk
+// loop and its kernel sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/sdm.h"
+#include "runtime.hpp"
+#include "sdm_types.hpp"
+#include "surrogate.hpp"
+#include "wavefront.hpp"
+
+using namespace sdm;
+using namespace sdm_rt;
+
+// ---------------------------------------------------------------------------
+// Render
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Plan {
+    std::vector<BandDev> bands;
+    std::vector<ItemDev> items;
+    uint64_t total_rays = 0;
+    int nbmax = 0;
+};
+
+int plan_work(sdm_context *ctx, const sdm_render_params *p, int job, int tw, int th, Plan &plan)
+{
+    const int nl = p->n_lambda;
+    std::vector<int> edges;
+    if (p->band_edges) {
+        edges.assign(p->band_edges, p->band_edges + p->n_bands + 1);
+        if (edges.front() != 0 || edges.back() != nl)
+            return fail(ctx, SDM_E_INVALID, "band_edges must start at 0 and end at n_lambda");
+        for (int b = 0; b < p->n_bands; ++b)
+            if (edges[b + 1] <= edges[b]) return fail(ctx, SDM_E_INVALID, "band_edges must increase");
+    } else {
+        // contiguous bands, the first nl mod B one wavelength larger
+        const int B = p->n_bands, base = nl / B, extra = nl % B;
+        edges.push_back(0);
+        for (int b = 0; b < B; ++b) edges.push_back(edges.back() + base + (b < extra ? 1 : 0));
+    }
+    const int b0 = (int)plan.bands.size();
+    for (size_t b = 0; b + 1 < edges.size(); ++b) {
+        const int nb = edges[b + 1] - edges[b];
+        if (nb > kMaxBand) return fail(ctx, SDM_E_UNSUPPORTED, "a band holds %d > %d wavelengths", nb, kMaxBand);
+        plan.bands.push_back(BandDev{job, edges[b], nb, 0});
+        plan.nbmax = std::max(plan.nbmax, nb);
+    }
+    if ((int)plan.bands.size() >= (1 << kAuxBandBits)) return fail(ctx, SDM_E_UNSUPPORTED, "too many bands");
+    const int W = p->camera.W, H = p->camera.H;
+    for (int y0 = 0; y0 < H; y0 += th)
+        for (int x0 = 0; x0 < W; x0 += tw)
+            for (int b = b0; b < (int)plan.bands.size(); ++b) {
+                ItemDev it{};
+                it.band = b;
+                it.x0 = x0;
+                it.y0 = y0;
+                it.tw = std::min(tw, W - x0);
+                it.th = std::min(th, H - y0);
+                it.s0 = 0;
+                it.ns = p->spp;
+                it.first = plan.total_rays;
+                plan.total_rays += (uint64_t)it.tw * it.th * it.ns;
+                plan.items.push_back(it);
+            }
+    return SDM_OK;
+}
+
+int validate_params(sdm_context *ctx, const sdm_render_params *p)
+{
+    if (!p) return fail(ctx, SDM_E_INVALID, "null render parameters");
+    const sdm_camera &c = p->camera;
+    if (c.W < 1 || c.H < 1 || (int64_t)c.W * c.H > (1ll << 31))
+        return fail(ctx, SDM_E_INVALID, "image size %d x %d out of range", c.W, c.H);
+    if (p->spp < 1 || p->spp > 65535) return fail(ctx, SDM_E_INVALID, "spp must be in [1, 65535]");
+    if (p->max_depth < 1 || p->max_depth > 255) return fail(ctx, SDM_E_INVALID, "max_depth must be in [1, 255]");
+    if (p->n_lambda < 1 || !p->lambda_nm) return fail(ctx, SDM_E_INVALID, "need n_lambda >= 1 wavelengths");
+    if (p->n_bands < 1 || p->n_bands > p->n_lambda)
+        return fail(ctx, SDM_E_INVALID, "n_bands must be in [1, n_lambda]");
+    if (c.projection != SDM_PINHOLE && c.projection != SDM_ORTHO)
+        return fail(ctx, SDM_E_INVALID, "unknown projection");
+    if (p->precision != SDM_PREC_FP32 && p->precision != SDM_PREC_FP64)
+        return fail(ctx, SDM_E_INVALID, "unknown precision");
+    if (p->btdf_mode != SDM_BTDF_EXACT && p->btdf_mode != SDM_BTDF_SURROGATE && p->btdf_mode != SDM_BTDF_FALLBACK)
+        return fail(ctx, SDM_E_INVALID, "unknown btdf_mode");
+    return SDM_OK;
+}
+
+// Network and error table of the bubbly panes of a scene (none needed for
+// exact walks or scenes without bubbly panes).
+int validate_btdf(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p)
+{
+    if (sc->max_pane < 0 || p->btdf_mode == SDM_BTDF_EXACT) return SDM_OK;
+    if (!p->mlp) return fail(ctx, SDM_E_INVALID, "surrogate modes need a network (mlp)");
+    if (p->mlp->ctx != ctx) return fail(ctx, SDM_E_INVALID, "the network belongs to another context");
+    if (sc->max_pane >= p->mlp->n_panes)
+        return fail(ctx, SDM_E_INVALID, "pane type %d is beyond the network's %d embeddings", sc->max_pane,
+                    p->mlp->n_panes);
+    if (p->btdf_mode == SDM_BTDF_FALLBACK) {
+        if (!p->err_table) return fail(ctx, SDM_E_INVALID, "fallback mode needs an error table");
+        for (int a = 0; a < 3; ++a)
+            if (p->err_dims[a] < 1 || p->err_dims[a] > 1024)
+                return fail(ctx, SDM_E_INVALID, "err_dims must be in [1, 1024]");
+        if ((int64_t)p->err_dims[0] * p->err_dims[1] * p->err_dims[2] > (1 << 20))
+            return fail(ctx, SDM_E_INVALID, "error table too large");
+    }
+    return SDM_OK;
+}
+
+void camera_basis(const sdm_camera &c, JobDev &jb)
+{
+    double f[3], r[3], u[3];
+    for (int a = 0; a < 3; ++a) f[a] = (double)c.target[a] - c.eye[a];
+    auto nrm = [](double *v) {
+        double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (l > 0) for (int a = 0; a < 3; ++a) v[a] /= l;
+    };
+    nrm(f);
+    const double up[3] = {c.up[0], c.up[1], c.up[2]};
+    r[0] = f[1] * up[2] - f[2] * up[1];
+    r[1] = f[2] * up[0] - f[0] * up[2];
+    r[2] = f[0] * up[1] - f[1] * up[0];
+    nrm(r);
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    for (int a = 0; a < 3; ++a) {
+        jb.eye[a] = c.eye[a];
+        jb.f[a] = f[a];
+        jb.r[a] = r[a];
+        jb.u[a] = u[a];
+    }
+    jb.th = std::tan(0.5 * (double)c.vfov_deg * M_PI / 180.0);
+    jb.aspect = (double)c.W / (double)c.H;
+    jb.oh = 0.5 * (double)c.ortho_height;
+    jb.projection = c.projection;
+    jb.W = c.W;
+    jb.H = c.H;
+}
+
+struct Timer {
+    sdm_context *ctx;
+    hipStream_t s;
+    bool on;
+    size_t next = 0;
+    std::vector<std::pair<int, size_t>> marks;  // (kernel class, event index of start)
+    hipError_t begin(int cls)
+    {
+        if (!on) return hipSuccess;
+        if (next + 2 > ctx->events.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                ctx->events.push_back(e);
+            }
+        }
+        marks.push_back({cls, next});
+        hipError_t r = hipEventRecord(ctx->events[next], s);
+        next += 2;
+        return r;
+    }
+    hipError_t end()
+    {
+        if (!on) return hipSuccess;
+        return hipEventRecord(ctx->events[marks.back().second + 1], s);
+    }
+};
+
+struct JobIn {
+    const sdm_scene *sc;
+    const sdm_render_params *p;
+    const sdm_outputs *out;
+};
+
+// Tuned (chunk, tile) of the context for a job, or the library defaults.
+void job_shape(const sdm_context *ctx, const JobIn &j, uint64_t &chunk, int &tw, int &th)
+{
+    const sdm_render_params *p = j.p;
+    chunk = p->chunk_paths > 0 ? (uint64_t)p->chunk_paths : 0;
+    tw = p->tile_w;
+    th = p->tile_h;
+    if (chunk == 0 && tw <= 0 && th <= 0)
+        for (const auto &t : ctx->tuned)
+            if (t.scene == j.sc && t.W == p->camera.W && t.H == p->camera.H && t.nl == p->n_lambda &&
+                t.depth == p->max_depth && t.precision == p->precision) {
+                chunk = (uint64_t)t.chunk;
+                tw = t.tw;
+                th = t.th;
+            }
+    if (chunk == 0) chunk = (uint64_t)1 << 21;
+    if (tw <= 0) tw = 16;
+    if (th <= 0) th = 16;
+}
+
+// Launch arguments of one chunk's kernel sequence; a cached graph is reused
+// while they are unchanged.
+template <class R>
+struct ChunkArgs {
+    Work<R> w;
+    const JobDev *jobs;
+    const BandDev *bands;
+    const ItemDev *items;
+    const void *wb;
+    const float *bb, *params, *E;
+    uint64_t total;
+    uint32_t chunk;
+    int32_t n_items, depth, lds_job, surr, bubbly, grid_t, grid_st, grid_s, grid_g, grid_e, prec;
+};
+
+template <class R>
+void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
+{
+    auto mark = [&](int cls) { if (tm) (void)tm->begin(cls); };
+    auto done = [&]() { if (tm) (void)tm->end(); };
+    int cur = 0;
+    mark(SDM_K_GENERATE);
+    launch_generate<R>(a.jobs, a.bands, a.items, a.n_items, a.w, a.total, a.chunk, a.grid_g, s);
+    done();
+    for (int dpt = 0; dpt < a.depth; ++dpt) {
+        mark(SDM_K_TRACE);
+        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, a.grid_t, s);
+        done();
+        mark(SDM_K_SHADE);
+        launch_shade<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
+        done();
+        mark(SDM_K_SHADE_GLASS);
+        launch_shade_glass<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
+        done();
+        if (a.surr) {
+            mark(SDM_K_BUBBLY_EVAL);
+            launch_bubbly_eval<R>(a.jobs, a.bands, a.w, cur, a.wb, a.bb, a.params, a.E, a.grid_e, s);
+            done();
+        }
+        if (a.bubbly) {
+            mark(SDM_K_SHADE_BUBBLY);
+            launch_shade_bubbly<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
+            done();
+        }
+        mark(SDM_K_SHADOW);
+        launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.grid_st, s);
+        done();
+        mark(SDM_K_SHADOW_ACCUM);
+        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.grid_s, s);
+        done();
+        cur ^= 1;
+    }
+    launch_advance_cursor(a.w.cnt, a.chunk, s);
+}
+
+// All chunks on the context's graph stream: capture one chunk's sequence
+// once (or reuse the cached graph) and launch it n_chunks times; the
+// caller's stream and the graph stream are ordered by events.
+template <class R>
+int run_graph(sdm_context *ctx, const ChunkArgs<R> &a, uint64_t n_chunks, hipStream_t s)
+{
+    const unsigned char *kb = reinterpret_cast<const unsigned char *>(&a);
+    std::vector<unsigned char> key(kb, kb + sizeof(a));
+    if (!ctx->gexec || key != ctx->gkey) {
+        if (ctx->gexec) {
+            HIPCHK(ctx, hipGraphExecDestroy(ctx->gexec));
+            ctx->gexec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+        enqueue_chunk<R>(a, ctx->gstream, nullptr);
+        HIPCHK(ctx, hipStreamEndCapture(ctx->gstream, &g));
+        const hipError_t e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ctx->gexec = nullptr;
+            return fail(ctx, SDM_E_DEVICE, "graph instantiation: %s", hipGetErrorString(e));
+        }
+        ctx->gkey.swap(key);
+    }
+    HIPCHK(ctx, hipEventRecord(ctx->join[0], s));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->gstream, ctx->join[0], 0));
+    for (uint64_t c = 0; c < n_chunks; ++c) HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->gstream));
+    HIPCHK(ctx, hipEventRecord(ctx->join[1], ctx->gstream));
+    HIPCHK(ctx, hipStreamWaitEvent(s, ctx->join[1], 0));
+    return SDM_OK;
+}
+
+// Per-job device tables: [R: rho, n, k, tint (n_mat x nl each), E, Lsky,
+// lambda][lambda float][trapezoid weights double][observer double].
+struct TableLayout {
+    size_t off, off_lamf, off_w, off_c, end;
+};
+
+TableLayout table_layout(size_t base, int nm, int nl, size_t rsize)
+{
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    TableLayout t;
+    t.off = up(base);
+    t.off_lamf = t.off + up((4 * (size_t)nm * nl + 3 * (size_t)nl) * rsize);
+    t.off_w = t.off_lamf + up(nl * sizeof(float));
+    t.off_c = t.off_w + up(nl * sizeof(double));
+    t.end = t.off_c + 3 * nl * sizeof(double);
+    return t;
+}
+
+template <class R>
+int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s)
+{
+    const int nj = (int)jobs.size();
+    const sdm_render_params *p0 = jobs[0].p;
+    Plan plan;
+    uint64_t chunk = 0;
+    int depth = 0;
+    std::vector<int64_t> acc_off(nj + 1, 0);
+    for (int j = 0; j < nj; ++j) {
+        uint64_t ch;
+        int tw, th;
+        job_shape(ctx, jobs[j], ch, tw, th);
+        if (j == 0) chunk = ch;
+        if (int rc = plan_work(ctx, jobs[j].p, j, tw, th, plan)) return rc;
+        depth = std::max(depth, jobs[j].p->max_depth);
+        acc_off[j + 1] = acc_off[j] + (int64_t)jobs[j].p->camera.W * jobs[j].p->camera.H * jobs[j].p->n_lambda;
+    }
+    // tables of every job
+    std::vector<TableLayout> lay(nj);
+    size_t tab_bytes = 0;
+    for (int j = 0; j < nj; ++j) {
+        lay[j] = table_layout(tab_bytes, jobs[j].sc->n_mat, jobs[j].p->n_lambda, sizeof(R));
+        tab_bytes = lay[j].end;
+    }
+    HIPCHK(ctx, ctx->tables.ensure(tab_bytes));
+    // network and error tables (one network per batch)
+    const sdm_mlp *net = nullptr;
+    bool bubbly = false, surr = false;
+    size_t err_elems = 0;
+    for (const auto &j : jobs) {
+        if (j.sc->max_pane < 0) continue;
+        bubbly = true;
+        if (j.p->btdf_mode == SDM_BTDF_EXACT) continue;
+        surr = true;
+        if (net && net != j.p->mlp) return fail(ctx, SDM_E_INVALID, "the jobs of a batch must share one network");
+        net = j.p->mlp;
+        if (j.p->btdf_mode == SDM_BTDF_FALLBACK)
+            err_elems += (size_t)net->n_panes * j.p->err_dims[0] * j.p->err_dims[1] * j.p->err_dims[2];
+    }
+    if (err_elems) HIPCHK(ctx, ctx->errtab.ensure(err_elems * sizeof(float)));
+    std::vector<JobDev> jd(nj);
+    size_t err_pos = 0;
+    for (int j = 0; j < nj; ++j) {
+        const sdm_scene *sc = jobs[j].sc;
+        const sdm_render_params *p = jobs[j].p;
+        const int nl = p->n_lambda, nm = sc->n_mat;
+        char *tb = ctx->tables.as<char>();
+        R *tR = reinterpret_cast<R *>(tb + lay[j].off);
+        float *lamf = reinterpret_cast<float *>(tb + lay[j].off_lamf);
+        double *wts_d = reinterpret_cast<double *>(tb + lay[j].off_w);
+        double *cmf_d = reinterpret_cast<double *>(tb + lay[j].off_c);
+        std::vector<double> wts(nl), cmf(3 * (size_t)nl, 0.0);
+        if (nl == 1) wts[0] = 1.0;
+        else
+            for (int i = 0; i < nl; ++i)
+                wts[i] = 0.5 * ((double)p->lambda_nm[std::min(i + 1, nl - 1)] - p->lambda_nm[std::max(i - 1, 0)]);
+        if (p->cmf_xyz)
+            for (size_t i = 0; i < 3 * (size_t)nl; ++i) cmf[i] = p->cmf_xyz[i];
+        HIPCHK(ctx, hipMemcpyAsync(lamf, p->lambda_nm, nl * sizeof(float), hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemcpyAsync(wts_d, wts.data(), nl * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemcpyAsync(cmf_d, cmf.data(), 3 * nl * sizeof(double), hipMemcpyHostToDevice, s));
+        // the host vectors must outlive the asynchronous copies
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lamf, nl, tR, s);
+        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sun.as<float>(), 1, lamf, nl,
+                           tR + 4 * (size_t)nm * nl, s);
+        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sky.as<float>(), 1, lamf, nl,
+                           tR + 4 * (size_t)nm * nl + nl, s);
+        launch_resample<R>(lamf, nl, lamf, 1, lamf, nl, tR + 4 * (size_t)nm * nl + 2 * nl, s);
+        JobDev &jb = jd[j];
+        jb = JobDev{};
+        jb.sc = sc->dev;
+        camera_basis(p->camera, jb);
+        jb.spp = p->spp;
+        jb.nl = nl;
+        jb.max_depth = p->max_depth;
+        jb.seed = p->seed;
+        jb.job_word = p->job_id;
+        jb.acc_off = (uint64_t)acc_off[j];
+        jb.rho = tR;
+        jb.n = tR + (size_t)nm * nl;
+        jb.k = tR + 2 * (size_t)nm * nl;
+        jb.tint = tR + 3 * (size_t)nm * nl;
+        jb.E = tR + 4 * (size_t)nm * nl;
+        jb.Lsky = tR + 4 * (size_t)nm * nl + nl;
+        jb.lam = tR + 4 * (size_t)nm * nl + 2 * nl;
+        jb.beta_thr = p->beta_threshold;
+        jb.btdf_mode = p->btdf_mode;
+        jb.err_bound = p->err_bound;
+        if (sc->max_pane >= 0 && p->btdf_mode == SDM_BTDF_FALLBACK) {
+            const size_t ncell = (size_t)net->n_panes * p->err_dims[0] * p->err_dims[1] * p->err_dims[2];
+            HIPCHK(ctx, hipMemcpyAsync(ctx->errtab.as<float>() + err_pos, p->err_table, ncell * sizeof(float),
+                                       hipMemcpyHostToDevice, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            for (int a = 0; a < 3; ++a) jb.err_dims[a] = p->err_dims[a];
+            jb.err_table = ctx->errtab.as<float>() + err_pos;
+            err_pos += ncell;
+        }
+    }
+    HIPCHK(ctx, hipGetLastError());
+    if (surr) launch_mlp_pack(net->params.as<float>(), net->wb.p, net->bb.as<float>(), s);
+    HIPCHK(ctx, upload(ctx->jobs, jd.data(), jd.size(), s));
+    HIPCHK(ctx, upload(ctx->bands, plan.bands.data(), plan.bands.size(), s));
+    HIPCHK(ctx, upload(ctx->items, plan.items.data(), plan.items.size(), s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+
+    const uint64_t total = plan.total_rays;
+    chunk = std::max<uint64_t>(1, std::min<uint64_t>(chunk, total));
+    const bool timing = p0->timing != 0;
+    const bool graph = p0->graph != 0 && !timing;
+    int attempt = 0;
+    for (;;) {
+        // pool capacity: the chunk plus headroom for forks (doubled on overflow)
+        const uint64_t cap64 = ((chunk + (chunk >> 2) * (1ull << attempt) + 1024 + 63) / 64) * 64;
+        if (cap64 >= (1ull << 31)) return fail(ctx, SDM_E_NOMEM, "path pool would exceed 2^31 slots");
+        const uint32_t cap = (uint32_t)cap64;
+        const int nb = plan.nbmax;
+        const size_t plane = (size_t)cap * sizeof(R);
+        const size_t pool_b = 6 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R);
+        const size_t hit_b = 3 * plane + 2 * (size_t)cap * 4;
+        const size_t sh_b = 3 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
+                            (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R));
+        HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
+        HIPCHK(ctx, ctx->hits.ensure(hit_b + 2048));
+        HIPCHK(ctx, ctx->shadowq.ensure(sh_b + 2048));
+        HIPCHK(ctx, ctx->acc.ensure((size_t)acc_off[nj] * sizeof(double)));
+        HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
+        ChunkArgs<R> a{};
+        a.grid_t = ctx->num_cu * occupancy_trace<R>();
+        a.grid_st = ctx->num_cu * occupancy_shadow<R>();
+        a.grid_s = ctx->num_cu * occupancy_shade<R>();
+        a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
+        a.grid_e = ctx->num_cu * (sizeof(R) == 4 ? 2 : 4);
+        const size_t gthreads = (size_t)std::max(a.grid_t, a.grid_st) * block_size();
+        HIPCHK(ctx, ctx->gstack.ensure(gthreads * kGlobalStack * sizeof(int32_t)));
+        Work<R> &w = a.w;
+        char *pb = nullptr;
+        auto take = [&](size_t bytes) { char *r = pb; pb += (bytes + 255) / 256 * 256; return r; };
+        pb = ctx->pool.as<char>();
+        for (int q = 0; q < 2; ++q) {
+            Pool<R> &P = w.p[q];
+            P.ox = (R *)take(plane); P.oy = (R *)take(plane); P.oz = (R *)take(plane);
+            P.dx = (R *)take(plane); P.dy = (R *)take(plane); P.dz = (R *)take(plane);
+            P.pix = (uint32_t *)take((size_t)cap * 4); P.smp = (uint32_t *)take((size_t)cap * 4);
+            P.aux = (uint32_t *)take((size_t)cap * 4); P.skip = (int32_t *)take((size_t)cap * 4);
+            P.beta = (R *)take((size_t)cap * nb * sizeof(R));
+        }
+        pb = ctx->hits.as<char>();
+        w.ht = (R *)take(plane); w.hu = (R *)take(plane); w.hv = (R *)take(plane);
+        w.htri = (int32_t *)take((size_t)cap * 4);
+        w.gidx = (uint32_t *)take((size_t)cap * 4);
+        if (surr) {
+            HIPCHK(ctx, ctx->bubq.ensure((size_t)cap * nb * sizeof(R) + plane + 1024));
+            pb = ctx->bubq.as<char>();
+            w.bratio = (R *)take((size_t)cap * nb * sizeof(R));
+            w.bw = (R *)take(plane);
+        }
+        pb = ctx->shadowq.as<char>();
+        w.sx = (R *)take(plane); w.sy = (R *)take(plane); w.sz = (R *)take(plane);
+        w.sskip = (int32_t *)take((size_t)cap * 4); w.spix = (uint32_t *)take((size_t)cap * 4);
+        w.saux = (uint32_t *)take((size_t)cap * 4); w.socc = (int32_t *)take((size_t)cap * 4);
+        w.contrib = (R *)take((size_t)cap * nb * sizeof(R));
+        w.sg_leaf = (int32_t *)take((size_t)cap * kMaxGlass * 4);
+        w.sg_u = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
+        w.sg_v = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
+        w.acc = ctx->acc.as<double>();
+        w.cnt = ctx->counters.as<Counters>();
+        w.cap = cap;
+        w.nbmax = nb;
+        w.gstack = ctx->gstack.as<int32_t>();
+        a.jobs = ctx->jobs.as<JobDev>();
+        a.bands = ctx->bands.as<BandDev>();
+        a.items = ctx->items.as<ItemDev>();
+        a.n_items = (int32_t)plan.items.size();
+        a.total = total;
+        a.chunk = (uint32_t)chunk;
+        a.depth = depth;
+        a.lds_job = nj == 1 ? 0 : -2;   // a batch stages the BVH of each chunk's first job
+        a.surr = surr;
+        a.bubbly = bubbly;
+        a.prec = sizeof(R) == 8;
+        if (surr) {
+            a.wb = net->wb.p;
+            a.bb = net->bb.as<float>();
+            a.params = net->params.as<float>();
+            a.E = net->params.as<float>() + mlp_net_params();
+        }
+        const uint64_t n_chunks = (total + chunk - 1) / chunk;
+
+        Timer tm{ctx, s, timing};
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        HIPCHK(ctx, hipEventCreate(&ev0));
+        HIPCHK(ctx, hipEventCreate(&ev1));
+        HIPCHK(ctx, hipEventRecord(ev0, s));
+        launch_zero_f64(w.acc, acc_off[nj], s);
+        launch_zero_counters(w.cnt, s);
+        if (graph) {
+            if (int rc = run_graph<R>(ctx, a, n_chunks, s)) return rc;
+        } else {
+            for (uint64_t c = 0; c < n_chunks; ++c) enqueue_chunk<R>(a, s, timing ? &tm : nullptr);
+        }
+        HIPCHK(ctx, hipGetLastError());
+        // finalize every job into device outputs (or staging for host outputs)
+        size_t stage_b = 0;
+        for (const auto &j : jobs) {
+            const size_t npix = (size_t)j.p->camera.W * j.p->camera.H;
+            if (j.out->spectral && j.out->spectral_mem == SDM_MEM_HOST)
+                stage_b += (npix * j.p->n_lambda * sizeof(float) + 255) / 256 * 256;
+            if (j.out->xyz && j.out->xyz_mem == SDM_MEM_HOST) stage_b += (npix * 3 * sizeof(double) + 255) / 256 * 256;
+        }
+        if (stage_b) HIPCHK(ctx, ctx->outs.ensure(stage_b));
+        size_t stage_pos = 0;
+        struct Copy { void *dst; const void *src; size_t bytes; };
+        std::vector<Copy> copies;
+        for (int j = 0; j < nj; ++j) {
+            const sdm_render_params *p = jobs[j].p;
+            const sdm_outputs *out = jobs[j].out;
+            const int64_t npix = (int64_t)p->camera.W * p->camera.H;
+            const int nl = p->n_lambda;
+            float *spec_d = nullptr;
+            double *xyz_d = nullptr;
+            const size_t spec_b = (size_t)npix * nl * sizeof(float), xyz_b = (size_t)npix * 3 * sizeof(double);
+            if (out->spectral) {
+                if (out->spectral_mem == SDM_MEM_HOST) {
+                    spec_d = reinterpret_cast<float *>(ctx->outs.as<char>() + stage_pos);
+                    stage_pos += (spec_b + 255) / 256 * 256;
+                    copies.push_back({out->spectral, spec_d, spec_b});
+                } else {
+                    spec_d = out->spectral;
+                }
+            }
+            if (out->xyz && p->cmf_xyz) {
+                if (out->xyz_mem == SDM_MEM_HOST) {
+                    xyz_d = reinterpret_cast<double *>(ctx->outs.as<char>() + stage_pos);
+                    stage_pos += (xyz_b + 255) / 256 * 256;
+                    copies.push_back({out->xyz, xyz_d, xyz_b});
+                } else {
+                    xyz_d = out->xyz;
+                }
+            }
+            const char *tb = ctx->tables.as<char>();
+            if (timing) HIPCHK(ctx, tm.begin(SDM_K_FINALIZE));
+            launch_finalize(w.acc + acc_off[j], npix, nl, p->spp,
+                            reinterpret_cast<const double *>(tb + lay[j].off_w),
+                            reinterpret_cast<const double *>(tb + lay[j].off_c), spec_d, xyz_d, s);
+            if (timing) HIPCHK(ctx, tm.end());
+        }
+        HIPCHK(ctx, hipEventRecord(ev1, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        for (const auto &c : copies) HIPCHK(ctx, hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        const Counters c = *ctx->host_counters;
+        if (c.overflow & 2u) {
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
+            return fail(ctx, SDM_E_UNSUPPORTED, "a shadow ray crossed more than %d glass panes", kMaxGlass);
+        }
+        if (c.overflow) {
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
+            if (++attempt > 8)
+                return fail(ctx, SDM_E_DEVICE, "path pool overflow: glass forks exceed %llu slots",
+                            (unsigned long long)cap64);
+            continue;  // deterministic: render again with a larger pool
+        }
+        if (stats) {
+            sdm_stats &st = *stats;
+            std::memset(&st, 0, sizeof(st));
+            for (const auto &j : jobs)
+                st.spectral_samples += (uint64_t)j.p->camera.W * j.p->camera.H * j.p->spp * j.p->n_lambda;
+            st.paths = total;
+            st.closest_segments = c.closest;
+            st.shadow_segments = c.shadow;
+            st.forks = c.forks;
+            st.bubbly_vertices = c.bubbly;
+            st.chunks = n_chunks;
+            for (int q = 0; q < 2; ++q) {
+                st.nodes_visited[q] = c.nodes[q];
+                st.tris_tested[q] = c.tris[q];
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev0, ev1);
+            st.ms_render = ms;
+            if (tm.on)
+                for (auto &mk : tm.marks) {
+                    float km = 0;
+                    (void)hipEventElapsedTime(&km, ctx->events[mk.second], ctx->events[mk.second + 1]);
+                    st.kernel_ms[mk.first] += km;
+                    st.kernel_launches[mk.first] += 1;
+                }
+        }
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        return SDM_OK;
+    }
+}
+
+int check_job(sdm_context *ctx, const JobIn &j)
+{
+    if (!j.sc || !j.out) return fail(ctx, SDM_E_INVALID, "null scene or outputs");
+    if (j.sc->ctx != ctx) return fail(ctx, SDM_E_INVALID, "scene belongs to another context");
+    if (int rc = validate_params(ctx, j.p)) return rc;
+    if (int rc = validate_btdf(ctx, j.sc, j.p)) return rc;
+    if (j.out->spectral && j.out->spectral_mem == SDM_MEM_DEVICE && !ptr_is_device(j.out->spectral))
+        return fail(ctx, SDM_E_INVALID, "spectral output is not device memory");
+    if (j.out->xyz && j.out->xyz_mem == SDM_MEM_DEVICE && !ptr_is_device(j.out->xyz))
+        return fail(ctx, SDM_E_INVALID, "xyz output is not device memory");
+    return SDM_OK;
+}
+
+int render_any(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s)
+{
+    const int prec = jobs[0].p->precision;
+    for (const auto &j : jobs)
+        if (j.p->precision != prec) return fail(ctx, SDM_E_INVALID, "the jobs of a batch must share one precision");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (prec == SDM_PREC_FP64) return render_jobs<double>(ctx, jobs, stats, s);
+    return render_jobs<float>(ctx, jobs, stats, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdm_render(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p, const sdm_outputs *out,
+               void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    const JobIn j{sc, p, out};
+    if (!p) return fail(ctx, SDM_E_INVALID, "null render parameters");
+    if (int rc = check_job(ctx, j)) return rc;
+    return render_any(ctx, {j}, out->stats, (hipStream_t)hip_stream);
+}
+
+int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_stats *stats, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (n_jobs < 1 || !jobs) return fail(ctx, SDM_E_INVALID, "need at least one job");
+    if (n_jobs >= (1 << (32 - kAuxJobShift))) return fail(ctx, SDM_E_UNSUPPORTED, "too many jobs");
+    std::vector<JobIn> js;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        if (!jobs[i].params) return fail(ctx, SDM_E_INVALID, "job %d has no parameters", i);
+        js.push_back({jobs[i].scene, jobs[i].params, jobs[i].out});
+        if (int rc = check_job(ctx, js.back())) return rc;
+    }
+    return render_any(ctx, js, stats, (hipStream_t)hip_stream);
+}
+
+int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p, const char *cache_path,
+                 sdm_tune_result *res, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!sc || !p || !res) return fail(ctx, SDM_E_INVALID, "null argument");
+    if (sc->ctx != ctx) return fail(ctx, SDM_E_INVALID, "scene belongs to another context");
+    if (int rc = validate_params(ctx, p)) return rc;
+    if (int rc = validate_btdf(ctx, sc, p)) return rc;
+    std::memset(res, 0, sizeof(*res));
+    const int W = p->camera.W, H = p->camera.H;
+    char key[160];
+    snprintf(key, sizeof(key), "nt=%d nmat=%d W=%d H=%d nl=%d depth=%d prec=%d bands=%d", sc->nt, sc->n_mat, W, H,
+             p->n_lambda, p->max_depth, p->precision, p->n_bands);
+    bool found = false;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[256];
+            while (std::fgets(line, sizeof(line), f)) {
+                long long ch;
+                int tw, th;
+                double ms;
+                const size_t kl = std::strlen(key);
+                if (std::strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
+                    std::sscanf(line + kl, " -> chunk=%lld tile=%dx%d ms=%lf", &ch, &tw, &th, &ms) == 4) {
+                    res->chunk_paths = ch;
+                    res->tile_w = tw;
+                    res->tile_h = th;
+                    res->ms = ms;
+                    res->from_cache = 1;
+                    found = true;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    if (!found) {
+        // measure at reduced samples per pixel; outputs are not needed
+        sdm_render_params q = *p;
+        q.spp = std::max(1, p->spp / 8);
+        q.timing = 0;
+        q.graph = 0;
+        sdm_outputs none{};
+        sdm_stats st{};
+        none.stats = &st;
+        const long long chunks[3] = {1ll << 20, 1ll << 21, 1ll << 22};
+        const int tiles[3] = {8, 16, 32};
+        double best = 1e300;
+        for (long long ch : chunks)
+            for (int t : tiles) {
+                q.chunk_paths = ch;
+                q.tile_w = q.tile_h = t;
+                double ms = 1e300;
+                for (int rep = 0; rep < 2; ++rep) {
+                    const JobIn j{sc, &q, &none};
+                    if (int rc = render_any(ctx, {j}, &st, (hipStream_t)hip_stream)) return rc;
+                    ms = std::min(ms, st.ms_render);
+                }
+                if (ms < best) {
+                    best = ms;
+                    res->chunk_paths = ch;
+                    res->tile_w = res->tile_h = t;
+                    res->ms = ms;
+                }
+            }
+        if (cache_path)
+            if (FILE *f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "%s -> chunk=%lld tile=%dx%d ms=%.4f\n", key, (long long)res->chunk_paths,
+                             res->tile_w, res->tile_h, res->ms);
+                std::fclose(f);
+            }
+    }
+    auto &tv = ctx->tuned;
+    tv.erase(std::remove_if(tv.begin(), tv.end(),
+                            [&](const sdm_context::Tuned &t) {
+                                return t.scene == sc && t.W == W && t.H == H && t.nl == p->n_lambda &&
+                                       t.depth == p->max_depth && t.precision == p->precision;
+                            }),
+             tv.end());
+    tv.push_back({sc, W, H, p->n_lambda, p->max_depth, p->precision, res->chunk_paths, res->tile_w, res->tile_h});
+    return SDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// runtime.hpp -- host-side objects behind the C ABI handles (context, scene,
+// network) and the error helpers shared by the API translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sdm.h"
+#include "sdm_types.hpp"
+
+namespace sdm_rt {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t b)
+    {
+        if (b <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
+        if (e != hipSuccess) { p = nullptr; bytes = 0; return e; }
+        bytes = std::max<size_t>(b, 256);
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+    ~DevBuf() { release(); }
+};
+
+}  // namespace sdm_rt
+
+using sdm_rt::DevBuf;
+
+struct sdm_context {
+    int device = 0;
+    int num_cu = 0;
+    std::string err;
+    DevBuf gstack;
+    // render work buffers (one set; reallocated when a render needs more)
+    DevBuf pool, hits, shadowq, acc, counters, jobs, bands, items, tables, outs;
+    sdm::Counters *host_counters = nullptr;
+    std::vector<hipEvent_t> events;
+    DevBuf slab_tmp;
+    DevBuf mc_acc, flag;
+    DevBuf bubq, errtab;        // surrogate branch ratios and lobe widths; error table
+    // graph replay of a chunk's kernel sequence (on a stream of the context,
+    // default priority), cached while its launch arguments stay the same
+    hipStream_t gstream = nullptr;
+    hipEvent_t join[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey;
+    // autotuned (chunk, tile) per scene and render shape
+    struct Tuned {
+        const sdm_scene *scene;
+        int32_t W, H, nl, depth, precision;
+        int64_t chunk;
+        int32_t tw, th;
+    };
+    std::vector<Tuned> tuned;
+};
+
+struct sdm_mlp {
+    sdm_context *ctx = nullptr;
+    int32_t n_panes = 0;
+    int64_t P = 0;
+    int64_t t = 0;   // Adam steps taken
+    DevBuf params, m1, m2, grad, wb, bb, partial, loss_partial, loss;
+};
+
+struct sdm_scene {
+    sdm_context *ctx = nullptr;
+    sdm::SceneDev dev{};
+    DevBuf nodes, tris, thick, mat_type, mat_thick, mat_bub, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
+    int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
+    int32_t max_pane = -1;      // largest pane type of a bubbly material (-1: none)
+};
+
+namespace sdm_rt {
+
+// Records the message of a failure in the context and returns code.
+int fail(sdm_context *ctx, int code, const char *fmt, ...);
+bool ptr_is_device(const void *p);
+
+#define HIPCHK(ctx, x)                                                                            \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess)                                                                     \
+            return ::sdm_rt::fail(ctx, e_ == hipErrorOutOfMemory ? SDM_E_NOMEM : SDM_E_DEVICE,    \
+                                  "%s: %s", #x, hipGetErrorString(e_));                           \
+    } while (0)
+
+template <class T>
+hipError_t upload(DevBuf &b, const T *src, size_t n, hipStream_t s = nullptr)
+{
+    hipError_t e = b.ensure(n * sizeof(T));
+    if (e != hipSuccess || n == 0) return e;
+    return hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+}  // namespace sdm_rt

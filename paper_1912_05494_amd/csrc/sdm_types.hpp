@@ -84,6 +84,9 @@ struct Counters {
                                 // bit 1: a shadow ray crossed more than kMaxGlass panes
     uint32_t gcount;            // glass vertices queued for the glass shading pass
     uint32_t bcount;            // bubbly-glass vertices, queued from the back of gidx
+    unsigned long long r0;      // first primary path of the current chunk (advanced per chunk)
+    int32_t lds_job;            // job whose BVH prefix the traversal kernels stage in LDS
+    int32_t pad2;
     unsigned long long closest, shadow, forks, bubbly;
     unsigned long long nodes[2], tris[2];   // traversal work [closest, shadow]
 };

@@ -340,9 +340,21 @@ __device__ __forceinline__ void run_add_k(double *acc, uint64_t key0, int j, int
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const BandDev *bands,
                                                      const ItemDev *items, int32_t n_items, Work<R> w,
-                                                     uint64_t r0, uint32_t n)
+                                                     uint64_t total, uint32_t chunk)
 {
+    // the chunk starts at the device cursor, so every chunk launches the same
+    // kernel sequence with the same arguments (a graph replays it)
+    const uint64_t r0 = w.cnt->r0;
+    const uint32_t n = (uint32_t)min((uint64_t)chunk, total - min(r0, total));
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (n > 0) {
+            int lo = 0, hi = n_items - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (items[mid].first <= r0) lo = mid; else hi = mid - 1;
+            }
+            w.cnt->lds_job = bands[items[lo].band].job;
+        }
         w.cnt->count[0] = n;
         w.cnt->count[1] = 0;
         w.cnt->tfetch = 0;
@@ -396,6 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const B
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w, int cur, int lds_job)
 {
+    if (lds_job < -1) lds_job = w.cnt->lds_job;   // the job of the chunk's first path
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
@@ -1026,6 +1039,7 @@ template <class R>
 __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, const BandDev *bands, Work<R> w,
                                                          int lds_job)
 {
+    if (lds_job < -1) lds_job = w.cnt->lds_job;
     __shared__ float4 s_nodes[4 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const uint32_t count = min(w.cnt->scount, w.cap);
@@ -1221,9 +1235,16 @@ __global__ void k_zero_f64(double *a, int64_t n)
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0.0;
 }
 
+__global__ void k_advance_cursor(Counters *c, uint32_t chunk)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) c->r0 += chunk;
+}
+
 __global__ void k_zero_counters(Counters *c)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->r0 = 0;
+        c->lds_job = 0;
         c->count[0] = c->count[1] = 0;
         c->scount = 0;
         c->tfetch = c->sfetch = 0;
@@ -1379,9 +1400,9 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
 // ---------------------------------------------------------------------------
 template <class R>
 void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *items, int n_items, const Work<R> &w,
-                     uint64_t r0, uint32_t n, int grid, hipStream_t s)
+                     uint64_t total, uint32_t chunk, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_generate<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, items, n_items, w, r0, n);
+    hipLaunchKernelGGL(k_generate<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, items, n_items, w, total, chunk);
 }
 template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, int grid, hipStream_t s)
@@ -1443,6 +1464,10 @@ void launch_zero_f64(double *a, int64_t n, hipStream_t s)
 {
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(16384, (n + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(k_zero_f64, dim3(grid), dim3(kBlock), 0, s, a, n);
+}
+void launch_advance_cursor(Counters *c, uint32_t chunk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_cursor, dim3(1), dim3(64), 0, s, c, chunk);
 }
 void launch_zero_counters(Counters *c, hipStream_t s)
 {

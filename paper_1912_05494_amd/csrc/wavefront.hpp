@@ -10,7 +10,7 @@ namespace sdm {
 
 template <class R>
 void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *items, int n_items, const Work<R> &w,
-                     uint64_t r0, uint32_t n, int grid, hipStream_t s);
+                     uint64_t total, uint32_t chunk, int grid, hipStream_t s);
 template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, int grid, hipStream_t s);
 template <class R>
@@ -41,6 +41,7 @@ void launch_finalize(const double *acc, int64_t npix, int nl, int spp, const dou
                      float *spec, double *xyz, hipStream_t s);
 void launch_zero_f64(double *a, int64_t n, hipStream_t s);
 void launch_zero_counters(Counters *c, hipStream_t s);
+void launch_advance_cursor(Counters *c, uint32_t chunk, hipStream_t s);
 void launch_slab_eval(int64_t m, const float *c, const float *lam, const float *d, const float *n, const float *k,
                       const float *tint, float *R, float *T, hipStream_t s);
 void launch_debug_intersect(const SceneDev &sc, uint32_t m, const float *o, const float *d, const int32_t *skip,

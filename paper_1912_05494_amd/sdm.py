@@ -53,7 +53,7 @@ class RenderParams(C.Structure):
                 ("tile_h", C.c_int32), ("beta_threshold", C.c_float), ("precision", C.c_int32),
                 ("chunk_paths", C.c_int64), ("timing", C.c_int32), ("btdf_mode", C.c_int32),
                 ("err_dims", C.c_int32 * 3), ("mlp", C.c_void_p), ("err_table", _FP),
-                ("err_bound", C.c_float)]
+                ("err_bound", C.c_float), ("graph", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -78,6 +78,15 @@ class Stats(C.Structure):
 class Outputs(C.Structure):
     _fields_ = [("spectral", C.c_void_p), ("xyz", C.c_void_p), ("spectral_mem", C.c_int32),
                 ("xyz_mem", C.c_int32), ("stats", C.POINTER(Stats))]
+
+
+class Job(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("params", C.POINTER(RenderParams)), ("out", C.POINTER(Outputs))]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("chunk_paths", C.c_int64), ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("ms", C.c_double),
+                ("from_cache", C.c_int32)]
 
 
 class TrainParams(C.Structure):
@@ -123,6 +132,8 @@ def lib():
         L.sdm_mlp_infer.argtypes = [vp, C.c_int64] + [vp] * 4
         L.sdm_debug_mfma.argtypes = [vp] * 8
         L.sdm_mlp_error_table.argtypes = [vp, C.c_int64] + [vp] * 6
+        L.sdm_render_batch.argtypes = [vp, C.c_int32, C.POINTER(Job), C.POINTER(Stats), vp]
+        L.sdm_autotune.argtypes = [vp, vp, C.POINTER(RenderParams), C.c_char_p, C.POINTER(TuneResult), vp]
         _lib = L
     return _lib
 
@@ -131,7 +142,8 @@ EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_
             "sdm_scene_destroy", "sdm_scene_info", "sdm_render", "sdm_slab_eval",
             "sdm_debug_intersect", "sdm_debug_shadow", "sdm_slab_mc", "sdm_mlp_nparams",
             "sdm_mlp_create", "sdm_mlp_destroy", "sdm_mlp_get_params", "sdm_mlp_grad",
-            "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table")
+            "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table",
+            "sdm_render_batch", "sdm_autotune")
 
 
 def _stream(stream=None):
@@ -224,7 +236,7 @@ class Scene:
 
 
 def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision="fp32",
-                chunk_paths=0, timing=False, btdf=None):
+                chunk_paths=0, timing=False, btdf=None, graph=False):
     """btdf: None (exact walks on bubbly panes) or a dict with mode ("exact",
     "surrogate", "fallback"), mlp (an MLP) and, for "fallback", err_table
     (array (n_panes, n_cos, n_d, n_rho)) and bound."""
@@ -247,6 +259,7 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
         be.ctypes.data_as(C.POINTER(C.c_int32)) if be is not None else None,
         int(tile[0]), int(tile[1]), float(settings.beta_threshold),
         SDM_PREC_FP64 if precision == "fp64" else SDM_PREC_FP32, int(chunk_paths), int(timing))
+    p.graph = int(bool(graph))
     if btdf is not None:
         p.btdf_mode = BTDF_MODES[btdf.get("mode", "exact")]
         if btdf.get("mlp") is not None:
@@ -263,7 +276,7 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
 
 def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, tile=(0, 0),
            precision="fp32", chunk_paths=0, timing=False, stream=None, spectral=True, xyz=True,
-           btdf=None):
+           btdf=None, graph=False):
     """Render into new device tensors: (spectral (H, W, nl) float32, xyz (H, W, 3) float64,
     stats dict)."""
     import torch
@@ -272,7 +285,7 @@ def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, 
     dev = torch.device("cuda", ctx.device)
     spec_t = torch.empty((cam.H, cam.W, nl), dtype=torch.float32, device=dev) if spectral else None
     xyz_t = torch.empty((cam.H, cam.W, 3), dtype=torch.float64, device=dev) if xyz else None
-    p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing, btdf)
+    p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing, btdf, graph)
     st = Stats()
     out = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, C.pointer(st))
     ctx.check(lib().sdm_render(ctx.ptr, scene.ptr, C.byref(p), C.byref(out), _stream(stream)),
@@ -420,3 +433,40 @@ def debug_mfma(ctx: Context, A32, B32, A16, B16, stream=None):
     ctx.check(lib().sdm_debug_mfma(ctx.ptr, _ptr(A32), _ptr(B32), _ptr(C32), _ptr(A16), _ptr(B16), _ptr(C16),
                                    _stream(stream)), "sdm_debug_mfma")
     return C32, C16
+
+
+def render_batch(ctx: Context, jobs, precision="fp32", chunk_paths=0, graph=False, timing=False, stream=None):
+    """jobs: list of (Scene, settings) or (Scene, settings, btdf); renders them
+    in one wavefront.  Returns ([(spectral, xyz) device tensors], stats)."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    arr = (Job * len(jobs))()
+    keep, outs, images = [], [], []
+    for i, jb in enumerate(jobs):
+        scene, settings = jb[0], jb[1]
+        btdf = jb[2] if len(jb) > 2 else None
+        cam = settings.camera
+        nl = len(settings.lambda_nm)
+        spec_t = torch.empty((cam.H, cam.W, nl), dtype=torch.float32, device=dev)
+        xyz_t = torch.empty((cam.H, cam.W, 3), dtype=torch.float64, device=dev)
+        p, k = make_params(settings, precision=precision, chunk_paths=chunk_paths if i == 0 else 0,
+                           timing=timing, btdf=btdf, graph=graph)
+        o = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, None)
+        keep += [p, k, o, scene]
+        arr[i] = Job(scene.ptr, C.pointer(p), C.pointer(o))
+        images.append((spec_t, xyz_t))
+    st = Stats()
+    ctx.check(lib().sdm_render_batch(ctx.ptr, len(jobs), arr, C.byref(st), _stream(stream)), "sdm_render_batch")
+    return images, st.as_dict()
+
+
+def autotune(ctx: Context, scene: Scene, settings, precision="fp32", cache_path=None, n_bands=None, stream=None):
+    """Chooses chunk size and pixel tile for (scene, settings); later renders
+    with default chunk/tile use it.  Returns a dict of the choice."""
+    p, keep = make_params(settings, n_bands=n_bands, precision=precision)
+    r = TuneResult()
+    ctx.check(lib().sdm_autotune(ctx.ptr, scene.ptr, C.byref(p),
+                                 None if cache_path is None else str(cache_path).encode(), C.byref(r),
+                                 _stream(stream)), "sdm_autotune")
+    return {"chunk_paths": int(r.chunk_paths), "tile": (int(r.tile_w), int(r.tile_h)), "ms": r.ms,
+            "from_cache": bool(r.from_cache)}

@@ -86,6 +86,10 @@ int main(void) {
   P(sdm_render_params, btdf_mode); P(sdm_render_params, err_dims); P(sdm_render_params, mlp);
   P(sdm_render_params, err_table); P(sdm_render_params, err_bound);
   P(sdm_stats, bubbly_vertices); P(sdm_stats, kernel_ms);
+  P(sdm_render_params, graph);
+  printf("sdm_job %zu\n", sizeof(sdm_job));
+  printf("sdm_tune_result %zu\n", sizeof(sdm_tune_result));
+  P(sdm_tune_result, ms); P(sdm_tune_result, from_cache);
   P(sdm_stats, ms_render); P(sdm_stats, kernel_launches);
   P(sdm_outputs, stats);
   return 0;
@@ -100,7 +104,7 @@ int main(void) {
     got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     m = {"sdm_material": sdm.Material, "sdm_scene_desc": sdm.SceneDesc, "sdm_camera": sdm.Camera,
          "sdm_render_params": sdm.RenderParams, "sdm_stats": sdm.Stats, "sdm_outputs": sdm.Outputs,
-         "sdm_train_params": sdm.TrainParams}
+         "sdm_train_params": sdm.TrainParams, "sdm_job": sdm.Job, "sdm_tune_result": sdm.TuneResult}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")

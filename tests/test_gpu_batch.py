@@ -1,0 +1,150 @@
+"""Batched rendering, graph replay and the autotuner, through the C ABI.
+
+A job's image depends neither on the other jobs of its batch, nor on graph
+replay, nor on the chunk size or pixel tile: each path does the same
+arithmetic; only the order of the FP64 accumulation differs, so images agree
+to 1e-9 relative (FP64 sums of the same terms).
+"""
+import numpy as np
+import pytest
+
+from paper_1912_05494_amd import surrogate, synth
+from scenes_for_tests import bubbly
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    from paper_1912_05494_amd import sdm
+    assert torch.cuda.is_available()
+    ctx = sdm.Context(0)
+    yield sdm, ctx, torch
+    ctx.close()
+
+
+def np64(t):
+    return t.cpu().numpy().astype(np.float64)
+
+
+def small_batch():
+    """Uneven jobs: different scenes, image sizes, wavelength counts, spp,
+    depths and band splits."""
+    jobs = synth.batch_jobs(n_jobs=4, seed=2, scale=0.08)
+    tiny = synth.tiny_scene()
+    st = synth.tiny_settings(W=40, H=24, spp=3, max_depth=5, n_bands=4)
+    st.job_id = 9
+    jobs.append((tiny, st))
+    return jobs
+
+
+def close(a, b, rtol=1e-9):
+    return np.allclose(a, b, rtol=rtol, atol=rtol * max(1e-30, np.abs(b).max()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_equals_single_renders(gpu, precision):
+    sdm, ctx, torch = gpu
+    jobs = small_batch()
+    scenes = [sdm.Scene(ctx, sc) for sc, _ in jobs]
+    images, stats = sdm.render_batch(ctx, [(g, st) for g, (_, st) in zip(scenes, jobs)], precision=precision,
+                                     chunk_paths=1 << 15)
+    assert stats["chunks"] > 1
+    for g, (sc, st), (spec, xyz) in zip(scenes, jobs, images):
+        s1, x1, _ = sdm.render(ctx, g, st, precision=precision, chunk_paths=1 << 15)
+        assert close(np64(spec), np64(s1)), st.camera.W
+        assert close(np64(xyz), np64(x1))
+
+
+def test_batch_matches_oracle_sampled(gpu, orc):
+    sdm, ctx, torch = gpu
+    jobs = small_batch()
+    scenes = [sdm.Scene(ctx, sc) for sc, _ in jobs]
+    images, _ = sdm.render_batch(ctx, [(g, st) for g, (_, st) in zip(scenes, jobs)], precision="fp64")
+    rng = np.random.default_rng(0)
+    for (sc, st), (spec, _) in zip(jobs, images):
+        W, H = st.camera.W, st.camera.H
+        pix = rng.choice(W * H, size=min(24, W * H), replace=False).astype(np.int32)
+        o = orc.render_pixels(orc.OracleScene(sc), st, pix)
+        g = np64(spec).reshape(W * H, -1)[pix]
+        ok = np.abs(g - o) <= 1e-4 * np.maximum(np.abs(o), 1e-3 * np.abs(o).mean())
+        assert ok.all(), (W, int((~ok).sum()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replay_matches_eager(gpu, precision):
+    """The chunk sequence captured once and replayed per chunk; renders with
+    the graph interleaved with eager renders, every replay checked."""
+    sdm, ctx, torch = gpu
+    sc = synth.nave_scene(seed=3, target_tris=6000)
+    st = synth.nave_settings(W=96, H=64, spp=8, max_depth=6, n_lambda=24)
+    g = sdm.Scene(ctx, sc)
+    ref, xref, _ = sdm.render(ctx, g, st, precision=precision, chunk_paths=10000)
+    ref, xref = np64(ref), np64(xref)
+    for _ in range(3):
+        spec, xyz, stats = sdm.render(ctx, g, st, precision=precision, chunk_paths=10000, graph=True)
+        torch.cuda.synchronize()
+        assert stats["chunks"] > 3
+        assert close(np64(spec), ref) and close(np64(xyz), xref)
+        e, _, _ = sdm.render(ctx, g, st, precision=precision, chunk_paths=10000)
+        assert close(np64(e), ref)
+
+
+def test_graph_batch_with_bubbly_surrogate(gpu):
+    """Graph replay of a batch whose jobs mix clear glass and bubbly panes in
+    the surrogate form."""
+    sdm, ctx, torch = gpu
+    tiny_b = synth.tiny_scene(bubbly=True)
+    tiny = synth.tiny_scene()
+    st = synth.tiny_settings(W=32, H=32, spp=2, max_depth=4)
+    st2 = synth.tiny_settings(W=16, H=24, spp=3, max_depth=3, n_bands=2)
+    net = sdm.MLP(ctx, 1, surrogate.init_params(1, seed=4))
+    gb, gt = sdm.Scene(ctx, tiny_b), sdm.Scene(ctx, tiny)
+    btdf = {"mode": "surrogate", "mlp": net}
+    jobs = [(gb, st, btdf), (gt, st2)]
+    a, _ = sdm.render_batch(ctx, jobs, graph=False, chunk_paths=1000)
+    for _ in range(2):
+        b, _ = sdm.render_batch(ctx, jobs, graph=True, chunk_paths=1000)
+        for (sa, xa), (sb, xb) in zip(a, b):
+            assert close(np64(sb), np64(sa))
+    single, _, _ = sdm.render(ctx, gb, st, btdf=btdf, chunk_paths=1000)
+    assert close(np64(a[0][0]), np64(single))
+    net.close()
+
+
+def test_autotune_choice_and_cache(gpu, tmp_path):
+    sdm, ctx, torch = gpu
+    sc = synth.nave_scene(seed=4, target_tris=8000)
+    st = synth.nave_settings(W=128, H=96, spp=16, max_depth=5, n_lambda=16)
+    g = sdm.Scene(ctx, sc)
+    base, _, _ = sdm.render(ctx, g, st, precision="fp64")
+    cache = tmp_path / "tune.txt"
+    r = sdm.autotune(ctx, g, st, precision="fp64", cache_path=cache)
+    assert r["chunk_paths"] in (1 << 20, 1 << 21, 1 << 22) and r["tile"][0] in (8, 16, 32)
+    assert not r["from_cache"] and r["ms"] > 0
+    r2 = sdm.autotune(ctx, g, st, precision="fp64", cache_path=cache)
+    assert r2["from_cache"] and r2["chunk_paths"] == r["chunk_paths"] and r2["tile"] == r["tile"]
+    tuned, _, _ = sdm.render(ctx, g, st, precision="fp64")
+    assert close(np64(tuned), np64(base))
+
+
+def test_batch_invalid(gpu):
+    sdm, ctx, torch = gpu
+    tiny = sdm.Scene(ctx, synth.tiny_scene())
+    st = synth.tiny_settings(W=8, H=8, spp=1)
+    import ctypes as C
+    p1, k1 = sdm.make_params(st, precision="fp32")
+    p2, k2 = sdm.make_params(st, precision="fp64")
+    spec = torch.empty((8, 8, 16), device="cuda")
+    o = sdm.Outputs(sdm._ptr(spec), None, sdm.SDM_MEM_DEVICE, sdm.SDM_MEM_DEVICE, None)
+    arr = (sdm.Job * 2)(sdm.Job(tiny.ptr, C.pointer(p1), C.pointer(o)), sdm.Job(tiny.ptr, C.pointer(p2), C.pointer(o)))
+    assert sdm.lib().sdm_render_batch(ctx.ptr, 2, arr, None, None) != 0
+    assert sdm.lib().sdm_render_batch(ctx.ptr, 0, arr, None, None) != 0
+    b = sdm.Scene(ctx, synth.tiny_scene(bubbly=True))
+    n1 = sdm.MLP(ctx, 1, surrogate.init_params(1, seed=0))
+    n2 = sdm.MLP(ctx, 1, surrogate.init_params(1, seed=1))
+    with pytest.raises(sdm.SdmError):
+        sdm.render_batch(ctx, [(b, st, {"mode": "surrogate", "mlp": n1}), (b, st, {"mode": "surrogate", "mlp": n2})])
+    n1.close()
+    n2.close()

@@ -21,6 +21,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# chunk size and pixel tile of the workload as chosen by sdm_autotune on MI355X
+# (bench.py --autotune repeats the choice); the timed runs and the counter
+# runs use the same
+CHUNK_PATHS = 1 << 22
+TILE = 8
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # Plain VALU issue rate of FP32 arithmetic without packed math:
@@ -75,7 +80,7 @@ def profile_once():
     from paper_1912_05494_amd import sdm, synth
     ctx = sdm.Context(0)
     gs = sdm.Scene(ctx, synth.nave_scene(seed=1))
-    spec, xyz, stats = sdm.render(ctx, gs, synth.nave_settings())
+    spec, xyz, stats = sdm.render(ctx, gs, synth.nave_settings(), chunk_paths=CHUNK_PATHS, tile=(TILE, TILE))
     torch.cuda.synchronize()
     a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -242,6 +247,53 @@ def bubbly_bench(args):
     ctx.close()
 
 
+def batch_bench(args):
+    """The uneven 32-job batch (square sides 128-1024, 10k-200k triangles,
+    8-81 wavelengths, 16-128 spp; scene seed 2 + job) as one wavefront,
+    against the same jobs rendered one after the other."""
+    import torch
+    from paper_1912_05494_amd import sdm, synth
+
+    t0 = time.perf_counter()
+    jobs = synth.batch_jobs(n_jobs=args.batch_jobs, seed=2, scale=args.batch_scale)
+    ctx = sdm.Context(0)
+    scenes = [sdm.Scene(ctx, sc) for sc, _ in jobs]
+    print(f"{len(jobs)} scenes built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    samples = sum(st.camera.W * st.camera.H * st.spp * len(st.lambda_nm) for _, st in jobs)
+    tris = sum(sc.nt for sc, _ in jobs)
+    batch = [(g, st) for g, (_, st) in zip(scenes, jobs)]
+    sdm.render_batch(ctx, batch, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, stats = sdm.render_batch(ctx, batch, graph=True)
+        print(f"batch step {i}: {stats['ms_render']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # the same jobs one after the other
+    t0 = time.perf_counter()
+    for g, st in batch:
+        sdm.render(ctx, g, st, graph=True)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    out = {
+        "metric": "spectral ray samples/sec (32-job batch)",
+        "value": samples / dt,
+        "unit": "spectral ray samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(jobs)} procedural naves, {tris} triangles in all, square sides "
+                               f"128-1024 x {args.batch_scale}, 8-81 wavelengths, 16-128 spp, depth 8, "
+                               "one wavefront with graph replay",
+                   "spectral_samples_per_step": samples},
+        "sequential_single_renders": {"value": samples / dt_seq, "ms": dt_seq * 1e3},
+        "batch_speedup_over_sequential": dt_seq / dt,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,8 +304,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
-    ap.add_argument("--form", default="plain", choices=["plain", "bubbly"],
-                    help="plain: the clear-glass nave (default); bubbly: bubbly panes in three forms")
+    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch"],
+                    help="plain: the clear-glass nave (default); bubbly: bubbly panes in three forms; "
+                         "batch: the uneven 32-job batch in one wavefront")
+    ap.add_argument("--batch-jobs", type=int, default=32)
+    ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose chunk size and tile with sdm_autotune before timing")
     ap.add_argument("--bubbly-spp", type=int, default=64)
     ap.add_argument("--bubbly-train", type=int, default=10_000_000)
     ap.add_argument("--bubbly-steps", type=int, default=10000)
@@ -273,6 +330,9 @@ def main():
     if args.form == "bubbly":
         bubbly_bench(args)
         return
+    if args.form == "batch":
+        batch_bench(args)
+        return
 
     import torch
     from paper_1912_05494_amd import sdm, synth
@@ -288,7 +348,14 @@ def main():
     dev = torch.device("cuda", 0)
     spec = torch.empty((H, W, nl), dtype=torch.float32, device=dev)
     xyz = torch.empty((H, W, 3), dtype=torch.float64, device=dev)
-    params, keep = sdm.make_params(st, precision=args.precision, timing=True)
+    chunk, tile = CHUNK_PATHS, (TILE, TILE)
+    tuned = None
+    if args.autotune:
+        # chunk size and pixel tile for this scene and shape (untimed)
+        tuned = sdm.autotune(ctx, gs, st, precision=args.precision)
+        chunk, tile = tuned["chunk_paths"], tuned["tile"]
+        print(f"autotune: {tuned}", file=sys.stderr, flush=True)
+    params, keep = sdm.make_params(st, precision=args.precision, timing=True, chunk_paths=chunk, tile=tile)
     for _ in range(args.warmup):
         sdm.render_into(ctx, gs, params, spec, xyz)
     torch.cuda.synchronize()
@@ -323,6 +390,15 @@ def main():
         kernels[k] = {"ms_per_step": kms[k] / args.steps, "launches_per_step": kl[k] // args.steps,
                       "avg_launch_ms": avg_ms, "bound": bound, "achieved": ach, "peak": peak,
                       "unit": unit, "frac": ach / peak}
+    # the same render replayed as a graph per chunk (no per-kernel events)
+    gparams, gkeep = sdm.make_params(st, precision=args.precision, graph=True, chunk_paths=chunk, tile=tile)
+    sdm.render_into(ctx, gs, gparams, spec, xyz)
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        sdm.render_into(ctx, gs, gparams, spec, xyz)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - tg) / max(1, args.steps // 2) * 1e3
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     kd = kernels[dom]
     out = {
@@ -349,6 +425,8 @@ def main():
         "segments_per_s": (s["closest_segments"] + s["shadow_segments"]) * args.steps / dt,
         "distinct_rays_per_step": {"closest": s["closest_segments"], "shadow": s["shadow_segments"],
                                    "forks": s["forks"]},
+        "graph_replay": {"ms_per_step": graph_ms, "value": samples / (graph_ms * 1e-3)},
+        "chunk_paths": chunk, "tile": list(tile), "autotune": tuned,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, st)

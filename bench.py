@@ -36,16 +36,29 @@ FLOPS_PER_TRI = 50      # Moeller-Trumbore: edges, two cross products, four dots
 
 
 def kernel_models(stats, nb, npix, nl):
-    """Algorithmic work of each kernel class (see the design doc for the model)."""
+    """Algorithmic work of each kernel class per render.  Weights are stored
+    as a scalar per path or shadow record plus nb per-wavelength factors only
+    for paths and records whose wavelengths differ (glass, coloured albedo):
+      generate      44 B per path written (origin, direction, pixel, sample,
+                    depth/band/job word, skip, scalar factor)
+      shade         per closest segment 56 B read (ray 36, hit 16, factor 4)
+                    and 44 B written for the continuing path, 28 B per shadow
+                    record; 8 nb B per spectral path (read + write), 4 nb B
+                    per spectral record; forks 44 + 4 nb B
+      shadow_accum  16 B per record plus 4 nb B per spectral record
+      finalize      12 nl + 24 B per pixel
+    Traversal (trace, shadow) counts 48 flop per node visited and 50 per
+    triangle tested; the network 2 x 9216 flop per (vertex, wavelength)."""
     Ng, Nc, Ns, F = stats["paths"], stats["closest_segments"], stats["shadow_segments"], stats["forks"]
+    Nsp, Nsr = stats.get("spectral_paths", 0), stats.get("spectral_records", 0)
     m = {
-        "generate": ("hbm", Ng * (44 + 4 * nb)),
+        "generate": ("hbm", Ng * 44),
         "trace": ("alu", stats["nodes_visited"]["closest"] * FLOPS_PER_NODE
                   + stats["tris_tested"]["closest"] * FLOPS_PER_TRI),
-        "shade": ("hbm", Nc * (84 + 8 * nb) + Ns * (24 + 4 * nb) + F * (40 + 4 * nb)),
+        "shade": ("hbm", Nc * (56 + 44) + Ns * 28 + Nsp * 8 * nb + Nsr * 4 * nb + F * (44 + 4 * nb)),
         "shadow": ("alu", stats["nodes_visited"]["shadow"] * FLOPS_PER_NODE
                    + stats["tris_tested"]["shadow"] * FLOPS_PER_TRI),
-        "shadow_accum": ("hbm", Ns * (16 + 4 * nb)),
+        "shadow_accum": ("hbm", Ns * 16 + Nsr * 4 * nb),
         "shade_glass": ("alu", 0),
         "finalize": ("hbm", npix * nl * 12 + npix * 24),
         # network on the matrix cores: 2 x 9216 multiply-adds per (vertex, wavelength) tuple,

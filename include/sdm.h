@@ -151,6 +151,9 @@ typedef struct {
     uint64_t nodes_visited[2];  /* BVH node fetches [closest-hit, shadow]      */
     uint64_t tris_tested[2];    /* ray-triangle tests [closest-hit, shadow]    */
     uint64_t bubbly_vertices;   /* path vertices shaded on bubbly panes         */
+    uint64_t spectral_paths;    /* closest-hit segments whose wavelengths carry
+                                   different weights (per-wavelength factors)  */
+    uint64_t spectral_records;  /* shadow records with per-wavelength factors   */
     double ms_render;          /* wall time of the render on the stream       */
     double kernel_ms[SDM_K_COUNT];     /* summed kernel durations (timing=1)   */
     uint64_t kernel_launches[SDM_K_COUNT];

@@ -242,6 +242,12 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     for (int32_t m = 0; m < d->n_mat; ++m) {
         const sdm_material &mm = d->mats[m];
         mtype[m] = mm.type == SDM_LAMBERT ? 0 : (mm.type == SDM_GLASS ? 1 : 2);
+        if (mm.type == SDM_LAMBERT) {
+            // a flat albedo table is gray: its bounces scale every wavelength alike
+            bool flat = true;
+            for (int i = 1; i < d->n_tab; ++i) flat = flat && mm.albedo[i] == mm.albedo[0];
+            if (flat) mtype[m] = 3;
+        }
         mthick[m] = mm.thick_mm;
         if (mm.type == SDM_GLASS_BUBBLY) {
             // extinction rho_b pi <r^2> (r ~ U(rmin, rmax), mm) and the inner index:

@@ -425,10 +425,10 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         const uint32_t cap = (uint32_t)cap64;
         const int nb = plan.nbmax;
         const size_t plane = (size_t)cap * sizeof(R);
-        const size_t pool_b = 6 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R);
+        const size_t pool_b = 7 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) + 8 * 256;
         const size_t hit_b = 3 * plane + 2 * (size_t)cap * 4;
-        const size_t sh_b = 3 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
-                            (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R));
+        const size_t sh_b = 4 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
+                            (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R)) + 12 * 256;
         HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
         HIPCHK(ctx, ctx->hits.ensure(hit_b + 2048));
         HIPCHK(ctx, ctx->shadowq.ensure(sh_b + 2048));
@@ -452,6 +452,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             P.dx = (R *)take(plane); P.dy = (R *)take(plane); P.dz = (R *)take(plane);
             P.pix = (uint32_t *)take((size_t)cap * 4); P.smp = (uint32_t *)take((size_t)cap * 4);
             P.aux = (uint32_t *)take((size_t)cap * 4); P.skip = (int32_t *)take((size_t)cap * 4);
+            P.g = (R *)take(plane);
             P.beta = (R *)take((size_t)cap * nb * sizeof(R));
         }
         pb = ctx->hits.as<char>();
@@ -468,6 +469,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         w.sx = (R *)take(plane); w.sy = (R *)take(plane); w.sz = (R *)take(plane);
         w.sskip = (int32_t *)take((size_t)cap * 4); w.spix = (uint32_t *)take((size_t)cap * 4);
         w.saux = (uint32_t *)take((size_t)cap * 4); w.socc = (int32_t *)take((size_t)cap * 4);
+        w.scs = (R *)take(plane);
         w.contrib = (R *)take((size_t)cap * nb * sizeof(R));
         w.sg_leaf = (int32_t *)take((size_t)cap * kMaxGlass * 4);
         w.sg_u = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
@@ -582,6 +584,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             st.shadow_segments = c.shadow;
             st.forks = c.forks;
             st.bubbly_vertices = c.bubbly;
+            st.spectral_paths = c.spec_paths;
+            st.spectral_records = c.spec_records;
             st.chunks = n_chunks;
             for (int q = 0; q < 2; ++q) {
                 st.nodes_visited[q] = c.nodes[q];

@@ -28,7 +28,7 @@ struct SceneDev {
     const BvhNode *nodes;
     const TriDev *tris;
     const float4 *thick;        // per leaf-order triangle: vertex thickness (mm)
-    const int32_t *mat_type;    // [n_mat]: 0 Lambert, 1 glass, 2 bubbly glass
+    const int32_t *mat_type;    // [n_mat]: 0 Lambert, 1 glass, 2 bubbly glass, 3 gray Lambert
     const float *mat_thick;     // [n_mat] default thickness
     const double *mat_bub;      // [n_mat][4]: bubble extinction (per mm), inner index n_ref,
                                 // density (per mm^3), pane type; zeros for other materials
@@ -76,18 +76,30 @@ struct ItemDev {
 
 // Device counters.  Kernels clear the counters the next kernel needs (never
 // a memset), so a captured launch sequence replays cleanly.
-struct Counters {
-    uint32_t count[2];          // paths in pool 0 / pool 1
+// Each counter that waves update concurrently sits in a 256-byte line of
+// its own, so atomics on different counters do not serialise on one line.
+constexpr int kCounterPad = 64;   // 32-bit words per line
+struct alignas(256) Counters {
+    uint32_t count[2];          // paths in pool 0 / pool 1 (only count[cur ^ 1] is updated in a pass)
+    uint32_t pad_c[kCounterPad - 2];
     uint32_t scount;            // shadow records
-    uint32_t tfetch, sfetch;    // work cursors of the two traversal kernels
+    uint32_t pad_s[kCounterPad - 1];
+    uint32_t gcount;            // glass vertices queued for the glass shading pass
+    uint32_t pad_g[kCounterPad - 1];
+    uint32_t bcount;            // bubbly-glass vertices, queued from the back of gidx
+    uint32_t pad_b[kCounterPad - 1];
+    uint32_t kcount;            // sky records (escaped paths), from the back of the record buffer
+    uint32_t pad_k[kCounterPad - 1];
+    uint32_t tfetch;            // work cursor of the closest-hit traversal
+    uint32_t pad_t[kCounterPad - 1];
+    uint32_t sfetch;            // work cursor of the shadow traversal
+    uint32_t pad_f[kCounterPad - 1];
     uint32_t overflow;          // bit 0: a pool or record buffer was full;
                                 // bit 1: a shadow ray crossed more than kMaxGlass panes
-    uint32_t gcount;            // glass vertices queued for the glass shading pass
-    uint32_t bcount;            // bubbly-glass vertices, queued from the back of gidx
-    unsigned long long r0;      // first primary path of the current chunk (advanced per chunk)
     int32_t lds_job;            // job whose BVH prefix the traversal kernels stage in LDS
-    int32_t pad2;
+    unsigned long long r0;      // first primary path of the current chunk (advanced per chunk)
     unsigned long long closest, shadow, forks, bubbly;
+    unsigned long long spec_paths, spec_records;   // kSpectral paths shaded / shadow records made
     unsigned long long nodes[2], tris[2];   // traversal work [closest, shadow]
 };
 
@@ -102,12 +114,21 @@ __host__ __device__ __forceinline__ size_t aosoa(uint32_t slot, int j, int nbmax
 
 // Path pool (SoA).  Two pools alternate: shade reads one and writes the
 // survivors, compacted, into the other.
+// Path weights are factored: beta_j = g * b_j.  A path whose wavelengths all
+// carry the same weight (camera rays, bounces on gray materials) keeps only
+// the scalar g; the per-wavelength factors b_j exist once glass or a coloured
+// material has made the weights differ, which kSpectral in its sample word
+// records.  Shadow records likewise: contribution_j = scs * E_j * c_j with the
+// c_j stored only for records flagged kSpectral in their pixel word.
+constexpr uint32_t kSpectral = 0x80000000u;
+
 template <class R>
 struct Pool {
     R *ox, *oy, *oz, *dx, *dy, *dz;
-    uint32_t *pix, *smp, *aux;  // aux = depth | band << 8 | job << 20
+    uint32_t *pix, *smp, *aux;  // smp: sample | kSpectral; aux = depth | band << 8 | job << 20
     int32_t *skip;              // leaf-order index of the last hit triangle
-    R *beta;                    // AoSoA [slot][j] path weights
+    R *g;                       // [slot] scalar factor of the weights
+    R *beta;                    // AoSoA [slot][j] per-wavelength factors (kSpectral paths)
 };
 
 constexpr int kMaxGlass = 8;    // panes a shadow ray may cross (more: SDM_E_UNSUPPORTED)
@@ -121,10 +142,12 @@ struct Work {
                                 // the front, bubbly glass from the back: gidx[cap - 1 - b])
     R *bratio;                  // AoSoA [slot][j]: surrogate R / (R + T) at bubbly vertices
     R *bw;                      // [slot]: surrogate lobe width at kLambdaRef
-    R *sx, *sy, *sz;            // shadow records
+    R *sx, *sy, *sz;            // shadow records [0, scount); sky records of escaped paths at
+                                // cap - 1 - k, k < kcount (pixel, aux, scalar and spectral factors only)
     int32_t *sskip;
-    uint32_t *spix, *saux;
-    R *contrib;                 // AoSoA [record][j]
+    uint32_t *spix, *saux;      // spix: pixel | kSpectral
+    R *scs;                     // [record] scalar factor of the contributions
+    R *contrib;                 // AoSoA [record][j] per-wavelength factors (kSpectral records)
     int32_t *socc;              // panes crossed (0..kMaxGlass), -1 occluded
     int32_t *sg_leaf;           // [record][kMaxGlass]
     R *sg_u, *sg_v;

@@ -9,12 +9,19 @@
 //
 // One step of the loop of Sec. 3.1 over a pool of paths:
 //   k_trace         closest hit of every path (persistent, lanes refilled)
-//   k_shade         sky for escaping paths, a shadow record per Lambert
-//                   vertex (eq. (3)), reflect/refract, survivors compacted
-//                   with their per-wavelength weights into the other pool
+//   k_shade         a sky record per escaping path, a shadow record per
+//                   Lambert vertex (eq. (3)), the cosine bounce, survivors
+//                   compacted into the other pool; glass vertices queued
+//   k_shade_glass   clear panes: slab R, T per wavelength, reflect or pass,
+//                   forks where the wavelengths disagree
+//   k_bubbly_eval,  bubbly panes: surrogate network on the matrix cores,
+//   k_shade_bubbly  exact walk or surrogate branch
 //   k_shadow_trace  any-hit walk of the shadow records toward the sun
-//   k_shadow_accum  per wavelength: slab transmittance of the panes crossed,
-//                   wave-level segmented sums, FP64 atomics per pixel
+//   k_shadow_accum  per wavelength: slab transmittance of the panes crossed
+//                   (sun records) or sky radiance (sky records), wave-level
+//                   segmented sums, FP64 atomics per pixel
+// Weights are a scalar per path times per-wavelength factors that exist only
+// once the wavelengths' weights differ (kSpectral).
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -233,7 +240,8 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
             R t, u, v;
             if (!tri_hit(ry.o, ry.d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
             if (!(t > teps)) continue;
-            if (gld(sc.mat_type + __float_as_int(tr.b.w)) == 0) {
+            const int mt = gld(sc.mat_type + __float_as_int(tr.b.w));
+            if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
                 occluded = true;
                 ry.cur = kDone;
                 return true;
@@ -395,10 +403,10 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const B
         P.ox[i] = o.x; P.oy[i] = o.y; P.oz[i] = o.z;
         P.dx[i] = d.x; P.dy[i] = d.y; P.dz[i] = d.z;
         P.pix[i] = pixel;
-        P.smp[i] = smp;
+        P.smp[i] = smp;                  // all wavelengths start with weight 1: no kSpectral
+        P.g[i] = R(1);
         P.aux[i] = pack_aux(0, it.band, bd.job);
         P.skip[i] = -1;
-        for (int j = 0; j < bd.nb; ++j) P.beta[aosoa(i, j, w.nbmax)] = R(1);
     }
 }
 
@@ -415,6 +423,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.cnt->count[cur ^ 1] = 0;
         w.cnt->scount = 0;
+        w.cnt->kcount = 0;
         w.cnt->sfetch = 0;
         w.cnt->gcount = 0;
         w.cnt->bcount = 0;
@@ -472,6 +481,39 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
 // pool.  Glass vertices are queued for k_shade_glass so that the costly
 // per-wavelength slab optics run in dense waves.
 // ---------------------------------------------------------------------------
+// Block-wide reservation of output slots in Q queues: every thread of the
+// block calls it (block-uniform control flow).  One atomic per queue and
+// block instead of one per wave; slots keep lane order within the block.
+template <int Q>
+__device__ __forceinline__ void block_reserve(const bool (&want)[Q], uint32_t *const (&ctr)[Q], uint32_t (&slot)[Q],
+                                              uint32_t *s_cnt, uint32_t *s_base)
+{
+    const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint32_t pre[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint64_t m = __ballot(want[q]);
+        pre[q] = (uint32_t)__popcll(m & lt);
+        if (lane == 0) s_cnt[wv * Q + q] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)Q) {
+        const int q = threadIdx.x;
+        uint32_t total = 0;
+        for (int w2 = 0; w2 < kBlock / 64; ++w2) total += s_cnt[w2 * Q + q];
+        s_base[q] = total ? atomicAdd(ctr[q], total) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        uint32_t off = s_base[q] + pre[q];
+        for (uint32_t w2 = 0; w2 < wv; ++w2) off += s_cnt[w2 * Q + q];
+        slot[q] = off;
+    }
+    __syncthreads();   // s_cnt and s_base are reused by the next call
+}
+
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
 {
@@ -480,18 +522,19 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const R inv_pi = R(0.31830988618379067);
-    for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
-        const uint32_t i = base + lane;
+    __shared__ uint32_t s_cnt[(kBlock / 64) * 5], s_base[5];
+    uint32_t n_spec = 0, n_srec = 0;
+    // block-strided so that the block reserves its output slots together
+    for (uint32_t bbase = blockIdx.x * kBlock; bbase < count; bbase += gridDim.x * kBlock) {
+        const uint32_t i = bbase + threadIdx.x;
         const bool active = i < count;
         uint32_t aux = 0, pix = 0, smp = 0;
         int32_t tri = -1;
         int kind = -1;            // 0 miss, 1 Lambert, 2 glass, 3 bubbly glass (both queued)
-        bool want_shadow = false, keep = false;
+        bool want_shadow = false, keep = false, spec = false, gray = false;
         V3<R> x = {R(0), R(0), R(0)}, dnew = x;
-        R cs = R(0);
+        R cs = R(0), g = R(0), rho_g = R(1);
         int mat = 0;
         const JobDev *jb = nullptr;
         BandDev bd = {0, 0, 0, 0};
@@ -499,6 +542,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
             aux = Pi.aux[i];
             pix = Pi.pix[i];
             smp = Pi.smp[i];
+            spec = (smp & kSpectral) != 0u;
+            g = Pi.g[i];
             const int depth = (int)(aux & 0xffu);
             jb = &jobs[aux >> kAuxJobShift];
             bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
@@ -509,8 +554,11 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
             } else {
                 const TriDev tr = load_tri(jb->sc.tris, tri);
                 mat = __float_as_int(tr.b.w);
-                if (gld(jb->sc.mat_type + mat) == 0) {
+                const int mt = gld(jb->sc.mat_type + mat);
+                if (mt == 0 || mt == 3) {
                     kind = 1;
+                    gray = mt == 3;
+                    if (gray) rho_g = gld((const R *)jb->rho + (size_t)mat * jb->nl + bd.l0);
                     const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
                     x = o + w.ht[i] * d;
                     const V3<R> ng = tri_normal<R>(tr);
@@ -520,133 +568,136 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
                     want_shadow = cs > R(0);
                     keep = !last;
                     if (!last) {
-                        const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp, depth, 0);
+                        const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
                         dnew = cosine_dir(ns, u01<R>(rr.y), u01<R>(rr.z));
                     }
                 } else if (!last) {
                     // no light sum at glass; a glass vertex at the depth limit ends the path
-                    kind = gld(jb->sc.mat_type + mat) == 2 ? 3 : 2;
+                    kind = mt == 2 ? 3 : 2;
                 }
             }
         }
-        // glass queue, shadow records and pool slots: one atomic per wave and buffer
-        const uint32_t gslot = wave_reserve(kind == 2, &w.cnt->gcount);
-        if (kind == 2) w.gidx[gslot] = i;
-        const uint32_t bslot = wave_reserve(kind == 3, &w.cnt->bcount);
-        if (kind == 3) w.gidx[w.cap - 1u - bslot] = i;
-        uint32_t sslot = wave_reserve(want_shadow, &w.cnt->scount);
+        n_spec += (active && spec) ? 1u : 0u;
+        // glass and bubbly queues, shadow and sky records, pool slots: one
+        // atomic per block and buffer
+        const bool want[5] = {kind == 2, kind == 3, want_shadow, keep, kind == 0};
+        uint32_t *const ctr[5] = {&w.cnt->gcount, &w.cnt->bcount, &w.cnt->scount, &w.cnt->count[cur ^ 1],
+                                  &w.cnt->kcount};
+        uint32_t slot[5];
+        block_reserve<5>(want, ctr, slot, s_cnt, s_base);
+        if (kind == 2) w.gidx[slot[0]] = i;
+        if (kind == 3) w.gidx[w.cap - 1u - slot[1]] = i;
+        uint32_t sslot = slot[2];
         if (want_shadow && sslot >= w.cap) { w.cnt->overflow |= 1u; want_shadow = false; }
-        uint32_t om = wave_reserve(keep, &w.cnt->count[cur ^ 1]);
+        uint32_t om = slot[3];
         if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
         if (kind == 1) {
-            const int nl = jb->nl;
+            // Lambert: the shadow record carries g rho cos / pi (rho when gray), the
+            // continuing path g rho; a spectral albedo or spectral weights keep
+            // per-wavelength factors
+            const bool out_spec = spec || !gray;
+            const R thr = R(jb->beta_thr);
+            const R gn = gray ? g * rho_g : g;
             if (want_shadow) {
                 w.sx[sslot] = x.x; w.sy[sslot] = x.y; w.sz[sslot] = x.z;
                 w.sskip[sslot] = tri;
-                w.spix[sslot] = pix;
+                w.spix[sslot] = pix | (out_spec ? kSpectral : 0u);
                 w.saux[sslot] = aux;
+                w.scs[sslot] = gn * inv_pi * cs;
+                n_srec += out_spec ? 1u : 0u;
             }
             if (keep) {
                 Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
                 Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
-                Po.pix[om] = pix; Po.smp[om] = smp; Po.aux[om] = aux + 1u; Po.skip[om] = tri;
+                Po.pix[om] = pix;
+                Po.smp[om] = (smp & ~kSpectral) | (out_spec ? kSpectral : 0u);
+                Po.aux[om] = aux + 1u;
+                Po.skip[om] = tri;
+                // the energy threshold of a gray path acts on g
+                Po.g[om] = (!out_spec && gn < thr) ? R(0) : gn;
             }
-            const R thr = R(jb->beta_thr);
-            const R *rho = (const R *)jb->rho + (size_t)mat * nl + bd.l0;
-            const R *E = (const R *)jb->E + bd.l0;
-            const R *__restrict__ bin = Pi.beta;
-            R *__restrict__ bout = Po.beta;
-            R *__restrict__ cout = w.contrib;
-            const R ncs = inv_pi * cs;
-            // eight wavelengths per round: all loads issued before the stores
-            int j = 0;
-            for (; j + 8 <= bd.nb; j += 8) {
-                R b[8], r[8], e[8];
+            if (out_spec) {
+                const R *rho = (const R *)jb->rho + (size_t)mat * jb->nl + bd.l0;
+                const R *__restrict__ bin = Pi.beta;
+                R *__restrict__ bout = Po.beta;
+                R *__restrict__ cout = w.contrib;
+                // eight wavelengths per round: all loads issued before the stores
+                for (int j = 0; j < bd.nb; j += 8) {
+                    R f[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    b[q] = bin[aosoa(i, j + q, nbm)];
-                    r[q] = gld(rho + j + q);
-                    e[q] = gld(E + j + q);
-                }
+                    for (int q = 0; q < 8; ++q) {
+                        const int jj = j + q < bd.nb ? j + q : bd.nb - 1;
+                        const R b = spec ? bin[aosoa(i, jj, nbm)] : R(1);
+                        f[q] = gray ? b : b * gld(rho + jj);
+                    }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    if (want_shadow) cout[aosoa(sslot, j + q, nbm)] = b[q] * r[q] * ncs * e[q];
-                    if (keep) {
-                        R bn = b[q] * r[q];
-                        if (bn < thr) bn = R(0);
-                        bout[aosoa(om, j + q, nbm)] = bn;
+                    for (int q = 0; q < 8; ++q) {
+                        if (j + q >= bd.nb) break;
+                        if (want_shadow) cout[aosoa(sslot, j + q, nbm)] = f[q];
+                        if (keep) bout[aosoa(om, j + q, nbm)] = (gn * f[q] < thr) ? R(0) : f[q];
                     }
                 }
             }
-            for (; j < bd.nb; ++j) {
-                const R b = bin[aosoa(i, j, nbm)];
-                const R rj = gld(rho + j);
-                if (want_shadow) cout[aosoa(sslot, j, nbm)] = b * rj * ncs * gld(E + j);
-                if (keep) {
-                    R bn = b * rj;
-                    if (bn < thr) bn = R(0);
-                    bout[aosoa(om, j, nbm)] = bn;
-                }
-            }
         }
-        // escaping paths: sky radiance, summed per pixel across the wave
-        if (__ballot(kind == 0)) {
-            const int nb = kind == 0 ? bd.nb : 0;
-            int jmax = nb;
-            for (int off = 32; off > 0; off >>= 1) jmax = max(jmax, __shfl_xor(jmax, off));
-            const uint64_t key0 = kind == 0 ? jb->acc_off + (uint64_t)pix * jb->nl + bd.l0 : ~0ull;
-            const uint32_t start = run_start(key0);
-            const bool lst = run_last(key0);
-            for (int j = 0; j < jmax; j += 4) {
-                double v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    v[q] = j + q < nb ? (double)(Pi.beta[aosoa(i, j + q, nbm)] *
-                                                 gld((const R *)jb->Lsky + bd.l0 + j + q))
-                                      : 0.0;
-                run_add_k<4>(w.acc, key0, j, nb, start, lst, v);
+        // escaping paths: a sky record each (summed per pixel by the
+        // accumulation pass, which keeps its waves dense)
+        const uint32_t kslot = slot[4];
+        if (kind == 0 && kslot >= w.cap) w.cnt->overflow |= 1u;   // cannot happen: one record per path
+        if (kind == 0 && kslot < w.cap) {
+            const uint32_t r = w.cap - 1u - kslot;
+            w.spix[r] = pix | (spec ? kSpectral : 0u);
+            w.saux[r] = aux;
+            w.scs[r] = g;
+            if (spec) {
+                for (int j = 0; j < bd.nb; ++j) w.contrib[aosoa(r, j, nbm)] = Pi.beta[aosoa(i, j, nbm)];
+                ++n_srec;
             }
         }
     }
+    // per-wave counts of spectral paths and records
+    for (int off = 32; off > 0; off >>= 1) {
+        n_spec += __shfl_xor(n_spec, off);
+        n_srec += __shfl_xor(n_srec, off);
+    }
+    if (lane == 0 && (n_spec | n_srec)) {
+        atomicAdd(&w.cnt->spec_paths, (unsigned long long)n_spec);
+        atomicAdd(&w.cnt->spec_records, (unsigned long long)n_srec);
+    }
 }
 
+// ---------------------------------------------------------------------------
 // Outputs of a split vertex: the kept path (direction dnew, the wavelengths
 // whose reflect bit is clear, or all of them when there is no fork) and, when
 // both branches occur, a forked path (direction drefl, the wavelengths whose
-// bit is set).  The new weights sit in Pi.beta at slot i.  One atomic per wave.
+// bit is set).  The new per-wavelength factors sit in Pi.beta at slot i; both
+// outputs keep the scalar factor g.  Called by every thread of the block
+// (block-uniform loop); one reservation per block.
 template <class R>
 __device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, const Pool<R> &Po, int cur, bool keep,
                                            bool fork, uint32_t i, V3<R> x, V3<R> dnew, V3<R> drefl, uint32_t pix,
                                            uint32_t smp, uint32_t aux, int32_t tri, int nb, uint32_t m0, uint32_t m1,
-                                           uint32_t m2, uint32_t m3)
+                                           uint32_t m2, uint32_t m3, R g, uint32_t *s_cnt, uint32_t *s_base)
 {
+    smp |= kSpectral;   // the outputs carry per-wavelength factors
     const int nbm = w.nbmax;
-    const uint32_t lane = lane_id();
-    const uint64_t mk = __ballot(keep), mf = __ballot(fork);
-    const uint32_t nk = (uint32_t)__popcll(mk), nf = (uint32_t)__popcll(mf);
-    const uint64_t lt = (1ull << lane) - 1ull;
-    uint32_t obase = 0;
-    if (nk + nf) {
-        const int leader = __ffsll((unsigned long long)(mk | mf)) - 1;
-        if ((int)lane == leader) {
-            obase = atomicAdd(&w.cnt->count[cur ^ 1], nk + nf);
-            if (nf) atomicAdd(&w.cnt->forks, (unsigned long long)nf);
-        }
-        obase = __shfl(obase, leader);
-    }
-    const uint32_t om = obase + (uint32_t)__popcll(mk & lt);
-    const uint32_t of = obase + nk + (uint32_t)__popcll(mf & lt);
+    const bool want[2] = {keep, fork};
+    uint32_t *const ctr[2] = {&w.cnt->count[cur ^ 1], &w.cnt->count[cur ^ 1]};
+    uint32_t slot[2];
+    block_reserve<2>(want, ctr, slot, s_cnt, s_base);
+    const uint32_t om = slot[0], of = slot[1];
     if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
     if (fork && of >= w.cap) { w.cnt->overflow |= 1u; fork = false; }
     if (keep) {
         Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
         Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
         Po.pix[om] = pix; Po.smp[om] = smp; Po.aux[om] = aux + 1u; Po.skip[om] = tri;
+        Po.g[om] = g;
     }
     if (fork) {
         Po.ox[of] = x.x; Po.oy[of] = x.y; Po.oz[of] = x.z;
         Po.dx[of] = drefl.x; Po.dy[of] = drefl.y; Po.dz[of] = drefl.z;
         Po.pix[of] = pix; Po.smp[of] = smp; Po.aux[of] = aux + 1u; Po.skip[of] = tri;
+        Po.g[of] = g;
     }
     if (keep) {
         const R *__restrict__ bin = Pi.beta;
@@ -681,21 +732,25 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, cons
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
-        const bool active = base + lane < count;
+    __shared__ uint32_t s_cnt[(kBlock / 64) * 2], s_base[2];
+    uint32_t n_fork = 0;
+    // block-strided: the block reserves its output slots together
+    for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
+        const bool active = base + threadIdx.x < count;
         uint32_t i = 0, aux = 0, pix = 0, smp = 0;
         int32_t tri = -1;
         V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x;
         uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;   // reflected wavelengths
         bool keep = false, fork = false;
+        R g = R(0);
         BandDev bd = {0, 0, 0, 0};
         if (active) {
-            i = w.gidx[base + lane];
+            i = w.gidx[base + threadIdx.x];
             aux = Pi.aux[i];
             pix = Pi.pix[i];
             smp = Pi.smp[i];
+            const bool spec = (smp & kSpectral) != 0u;
+            g = Pi.g[i];
             const int depth = (int)(aux & 0xffu);
             const JobDev *jb = &jobs[aux >> kAuxJobShift];
             bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
@@ -705,7 +760,7 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, cons
             const TriDev tr = load_tri(jb->sc.tris, tri);
             const int mat = __float_as_int(tr.b.w);
             const V3<R> ng = tri_normal<R>(tr);
-            const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp, depth, 0);
+            const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
             const R u0 = u01<R>(rr.x);
             const R cos_i = fabs(dot(d, ng));
             const R thick = pane_thickness<R>(jb->sc, tri, w.hu[i], w.hv[i]);
@@ -718,16 +773,17 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, cons
             const R *lam = (const R *)jb->lam + bd.l0;
             const R thr = R(jb->beta_thr);
             bool anyR = false, anyT = false;
-            // the new weights stay in the input slot until the output slots are known
+            // the new factors stay in the input slot until the output slots are
+            // known (a path without per-wavelength factors gets them here)
             for (int j = 0; j < bd.nb; ++j) {
                 const size_t q = aosoa(i, j, nbm);
-                const R b = Pi.beta[q];
+                const R b = spec ? Pi.beta[q] : R(1);
                 if (b == R(0)) continue;
                 R Rr, Tt;
                 slab_RT<R>(cos_i, gld(lam + j), thick, gld(nn + j), gld(kk + j), gld(tt + j), Rr, Tt);
                 const R rt = Rr + Tt;
                 R bn = b * rt;
-                if (bn < thr) bn = R(0);
+                if (g * bn < thr) bn = R(0);
                 Pi.beta[q] = bn;
                 if (bn == R(0)) continue;
                 if (rt > R(0) && u0 < Rr / rt) {
@@ -742,8 +798,12 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, cons
             fork = anyR && anyT;
             if (anyR && !anyT) dnew = drefl;
         }
-        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3);
+        n_fork += fork ? 1u : 0u;
+        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3, g,
+                      s_cnt, s_base);
     }
+    for (int off = 32; off > 0; off >>= 1) n_fork += __shfl_xor(n_fork, off);
+    if (lane == 0 && n_fork) atomicAdd(&w.cnt->forks, (unsigned long long)n_fork);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,7 +901,8 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *jobs,
                 w.bw[v.i] = R(wl);
             } else {
                 const size_t q = aosoa(v.i, (int)j, w.nbmax);
-                Pi.beta[q] = Pi.beta[q] * R(Rr + Tt);
+                const R b = (Pi.smp[v.i] & kSpectral) ? Pi.beta[q] : R(1);
+                Pi.beta[q] = b * R(Rr + Tt);
                 w.bratio[q] = R(Rr / (Rr + Tt));
             }
         }
@@ -911,7 +972,8 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *jobs,
             w.bw[v.i] = y[2];
         } else {
             const size_t q = aosoa(v.i, (int)j, w.nbmax);
-            Pi.beta[q] = Pi.beta[q] * (y[0] + y[1]);
+            const double b = (Pi.smp[v.i] & kSpectral) ? Pi.beta[q] : 1.0;
+            Pi.beta[q] = b * (y[0] + y[1]);
             w.bratio[q] = y[0] / (y[0] + y[1]);
         }
     }
@@ -931,26 +993,30 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, con
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
-        const bool active = base + lane < count;
+    __shared__ uint32_t s_cnt[(kBlock / 64) * 2], s_base[2];
+    uint32_t n_fork = 0;
+    // block-strided: the block reserves its output slots together
+    for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
+        const bool active = base + threadIdx.x < count;
         uint32_t i = 0, aux = 0, pix = 0, smp = 0;
         int32_t tri = -1;
         V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x;
         uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
         bool keep = false, fork = false;
+        R g = R(0);
         BandDev bd = {0, 0, 0, 0};
         if (active) {
             V3<R> d, ng;
             R cos_i, thick;
-            const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, base + lane, d, ng, cos_i, thick);
+            const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, base + threadIdx.x, d, ng, cos_i, thick);
             i = v.i;
             bd = v.bd;
             tri = v.tri;
             aux = Pi.aux[i];
             pix = Pi.pix[i];
             smp = Pi.smp[i];
+            const bool spec = (smp & kSpectral) != 0u;
+            g = Pi.g[i];
             const int depth = (int)(aux & 0xffu);
             const JobDev *jb = v.jb;
             x = V3<R>{Pi.ox[i], Pi.oy[i], Pi.oz[i]} + w.ht[i] * d;
@@ -968,13 +1034,13 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, con
                 if (j < 32) m0 |= bit; else if (j < 64) m1 |= bit; else if (j < 96) m2 |= bit; else m3 |= bit;
             };
             if (v.mode == kBtdfExact) {
-                const WalkStream ws = {jb->seed, pix, smp, jb->job_word, (uint32_t)depth, true};
+                const WalkStream ws = {jb->seed, pix, smp & ~kSpectral, jb->job_word, (uint32_t)depth, true};
                 R ue[4];
                 walk_draw<R>(ws, 0, 0, ue);
                 const int pol = ue[1] < R(0.5) ? 0 : 1;
                 bool enter = false;
                 for (int j = 0; j < bd.nb; ++j) {
-                    if (Pi.beta[aosoa(i, j, nbm)] == R(0)) continue;
+                    if (spec && Pi.beta[aosoa(i, j, nbm)] == R(0)) continue;
                     R Rs, Rp;
                     fresnel_sp<R>(cos_i, gld(nn + j), gld(kk + j), Rs, Rp);
                     if (ue[0] < (pol == 0 ? Rs : Rp)) set_bit(j);
@@ -991,7 +1057,7 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, con
                 m0 = m1 = m2 = m3 = 0;
                 for (int j = 0; j < bd.nb; ++j) {
                     const size_t q = aosoa(i, j, nbm);
-                    const R b = Pi.beta[q];
+                    const R b = spec ? Pi.beta[q] : R(1);
                     if (b == R(0)) continue;
                     const uint32_t word = j < 32 ? r0 : j < 64 ? r1 : j < 96 ? r2 : r3;
                     const bool refl = (word >> (j & 31)) & 1u;
@@ -1002,21 +1068,21 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, con
                         const R alpha = R(12.566370614359172) * gld(kk + j) / (gld(lam + j) * R(1e-6)) + gld(tt + j);
                         bn = b * exp(-alpha * wo.L);
                     }
-                    if (bn < thr) bn = R(0);
+                    if (g * bn < thr) bn = R(0);
                     Pi.beta[q] = bn;
                     if (bn == R(0)) continue;
                     if (refl) { anyR = true; set_bit(j); }
                     else anyT = true;
                 }
             } else {
-                const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp, depth, 0);
+                const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
                 const R u0 = u01<R>(rr.x);
                 dnew = lobe_dir<R>(d, w.bw[i], u01<R>(rr.y), u01<R>(rr.z));
                 for (int j = 0; j < bd.nb; ++j) {
                     const size_t q = aosoa(i, j, nbm);
                     R bn = Pi.beta[q];
                     if (bn == R(0)) continue;
-                    if (bn < thr) { Pi.beta[q] = R(0); continue; }
+                    if (g * bn < thr) { Pi.beta[q] = R(0); continue; }
                     if (u0 < w.bratio[q]) { anyR = true; set_bit(j); }
                     else anyT = true;
                 }
@@ -1025,8 +1091,12 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, con
             fork = anyR && anyT;
             if (anyR && !anyT) dnew = drefl;
         }
-        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3);
+        n_fork += fork ? 1u : 0u;
+        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3, g,
+                      s_cnt, s_base);
     }
+    for (int off = 32; off > 0; off >>= 1) n_fork += __shfl_xor(n_fork, off);
+    if (lane == 0 && n_fork) atomicAdd(&w.cnt->forks, (unsigned long long)n_fork);
 }
 
 // ---------------------------------------------------------------------------
@@ -1102,7 +1172,8 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
 }
 
 // Per wavelength: the record's contribution times the slab transmittance of
-// each pane crossed (at the sun angle, thickness at the crossing), summed
+// each pane crossed (at the sun angle, thickness at the crossing) -- or, for
+// the sky record of an escaped path, its weight times the sky radiance -- summed
 // over runs of lanes of the same pixel, added to the FP64 accumulator.  Each
 // wave walks a contiguous range of records and compacts the unoccluded ones
 // in LDS (order kept, so runs of one pixel stay together) before the
@@ -1111,7 +1182,11 @@ template <class R>
 __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, const BandDev *bands, Work<R> w)
 {
     __shared__ uint32_t s_buf[kBlock / 64][128];
-    const uint32_t count = min(w.cnt->scount, w.cap);
+    // sun records [0, ns), then the sky records of escaped paths stored from
+    // the back of the buffer (one record per path, so the ranges are disjoint)
+    const uint32_t ns = min(w.cnt->scount, w.cap);
+    const uint32_t nk = min(w.cnt->kcount, w.cap - ns);
+    const uint32_t count = ns + nk;
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -1124,9 +1199,10 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, con
     for (;;) {
         while (nbuf < 64 && base < r1) {
             const uint32_t i = base + lane;
-            const bool ok = i < r1 && w.socc[i] >= 0;
+            const uint32_t rec_i = i < ns ? i : w.cap - 1u - (i - ns);
+            const bool ok = i < r1 && (i >= ns || w.socc[i] >= 0);
             const uint64_t m = __ballot(ok);
-            if (ok) buf[nbuf + (uint32_t)__popcll(m & lt)] = i;
+            if (ok) buf[nbuf + (uint32_t)__popcll(m & lt)] = rec_i;
             nbuf += (uint32_t)__popcll(m);
             base += 64;
         }
@@ -1136,18 +1212,26 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, con
         const bool act = lane < take;
         const uint32_t rec = act ? buf[lane] : 0u;
         int ng = -1, nb = 0;
+        bool spec = false;
+        R scs = R(0);
         uint64_t key0 = ~0ull;
         const JobDev *jb = nullptr;
         BandDev bd = {0, 0, 0, 0};
         R gc[kMaxGlass], gd[kMaxGlass], gs[kMaxGlass];
         int gm[kMaxGlass];
+        const R *spectrum = nullptr;   // sun irradiance, or sky radiance for sky records
         if (act) {
-            ng = w.socc[rec];
+            const bool sky = rec >= ns;
+            ng = sky ? 0 : w.socc[rec];
             const uint32_t aux = w.saux[rec];
             jb = &jobs[aux >> kAuxJobShift];
             bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
             nb = bd.nb;
-            key0 = jb->acc_off + (uint64_t)w.spix[rec] * jb->nl + bd.l0;
+            const uint32_t sp = w.spix[rec];
+            spec = (sp & kSpectral) != 0u;
+            scs = w.scs[rec];
+            key0 = jb->acc_off + (uint64_t)(sp & ~kSpectral) * jb->nl + bd.l0;
+            spectrum = (const R *)(sky ? jb->Lsky : jb->E) + bd.l0;
             const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
 #pragma unroll
             for (int g = 0; g < kMaxGlass; ++g) {
@@ -1177,7 +1261,8 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, con
             for (int q = 0; q < 4; ++q) {
                 v[q] = 0.0;
                 if (j + q < nb) {
-                    R T = w.contrib[aosoa(rec, j + q, nbm)];
+                    R T = scs * gld(spectrum + j + q);
+                    if (spec) T *= w.contrib[aosoa(rec, j + q, nbm)];
                     for (int g = 0; g < ng; ++g) {
                         const size_t mo = (size_t)gm[g] * jb->nl + bd.l0 + j + q;
                         R Rr, Tt;
@@ -1246,11 +1331,12 @@ __global__ void k_zero_counters(Counters *c)
         c->r0 = 0;
         c->lds_job = 0;
         c->count[0] = c->count[1] = 0;
-        c->scount = 0;
+        c->scount = c->kcount = 0;
         c->tfetch = c->sfetch = 0;
         c->overflow = 0;
         c->gcount = c->bcount = 0;
         c->closest = c->shadow = c->forks = c->bubbly = 0;
+        c->spec_paths = c->spec_records = 0;
         c->nodes[0] = c->nodes[1] = c->tris[0] = c->tris[1] = 0;
     }
 }

@@ -61,6 +61,7 @@ class Stats(C.Structure):
                 ("closest_segments", C.c_uint64), ("shadow_segments", C.c_uint64),
                 ("forks", C.c_uint64), ("chunks", C.c_uint64), ("nodes_visited", C.c_uint64 * 2),
                 ("tris_tested", C.c_uint64 * 2), ("bubbly_vertices", C.c_uint64),
+                ("spectral_paths", C.c_uint64), ("spectral_records", C.c_uint64),
                 ("ms_render", C.c_double), ("kernel_ms", C.c_double * 9),
                 ("kernel_launches", C.c_uint64 * 9)]
 
@@ -70,6 +71,8 @@ class Stats(C.Structure):
         d["nodes_visited"] = {"closest": int(self.nodes_visited[0]), "shadow": int(self.nodes_visited[1])}
         d["tris_tested"] = {"closest": int(self.tris_tested[0]), "shadow": int(self.tris_tested[1])}
         d["bubbly_vertices"] = int(self.bubbly_vertices)
+        d["spectral_paths"] = int(self.spectral_paths)
+        d["spectral_records"] = int(self.spectral_records)
         d["kernel_ms"] = {k: self.kernel_ms[i] for i, k in enumerate(KERNELS)}
         d["kernel_launches"] = {k: int(self.kernel_launches[i]) for i, k in enumerate(KERNELS)}
         return d

@@ -211,6 +211,15 @@ def test_nave_small_fp64_and_fp32(gpu, orc, nave):
     assert tol_ok(g32, ref).mean() >= 0.99
     assert abs(g32.mean() - ref.mean()) <= 1e-5 * ref.mean()
     assert s64["forks"] > 0
+    # the mixed-precision report: FP64 kernels exact to tolerance, FP32 with
+    # a few path flips and an unbiased mean
+    from paper_1912_05494_amd.report import error_report
+    r64, r32 = error_report(g64, ref), error_report(g32, ref)
+    print("error report fp64", r64, "fp32", r32)
+    assert r64["flips"] == 0 and r64["max_rel"] <= 1e-4
+    assert r32["frac_within_tol"] >= 0.99 and abs(r32["mean_ratio"] - 1) <= 1e-5
+    # gray walls: most paths carry one weight for every wavelength
+    assert 0 < s32["spectral_paths"] < s32["closest_segments"]
     # spectral sub-domains give the same image
     g16, _, _ = render_np(gpu, nave, st, n_bands=16)
     assert np.allclose(g16, g32, rtol=1e-6, atol=0)

@@ -423,7 +423,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         const uint64_t cap64 = ((chunk + (chunk >> 2) * (1ull << attempt) + 1024 + 63) / 64) * 64;
         if (cap64 >= (1ull << 31)) return fail(ctx, SDM_E_NOMEM, "path pool would exceed 2^31 slots");
         const uint32_t cap = (uint32_t)cap64;
-        const int nb = plan.nbmax;
+        const int nb = (plan.nbmax + 3) & ~3;   // per-wavelength row, 16-byte aligned
         const size_t plane = (size_t)cap * sizeof(R);
         const size_t pool_b = 7 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) + 8 * 256;
         const size_t hit_b = 3 * plane + 2 * (size_t)cap * 4;

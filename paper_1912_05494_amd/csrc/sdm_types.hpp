@@ -103,13 +103,14 @@ struct alignas(256) Counters {
     unsigned long long nodes[2], tris[2];   // traversal work [closest, shadow]
 };
 
-// Per-wavelength arrays use an AoSoA layout: the values of wavelength j for
-// the 64 paths of block b = slot / 64 are contiguous, and a block holds all
-// nb_max wavelengths, so a wave that works on 64 consecutive slots touches one
-// contiguous region.
+// Per-wavelength arrays are slot-major: the nb_max values of a slot are
+// contiguous (nb_max is a multiple of 4, so every row is 16-byte aligned).
+// The per-wavelength factors are touched only at sparse slots (glass
+// vertices, spectral paths and records), so each lane reads and writes one
+// contiguous row rather than a word in every 64-slot block.
 __host__ __device__ __forceinline__ size_t aosoa(uint32_t slot, int j, int nbmax)
 {
-    return ((size_t)(slot >> 6) * (size_t)nbmax + (size_t)j) * 64u + (slot & 63u);
+    return (size_t)slot * (size_t)nbmax + (size_t)j;
 }
 
 // Path pool (SoA).  Two pools alternate: shade reads one and writes the
@@ -154,7 +155,7 @@ struct Work {
     double *acc;
     Counters *cnt;
     uint32_t cap;               // slots of each pool and of the record buffer
-    int32_t nbmax;              // per-wavelength stride of the AoSoA arrays
+    int32_t nbmax;              // row length of the per-wavelength arrays (band size rounded up to 4)
     int32_t *gstack;            // traversal stack overflow (global)
 };
 

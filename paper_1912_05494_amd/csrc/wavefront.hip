@@ -617,24 +617,24 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
                 Po.g[om] = (!out_spec && gn < thr) ? R(0) : gn;
             }
             if (out_spec) {
+                // rows are 16-byte aligned and padded to a multiple of 4: move
+                // four wavelengths per load and store (the padding is unused)
                 const R *rho = (const R *)jb->rho + (size_t)mat * jb->nl + bd.l0;
-                const R *__restrict__ bin = Pi.beta;
-                R *__restrict__ bout = Po.beta;
-                R *__restrict__ cout = w.contrib;
-                // eight wavelengths per round: all loads issued before the stores
-                for (int j = 0; j < bd.nb; j += 8) {
-                    R f[8];
+                const R *__restrict__ bin = Pi.beta + aosoa(i, 0, nbm);
+                R *__restrict__ bout = Po.beta + aosoa(om, 0, nbm);
+                R *__restrict__ cout = w.contrib + aosoa(sslot, 0, nbm);
+                for (int j = 0; j < bd.nb; j += 4) {
+                    Vec4<R> f;
+                    if (spec) f = row_load4(bin + j);
+                    else f.v[0] = f.v[1] = f.v[2] = f.v[3] = R(1);
+                    if (!gray)
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int jj = j + q < bd.nb ? j + q : bd.nb - 1;
-                        const R b = spec ? bin[aosoa(i, jj, nbm)] : R(1);
-                        f[q] = gray ? b : b * gld(rho + jj);
-                    }
+                        for (int q = 0; q < 4; ++q) f.v[q] *= gld(rho + min(j + q, bd.nb - 1));
+                    if (want_shadow) row_store4(cout + j, f);
+                    if (keep) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        if (j + q >= bd.nb) break;
-                        if (want_shadow) cout[aosoa(sslot, j + q, nbm)] = f[q];
-                        if (keep) bout[aosoa(om, j + q, nbm)] = (gn * f[q] < thr) ? R(0) : f[q];
+                        for (int q = 0; q < 4; ++q) f.v[q] = (gn * f.v[q] < thr) ? R(0) : f.v[q];
+                        row_store4(bout + j, f);
                     }
                 }
             }
@@ -649,7 +649,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const Band
             w.saux[r] = aux;
             w.scs[r] = g;
             if (spec) {
-                for (int j = 0; j < bd.nb; ++j) w.contrib[aosoa(r, j, nbm)] = Pi.beta[aosoa(i, j, nbm)];
+                for (int j = 0; j < bd.nb; j += 4)
+                    row_store4(w.contrib + aosoa(r, j, nbm), row_load4(Pi.beta + aosoa(i, j, nbm)));
                 ++n_srec;
             }
         }
@@ -700,21 +701,22 @@ __device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, 
         Po.g[of] = g;
     }
     if (keep) {
-        const R *__restrict__ bin = Pi.beta;
-        R *__restrict__ bout = Po.beta;
-        for (int j = 0; j < nb; j += 8) {
-            R bn[8];
+        const R *__restrict__ bin = Pi.beta + aosoa(i, 0, nbm);
+        R *__restrict__ bk = Po.beta + aosoa(om, 0, nbm);
+        R *__restrict__ bf = Po.beta + aosoa(fork ? of : om, 0, nbm);
+        for (int j = 0; j < nb; j += 4) {
+            const Vec4<R> b = row_load4(bin + j);
+            Vec4<R> k4 = b, f4 = b;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) bn[q] = j + q < nb ? bin[aosoa(i, j + q, nbm)] : R(0);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 4; ++q) {
                 const int jj = j + q;
-                if (jj >= nb) break;
                 const uint32_t word = jj < 32 ? m0 : jj < 64 ? m1 : jj < 96 ? m2 : m3;
                 const bool refl = (word >> (jj & 31)) & 1u;
-                bout[aosoa(om, jj, nbm)] = (fork && refl) ? R(0) : bn[q];
-                if (fork) bout[aosoa(of, jj, nbm)] = refl ? bn[q] : R(0);
+                k4.v[q] = (fork && refl) ? R(0) : b.v[q];
+                f4.v[q] = refl ? b.v[q] : R(0);
             }
+            row_store4(bk + j, k4);
+            if (fork) row_store4(bf + j, f4);
         }
     }
 }

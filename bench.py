@@ -31,7 +31,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 # Plain VALU issue rate of FP32 arithmetic without packed math:
 # 256 CUs x 64 lanes x 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s.
 ALU_PEAK_TFLOPS = 78.6
-FLOPS_PER_NODE = 48     # two slab box tests (6 sub, 6 mul, 12 min/max each)
+FLOPS_PER_NODE = 96     # four slab box tests per wide node (6 sub, 6 mul, 12 min/max each)
 FLOPS_PER_TRI = 50      # Moeller-Trumbore: edges, two cross products, four dots, reciprocal
 
 
@@ -47,7 +47,7 @@ def kernel_models(stats, nb, npix, nl):
                     per spectral record; forks 44 + 4 nb B
       shadow_accum  16 B per record plus 4 nb B per spectral record
       finalize      12 nl + 24 B per pixel
-    Traversal (trace, shadow) counts 48 flop per node visited and 50 per
+    Traversal (trace, shadow) counts 96 flop per wide node visited and 50 per
     triangle tested; the network 2 x 9216 flop per (vertex, wavelength)."""
     Ng, Nc, Ns, F = stats["paths"], stats["closest_segments"], stats["shadow_segments"], stats["forks"]
     Nsp, Nsr = stats.get("spectral_paths", 0), stats.get("spectral_records", 0)
@@ -438,6 +438,9 @@ def main():
         "segments_per_s": (s["closest_segments"] + s["shadow_segments"]) * args.steps / dt,
         "distinct_rays_per_step": {"closest": s["closest_segments"], "shadow": s["shadow_segments"],
                                    "forks": s["forks"]},
+        "traversal_per_ray": {k: {"nodes": s["nodes_visited"][k] / max(1, s[seg]),
+                                  "tris": s["tris_tested"][k] / max(1, s[seg])}
+                              for k, seg in (("closest", "closest_segments"), ("shadow", "shadow_segments"))},
         "graph_replay": {"ms_per_step": graph_ms, "value": samples / (graph_ms * 1e-3)},
         "chunk_paths": chunk, "tile": list(tile), "autotune": tuned,
     }

@@ -201,6 +201,7 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
                     kMaxLeafTris);
     }
     sc->depth = bvh.depth;
+    sc->stack = bvh.stack;
     sc->n_nodes = (int32_t)bvh.nodes.size();
     std::vector<TriDev> tris(d->nt);
     std::vector<float4> thick(d->nt);
@@ -351,7 +352,7 @@ int sdm_debug_intersect(sdm_context *ctx, const sdm_scene *sc, int64_t m, const 
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
-    HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * kGlobalStack * sizeof(int32_t)));
+    HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * global_stack_levels(sc->stack) * sizeof(int32_t)));
     HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
     launch_zero_counters(ctx->counters.as<Counters>(), s);
     launch_debug_intersect(sc->dev, (uint32_t)m, o, d, skip, sc->orig_to_leaf.as<int32_t>(), t, tri, uv,
@@ -376,7 +377,7 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const flo
     HIPCHK(ctx, hipMemcpyAsync(lam, &lambda_nm, sizeof(float), hipMemcpyHostToDevice, s));
     launch_resample<float>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lam, 1, tabs, s);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
-    HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * kGlobalStack * sizeof(int32_t)));
+    HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * global_stack_levels(sc->stack) * sizeof(int32_t)));
     HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
     launch_zero_counters(ctx->counters.as<Counters>(), s);
     launch_debug_shadow(sc->dev, (uint32_t)m, o, skip, sc->orig_to_leaf.as<int32_t>(), lambda_nm, tabs + nm,

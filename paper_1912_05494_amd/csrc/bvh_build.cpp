@@ -1,7 +1,8 @@
-// bvh_build.cpp -- host BVH2 builder: binned surface-area heuristic over the
-// three axes, leaves of at most kLeafMax triangles, depth capped so the
-// traversal stack bound always holds, output in breadth-first order (the top
-// levels form an index prefix the traversal kernels stage in LDS).
+// bvh_build.cpp -- host BVH builder: a binary tree by the binned surface-area
+// heuristic over the three axes (leaves of at most kLeafMax triangles, depth
+// capped), collapsed into 4-wide nodes by opening the largest-area inner
+// child until a node has four children, output in breadth-first order (the
+// top levels form an index prefix the traversal kernels stage in LDS).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -157,24 +158,51 @@ struct Builder {
     }
 };
 
-void set_child(BvhNode &g, int which, const Box &b, int32_t c, int32_t n, float pad_abs)
+void set_child(BvhNode &g, int which, const Box &b, int32_t entry, float pad_abs)
 {
-    float *lo = which == 0 ? g.lo0 : g.lo1;
-    float *hi = which == 0 ? g.hi0 : g.hi1;
-    if (c < 0 || b.empty()) {
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = std::numeric_limits<float>::infinity();
-            hi[a] = -std::numeric_limits<float>::infinity();
-        }
-        if (which == 0) { g.c0 = -1; g.n0 = 0; } else { g.c1 = -1; g.n1 = 0; }
+    if (entry == kNoChild || b.empty()) {
+        g.lox[which] = g.loy[which] = g.loz[which] = std::numeric_limits<float>::infinity();
+        g.hix[which] = g.hiy[which] = g.hiz[which] = -std::numeric_limits<float>::infinity();
+        g.child[which] = kNoChild;
         return;
     }
+    float lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
         const float p = pad_abs + 1e-5f * std::max(std::fabs(b.lo[a]), std::fabs(b.hi[a]));
         lo[a] = b.lo[a] - p;
         hi[a] = b.hi[a] + p;
     }
-    if (which == 0) { g.c0 = c; g.n0 = n; } else { g.c1 = c; g.n1 = n; }
+    g.lox[which] = lo[0]; g.loy[which] = lo[1]; g.loz[which] = lo[2];
+    g.hix[which] = hi[0]; g.hiy[which] = hi[1]; g.hiz[which] = hi[2];
+    g.child[which] = entry;
+}
+
+int32_t leaf_entry(const TNode &n) { return -1 - ((n.first << 8) | n.count); }
+
+// Children of the wide node rooted at binary node t: start from its two
+// children and open the inner child of largest surface area until there are
+// four or only leaves remain.
+int collapse(const std::vector<TNode> &nodes, int32_t t, int32_t (&kids)[4])
+{
+    int nk = 2;
+    kids[0] = nodes[t].left;
+    kids[1] = nodes[t].right;
+    while (nk < 4) {
+        int best = -1;
+        double best_area = -1.0;
+        for (int i = 0; i < nk; ++i) {
+            const TNode &c = nodes[kids[i]];
+            if (!c.leaf() && c.box.area() > best_area) {
+                best_area = c.box.area();
+                best = i;
+            }
+        }
+        if (best < 0) break;
+        const TNode &c = nodes[kids[best]];
+        kids[best] = c.left;
+        kids[nk++] = c.right;
+    }
+    return nk;
 }
 
 }  // namespace
@@ -202,50 +230,73 @@ BvhResult build_bvh(const float *pos, int32_t nv, const int32_t *idx, int32_t nt
     B.nodes.reserve(2 * (size_t)nt);
     const int32_t root = B.build(0, nt, 0);
     out.ok = !B.too_big;
+    out.order = B.prims;
     double diag = 0.0;
     for (int a = 0; a < 3; ++a) diag += double(scene.hi[a] - scene.lo[a]) * (scene.hi[a] - scene.lo[a]);
     diag = std::sqrt(diag);
     const float pad_abs = (float)(1e-5 * diag) + 1e-30f;
 
-    // Breadth-first emission of inner nodes; leaves live in their parent.
-    std::vector<int32_t> gidx(B.nodes.size(), -1);
-    std::deque<int32_t> q;
-    std::vector<int32_t> inner;
-    if (!B.nodes[root].leaf()) {
-        q.push_back(root);
-        while (!q.empty()) {
-            const int32_t t = q.front();
-            q.pop_front();
-            gidx[t] = (int32_t)inner.size();
-            inner.push_back(t);
-            for (int32_t ch : {B.nodes[t].left, B.nodes[t].right})
-                if (!B.nodes[ch].leaf()) q.push_back(ch);
-        }
-    }
-    out.order = B.prims;
-    if (inner.empty()) {
+    if (B.nodes[root].leaf()) {   // one leaf: a single node with one child
         BvhNode g;
         std::memset(&g, 0, sizeof(g));
-        set_child(g, 0, B.nodes[root].box, 0, B.nodes[root].count, pad_abs);
-        set_child(g, 1, Box(), -1, 0, pad_abs);
+        set_child(g, 0, B.nodes[root].box, leaf_entry(B.nodes[root]), pad_abs);
+        for (int w = 1; w < 4; ++w) set_child(g, w, Box(), kNoChild, pad_abs);
         out.nodes.push_back(g);
-        out.depth = 1;
+        out.depth = 2;
+        out.stack = 0;
         return out;
     }
-    out.nodes.resize(inner.size());
-    for (size_t i = 0; i < inner.size(); ++i) {
-        const TNode &n = B.nodes[inner[i]];
+    // Breadth-first emission of wide nodes; leaves live in their parent.
+    struct Wide {
+        int32_t kids[4];
+        int nk, level;
+    };
+    std::vector<Wide> wide;
+    std::vector<int32_t> gidx(B.nodes.size(), -1);
+    std::deque<std::pair<int32_t, int>> q;
+    q.push_back({root, 0});
+    gidx[root] = 0;
+    int32_t next = 1;
+    while (!q.empty()) {
+        const auto [t, level] = q.front();
+        q.pop_front();
+        Wide wn;
+        wn.level = level;
+        wn.nk = collapse(B.nodes, t, wn.kids);
+        for (int i = 0; i < wn.nk; ++i)
+            if (!B.nodes[wn.kids[i]].leaf()) {
+                gidx[wn.kids[i]] = next++;
+                q.push_back({wn.kids[i], level + 1});
+            }
+        wide.push_back(wn);
+    }
+    out.nodes.resize(wide.size());
+    std::vector<int> need(wide.size(), 0);
+    for (size_t i = wide.size(); i-- > 0;) {   // children come after their parent
+        const Wide &wn = wide[i];
         BvhNode g;
         std::memset(&g, 0, sizeof(g));
-        const int32_t ch[2] = {n.left, n.right};
-        for (int w = 0; w < 2; ++w) {
-            const TNode &c = B.nodes[ch[w]];
-            if (c.leaf()) set_child(g, w, c.box, c.first, c.count, pad_abs);
-            else set_child(g, w, c.box, gidx[ch[w]], 0, pad_abs);
+        int deeper = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w >= wn.nk) {
+                set_child(g, w, Box(), kNoChild, pad_abs);
+                continue;
+            }
+            const TNode &c = B.nodes[wn.kids[w]];
+            if (c.leaf()) {
+                set_child(g, w, c.box, leaf_entry(c), pad_abs);
+            } else {
+                set_child(g, w, c.box, gidx[wn.kids[w]], pad_abs);
+                deeper = std::max(deeper, need[gidx[wn.kids[w]]]);
+            }
         }
+        // a walk at this node keeps at most nk - 1 siblings on the stack while
+        // it descends into one child
+        need[i] = wn.nk - 1 + deeper;
         out.nodes[i] = g;
+        out.depth = std::max(out.depth, wn.level + 2);
     }
-    out.depth = B.max_depth;
+    out.stack = need[0];
     return out;
 }
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/sdm.h"
+#include "bvh_build.hpp"
 #include "runtime.hpp"
 #include "sdm_types.hpp"
 #include "surrogate.hpp"
@@ -212,7 +213,8 @@ struct ChunkArgs {
     const float *bb, *params, *E;
     uint64_t total;
     uint32_t chunk;
-    int32_t n_items, depth, lds_job, surr, bubbly, grid_t, grid_st, grid_s, grid_g, grid_e, prec;
+    int32_t n_items, depth, lds_job, surr, bubbly, prec;
+    int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
 };
 
 template <class R>
@@ -232,7 +234,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         launch_shade<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
         done();
         mark(SDM_K_SHADE_GLASS);
-        launch_shade_glass<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
+        launch_shade_glass<R>(a.jobs, a.bands, a.w, cur, a.grid_gl, s);
         done();
         if (a.surr) {
             mark(SDM_K_BUBBLY_EVAL);
@@ -241,14 +243,14 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         }
         if (a.bubbly) {
             mark(SDM_K_SHADE_BUBBLY);
-            launch_shade_bubbly<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
+            launch_shade_bubbly<R>(a.jobs, a.bands, a.w, cur, a.grid_b, s);
             done();
         }
         mark(SDM_K_SHADOW);
         launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.grid_st, s);
         done();
         mark(SDM_K_SHADOW_ACCUM);
-        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.grid_s, s);
+        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.grid_a, s);
         done();
         cur ^= 1;
     }
@@ -435,13 +437,18 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         HIPCHK(ctx, ctx->acc.ensure((size_t)acc_off[nj] * sizeof(double)));
         HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
         ChunkArgs<R> a{};
-        a.grid_t = ctx->num_cu * occupancy_trace<R>();
-        a.grid_st = ctx->num_cu * occupancy_shadow<R>();
-        a.grid_s = ctx->num_cu * occupancy_shade<R>();
+        a.grid_t = ctx->num_cu * occupancy<R>(SDM_K_TRACE);
+        a.grid_s = ctx->num_cu * occupancy<R>(SDM_K_SHADE);
+        a.grid_gl = ctx->num_cu * occupancy<R>(SDM_K_SHADE_GLASS);
+        a.grid_e = ctx->num_cu * occupancy<R>(SDM_K_BUBBLY_EVAL);
+        a.grid_b = ctx->num_cu * occupancy<R>(SDM_K_SHADE_BUBBLY);
+        a.grid_st = ctx->num_cu * occupancy<R>(SDM_K_SHADOW);
+        a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM);
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
-        a.grid_e = ctx->num_cu * (sizeof(R) == 4 ? 2 : 4);
         const size_t gthreads = (size_t)std::max(a.grid_t, a.grid_st) * block_size();
-        HIPCHK(ctx, ctx->gstack.ensure(gthreads * kGlobalStack * sizeof(int32_t)));
+        int stack = 0;
+        for (const auto &jj : jobs) stack = std::max(stack, jj.sc->stack);
+        HIPCHK(ctx, ctx->gstack.ensure(gthreads * global_stack_levels(stack) * sizeof(int32_t)));
         Work<R> &w = a.w;
         char *pb = nullptr;
         auto take = [&](size_t bytes) { char *r = pb; pb += (bytes + 255) / 256 * 256; return r; };

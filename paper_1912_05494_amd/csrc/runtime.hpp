@@ -79,6 +79,7 @@ struct sdm_scene {
     sdm::SceneDev dev{};
     DevBuf nodes, tris, thick, mat_type, mat_thick, mat_bub, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
     int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
+    int32_t stack = 0;          // most traversal stack entries a walk can hold
     int32_t max_pane = -1;      // largest pane type of a bubbly material (-1: none)
 };
 

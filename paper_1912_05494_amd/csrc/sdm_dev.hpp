@@ -227,22 +227,6 @@ __device__ __forceinline__ bool tri_hit(V3<R> o, V3<R> d, V3<R> p0, V3<R> p1, V3
     return true;
 }
 
-// Slab test against an axis-aligned box given the reciprocal direction; the
-// boxes are padded at build time, so rounding never loses a hit.
-template <class R>
-__device__ __forceinline__ bool box_hit(const float lo[3], const float hi[3], V3<R> o, V3<R> inv,
-                                        R tlo, R thi, R &tnear)
-{
-    R t1 = (R(lo[0]) - o.x) * inv.x, t2 = (R(hi[0]) - o.x) * inv.x;
-    R a = fmin(t1, t2), b = fmax(t1, t2);
-    t1 = (R(lo[1]) - o.y) * inv.y; t2 = (R(hi[1]) - o.y) * inv.y;
-    a = fmax(a, fmin(t1, t2)); b = fmin(b, fmax(t1, t2));
-    t1 = (R(lo[2]) - o.z) * inv.z; t2 = (R(hi[2]) - o.z) * inv.z;
-    a = fmax(a, fmin(t1, t2)); b = fmin(b, fmax(t1, t2));
-    tnear = a;
-    return a <= b && b >= tlo && a <= thi;
-}
-
 template <class R>
 __device__ __forceinline__ V3<R> safe_inv(V3<R> d)
 {

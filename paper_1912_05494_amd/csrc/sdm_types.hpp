@@ -5,16 +5,19 @@
 
 namespace sdm {
 
-// BVH2 node: the boxes of both children (so one node fetch tests two boxes)
-// and, per child, either an inner-node index (count 0), a leaf (first
-// triangle, count > 0) or nothing (index -1, count 0, empty box).  Nodes are
-// stored breadth-first so the top levels are a prefix that kernels stage in
-// LDS.  64 bytes = four 16-byte loads.
-struct alignas(16) BvhNode {
-    float lo0[3], hi0[3], lo1[3], hi1[3];
-    int32_t c0, c1, n0, n1;
+// Wide BVH node: the boxes of up to four children in SoA order (so one node
+// fetch tests four boxes with vector-friendly loads) and, per child, a
+// traversal entry: an inner-node index (>= 0), a leaf -1 - (first << 8 |
+// count) (<= -2), or kNoChild.  Nodes are stored breadth-first so the top
+// levels are an index prefix that kernels stage in LDS.  128 bytes, one
+// cache line; the last 16 bytes are padding.
+constexpr int32_t kNoChild = -1;
+struct alignas(128) BvhNode {
+    float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+    int32_t child[4];
+    int32_t pad[4];
 };
-static_assert(sizeof(BvhNode) == 64, "node layout");
+static_assert(sizeof(BvhNode) == 128, "node layout");
 
 // Triangle in BVH leaf order: the three vertices (exact float inputs, edges
 // are formed in the kernel's precision); a.w holds the caller's triangle
@@ -164,9 +167,8 @@ constexpr int kAuxBandShift = 8;
 constexpr int kAuxBandBits = 12;
 constexpr int kAuxJobShift = 20;
 constexpr int kMaxBand = 128;
-constexpr int kLdsStack = 12;      // traversal stack levels held in LDS
-constexpr int kGlobalStack = 52;   // further levels in global memory
-constexpr int kMaxBvhDepth = kLdsStack + kGlobalStack - 2;
+constexpr int kLdsStack = 12;      // traversal stack levels held in LDS; deeper ones in global memory
+constexpr int kMaxBvhDepth = 62;   // depth cap of the binary tree the wide nodes are collapsed from
 constexpr int kMaxLeafTris = 255;  // leaf size bound of the stack encoding
 constexpr int kMaxTris = 1 << 23;  // triangles per scene (stack encoding)
 

@@ -24,8 +24,10 @@
 // once the wavelengths' weights differ (kSpectral).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
+#include "../../include/sdm.h"
 #include "bubbly_dev.hpp"
 #include "mlp_dev.hpp"
 #include "sdm_dev.hpp"
@@ -33,7 +35,7 @@
 
 namespace sdm {
 
-constexpr int kLdsNodes = 128;    // BVH prefix staged in LDS (8 KB)
+constexpr int kLdsNodes = 64;     // wide-node prefix staged in LDS (8 KB)
 constexpr int kBlock = 256;
 constexpr uint32_t kFetch = 256;  // rays a traversal wave claims at a time
 constexpr int32_t kDone = INT_MIN;
@@ -75,6 +77,23 @@ struct Stack {
         --sp;
         return sp < kLdsStack ? lds[sp * kBlock + threadIdx.x] : glob[(size_t)(sp - kLdsStack) * gstride + gtid];
     }
+    // Pushes e[m], ..., e[1] (m <= 3), so that e[1] is popped first.  With
+    // three free LDS levels the three slots are written whatever m is (slots
+    // above the new top are dead), which keeps the lanes of a wave together.
+    __device__ __forceinline__ void push_sorted(int m, int32_t e1, int32_t e2, int32_t e3)
+    {
+        if (sp + 3 <= kLdsStack) {
+            int32_t *p = lds + sp * kBlock + threadIdx.x;
+            p[0] = m == 3 ? e3 : (m == 2 ? e2 : e1);
+            p[kBlock] = m == 3 ? e2 : e1;
+            p[2 * kBlock] = e1;
+            sp += m;
+        } else {
+            if (m == 3) push(e3);
+            if (m >= 2) push(e2);
+            if (m >= 1) push(e1);
+        }
+    }
 };
 
 __device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
@@ -88,44 +107,127 @@ __device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
     return st;
 }
 
-__device__ __forceinline__ int32_t leaf_code(int32_t first, int32_t cnt) { return -1 - ((first << 8) | cnt); }
-
-struct NodeView {
-    float lo0[3], hi0[3], lo1[3], hi1[3];
-    int32_t e0, e1;      // stack entries of the children (-1 - code for leaves)
-    bool v0, v1;         // child present
+// Wide-node fetch.  The first kLdsNodes nodes (the top levels, breadth-first)
+// are read from LDS, where the 16-byte word k of node i sits at
+// i * 8 + (k ^ (i & 7)): lanes reading the same word of different nodes then
+// fall into different bank groups.  The padding word (k = 7) is not read.
+struct WideNode {
+    float4 lox, hix, loy, hiy, loz, hiz;
+    int32_t c0, c1, c2, c3;   // child entries (separate values: an indexed array would go to scratch)
 };
 
-__device__ __forceinline__ NodeView load_node(const float4 *lds_nodes, int n_lds, const BvhNode *nodes, int i)
+__device__ __forceinline__ int lds_slot(int i, int k) { return i * 8 + (k ^ (i & 7)); }
+
+__device__ __forceinline__ WideNode load_node(const float4 *lds_nodes, int n_lds, const BvhNode *nodes, int i)
 {
-    float4 a, b, c, d;
+    float4 q[7];
     if (i < n_lds) {
-        a = lds_nodes[4 * i]; b = lds_nodes[4 * i + 1]; c = lds_nodes[4 * i + 2]; d = lds_nodes[4 * i + 3];
+        // byte address of word k: (i * 128 | (i & 7) * 16) ^ k * 16
+        const uint32_t a0 = ((uint32_t)i << 7) | (((uint32_t)i & 7u) << 4);
+        const char *base = reinterpret_cast<const char *>(lds_nodes);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) q[k] = *reinterpret_cast<const float4 *>(base + (a0 ^ ((uint32_t)k << 4)));
     } else {
-        const float4 *p = reinterpret_cast<const float4 *>(nodes) + 4 * (size_t)i;
-        a = gld4(p); b = gld4(p + 1); c = gld4(p + 2); d = gld4(p + 3);
+        const float4 *p = reinterpret_cast<const float4 *>(nodes) + 8 * (size_t)i;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) q[k] = gld4(p + k);
     }
-    NodeView v;
-    v.lo0[0] = a.x; v.lo0[1] = a.y; v.lo0[2] = a.z; v.hi0[0] = a.w;
-    v.hi0[1] = b.x; v.hi0[2] = b.y; v.lo1[0] = b.z; v.lo1[1] = b.w;
-    v.lo1[2] = c.x; v.hi1[0] = c.y; v.hi1[1] = c.z; v.hi1[2] = c.w;
-    const int32_t c0 = __float_as_int(d.x), c1 = __float_as_int(d.y);
-    const int32_t n0 = __float_as_int(d.z), n1 = __float_as_int(d.w);
-    v.v0 = n0 > 0 || c0 > 0;
-    v.v1 = n1 > 0 || c1 > 0;
-    v.e0 = n0 > 0 ? leaf_code(c0, n0) : c0;
-    v.e1 = n1 > 0 ? leaf_code(c1, n1) : c1;
-    return v;
+    WideNode n;
+    n.lox = q[0]; n.hix = q[1]; n.loy = q[2]; n.hiy = q[3]; n.loz = q[4]; n.hiz = q[5];
+    n.c0 = __float_as_int(q[6].x);
+    n.c1 = __float_as_int(q[6].y);
+    n.c2 = __float_as_int(q[6].z);
+    n.c3 = __float_as_int(q[6].w);
+    return n;
 }
 
 __device__ __forceinline__ int stage_nodes(float4 *lds_nodes, const SceneDev &sc)
 {
     const int n = min(sc.n_nodes, kLdsNodes);
     const float4 *src = reinterpret_cast<const float4 *>(sc.nodes);
-    for (int i = threadIdx.x; i < 4 * n; i += blockDim.x) lds_nodes[i] = gld4(src + i);
+    for (int x = threadIdx.x; x < 8 * n; x += blockDim.x) lds_nodes[lds_slot(x >> 3, x & 7)] = gld4(src + x);
     __syncthreads();
     return n;
 }
+
+__device__ __forceinline__ float f4get(const float4 &v, int c)
+{
+    return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ int32_t child_at(const WideNode &nd, int c)
+{
+    return c == 0 ? nd.c0 : c == 1 ? nd.c1 : c == 2 ? nd.c2 : nd.c3;
+}
+
+// Slab tests of the four child boxes against [tlo, thi]; tn is the entry
+// distance clamped to tlo.  The boxes are padded at build time, so rounding
+// never loses a hit.
+template <class R>
+__device__ __forceinline__ void box4(const WideNode &nd, V3<R> o, V3<R> inv, R tlo, R thi, R (&tn)[4],
+                                     bool (&hit)[4])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        R t1 = (R(f4get(nd.lox, c)) - o.x) * inv.x, t2 = (R(f4get(nd.hix, c)) - o.x) * inv.x;
+        const R ax = fmin(t1, t2), bx = fmax(t1, t2);
+        t1 = (R(f4get(nd.loy, c)) - o.y) * inv.y; t2 = (R(f4get(nd.hiy, c)) - o.y) * inv.y;
+        const R ay = fmin(t1, t2), by = fmax(t1, t2);
+        t1 = (R(f4get(nd.loz, c)) - o.z) * inv.z; t2 = (R(f4get(nd.hiz, c)) - o.z) * inv.z;
+        const R az = fmin(t1, t2), bz = fmax(t1, t2);
+        const R a = fmax(fmax(ax, ay), fmax(az, tlo));
+        const R b = fmin(fmin(bx, by), fmin(bz, thi));
+        tn[c] = a;
+        hit[c] = child_at(nd, c) != kNoChild && a <= b;
+    }
+}
+
+// Compare-exchange of (key, entry) pairs by key.
+__device__ __forceinline__ void cswap(uint32_t &ka, int32_t &ea, uint32_t &kb, int32_t &eb)
+{
+    const bool sw = kb < ka;
+    const uint32_t k = sw ? kb : ka;
+    const int32_t e = sw ? eb : ea;
+    kb = sw ? ka : kb;
+    eb = sw ? ea : eb;
+    ka = k;
+    ea = e;
+}
+
+// Children hit by the ray, nearest first: keys hold the entry distance's
+// bits with the child slot in the two low bits (distances are >= teps > 0, so
+// their bits order like the values; misses sort last); a five-exchange
+// sorting network orders the (key, entry) pairs.  Returns the hit count.
+template <class R>
+__device__ __forceinline__ int order_children(const WideNode &nd, const R (&tn)[4], const bool (&hit)[4],
+                                              int32_t (&e)[4])
+{
+    uint32_t k[4];
+    int nh = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        k[c] = hit[c] ? ((__float_as_uint((float)tn[c]) & ~3u) | (uint32_t)c) : 0xFFFFFFFFu;
+        e[c] = child_at(nd, c);
+        nh += hit[c] ? 1 : 0;
+    }
+    cswap(k[0], e[0], k[1], e[1]);
+    cswap(k[2], e[2], k[3], e[3]);
+    cswap(k[0], e[0], k[2], e[2]);
+    cswap(k[1], e[1], k[3], e[3]);
+    cswap(k[1], e[1], k[2], e[2]);
+    return nh;
+}
+
+template <class R>
+struct Ray {
+    V3<R> o, d, inv;
+    int32_t skip, cur;
+};
+
+template <class R>
+struct Closest {
+    R tb, ub, vb;
+    int32_t trib, orig_b;
+};
 
 template <class R>
 __device__ __forceinline__ R teps_of(const SceneDev &sc)
@@ -143,43 +245,28 @@ __device__ __forceinline__ TriDev load_tri(const TriDev *tris, int i)
     return t;
 }
 
-template <class R>
-struct Ray {
-    V3<R> o, d, inv;
-    int32_t skip, cur;
-};
-
-template <class R>
-struct Closest {
-    R tb, ub, vb;
-    int32_t trib, orig_b;
-};
-
-// One step of a closest-hit search: visit inner nodes nearest-first until a
-// leaf is due, test that leaf, and report whether the search is complete.
-// Ties in t go to the smaller caller triangle index, so the result does not
-// depend on the tree.
+// One step of a closest-hit search: visit nodes, entering the nearest child
+// box hit and stacking the others farthest first, until a leaf is due; test
+// that leaf and report whether the search is complete.  Ties in t go to the
+// smaller caller triangle index, so the result does not depend on the tree.
 template <class R>
 __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
                                              Ray<R> &ry, Closest<R> &h, R teps, uint32_t &nodes, uint32_t &tests)
 {
     int32_t cur = ry.cur;
     while (cur >= 0) {
-        const NodeView nv = load_node(lds_nodes, n_lds, sc.nodes, cur);
+        const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
         ++nodes;
-        R tn0, tn1;
-        const bool h0 = nv.v0 && box_hit(nv.lo0, nv.hi0, ry.o, ry.inv, teps, h.tb, tn0);
-        const bool h1 = nv.v1 && box_hit(nv.lo1, nv.hi1, ry.o, ry.inv, teps, h.tb, tn1);
-        if (h0 && h1) {
-            const bool f0 = tn0 <= tn1;
-            st.push(f0 ? nv.e1 : nv.e0);
-            cur = f0 ? nv.e0 : nv.e1;
-        } else if (h0) {
-            cur = nv.e0;
-        } else if (h1) {
-            cur = nv.e1;
-        } else {
+        R tn[4];
+        bool hit[4];
+        box4(nd, ry.o, ry.inv, teps, h.tb, tn, hit);
+        int32_t e[4];
+        const int nh = order_children(nd, tn, hit, e);
+        if (nh == 0) {
             cur = st.sp ? st.pop() : kDone;
+        } else {
+            st.push_sorted(nh - 1, e[1], e[2], e[3]);
+            cur = e[0];
         }
     }
     if (cur != kDone) {
@@ -203,9 +290,9 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
     return cur == kDone;
 }
 
-// One step of an any-hit walk toward +infinity: visit inner nodes until a leaf
-// is due and test it.  An opaque triangle ends the walk (occluded); each pane
-// crossed is reported to on_glass(leaf, u, v).
+// One step of an any-hit walk toward +infinity: visit nodes until a leaf is
+// due and test it.  An opaque triangle ends the
+// walk (occluded); each pane crossed is reported to on_glass(leaf, u, v).
 template <class R, class F>
 __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
                                             Ray<R> &ry, bool &occluded, R teps, F &&on_glass, uint32_t &nodes,
@@ -214,21 +301,21 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
     const R tinf = R(INFINITY);
     int32_t cur = ry.cur;
     while (cur >= 0) {
-        const NodeView nv = load_node(lds_nodes, n_lds, sc.nodes, cur);
+        const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
         ++nodes;
-        R tn0, tn1;
-        const bool h0 = nv.v0 && box_hit(nv.lo0, nv.hi0, ry.o, ry.inv, teps, tinf, tn0);
-        const bool h1 = nv.v1 && box_hit(nv.lo1, nv.hi1, ry.o, ry.inv, teps, tinf, tn1);
-        if (h0 && h1) {
-            st.push(nv.e1);
-            cur = nv.e0;
-        } else if (h0) {
-            cur = nv.e0;
-        } else if (h1) {
-            cur = nv.e1;
-        } else {
-            cur = st.sp ? st.pop() : kDone;
+        R tn[4];
+        bool hit[4];
+        box4(nd, ry.o, ry.inv, teps, tinf, tn, hit);
+        // any order finds every pane: enter the first child hit, stack the others
+        int32_t nxt = kDone;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!hit[c]) continue;
+            const int32_t e = child_at(nd, c);
+            if (nxt == kDone) nxt = e;
+            else st.push(e);
         }
+        cur = nxt != kDone ? nxt : (st.sp ? st.pop() : kDone);
     }
     if (cur != kDone) {
         const int32_t code = -1 - cur;
@@ -417,7 +504,7 @@ template <class R>
 __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w, int cur, int lds_job)
 {
     if (lds_job < -1) lds_job = w.cnt->lds_job;   // the job of the chunk's first path
-    __shared__ float4 s_nodes[4 * kLdsNodes];
+    __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1112,7 +1199,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
                                                          int lds_job)
 {
     if (lds_job < -1) lds_job = w.cnt->lds_job;
-    __shared__ float4 s_nodes[4 * kLdsNodes];
+    __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const uint32_t count = min(w.cnt->scount, w.cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->shadow += count;
@@ -1122,7 +1209,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
     Ray<R> ry;
     int64_t item = -1;
     int job = 0, ng = 0;
-    bool occ = false;
+    bool occ = false, over = false;
     R teps = R(0);
     uint32_t n_nodes = 0, n_tests = 0;
     for (;;) {
@@ -1140,6 +1227,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
             teps = teps_of<R>(sc);
             ng = 0;
             occ = false;
+            over = false;
             st.sp = 0;
         }
         if (!__ballot(item >= 0)) {
@@ -1152,7 +1240,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
                              shadow_step(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, occ, teps,
                                          [&](int leaf, R u, R v) {
                                              if (ng == kMaxGlass) {
-                                                 atomicOr(&w.cnt->overflow, 2u);
+                                                 over = true;
                                                  return;
                                              }
                                              w.sg_leaf[(size_t)rec * kMaxGlass + ng] = leaf;
@@ -1162,6 +1250,8 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
                                          },
                                          n_nodes, n_tests);
             if (fin) {
+                // an occluded walk needs no pane list, whatever the visiting order found first
+                if (over && !occ) atomicOr(&w.cnt->overflow, 2u);
                 w.socc[rec] = occ ? -1 : ng;
                 item = -1;
             }
@@ -1179,7 +1269,12 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
 // over runs of lanes of the same pixel, added to the FP64 accumulator.  Each
 // wave walks a contiguous range of records and compacts the unoccluded ones
 // in LDS (order kept, so runs of one pixel stay together) before the
-// per-wavelength loop, which then runs on full waves.
+// per-wavelength loop, which then runs on full waves.  Wave w takes the
+// 64-record groups w, w + W, w + 2W, ... (W waves): occlusion and pane counts
+// vary along the record buffer, so one contiguous range per wave would leave
+// most waves idle at the end, and a shared claim counter costs more than it
+// balances.
+
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, const BandDev *bands, Work<R> w)
 {
@@ -1193,20 +1288,17 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, con
     const uint32_t lane = lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
     uint32_t *buf = s_buf[threadIdx.x >> 6];
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t per = ((count + nwaves - 1) / nwaves + 63) / 64 * 64;
-    const uint32_t r0 = min(count, wave * per), r1 = min(count, r0 + per);
-    uint32_t base = r0, nbuf = 0;
+    uint32_t base = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64u, nbuf = 0;
     for (;;) {
-        while (nbuf < 64 && base < r1) {
+        while (nbuf < 64 && base < count) {
             const uint32_t i = base + lane;
             const uint32_t rec_i = i < ns ? i : w.cap - 1u - (i - ns);
-            const bool ok = i < r1 && (i >= ns || w.socc[i] >= 0);
+            const bool ok = i < count && (i >= ns || w.socc[i] >= 0);
             const uint64_t m = __ballot(ok);
             if (ok) buf[nbuf + (uint32_t)__popcll(m & lt)] = rec_i;
             nbuf += (uint32_t)__popcll(m);
-            base += 64;
+            base += 64u * nwaves;
         }
         __builtin_amdgcn_wave_barrier();
         if (nbuf == 0) break;
@@ -1389,7 +1481,7 @@ __global__ void __launch_bounds__(kBlock) k_debug_intersect(SceneDev sc, uint32_
                                                             float *t, int32_t *tri, float *uv, uint32_t *cursor,
                                                             int32_t *gstack)
 {
-    __shared__ float4 s_nodes[4 * kLdsNodes];
+    __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const int n_lds = stage_nodes(s_nodes, sc);
     Stack st = make_stack(s_stack, gstack);
@@ -1432,7 +1524,7 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
                                                          const float *n_at, const float *k_at, const float *t_at,
                                                          float *T, uint32_t *cursor, int32_t *gstack)
 {
-    __shared__ float4 s_nodes[4 * kLdsNodes];
+    __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const int n_lds = stage_nodes(s_nodes, sc);
     Stack st = make_stack(s_stack, gstack);
@@ -1584,25 +1676,28 @@ void launch_debug_shadow(const SceneDev &sc, uint32_t m, const float *o, const i
 
 int block_size() { return kBlock; }
 
+// Resident blocks per CU of each render kernel: every pass is launched with
+// exactly the blocks the chip holds at once, so no block waits for a second
+// round while the others idle.
 template <class R>
-int occupancy_trace()
+int occupancy(int kernel_class)
 {
+    const void *f = nullptr;
+    switch (kernel_class) {
+    case SDM_K_TRACE: f = (const void *)k_trace<R>; break;
+    case SDM_K_SHADE: f = (const void *)k_shade<R>; break;
+    case SDM_K_SHADE_GLASS: f = (const void *)k_shade_glass<R>; break;
+    case SDM_K_BUBBLY_EVAL:
+        if constexpr (sizeof(R) == 4) f = (const void *)k_bubbly_eval_mfma<R>;
+        else f = (const void *)k_bubbly_eval_fp64;
+        break;
+    case SDM_K_SHADE_BUBBLY: f = (const void *)k_shade_bubbly<R>; break;
+    case SDM_K_SHADOW: f = (const void *)k_shadow_trace<R>; break;
+    case SDM_K_SHADOW_ACCUM: f = (const void *)k_shadow_accum<R>; break;
+    default: return 1;
+    }
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace<R>, kBlock, 0) != hipSuccess) return 1;
-    return std::max(1, b);
-}
-template <class R>
-int occupancy_shadow()
-{
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_shadow_trace<R>, kBlock, 0) != hipSuccess) return 1;
-    return std::max(1, b);
-}
-template <class R>
-int occupancy_shade()
-{
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_shade<R>, kBlock, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, kBlock, 0) != hipSuccess) return 1;
     return std::max(1, b);
 }
 
@@ -1619,9 +1714,7 @@ int occupancy_shade()
     template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, int, hipStream_t);      \
     template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,              \
                                      hipStream_t);                                                                 \
-    template int occupancy_trace<R>();                                                                             \
-    template int occupancy_shadow<R>();                                                                            \
-    template int occupancy_shade<R>();
+    template int occupancy<R>(int);
 
 SDM_INSTANTIATE(float)
 SDM_INSTANTIATE(double)

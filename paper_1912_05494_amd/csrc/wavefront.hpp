@@ -30,12 +30,9 @@ void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R>
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
                      hipStream_t s);
+// Resident blocks of 256 threads per CU of a render kernel (SDM_K_* class).
 template <class R>
-int occupancy_trace();
-template <class R>
-int occupancy_shadow();
-template <class R>
-int occupancy_shade();
+int occupancy(int kernel_class);
 
 void launch_finalize(const double *acc, int64_t npix, int nl, int spp, const double *wts, const double *cmf,
                      float *spec, double *xyz, hipStream_t s);

@@ -228,7 +228,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
     done();
     for (int dpt = 0; dpt < a.depth; ++dpt) {
         mark(SDM_K_TRACE);
-        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, a.grid_t, s);
+        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0, a.grid_t, s);
         done();
         mark(SDM_K_SHADE);
         launch_shade<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);

@@ -159,20 +159,50 @@ __device__ __forceinline__ int32_t child_at(const WideNode &nd, int c)
     return c == 0 ? nd.c0 : c == 1 ? nd.c1 : c == 2 ? nd.c2 : nd.c3;
 }
 
+template <class R>
+struct Ray {
+    V3<R> o, d, inv;
+    V3<R> oi;            // o * inv, for the fused slab form
+    int32_t skip, cur;
+};
+
+template <class R>
+__device__ __forceinline__ void set_dir(Ray<R> &ry, V3<R> o, V3<R> d)
+{
+    ry.o = o;
+    ry.d = d;
+    ry.inv = safe_inv(d);
+    ry.oi = {o.x * ry.inv.x, o.y * ry.inv.y, o.z * ry.inv.z};
+}
+
+// Distance to the plane x = b along one axis.  The fused form b * inv - o *
+// inv saves a subtraction per plane; its rounding error, about |o| u in
+// distance (u = 2^-24 in FP32), stays far inside the box padding (1e-5 of
+// the scene diagonal plus 1e-5 of the box coordinates) when the origin lies
+// in the scene's bounds, as it does for rays leaving a surface.  Rays from
+// elsewhere (the camera, test rays) use (b - o) * inv.
+template <bool kFused, class R>
+__device__ __forceinline__ R slab_t(float b, R o, R inv, R oi)
+{
+    if constexpr (kFused) return fma(R(b), inv, -oi);
+    else return (R(b) - o) * inv;
+}
+
 // Slab tests of the four child boxes against [tlo, thi]; tn is the entry
 // distance clamped to tlo.  The boxes are padded at build time, so rounding
 // never loses a hit.
-template <class R>
-__device__ __forceinline__ void box4(const WideNode &nd, V3<R> o, V3<R> inv, R tlo, R thi, R (&tn)[4],
+template <bool kFused, class R>
+__device__ __forceinline__ void box4(const WideNode &nd, const Ray<R> &ry, R tlo, R thi, R (&tn)[4],
                                      bool (&hit)[4])
 {
+    const V3<R> o = ry.o, inv = ry.inv, oi = ry.oi;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        R t1 = (R(f4get(nd.lox, c)) - o.x) * inv.x, t2 = (R(f4get(nd.hix, c)) - o.x) * inv.x;
+        R t1 = slab_t<kFused>(f4get(nd.lox, c), o.x, inv.x, oi.x), t2 = slab_t<kFused>(f4get(nd.hix, c), o.x, inv.x, oi.x);
         const R ax = fmin(t1, t2), bx = fmax(t1, t2);
-        t1 = (R(f4get(nd.loy, c)) - o.y) * inv.y; t2 = (R(f4get(nd.hiy, c)) - o.y) * inv.y;
+        t1 = slab_t<kFused>(f4get(nd.loy, c), o.y, inv.y, oi.y); t2 = slab_t<kFused>(f4get(nd.hiy, c), o.y, inv.y, oi.y);
         const R ay = fmin(t1, t2), by = fmax(t1, t2);
-        t1 = (R(f4get(nd.loz, c)) - o.z) * inv.z; t2 = (R(f4get(nd.hiz, c)) - o.z) * inv.z;
+        t1 = slab_t<kFused>(f4get(nd.loz, c), o.z, inv.z, oi.z); t2 = slab_t<kFused>(f4get(nd.hiz, c), o.z, inv.z, oi.z);
         const R az = fmin(t1, t2), bz = fmax(t1, t2);
         const R a = fmax(fmax(ax, ay), fmax(az, tlo));
         const R b = fmin(fmin(bx, by), fmin(bz, thi));
@@ -218,12 +248,6 @@ __device__ __forceinline__ int order_children(const WideNode &nd, const R (&tn)[
 }
 
 template <class R>
-struct Ray {
-    V3<R> o, d, inv;
-    int32_t skip, cur;
-};
-
-template <class R>
 struct Closest {
     R tb, ub, vb;
     int32_t trib, orig_b;
@@ -249,28 +273,43 @@ __device__ __forceinline__ TriDev load_tri(const TriDev *tris, int i)
 // box hit and stacking the others farthest first, until a leaf is due; test
 // that leaf and report whether the search is complete.  Ties in t go to the
 // smaller caller triangle index, so the result does not depend on the tree.
-template <class R>
+//
+// Descent is speculative: a lane that reaches a leaf keeps it for the test
+// and goes on with its stack while other lanes of the wave are still
+// searching for theirs, so lanes do not idle through the longest descent of
+// the wave (its extra visits use the larger bound of before the test, which
+// changes no result).  The descent ends when every lane holds a leaf or has
+// nothing left to visit.
+template <bool kFused, class R>
 __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
                                              Ray<R> &ry, Closest<R> &h, R teps, uint32_t &nodes, uint32_t &tests)
 {
-    int32_t cur = ry.cur;
-    while (cur >= 0) {
-        const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
-        ++nodes;
-        R tn[4];
-        bool hit[4];
-        box4(nd, ry.o, ry.inv, teps, h.tb, tn, hit);
-        int32_t e[4];
-        const int nh = order_children(nd, tn, hit, e);
-        if (nh == 0) {
+    int32_t cur = ry.cur;      // inner node (>= 0), leaf (< -1) or kDone
+    int32_t leaf = kDone;
+    for (;;) {
+        if (cur < 0 && cur != kDone && leaf == kDone) {
+            leaf = cur;
             cur = st.sp ? st.pop() : kDone;
-        } else {
-            st.push_sorted(nh - 1, e[1], e[2], e[3]);
-            cur = e[0];
+        }
+        if (!__any(leaf == kDone && cur >= 0)) break;
+        if (cur >= 0) {
+            const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
+            ++nodes;
+            R tn[4];
+            bool hit[4];
+            box4<kFused>(nd, ry, teps, h.tb, tn, hit);
+            int32_t e[4];
+            const int nh = order_children(nd, tn, hit, e);
+            if (nh == 0) {
+                cur = st.sp ? st.pop() : kDone;
+            } else {
+                st.push_sorted(nh - 1, e[1], e[2], e[3]);
+                cur = e[0];
+            }
         }
     }
-    if (cur != kDone) {
-        const int32_t code = -1 - cur;
+    if (leaf != kDone) {
+        const int32_t code = -1 - leaf;
         const int first = code >> 8, cnt = code & 255;
         tests += (uint32_t)cnt;
         for (int i = first; i < first + cnt; ++i) {
@@ -284,41 +323,49 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
                 h.tb = t; h.trib = i; h.ub = u; h.vb = v; h.orig_b = orig;
             }
         }
-        cur = st.sp ? st.pop() : kDone;
     }
     ry.cur = cur;
     return cur == kDone;
 }
 
 // One step of an any-hit walk toward +infinity: visit nodes until a leaf is
-// due and test it.  An opaque triangle ends the
-// walk (occluded); each pane crossed is reported to on_glass(leaf, u, v).
-template <class R, class F>
+// due (speculatively, as in the closest-hit step) and test it.  An opaque
+// triangle ends the walk (occluded); each pane crossed is reported to
+// on_glass(leaf, u, v).
+template <bool kFused, class R, class F>
 __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
                                             Ray<R> &ry, bool &occluded, R teps, F &&on_glass, uint32_t &nodes,
                                             uint32_t &tests)
 {
     const R tinf = R(INFINITY);
     int32_t cur = ry.cur;
-    while (cur >= 0) {
-        const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
-        ++nodes;
-        R tn[4];
-        bool hit[4];
-        box4(nd, ry.o, ry.inv, teps, tinf, tn, hit);
-        // any order finds every pane: enter the first child hit, stack the others
-        int32_t nxt = kDone;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (!hit[c]) continue;
-            const int32_t e = child_at(nd, c);
-            if (nxt == kDone) nxt = e;
-            else st.push(e);
+    int32_t leaf = kDone;
+    for (;;) {
+        if (cur < 0 && cur != kDone && leaf == kDone) {
+            leaf = cur;
+            cur = st.sp ? st.pop() : kDone;
         }
-        cur = nxt != kDone ? nxt : (st.sp ? st.pop() : kDone);
+        if (!__any(leaf == kDone && cur >= 0)) break;
+        if (cur >= 0) {
+            const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
+            ++nodes;
+            R tn[4];
+            bool hit[4];
+            box4<kFused>(nd, ry, teps, tinf, tn, hit);
+            // any order finds every pane: enter the first child hit, stack the others
+            int32_t nxt = kDone;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (!hit[c]) continue;
+                const int32_t e = child_at(nd, c);
+                if (nxt == kDone) nxt = e;
+                else st.push(e);
+            }
+            cur = nxt != kDone ? nxt : (st.sp ? st.pop() : kDone);
+        }
     }
-    if (cur != kDone) {
-        const int32_t code = -1 - cur;
+    if (leaf != kDone) {
+        const int32_t code = -1 - leaf;
         const int first = code >> 8, cnt = code & 255;
         tests += (uint32_t)cnt;
         for (int i = first; i < first + cnt; ++i) {
@@ -335,7 +382,6 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
             }
             on_glass(i, u, v);
         }
-        cur = st.sp ? st.pop() : kDone;
     }
     ry.cur = cur;
     return cur == kDone;
@@ -500,7 +546,9 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const B
 // ---------------------------------------------------------------------------
 // Closest hit of every path of pool `cur`.
 // ---------------------------------------------------------------------------
-template <class R>
+// kSurface: every ray of the pool leaves a surface (after the first bounce),
+// so the fused slab form applies; camera rays take the plain form.
+template <class R, bool kSurface>
 __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w, int cur, int lds_job)
 {
     if (lds_job < -1) lds_job = w.cnt->lds_job;   // the job of the chunk's first path
@@ -533,9 +581,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
             const uint32_t s = (uint32_t)got;
             job = (int)(P.aux[s] >> kAuxJobShift);
             const SceneDev &sc = jobs[job].sc;
-            ry.o = {P.ox[s], P.oy[s], P.oz[s]};
-            ry.d = {P.dx[s], P.dy[s], P.dz[s]};
-            ry.inv = safe_inv(ry.d);
+            set_dir(ry, V3<R>{P.ox[s], P.oy[s], P.oz[s]}, V3<R>{P.dx[s], P.dy[s], P.dz[s]});
             ry.skip = P.skip[s];
             ry.cur = sc.n_nodes > 0 ? 0 : kDone;
             teps = teps_of<R>(sc);
@@ -548,7 +594,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
         }
         if (item >= 0) {
             const bool fin = ry.cur == kDone ||
-                             closest_step(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, h, teps, n_nodes,
+                             closest_step<kSurface>(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, h, teps, n_nodes,
                                           n_tests);
             if (fin) {
                 w.ht[item] = h.tb; w.htri[item] = h.trib; w.hu[item] = h.ub; w.hv[item] = h.vb;
@@ -1219,9 +1265,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
             const uint32_t s = (uint32_t)got;
             job = (int)(w.saux[s] >> kAuxJobShift);
             const SceneDev &sc = jobs[job].sc;
-            ry.o = {w.sx[s], w.sy[s], w.sz[s]};
-            ry.d = {R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])};
-            ry.inv = safe_inv(ry.d);
+            set_dir(ry, V3<R>{w.sx[s], w.sy[s], w.sz[s]}, V3<R>{R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])});
             ry.skip = w.sskip[s];
             ry.cur = sc.n_nodes > 0 ? 0 : kDone;
             teps = teps_of<R>(sc);
@@ -1237,7 +1281,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
         if (item >= 0) {
             const uint32_t rec = (uint32_t)item;
             const bool fin = ry.cur == kDone ||
-                             shadow_step(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, occ, teps,
+                             shadow_step<true>(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, occ, teps,
                                          [&](int leaf, R u, R v) {
                                              if (ng == kMaxGlass) {
                                                  over = true;
@@ -1494,9 +1538,8 @@ __global__ void __launch_bounds__(kBlock) k_debug_intersect(SceneDev sc, uint32_
         const int64_t got = feed.next(item < 0, cursor, m);
         if (got >= 0) {
             item = got;
-            ry.o = {o[3 * got], o[3 * got + 1], o[3 * got + 2]};
-            ry.d = {d[3 * got], d[3 * got + 1], d[3 * got + 2]};
-            ry.inv = safe_inv(ry.d);
+            set_dir(ry, V3<float>{o[3 * got], o[3 * got + 1], o[3 * got + 2]},
+                    V3<float>{d[3 * got], d[3 * got + 1], d[3 * got + 2]});
             ry.skip = (skip && skip[got] >= 0 && skip[got] < sc.nt) ? orig_to_leaf[skip[got]] : -1;
             ry.cur = sc.n_nodes > 0 ? 0 : kDone;
             h.tb = INFINITY; h.ub = h.vb = 0.0f; h.trib = -1; h.orig_b = INT_MAX;
@@ -1507,7 +1550,7 @@ __global__ void __launch_bounds__(kBlock) k_debug_intersect(SceneDev sc, uint32_
             continue;
         }
         if (item >= 0) {
-            const bool fin = ry.cur == kDone || closest_step<float>(sc, s_nodes, n_lds, st, ry, h, sc.teps_f, nn, nt);
+            const bool fin = ry.cur == kDone || closest_step<false>(sc, s_nodes, n_lds, st, ry, h, sc.teps_f, nn, nt);
             if (fin) {
                 t[item] = h.tb;
                 tri[item] = h.trib >= 0 ? __float_as_int(sc.tris[h.trib].a.w) : -1;
@@ -1539,9 +1582,7 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
         const int64_t got = feed.next(item < 0, cursor, m);
         if (got >= 0) {
             item = got;
-            ry.o = {o[3 * got], o[3 * got + 1], o[3 * got + 2]};
-            ry.d = sun;
-            ry.inv = safe_inv(ry.d);
+            set_dir(ry, V3<float>{o[3 * got], o[3 * got + 1], o[3 * got + 2]}, sun);
             ry.skip = (skip && skip[got] >= 0 && skip[got] < sc.nt) ? orig_to_leaf[skip[got]] : -1;
             ry.cur = sc.n_nodes > 0 ? 0 : kDone;
             occ = false;
@@ -1554,7 +1595,7 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
         }
         if (item >= 0) {
             const bool fin = ry.cur == kDone ||
-                             shadow_step<float>(sc, s_nodes, n_lds, st, ry, occ, sc.teps_f,
+                             shadow_step<false>(sc, s_nodes, n_lds, st, ry, occ, sc.teps_f,
                                                 [&](int leaf, float u, float v) {
                                                     const TriDev tr = load_tri(sc.tris, leaf);
                                                     const int mt = __float_as_int(tr.b.w);
@@ -1585,9 +1626,11 @@ void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *it
     hipLaunchKernelGGL(k_generate<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, items, n_items, w, total, chunk);
 }
 template <class R>
-void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, int grid, hipStream_t s)
+void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, int grid,
+                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_trace<R>, dim3(grid), dim3(kBlock), 0, s, jobs, w, cur, lds_job);
+    if (surface) hipLaunchKernelGGL((k_trace<R, true>), dim3(grid), dim3(kBlock), 0, s, jobs, w, cur, lds_job);
+    else hipLaunchKernelGGL((k_trace<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, w, cur, lds_job);
 }
 template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
@@ -1684,7 +1727,7 @@ int occupancy(int kernel_class)
 {
     const void *f = nullptr;
     switch (kernel_class) {
-    case SDM_K_TRACE: f = (const void *)k_trace<R>; break;
+    case SDM_K_TRACE: f = (const void *)k_trace<R, true>; break;
     case SDM_K_SHADE: f = (const void *)k_shade<R>; break;
     case SDM_K_SHADE_GLASS: f = (const void *)k_shade_glass<R>; break;
     case SDM_K_BUBBLY_EVAL:
@@ -1704,7 +1747,7 @@ int occupancy(int kernel_class)
 #define SDM_INSTANTIATE(R)                                                                                         \
     template void launch_generate<R>(const JobDev *, const BandDev *, const ItemDev *, int, const Work<R> &,       \
                                      uint64_t, uint32_t, int, hipStream_t);                                        \
-    template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, int, hipStream_t);                    \
+    template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, bool, int, hipStream_t);              \
     template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);        \
     template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);  \
     template void launch_bubbly_eval<R>(const JobDev *, const BandDev *, const Work<R> &, int, const void *,       \

@@ -12,7 +12,8 @@ template <class R>
 void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *items, int n_items, const Work<R> &w,
                      uint64_t total, uint32_t chunk, int grid, hipStream_t s);
 template <class R>
-void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, int grid, hipStream_t s);
+void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, int grid,
+                  hipStream_t s);
 template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
 template <class R>

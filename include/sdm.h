@@ -49,6 +49,11 @@ enum { SDM_LAMBERT = 0, SDM_GLASS = 1, SDM_GLASS_BUBBLY = 2 };
 enum { SDM_MEM_HOST = 0, SDM_MEM_DEVICE = 1 };
 enum { SDM_PREC_FP32 = 0, SDM_PREC_FP64 = 1 };
 enum { SDM_PINHOLE = 0, SDM_ORTHO = 1 };
+/* How shadow rays (all along the scene's sun direction) find what they cross:
+ * a grid over the triangles projected along the sun where it is compact, else
+ * the BVH; or always the BVH.  Both report the same crossings (the same
+ * triangle test decides). */
+enum { SDM_SHADOW_AUTO = 0, SDM_SHADOW_BVH = 1 };
 /* Evaluation of path vertices on bubbly panes (SDM_GLASS_BUBBLY). */
 enum { SDM_BTDF_EXACT = 0, SDM_BTDF_SURROGATE = 1, SDM_BTDF_FALLBACK = 2 };
 
@@ -90,6 +95,7 @@ typedef struct {
     float sun_dir[3];           /* unit vector toward the sun                   */
     const float *sun_E;         /* [n_tab] sun irradiance                       */
     const float *sky_L;         /* [n_tab] uniform sky radiance                 */
+    int32_t shadow_walk;        /* SDM_SHADOW_AUTO or SDM_SHADOW_BVH            */
 } sdm_scene_desc;
 
 typedef struct {
@@ -247,8 +253,12 @@ int sdm_debug_intersect(sdm_context *ctx, const sdm_scene *scene, int64_t m, con
 int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *scene, int64_t m, const float *o,
                      const int32_t *skip, float lambda_nm, float *T, void *hip_stream);
 
-/* BVH shape of a scene (for tests and tuning): node count and depth. */
-int sdm_scene_info(const sdm_scene *scene, int32_t *n_nodes, int32_t *depth);
+/* Acceleration structures of a scene (for tests and tuning): wide BVH node
+ * count, depth (node levels plus leaves) and traversal stack bound; cells and
+ * candidate entries of the sun grid (0 and 0 when shadow rays walk the BVH).
+ * Any output pointer may be NULL. */
+int sdm_scene_info(const sdm_scene *scene, int32_t *n_nodes, int32_t *depth, int32_t *stack,
+                   int64_t *grid_cells, int64_t *grid_candidates);
 
 /* ---------------------------------------------------------------------------
  * Bubbly glass (air micro-particles in the glass body, Sec. 1; light

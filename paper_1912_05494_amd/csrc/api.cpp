@@ -11,6 +11,7 @@
 
 #include "../../include/sdm.h"
 #include "bvh_build.hpp"
+#include "sun_grid.hpp"
 #include "sdm_types.hpp"
 #include "surrogate.hpp"
 #include "wavefront.hpp"
@@ -140,11 +141,15 @@ int sdm_context_destroy(sdm_context *ctx)
 
 const char *sdm_last_error(const sdm_context *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-int sdm_scene_info(const sdm_scene *sc, int32_t *n_nodes, int32_t *depth)
+int sdm_scene_info(const sdm_scene *sc, int32_t *n_nodes, int32_t *depth, int32_t *stack, int64_t *grid_cells,
+                   int64_t *grid_candidates)
 {
     if (!sc) return SDM_E_INVALID;
     if (n_nodes) *n_nodes = sc->n_nodes;
     if (depth) *depth = sc->depth;
+    if (stack) *stack = sc->stack;
+    if (grid_cells) *grid_cells = sc->grid_cells;
+    if (grid_candidates) *grid_candidates = sc->grid_cands;
     return SDM_OK;
 }
 
@@ -154,6 +159,8 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     if (!d || !out) return fail(ctx, SDM_E_INVALID, "null scene description or output");
     *out = nullptr;
     if (d->nv < 0 || d->nt < 0) return fail(ctx, SDM_E_INVALID, "negative vertex/triangle count");
+    if (d->shadow_walk != SDM_SHADOW_AUTO && d->shadow_walk != SDM_SHADOW_BVH)
+        return fail(ctx, SDM_E_INVALID, "unknown shadow walk %d", d->shadow_walk);
     if (d->nt > 0 && (!d->pos || !d->idx || !d->mat || !d->mats || d->n_mat < 1))
         return fail(ctx, SDM_E_INVALID, "triangles need pos, idx, mat and materials");
     if (d->n_tab < 1 || !d->tab_lambda_nm || !d->sun_E || !d->sky_L)
@@ -278,8 +285,17 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
             if (src[q])
                 std::memcpy(&tabm[((size_t)q * d->n_mat + m) * d->n_tab], src[q], sizeof(float) * d->n_tab);
     }
+    double maxabs = 0.0;
+    for (int a = 0; a < 3 && d->nv > 0; ++a) maxabs = std::max({maxabs, std::fabs(lo[a]), std::fabs(hi[a])});
+    const SunGrid grid = d->shadow_walk == SDM_SHADOW_BVH
+                             ? SunGrid()
+                             : build_sun_grid(tris.data(), d->nt, mtype.data(), d->sun_dir, diag + maxabs);
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    if (grid.use) {
+        chk(upload(sc->g_start, grid.start.data(), grid.start.size()));
+        chk(upload(sc->g_cand, grid.cand.data(), grid.cand.size()));
+    }
     chk(upload(sc->nodes, bvh.nodes.data(), bvh.nodes.size()));
     chk(upload(sc->tris, tris.data(), tris.size()));
     chk(upload(sc->thick, thick.data(), thick.size()));
@@ -309,6 +325,22 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     sd.n_mat = d->n_mat;
     sd.has_vthick = d->vthick_mm ? 1 : 0;
     for (int a = 0; a < 3; ++a) sd.sun[a] = d->sun_dir[a];
+    sd.g_use = grid.use ? 1 : 0;
+    sd.g_start = grid.use ? sc->g_start.as<int32_t>() : nullptr;
+    sd.g_cand = grid.use ? sc->g_cand.as<GridCand>() : nullptr;
+    for (int a = 0; a < 3; ++a) {
+        sd.g_e1[a] = grid.e1[a];
+        sd.g_e2[a] = grid.e2[a];
+    }
+    sd.g_u0 = grid.u0;
+    sd.g_v0 = grid.v0;
+    sd.g_idu = grid.idu;
+    sd.g_idv = grid.idv;
+    sd.g_marg = grid.marg;
+    sd.g_nx = grid.nx;
+    sd.g_ny = grid.ny;
+    sc->grid_cells = (int64_t)grid.nx * grid.ny;
+    sc->grid_cands = (int64_t)grid.cand.size();
     sd.teps_d = 1e-6 * diag;
     sd.teps_f = (float)sd.teps_d;
     *out = sc;
@@ -353,10 +385,8 @@ int sdm_debug_intersect(sdm_context *ctx, const sdm_scene *sc, int64_t m, const 
     hipStream_t s = (hipStream_t)hip_stream;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
     HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * global_stack_levels(sc->stack) * sizeof(int32_t)));
-    HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
-    launch_zero_counters(ctx->counters.as<Counters>(), s);
     launch_debug_intersect(sc->dev, (uint32_t)m, o, d, skip, sc->orig_to_leaf.as<int32_t>(), t, tri, uv,
-                           &ctx->counters.as<Counters>()->tfetch, ctx->gstack.as<int32_t>(), grid, s);
+                           ctx->gstack.as<int32_t>(), grid, s);
     HIPCHK(ctx, hipGetLastError());
     return SDM_OK;
 }
@@ -378,10 +408,8 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const flo
     launch_resample<float>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lam, 1, tabs, s);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
     HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * global_stack_levels(sc->stack) * sizeof(int32_t)));
-    HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
-    launch_zero_counters(ctx->counters.as<Counters>(), s);
     launch_debug_shadow(sc->dev, (uint32_t)m, o, skip, sc->orig_to_leaf.as<int32_t>(), lambda_nm, tabs + nm,
-                        tabs + 2 * nm, tabs + 3 * nm, T, &ctx->counters.as<Counters>()->sfetch,
+                        tabs + 2 * nm, tabs + 3 * nm, T,
                         ctx->gstack.as<int32_t>(), grid, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));

@@ -213,7 +213,7 @@ struct ChunkArgs {
     const float *bb, *params, *E;
     uint64_t total;
     uint32_t chunk;
-    int32_t n_items, depth, lds_job, surr, bubbly, prec;
+    int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec;
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
 };
 
@@ -228,7 +228,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
     done();
     for (int dpt = 0; dpt < a.depth; ++dpt) {
         mark(SDM_K_TRACE);
-        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0, a.grid_t, s);
+        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0, a.one_job != 0, a.grid_t, s);
         done();
         mark(SDM_K_SHADE);
         launch_shade<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
@@ -247,7 +247,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
             done();
         }
         mark(SDM_K_SHADOW);
-        launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.grid_st, s);
+        launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.one_job != 0, a.grid_st, s);
         done();
         mark(SDM_K_SHADOW_ACCUM);
         launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.grid_a, s);
@@ -494,6 +494,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.chunk = (uint32_t)chunk;
         a.depth = depth;
         a.lds_job = nj == 1 ? 0 : -2;   // a batch stages the BVH of each chunk's first job
+        a.one_job = nj == 1;
         a.surr = surr;
         a.bubbly = bubbly;
         a.prec = sizeof(R) == 8;

@@ -26,6 +26,17 @@ struct alignas(16) TriDev {
     float4 a, b, c;
 };
 
+// Candidate of the sun grid: a copy of the triangle's vertices (the exact
+// floats of TriDev, so the triangle test gives the same result) with, in the
+// w words, its leaf index (integer bits), its largest depth along the sun
+// direction and its material type (integer bits).  A ray reads its cell's
+// candidates as one contiguous stream, with no dependent loads.
+struct alignas(16) GridCand {
+    float4 a;   // vertex 0, leaf
+    float4 b;   // vertex 1, largest depth
+    float4 c;   // vertex 2, material type
+};
+
 // Scene data resident on the device.
 struct SceneDev {
     const BvhNode *nodes;
@@ -37,6 +48,13 @@ struct SceneDev {
                                 // density (per mm^3), pane type; zeros for other materials
     int32_t n_nodes, nt, n_mat, has_vthick;
     float sun[3];
+    // sun grid (shadow rays): the point o projects to (o.e1, o.e2); cell
+    // (floor((a - u0) idu), floor((b - v0) idv)) lists its candidates in
+    // g_cand[g_start[c] .. g_start[c + 1]) by increasing smallest depth o.sun
+    const int32_t *g_start;
+    const GridCand *g_cand;
+    float g_e1[3], g_e2[3], g_u0, g_v0, g_idu, g_idv, g_marg;
+    int32_t g_nx, g_ny, g_use;
     float teps_f;
     double teps_d;
 };
@@ -93,10 +111,6 @@ struct alignas(256) Counters {
     uint32_t pad_b[kCounterPad - 1];
     uint32_t kcount;            // sky records (escaped paths), from the back of the record buffer
     uint32_t pad_k[kCounterPad - 1];
-    uint32_t tfetch;            // work cursor of the closest-hit traversal
-    uint32_t pad_t[kCounterPad - 1];
-    uint32_t sfetch;            // work cursor of the shadow traversal
-    uint32_t pad_f[kCounterPad - 1];
     uint32_t overflow;          // bit 0: a pool or record buffer was full;
                                 // bit 1: a shadow ray crossed more than kMaxGlass panes
     int32_t lds_job;            // job whose BVH prefix the traversal kernels stage in LDS

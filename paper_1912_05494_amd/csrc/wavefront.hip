@@ -37,7 +37,7 @@ namespace sdm {
 
 constexpr int kLdsNodes = 64;     // wide-node prefix staged in LDS (8 KB)
 constexpr int kBlock = 256;
-constexpr uint32_t kFetch = 256;  // rays a traversal wave claims at a time
+constexpr uint32_t kFetch = 256;  // items per group of the traversal work distribution
 constexpr int32_t kDone = INT_MIN;
 
 // ---------------------------------------------------------------------------
@@ -387,26 +387,88 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
     return cur == kDone;
 }
 
-// Work distribution of the persistent traversal kernels: a wave claims
-// kFetch consecutive items with one atomic and hands them to idle lanes.
+// Sun-grid walk of a shadow ray (scenes with a sun grid): the candidates of
+// the ray's cell, by increasing smallest depth, up to kGridBatch per step.
+// Candidates entirely behind the origin are skipped; the triangle test
+// decides the rest exactly as in the BVH walk, and the first opaque triangle
+// crossed ends the walk.
+constexpr uint32_t kGridBatch = 8;
+
+template <class R>
+struct GridRange {
+    uint32_t cur, end;
+    R depth;             // o . sun, less the padding
+};
+
+template <class R>
+__device__ __forceinline__ GridRange<R> grid_range(const SceneDev &sc, V3<R> o)
+{
+    GridRange<R> g;
+    const R a = o.x * R(sc.g_e1[0]) + o.y * R(sc.g_e1[1]) + o.z * R(sc.g_e1[2]);
+    const R b = o.x * R(sc.g_e2[0]) + o.y * R(sc.g_e2[1]) + o.z * R(sc.g_e2[2]);
+    g.depth = o.x * R(sc.sun[0]) + o.y * R(sc.sun[1]) + o.z * R(sc.sun[2]) - R(sc.g_marg);
+    const R fx = (a - R(sc.g_u0)) * R(sc.g_idu), fy = (b - R(sc.g_v0)) * R(sc.g_idv);
+    g.cur = g.end = 0;
+    // outside the grid no padded projection covers the point
+    if (fx >= R(0) && fx < R(sc.g_nx) && fy >= R(0) && fy < R(sc.g_ny)) {
+        const int c = (int)fx + sc.g_nx * (int)fy;
+        g.cur = (uint32_t)gld(sc.g_start + c);
+        g.end = (uint32_t)gld(sc.g_start + c + 1);
+    }
+    return g;
+}
+
+template <class R, class F>
+__device__ __forceinline__ bool grid_step(const SceneDev &sc, const Ray<R> &ry, GridRange<R> &g, bool &occluded,
+                                          R teps, F &&on_glass, uint32_t &cands, uint32_t &tests)
+{
+    const uint32_t stop = min(g.end, g.cur + kGridBatch);
+    for (; g.cur < stop; ++g.cur) {
+        const float4 *cp = reinterpret_cast<const float4 *>(sc.g_cand) + 3 * (size_t)g.cur;
+        const float4 A = gld4(cp), B = gld4(cp + 1), C = gld4(cp + 2);
+        ++cands;
+        const int leaf = __float_as_int(A.w);
+        if (R(B.w) < g.depth || leaf == ry.skip) continue;
+        ++tests;
+        R t, u, v;
+        if (!tri_hit(ry.o, ry.d, from4<R>(A), from4<R>(B), from4<R>(C), t, u, v)) continue;
+        if (!(t > teps)) continue;
+        const int mt = __float_as_int(C.w);
+        if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
+            occluded = true;
+            g.cur = g.end;
+            return true;
+        }
+        on_glass(leaf, u, v);
+    }
+    return g.cur >= g.end;
+}
+
+// Work distribution of the persistent traversal kernels: wave w of W takes
+// the kFetch-item groups w, w + W, w + 2W, ... and hands their items to its
+// idle lanes as they finish.  The interleaving spreads costly regions of the
+// ray buffer over all waves; a shared claim counter, hit by every wave of all
+// XCDs, costs more than the balance it buys.
 struct WaveFeed {
     uint32_t beg, end;
     bool done;
+    uint32_t group;      // groups taken so far
     // All lanes call this together; returns the item of an idle lane or -1.
-    __device__ __forceinline__ int64_t next(bool idle, uint32_t *cursor, uint32_t count)
+    __device__ __forceinline__ int64_t next(bool idle, uint32_t count)
     {
         const uint64_t m = __ballot(idle);
         if (!m || done) return -1;
         if (beg >= end) {
-            uint32_t base = 0;
-            if (lane_id() == 0) base = atomicAdd(cursor, kFetch);
-            base = __shfl(base, 0);
+            const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+            const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+            const uint64_t base = ((uint64_t)wid + (uint64_t)group * nw) * kFetch;
+            ++group;
             if (base >= count) {
                 done = true;
                 return -1;
             }
-            beg = base;
-            end = min(base + kFetch, count);
+            beg = (uint32_t)base;
+            end = (uint32_t)min<uint64_t>(base + kFetch, count);
         }
         const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
         const int64_t item = (idle && beg + before < end) ? (int64_t)(beg + before) : -1;
@@ -479,7 +541,7 @@ __device__ __forceinline__ void run_add_k(double *acc, uint64_t key0, int j, int
 // plane, or orthographic rays along the view axis.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const BandDev *bands,
+__global__ void __launch_bounds__(kBlock) k_generate(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands,
                                                      const ItemDev *items, int32_t n_items, Work<R> w,
                                                      uint64_t total, uint32_t chunk)
 {
@@ -498,7 +560,6 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const B
         }
         w.cnt->count[0] = n;
         w.cnt->count[1] = 0;
-        w.cnt->tfetch = 0;
         w.cnt->scount = 0;
     }
     const Pool<R> P = w.p[0];
@@ -547,9 +608,11 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *jobs, const B
 // Closest hit of every path of pool `cur`.
 // ---------------------------------------------------------------------------
 // kSurface: every ray of the pool leaves a surface (after the first bounce),
-// so the fused slab form applies; camera rays take the plain form.
-template <class R, bool kSurface>
-__global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w, int cur, int lds_job)
+// so the fused slab form applies; camera rays take the plain form.  kOne: the
+// launch renders one job, so the scene's constants are uniform (scalar loads
+// hoisted out of the loops) rather than looked up per lane.
+template <class R, bool kSurface, bool kOne>
+__global__ void __launch_bounds__(kBlock) k_trace(const JobDev *__restrict__ jobs, Work<R> w, int cur, int lds_job)
 {
     if (lds_job < -1) lds_job = w.cnt->lds_job;   // the job of the chunk's first path
     __shared__ float4 s_nodes[8 * kLdsNodes];
@@ -559,7 +622,6 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
         w.cnt->count[cur ^ 1] = 0;
         w.cnt->scount = 0;
         w.cnt->kcount = 0;
-        w.cnt->sfetch = 0;
         w.cnt->gcount = 0;
         w.cnt->bcount = 0;
         w.cnt->closest += count;
@@ -567,7 +629,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
     const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
     Stack st = make_stack(s_stack, w.gstack);
     const Pool<R> P = w.p[cur];
-    WaveFeed feed{0, 0, false};
+    WaveFeed feed{0, 0, false, 0};
     Ray<R> ry;
     Closest<R> h;
     int64_t item = -1;
@@ -575,11 +637,11 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *jobs, Work<R> w,
     R teps = R(0);
     uint32_t n_nodes = 0, n_tests = 0;
     for (;;) {
-        const int64_t got = feed.next(item < 0, &w.cnt->tfetch, count);
+        const int64_t got = feed.next(item < 0, count);
         if (got >= 0) {
             item = got;
             const uint32_t s = (uint32_t)got;
-            job = (int)(P.aux[s] >> kAuxJobShift);
+            job = kOne ? 0 : (int)(P.aux[s] >> kAuxJobShift);
             const SceneDev &sc = jobs[job].sc;
             set_dir(ry, V3<R>{P.ox[s], P.oy[s], P.oz[s]}, V3<R>{P.dx[s], P.dy[s], P.dz[s]});
             ry.skip = P.skip[s];
@@ -648,10 +710,9 @@ __device__ __forceinline__ void block_reserve(const bool (&want)[Q], uint32_t *c
 }
 
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_shade(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
+__global__ void __launch_bounds__(kBlock) k_shade(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
-    if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->tfetch = 0;
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
@@ -861,7 +922,7 @@ __device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, 
 // reflected wavelengths continue in a new pool slot.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
+__global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->gcount, w.cap);
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
@@ -993,7 +1054,7 @@ __device__ __forceinline__ BubblyVertex bubbly_vertex(const JobDev *jobs, const 
 // operands, FP32 sums); tuple j of a vertex is its band's wavelength j, and
 // j = nb_max the reference wavelength.
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *jobs, const BandDev *bands, Work<R> w,
+__global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w,
                                                             int cur, const __bf16 *wb, const float *bb,
                                                             const float *E)
 {
@@ -1087,7 +1148,7 @@ __device__ double net_fp64(const float *p, const float *E, int pane, double cos_
     return out[0];
 }
 
-__global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *jobs, const BandDev *bands, Work<double> w,
+__global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<double> w,
                                                             int cur, const float *params, const float *E)
 {
     const Pool<double> Pi = w.p[cur];
@@ -1121,7 +1182,7 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *jobs,
 // transmitted lobe of width w.  Either way a band splits into at most a
 // reflected and a continuing packet.
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, const BandDev *bands, Work<R> w, int cur)
+__global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->bcount, w.cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->bubbly += count;
@@ -1240,8 +1301,8 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *jobs, con
 // transmittance pass.  A walk that crosses more than kMaxGlass panes sets
 // bit 1 of the overflow word and the render reports it.
 // ---------------------------------------------------------------------------
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, const BandDev *bands, Work<R> w,
+template <class R, bool kOne>
+__global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w,
                                                          int lds_job)
 {
     if (lds_job < -1) lds_job = w.cnt->lds_job;
@@ -1251,23 +1312,26 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->shadow += count;
     const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
     Stack st = make_stack(s_stack, w.gstack);
-    WaveFeed feed{0, 0, false};
+    WaveFeed feed{0, 0, false, 0};
     Ray<R> ry;
+    GridRange<R> gr{0, 0, R(0)};
     int64_t item = -1;
     int job = 0, ng = 0;
-    bool occ = false, over = false;
+    bool occ = false, over = false, grid = false;
     R teps = R(0);
     uint32_t n_nodes = 0, n_tests = 0;
     for (;;) {
-        const int64_t got = feed.next(item < 0, &w.cnt->sfetch, count);
+        const int64_t got = feed.next(item < 0, count);
         if (got >= 0) {
             item = got;
             const uint32_t s = (uint32_t)got;
-            job = (int)(w.saux[s] >> kAuxJobShift);
+            job = kOne ? 0 : (int)(w.saux[s] >> kAuxJobShift);
             const SceneDev &sc = jobs[job].sc;
             set_dir(ry, V3<R>{w.sx[s], w.sy[s], w.sz[s]}, V3<R>{R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])});
             ry.skip = w.sskip[s];
-            ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+            grid = sc.g_use != 0;
+            if (grid) gr = grid_range(sc, ry.o);
+            ry.cur = !grid && sc.n_nodes > 0 ? 0 : kDone;
             teps = teps_of<R>(sc);
             ng = 0;
             occ = false;
@@ -1280,19 +1344,22 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
         }
         if (item >= 0) {
             const uint32_t rec = (uint32_t)item;
-            const bool fin = ry.cur == kDone ||
-                             shadow_step<true>(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, occ, teps,
-                                         [&](int leaf, R u, R v) {
-                                             if (ng == kMaxGlass) {
-                                                 over = true;
-                                                 return;
-                                             }
-                                             w.sg_leaf[(size_t)rec * kMaxGlass + ng] = leaf;
-                                             w.sg_u[(size_t)rec * kMaxGlass + ng] = u;
-                                             w.sg_v[(size_t)rec * kMaxGlass + ng] = v;
-                                             ++ng;
-                                         },
-                                         n_nodes, n_tests);
+            auto on_glass = [&](int leaf, R u, R v) {
+                if (ng == kMaxGlass) {
+                    over = true;
+                    return;
+                }
+                w.sg_leaf[(size_t)rec * kMaxGlass + ng] = leaf;
+                w.sg_u[(size_t)rec * kMaxGlass + ng] = u;
+                w.sg_v[(size_t)rec * kMaxGlass + ng] = v;
+                ++ng;
+            };
+            bool fin;
+            if (grid)
+                fin = grid_step(jobs[job].sc, ry, gr, occ, teps, on_glass, n_nodes, n_tests);
+            else
+                fin = ry.cur == kDone || shadow_step<true>(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry,
+                                                           occ, teps, on_glass, n_nodes, n_tests);
             if (fin) {
                 // an occluded walk needs no pane list, whatever the visiting order found first
                 if (over && !occ) atomicOr(&w.cnt->overflow, 2u);
@@ -1320,7 +1387,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *jobs, con
 // balances.
 
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *jobs, const BandDev *bands, Work<R> w)
+__global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w)
 {
     __shared__ uint32_t s_buf[kBlock / 64][128];
     // sun records [0, ns), then the sky records of escaped paths stored from
@@ -1470,7 +1537,6 @@ __global__ void k_zero_counters(Counters *c)
         c->lds_job = 0;
         c->count[0] = c->count[1] = 0;
         c->scount = c->kcount = 0;
-        c->tfetch = c->sfetch = 0;
         c->overflow = 0;
         c->gcount = c->bcount = 0;
         c->closest = c->shadow = c->forks = c->bubbly = 0;
@@ -1522,20 +1588,20 @@ __global__ void k_slab_eval(int64_t m, const float *c, const float *lam, const f
 
 __global__ void __launch_bounds__(kBlock) k_debug_intersect(SceneDev sc, uint32_t m, const float *o, const float *d,
                                                             const int32_t *skip, const int32_t *orig_to_leaf,
-                                                            float *t, int32_t *tri, float *uv, uint32_t *cursor,
+                                                            float *t, int32_t *tri, float *uv,
                                                             int32_t *gstack)
 {
     __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const int n_lds = stage_nodes(s_nodes, sc);
     Stack st = make_stack(s_stack, gstack);
-    WaveFeed feed{0, 0, false};
+    WaveFeed feed{0, 0, false, 0};
     Ray<float> ry;
     Closest<float> h;
     int64_t item = -1;
     uint32_t nn = 0, nt = 0;
     for (;;) {
-        const int64_t got = feed.next(item < 0, cursor, m);
+        const int64_t got = feed.next(item < 0, m);
         if (got >= 0) {
             item = got;
             set_dir(ry, V3<float>{o[3 * got], o[3 * got + 1], o[3 * got + 2]},
@@ -1565,26 +1631,28 @@ __global__ void __launch_bounds__(kBlock) k_debug_intersect(SceneDev sc, uint32_
 __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m, const float *o, const int32_t *skip,
                                                          const int32_t *orig_to_leaf, float lambda_nm,
                                                          const float *n_at, const float *k_at, const float *t_at,
-                                                         float *T, uint32_t *cursor, int32_t *gstack)
+                                                         float *T, int32_t *gstack)
 {
     __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const int n_lds = stage_nodes(s_nodes, sc);
     Stack st = make_stack(s_stack, gstack);
-    WaveFeed feed{0, 0, false};
+    WaveFeed feed{0, 0, false, 0};
     Ray<float> ry;
     int64_t item = -1;
     bool occ = false;
     float prod = 1.0f;
+    GridRange<float> gr{0, 0, 0.0f};
     uint32_t nn = 0, nt = 0;
     const V3<float> sun = {sc.sun[0], sc.sun[1], sc.sun[2]};
     for (;;) {
-        const int64_t got = feed.next(item < 0, cursor, m);
+        const int64_t got = feed.next(item < 0, m);
         if (got >= 0) {
             item = got;
             set_dir(ry, V3<float>{o[3 * got], o[3 * got + 1], o[3 * got + 2]}, sun);
             ry.skip = (skip && skip[got] >= 0 && skip[got] < sc.nt) ? orig_to_leaf[skip[got]] : -1;
-            ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+            if (sc.g_use) gr = grid_range(sc, ry.o);
+            ry.cur = !sc.g_use && sc.n_nodes > 0 ? 0 : kDone;
             occ = false;
             prod = 1.0f;
             st.sp = 0;
@@ -1594,20 +1662,19 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
             continue;
         }
         if (item >= 0) {
-            const bool fin = ry.cur == kDone ||
-                             shadow_step<false>(sc, s_nodes, n_lds, st, ry, occ, sc.teps_f,
-                                                [&](int leaf, float u, float v) {
-                                                    const TriDev tr = load_tri(sc.tris, leaf);
-                                                    const int mt = __float_as_int(tr.b.w);
-                                                    float Rr, Tt;
-                                                    slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm,
-                                                                   pane_thickness<float>(sc, leaf, u, v), n_at[mt],
-                                                                   k_at[mt],
-                                                                   t_at[mt] + (float)gld(sc.mat_bub + 4 * mt),
-                                                                   Rr, Tt);
-                                                    prod *= Tt;
-                                                },
-                                                nn, nt);
+            auto on_glass = [&](int leaf, float u, float v) {
+                const TriDev tr = load_tri(sc.tris, leaf);
+                const int mt = __float_as_int(tr.b.w);
+                float Rr, Tt;
+                slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm, pane_thickness<float>(sc, leaf, u, v),
+                               n_at[mt], k_at[mt], t_at[mt] + (float)gld(sc.mat_bub + 4 * mt), Rr, Tt);
+                prod *= Tt;
+            };
+            // the walk of the render: the sun grid where the scene has one (test
+            // origins lie in the scene's bounds, as render origins do), else the BVH
+            const bool fin = sc.g_use ? grid_step(sc, ry, gr, occ, sc.teps_f, on_glass, nn, nt)
+                                      : (ry.cur == kDone ||
+                                         shadow_step<false>(sc, s_nodes, n_lds, st, ry, occ, sc.teps_f, on_glass, nn, nt));
             if (fin) {
                 T[item] = occ ? 0.0f : prod;
                 item = -1;
@@ -1626,11 +1693,17 @@ void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *it
     hipLaunchKernelGGL(k_generate<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, items, n_items, w, total, chunk);
 }
 template <class R>
-void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, int grid,
+void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, bool one_job, int grid,
                   hipStream_t s)
 {
-    if (surface) hipLaunchKernelGGL((k_trace<R, true>), dim3(grid), dim3(kBlock), 0, s, jobs, w, cur, lds_job);
-    else hipLaunchKernelGGL((k_trace<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, w, cur, lds_job);
+    const dim3 g(grid), b(kBlock);
+    if (one_job) {
+        if (surface) hipLaunchKernelGGL((k_trace<R, true, true>), g, b, 0, s, jobs, w, cur, lds_job);
+        else hipLaunchKernelGGL((k_trace<R, false, true>), g, b, 0, s, jobs, w, cur, lds_job);
+    } else {
+        if (surface) hipLaunchKernelGGL((k_trace<R, true, false>), g, b, 0, s, jobs, w, cur, lds_job);
+        else hipLaunchKernelGGL((k_trace<R, false, false>), g, b, 0, s, jobs, w, cur, lds_job);
+    }
 }
 template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
@@ -1658,10 +1731,11 @@ void launch_shade_bubbly(const JobDev *jobs, const BandDev *bands, const Work<R>
     hipLaunchKernelGGL(k_shade_bubbly<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
 }
 template <class R>
-void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid,
-                         hipStream_t s)
+void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, bool one_job,
+                         int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shadow_trace<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, lds_job);
+    if (one_job) hipLaunchKernelGGL((k_shadow_trace<R, true>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, lds_job);
+    else hipLaunchKernelGGL((k_shadow_trace<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, lds_job);
 }
 template <class R>
 void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s)
@@ -1703,18 +1777,18 @@ void launch_slab_eval(int64_t m, const float *c, const float *lam, const float *
     hipLaunchKernelGGL(k_slab_eval, dim3(grid), dim3(kBlock), 0, s, m, c, lam, d, n, k, tint, R, T);
 }
 void launch_debug_intersect(const SceneDev &sc, uint32_t m, const float *o, const float *d, const int32_t *skip,
-                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv, uint32_t *cursor,
+                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv,
                             int32_t *gstack, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_debug_intersect, dim3(grid), dim3(kBlock), 0, s, sc, m, o, d, skip, orig_to_leaf, t, tri,
-                       uv, cursor, gstack);
+                       uv, gstack);
 }
 void launch_debug_shadow(const SceneDev &sc, uint32_t m, const float *o, const int32_t *skip,
                          const int32_t *orig_to_leaf, float lambda_nm, const float *n_at, const float *k_at,
-                         const float *t_at, float *T, uint32_t *cursor, int32_t *gstack, int grid, hipStream_t s)
+                         const float *t_at, float *T, int32_t *gstack, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_debug_shadow, dim3(grid), dim3(kBlock), 0, s, sc, m, o, skip, orig_to_leaf, lambda_nm, n_at,
-                       k_at, t_at, T, cursor, gstack);
+                       k_at, t_at, T, gstack);
 }
 
 int block_size() { return kBlock; }
@@ -1727,7 +1801,7 @@ int occupancy(int kernel_class)
 {
     const void *f = nullptr;
     switch (kernel_class) {
-    case SDM_K_TRACE: f = (const void *)k_trace<R, true>; break;
+    case SDM_K_TRACE: f = (const void *)k_trace<R, true, false>; break;
     case SDM_K_SHADE: f = (const void *)k_shade<R>; break;
     case SDM_K_SHADE_GLASS: f = (const void *)k_shade_glass<R>; break;
     case SDM_K_BUBBLY_EVAL:
@@ -1735,7 +1809,7 @@ int occupancy(int kernel_class)
         else f = (const void *)k_bubbly_eval_fp64;
         break;
     case SDM_K_SHADE_BUBBLY: f = (const void *)k_shade_bubbly<R>; break;
-    case SDM_K_SHADOW: f = (const void *)k_shadow_trace<R>; break;
+    case SDM_K_SHADOW: f = (const void *)k_shadow_trace<R, false>; break;
     case SDM_K_SHADOW_ACCUM: f = (const void *)k_shadow_accum<R>; break;
     default: return 1;
     }
@@ -1747,13 +1821,13 @@ int occupancy(int kernel_class)
 #define SDM_INSTANTIATE(R)                                                                                         \
     template void launch_generate<R>(const JobDev *, const BandDev *, const ItemDev *, int, const Work<R> &,       \
                                      uint64_t, uint32_t, int, hipStream_t);                                        \
-    template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, bool, int, hipStream_t);              \
+    template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, bool, bool, int, hipStream_t);        \
     template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);        \
     template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);  \
     template void launch_bubbly_eval<R>(const JobDev *, const BandDev *, const Work<R> &, int, const void *,       \
                                         const float *, const float *, const float *, int, hipStream_t);            \
     template void launch_shade_bubbly<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
-    template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
+    template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t); \
     template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, int, hipStream_t);      \
     template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,              \
                                      hipStream_t);                                                                 \

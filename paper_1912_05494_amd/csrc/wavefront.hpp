@@ -12,7 +12,7 @@ template <class R>
 void launch_generate(const JobDev *jobs, const BandDev *bands, const ItemDev *items, int n_items, const Work<R> &w,
                      uint64_t total, uint32_t chunk, int grid, hipStream_t s);
 template <class R>
-void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, int grid,
+void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, bool one_job, int grid,
                   hipStream_t s);
 template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
@@ -24,8 +24,8 @@ void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> 
 template <class R>
 void launch_shade_bubbly(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
 template <class R>
-void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, int grid,
-                         hipStream_t s);
+void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, bool one_job,
+                         int grid, hipStream_t s);
 template <class R>
 void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s);
 template <class R>
@@ -43,11 +43,11 @@ void launch_advance_cursor(Counters *c, uint32_t chunk, hipStream_t s);
 void launch_slab_eval(int64_t m, const float *c, const float *lam, const float *d, const float *n, const float *k,
                       const float *tint, float *R, float *T, hipStream_t s);
 void launch_debug_intersect(const SceneDev &sc, uint32_t m, const float *o, const float *d, const int32_t *skip,
-                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv, uint32_t *cursor,
+                            const int32_t *orig_to_leaf, float *t, int32_t *tri, float *uv,
                             int32_t *gstack, int grid, hipStream_t s);
 void launch_debug_shadow(const SceneDev &sc, uint32_t m, const float *o, const int32_t *skip,
                          const int32_t *orig_to_leaf, float lambda_nm, const float *n_at, const float *k_at,
-                         const float *t_at, float *T, uint32_t *cursor, int32_t *gstack, int grid, hipStream_t s);
+                         const float *t_at, float *T, int32_t *gstack, int grid, hipStream_t s);
 int block_size();
 
 }  // namespace sdm

@@ -20,6 +20,7 @@ SDM_PREC_FP32, SDM_PREC_FP64 = 0, 1
 KERNELS = ("generate", "trace", "shade", "shadow", "finalize", "shadow_accum", "shade_glass", "bubbly_eval",
            "shade_bubbly")
 BTDF_MODES = {"exact": 0, "surrogate": 1, "fallback": 2}
+SHADOW_WALKS = {"auto": 0, "bvh": 1}
 
 _FP = C.POINTER(C.c_float)
 
@@ -36,7 +37,7 @@ class SceneDesc(C.Structure):
                 ("idx", C.POINTER(C.c_int32)), ("mat", C.POINTER(C.c_int32)),
                 ("n_mat", C.c_int32), ("mats", C.POINTER(Material)), ("n_tab", C.c_int32),
                 ("tab_lambda_nm", _FP), ("sun_dir", C.c_float * 3), ("sun_E", _FP),
-                ("sky_L", _FP)]
+                ("sky_L", _FP), ("shadow_walk", C.c_int32)]
 
 
 class Camera(C.Structure):
@@ -118,7 +119,8 @@ def lib():
         L.sdm_last_error.argtypes = [vp]
         L.sdm_scene_create.argtypes = [vp, C.POINTER(SceneDesc), C.POINTER(vp)]
         L.sdm_scene_destroy.argtypes = [vp]
-        L.sdm_scene_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sdm_scene_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sdm_render.argtypes = [vp, vp, C.POINTER(RenderParams), C.POINTER(Outputs), vp]
         L.sdm_slab_eval.argtypes = [vp, C.c_int64] + [vp] * 9
         L.sdm_debug_intersect.argtypes = [vp, vp, C.c_int64] + [vp] * 7
@@ -194,7 +196,8 @@ class Context:
 class Scene:
     """Uploads a ``synth.Scene``-like object (pos, idx, mat, materials, tables)."""
 
-    def __init__(self, ctx: Context, scene):
+    def __init__(self, ctx: Context, scene, shadow_walk="auto"):
+        """shadow_walk: "auto" (sun grid where it is compact) or "bvh"."""
         self.ctx = ctx
         keep = []
         pos = _f32(scene.pos.reshape(-1))
@@ -216,15 +219,17 @@ class Scene:
                       idx.ctypes.data_as(C.POINTER(C.c_int32)),
                       mat.ctypes.data_as(C.POINTER(C.c_int32)), len(scene.materials), mats,
                       len(tab), fp(tab), (C.c_float * 3)(*[float(x) for x in scene.sun_dir]),
-                      fp(sE), fp(sL))
+                      fp(sE), fp(sL), SHADOW_WALKS[shadow_walk])
         self.ptr = C.c_void_p()
         ctx.check(lib().sdm_scene_create(ctx.ptr, C.byref(d), C.byref(self.ptr)), "sdm_scene_create")
         self.nt = int(scene.idx.shape[0])
 
     def info(self):
-        n, dep = C.c_int32(), C.c_int32()
-        lib().sdm_scene_info(self.ptr, C.byref(n), C.byref(dep))
-        return {"n_nodes": n.value, "depth": dep.value}
+        n, dep, stk = C.c_int32(), C.c_int32(), C.c_int32()
+        cells, cands = C.c_int64(), C.c_int64()
+        lib().sdm_scene_info(self.ptr, C.byref(n), C.byref(dep), C.byref(stk), C.byref(cells), C.byref(cands))
+        return {"n_nodes": n.value, "depth": dep.value, "stack": stk.value, "grid_cells": cells.value,
+                "grid_candidates": cands.value}
 
     def close(self):
         if self.ptr:

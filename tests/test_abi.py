@@ -80,7 +80,7 @@ int main(void) {
   printf("sdm_train_params %zu\n", sizeof(sdm_train_params));
   P(sdm_train_params, lr); P(sdm_train_params, eps);
   P(sdm_material, thick_mm); P(sdm_material, pane_id);
-  P(sdm_scene_desc, mats); P(sdm_scene_desc, sun_dir); P(sdm_scene_desc, sky_L);
+  P(sdm_scene_desc, mats); P(sdm_scene_desc, sun_dir); P(sdm_scene_desc, sky_L); P(sdm_scene_desc, shadow_walk);
   P(sdm_render_params, seed); P(sdm_render_params, band_edges);
   P(sdm_render_params, chunk_paths); P(sdm_render_params, timing);
   P(sdm_render_params, btdf_mode); P(sdm_render_params, err_dims); P(sdm_render_params, mlp);

@@ -95,10 +95,13 @@ def test_intersect_parity(gpu, orc, seed):
     assert np.all(np.abs(uv[hit, 0] - uo[hit]) < 1e-4) and np.all(np.abs(uv[hit, 1] - vo[hit]) < 1e-4)
 
 
-def test_shadow_parity(gpu, orc):
+@pytest.mark.parametrize("walk", ["auto", "bvh"])
+def test_shadow_parity(gpu, orc, walk):
+    """Shadow transmittance through the sun grid (auto) and the BVH walk."""
     sdm, ctx, torch = gpu
     sc = synth.random_soup(4, n_tris=500, n_glass=300)
-    gs = sdm.Scene(ctx, sc)
+    gs = sdm.Scene(ctx, sc, shadow_walk=walk)
+    assert (gs.info()["grid_cells"] > 0) == (walk == "auto")
     o, _ = synth.random_rays(9, 20000)
     for lam in (400.0, 555.0, 700.0):
         T = sdm.debug_shadow(ctx, gs, torch.from_numpy(o).cuda(), lam).cpu().numpy()
@@ -306,3 +309,24 @@ def test_invalid_arguments(gpu):
     bad.idx[1, 2] = 99
     with pytest.raises(sdm.SdmError, match="vertex"):
         sdm.Scene(ctx, bad)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sun_grid_matches_bvh_walk(gpu, precision):
+    """Renders whose shadow rays use the sun grid equal those walking the BVH:
+    the same triangle test decides every crossing; only the order of the
+    pane factors (and so their rounding) may differ."""
+    sdm, ctx, torch = gpu
+    sc = synth.nave_scene(seed=5, target_tris=8000)
+    st = synth.nave_settings(W=96, H=64, spp=4, max_depth=4, n_lambda=24)
+    ga, gb = sdm.Scene(ctx, sc), sdm.Scene(ctx, sc, shadow_walk="bvh")
+    assert ga.info()["grid_cells"] > 0 and gb.info()["grid_cells"] == 0
+    a, xa, sa = sdm.render(ctx, ga, st, precision=precision)
+    b, xb, sb = sdm.render(ctx, gb, st, precision=precision)
+    a, b = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+    rt = 2e-7 if precision == "fp64" else 2e-6        # spectral output is float32
+    assert np.allclose(a, b, rtol=rt, atol=rt * np.abs(b).max())
+    if precision == "fp64":
+        xa, xb = xa.cpu().numpy(), xb.cpu().numpy()
+        assert np.allclose(xa, xb, rtol=1e-12, atol=1e-12 * np.abs(xb).max())
+    assert sa["shadow_segments"] == sb["shadow_segments"]

@@ -33,9 +33,10 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 ALU_PEAK_TFLOPS = 78.6
 FLOPS_PER_NODE = 96     # four slab box tests per wide node (6 sub, 6 mul, 12 min/max each)
 FLOPS_PER_TRI = 50      # Moeller-Trumbore: edges, two cross products, four dots, reciprocal
+FLOPS_PER_CAND = 2      # sun-grid candidate: depth comparison and skip test
 
 
-def kernel_models(stats, nb, npix, nl):
+def kernel_models(stats, nb, npix, nl, sun_grid=False):
     """Algorithmic work of each kernel class per render.  Weights are stored
     as a scalar per path or shadow record plus nb per-wavelength factors only
     for paths and records whose wavelengths differ (glass, coloured albedo):
@@ -48,7 +49,9 @@ def kernel_models(stats, nb, npix, nl):
       shadow_accum  16 B per record plus 4 nb B per spectral record
       finalize      12 nl + 24 B per pixel
     Traversal (trace, shadow) counts 96 flop per wide node visited and 50 per
-    triangle tested; the network 2 x 9216 flop per (vertex, wavelength)."""
+    triangle tested; with a sun grid, shadow rays count 2 flop per candidate
+    examined instead of node visits; the network 2 x 9216 flop per (vertex,
+    wavelength)."""
     Ng, Nc, Ns, F = stats["paths"], stats["closest_segments"], stats["shadow_segments"], stats["forks"]
     Nsp, Nsr = stats.get("spectral_paths", 0), stats.get("spectral_records", 0)
     m = {
@@ -56,7 +59,7 @@ def kernel_models(stats, nb, npix, nl):
         "trace": ("alu", stats["nodes_visited"]["closest"] * FLOPS_PER_NODE
                   + stats["tris_tested"]["closest"] * FLOPS_PER_TRI),
         "shade": ("hbm", Nc * (56 + 44) + Ns * 28 + Nsp * 8 * nb + Nsr * 4 * nb + F * (44 + 4 * nb)),
-        "shadow": ("alu", stats["nodes_visited"]["shadow"] * FLOPS_PER_NODE
+        "shadow": ("alu", stats["nodes_visited"]["shadow"] * (FLOPS_PER_CAND if sun_grid else FLOPS_PER_NODE)
                    + stats["tris_tested"]["shadow"] * FLOPS_PER_TRI),
         "shadow_accum": ("hbm", Ns * 16 + Nsr * 4 * nb),
         "shade_glass": ("alu", 0),
@@ -386,7 +389,8 @@ def main():
     samples = W * H * st.spp * nl
     value = samples * args.steps / dt
     nb = -(-nl // args.bands)
-    models = kernel_models(s, nb, W * H, nl)
+    info = gs.info()
+    models = kernel_models(s, nb, W * H, nl, sun_grid=info["grid_cells"] > 0)
     kernels = {}
     for k in sdm.KERNELS:
         if kl[k] == 0:
@@ -435,6 +439,8 @@ def main():
         "roofline": {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
                      "unit": kd["unit"], "frac": kd["frac"], "traffic": measured_traffic(dom)},
         "kernels": kernels,
+        "accel": {"bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"], "stack_bound": info["stack"],
+                  "sun_grid_cells": info["grid_cells"], "sun_grid_candidates": info["grid_candidates"]},
         "segments_per_s": (s["closest_segments"] + s["shadow_segments"]) * args.steps / dt,
         "distinct_rays_per_step": {"closest": s["closest_segments"], "shadow": s["shadow_segments"],
                                    "forks": s["forks"]},

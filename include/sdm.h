@@ -154,7 +154,9 @@ typedef struct {
     uint64_t shadow_segments;   /* shadow (any-hit) traversals                 */
     uint64_t forks;             /* paths split at glass by wavelength          */
     uint64_t chunks;            /* wavefront chunks                            */
-    uint64_t nodes_visited[2];  /* BVH node fetches [closest-hit, shadow]      */
+    uint64_t nodes_visited[2];  /* [closest-hit, shadow]: wide BVH node fetches;
+                                   for shadow rays of a scene with a sun grid,
+                                   grid candidates examined instead          */
     uint64_t tris_tested[2];    /* ray-triangle tests [closest-hit, shadow]    */
     uint64_t bubbly_vertices;   /* path vertices shaded on bubbly panes         */
     uint64_t spectral_paths;    /* closest-hit segments whose wavelengths carry

@@ -72,19 +72,31 @@ def kernel_models(stats, nb, npix, nl, sun_grid=False):
     return m
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel factors),
-    or None when the kernel source has changed since it was measured."""
+def source_digest():
+    """sha256 over the library's sources (every file of csrc/, by name): the
+    kernels and the structures the host builds for them."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1912_05494_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".cpp", ".hpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of kernel class `kernel` from the committed
+    rocprofv3 --pmc summary (FETCH_SIZE and WRITE_SIZE scaled by the
+    copy-kernel factors), or None when the sources have changed since it was
+    measured."""
     path = os.path.join(ROOT, "profiles", "nave512_pmc_traffic.json")
-    src = os.path.join(ROOT, "paper_1912_05494_amd", "csrc", "wavefront.hip")
     try:
         meta = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = source_digest()
     except (OSError, ValueError):
         return None
-    if meta.get("kernel_source_sha256") != sha or kernel not in meta.get("kernels", {}):
+    if meta.get("source_sha256") != sha or kernel not in meta.get("kernels", {}):
         return None
     return meta["kernels"][kernel]["bytes_per_launch"]
 

@@ -215,6 +215,7 @@ struct ChunkArgs {
     uint32_t chunk;
     int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec;
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
+    int32_t acc_lds;            // staged table bytes of the accumulation pass (one job), or 0
 };
 
 template <class R>
@@ -250,7 +251,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.one_job != 0, a.grid_st, s);
         done();
         mark(SDM_K_SHADOW_ACCUM);
-        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.grid_a, s);
+        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.one_job != 0, a.acc_lds, a.grid_a, s);
         done();
         cur ^= 1;
     }
@@ -443,7 +444,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.grid_e = ctx->num_cu * occupancy<R>(SDM_K_BUBBLY_EVAL);
         a.grid_b = ctx->num_cu * occupancy<R>(SDM_K_SHADE_BUBBLY);
         a.grid_st = ctx->num_cu * occupancy<R>(SDM_K_SHADOW);
-        a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM);
+        a.acc_lds = nj == 1 ? accum_lds_bytes<R>(jobs[0].sc->n_mat, jobs[0].p->n_lambda) : 0;
+        a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM, a.acc_lds);
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
         const size_t gthreads = (size_t)std::max(a.grid_t, a.grid_st) * block_size();
         int stack = 0;

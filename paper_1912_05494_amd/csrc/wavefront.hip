@@ -1386,10 +1386,47 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
 // most waves idle at the end, and a shared claim counter costs more than it
 // balances.
 
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w)
+// Spectral tables of the accumulation pass for one job: wavelengths, sun and
+// sky spectra [nl], then the materials' n, k and tint [n_mat][nl].  kLds: the
+// launch renders one job whose tables fit kAccLdsBytes, staged once per block
+// in LDS; otherwise each lane reads its job's arrays.
+constexpr int kAccLdsBytes = 36 * 1024;
+
+template <class R, bool kLds>
+struct AccTab {
+    const R *lam, *E, *sky, *n, *k, *tint;
+    __device__ __forceinline__ R get(const R *p, size_t i) const
+    {
+        if constexpr (kLds) return p[i];
+        else return gld(p + i);
+    }
+};
+
+template <class R, bool kOne, bool kLds>
+__global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restrict__ jobs,
+                                                         const BandDev *__restrict__ bands, Work<R> w)
 {
     __shared__ uint32_t s_buf[kBlock / 64][128];
+    extern __shared__ __align__(16) unsigned char s_tab[];
+    static_assert(kOne || !kLds, "tables are staged for one job only");
+    AccTab<R, kLds> tab{};
+    if constexpr (kLds) {
+        const JobDev &j0 = jobs[0];
+        const int nl = j0.nl, nmnl = j0.sc.n_mat * j0.nl;
+        R *d = reinterpret_cast<R *>(s_tab);
+        for (int i = threadIdx.x; i < nl; i += kBlock) {
+            d[i] = gld((const R *)j0.lam + i);
+            d[nl + i] = gld((const R *)j0.E + i);
+            d[2 * nl + i] = gld((const R *)j0.Lsky + i);
+        }
+        for (int i = threadIdx.x; i < nmnl; i += kBlock) {
+            d[3 * nl + i] = gld((const R *)j0.n + i);
+            d[3 * nl + nmnl + i] = gld((const R *)j0.k + i);
+            d[3 * nl + 2 * nmnl + i] = gld((const R *)j0.tint + i);
+        }
+        __syncthreads();
+        tab = {d, d + nl, d + 2 * nl, d + 3 * nl, d + 3 * nl + nmnl, d + 3 * nl + 2 * nmnl};
+    }
     // sun records [0, ns), then the sky records of escaped paths stored from
     // the back of the buffer (one record per path, so the ranges are disjoint)
     const uint32_t ns = min(w.cnt->scount, w.cap);
@@ -1416,27 +1453,26 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restric
         const uint32_t take = min(nbuf, 64u);
         const bool act = lane < take;
         const uint32_t rec = act ? buf[lane] : 0u;
-        int ng = -1, nb = 0;
-        bool spec = false;
+        int ng = -1, nb = 0, nl = 0, l0 = 0;
+        bool spec = false, sky = false;
         R scs = R(0);
         uint64_t key0 = ~0ull;
-        const JobDev *jb = nullptr;
-        BandDev bd = {0, 0, 0, 0};
+        const JobDev *jb = &jobs[0];
         R gc[kMaxGlass], gd[kMaxGlass], gs[kMaxGlass];
         int gm[kMaxGlass];
-        const R *spectrum = nullptr;   // sun irradiance, or sky radiance for sky records
         if (act) {
-            const bool sky = rec >= ns;
+            sky = rec >= ns;
             ng = sky ? 0 : w.socc[rec];
             const uint32_t aux = w.saux[rec];
-            jb = &jobs[aux >> kAuxJobShift];
-            bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+            if (!kOne) jb = &jobs[aux >> kAuxJobShift];
+            const BandDev bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
             nb = bd.nb;
+            l0 = bd.l0;
+            nl = jb->nl;
             const uint32_t sp = w.spix[rec];
             spec = (sp & kSpectral) != 0u;
             scs = w.scs[rec];
-            key0 = jb->acc_off + (uint64_t)(sp & ~kSpectral) * jb->nl + bd.l0;
-            spectrum = (const R *)(sky ? jb->Lsky : jb->E) + bd.l0;
+            key0 = jb->acc_off + (uint64_t)(sp & ~kSpectral) * nl + l0;
             const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
 #pragma unroll
             for (int g = 0; g < kMaxGlass; ++g) {
@@ -1456,29 +1492,48 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restric
                 }
             }
         }
+        if constexpr (!kLds) {
+            // per-lane tables of the lane's job
+            tab = {(const R *)jb->lam, (const R *)jb->E, (const R *)jb->Lsky, (const R *)jb->n, (const R *)jb->k,
+                   (const R *)jb->tint};
+        }
+        const R *spectrum = sky ? tab.sky : tab.E;   // sky radiance for sky records, else the sun's
         int jmax = nb;
         for (int off = 32; off > 0; off >>= 1) jmax = max(jmax, __shfl_xor(jmax, off));
         const uint32_t start = run_start(key0);
         const bool lst = run_last(key0);
-        for (int j = 0; j < jmax; j += 4) {
-            double v[4];
+        // one pane's factor on the four wavelengths l0 + j + q
+        auto pane = [&](R c, R d, int m, R sig, int j, R (&T)[4]) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                v[q] = 0.0;
                 if (j + q < nb) {
-                    R T = scs * gld(spectrum + j + q);
-                    if (spec) T *= w.contrib[aosoa(rec, j + q, nbm)];
-                    for (int g = 0; g < ng; ++g) {
-                        const size_t mo = (size_t)gm[g] * jb->nl + bd.l0 + j + q;
-                        R Rr, Tt;
-                        slab_RT<R>(gc[g], gld((const R *)jb->lam + bd.l0 + j + q), gd[g],
-                                   gld((const R *)jb->n + mo), gld((const R *)jb->k + mo),
-                                   gld((const R *)jb->tint + mo) + gs[g], Rr, Tt);
-                        T *= Tt;
-                    }
-                    v[q] = (double)T;
+                    const int l = l0 + j + q;
+                    const size_t mo = (size_t)m * nl + l;
+                    R Rr, Tt;
+                    slab_RT<R>(c, tab.get(tab.lam, l), d, tab.get(tab.n, mo), tab.get(tab.k, mo),
+                               tab.get(tab.tint, mo) + sig, Rr, Tt);
+                    T[q] *= Tt;
                 }
             }
+        };
+        for (int j = 0; j < jmax; j += 4) {
+            R T[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T[q] = R(0);
+                if (j + q < nb) {
+                    T[q] = scs * tab.get(spectrum, l0 + j + q);
+                    if (spec) T[q] *= w.contrib[aosoa(rec, j + q, nbm)];
+                }
+            }
+            // the first two panes with fixed slots (nearly every sun record crosses
+            // one), further ones in a loop
+            if (ng > 0) pane(gc[0], gd[0], gm[0], gs[0], j, T);
+            if (ng > 1) pane(gc[1], gd[1], gm[1], gs[1], j, T);
+            for (int g = 2; g < ng; ++g) pane(gc[g], gd[g], gm[g], gs[g], j, T);
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = (double)T[q];
             run_add_k<4>(w.acc, key0, j, nb, start, lst, v);
         }
         // keep the records not processed yet at the front of the buffer
@@ -1738,9 +1793,23 @@ void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R>
     else hipLaunchKernelGGL((k_shadow_trace<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, lds_job);
 }
 template <class R>
-void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s)
+void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int lds_bytes,
+                         int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shadow_accum<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w);
+    const dim3 g(grid), b(kBlock);
+    if (one_job && lds_bytes > 0)
+        hipLaunchKernelGGL((k_shadow_accum<R, true, true>), g, b, lds_bytes, s, jobs, bands, w);
+    else if (one_job)
+        hipLaunchKernelGGL((k_shadow_accum<R, true, false>), g, b, 0, s, jobs, bands, w);
+    else
+        hipLaunchKernelGGL((k_shadow_accum<R, false, false>), g, b, 0, s, jobs, bands, w);
+}
+
+template <class R>
+int accum_lds_bytes(int n_mat, int nl)
+{
+    const size_t b = (3 * (size_t)nl + 3 * (size_t)n_mat * nl) * sizeof(R);
+    return b <= (size_t)kAccLdsBytes ? (int)((b + 15) / 16 * 16) : 0;
 }
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
@@ -1797,7 +1866,7 @@ int block_size() { return kBlock; }
 // exactly the blocks the chip holds at once, so no block waits for a second
 // round while the others idle.
 template <class R>
-int occupancy(int kernel_class)
+int occupancy(int kernel_class, int lds_bytes)
 {
     const void *f = nullptr;
     switch (kernel_class) {
@@ -1810,11 +1879,14 @@ int occupancy(int kernel_class)
         break;
     case SDM_K_SHADE_BUBBLY: f = (const void *)k_shade_bubbly<R>; break;
     case SDM_K_SHADOW: f = (const void *)k_shadow_trace<R, false>; break;
-    case SDM_K_SHADOW_ACCUM: f = (const void *)k_shadow_accum<R>; break;
+    case SDM_K_SHADOW_ACCUM:
+        if (lds_bytes > 0) f = (const void *)k_shadow_accum<R, true, true>;
+        else f = (const void *)k_shadow_accum<R, false, false>;
+        break;
     default: return 1;
     }
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, kBlock, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, kBlock, lds_bytes) != hipSuccess) return 1;
     return std::max(1, b);
 }
 
@@ -1828,10 +1900,11 @@ int occupancy(int kernel_class)
                                         const float *, const float *, const float *, int, hipStream_t);            \
     template void launch_shade_bubbly<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
     template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t); \
-    template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, int, hipStream_t);      \
+    template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, bool, int, int, hipStream_t); \
     template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,              \
                                      hipStream_t);                                                                 \
-    template int occupancy<R>(int);
+    template int occupancy<R>(int, int);                                                                            \
+    template int accum_lds_bytes<R>(int, int);
 
 SDM_INSTANTIATE(float)
 SDM_INSTANTIATE(double)

@@ -27,13 +27,18 @@ template <class R>
 void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, bool one_job,
                          int grid, hipStream_t s);
 template <class R>
-void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s);
+void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int lds_bytes,
+                         int grid, hipStream_t s);
+// LDS bytes of the accumulation pass's staged tables for one job (0: they do not fit)
+template <class R>
+int accum_lds_bytes(int n_mat, int nl);
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
                      hipStream_t s);
-// Resident blocks of 256 threads per CU of a render kernel (SDM_K_* class).
+// Resident blocks of 256 threads per CU of a render kernel (SDM_K_* class)
+// with lds_bytes of dynamic LDS.
 template <class R>
-int occupancy(int kernel_class);
+int occupancy(int kernel_class, int lds_bytes = 0);
 
 void launch_finalize(const double *acc, int64_t npix, int nl, int spp, const double *wts, const double *cmf,
                      float *spec, double *xyz, hipStream_t s);

@@ -215,7 +215,6 @@ struct ChunkArgs {
     uint32_t chunk;
     int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec;
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
-    int32_t acc_lds;            // staged table bytes of the accumulation pass (one job), or 0
 };
 
 template <class R>
@@ -232,10 +231,10 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0, a.one_job != 0, a.grid_t, s);
         done();
         mark(SDM_K_SHADE);
-        launch_shade<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
+        launch_shade<R>(a.jobs, a.bands, a.w, cur, a.one_job != 0, a.grid_s, s);
         done();
         mark(SDM_K_SHADE_GLASS);
-        launch_shade_glass<R>(a.jobs, a.bands, a.w, cur, a.grid_gl, s);
+        launch_shade_glass<R>(a.jobs, a.bands, a.w, cur, a.one_job != 0, a.grid_gl, s);
         done();
         if (a.surr) {
             mark(SDM_K_BUBBLY_EVAL);
@@ -251,7 +250,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.one_job != 0, a.grid_st, s);
         done();
         mark(SDM_K_SHADOW_ACCUM);
-        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.one_job != 0, a.acc_lds, a.grid_a, s);
+        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.one_job != 0, a.grid_a, s);
         done();
         cur ^= 1;
     }
@@ -444,8 +443,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.grid_e = ctx->num_cu * occupancy<R>(SDM_K_BUBBLY_EVAL);
         a.grid_b = ctx->num_cu * occupancy<R>(SDM_K_SHADE_BUBBLY);
         a.grid_st = ctx->num_cu * occupancy<R>(SDM_K_SHADOW);
-        a.acc_lds = nj == 1 ? accum_lds_bytes<R>(jobs[0].sc->n_mat, jobs[0].p->n_lambda) : 0;
-        a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM, a.acc_lds);
+        a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM);
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
         const size_t gthreads = (size_t)std::max(a.grid_t, a.grid_st) * block_size();
         int stack = 0;

@@ -493,9 +493,6 @@ __device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, R u, R
 }
 
 // ---------------------------------------------------------------------------
-// Wave-level segmented sum over runs of lanes with equal keys, then one FP64
-// atomic per run.  All lanes call it; lanes with key ~0 add nothing.
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t run_start(uint64_t key)
 {
     const uint32_t lane = lane_id();
@@ -709,7 +706,7 @@ __device__ __forceinline__ void block_reserve(const bool (&want)[Q], uint32_t *c
     __syncthreads();   // s_cnt and s_base are reused by the next call
 }
 
-template <class R>
+template <class R, bool kOne>
 __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
@@ -739,7 +736,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(const JobDev *__restrict__ job
             spec = (smp & kSpectral) != 0u;
             g = Pi.g[i];
             const int depth = (int)(aux & 0xffu);
-            jb = &jobs[aux >> kAuxJobShift];
+            jb = &jobs[kOne ? 0u : aux >> kAuxJobShift];
             bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
             tri = w.htri[i];
             const bool last = depth >= jb->max_depth - 1;
@@ -921,7 +918,7 @@ __device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, 
 // its weight multiplied by R + T.  When a band splits, the path forks: the
 // reflected wavelengths continue in a new pool slot.
 // ---------------------------------------------------------------------------
-template <class R>
+template <class R, bool kOne>
 __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->gcount, w.cap);
@@ -948,7 +945,7 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict
             const bool spec = (smp & kSpectral) != 0u;
             g = Pi.g[i];
             const int depth = (int)(aux & 0xffu);
-            const JobDev *jb = &jobs[aux >> kAuxJobShift];
+            const JobDev *jb = &jobs[kOne ? 0u : aux >> kAuxJobShift];
             bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
             tri = w.htri[i];
             const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
@@ -1376,57 +1373,55 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
 
 // Per wavelength: the record's contribution times the slab transmittance of
 // each pane crossed (at the sun angle, thickness at the crossing) -- or, for
-// the sky record of an escaped path, its weight times the sky radiance -- summed
-// over runs of lanes of the same pixel, added to the FP64 accumulator.  Each
-// wave walks a contiguous range of records and compacts the unoccluded ones
-// in LDS (order kept, so runs of one pixel stay together) before the
-// per-wavelength loop, which then runs on full waves.  Wave w takes the
-// 64-record groups w, w + W, w + 2W, ... (W waves): occlusion and pane counts
-// vary along the record buffer, so one contiguous range per wave would leave
-// most waves idle at the end, and a shared claim counter costs more than it
-// balances.
+// the sky record of an escaped path, its weight times the sky radiance --
+// added to the FP64 accumulator row of its pixel.
+//
+// The accumulator's FP64 atomic adds are performed on the memory side, one
+// request per lane address, so the pass is arranged for few, contiguous
+// atomics.  Wave w takes the nominal groups w, w + W, w + 2W, ... of
+// kAccGroup records (W waves; interleaved because occlusion and pane counts
+// vary along the record buffer), each moved to start and end where the
+// pixel changes.  Batches of up to 64 unoccluded records go through two
+// phases: lanes over records compute each record's setup (pane cosines,
+// thicknesses, materials) into LDS; then lanes over wavelengths walk the
+// batch's records in order, summing a pixel's records in registers (also
+// across batches) and adding the row with one atomic instruction per 64
+// consecutive wavelengths when the pixel changes.
+constexpr uint32_t kAccGroup = 64;   // nominal records per group of the accumulation pass
+constexpr int kAccPanes = 2;         // panes per record held in LDS (more are read again from the record)
 
-// Spectral tables of the accumulation pass for one job: wavelengths, sun and
-// sky spectra [nl], then the materials' n, k and tint [n_mat][nl].  kLds: the
-// launch renders one job whose tables fit kAccLdsBytes, staged once per block
-// in LDS; otherwise each lane reads its job's arrays.
-constexpr int kAccLdsBytes = 36 * 1024;
-
-template <class R, bool kLds>
-struct AccTab {
-    const R *lam, *E, *sky, *n, *k, *tint;
-    __device__ __forceinline__ R get(const R *p, size_t i) const
-    {
-        if constexpr (kLds) return p[i];
-        else return gld(p + i);
-    }
+template <class R>
+struct AccRec {
+    uint64_t key;        // accumulator row (its wavelength l0 included)
+    R scs;               // scalar factor
+    uint32_t rec;        // record slot (per-wavelength factors, further panes)
+    int32_t job, l0, nb, ng;
+    int32_t flags;       // bit 0: spectral factors, bit 1: sky record
+    R c[kAccPanes], d[kAccPanes], sig[kAccPanes];
+    int32_t m[kAccPanes];
 };
 
-template <class R, bool kOne, bool kLds>
+template <class R>
+__device__ __forceinline__ void pane_geometry(const JobDev *jb, const Work<R> &w, uint32_t rec, int g, R &c, R &d,
+                                              int &m, R &sig)
+{
+    const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
+    const int leaf = w.sg_leaf[(size_t)rec * kMaxGlass + g];
+    const TriDev tr = load_tri(jb->sc.tris, leaf);
+    c = fabs(dot(sun, tri_normal<R>(tr)));
+    d = pane_thickness<R>(jb->sc, leaf, w.sg_u[(size_t)rec * kMaxGlass + g], w.sg_v[(size_t)rec * kMaxGlass + g]);
+    m = __float_as_int(tr.b.w);
+    // toward the delta sun a bubbly pane passes its unscattered light: the
+    // bubbles' extinction adds to the absorption
+    sig = R(gld(jb->sc.mat_bub + 4 * m));
+}
+
+template <class R, bool kOne>
 __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restrict__ jobs,
                                                          const BandDev *__restrict__ bands, Work<R> w)
 {
     __shared__ uint32_t s_buf[kBlock / 64][128];
-    extern __shared__ __align__(16) unsigned char s_tab[];
-    static_assert(kOne || !kLds, "tables are staged for one job only");
-    AccTab<R, kLds> tab{};
-    if constexpr (kLds) {
-        const JobDev &j0 = jobs[0];
-        const int nl = j0.nl, nmnl = j0.sc.n_mat * j0.nl;
-        R *d = reinterpret_cast<R *>(s_tab);
-        for (int i = threadIdx.x; i < nl; i += kBlock) {
-            d[i] = gld((const R *)j0.lam + i);
-            d[nl + i] = gld((const R *)j0.E + i);
-            d[2 * nl + i] = gld((const R *)j0.Lsky + i);
-        }
-        for (int i = threadIdx.x; i < nmnl; i += kBlock) {
-            d[3 * nl + i] = gld((const R *)j0.n + i);
-            d[3 * nl + nmnl + i] = gld((const R *)j0.k + i);
-            d[3 * nl + 2 * nmnl + i] = gld((const R *)j0.tint + i);
-        }
-        __syncthreads();
-        tab = {d, d + nl, d + 2 * nl, d + 3 * nl, d + 3 * nl + nmnl, d + 3 * nl + 2 * nmnl};
-    }
+    __shared__ AccRec<R> s_rec[kBlock / 64][64];
     // sun records [0, ns), then the sky records of escaped paths stored from
     // the back of the buffer (one record per path, so the ranges are disjoint)
     const uint32_t ns = min(w.cnt->scount, w.cap);
@@ -1435,106 +1430,135 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restric
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
-    uint32_t *buf = s_buf[threadIdx.x >> 6];
+    const uint32_t wv = threadIdx.x >> 6;
+    uint32_t *buf = s_buf[wv];
+    AccRec<R> *rb = s_rec[wv];
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    uint32_t base = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64u, nbuf = 0;
+    auto rec_of = [&](uint32_t i) { return i < ns ? i : w.cap - 1u - (i - ns); };
+    // records of one accumulator row (job, band, pixel) share this key
+    auto key_at = [&](uint32_t i) {
+        const uint32_t r = rec_of(i);
+        return ((uint64_t)(w.saux[r] >> kAuxBandShift) << 32) | (w.spix[r] & ~kSpectral);
+    };
+    // first index >= x that starts a run of equal keys (all lanes together)
+    auto run_start_at = [&](uint32_t x) -> uint32_t {
+        if (x == 0 || x >= count) return min(x, count);
+        const uint64_t kp = key_at(x - 1);
+        for (uint32_t y = x; y < count; y += 64) {
+            const uint32_t i = y + lane;
+            const uint64_t m = __ballot(i >= count || key_at(i) != kp);
+            if (m) return min(count, y + (uint32_t)__ffsll((unsigned long long)m) - 1u);
+        }
+        return count;
+    };
+    // the row being summed (wave-uniform) and its sums at wavelengths lane and lane + 64
+    uint64_t row = ~0ull;
+    int row_nb = 0;
+    double s0 = 0.0, s1 = 0.0;
+    auto flush = [&]() {
+        if (row != ~0ull) {
+            if ((int)lane < row_nb && s0 != 0.0) unsafeAtomicAdd(w.acc + row + lane, s0);
+            if ((int)lane + 64 < row_nb && s1 != 0.0) unsafeAtomicAdd(w.acc + row + lane + 64, s1);
+        }
+        s0 = s1 = 0.0;
+    };
+    uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    uint32_t base = 0, gb = 0, nbuf = 0;
+    bool groups_left = true;
     for (;;) {
-        while (nbuf < 64 && base < count) {
+        while (nbuf < 64 && groups_left) {
+            if (base >= gb) {   // next group of this wave
+                if ((uint64_t)g * kAccGroup >= count) {
+                    groups_left = false;
+                    break;
+                }
+                base = run_start_at(g * kAccGroup);
+                gb = run_start_at((uint32_t)min<uint64_t>((uint64_t)(g + 1) * kAccGroup, count));
+                g += nwaves;
+                continue;
+            }
             const uint32_t i = base + lane;
-            const uint32_t rec_i = i < ns ? i : w.cap - 1u - (i - ns);
-            const bool ok = i < count && (i >= ns || w.socc[i] >= 0);
+            const bool ok = i < gb && (i >= ns || w.socc[i] >= 0);
             const uint64_t m = __ballot(ok);
-            if (ok) buf[nbuf + (uint32_t)__popcll(m & lt)] = rec_i;
+            if (ok) buf[nbuf + (uint32_t)__popcll(m & lt)] = rec_of(i);
             nbuf += (uint32_t)__popcll(m);
-            base += 64u * nwaves;
+            base = min(gb, base + 64u);
         }
         __builtin_amdgcn_wave_barrier();
         if (nbuf == 0) break;
         const uint32_t take = min(nbuf, 64u);
-        const bool act = lane < take;
-        const uint32_t rec = act ? buf[lane] : 0u;
-        int ng = -1, nb = 0, nl = 0, l0 = 0;
-        bool spec = false, sky = false;
-        R scs = R(0);
-        uint64_t key0 = ~0ull;
-        const JobDev *jb = &jobs[0];
-        R gc[kMaxGlass], gd[kMaxGlass], gs[kMaxGlass];
-        int gm[kMaxGlass];
-        if (act) {
-            sky = rec >= ns;
-            ng = sky ? 0 : w.socc[rec];
+        // phase 1, lanes over records: each record's setup
+        if (lane < take) {
+            const uint32_t rec = buf[lane];
+            AccRec<R> a;
+            const bool sky = rec >= ns;
             const uint32_t aux = w.saux[rec];
-            if (!kOne) jb = &jobs[aux >> kAuxJobShift];
+            a.job = kOne ? 0 : (int)(aux >> kAuxJobShift);
+            const JobDev *jb = &jobs[a.job];
             const BandDev bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
-            nb = bd.nb;
-            l0 = bd.l0;
-            nl = jb->nl;
             const uint32_t sp = w.spix[rec];
-            spec = (sp & kSpectral) != 0u;
-            scs = w.scs[rec];
-            key0 = jb->acc_off + (uint64_t)(sp & ~kSpectral) * nl + l0;
-            const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
+            a.rec = rec;
+            a.l0 = bd.l0;
+            a.nb = bd.nb;
+            a.ng = sky ? 0 : w.socc[rec];
+            a.flags = ((sp & kSpectral) ? 1 : 0) | (sky ? 2 : 0);
+            a.scs = w.scs[rec];
+            a.key = jb->acc_off + (uint64_t)(sp & ~kSpectral) * jb->nl + bd.l0;
 #pragma unroll
-            for (int g = 0; g < kMaxGlass; ++g) {
-                if (g < ng) {
-                    const int leaf = w.sg_leaf[(size_t)rec * kMaxGlass + g];
-                    const TriDev tr = load_tri(jb->sc.tris, leaf);
-                    gc[g] = fabs(dot(sun, tri_normal<R>(tr)));
-                    gd[g] = pane_thickness<R>(jb->sc, leaf, w.sg_u[(size_t)rec * kMaxGlass + g],
-                                              w.sg_v[(size_t)rec * kMaxGlass + g]);
-                    gm[g] = __float_as_int(tr.b.w);
-                    // toward the delta sun a bubbly pane passes its unscattered light:
-                    // the bubbles' extinction adds to the absorption
-                    gs[g] = R(gld(jb->sc.mat_bub + 4 * gm[g]));
+            for (int q = 0; q < kAccPanes; ++q) {
+                if (q < a.ng) {
+                    pane_geometry(jb, w, rec, q, a.c[q], a.d[q], a.m[q], a.sig[q]);
                 } else {
-                    gc[g] = gd[g] = gs[g] = R(0);
-                    gm[g] = 0;
+                    a.c[q] = a.d[q] = a.sig[q] = R(0);
+                    a.m[q] = 0;
                 }
             }
+            rb[lane] = a;
         }
-        if constexpr (!kLds) {
-            // per-lane tables of the lane's job
-            tab = {(const R *)jb->lam, (const R *)jb->E, (const R *)jb->Lsky, (const R *)jb->n, (const R *)jb->k,
-                   (const R *)jb->tint};
-        }
-        const R *spectrum = sky ? tab.sky : tab.E;   // sky radiance for sky records, else the sun's
-        int jmax = nb;
-        for (int off = 32; off > 0; off >>= 1) jmax = max(jmax, __shfl_xor(jmax, off));
-        const uint32_t start = run_start(key0);
-        const bool lst = run_last(key0);
-        // one pane's factor on the four wavelengths l0 + j + q
-        auto pane = [&](R c, R d, int m, R sig, int j, R (&T)[4]) {
+        __builtin_amdgcn_wave_barrier();
+        // phase 2, lanes over wavelengths: the batch's records in order
+        for (uint32_t r = 0; r < take; ++r) {
+            const AccRec<R> a = rb[r];
+            if (a.key != row) {
+                flush();
+                row = a.key;
+                row_nb = a.nb;
+            }
+            const JobDev *jb = &jobs[kOne ? 0 : a.job];
+            const R *spectrum = (const R *)((a.flags & 2) ? jb->Lsky : jb->E);
+            const R *lam = (const R *)jb->lam;
+            const R *tn = (const R *)jb->n, *tk = (const R *)jb->k, *tt = (const R *)jb->tint;
+            const int nl = jb->nl;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (j + q < nb) {
-                    const int l = l0 + j + q;
+            for (int h = 0; h < 2; ++h) {
+                const int j = (int)lane + 64 * h;
+                if (j >= a.nb) continue;
+                const int l = a.l0 + j;
+                R T = a.scs * gld(spectrum + l);
+                if (a.flags & 1) T *= w.contrib[aosoa(a.rec, j, nbm)];
+                R lamv = R(0);
+                if (a.ng > 0) lamv = gld(lam + l);
+#pragma unroll
+                for (int q = 0; q < kAccPanes; ++q) {
+                    if (q < a.ng) {
+                        const size_t mo = (size_t)a.m[q] * nl + l;
+                        R Rr, Tt;
+                        slab_RT<R>(a.c[q], lamv, a.d[q], gld(tn + mo), gld(tk + mo), gld(tt + mo) + a.sig[q], Rr, Tt);
+                        T *= Tt;
+                    }
+                }
+                for (int q = kAccPanes; q < a.ng; ++q) {   // rare: further panes, set up again here
+                    R c, d, sig;
+                    int m;
+                    pane_geometry(jb, w, a.rec, q, c, d, m, sig);
                     const size_t mo = (size_t)m * nl + l;
                     R Rr, Tt;
-                    slab_RT<R>(c, tab.get(tab.lam, l), d, tab.get(tab.n, mo), tab.get(tab.k, mo),
-                               tab.get(tab.tint, mo) + sig, Rr, Tt);
-                    T[q] *= Tt;
+                    slab_RT<R>(c, lamv, d, gld(tn + mo), gld(tk + mo), gld(tt + mo) + sig, Rr, Tt);
+                    T *= Tt;
                 }
+                if (h == 0) s0 += (double)T;
+                else s1 += (double)T;
             }
-        };
-        for (int j = 0; j < jmax; j += 4) {
-            R T[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                T[q] = R(0);
-                if (j + q < nb) {
-                    T[q] = scs * tab.get(spectrum, l0 + j + q);
-                    if (spec) T[q] *= w.contrib[aosoa(rec, j + q, nbm)];
-                }
-            }
-            // the first two panes with fixed slots (nearly every sun record crosses
-            // one), further ones in a loop
-            if (ng > 0) pane(gc[0], gd[0], gm[0], gs[0], j, T);
-            if (ng > 1) pane(gc[1], gd[1], gm[1], gs[1], j, T);
-            for (int g = 2; g < ng; ++g) pane(gc[g], gd[g], gm[g], gs[g], j, T);
-            double v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = (double)T[q];
-            run_add_k<4>(w.acc, key0, j, nb, start, lst, v);
         }
         // keep the records not processed yet at the front of the buffer
         const uint32_t rem = nbuf - take;
@@ -1544,6 +1568,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restric
         __builtin_amdgcn_wave_barrier();
         nbuf = rem;
     }
+    flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -1761,14 +1786,18 @@ void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bo
     }
 }
 template <class R>
-void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
+void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
+                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shade<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+    if (one_job) hipLaunchKernelGGL((k_shade<R, true>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+    else hipLaunchKernelGGL((k_shade<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
 }
 template <class R>
-void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
+void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
+                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shade_glass<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+    if (one_job) hipLaunchKernelGGL((k_shade_glass<R, true>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+    else hipLaunchKernelGGL((k_shade_glass<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
 }
 template <class R>
 void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const void *wb,
@@ -1793,24 +1822,13 @@ void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R>
     else hipLaunchKernelGGL((k_shadow_trace<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, lds_job);
 }
 template <class R>
-void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int lds_bytes,
-                         int grid, hipStream_t s)
+void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int grid,
+                         hipStream_t s)
 {
-    const dim3 g(grid), b(kBlock);
-    if (one_job && lds_bytes > 0)
-        hipLaunchKernelGGL((k_shadow_accum<R, true, true>), g, b, lds_bytes, s, jobs, bands, w);
-    else if (one_job)
-        hipLaunchKernelGGL((k_shadow_accum<R, true, false>), g, b, 0, s, jobs, bands, w);
-    else
-        hipLaunchKernelGGL((k_shadow_accum<R, false, false>), g, b, 0, s, jobs, bands, w);
+    if (one_job) hipLaunchKernelGGL((k_shadow_accum<R, true>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w);
+    else hipLaunchKernelGGL((k_shadow_accum<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w);
 }
 
-template <class R>
-int accum_lds_bytes(int n_mat, int nl)
-{
-    const size_t b = (3 * (size_t)nl + 3 * (size_t)n_mat * nl) * sizeof(R);
-    return b <= (size_t)kAccLdsBytes ? (int)((b + 15) / 16 * 16) : 0;
-}
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
                      hipStream_t s)
@@ -1871,18 +1889,15 @@ int occupancy(int kernel_class, int lds_bytes)
     const void *f = nullptr;
     switch (kernel_class) {
     case SDM_K_TRACE: f = (const void *)k_trace<R, true, false>; break;
-    case SDM_K_SHADE: f = (const void *)k_shade<R>; break;
-    case SDM_K_SHADE_GLASS: f = (const void *)k_shade_glass<R>; break;
+    case SDM_K_SHADE: f = (const void *)k_shade<R, false>; break;
+    case SDM_K_SHADE_GLASS: f = (const void *)k_shade_glass<R, false>; break;
     case SDM_K_BUBBLY_EVAL:
         if constexpr (sizeof(R) == 4) f = (const void *)k_bubbly_eval_mfma<R>;
         else f = (const void *)k_bubbly_eval_fp64;
         break;
     case SDM_K_SHADE_BUBBLY: f = (const void *)k_shade_bubbly<R>; break;
     case SDM_K_SHADOW: f = (const void *)k_shadow_trace<R, false>; break;
-    case SDM_K_SHADOW_ACCUM:
-        if (lds_bytes > 0) f = (const void *)k_shadow_accum<R, true, true>;
-        else f = (const void *)k_shadow_accum<R, false, false>;
-        break;
+    case SDM_K_SHADOW_ACCUM: f = (const void *)k_shadow_accum<R, false>; break;
     default: return 1;
     }
     int b = 0;
@@ -1894,17 +1909,17 @@ int occupancy(int kernel_class, int lds_bytes)
     template void launch_generate<R>(const JobDev *, const BandDev *, const ItemDev *, int, const Work<R> &,       \
                                      uint64_t, uint32_t, int, hipStream_t);                                        \
     template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, bool, bool, int, hipStream_t);        \
-    template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);        \
-    template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);  \
+    template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t);  \
+    template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int,          \
+                                        hipStream_t);                                                              \
     template void launch_bubbly_eval<R>(const JobDev *, const BandDev *, const Work<R> &, int, const void *,       \
                                         const float *, const float *, const float *, int, hipStream_t);            \
     template void launch_shade_bubbly<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
     template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t); \
-    template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, bool, int, int, hipStream_t); \
+    template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, bool, int, hipStream_t); \
     template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,              \
                                      hipStream_t);                                                                 \
-    template int occupancy<R>(int, int);                                                                            \
-    template int accum_lds_bytes<R>(int, int);
+    template int occupancy<R>(int, int);
 
 SDM_INSTANTIATE(float)
 SDM_INSTANTIATE(double)

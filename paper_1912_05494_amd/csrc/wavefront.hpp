@@ -15,9 +15,11 @@ template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, bool one_job, int grid,
                   hipStream_t s);
 template <class R>
-void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
+void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
+                  hipStream_t s);
 template <class R>
-void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
+void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
+                        hipStream_t s);
 template <class R>
 void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const void *wb,
                         const float *bb, const float *params, const float *E, int grid, hipStream_t s);
@@ -27,11 +29,8 @@ template <class R>
 void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int lds_job, bool one_job,
                          int grid, hipStream_t s);
 template <class R>
-void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int lds_bytes,
-                         int grid, hipStream_t s);
-// LDS bytes of the accumulation pass's staged tables for one job (0: they do not fit)
-template <class R>
-int accum_lds_bytes(int n_mat, int nl);
+void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int grid,
+                         hipStream_t s);
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
                      hipStream_t s);

@@ -493,45 +493,6 @@ __device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, R u, R
 }
 
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t run_start(uint64_t key)
-{
-    const uint32_t lane = lane_id();
-    const uint64_t prev = __shfl_up(key, 1);
-    uint32_t start = (lane == 0 || prev != key) ? lane : 0u;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_up(start, off);
-        if ((int)lane >= off) start = max(start, o);
-    }
-    return start;
-}
-
-__device__ __forceinline__ bool run_last(uint64_t key)
-{
-    const uint64_t next = __shfl_down(key, 1);
-    return lane_id() == 63 || next != key;
-}
-
-// K wavelengths j .. j+K-1 at once (independent shuffle chains); a lane of
-// run base `key0` adds v[q] to acc[key0 + j + q] when j + q < nb.
-template <int K>
-__device__ __forceinline__ void run_add_k(double *acc, uint64_t key0, int j, int nb, uint32_t start, bool last,
-                                          double (&v)[K])
-{
-    const uint32_t lane = lane_id();
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            const double o = __shfl_up(v[q], off);
-            if (lane >= start + (uint32_t)off) v[q] += o;
-        }
-    }
-    if (last && key0 != ~0ull) {
-#pragma unroll
-        for (int q = 0; q < K; ++q)
-            if (j + q < nb && v[q] != 0.0) unsafeAtomicAdd(acc + key0 + j + q, v[q]);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Camera rays (Sec. 3.1: a ray from each pixel).  Image point ((i + u0) / W,
 // (j + u1) / H), row j from the top; pinhole through the unit-distance image

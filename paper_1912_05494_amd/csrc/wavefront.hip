@@ -493,7 +493,6 @@ __device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, R u, R
 }
 
 // ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
 // Camera rays (Sec. 3.1: a ray from each pixel).  Image point ((i + u0) / W,
 // (j + u1) / H), row j from the top; pinhole through the unit-distance image
 // plane, or orthographic rays along the view axis.

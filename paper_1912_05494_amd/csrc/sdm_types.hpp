@@ -181,7 +181,7 @@ constexpr int kAuxBandShift = 8;
 constexpr int kAuxBandBits = 12;
 constexpr int kAuxJobShift = 20;
 constexpr int kMaxBand = 128;
-constexpr int kLdsStack = 12;      // traversal stack levels held in LDS; deeper ones in global memory
+constexpr int kLdsStack = 8;       // traversal stack levels held in LDS; deeper ones in global memory
 constexpr int kMaxBvhDepth = 62;   // depth cap of the binary tree the wide nodes are collapsed from
 constexpr int kMaxLeafTris = 255;  // leaf size bound of the stack encoding
 constexpr int kMaxTris = 1 << 23;  // triangles per scene (stack encoding)

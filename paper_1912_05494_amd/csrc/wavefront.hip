@@ -35,7 +35,7 @@
 
 namespace sdm {
 
-constexpr int kLdsNodes = 64;     // wide-node prefix staged in LDS (8 KB)
+constexpr int kLdsNodes = 160;    // wide-node prefix staged in LDS (20 KB)
 constexpr int kBlock = 256;
 constexpr uint32_t kFetch = 256;  // items per group of the traversal work distribution
 constexpr int32_t kDone = INT_MIN;

@@ -15,7 +15,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(os.path.dirname(HERE), "paper_1912_05494_amd", "csrc")
 NODE = np.dtype([("lox", "<f4", 4), ("hix", "<f4", 4), ("loy", "<f4", 4), ("hiy", "<f4", 4),
                  ("loz", "<f4", 4), ("hiz", "<f4", 4), ("child", "<i4", 4), ("pad", "<i4", 4)])
-LDS_STACK = 12
 
 
 @pytest.fixture(scope="module")

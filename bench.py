@@ -22,10 +22,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # chunk size and pixel tile of the workload as chosen by sdm_autotune on MI355X
-# (bench.py --autotune repeats the choice); the timed runs and the counter
+# (bench.py --autotune repeats the choice): all 2^24 primary paths of the
+# 512x512x64 image in one chunk, 16x16 tiles; the timed runs and the counter
 # runs use the same
-CHUNK_PATHS = 1 << 22
-TILE = 8
+CHUNK_PATHS = 1 << 24
+TILE = 16
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # Plain VALU issue rate of FP32 arithmetic without packed math:

@@ -120,7 +120,7 @@ typedef struct {
     int32_t tile_w, tile_h;     /* pixel-tile work items (0 = library default) */
     float beta_threshold;       /* path-weight threshold (0 = off)             */
     int32_t precision;          /* SDM_PREC_FP32 (default) or SDM_PREC_FP64    */
-    int64_t chunk_paths;        /* in-flight primary paths (0 = default)       */
+    int64_t chunk_paths;        /* in-flight primary paths (0: tuned, else 2^23) */
     int32_t timing;             /* 1: time every kernel with HIP events        */
     /* Bubbly panes.  SDM_BTDF_EXACT: the photon walk of sdm_slab_mc at each
      * vertex (entry interface per wavelength with n + ik, walk inside at the
@@ -215,9 +215,9 @@ typedef struct {
 int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_stats *stats,
                      void *hip_stream);
 
-/* Tuning of the wavefront for a scene and parameters: renders at reduced
- * samples per pixel with candidate chunk sizes (2^20, 2^21, 2^22 paths) and
- * pixel tiles (8x8, 16x16, 32x32), keeps the fastest, and uses it in later
+/* Tuning of the wavefront for a scene and parameters: renders twice with
+ * each candidate chunk size (2^22, 2^23, 2^24 paths) and pixel tile (8x8,
+ * 16x16, 32x32), keeps the fastest, and uses it in later
  * renders of this context with the same scene, image size, wavelength
  * count, depth and precision whose chunk_paths, tile_w and tile_h are 0.
  * cache_path (may be NULL): a text file of earlier results; a matching entry

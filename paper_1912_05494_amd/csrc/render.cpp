@@ -196,7 +196,7 @@ void job_shape(const sdm_context *ctx, const JobIn &j, uint64_t &chunk, int &tw,
                 tw = t.tw;
                 th = t.th;
             }
-    if (chunk == 0) chunk = (uint64_t)1 << 21;
+    if (chunk == 0) chunk = (uint64_t)1 << 23;
     if (tw <= 0) tw = 16;
     if (th <= 0) th = 16;
 }
@@ -703,15 +703,15 @@ int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params 
         }
     }
     if (!found) {
-        // measure at reduced samples per pixel; outputs are not needed
+        // measure the render itself (a chunk size only matters relative to the
+        // whole workload); outputs are not needed
         sdm_render_params q = *p;
-        q.spp = std::max(1, p->spp / 8);
         q.timing = 0;
         q.graph = 0;
         sdm_outputs none{};
         sdm_stats st{};
         none.stats = &st;
-        const long long chunks[3] = {1ll << 20, 1ll << 21, 1ll << 22};
+        const long long chunks[3] = {1ll << 22, 1ll << 23, 1ll << 24};
         const int tiles[3] = {8, 16, 32};
         double best = 1e300;
         for (long long ch : chunks)

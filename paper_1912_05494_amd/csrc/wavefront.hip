@@ -1267,7 +1267,8 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
     __shared__ int32_t s_stack[kLdsStack * kBlock];
     const uint32_t count = min(w.cnt->scount, w.cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->shadow += count;
-    const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
+    // a scene whose shadow rays use the sun grid needs no BVH prefix
+    const int n_lds = lds_job >= 0 && !jobs[lds_job].sc.g_use ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
     Stack st = make_stack(s_stack, w.gstack);
     WaveFeed feed{0, 0, false, 0};
     Ray<R> ry;
@@ -1539,11 +1540,14 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double *acc, int64_t 
                                                      const double *wts, const double *cmf, float *spec,
                                                      double *xyz)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix; p += stride) {
+    // one wave per pixel, lanes over wavelengths: the row is read and the
+    // spectrum written contiguously; the XYZ sums are reduced across the wave
+    const uint32_t lane = lane_id();
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; p < npix; p += nw) {
         double X = 0.0, Y = 0.0, Z = 0.0;
         const double *a = acc + p * nl;
-        for (int l = 0; l < nl; ++l) {
+        for (int l = (int)lane; l < nl; l += 64) {
             const double v = a[l] / spp;
             if (spec) spec[p * nl + l] = (float)v;
             const double wv = wts[l] * v;
@@ -1551,7 +1555,12 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double *acc, int64_t 
             Y += wv * cmf[3 * l + 1];
             Z += wv * cmf[3 * l + 2];
         }
-        if (xyz) {
+        for (int off = 32; off > 0; off >>= 1) {
+            X += __shfl_xor(X, off);
+            Y += __shfl_xor(Y, off);
+            Z += __shfl_xor(Z, off);
+        }
+        if (xyz && lane == 0) {
             xyz[3 * p] = X;
             xyz[3 * p + 1] = Y;
             xyz[3 * p + 2] = Z;
@@ -1801,7 +1810,7 @@ void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows
 void launch_finalize(const double *acc, int64_t npix, int nl, int spp, const double *wts, const double *cmf,
                      float *spec, double *xyz, hipStream_t s)
 {
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (npix + kBlock - 1) / kBlock));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (npix + 3) / 4));   // 4 pixels per block
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, s, acc, npix, nl, spp, wts, cmf, spec, xyz);
 }
 void launch_zero_f64(double *a, int64_t n, hipStream_t s)

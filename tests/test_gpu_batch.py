@@ -121,7 +121,7 @@ def test_autotune_choice_and_cache(gpu, tmp_path):
     base, _, _ = sdm.render(ctx, g, st, precision="fp64")
     cache = tmp_path / "tune.txt"
     r = sdm.autotune(ctx, g, st, precision="fp64", cache_path=cache)
-    assert r["chunk_paths"] in (1 << 20, 1 << 21, 1 << 22) and r["tile"][0] in (8, 16, 32)
+    assert r["chunk_paths"] in (1 << 22, 1 << 23, 1 << 24) and r["tile"][0] in (8, 16, 32)
     assert not r["from_cache"] and r["ms"] > 0
     r2 = sdm.autotune(ctx, g, st, precision="fp64", cache_path=cache)
     assert r2["from_cache"] and r2["chunk_paths"] == r["chunk_paths"] and r2["tile"] == r["tile"]

@@ -666,8 +666,10 @@ __device__ __forceinline__ void block_reserve(const bool (&want)[Q], uint32_t *c
     __syncthreads();   // s_cnt and s_base are reused by the next call
 }
 
+// FP32: eight waves per SIMD (64 VGPRs, no spills) hide more of the pass's
+// memory latency; the FP64 instantiation keeps its registers
 template <class R, bool kOne>
-__global__ void __launch_bounds__(kBlock) k_shade(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1))) k_shade(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
@@ -1377,8 +1379,9 @@ __device__ __forceinline__ void pane_geometry(const JobDev *jb, const Work<R> &w
     sig = R(gld(jb->sc.mat_bub + 4 * m));
 }
 
+// FP32: six waves per SIMD (measured best; eight spill too much)
 template <class R, bool kOne>
-__global__ void __launch_bounds__(kBlock) k_shadow_accum(const JobDev *__restrict__ jobs,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 1))) k_shadow_accum(const JobDev *__restrict__ jobs,
                                                          const BandDev *__restrict__ bands, Work<R> w)
 {
     __shared__ uint32_t s_buf[kBlock / 64][128];

@@ -167,10 +167,14 @@ template <class R>
 __device__ __forceinline__ void slab_pol(R r, R tau, R &Rr, R &Tt)
 {
     if (r >= R(1)) { Rr = R(1); Tt = R(0); return; }
+    // R = r + (1-r)^2 r tau^2 / (1 - r^2 tau^2), T = (1-r)^2 tau / (1 - r^2 tau^2),
+    // with one division for both
     const R q = R(1) - r;
-    const R den = R(1) - r * r * tau * tau;
-    Rr = r + q * q * r * tau * tau / den;
-    Tt = q * q * tau / den;
+    const R rt = r * tau;
+    const R inv = R(1) / (R(1) - rt * rt);
+    const R qqt = q * q * tau;
+    Rr = r + qqt * rt * inv;
+    Tt = qqt * inv;
 }
 
 // Slab reflectance/transmittance: Fresnel per polarisation at both faces,
@@ -188,17 +192,21 @@ __device__ __forceinline__ void slab_RT(R c, R lambda_nm, R d_mm, R n, R k, R ti
     if (sizeof(R) == 4 && k < R(2.5e-4)) {
         // FP32: the complex index changes the reflectances by O(k^2), at most
         // the unit roundoff here, so the real-index form (on the Snell cosine
-        // the path length uses anyway) gives the same values
+        // the path length uses anyway) gives the same values; both ratios
+        // (c - n ct) / (c + n ct) and (n c - ct) / (n c + ct) share one division
         const R nc = n * c, nct = n * ct;
-        const R rs = (c - nct) / (c + nct), rp = (nc - ct) / (nc + ct);
+        const R a = c + nct, b = nc + ct;
+        const R inv = R(1) / (a * b);
+        const R rs = (c - nct) * b * inv, rp = (nc - ct) * a * inv;
         Rs = rs * rs;
         Rp = rp * rp;
     } else {
         fresnel_sp(c, n, k, Rs, Rp);
     }
-    const R alpha = R(12.566370614359172) * k / (lambda_nm * R(1e-6)) + tint;
-    const R ad = alpha * d_mm;
-    const R tau = (ad == R(0)) ? R(1) : (ct > R(0) ? exp(-ad / ct) : R(0));
+    // alpha d / ct with alpha = 4 pi k / lambda + tint (lambda in mm):
+    // (4 pi 1e6 k + tint lambda_nm) d / (lambda_nm ct), one division
+    const R num = (R(12566370.614359172) * k + tint * lambda_nm) * d_mm;
+    const R tau = (num == R(0)) ? R(1) : (ct > R(0) ? exp(-num / (lambda_nm * ct)) : R(0));
     R R1, T1, R2, T2;
     slab_pol(Rs, tau, R1, T1);
     slab_pol(Rp, tau, R2, T2);

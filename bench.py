@@ -46,7 +46,14 @@ def kernel_models(stats, nb, npix, nl, sun_grid=False):
       shade         per closest segment 56 B read (ray 36, hit 16, factor 4)
                     and 44 B written for the continuing path, 28 B per shadow
                     record; 8 nb B per spectral path (read + write), 4 nb B
-                    per spectral record; forks 44 + 4 nb B
+                    per spectral record
+      shade_glass   per glass vertex 60 B read (queue entry 4, ray 36, hit
+                    16, factor 4), 44 + 4 nb B written (the continuing path
+                    and its factors); 4 nb B read where the factors already
+                    differed on arrival; a fork writes a second path and row,
+                    44 + 4 nb B
+      shade_bubbly  per bubbly vertex 60 B read, 44 + 4 nb B written, 4 nb B
+                    read (factors or the network's reflectance ratios)
       shadow_accum  16 B per record plus 4 nb B per spectral record
       finalize      12 nl + 24 B per pixel
     Traversal (trace, shadow) counts 96 flop per wide node visited and 50 per
@@ -55,20 +62,22 @@ def kernel_models(stats, nb, npix, nl, sun_grid=False):
     wavelength)."""
     Ng, Nc, Ns, F = stats["paths"], stats["closest_segments"], stats["shadow_segments"], stats["forks"]
     Nsp, Nsr = stats.get("spectral_paths", 0), stats.get("spectral_records", 0)
+    gv = stats.get("glass_vertices", {"all": 0, "spectral": 0})
+    Nb = stats.get("bubbly_vertices", 0)
     m = {
         "generate": ("hbm", Ng * 44),
         "trace": ("alu", stats["nodes_visited"]["closest"] * FLOPS_PER_NODE
                   + stats["tris_tested"]["closest"] * FLOPS_PER_TRI),
-        "shade": ("hbm", Nc * (56 + 44) + Ns * 28 + Nsp * 8 * nb + Nsr * 4 * nb + F * (44 + 4 * nb)),
+        "shade": ("hbm", Nc * (56 + 44) + Ns * 28 + Nsp * 8 * nb + Nsr * 4 * nb),
         "shadow": ("alu", stats["nodes_visited"]["shadow"] * (FLOPS_PER_CAND if sun_grid else FLOPS_PER_NODE)
                    + stats["tris_tested"]["shadow"] * FLOPS_PER_TRI),
         "shadow_accum": ("hbm", Ns * 16 + Nsr * 4 * nb),
-        "shade_glass": ("alu", 0),
+        "shade_glass": ("hbm", gv["all"] * (60 + 44 + 4 * nb) + gv["spectral"] * 4 * nb + F * (44 + 4 * nb)),
         "finalize": ("hbm", npix * nl * 12 + npix * 24),
         # network on the matrix cores: 2 x 9216 multiply-adds per (vertex, wavelength) tuple,
         # nb wavelengths plus the reference one per bubbly vertex
         "bubbly_eval": ("mfma", stats.get("bubbly_vertices", 0) * (nb + 1) * 2 * 9216),
-        "shade_bubbly": ("alu", 0),
+        "shade_bubbly": ("hbm", Nb * (60 + 44 + 8 * nb)),
     }
     return m
 

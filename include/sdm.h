@@ -162,6 +162,8 @@ typedef struct {
     uint64_t spectral_paths;    /* closest-hit segments whose wavelengths carry
                                    different weights (per-wavelength factors)  */
     uint64_t spectral_records;  /* shadow records with per-wavelength factors   */
+    uint64_t glass_vertices[2]; /* glass vertices shaded [all, those arriving
+                                   with per-wavelength factors]               */
     double ms_render;          /* wall time of the render on the stream       */
     double kernel_ms[SDM_K_COUNT];     /* summed kernel durations (timing=1)   */
     uint64_t kernel_launches[SDM_K_COUNT];

@@ -405,7 +405,7 @@ int sdm_debug_shadow(sdm_context *ctx, const sdm_scene *sc, int64_t m, const flo
     float *lam = ctx->slab_tmp.as<float>();
     float *tabs = lam + 64;  // [4][nm] : rho, n, k, tint at lambda
     HIPCHK(ctx, hipMemcpyAsync(lam, &lambda_nm, sizeof(float), hipMemcpyHostToDevice, s));
-    launch_resample<float>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lam, 1, tabs, s);
+    launch_resample<float>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lam, 1, 1, tabs, s);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4LL * ctx->num_cu, (m + 255) / 256));
     HIPCHK(ctx, ctx->gstack.ensure((size_t)grid * block_size() * global_stack_levels(sc->stack) * sizeof(int32_t)));
     launch_debug_shadow(sc->dev, (uint32_t)m, o, skip, sc->orig_to_leaf.as<int32_t>(), lambda_nm, tabs + nm,

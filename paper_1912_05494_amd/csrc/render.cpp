@@ -290,18 +290,23 @@ int run_graph(sdm_context *ctx, const ChunkArgs<R> &a, uint64_t n_chunks, hipStr
     return SDM_OK;
 }
 
-// Per-job device tables: [R: rho, n, k, tint (n_mat x nl each), E, Lsky,
-// lambda][lambda float][trapezoid weights double][observer double].
+// Per-job device tables: [R: rho, n, k, tint (n_mat rows each), E, Lsky,
+// lambda; rows of ms = nl rounded up to 4 values, zero padded, so a row
+// position that is a multiple of 4 is 16-byte aligned][lambda float]
+// [trapezoid weights double][observer double].
 struct TableLayout {
     size_t off, off_lamf, off_w, off_c, end;
 };
 
+inline int table_stride(int nl) { return (nl + 3) & ~3; }
+
 TableLayout table_layout(size_t base, int nm, int nl, size_t rsize)
 {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t ms = (size_t)table_stride(nl);
     TableLayout t;
     t.off = up(base);
-    t.off_lamf = t.off + up((4 * (size_t)nm * nl + 3 * (size_t)nl) * rsize);
+    t.off_lamf = t.off + up((4 * (size_t)nm + 3) * ms * rsize);
     t.off_w = t.off_lamf + up(nl * sizeof(float));
     t.off_c = t.off_w + up(nl * sizeof(double));
     t.end = t.off_c + 3 * nl * sizeof(double);
@@ -372,12 +377,13 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         HIPCHK(ctx, hipMemcpyAsync(cmf_d, cmf.data(), 3 * nl * sizeof(double), hipMemcpyHostToDevice, s));
         // the host vectors must outlive the asynchronous copies
         HIPCHK(ctx, hipStreamSynchronize(s));
-        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lamf, nl, tR, s);
-        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sun.as<float>(), 1, lamf, nl,
-                           tR + 4 * (size_t)nm * nl, s);
-        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sky.as<float>(), 1, lamf, nl,
-                           tR + 4 * (size_t)nm * nl + nl, s);
-        launch_resample<R>(lamf, nl, lamf, 1, lamf, nl, tR + 4 * (size_t)nm * nl + 2 * nl, s);
+        const size_t ms = (size_t)table_stride(nl);
+        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_mat.as<float>(), 4 * nm, lamf, nl, (int)ms, tR, s);
+        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sun.as<float>(), 1, lamf, nl, (int)ms,
+                           tR + 4 * nm * ms, s);
+        launch_resample<R>(sc->tab_x.as<float>(), sc->n_tab, sc->tab_sky.as<float>(), 1, lamf, nl, (int)ms,
+                           tR + (4 * nm + 1) * ms, s);
+        launch_resample<R>(lamf, nl, lamf, 1, lamf, nl, (int)ms, tR + (4 * nm + 2) * ms, s);
         JobDev &jb = jd[j];
         jb = JobDev{};
         jb.sc = sc->dev;
@@ -388,13 +394,14 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         jb.seed = p->seed;
         jb.job_word = p->job_id;
         jb.acc_off = (uint64_t)acc_off[j];
+        jb.ms = (int32_t)ms;
         jb.rho = tR;
-        jb.n = tR + (size_t)nm * nl;
-        jb.k = tR + 2 * (size_t)nm * nl;
-        jb.tint = tR + 3 * (size_t)nm * nl;
-        jb.E = tR + 4 * (size_t)nm * nl;
-        jb.Lsky = tR + 4 * (size_t)nm * nl + nl;
-        jb.lam = tR + 4 * (size_t)nm * nl + 2 * nl;
+        jb.n = tR + nm * ms;
+        jb.k = tR + 2 * nm * ms;
+        jb.tint = tR + 3 * nm * ms;
+        jb.E = tR + 4 * nm * ms;
+        jb.Lsky = tR + (4 * nm + 1) * ms;
+        jb.lam = tR + (4 * nm + 2) * ms;
         jb.beta_thr = p->beta_threshold;
         jb.btdf_mode = p->btdf_mode;
         jb.err_bound = p->err_bound;
@@ -594,6 +601,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             st.bubbly_vertices = c.bubbly;
             st.spectral_paths = c.spec_paths;
             st.spectral_records = c.spec_records;
+            st.glass_vertices[0] = c.glass[0];
+            st.glass_vertices[1] = c.glass[1];
             st.chunks = n_chunks;
             for (int q = 0; q < 2; ++q) {
                 st.nodes_visited[q] = c.nodes[q];

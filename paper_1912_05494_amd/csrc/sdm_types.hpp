@@ -68,9 +68,9 @@ struct JobDev {
     int32_t projection, W, H, spp, nl, max_depth;
     uint64_t seed;
     uint32_t job_word;
-    uint32_t pad0;
+    int32_t ms;                 // row stride of the wavelength tables: nl rounded up to 4
     uint64_t acc_off;           // offset of this job's accumulator (doubles)
-    const void *rho, *n, *k, *tint, *E, *Lsky, *lam;
+    const void *rho, *n, *k, *tint, *E, *Lsky, *lam;   // rows of ms values, 16-byte aligned
     double beta_thr;
     // bubbly panes
     int32_t btdf_mode;          // kBtdfExact, kBtdfSurrogate or kBtdfFallback
@@ -117,6 +117,7 @@ struct alignas(256) Counters {
     unsigned long long r0;      // first primary path of the current chunk (advanced per chunk)
     unsigned long long closest, shadow, forks, bubbly;
     unsigned long long spec_paths, spec_records;   // kSpectral paths shaded / shadow records made
+    unsigned long long glass[2];   // glass vertices shaded [all, arriving with per-wavelength factors]
     unsigned long long nodes[2], tris[2];   // traversal work [closest, shadow]
 };
 

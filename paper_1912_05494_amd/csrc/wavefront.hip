@@ -56,6 +56,31 @@ __device__ __forceinline__ T gld(const T *p)
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// Wavelengths j .. j+3 of a band's row in a wavelength table (rows of ms
+// values, ms a multiple of 4).  A band that starts at a multiple of 4 reads
+// them with one 16-byte load (two for double); otherwise four loads, each
+// clamped to the band's last wavelength so none leaves the row.
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <class R>
+__device__ __forceinline__ Vec4<R> tab4(const R *row, bool aligned, int j, int nb)
+{
+    Vec4<R> r;
+    if (aligned) {
+        if constexpr (sizeof(R) == 4) {
+            const f4v v = *(const __attribute__((address_space(1))) f4v *)(row + j);
+            r.v[0] = v.x; r.v[1] = v.y; r.v[2] = v.z; r.v[3] = v.w;
+        } else {
+            const __attribute__((address_space(1))) d2v *p = (const __attribute__((address_space(1))) d2v *)(row + j);
+            const d2v a = p[0], b = p[1];
+            r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r.v[q] = gld(row + min(j + q, nb - 1));
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Traversal stack: kLdsStack levels per lane in LDS, deeper levels in a
 // per-thread global region.  Entries are inner-node indices (>= 0) or leaves
@@ -711,7 +736,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                 if (mt == 0 || mt == 3) {
                     kind = 1;
                     gray = mt == 3;
-                    if (gray) rho_g = gld((const R *)jb->rho + (size_t)mat * jb->nl + bd.l0);
+                    if (gray) rho_g = gld((const R *)jb->rho + (size_t)mat * jb->ms + bd.l0);
                     const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
                     x = o + w.ht[i] * d;
                     const V3<R> ng = tri_normal<R>(tr);
@@ -772,7 +797,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             if (out_spec) {
                 // rows are 16-byte aligned and padded to a multiple of 4: move
                 // four wavelengths per load and store (the padding is unused)
-                const R *rho = (const R *)jb->rho + (size_t)mat * jb->nl + bd.l0;
+                const R *rho = (const R *)jb->rho + (size_t)mat * jb->ms + bd.l0;
+                const bool al = (bd.l0 & 3) == 0;
                 const R *__restrict__ bin = Pi.beta + aosoa(i, 0, nbm);
                 R *__restrict__ bout = Po.beta + aosoa(om, 0, nbm);
                 R *__restrict__ cout = w.contrib + aosoa(sslot, 0, nbm);
@@ -780,9 +806,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     Vec4<R> f;
                     if (spec) f = row_load4(bin + j);
                     else f.v[0] = f.v[1] = f.v[2] = f.v[3] = R(1);
-                    if (!gray)
+                    if (!gray) {
+                        const Vec4<R> r4 = tab4(rho, al, j, bd.nb);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) f.v[q] *= gld(rho + min(j + q, bd.nb - 1));
+                        for (int q = 0; q < 4; ++q) f.v[q] *= r4.v[q];
+                    }
                     if (want_shadow) row_store4(cout + j, f);
                     if (keep) {
 #pragma unroll
@@ -888,10 +916,11 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     __shared__ uint32_t s_cnt[(kBlock / 64) * 2], s_base[2];
-    uint32_t n_fork = 0;
+    uint32_t n_fork = 0, n_in = 0, n_spec = 0;
     // block-strided: the block reserves its output slots together
     for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
         const bool active = base + threadIdx.x < count;
+        n_in += active ? 1u : 0u;
         uint32_t i = 0, aux = 0, pix = 0, smp = 0;
         int32_t tri = -1;
         V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x;
@@ -905,6 +934,7 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict
             pix = Pi.pix[i];
             smp = Pi.smp[i];
             const bool spec = (smp & kSpectral) != 0u;
+            n_spec += spec ? 1u : 0u;
             g = Pi.g[i];
             const int depth = (int)(aux & 0xffu);
             const JobDev *jb = &jobs[kOne ? 0u : aux >> kAuxJobShift];
@@ -921,33 +951,46 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict
             const R thick = pane_thickness<R>(jb->sc, tri, w.hu[i], w.hv[i]);
             dnew = d;
             drefl = d - (R(2) * dot(d, ng)) * ng;
-            const int nl = jb->nl;
-            const R *nn = (const R *)jb->n + (size_t)mat * nl + bd.l0;
-            const R *kk = (const R *)jb->k + (size_t)mat * nl + bd.l0;
-            const R *tt = (const R *)jb->tint + (size_t)mat * nl + bd.l0;
+            const size_t mo = (size_t)mat * jb->ms + bd.l0;
+            const R *nn = (const R *)jb->n + mo;
+            const R *kk = (const R *)jb->k + mo;
+            const R *tt = (const R *)jb->tint + mo;
             const R *lam = (const R *)jb->lam + bd.l0;
+            const bool al = (bd.l0 & 3) == 0;
             const R thr = R(jb->beta_thr);
             bool anyR = false, anyT = false;
             // the new factors stay in the input slot until the output slots are
-            // known (a path without per-wavelength factors gets them here)
-            for (int j = 0; j < bd.nb; ++j) {
-                const size_t q = aosoa(i, j, nbm);
-                const R b = spec ? Pi.beta[q] : R(1);
-                if (b == R(0)) continue;
-                R Rr, Tt;
-                slab_RT<R>(cos_i, gld(lam + j), thick, gld(nn + j), gld(kk + j), gld(tt + j), Rr, Tt);
-                const R rt = Rr + Tt;
-                R bn = b * rt;
-                if (g * bn < thr) bn = R(0);
-                Pi.beta[q] = bn;
-                if (bn == R(0)) continue;
-                if (rt > R(0) && u0 < Rr / rt) {
-                    anyR = true;
-                    const uint32_t bit = 1u << (j & 31);
-                    if (j < 32) m0 |= bit; else if (j < 64) m1 |= bit; else if (j < 96) m2 |= bit; else m3 |= bit;
-                } else {
-                    anyT = true;
+            // known (a path without per-wavelength factors gets them here);
+            // four wavelengths per step, the row's padding set to zero
+            R *__restrict__ brow = Pi.beta + aosoa(i, 0, nbm);
+            for (int j = 0; j < bd.nb; j += 4) {
+                Vec4<R> b4;
+                if (spec) b4 = row_load4(brow + j);
+                else b4.v[0] = b4.v[1] = b4.v[2] = b4.v[3] = R(1);
+                const Vec4<R> l4 = tab4(lam, al, j, bd.nb), n4 = tab4(nn, al, j, bd.nb), k4 = tab4(kk, al, j, bd.nb),
+                              t4 = tab4(tt, al, j, bd.nb);
+                Vec4<R> o4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int jq = j + q;
+                    o4.v[q] = R(0);
+                    if (jq >= bd.nb || b4.v[q] == R(0)) continue;
+                    R Rr, Tt;
+                    slab_RT<R>(cos_i, l4.v[q], thick, n4.v[q], k4.v[q], t4.v[q], Rr, Tt);
+                    const R rt = Rr + Tt;
+                    R bn = b4.v[q] * rt;
+                    if (g * bn < thr) bn = R(0);
+                    o4.v[q] = bn;
+                    if (bn == R(0)) continue;
+                    if (rt > R(0) && u0 < Rr / rt) {
+                        anyR = true;
+                        const uint32_t bit = 1u << (jq & 31);
+                        if (jq < 32) m0 |= bit; else if (jq < 64) m1 |= bit; else if (jq < 96) m2 |= bit; else m3 |= bit;
+                    } else {
+                        anyT = true;
+                    }
                 }
+                row_store4(brow + j, o4);
             }
             keep = anyR || anyT;
             fork = anyR && anyT;
@@ -957,8 +1000,14 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict
         emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3, g,
                       s_cnt, s_base);
     }
-    for (int off = 32; off > 0; off >>= 1) n_fork += __shfl_xor(n_fork, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        n_fork += __shfl_xor(n_fork, off);
+        n_in += __shfl_xor(n_in, off);
+        n_spec += __shfl_xor(n_spec, off);
+    }
     if (lane == 0 && n_fork) atomicAdd(&w.cnt->forks, (unsigned long long)n_fork);
+    if (lane == 0 && n_in) atomicAdd(&w.cnt->glass[0], (unsigned long long)n_in);
+    if (lane == 0 && n_spec) atomicAdd(&w.cnt->glass[1], (unsigned long long)n_spec);
 }
 
 // ---------------------------------------------------------------------------
@@ -1177,10 +1226,10 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restric
             x = V3<R>{Pi.ox[i], Pi.oy[i], Pi.oz[i]} + w.ht[i] * d;
             dnew = d;
             drefl = d - (R(2) * dot(d, ng)) * ng;
-            const int nl = jb->nl;
-            const R *nn = (const R *)jb->n + (size_t)v.mat * nl + bd.l0;
-            const R *kk = (const R *)jb->k + (size_t)v.mat * nl + bd.l0;
-            const R *tt = (const R *)jb->tint + (size_t)v.mat * nl + bd.l0;
+            const size_t mo = (size_t)v.mat * jb->ms + bd.l0;
+            const R *nn = (const R *)jb->n + mo;
+            const R *kk = (const R *)jb->k + mo;
+            const R *tt = (const R *)jb->tint + mo;
             const R *lam = (const R *)jb->lam + bd.l0;
             const R thr = R(jb->beta_thr);
             bool anyR = false, anyT = false;
@@ -1492,7 +1541,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             const R *spectrum = (const R *)((a.flags & 2) ? jb->Lsky : jb->E);
             const R *lam = (const R *)jb->lam;
             const R *tn = (const R *)jb->n, *tk = (const R *)jb->k, *tt = (const R *)jb->tint;
-            const int nl = jb->nl;
+            const int ms = jb->ms;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int j = (int)lane + 64 * h;
@@ -1505,7 +1554,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
 #pragma unroll
                 for (int q = 0; q < kAccPanes; ++q) {
                     if (q < a.ng) {
-                        const size_t mo = (size_t)a.m[q] * nl + l;
+                        const size_t mo = (size_t)a.m[q] * ms + l;
                         R Rr, Tt;
                         slab_RT<R>(a.c[q], lamv, a.d[q], gld(tn + mo), gld(tk + mo), gld(tt + mo) + a.sig[q], Rr, Tt);
                         T *= Tt;
@@ -1515,7 +1564,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     R c, d, sig;
                     int m;
                     pane_geometry(jb, w, a.rec, q, c, d, m, sig);
-                    const size_t mo = (size_t)m * nl + l;
+                    const size_t mo = (size_t)m * ms + l;
                     R Rr, Tt;
                     slab_RT<R>(c, lamv, d, gld(tn + mo), gld(tk + mo), gld(tt + mo) + sig, Rr, Tt);
                     T *= Tt;
@@ -1593,19 +1642,25 @@ __global__ void k_zero_counters(Counters *c)
         c->gcount = c->bcount = 0;
         c->closest = c->shadow = c->forks = c->bubbly = 0;
         c->spec_paths = c->spec_records = 0;
+        c->glass[0] = c->glass[1] = 0;
         c->nodes[0] = c->nodes[1] = c->tris[0] = c->tris[1] = 0;
     }
 }
 
 // Linear interpolation of a table (tab_x[n_tab], tab_y[n_tab]) at xs[nl],
-// held constant beyond the ends; rows of `rows` tables.
+// held constant beyond the ends; `rows` tables, written as rows of `stride`
+// (>= nl) values whose padding is set to zero.
 template <class R>
 __global__ void k_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl,
-                           R *out)
+                           int stride, R *out)
 {
-    const int total = rows * nl;
+    const int total = rows * stride;
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
-        const int r = id / nl, l = id % nl;
+        const int r = id / stride, l = id % stride;
+        if (l >= nl) {
+            out[id] = R(0);
+            continue;
+        }
         const float *y = tab_y + (size_t)r * n_tab;
         const double x = xs[l];
         double v;
@@ -1802,12 +1857,13 @@ void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R>
 }
 
 template <class R>
-void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
-                     hipStream_t s)
+void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl,
+                     int stride, R *out, hipStream_t s)
 {
-    const int total = rows * nl;
+    const int total = rows * stride;
     const int grid = std::max(1, std::min(1024, (total + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(k_resample<R>, dim3(grid), dim3(kBlock), 0, s, tab_x, n_tab, tab_y, rows, xs, nl, out);
+    hipLaunchKernelGGL(k_resample<R>, dim3(grid), dim3(kBlock), 0, s, tab_x, n_tab, tab_y, rows, xs, nl, stride,
+                       out);
 }
 
 void launch_finalize(const double *acc, int64_t npix, int nl, int spp, const double *wts, const double *cmf,
@@ -1889,7 +1945,7 @@ int occupancy(int kernel_class, int lds_bytes)
     template void launch_shade_bubbly<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
     template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t); \
     template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, bool, int, hipStream_t); \
-    template void launch_resample<R>(const float *, int, const float *, int, const float *, int, R *,              \
+    template void launch_resample<R>(const float *, int, const float *, int, const float *, int, int, R *,         \
                                      hipStream_t);                                                                 \
     template int occupancy<R>(int, int);
 

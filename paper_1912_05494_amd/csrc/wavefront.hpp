@@ -32,8 +32,8 @@ template <class R>
 void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int grid,
                          hipStream_t s);
 template <class R>
-void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl, R *out,
-                     hipStream_t s);
+void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl,
+                     int stride, R *out, hipStream_t s);
 // Resident blocks of 256 threads per CU of a render kernel (SDM_K_* class)
 // with lds_bytes of dynamic LDS.
 template <class R>

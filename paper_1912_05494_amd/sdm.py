@@ -63,7 +63,7 @@ class Stats(C.Structure):
                 ("forks", C.c_uint64), ("chunks", C.c_uint64), ("nodes_visited", C.c_uint64 * 2),
                 ("tris_tested", C.c_uint64 * 2), ("bubbly_vertices", C.c_uint64),
                 ("spectral_paths", C.c_uint64), ("spectral_records", C.c_uint64),
-                ("ms_render", C.c_double), ("kernel_ms", C.c_double * 9),
+                ("glass_vertices", C.c_uint64 * 2), ("ms_render", C.c_double), ("kernel_ms", C.c_double * 9),
                 ("kernel_launches", C.c_uint64 * 9)]
 
     def as_dict(self):
@@ -74,6 +74,7 @@ class Stats(C.Structure):
         d["bubbly_vertices"] = int(self.bubbly_vertices)
         d["spectral_paths"] = int(self.spectral_paths)
         d["spectral_records"] = int(self.spectral_records)
+        d["glass_vertices"] = {"all": int(self.glass_vertices[0]), "spectral": int(self.glass_vertices[1])}
         d["kernel_ms"] = {k: self.kernel_ms[i] for i, k in enumerate(KERNELS)}
         d["kernel_launches"] = {k: int(self.kernel_launches[i]) for i, k in enumerate(KERNELS)}
         return d

@@ -85,7 +85,7 @@ int main(void) {
   P(sdm_render_params, chunk_paths); P(sdm_render_params, timing);
   P(sdm_render_params, btdf_mode); P(sdm_render_params, err_dims); P(sdm_render_params, mlp);
   P(sdm_render_params, err_table); P(sdm_render_params, err_bound);
-  P(sdm_stats, bubbly_vertices); P(sdm_stats, kernel_ms); P(sdm_stats, spectral_records);
+  P(sdm_stats, bubbly_vertices); P(sdm_stats, kernel_ms); P(sdm_stats, spectral_records); P(sdm_stats, glass_vertices);
   P(sdm_render_params, graph);
   printf("sdm_job %zu\n", sizeof(sdm_job));
   printf("sdm_tune_result %zu\n", sizeof(sdm_tune_result));

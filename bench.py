@@ -113,7 +113,8 @@ def measured_traffic(kernel):
 
 def profile_once():
     """One render of the workload, then a 256 MiB device-to-device copy whose
-    FETCH_SIZE / WRITE_SIZE calibrate the traffic counters."""
+    FETCH_SIZE / WRITE_SIZE calibrate the traffic counters, then two tiny
+    kernels (a fill and an add on 1 KiB)."""
     import torch
     from paper_1912_05494_amd import sdm, synth
     ctx = sdm.Context(0)
@@ -123,6 +124,12 @@ def profile_once():
     a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
+    torch.cuda.synchronize()
+    # a tiny kernel after the copy: its counters show whether write-backs of
+    # the copy's dirty cache lines land in the next dispatch's window
+    c = torch.zeros(256, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    c.add_(1.0)
     torch.cuda.synchronize()
     print(json.dumps({"closest": stats["closest_segments"], "shadow": stats["shadow_segments"],
                       "copy_bytes": a.numel() * 4}), flush=True)
@@ -465,7 +472,8 @@ def main():
                   "sun_grid_cells": info["grid_cells"], "sun_grid_candidates": info["grid_candidates"]},
         "segments_per_s": (s["closest_segments"] + s["shadow_segments"]) * args.steps / dt,
         "distinct_rays_per_step": {"closest": s["closest_segments"], "shadow": s["shadow_segments"],
-                                   "forks": s["forks"]},
+                                   "forks": s["forks"], "glass_vertices": s["glass_vertices"]["all"],
+                                   "spectral_paths": s["spectral_paths"], "spectral_records": s["spectral_records"]},
         "traversal_per_ray": {k: {"nodes": s["nodes_visited"][k] / max(1, s[seg]),
                                   "tris": s["tris_tested"][k] / max(1, s[seg])}
                               for k, seg in (("closest", "closest_segments"), ("shadow", "shadow_segments"))},

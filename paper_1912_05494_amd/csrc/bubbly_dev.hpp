@@ -105,7 +105,7 @@ __device__ WalkOut<R> bubbly_walk(const WalkStream &s, R cos_i, R d, R sigma, R 
         V3<R> t1, t2;
         onb(dir, t1, t2);
         R sphi, cphi;
-        if constexpr (sizeof(R) == 4) sincosf(R(6.283185307179586) * u[3], &sphi, &cphi);
+        if constexpr (sizeof(R) == 4) sincospif(R(2) * u[3], &sphi, &cphi);
         else sincos(R(6.283185307179586) * u[3], &sphi, &cphi);
         const V3<R> ep = cphi * t1 + sphi * t2;
         uint32_t sub = 1;
@@ -165,7 +165,7 @@ __device__ __forceinline__ V3<R> lobe_dir(V3<R> d, R w, R u1, R u2)
     onb(d, t1, t2);
     const R g = sqrt(R(-2) * log1p(-u1));
     R s, c;
-    if constexpr (sizeof(R) == 4) sincosf(R(6.283185307179586) * u2, &s, &c);
+    if constexpr (sizeof(R) == 4) sincospif(R(2) * u2, &s, &c);
     else sincos(R(6.283185307179586) * u2, &s, &c);
     return normalize(d + w * ((g * c) * t1 + (g * s) * t2));
 }

@@ -88,10 +88,12 @@ __device__ __forceinline__ V3<R> cosine_dir(V3<R> n, R u1, R u2)
 {
     V3<R> t1, t2;
     onb(n, t1, t2);
-    const R r = sqrt(u1), phi = R(6.283185307179586) * u2, lz = sqrt(R(1) - u1);
+    const R r = sqrt(u1), lz = sqrt(R(1) - u1);
     R s, c;
-    if constexpr (sizeof(R) == 4) sincosf(phi, &s, &c);
-    else sincos(phi, &s, &c);
+    // FP32: the angle 2 pi u2 as sincospi(2 u2), which needs no reduction of
+    // large arguments (the general sincos carries one, and its registers)
+    if constexpr (sizeof(R) == 4) sincospif(R(2) * u2, &s, &c);
+    else sincos(R(6.283185307179586) * u2, &s, &c);
     return (r * c) * t1 + (r * s) * t2 + lz * n;
 }
 

@@ -152,13 +152,28 @@ struct Pool {
 
 constexpr int kMaxGlass = 8;    // panes a shadow ray may cross (more: SDM_E_UNSUPPORTED)
 
+// A clear-glass vertex as the shade pass queues it for the glass pass: the
+// state the glass pass needs, gathered into one record (64 bytes in FP32)
+// so that it is read with a few wide loads instead of a word from each pool
+// array at a scattered slot.
+template <class R>
+struct alignas(16) GlassRec {
+    R x[3];                     // hit point
+    R d[3];                     // incoming direction
+    R g, u, v;                  // scalar factor; barycentric coordinates of the hit
+    int32_t tri;                // leaf-order index of the pane triangle
+    uint32_t aux, pix, smp;     // as in the pool
+    uint32_t slot;              // pool slot (its per-wavelength factors)
+};
+
 template <class R>
 struct Work {
     Pool<R> p[2];
     R *ht, *hu, *hv;            // closest hit per slot of the current pool
     int32_t *htri;
-    uint32_t *gidx;             // slots of the current pool at a glass vertex (clear glass from
-                                // the front, bubbly glass from the back: gidx[cap - 1 - b])
+    uint32_t *gidx;             // slots of the current pool at a bubbly-glass vertex, from the
+                                // back: gidx[cap - 1 - b]
+    GlassRec<R> *grec;          // clear-glass vertices [0, gcount)
     R *bratio;                  // AoSoA [slot][j]: surrogate R / (R + T) at bubbly vertices
     R *bw;                      // [slot]: surrogate lobe width at kLambdaRef
     R *sx, *sy, *sz;            // shadow records [0, scount); sky records of escaped paths at

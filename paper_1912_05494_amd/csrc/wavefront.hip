@@ -56,6 +56,31 @@ __device__ __forceinline__ T gld(const T *p)
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// Records moved as 16-byte words with global loads and stores.
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ T rec_load(const T *p)
+{
+    static_assert(sizeof(T) % 16 == 0, "record size");
+    const __attribute__((address_space(1))) u4v *q = (const __attribute__((address_space(1))) u4v *)p;
+    u4v t[sizeof(T) / 16];
+#pragma unroll
+    for (size_t k = 0; k < sizeof(T) / 16; ++k) t[k] = q[k];
+    T r;
+    __builtin_memcpy(&r, t, sizeof(T));
+    return r;
+}
+template <class T>
+__device__ __forceinline__ void rec_store(T *p, const T &r)
+{
+    static_assert(sizeof(T) % 16 == 0, "record size");
+    __attribute__((address_space(1))) u4v *q = (__attribute__((address_space(1))) u4v *)p;
+    u4v t[sizeof(T) / 16];
+    __builtin_memcpy(t, &r, sizeof(T));
+#pragma unroll
+    for (size_t k = 0; k < sizeof(T) / 16; ++k) q[k] = t[k];
+}
+
 // Wavelengths j .. j+3 of a band's row in a wavelength table (rows of ms
 // values, ms a multiple of 4).  A band that starts at a multiple of 4 reads
 // them with one 16-byte load (two for double); otherwise four loads, each
@@ -653,6 +678,55 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *__restrict__ job
 }
 
 // ---------------------------------------------------------------------------
+// Per-wavelength rows handled by the whole wave.  Each lane whose flag is set
+// owns a task on rows of nbm values (nbm a multiple of 4); the wave works
+// through the tasks ng at a time, gl = nbm / 4 lanes per task and four
+// wavelengths per lane, one 16-byte access each.  A row's cache lines are
+// then read or written by one instruction, where a lane walking its own row
+// 16 bytes per step leaves them partly written while other rows evict them.
+// Called by every lane of the wave; s_map is the wave's 64-entry LDS table.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRowSrc = 1u, kRowRho = 2u, kRowRec = 4u, kRowKeep = 8u, kRowAl = 16u, kRowFork = 32u;
+constexpr int kRowNbShift = 8;   // band size in bits 8..15 of a task's flags
+struct RowTasks {
+    int n;              // tasks in the wave
+    int gl, ng;         // lanes per task, tasks per step
+    int sub;            // this lane's task within a step (idle when >= ng)
+    int j;              // first of this lane's four wavelengths
+    uint32_t rank;      // this lane's own task number (lanes with a task)
+    __device__ __forceinline__ bool busy(int base) const { return sub < ng && base + sub < n; }
+    // the lane owning the task this lane works on at step `base` (itself when idle)
+    __device__ __forceinline__ int src(int base, const uint32_t *s_map) const
+    {
+        return busy(base) ? (int)s_map[min(base + sub, 63)] : (int)lane_id();
+    }
+    // whether this lane's own task is in step `base`, and its lanes there
+    __device__ __forceinline__ bool mine(bool want, int base, uint64_t &lanes) const
+    {
+        const uint32_t s = rank - (uint32_t)base;
+        if (!want || s >= (uint32_t)ng) return false;
+        lanes = (gl == 64 ? ~0ull : ((1ull << gl) - 1ull)) << (s * gl);
+        return true;
+    }
+};
+
+__device__ __forceinline__ RowTasks row_tasks(bool want, int nbm, uint32_t *s_map)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t m = __ballot(want);
+    RowTasks t;
+    t.rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (want) s_map[t.rank] = lane;
+    __builtin_amdgcn_wave_barrier();
+    t.n = __popcll(m);
+    t.gl = nbm >> 2;
+    t.ng = 64 / t.gl;
+    t.sub = (int)lane / t.gl;
+    t.j = ((int)lane - t.sub * t.gl) * 4;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
 // Shade: misses add the sky, Lambert vertices emit a shadow record (eq. (3))
 // and bounce; survivors are compacted with their weights into the other
 // pool.  Glass vertices are queued for k_shade_glass so that the costly
@@ -702,6 +776,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     const uint32_t lane = lane_id();
     const R inv_pi = R(0.31830988618379067);
     __shared__ uint32_t s_cnt[(kBlock / 64) * 5], s_base[5];
+    __shared__ uint32_t s_map_all[kBlock];
+    uint32_t *const s_map = s_map_all + (threadIdx.x & ~63u);
     uint32_t n_spec = 0, n_srec = 0;
     // block-strided so that the block reserves its output slots together
     for (uint32_t bbase = blockIdx.x * kBlock; bbase < count; bbase += gridDim.x * kBlock) {
@@ -752,10 +828,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                 } else if (!last) {
                     // no light sum at glass; a glass vertex at the depth limit ends the path
                     kind = mt == 2 ? 3 : 2;
+                    if (kind == 2) {   // gathered for the glass pass's record (cs and rho_g,
+                                       // unused at glass, carry the barycentrics)
+                        const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]};
+                        dnew = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
+                        x = o + w.ht[i] * dnew;
+                        cs = w.hu[i];
+                        rho_g = w.hv[i];
+                    }
                 }
             }
         }
-        n_spec += (active && spec) ? 1u : 0u;
+        n_spec += (uint32_t)__popcll(__ballot(active && spec));   // wave-uniform counts
         // glass and bubbly queues, shadow and sky records, pool slots: one
         // atomic per block and buffer
         const bool want[5] = {kind == 2, kind == 3, want_shadow, keep, kind == 0};
@@ -763,26 +847,35 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                                   &w.cnt->kcount};
         uint32_t slot[5];
         block_reserve<5>(want, ctr, slot, s_cnt, s_base);
-        if (kind == 2) w.gidx[slot[0]] = i;
+        if (kind == 2) {
+            GlassRec<R> r;
+            r.x[0] = x.x; r.x[1] = x.y; r.x[2] = x.z;
+            r.d[0] = dnew.x; r.d[1] = dnew.y; r.d[2] = dnew.z;
+            r.g = g; r.u = cs; r.v = rho_g;
+            r.tri = tri; r.aux = aux; r.pix = pix; r.smp = smp; r.slot = i;
+            rec_store(w.grec + slot[0], r);
+        }
         if (kind == 3) w.gidx[w.cap - 1u - slot[1]] = i;
         uint32_t sslot = slot[2];
         if (want_shadow && sslot >= w.cap) { w.cnt->overflow |= 1u; want_shadow = false; }
         uint32_t om = slot[3];
         if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
+        // row tasks: flags, record row, albedo row offset (see below)
+        uint32_t rflags = 0, rrec = 0, rrho = 0;
+        R gn = g;
         if (kind == 1) {
             // Lambert: the shadow record carries g rho cos / pi (rho when gray), the
             // continuing path g rho; a spectral albedo or spectral weights keep
             // per-wavelength factors
             const bool out_spec = spec || !gray;
             const R thr = R(jb->beta_thr);
-            const R gn = gray ? g * rho_g : g;
+            if (gray) gn = g * rho_g;
             if (want_shadow) {
                 w.sx[sslot] = x.x; w.sy[sslot] = x.y; w.sz[sslot] = x.z;
                 w.sskip[sslot] = tri;
                 w.spix[sslot] = pix | (out_spec ? kSpectral : 0u);
                 w.saux[sslot] = aux;
                 w.scs[sslot] = gn * inv_pi * cs;
-                n_srec += out_spec ? 1u : 0u;
             }
             if (keep) {
                 Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
@@ -795,29 +888,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                 Po.g[om] = (!out_spec && gn < thr) ? R(0) : gn;
             }
             if (out_spec) {
-                // rows are 16-byte aligned and padded to a multiple of 4: move
-                // four wavelengths per load and store (the padding is unused)
-                const R *rho = (const R *)jb->rho + (size_t)mat * jb->ms + bd.l0;
-                const bool al = (bd.l0 & 3) == 0;
-                const R *__restrict__ bin = Pi.beta + aosoa(i, 0, nbm);
-                R *__restrict__ bout = Po.beta + aosoa(om, 0, nbm);
-                R *__restrict__ cout = w.contrib + aosoa(sslot, 0, nbm);
-                for (int j = 0; j < bd.nb; j += 4) {
-                    Vec4<R> f;
-                    if (spec) f = row_load4(bin + j);
-                    else f.v[0] = f.v[1] = f.v[2] = f.v[3] = R(1);
-                    if (!gray) {
-                        const Vec4<R> r4 = tab4(rho, al, j, bd.nb);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) f.v[q] *= r4.v[q];
-                    }
-                    if (want_shadow) row_store4(cout + j, f);
-                    if (keep) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) f.v[q] = (gn * f.v[q] < thr) ? R(0) : f.v[q];
-                        row_store4(bout + j, f);
-                    }
-                }
+                rflags = (spec ? kRowSrc : 0u) | (gray ? 0u : kRowRho) | (want_shadow ? kRowRec : 0u) |
+                         (keep ? kRowKeep : 0u);
+                rrec = sslot;
+                rrho = (uint32_t)(mat * jb->ms + bd.l0);
             }
         }
         // escaping paths: a sky record each (summed per pixel by the
@@ -830,16 +904,44 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             w.saux[r] = aux;
             w.scs[r] = g;
             if (spec) {
-                for (int j = 0; j < bd.nb; j += 4)
-                    row_store4(w.contrib + aosoa(r, j, nbm), row_load4(Pi.beta + aosoa(i, j, nbm)));
-                ++n_srec;
+                rflags = kRowSrc | kRowRec;
+                rrec = r;
             }
         }
-    }
-    // per-wave counts of spectral paths and records
-    for (int off = 32; off > 0; off >>= 1) {
-        n_spec += __shfl_xor(n_spec, off);
-        n_srec += __shfl_xor(n_srec, off);
+        // Per-wavelength rows (16-byte aligned, padded to a multiple of 4; the
+        // padding is unused): the factors (or 1), times the albedo row for a
+        // spectral albedo, go to the record and, thresholded, to the
+        // continuing path.
+        n_srec += (uint32_t)__popcll(__ballot((rflags & kRowRec) != 0u));
+        if (!(rflags & (kRowRec | kRowKeep))) rflags = 0;
+        if (rflags) rflags |= (uint32_t)bd.nb << kRowNbShift | ((bd.l0 & 3) == 0 ? kRowAl : 0u);
+        const RowTasks rt = row_tasks(rflags != 0, nbm, s_map);
+        for (int b0 = 0; b0 < rt.n; b0 += rt.ng) {
+            const int src = rt.src(b0, s_map);
+            const uint32_t f = (uint32_t)__shfl((int)rflags, src);
+            const uint32_t si = (uint32_t)__shfl((int)i, src), rec = (uint32_t)__shfl((int)rrec, src);
+            const uint32_t so = (uint32_t)__shfl((int)om, src), ro = (uint32_t)__shfl((int)rrho, src);
+            const R sg = __shfl(gn, src);
+            const uint32_t sjob = kOne ? 0u : (uint32_t)__shfl((int)(aux >> kAuxJobShift), src);
+            const int nb = (int)(f >> kRowNbShift), j = rt.j;
+            if (!rt.busy(b0) || j >= nb) continue;
+            Vec4<R> v;
+            if (f & kRowSrc) v = row_load4(Pi.beta + aosoa(si, j, nbm));
+            else v.v[0] = v.v[1] = v.v[2] = v.v[3] = R(1);
+            const JobDev *sj = &jobs[sjob];
+            if (f & kRowRho) {
+                const Vec4<R> r4 = tab4((const R *)sj->rho + ro, (f & kRowAl) != 0u, j, nb);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v.v[q] *= r4.v[q];
+            }
+            if (f & kRowRec) row_store4(w.contrib + aosoa(rec, j, nbm), v);
+            if (f & kRowKeep) {
+                const R thr = R(sj->beta_thr);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v.v[q] = (sg * v.v[q] < thr) ? R(0) : v.v[q];
+                row_store4(Po.beta + aosoa(so, j, nbm), v);
+            }
+        }
     }
     if (lane == 0 && (n_spec | n_srec)) {
         atomicAdd(&w.cnt->spec_paths, (unsigned long long)n_spec);
@@ -855,18 +957,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
 // outputs keep the scalar factor g.  Called by every thread of the block
 // (block-uniform loop); one reservation per block.
 template <class R>
-__device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, const Pool<R> &Po, int cur, bool keep,
-                                           bool fork, uint32_t i, V3<R> x, V3<R> dnew, V3<R> drefl, uint32_t pix,
-                                           uint32_t smp, uint32_t aux, int32_t tri, int nb, uint32_t m0, uint32_t m1,
-                                           uint32_t m2, uint32_t m3, R g, uint32_t *s_cnt, uint32_t *s_base)
+__device__ __forceinline__ void emit_paths(const Work<R> &w, const Pool<R> &Po, int cur, bool &keep, bool &fork,
+                                           V3<R> x, V3<R> dnew, V3<R> drefl, uint32_t pix, uint32_t smp, uint32_t aux,
+                                           int32_t tri, R g, uint32_t &om, uint32_t &of, uint32_t *s_cnt,
+                                           uint32_t *s_base)
 {
     smp |= kSpectral;   // the outputs carry per-wavelength factors
-    const int nbm = w.nbmax;
     const bool want[2] = {keep, fork};
     uint32_t *const ctr[2] = {&w.cnt->count[cur ^ 1], &w.cnt->count[cur ^ 1]};
     uint32_t slot[2];
     block_reserve<2>(want, ctr, slot, s_cnt, s_base);
-    const uint32_t om = slot[0], of = slot[1];
+    om = slot[0];
+    of = slot[1];
     if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
     if (fork && of >= w.cap) { w.cnt->overflow |= 1u; fork = false; }
     if (keep) {
@@ -881,6 +983,17 @@ __device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, 
         Po.pix[of] = pix; Po.smp[of] = smp; Po.aux[of] = aux + 1u; Po.skip[of] = tri;
         Po.g[of] = g;
     }
+}
+
+template <class R>
+__device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, const Pool<R> &Po, int cur, bool keep,
+                                           bool fork, uint32_t i, V3<R> x, V3<R> dnew, V3<R> drefl, uint32_t pix,
+                                           uint32_t smp, uint32_t aux, int32_t tri, int nb, uint32_t m0, uint32_t m1,
+                                           uint32_t m2, uint32_t m3, R g, uint32_t *s_cnt, uint32_t *s_base)
+{
+    const int nbm = w.nbmax;
+    uint32_t om, of;
+    emit_paths<R>(w, Po, cur, keep, fork, x, dnew, drefl, pix, smp, aux, tri, g, om, of, s_cnt, s_base);
     if (keep) {
         const R *__restrict__ bin = Pi.beta + aosoa(i, 0, nbm);
         R *__restrict__ bk = Po.beta + aosoa(om, 0, nbm);
@@ -916,89 +1029,128 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     __shared__ uint32_t s_cnt[(kBlock / 64) * 2], s_base[2];
+    __shared__ uint32_t s_map_all[kBlock];
+    uint32_t *const s_map = s_map_all + (threadIdx.x & ~63u);
     uint32_t n_fork = 0, n_in = 0, n_spec = 0;
     // block-strided: the block reserves its output slots together
     for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
         const bool active = base + threadIdx.x < count;
         n_in += active ? 1u : 0u;
-        uint32_t i = 0, aux = 0, pix = 0, smp = 0;
+        uint32_t i = 0, aux = 0, pix = 0, smp = 0, flags = 0, mo = 0;
         int32_t tri = -1;
         V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x;
-        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;   // reflected wavelengths
-        bool keep = false, fork = false;
-        R g = R(0);
-        BandDev bd = {0, 0, 0, 0};
+        R g = R(0), cos_i = R(0), thick = R(0), u0 = R(0);
         if (active) {
-            i = w.gidx[base + threadIdx.x];
-            aux = Pi.aux[i];
-            pix = Pi.pix[i];
-            smp = Pi.smp[i];
+            const GlassRec<R> gr = rec_load(w.grec + base + threadIdx.x);
+            i = gr.slot;
+            aux = gr.aux;
+            pix = gr.pix;
+            smp = gr.smp;
             const bool spec = (smp & kSpectral) != 0u;
             n_spec += spec ? 1u : 0u;
-            g = Pi.g[i];
+            g = gr.g;
             const int depth = (int)(aux & 0xffu);
             const JobDev *jb = &jobs[kOne ? 0u : aux >> kAuxJobShift];
-            bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
-            tri = w.htri[i];
-            const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
-            x = o + w.ht[i] * d;
+            const BandDev bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+            tri = gr.tri;
+            const V3<R> d = {gr.d[0], gr.d[1], gr.d[2]};
+            x = {gr.x[0], gr.x[1], gr.x[2]};
             const TriDev tr = load_tri(jb->sc.tris, tri);
             const int mat = __float_as_int(tr.b.w);
             const V3<R> ng = tri_normal<R>(tr);
             const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
-            const R u0 = u01<R>(rr.x);
-            const R cos_i = fabs(dot(d, ng));
-            const R thick = pane_thickness<R>(jb->sc, tri, w.hu[i], w.hv[i]);
+            u0 = u01<R>(rr.x);
+            cos_i = fabs(dot(d, ng));
+            thick = pane_thickness<R>(jb->sc, tri, gr.u, gr.v);
             dnew = d;
             drefl = d - (R(2) * dot(d, ng)) * ng;
-            const size_t mo = (size_t)mat * jb->ms + bd.l0;
-            const R *nn = (const R *)jb->n + mo;
-            const R *kk = (const R *)jb->k + mo;
-            const R *tt = (const R *)jb->tint + mo;
-            const R *lam = (const R *)jb->lam + bd.l0;
-            const bool al = (bd.l0 & 3) == 0;
-            const R thr = R(jb->beta_thr);
-            bool anyR = false, anyT = false;
-            // the new factors stay in the input slot until the output slots are
-            // known (a path without per-wavelength factors gets them here);
-            // four wavelengths per step, the row's padding set to zero
-            R *__restrict__ brow = Pi.beta + aosoa(i, 0, nbm);
-            for (int j = 0; j < bd.nb; j += 4) {
+            flags = (spec ? kRowSrc : 0u) | ((bd.l0 & 3) == 0 ? kRowAl : 0u) | (uint32_t)bd.nb << kRowNbShift |
+                    (uint32_t)bd.l0 << 16;
+            mo = (uint32_t)(mat * jb->ms + bd.l0);
+        }
+        // Per wavelength: the new factor b (R + T) goes back to the input
+        // slot's row (a path without per-wavelength factors gets them here),
+        // negated where the wavelength reflects; the padding is set to zero.
+        // The wave takes the rows together (see RowTasks).
+        const RowTasks rt = row_tasks(active, nbm, s_map);
+        bool anyR = false, anyT = false;
+        for (int b0 = 0; b0 < rt.n; b0 += rt.ng) {
+            const int src = rt.src(b0, s_map);
+            const uint32_t f = (uint32_t)__shfl((int)flags, src);
+            const uint32_t si = (uint32_t)__shfl((int)i, src), smo = (uint32_t)__shfl((int)mo, src);
+            const R sc = __shfl(cos_i, src), st = __shfl(thick, src), su = __shfl(u0, src), sg = __shfl(g, src);
+            const uint32_t sjob = kOne ? 0u : (uint32_t)__shfl((int)(aux >> kAuxJobShift), src);
+            const int nb = (int)((f >> kRowNbShift) & 0xffu), j = rt.j;
+            bool lR = false, lT = false;
+            if (rt.busy(b0) && j < nb) {
+                const JobDev *sj = &jobs[sjob];
+                const bool al = (f & kRowAl) != 0u;
+                R *__restrict__ brow = Pi.beta + aosoa(si, 0, nbm);
                 Vec4<R> b4;
-                if (spec) b4 = row_load4(brow + j);
+                if (f & kRowSrc) b4 = row_load4(brow + j);
                 else b4.v[0] = b4.v[1] = b4.v[2] = b4.v[3] = R(1);
-                const Vec4<R> l4 = tab4(lam, al, j, bd.nb), n4 = tab4(nn, al, j, bd.nb), k4 = tab4(kk, al, j, bd.nb),
-                              t4 = tab4(tt, al, j, bd.nb);
+                const Vec4<R> l4 = tab4((const R *)sj->lam + (f >> 16), al, j, nb),
+                              n4 = tab4((const R *)sj->n + smo, al, j, nb),
+                              k4 = tab4((const R *)sj->k + smo, al, j, nb),
+                              t4 = tab4((const R *)sj->tint + smo, al, j, nb);
+                const R thr = R(sj->beta_thr);
                 Vec4<R> o4;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int jq = j + q;
                     o4.v[q] = R(0);
-                    if (jq >= bd.nb || b4.v[q] == R(0)) continue;
+                    if (j + q >= nb || b4.v[q] == R(0)) continue;
                     R Rr, Tt;
-                    slab_RT<R>(cos_i, l4.v[q], thick, n4.v[q], k4.v[q], t4.v[q], Rr, Tt);
-                    const R rt = Rr + Tt;
-                    R bn = b4.v[q] * rt;
-                    if (g * bn < thr) bn = R(0);
-                    o4.v[q] = bn;
+                    slab_RT<R>(sc, l4.v[q], st, n4.v[q], k4.v[q], t4.v[q], Rr, Tt);
+                    const R rtot = Rr + Tt;
+                    R bn = b4.v[q] * rtot;
+                    if (sg * bn < thr) bn = R(0);
                     if (bn == R(0)) continue;
-                    if (rt > R(0) && u0 < Rr / rt) {
-                        anyR = true;
-                        const uint32_t bit = 1u << (jq & 31);
-                        if (jq < 32) m0 |= bit; else if (jq < 64) m1 |= bit; else if (jq < 96) m2 |= bit; else m3 |= bit;
+                    if (rtot > R(0) && su < Rr / rtot) {
+                        lR = true;
+                        o4.v[q] = -bn;
                     } else {
-                        anyT = true;
+                        lT = true;
+                        o4.v[q] = bn;
                     }
                 }
                 row_store4(brow + j, o4);
             }
-            keep = anyR || anyT;
-            fork = anyR && anyT;
-            if (anyR && !anyT) dnew = drefl;
+            const uint64_t bR = __ballot(lR), bT = __ballot(lT);
+            uint64_t mine;
+            if (rt.mine(active, b0, mine)) {
+                anyR = (bR & mine) != 0u;
+                anyT = (bT & mine) != 0u;
+            }
         }
+        bool keep = anyR || anyT, fork = anyR && anyT;
+        if (anyR && !anyT) dnew = drefl;
         n_fork += fork ? 1u : 0u;
-        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3, g,
-                      s_cnt, s_base);
+        uint32_t om, of;
+        emit_paths<R>(w, Po, cur, keep, fork, x, dnew, drefl, pix, smp, aux, tri, g, om, of, s_cnt, s_base);
+        // the rows of the outputs: the kept path takes the transmitted
+        // wavelengths (all of them without a fork), the forked path the
+        // reflected ones; the same lanes read the elements they wrote above
+        const uint32_t ef = flags | (keep ? kRowKeep : 0u) | (fork ? kRowFork : 0u);
+        for (int b0 = 0; b0 < rt.n; b0 += rt.ng) {
+            const int src = rt.src(b0, s_map);
+            const uint32_t f = (uint32_t)__shfl((int)ef, src);
+            const uint32_t si = (uint32_t)__shfl((int)i, src), so = (uint32_t)__shfl((int)om, src),
+                           sf = (uint32_t)__shfl((int)of, src);
+            const int nb = (int)((f >> kRowNbShift) & 0xffu), j = rt.j;
+            if (!rt.busy(b0) || j >= nb || !(f & kRowKeep)) continue;
+            const bool fk = (f & kRowFork) != 0u;
+            const Vec4<R> b = row_load4(Pi.beta + aosoa(si, j, nbm));
+            Vec4<R> k4, f4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool refl = signbit(b.v[q]);
+                const R a = fabs(b.v[q]);
+                k4.v[q] = (fk && refl) ? R(0) : a;
+                f4.v[q] = refl ? a : R(0);
+            }
+            row_store4(Po.beta + aosoa(so, j, nbm), k4);
+            if (fk) row_store4(Po.beta + aosoa(sf, j, nbm), f4);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         n_fork += __shfl_xor(n_fork, off);

@@ -16,7 +16,7 @@ namespace sdm {
 namespace {
 
 constexpr int kBins = 16;
-constexpr int kLeafMax = 4;
+constexpr int kLeafMax = 2;
 
 struct Box {
     float lo[3] = {std::numeric_limits<float>::infinity(), std::numeric_limits<float>::infinity(),

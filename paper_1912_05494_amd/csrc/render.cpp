@@ -449,7 +449,12 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.grid_gl = ctx->num_cu * occupancy<R>(SDM_K_SHADE_GLASS);
         a.grid_e = ctx->num_cu * occupancy<R>(SDM_K_BUBBLY_EVAL);
         a.grid_b = ctx->num_cu * occupancy<R>(SDM_K_SHADE_BUBBLY);
-        a.grid_st = ctx->num_cu * occupancy<R>(SDM_K_SHADOW);
+        // Sun-grid walks stream their cells' candidate lists; with five
+        // resident blocks per CU the lists in flight evict each other, four
+        // keep the pass faster (measured on the nave: 5.33 -> 4.93 ms)
+        bool grid_walk = false;
+        for (const auto &jj : jobs) grid_walk = grid_walk || jj.sc->dev.g_use != 0;
+        a.grid_st = ctx->num_cu * (grid_walk ? std::min(4, occupancy<R>(SDM_K_SHADOW)) : occupancy<R>(SDM_K_SHADOW));
         a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM);
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
         const size_t gthreads = (size_t)std::max(a.grid_t, a.grid_st) * block_size();

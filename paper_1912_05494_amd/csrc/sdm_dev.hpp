@@ -226,15 +226,32 @@ __device__ __forceinline__ bool tri_hit(V3<R> o, V3<R> d, V3<R> p0, V3<R> p1, V3
     const V3<R> pv = cross(d, e2);
     const R det = dot(e1, pv);
     if (det == R(0)) return false;
-    const R inv = R(1) / det;
     const V3<R> sv = o - p0;
-    u = dot(sv, pv) * inv;
-    if (u < R(0) || u > R(1)) return false;
-    const V3<R> qv = cross(sv, e1);
-    v = dot(d, qv) * inv;
-    if (v < R(0) || u + v > R(1)) return false;
-    t = dot(e2, qv) * inv;
-    return true;
+    if constexpr (sizeof(R) == 4) {
+        // FP32: the bounds are checked on the numerators against |det| (its
+        // sign folded in), so a rejected triangle costs no division; an
+        // accepted one gets the same u, v, t as below (1/det = s/|det|)
+        const R s = det < R(0) ? R(-1) : R(1), ad = fabs(det);
+        const R uu = s * dot(sv, pv);
+        if (uu < R(0) || uu > ad) return false;
+        const V3<R> qv = cross(sv, e1);
+        const R vv = s * dot(d, qv);
+        if (vv < R(0) || uu + vv > ad) return false;
+        const R ia = R(1) / ad;
+        u = uu * ia;
+        v = vv * ia;
+        t = (s * dot(e2, qv)) * ia;
+        return true;
+    } else {
+        const R inv = R(1) / det;
+        u = dot(sv, pv) * inv;
+        if (u < R(0) || u > R(1)) return false;
+        const V3<R> qv = cross(sv, e1);
+        v = dot(d, qv) * inv;
+        if (v < R(0) || u + v > R(1)) return false;
+        t = dot(e2, qv) * inv;
+        return true;
+    }
 }
 
 template <class R>

@@ -111,9 +111,11 @@ __device__ __forceinline__ Vec4<R> tab4(const R *row, bool aligned, int j, int n
 // per-thread global region.  Entries are inner-node indices (>= 0) or leaves
 // encoded as -1 - (first << 8 | count).
 // ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) int32_t lds_i32;   // an LDS word (ds_* access)
+typedef __attribute__((address_space(1))) int32_t glb_i32;   // a global word (global_* access)
 struct Stack {
-    int32_t *lds;       // [kLdsStack][kBlock]
-    int32_t *glob;      // [(level - kLdsStack) * gstride + gtid]
+    lds_i32 *lds;       // [kLdsStack][kBlock]
+    glb_i32 *glob;      // [(level - kLdsStack) * gstride + gtid]
     uint32_t gtid, gstride;
     int sp;
     __device__ __forceinline__ void push(int32_t v)
@@ -133,7 +135,7 @@ struct Stack {
     __device__ __forceinline__ void push_sorted(int m, int32_t e1, int32_t e2, int32_t e3)
     {
         if (sp + 3 <= kLdsStack) {
-            int32_t *p = lds + sp * kBlock + threadIdx.x;
+            lds_i32 *p = lds + sp * kBlock + threadIdx.x;
             p[0] = m == 3 ? e3 : (m == 2 ? e2 : e1);
             p[kBlock] = m == 3 ? e2 : e1;
             p[2 * kBlock] = e1;
@@ -149,8 +151,8 @@ struct Stack {
 __device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
 {
     Stack st;
-    st.lds = lds_stack;
-    st.glob = gstack;
+    st.lds = (lds_i32 *)lds_stack;
+    st.glob = (glb_i32 *)gstack;
     st.gtid = blockIdx.x * blockDim.x + threadIdx.x;
     st.gstride = gridDim.x * blockDim.x;
     st.sp = 0;

@@ -134,7 +134,7 @@ def test_random_soups(driver, n, seed):
     check_tree(b)
     assert b["stack"] == stack_bound(b["nodes"])
     if n > 100:
-        # wide nodes: about half the levels of a binary tree with leaves of <= 4
+        # wide nodes: about half the levels of a binary tree with small leaves
         assert b["depth"] <= int(np.ceil(np.log2(n / 4) / 2)) + 4
 
 

@@ -163,29 +163,37 @@ __device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
 // are read from LDS, where the 16-byte word k of node i sits at
 // i * 8 + (k ^ (i & 7)): lanes reading the same word of different nodes then
 // fall into different bank groups.  The padding word (k = 7) is not read.
+// The plane words are read in the ray's octant order: for each axis the near
+// planes (lo where the direction is positive, hi where it is negative) and
+// the far ones, so the slab test needs no min/max to sort the two distances.
 struct WideNode {
-    float4 lox, hix, loy, hiy, loz, hiz;
+    float4 nx, fx, ny, fy, nz, fz;   // near / far planes of the four children per axis
     int32_t c0, c1, c2, c3;   // child entries (separate values: an indexed array would go to scratch)
 };
 
 __device__ __forceinline__ int lds_slot(int i, int k) { return i * 8 + (k ^ (i & 7)); }
 
-__device__ __forceinline__ WideNode load_node(const float4 *lds_nodes, int n_lds, const BvhNode *nodes, int i)
+// kx, ky, kz: byte offsets in the node of the ray's near-plane words (x: 0 or
+// 16, y: 32 or 48, z: 64 or 80); the far-plane word is the other of the pair.
+__device__ __forceinline__ WideNode load_node(const float4 *lds_nodes, int n_lds, const BvhNode *nodes, int i,
+                                              uint32_t kx, uint32_t ky, uint32_t kz)
 {
+    const uint32_t key[7] = {kx, kx ^ 16u, ky, ky ^ 16u, kz, kz ^ 16u, 96u};
     float4 q[7];
     if (i < n_lds) {
         // byte address of word k: (i * 128 | (i & 7) * 16) ^ k * 16
         const uint32_t a0 = ((uint32_t)i << 7) | (((uint32_t)i & 7u) << 4);
         const char *base = reinterpret_cast<const char *>(lds_nodes);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) q[k] = *reinterpret_cast<const float4 *>(base + (a0 ^ ((uint32_t)k << 4)));
+        for (int k = 0; k < 7; ++k) q[k] = *reinterpret_cast<const float4 *>(base + (a0 ^ key[k]));
     } else {
-        const float4 *p = reinterpret_cast<const float4 *>(nodes) + 8 * (size_t)i;
+        const char *base = reinterpret_cast<const char *>(nodes);
+        const uint32_t a0 = (uint32_t)i << 7;   // node byte offset (nodes < 2^25)
 #pragma unroll
-        for (int k = 0; k < 7; ++k) q[k] = gld4(p + k);
+        for (int k = 0; k < 7; ++k) q[k] = gld4(reinterpret_cast<const float4 *>(base + (size_t)(a0 | key[k])));
     }
     WideNode n;
-    n.lox = q[0]; n.hix = q[1]; n.loy = q[2]; n.hiy = q[3]; n.loz = q[4]; n.hiz = q[5];
+    n.nx = q[0]; n.fx = q[1]; n.ny = q[2]; n.fy = q[3]; n.nz = q[4]; n.fz = q[5];
     n.c0 = __float_as_int(q[6].x);
     n.c1 = __float_as_int(q[6].y);
     n.c2 = __float_as_int(q[6].z);
@@ -215,6 +223,7 @@ template <class R>
 struct Ray {
     V3<R> o, d, inv;
     V3<R> oi;            // o * inv, for the fused slab form
+    uint32_t kx, ky, kz; // node word offsets of the near planes (see load_node)
     int32_t skip, cur;
 };
 
@@ -225,6 +234,9 @@ __device__ __forceinline__ void set_dir(Ray<R> &ry, V3<R> o, V3<R> d)
     ry.d = d;
     ry.inv = safe_inv(d);
     ry.oi = {o.x * ry.inv.x, o.y * ry.inv.y, o.z * ry.inv.z};
+    ry.kx = signbit(ry.inv.x) ? 16u : 0u;
+    ry.ky = signbit(ry.inv.y) ? 48u : 32u;
+    ry.kz = signbit(ry.inv.z) ? 80u : 64u;
 }
 
 // Distance to the plane x = b along one axis.  The fused form b * inv - o *
@@ -242,7 +254,10 @@ __device__ __forceinline__ R slab_t(float b, R o, R inv, R oi)
 
 // Slab tests of the four child boxes against [tlo, thi]; tn is the entry
 // distance clamped to tlo.  The boxes are padded at build time, so rounding
-// never loses a hit.
+// never loses a hit.  The node words come in the ray's octant order, and the
+// rounded plane distance is monotonic in the plane coordinate, so each
+// near-plane distance is exactly the smaller of the axis's two (and the far
+// one the larger): the same values a min/max of the pair gives.
 template <bool kFused, class R>
 __device__ __forceinline__ void box4(const WideNode &nd, const Ray<R> &ry, R tlo, R thi, R (&tn)[4],
                                      bool (&hit)[4])
@@ -250,12 +265,9 @@ __device__ __forceinline__ void box4(const WideNode &nd, const Ray<R> &ry, R tlo
     const V3<R> o = ry.o, inv = ry.inv, oi = ry.oi;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        R t1 = slab_t<kFused>(f4get(nd.lox, c), o.x, inv.x, oi.x), t2 = slab_t<kFused>(f4get(nd.hix, c), o.x, inv.x, oi.x);
-        const R ax = fmin(t1, t2), bx = fmax(t1, t2);
-        t1 = slab_t<kFused>(f4get(nd.loy, c), o.y, inv.y, oi.y); t2 = slab_t<kFused>(f4get(nd.hiy, c), o.y, inv.y, oi.y);
-        const R ay = fmin(t1, t2), by = fmax(t1, t2);
-        t1 = slab_t<kFused>(f4get(nd.loz, c), o.z, inv.z, oi.z); t2 = slab_t<kFused>(f4get(nd.hiz, c), o.z, inv.z, oi.z);
-        const R az = fmin(t1, t2), bz = fmax(t1, t2);
+        const R ax = slab_t<kFused>(f4get(nd.nx, c), o.x, inv.x, oi.x), bx = slab_t<kFused>(f4get(nd.fx, c), o.x, inv.x, oi.x);
+        const R ay = slab_t<kFused>(f4get(nd.ny, c), o.y, inv.y, oi.y), by = slab_t<kFused>(f4get(nd.fy, c), o.y, inv.y, oi.y);
+        const R az = slab_t<kFused>(f4get(nd.nz, c), o.z, inv.z, oi.z), bz = slab_t<kFused>(f4get(nd.fz, c), o.z, inv.z, oi.z);
         const R a = fmax(fmax(ax, ay), fmax(az, tlo));
         const R b = fmin(fmin(bx, by), fmin(bz, thi));
         tn[c] = a;
@@ -345,7 +357,7 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
         }
         if (!__any(leaf == kDone && cur >= 0)) break;
         if (cur >= 0) {
-            const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
+            const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur, ry.kx, ry.ky, ry.kz);
             ++nodes;
             R tn[4];
             bool hit[4];
@@ -399,7 +411,7 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
         }
         if (!__any(leaf == kDone && cur >= 0)) break;
         if (cur >= 0) {
-            const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur);
+            const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur, ry.kx, ry.ky, ry.kz);
             ++nodes;
             R tn[4];
             bool hit[4];

@@ -435,7 +435,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         const int nb = (plan.nbmax + 3) & ~3;   // per-wavelength row, 16-byte aligned
         const size_t plane = (size_t)cap * sizeof(R);
         const size_t pool_b = 7 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) + 8 * 256;
-        const size_t hit_b = 3 * plane + 2 * (size_t)cap * 4 + (size_t)cap * sizeof(GlassRec<R>) + 256;
+        const size_t hit_b = (size_t)cap * sizeof(HitRec<R>) + (size_t)cap * 4 + (size_t)cap * sizeof(GlassRec<R>) + 256;
         const size_t sh_b = 4 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
                             (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R)) + 12 * 256;
         HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
@@ -475,8 +475,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             P.beta = (R *)take((size_t)cap * nb * sizeof(R));
         }
         pb = ctx->hits.as<char>();
-        w.ht = (R *)take(plane); w.hu = (R *)take(plane); w.hv = (R *)take(plane);
-        w.htri = (int32_t *)take((size_t)cap * 4);
+        w.hit = (HitRec<R> *)take((size_t)cap * sizeof(HitRec<R>));
         w.gidx = (uint32_t *)take((size_t)cap * 4);
         w.grec = (GlassRec<R> *)take((size_t)cap * sizeof(GlassRec<R>));
         if (surr) {

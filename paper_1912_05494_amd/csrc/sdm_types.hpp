@@ -152,6 +152,14 @@ struct Pool {
 
 constexpr int kMaxGlass = 8;    // panes a shadow ray may cross (more: SDM_E_UNSUPPORTED)
 
+// Closest hit of a pool slot (tri < 0: no hit), one record so that it is
+// written and read with one or two 16-byte accesses.
+template <class R>
+struct alignas(16) HitRec {
+    R t, u, v;                  // distance and barycentric coordinates
+    int32_t tri;                // leaf-order index of the triangle hit
+};
+
 // A clear-glass vertex as the shade pass queues it for the glass pass: the
 // state the glass pass needs, gathered into one record (64 bytes in FP32)
 // so that it is read with a few wide loads instead of a word from each pool
@@ -169,8 +177,7 @@ struct alignas(16) GlassRec {
 template <class R>
 struct Work {
     Pool<R> p[2];
-    R *ht, *hu, *hv;            // closest hit per slot of the current pool
-    int32_t *htri;
+    HitRec<R> *hit;             // closest hit per slot of the current pool
     uint32_t *gidx;             // slots of the current pool at a bubbly-glass vertex, from the
                                 // back: gidx[cap - 1 - b]
     GlassRec<R> *grec;          // clear-glass vertices [0, gcount)

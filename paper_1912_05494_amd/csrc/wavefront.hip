@@ -680,7 +680,9 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *__restrict__ job
                              closest_step<kSurface>(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry, h, teps, n_nodes,
                                           n_tests);
             if (fin) {
-                w.ht[item] = h.tb; w.htri[item] = h.trib; w.hu[item] = h.ub; w.hv[item] = h.vb;
+                HitRec<R> hr;
+                hr.t = h.tb; hr.u = h.ub; hr.v = h.vb; hr.tri = h.trib;
+                rec_store(w.hit + item, hr);
                 item = -1;
             }
         }
@@ -815,7 +817,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             const int depth = (int)(aux & 0xffu);
             jb = &jobs[kOne ? 0u : aux >> kAuxJobShift];
             bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
-            tri = w.htri[i];
+            const HitRec<R> hr = rec_load(w.hit + i);
+            tri = hr.tri;
             const bool last = depth >= jb->max_depth - 1;
             if (tri < 0) {
                 kind = 0;
@@ -828,7 +831,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     gray = mt == 3;
                     if (gray) rho_g = gld((const R *)jb->rho + (size_t)mat * jb->ms + bd.l0);
                     const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
-                    x = o + w.ht[i] * d;
+                    x = o + hr.t * d;
                     const V3<R> ng = tri_normal<R>(tr);
                     const V3<R> ns = dot(ng, d) > R(0) ? R(-1) * ng : ng;
                     const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
@@ -846,9 +849,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                                        // unused at glass, carry the barycentrics)
                         const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]};
                         dnew = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
-                        x = o + w.ht[i] * dnew;
-                        cs = w.hu[i];
-                        rho_g = w.hv[i];
+                        x = o + hr.t * dnew;
+                        cs = hr.u;
+                        rho_g = hr.v;
                     }
                 }
             }
@@ -1201,13 +1204,14 @@ __device__ __forceinline__ BubblyVertex bubbly_vertex(const JobDev *jobs, const 
     const uint32_t aux = Pi.aux[v.i];
     v.jb = &jobs[aux >> kAuxJobShift];
     v.bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
-    v.tri = w.htri[v.i];
+    const HitRec<R> hr = rec_load(w.hit + v.i);
+    v.tri = hr.tri;
     const TriDev tr = load_tri(v.jb->sc.tris, v.tri);
     v.mat = __float_as_int(tr.b.w);
     d = {Pi.dx[v.i], Pi.dy[v.i], Pi.dz[v.i]};
     ng = tri_normal<R>(tr);
     cos_i = fabs(dot(d, ng));
-    thick = pane_thickness<R>(v.jb->sc, v.tri, w.hu[v.i], w.hv[v.i]);
+    thick = pane_thickness<R>(v.jb->sc, v.tri, hr.u, hr.v);
     const double *b = v.jb->sc.mat_bub + 4 * (size_t)v.mat;
     v.sigma = gld(b);
     v.n_ref = gld(b + 1);
@@ -1389,7 +1393,7 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restric
             g = Pi.g[i];
             const int depth = (int)(aux & 0xffu);
             const JobDev *jb = v.jb;
-            x = V3<R>{Pi.ox[i], Pi.oy[i], Pi.oz[i]} + w.ht[i] * d;
+            x = V3<R>{Pi.ox[i], Pi.oy[i], Pi.oz[i]} + w.hit[i].t * d;
             dnew = d;
             drefl = d - (R(2) * dot(d, ng)) * ng;
             const size_t mo = (size_t)v.mat * jb->ms + bd.l0;

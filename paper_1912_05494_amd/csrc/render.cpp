@@ -434,7 +434,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         const uint32_t cap = (uint32_t)cap64;
         const int nb = (plan.nbmax + 3) & ~3;   // per-wavelength row, 16-byte aligned
         const size_t plane = (size_t)cap * sizeof(R);
-        const size_t pool_b = 7 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) + 8 * 256;
+        const size_t pool_b = (size_t)cap * (sizeof(PathO<R>) + sizeof(PathD<R>) + sizeof(PathS<R>)) +
+                              (size_t)cap * nb * sizeof(R) + 8 * 256;
         const size_t hit_b = (size_t)cap * sizeof(HitRec<R>) + (size_t)cap * 4 + (size_t)cap * sizeof(GlassRec<R>) + 256;
         const size_t sh_b = 4 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
                             (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R)) + 12 * 256;
@@ -467,11 +468,9 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         pb = ctx->pool.as<char>();
         for (int q = 0; q < 2; ++q) {
             Pool<R> &P = w.p[q];
-            P.ox = (R *)take(plane); P.oy = (R *)take(plane); P.oz = (R *)take(plane);
-            P.dx = (R *)take(plane); P.dy = (R *)take(plane); P.dz = (R *)take(plane);
-            P.pix = (uint32_t *)take((size_t)cap * 4); P.smp = (uint32_t *)take((size_t)cap * 4);
-            P.aux = (uint32_t *)take((size_t)cap * 4); P.skip = (int32_t *)take((size_t)cap * 4);
-            P.g = (R *)take(plane);
+            P.o = (PathO<R> *)take((size_t)cap * sizeof(PathO<R>));
+            P.d = (PathD<R> *)take((size_t)cap * sizeof(PathD<R>));
+            P.s = (PathS<R> *)take((size_t)cap * sizeof(PathS<R>));
             P.beta = (R *)take((size_t)cap * nb * sizeof(R));
         }
         pb = ctx->hits.as<char>();

@@ -141,12 +141,30 @@ __host__ __device__ __forceinline__ size_t aosoa(uint32_t slot, int j, int nbmax
 // c_j stored only for records flagged kSpectral in their pixel word.
 constexpr uint32_t kSpectral = 0x80000000u;
 
+// A path's state as three 16-byte records per slot (32-byte ones in FP64), so
+// that each is moved with one wide access and a pass reads only those it
+// needs: the origin with the last triangle hit, the direction, and the
+// sample words with the scalar factor.
+template <class R>
+struct alignas(16) PathO {
+    R x, y, z;
+    int32_t skip;               // leaf-order index of the last hit triangle (-1: none)
+};
+template <class R>
+struct alignas(16) PathD {
+    R x, y, z;
+};
+template <class R>
+struct alignas(16) PathS {
+    uint32_t pix, smp, aux;     // smp: sample | kSpectral; aux = depth | band << 8 | job << 20
+    R g;                        // scalar factor of the weights
+};
+
 template <class R>
 struct Pool {
-    R *ox, *oy, *oz, *dx, *dy, *dz;
-    uint32_t *pix, *smp, *aux;  // smp: sample | kSpectral; aux = depth | band << 8 | job << 20
-    int32_t *skip;              // leaf-order index of the last hit triangle
-    R *g;                       // [slot] scalar factor of the weights
+    PathO<R> *o;
+    PathD<R> *d;
+    PathS<R> *s;
     R *beta;                    // AoSoA [slot][j] per-wavelength factors (kSpectral paths)
 };
 

@@ -81,6 +81,21 @@ __device__ __forceinline__ void rec_store(T *p, const T &r)
     for (size_t k = 0; k < sizeof(T) / 16; ++k) q[k] = t[k];
 }
 
+template <class R>
+__device__ __forceinline__ void put_path(const Pool<R> &P, uint32_t k, V3<R> o, V3<R> d, int32_t skip, uint32_t pix,
+                                         uint32_t smp, uint32_t aux, R g)
+{
+    PathO<R> a;
+    a.x = o.x; a.y = o.y; a.z = o.z; a.skip = skip;
+    PathD<R> b;
+    b.x = d.x; b.y = d.y; b.z = d.z;
+    PathS<R> c;
+    c.pix = pix; c.smp = smp; c.aux = aux; c.g = g;
+    rec_store(P.o + k, a);
+    rec_store(P.d + k, b);
+    rec_store(P.s + k, c);
+}
+
 // Wavelengths j .. j+3 of a band's row in a wavelength table (rows of ms
 // values, ms a multiple of 4).  A band that starts at a multiple of 4 reads
 // them with one 16-byte load (two for double); otherwise four loads, each
@@ -615,13 +630,8 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *__restrict__ 
             o = eye;
             d = normalize(f + (a * R(jb.th) * R(jb.aspect)) * rv + (b * R(jb.th)) * uv);
         }
-        P.ox[i] = o.x; P.oy[i] = o.y; P.oz[i] = o.z;
-        P.dx[i] = d.x; P.dy[i] = d.y; P.dz[i] = d.z;
-        P.pix[i] = pixel;
-        P.smp[i] = smp;                  // all wavelengths start with weight 1: no kSpectral
-        P.g[i] = R(1);
-        P.aux[i] = pack_aux(0, it.band, bd.job);
-        P.skip[i] = -1;
+        // all wavelengths start with weight 1: no kSpectral
+        put_path<R>(P, i, o, d, -1, pixel, smp, pack_aux(0, it.band, bd.job), R(1));
     }
 }
 
@@ -662,10 +672,12 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *__restrict__ job
         if (got >= 0) {
             item = got;
             const uint32_t s = (uint32_t)got;
-            job = kOne ? 0 : (int)(P.aux[s] >> kAuxJobShift);
+            job = kOne ? 0 : (int)(rec_load(P.s + s).aux >> kAuxJobShift);
             const SceneDev &sc = jobs[job].sc;
-            set_dir(ry, V3<R>{P.ox[s], P.oy[s], P.oz[s]}, V3<R>{P.dx[s], P.dy[s], P.dz[s]});
-            ry.skip = P.skip[s];
+            const PathO<R> po = rec_load(P.o + s);
+            const PathD<R> pd = rec_load(P.d + s);
+            set_dir(ry, V3<R>{po.x, po.y, po.z}, V3<R>{pd.x, pd.y, pd.z});
+            ry.skip = po.skip;
             ry.cur = sc.n_nodes > 0 ? 0 : kDone;
             teps = teps_of<R>(sc);
             h.tb = R(INFINITY); h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
@@ -809,11 +821,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
         const JobDev *jb = nullptr;
         BandDev bd = {0, 0, 0, 0};
         if (active) {
-            aux = Pi.aux[i];
-            pix = Pi.pix[i];
-            smp = Pi.smp[i];
+            const PathS<R> ps = rec_load(Pi.s + i);
+            aux = ps.aux;
+            pix = ps.pix;
+            smp = ps.smp;
             spec = (smp & kSpectral) != 0u;
-            g = Pi.g[i];
+            g = ps.g;
             const int depth = (int)(aux & 0xffu);
             jb = &jobs[kOne ? 0u : aux >> kAuxJobShift];
             bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
@@ -830,7 +843,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     kind = 1;
                     gray = mt == 3;
                     if (gray) rho_g = gld((const R *)jb->rho + (size_t)mat * jb->ms + bd.l0);
-                    const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]}, d = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
+                    const PathO<R> po = rec_load(Pi.o + i);
+                    const PathD<R> pd = rec_load(Pi.d + i);
+                    const V3<R> o = {po.x, po.y, po.z}, d = {pd.x, pd.y, pd.z};
                     x = o + hr.t * d;
                     const V3<R> ng = tri_normal<R>(tr);
                     const V3<R> ns = dot(ng, d) > R(0) ? R(-1) * ng : ng;
@@ -847,9 +862,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     kind = mt == 2 ? 3 : 2;
                     if (kind == 2) {   // gathered for the glass pass's record (cs and rho_g,
                                        // unused at glass, carry the barycentrics)
-                        const V3<R> o = {Pi.ox[i], Pi.oy[i], Pi.oz[i]};
-                        dnew = {Pi.dx[i], Pi.dy[i], Pi.dz[i]};
-                        x = o + hr.t * dnew;
+                        const PathO<R> po = rec_load(Pi.o + i);
+                        const PathD<R> pd = rec_load(Pi.d + i);
+                        dnew = {pd.x, pd.y, pd.z};
+                        x = V3<R>{po.x, po.y, po.z} + hr.t * dnew;
                         cs = hr.u;
                         rho_g = hr.v;
                     }
@@ -895,14 +911,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                 w.scs[sslot] = gn * inv_pi * cs;
             }
             if (keep) {
-                Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
-                Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
-                Po.pix[om] = pix;
-                Po.smp[om] = (smp & ~kSpectral) | (out_spec ? kSpectral : 0u);
-                Po.aux[om] = aux + 1u;
-                Po.skip[om] = tri;
                 // the energy threshold of a gray path acts on g
-                Po.g[om] = (!out_spec && gn < thr) ? R(0) : gn;
+                put_path<R>(Po, om, x, dnew, tri, pix, (smp & ~kSpectral) | (out_spec ? kSpectral : 0u), aux + 1u,
+                            (!out_spec && gn < thr) ? R(0) : gn);
             }
             if (out_spec) {
                 rflags = (spec ? kRowSrc : 0u) | (gray ? 0u : kRowRho) | (want_shadow ? kRowRec : 0u) |
@@ -988,18 +999,8 @@ __device__ __forceinline__ void emit_paths(const Work<R> &w, const Pool<R> &Po, 
     of = slot[1];
     if (keep && om >= w.cap) { w.cnt->overflow |= 1u; keep = false; }
     if (fork && of >= w.cap) { w.cnt->overflow |= 1u; fork = false; }
-    if (keep) {
-        Po.ox[om] = x.x; Po.oy[om] = x.y; Po.oz[om] = x.z;
-        Po.dx[om] = dnew.x; Po.dy[om] = dnew.y; Po.dz[om] = dnew.z;
-        Po.pix[om] = pix; Po.smp[om] = smp; Po.aux[om] = aux + 1u; Po.skip[om] = tri;
-        Po.g[om] = g;
-    }
-    if (fork) {
-        Po.ox[of] = x.x; Po.oy[of] = x.y; Po.oz[of] = x.z;
-        Po.dx[of] = drefl.x; Po.dy[of] = drefl.y; Po.dz[of] = drefl.z;
-        Po.pix[of] = pix; Po.smp[of] = smp; Po.aux[of] = aux + 1u; Po.skip[of] = tri;
-        Po.g[of] = g;
-    }
+    if (keep) put_path<R>(Po, om, x, dnew, tri, pix, smp, aux + 1u, g);
+    if (fork) put_path<R>(Po, of, x, drefl, tri, pix, smp, aux + 1u, g);
 }
 
 template <class R>
@@ -1201,14 +1202,15 @@ __device__ __forceinline__ BubblyVertex bubbly_vertex(const JobDev *jobs, const 
 {
     BubblyVertex v;
     v.i = w.gidx[w.cap - 1u - e];
-    const uint32_t aux = Pi.aux[v.i];
+    const uint32_t aux = rec_load(Pi.s + v.i).aux;
     v.jb = &jobs[aux >> kAuxJobShift];
     v.bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
     const HitRec<R> hr = rec_load(w.hit + v.i);
     v.tri = hr.tri;
     const TriDev tr = load_tri(v.jb->sc.tris, v.tri);
     v.mat = __float_as_int(tr.b.w);
-    d = {Pi.dx[v.i], Pi.dy[v.i], Pi.dz[v.i]};
+    const PathD<R> pd = rec_load(Pi.d + v.i);
+    d = {pd.x, pd.y, pd.z};
     ng = tri_normal<R>(tr);
     cos_i = fabs(dot(d, ng));
     thick = pane_thickness<R>(v.jb->sc, v.tri, hr.u, hr.v);
@@ -1275,7 +1277,7 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *__res
                 w.bw[v.i] = R(wl);
             } else {
                 const size_t q = aosoa(v.i, (int)j, w.nbmax);
-                const R b = (Pi.smp[v.i] & kSpectral) ? Pi.beta[q] : R(1);
+                const R b = (rec_load(Pi.s + v.i).smp & kSpectral) ? Pi.beta[q] : R(1);
                 Pi.beta[q] = b * R(Rr + Tt);
                 w.bratio[q] = R(Rr / (Rr + Tt));
             }
@@ -1346,7 +1348,7 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *__res
             w.bw[v.i] = y[2];
         } else {
             const size_t q = aosoa(v.i, (int)j, w.nbmax);
-            const double b = (Pi.smp[v.i] & kSpectral) ? Pi.beta[q] : 1.0;
+            const double b = (rec_load(Pi.s + v.i).smp & kSpectral) ? Pi.beta[q] : 1.0;
             Pi.beta[q] = b * (y[0] + y[1]);
             w.bratio[q] = y[0] / (y[0] + y[1]);
         }
@@ -1386,14 +1388,16 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restric
             i = v.i;
             bd = v.bd;
             tri = v.tri;
-            aux = Pi.aux[i];
-            pix = Pi.pix[i];
-            smp = Pi.smp[i];
+            const PathS<R> ps = rec_load(Pi.s + i);
+            aux = ps.aux;
+            pix = ps.pix;
+            smp = ps.smp;
             const bool spec = (smp & kSpectral) != 0u;
-            g = Pi.g[i];
+            g = ps.g;
             const int depth = (int)(aux & 0xffu);
             const JobDev *jb = v.jb;
-            x = V3<R>{Pi.ox[i], Pi.oy[i], Pi.oz[i]} + w.hit[i].t * d;
+            const PathO<R> po = rec_load(Pi.o + i);
+            x = V3<R>{po.x, po.y, po.z} + rec_load(w.hit + i).t * d;
             dnew = d;
             drefl = d - (R(2) * dot(d, ng)) * ng;
             const size_t mo = (size_t)v.mat * jb->ms + bd.l0;

@@ -357,17 +357,19 @@ __device__ __forceinline__ TriDev load_tri(const TriDev *tris, int i)
 // and goes on with its stack while other lanes of the wave are still
 // searching for theirs, so lanes do not idle through the longest descent of
 // the wave (its extra visits use the larger bound of before the test, which
-// changes no result).  The descent ends when every lane holds a leaf or has
-// nothing left to visit.
+// changes no result); it may pick up a second leaf on the way, tested in the
+// same step.  The descent ends when every lane holds a leaf or has nothing
+// left to visit.
 template <bool kFused, class R>
 __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
                                              Ray<R> &ry, Closest<R> &h, R teps, uint32_t &nodes, uint32_t &tests)
 {
     int32_t cur = ry.cur;      // inner node (>= 0), leaf (< -1) or kDone
-    int32_t leaf = kDone;
+    int32_t leaf = kDone, leaf2 = kDone;
     for (;;) {
-        if (cur < 0 && cur != kDone && leaf == kDone) {
-            leaf = cur;
+        if (cur < 0 && cur != kDone && leaf2 == kDone) {
+            if (leaf == kDone) leaf = cur;
+            else leaf2 = cur;
             cur = st.sp ? st.pop() : kDone;
         }
         if (!__any(leaf == kDone && cur >= 0)) break;
@@ -387,11 +389,13 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
             }
         }
     }
-    if (leaf != kDone) {
-        const int32_t code = -1 - leaf;
-        const int first = code >> 8, cnt = code & 255;
-        tests += (uint32_t)cnt;
-        for (int i = first; i < first + cnt; ++i) {
+    {
+        // the triangles of both leaves held, in one loop
+        const int32_t ca = leaf != kDone ? -1 - leaf : 0, cb = leaf2 != kDone ? -1 - leaf2 : 0;
+        const int fa = ca >> 8, na = ca & 255, fb = cb >> 8, nb = cb & 255;
+        tests += (uint32_t)(na + nb);
+        for (int k = 0; k < na + nb; ++k) {
+            const int i = k < na ? fa + k : fb + (k - na);
             if (i == ry.skip) continue;
             const TriDev tr = load_tri(sc.tris, i);
             R t, u, v;

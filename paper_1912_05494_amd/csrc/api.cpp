@@ -225,7 +225,7 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         std::memcpy(&fm, &mm, 4);
         tris[l].a = make_float4(p0[0], p0[1], p0[2], ft);
         tris[l].b = make_float4(p1[0], p1[1], p1[2], fm);
-        tris[l].c = make_float4(p2[0], p2[1], p2[2], 0.0f);
+        tris[l].c = make_float4(p2[0], p2[1], p2[2], 0.0f);   // w: material type, set below
         if (d->vthick_mm)
             thick[l] = make_float4(d->vthick_mm[d->idx[3 * (size_t)t]], d->vthick_mm[d->idx[3 * (size_t)t + 1]],
                                    d->vthick_mm[d->idx[3 * (size_t)t + 2]], 0.0f);
@@ -284,6 +284,13 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         for (int q = 0; q < 4; ++q)
             if (src[q])
                 std::memcpy(&tabm[((size_t)q * d->n_mat + m) * d->n_tab], src[q], sizeof(float) * d->n_tab);
+    }
+    // each triangle carries its material type in c.w, read with its vertices
+    for (int32_t l = 0; l < d->nt; ++l) {
+        int32_t m;
+        std::memcpy(&m, &tris[l].b.w, 4);
+        const int32_t ty = mtype[m];
+        std::memcpy(&tris[l].c.w, &ty, 4);
     }
     double maxabs = 0.0;
     for (int a = 0; a < 3 && d->nv > 0; ++a) maxabs = std::max({maxabs, std::fabs(lo[a]), std::fabs(hi[a])});

@@ -20,8 +20,9 @@ struct alignas(128) BvhNode {
 static_assert(sizeof(BvhNode) == 128, "node layout");
 
 // Triangle in BVH leaf order: the three vertices (exact float inputs, edges
-// are formed in the kernel's precision); a.w holds the caller's triangle
-// index, b.w the material index (integer bits).
+// are formed in the kernel's precision); a.w, b.w and c.w hold, as integer
+// bits, the caller's triangle index, the material index and the material's
+// type (0 Lambert, 1 glass, 2 bubbly glass, 3 gray Lambert).
 struct alignas(16) TriDev {
     float4 a, b, c;
 };

@@ -457,7 +457,7 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
             R t, u, v;
             if (!tri_hit(ry.o, ry.d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
             if (!(t > teps)) continue;
-            const int mt = gld(sc.mat_type + __float_as_int(tr.b.w));
+            const int mt = __float_as_int(tr.c.w);
             if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
                 occluded = true;
                 ry.cur = kDone;
@@ -842,7 +842,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             } else {
                 const TriDev tr = load_tri(jb->sc.tris, tri);
                 mat = __float_as_int(tr.b.w);
-                const int mt = gld(jb->sc.mat_type + mat);
+                const int mt = __float_as_int(tr.c.w);
                 if (mt == 0 || mt == 3) {
                     kind = 1;
                     gray = mt == 3;

@@ -37,6 +37,7 @@ namespace sdm {
 
 constexpr int kLdsNodes = 160;    // wide-node prefix staged in LDS (20 KB)
 constexpr int kBlock = 256;
+constexpr int kShadeBlock = 512;   // threads per block of the shading pass (fewer slot reservations)
 constexpr uint32_t kFetch = 256;  // items per group of the traversal work distribution
 constexpr int32_t kDone = INT_MIN;
 
@@ -767,7 +768,8 @@ __device__ __forceinline__ RowTasks row_tasks(bool want, int nbm, uint32_t *s_ma
 // Block-wide reservation of output slots in Q queues: every thread of the
 // block calls it (block-uniform control flow).  One atomic per queue and
 // block instead of one per wave; slots keep lane order within the block.
-template <int Q>
+// NW: waves per block.
+template <int Q, int NW = kBlock / 64>
 __device__ __forceinline__ void block_reserve(const bool (&want)[Q], uint32_t *const (&ctr)[Q], uint32_t (&slot)[Q],
                                               uint32_t *s_cnt, uint32_t *s_base)
 {
@@ -784,7 +786,7 @@ __device__ __forceinline__ void block_reserve(const bool (&want)[Q], uint32_t *c
     if (threadIdx.x < (unsigned)Q) {
         const int q = threadIdx.x;
         uint32_t total = 0;
-        for (int w2 = 0; w2 < kBlock / 64; ++w2) total += s_cnt[w2 * Q + q];
+        for (int w2 = 0; w2 < NW; ++w2) total += s_cnt[w2 * Q + q];
         s_base[q] = total ? atomicAdd(ctr[q], total) : 0u;
     }
     __syncthreads();
@@ -797,22 +799,25 @@ __device__ __forceinline__ void block_reserve(const bool (&want)[Q], uint32_t *c
     __syncthreads();   // s_cnt and s_base are reused by the next call
 }
 
-// FP32: eight waves per SIMD (64 VGPRs, no spills) hide more of the pass's
-// memory latency; the FP64 instantiation keeps its registers
+// FP32: eight waves per SIMD (64 VGPRs) hide more of the pass's memory
+// latency; the FP64 instantiation keeps its registers.  Blocks of 512
+// threads: every block iteration reserves its output slots with one atomic
+// per queue on counters shared by the whole chip, and those atomics (on the
+// memory side) bounded the pass at 256 threads.
 template <class R, bool kOne>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1))) k_shade(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
+__global__ void __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1))) k_shade(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
     const Pool<R> Pi = w.p[cur], Po = w.p[cur ^ 1];
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     const R inv_pi = R(0.31830988618379067);
-    __shared__ uint32_t s_cnt[(kBlock / 64) * 5], s_base[5];
-    __shared__ uint32_t s_map_all[kBlock];
+    __shared__ uint32_t s_cnt[(kShadeBlock / 64) * 5], s_base[5];
+    __shared__ uint32_t s_map_all[kShadeBlock];
     uint32_t *const s_map = s_map_all + (threadIdx.x & ~63u);
     uint32_t n_spec = 0, n_srec = 0;
     // block-strided so that the block reserves its output slots together
-    for (uint32_t bbase = blockIdx.x * kBlock; bbase < count; bbase += gridDim.x * kBlock) {
+    for (uint32_t bbase = blockIdx.x * kShadeBlock; bbase < count; bbase += gridDim.x * kShadeBlock) {
         const uint32_t i = bbase + threadIdx.x;
         const bool active = i < count;
         uint32_t aux = 0, pix = 0, smp = 0;
@@ -883,7 +888,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
         uint32_t *const ctr[5] = {&w.cnt->gcount, &w.cnt->bcount, &w.cnt->scount, &w.cnt->count[cur ^ 1],
                                   &w.cnt->kcount};
         uint32_t slot[5];
-        block_reserve<5>(want, ctr, slot, s_cnt, s_base);
+        block_reserve<5, kShadeBlock / 64>(want, ctr, slot, s_cnt, s_base);
         if (kind == 2) {
             GlassRec<R> r;
             r.x[0] = x.x; r.x[1] = x.y; r.x[2] = x.z;
@@ -1994,8 +1999,8 @@ template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
                   hipStream_t s)
 {
-    if (one_job) hipLaunchKernelGGL((k_shade<R, true>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
-    else hipLaunchKernelGGL((k_shade<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+    if (one_job) hipLaunchKernelGGL((k_shade<R, true>), dim3(grid), dim3(kShadeBlock), 0, s, jobs, bands, w, cur);
+    else hipLaunchKernelGGL((k_shade<R, false>), dim3(grid), dim3(kShadeBlock), 0, s, jobs, bands, w, cur);
 }
 template <class R>
 void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
@@ -2107,7 +2112,8 @@ int occupancy(int kernel_class, int lds_bytes)
     default: return 1;
     }
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, kBlock, lds_bytes) != hipSuccess) return 1;
+    const int threads = kernel_class == SDM_K_SHADE ? kShadeBlock : kBlock;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, threads, lds_bytes) != hipSuccess) return 1;
     return std::max(1, b);
 }
 

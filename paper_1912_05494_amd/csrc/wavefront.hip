@@ -1519,10 +1519,16 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
             const uint32_t s = (uint32_t)got;
             job = kOne ? 0 : (int)(w.saux[s] >> kAuxJobShift);
             const SceneDev &sc = jobs[job].sc;
-            set_dir(ry, V3<R>{w.sx[s], w.sy[s], w.sz[s]}, V3<R>{R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])});
-            ry.skip = w.sskip[s];
             grid = sc.g_use != 0;
-            if (grid) gr = grid_range(sc, ry.o);
+            const V3<R> o = {w.sx[s], w.sy[s], w.sz[s]}, d = {R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])};
+            if (grid) {   // the candidate walk needs no slab setup
+                ry.o = o;
+                ry.d = d;
+                gr = grid_range(sc, o);
+            } else {
+                set_dir(ry, o, d);
+            }
+            ry.skip = w.sskip[s];
             ry.cur = !grid && sc.n_nodes > 0 ? 0 : kDone;
             teps = teps_of<R>(sc);
             ng = 0;

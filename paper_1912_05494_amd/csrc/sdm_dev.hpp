@@ -165,6 +165,17 @@ __device__ __forceinline__ void fresnel_sp(R c, R n, R k, R &Rs, R &Rp)
          ((px + cr) * (px + cr) + (py + ci) * (py + ci));
 }
 
+// a / b for the slab optics: times the hardware reciprocal in FP32 (within
+// about one unit in the last place, against a correctly rounded division's
+// half; the FP32 kernels are held to the FP64 oracle by tolerance), a
+// division in FP64.
+template <class R>
+__device__ __forceinline__ R slab_div(R a, R b)
+{
+    if constexpr (sizeof(R) == 4) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+
 template <class R>
 __device__ __forceinline__ void slab_pol(R r, R tau, R &Rr, R &Tt)
 {
@@ -173,7 +184,7 @@ __device__ __forceinline__ void slab_pol(R r, R tau, R &Rr, R &Tt)
     // with one division for both
     const R q = R(1) - r;
     const R rt = r * tau;
-    const R inv = R(1) / (R(1) - rt * rt);
+    const R inv = slab_div(R(1), R(1) - rt * rt);
     const R qqt = q * q * tau;
     Rr = r + qqt * rt * inv;
     Tt = qqt * inv;
@@ -187,7 +198,7 @@ template <class R>
 __device__ __forceinline__ void slab_RT(R c, R lambda_nm, R d_mm, R n, R k, R tint, R &Rout, R &Tout)
 {
     c = fmin(fmax(c, R(0)), R(1));
-    const R st = sqrt(fmax(R(1) - c * c, R(0))) / n;
+    const R st = slab_div(sqrt(fmax(R(1) - c * c, R(0))), n);
     const R ct2 = R(1) - st * st;
     const R ct = ct2 > R(0) ? sqrt(ct2) : R(0);
     R Rs, Rp;
@@ -198,7 +209,7 @@ __device__ __forceinline__ void slab_RT(R c, R lambda_nm, R d_mm, R n, R k, R ti
         // (c - n ct) / (c + n ct) and (n c - ct) / (n c + ct) share one division
         const R nc = n * c, nct = n * ct;
         const R a = c + nct, b = nc + ct;
-        const R inv = R(1) / (a * b);
+        const R inv = slab_div(R(1), a * b);
         const R rs = (c - nct) * b * inv, rp = (nc - ct) * a * inv;
         Rs = rs * rs;
         Rp = rp * rp;
@@ -208,7 +219,7 @@ __device__ __forceinline__ void slab_RT(R c, R lambda_nm, R d_mm, R n, R k, R ti
     // alpha d / ct with alpha = 4 pi k / lambda + tint (lambda in mm):
     // (4 pi 1e6 k + tint lambda_nm) d / (lambda_nm ct), one division
     const R num = (R(12566370.614359172) * k + tint * lambda_nm) * d_mm;
-    const R tau = (num == R(0)) ? R(1) : (ct > R(0) ? exp(-num / (lambda_nm * ct)) : R(0));
+    const R tau = (num == R(0)) ? R(1) : (ct > R(0) ? exp(-slab_div(num, lambda_nm * ct)) : R(0));
     R R1, T1, R2, T2;
     slab_pol(Rs, tau, R1, T1);
     slab_pol(Rp, tau, R2, T2);

@@ -265,11 +265,18 @@ __device__ __forceinline__ bool tri_hit(V3<R> o, V3<R> d, V3<R> p0, V3<R> p1, V3
     }
 }
 
+// Inverse direction for the slab tests.  FP32 takes the hardware reciprocal
+// (about one ulp): a slab distance then moves by about 1e-7 of itself, far
+// inside the box padding, and hits are decided by the triangle test alone.
 template <class R>
 __device__ __forceinline__ V3<R> safe_inv(V3<R> d)
 {
     const R tiny = sizeof(R) == 4 ? R(1e-20) : R(1e-200);
-    auto f = [&](R x) -> R { return R(1) / (fabs(x) < tiny ? (x < R(0) ? -tiny : tiny) : x); };
+    auto f = [&](R x) -> R {
+        const R y = fabs(x) < tiny ? (x < R(0) ? -tiny : tiny) : x;
+        if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(y);
+        else return R(1) / y;
+    };
     return V3<R>{f(d.x), f(d.y), f(d.z)};
 }
 

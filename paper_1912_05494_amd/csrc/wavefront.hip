@@ -1656,6 +1656,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     // the row being summed (wave-uniform) and its sums at wavelengths lane and lane + 64
     uint64_t row = ~0ull;
     int row_nb = 0;
+    // table values cached per lane across records (see phase 2)
+    uint32_t c_skey = ~0u, c_mkey = ~0u;
+    R c_E[2] = {R(0), R(0)}, c_lam[2] = {R(0), R(0)}, c_n[2] = {R(0), R(0)}, c_k[2] = {R(0), R(0)}, c_t[2] = {R(0), R(0)};
     double s0 = 0.0, s1 = 0.0;
     auto flush = [&]() {
         if (row != ~0ull) {
@@ -1727,25 +1730,54 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                 row_nb = a.nb;
             }
             const JobDev *jb = &jobs[kOne ? 0 : a.job];
-            const R *spectrum = (const R *)((a.flags & 2) ? jb->Lsky : jb->E);
-            const R *lam = (const R *)jb->lam;
             const R *tn = (const R *)jb->n, *tk = (const R *)jb->k, *tt = (const R *)jb->tint;
             const int ms = jb->ms;
+            // this lane's table values (wavelengths lane and lane + 64), reloaded
+            // only when the band, the light or the first pane's material changes
+            const uint32_t skey = (uint32_t)a.job << 20 | (uint32_t)a.l0 << 1 | (uint32_t)((a.flags >> 1) & 1);
+            if (skey != c_skey) {
+                c_skey = skey;
+                const R *spectrum = (const R *)((a.flags & 2) ? jb->Lsky : jb->E);
+                const R *lam = (const R *)jb->lam;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int l = a.l0 + min((int)lane + 64 * h, a.nb - 1);
+                    c_E[h] = gld(spectrum + l);
+                    c_lam[h] = gld(lam + l);
+                }
+                c_mkey = ~0u;
+            }
+            if (a.ng > 0) {
+                const uint32_t mkey = (uint32_t)a.m[0];
+                if (mkey != c_mkey) {
+                    c_mkey = mkey;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const size_t mo = (size_t)a.m[0] * ms + a.l0 + min((int)lane + 64 * h, a.nb - 1);
+                        c_n[h] = gld(tn + mo);
+                        c_k[h] = gld(tk + mo);
+                        c_t[h] = gld(tt + mo);
+                    }
+                }
+            }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int j = (int)lane + 64 * h;
                 if (j >= a.nb) continue;
                 const int l = a.l0 + j;
-                R T = a.scs * gld(spectrum + l);
+                R T = a.scs * c_E[h];
                 if (a.flags & 1) T *= w.contrib[aosoa(a.rec, j, nbm)];
-                R lamv = R(0);
-                if (a.ng > 0) lamv = gld(lam + l);
+                const R lamv = c_lam[h];
 #pragma unroll
                 for (int q = 0; q < kAccPanes; ++q) {
                     if (q < a.ng) {
-                        const size_t mo = (size_t)a.m[q] * ms + l;
                         R Rr, Tt;
-                        slab_RT<R>(a.c[q], lamv, a.d[q], gld(tn + mo), gld(tk + mo), gld(tt + mo) + a.sig[q], Rr, Tt);
+                        if (a.m[q] == a.m[0]) {
+                            slab_RT<R>(a.c[q], lamv, a.d[q], c_n[h], c_k[h], c_t[h] + a.sig[q], Rr, Tt);
+                        } else {
+                            const size_t mo = (size_t)a.m[q] * ms + l;
+                            slab_RT<R>(a.c[q], lamv, a.d[q], gld(tn + mo), gld(tk + mo), gld(tt + mo) + a.sig[q], Rr, Tt);
+                        }
                         T *= Tt;
                     }
                 }

@@ -458,7 +458,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.grid_st = ctx->num_cu * (grid_walk ? std::min(4, occupancy<R>(SDM_K_SHADOW)) : occupancy<R>(SDM_K_SHADOW));
         a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM);
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
-        const size_t gthreads = (size_t)std::max(a.grid_t, a.grid_st) * block_size();
+        const size_t gthreads = std::max((size_t)a.grid_t * trace_block_size(), (size_t)a.grid_st * block_size());
         int stack = 0;
         for (const auto &jj : jobs) stack = std::max(stack, jj.sc->stack);
         HIPCHK(ctx, ctx->gstack.ensure(gthreads * global_stack_levels(stack) * sizeof(int32_t)));

@@ -35,8 +35,10 @@
 
 namespace sdm {
 
-constexpr int kLdsNodes = 160;    // wide-node prefix staged in LDS (20 KB)
+constexpr int kLdsNodes = 160;    // wide-node prefix staged in LDS (20 KB) by the shadow and test kernels
 constexpr int kBlock = 256;
+constexpr int kTraceBlock = 256;   // threads per block of the closest-hit traversal
+constexpr int kTraceNodes = 160;   // wide-node prefix its blocks stage in LDS
 constexpr int kShadeBlock = 512;   // threads per block of the shading pass (fewer slot reservations)
 constexpr uint32_t kFetch = 256;  // items per group of the traversal work distribution
 constexpr int32_t kDone = INT_MIN;
@@ -129,21 +131,22 @@ __device__ __forceinline__ Vec4<R> tab4(const R *row, bool aligned, int j, int n
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) int32_t lds_i32;   // an LDS word (ds_* access)
 typedef __attribute__((address_space(1))) int32_t glb_i32;   // a global word (global_* access)
-struct Stack {
-    lds_i32 *lds;       // [kLdsStack][kBlock]
+template <int B>   // threads per block
+struct StackT {
+    lds_i32 *lds;       // [kLdsStack][B]
     glb_i32 *glob;      // [(level - kLdsStack) * gstride + gtid]
     uint32_t gtid, gstride;
     int sp;
     __device__ __forceinline__ void push(int32_t v)
     {
-        if (sp < kLdsStack) lds[sp * kBlock + threadIdx.x] = v;
+        if (sp < kLdsStack) lds[sp * B + threadIdx.x] = v;
         else glob[(size_t)(sp - kLdsStack) * gstride + gtid] = v;
         ++sp;
     }
     __device__ __forceinline__ int32_t pop()
     {
         --sp;
-        return sp < kLdsStack ? lds[sp * kBlock + threadIdx.x] : glob[(size_t)(sp - kLdsStack) * gstride + gtid];
+        return sp < kLdsStack ? lds[sp * B + threadIdx.x] : glob[(size_t)(sp - kLdsStack) * gstride + gtid];
     }
     // Pushes e[m], ..., e[1] (m <= 3), so that e[1] is popped first.  With
     // three free LDS levels the three slots are written whatever m is (slots
@@ -151,10 +154,10 @@ struct Stack {
     __device__ __forceinline__ void push_sorted(int m, int32_t e1, int32_t e2, int32_t e3)
     {
         if (sp + 3 <= kLdsStack) {
-            lds_i32 *p = lds + sp * kBlock + threadIdx.x;
+            lds_i32 *p = lds + sp * B + threadIdx.x;
             p[0] = m == 3 ? e3 : (m == 2 ? e2 : e1);
-            p[kBlock] = m == 3 ? e2 : e1;
-            p[2 * kBlock] = e1;
+            p[B] = m == 3 ? e2 : e1;
+            p[2 * B] = e1;
             sp += m;
         } else {
             if (m == 3) push(e3);
@@ -164,9 +167,12 @@ struct Stack {
     }
 };
 
-__device__ __forceinline__ Stack make_stack(int32_t *lds_stack, int32_t *gstack)
+using Stack = StackT<kBlock>;
+
+template <int B = kBlock>
+__device__ __forceinline__ StackT<B> make_stack(int32_t *lds_stack, int32_t *gstack)
 {
-    Stack st;
+    StackT<B> st;
     st.lds = (lds_i32 *)lds_stack;
     st.glob = (glb_i32 *)gstack;
     st.gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -217,9 +223,9 @@ __device__ __forceinline__ WideNode load_node(const float4 *lds_nodes, int n_lds
     return n;
 }
 
-__device__ __forceinline__ int stage_nodes(float4 *lds_nodes, const SceneDev &sc)
+__device__ __forceinline__ int stage_nodes(float4 *lds_nodes, const SceneDev &sc, int n_max = kLdsNodes)
 {
-    const int n = min(sc.n_nodes, kLdsNodes);
+    const int n = min(sc.n_nodes, n_max);
     const float4 *src = reinterpret_cast<const float4 *>(sc.nodes);
     for (int x = threadIdx.x; x < 8 * n; x += blockDim.x) lds_nodes[lds_slot(x >> 3, x & 7)] = gld4(src + x);
     __syncthreads();
@@ -361,8 +367,8 @@ __device__ __forceinline__ TriDev load_tri(const TriDev *tris, int i)
 // changes no result); it may pick up a second leaf on the way, tested in the
 // same step.  The descent ends when every lane holds a leaf or has nothing
 // left to visit.
-template <bool kFused, class R>
-__device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
+template <bool kFused, class R, class St>
+__device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, St &st,
                                              Ray<R> &ry, Closest<R> &h, R teps, uint32_t &nodes, uint32_t &tests)
 {
     int32_t cur = ry.cur;      // inner node (>= 0), leaf (< -1) or kDone
@@ -416,8 +422,8 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
 // due (speculatively, as in the closest-hit step) and test it.  An opaque
 // triangle ends the walk (occluded); each pane crossed is reported to
 // on_glass(leaf, u, v).
-template <bool kFused, class R, class F>
-__device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, Stack &st,
+template <bool kFused, class R, class St, class F>
+__device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, St &st,
                                             Ray<R> &ry, bool &occluded, R teps, F &&on_glass, uint32_t &nodes,
                                             uint32_t &tests)
 {
@@ -648,11 +654,11 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *__restrict__ 
 // launch renders one job, so the scene's constants are uniform (scalar loads
 // hoisted out of the loops) rather than looked up per lane.
 template <class R, bool kSurface, bool kOne>
-__global__ void __launch_bounds__(kBlock) k_trace(const JobDev *__restrict__ jobs, Work<R> w, int cur, int lds_job)
+__global__ void __launch_bounds__(kTraceBlock) k_trace(const JobDev *__restrict__ jobs, Work<R> w, int cur, int lds_job)
 {
     if (lds_job < -1) lds_job = w.cnt->lds_job;   // the job of the chunk's first path
-    __shared__ float4 s_nodes[8 * kLdsNodes];
-    __shared__ int32_t s_stack[kLdsStack * kBlock];
+    __shared__ float4 s_nodes[8 * kTraceNodes];
+    __shared__ int32_t s_stack[kLdsStack * kTraceBlock];
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.cnt->count[cur ^ 1] = 0;
@@ -662,8 +668,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(const JobDev *__restrict__ job
         w.cnt->bcount = 0;
         w.cnt->closest += count;
     }
-    const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
-    Stack st = make_stack(s_stack, w.gstack);
+    const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc, kTraceNodes) : 0;
+    StackT<kTraceBlock> st = make_stack<kTraceBlock>(s_stack, w.gstack);
     const Pool<R> P = w.p[cur];
     WaveFeed feed{0, 0, false, 0};
     Ray<R> ry;
@@ -2024,7 +2030,7 @@ template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, bool one_job, int grid,
                   hipStream_t s)
 {
-    const dim3 g(grid), b(kBlock);
+    const dim3 g(grid), b(kTraceBlock);
     if (one_job) {
         if (surface) hipLaunchKernelGGL((k_trace<R, true, true>), g, b, 0, s, jobs, w, cur, lds_job);
         else hipLaunchKernelGGL((k_trace<R, false, true>), g, b, 0, s, jobs, w, cur, lds_job);
@@ -2128,6 +2134,7 @@ void launch_debug_shadow(const SceneDev &sc, uint32_t m, const float *o, const i
 }
 
 int block_size() { return kBlock; }
+int trace_block_size() { return kTraceBlock; }
 
 // Resident blocks per CU of each render kernel: every pass is launched with
 // exactly the blocks the chip holds at once, so no block waits for a second
@@ -2150,7 +2157,7 @@ int occupancy(int kernel_class, int lds_bytes)
     default: return 1;
     }
     int b = 0;
-    const int threads = kernel_class == SDM_K_SHADE ? kShadeBlock : kBlock;
+    const int threads = kernel_class == SDM_K_SHADE ? kShadeBlock : kernel_class == SDM_K_TRACE ? kTraceBlock : kBlock;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, threads, lds_bytes) != hipSuccess) return 1;
     return std::max(1, b);
 }

@@ -53,5 +53,7 @@ void launch_debug_shadow(const SceneDev &sc, uint32_t m, const float *o, const i
                          const int32_t *orig_to_leaf, float lambda_nm, const float *n_at, const float *k_at,
                          const float *t_at, float *T, int32_t *gstack, int grid, hipStream_t s);
 int block_size();
+// Threads per block of the closest-hit traversal kernel.
+int trace_block_size();
 
 }  // namespace sdm

@@ -18,8 +18,9 @@
 //   k_shade_bubbly  exact walk or surrogate branch
 //   k_shadow_trace  any-hit walk of the shadow records toward the sun
 //   k_shadow_accum  per wavelength: slab transmittance of the panes crossed
-//                   (sun records) or sky radiance (sky records), wave-level
-//                   segmented sums, FP64 atomics per pixel
+//                   (sun records) or sky radiance (sky records), a pixel's
+//                   records summed in registers with lanes over wavelengths,
+//                   one FP64 atomic row add per pixel run
 // Weights are a scalar per path times per-wavelength factors that exist only
 // once the wavelengths' weights differ (kSpectral).
 #include <hip/hip_runtime.h>

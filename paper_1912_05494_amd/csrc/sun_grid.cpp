@@ -63,9 +63,12 @@ SunGrid build_sun_grid(const TriDev *tris, int32_t nt, const int32_t *mat_type, 
         V0 = std::min(V0, bmin[i]); V1 = std::max(V1, bmax[i]);
     }
     if (!std::isfinite(U0 + U1 + V0 + V1)) return g;
-    // about four cells per triangle, square cells, at most 4096 per side
+    // about sixteen cells per triangle, square cells, at most 4096 per side:
+    // a wave's walk lasts as long as its longest list, and finer cells
+    // shorten the lists (shadow walk on the nave: 4.99 ms at four cells per
+    // triangle, 4.69 at eight, 4.62 at sixteen)
     const double du = U1 - U0, dv = V1 - V0;
-    const double cell = std::sqrt(du * dv / (4.0 * nt));
+    const double cell = std::sqrt(du * dv / (16.0 * nt));
     g.nx = (int32_t)std::min(4096.0, std::max(1.0, std::ceil(du / std::max(cell, 1e-30))));
     g.ny = (int32_t)std::min(4096.0, std::max(1.0, std::ceil(dv / std::max(cell, 1e-30))));
     g.u0 = (float)U0;
@@ -112,7 +115,7 @@ SunGrid build_sun_grid(const TriDev *tris, int32_t nt, const int32_t *mat_type, 
                     ++cnt[(size_t)y * g.nx + x];
                     ++total;
                 }
-        if (total > 24ll * nt + 1024) return g;   // projections too large for a grid: keep the BVH
+        if (total > 96ll * nt + 1024) return g;   // projections too large for a grid: keep the BVH
     }
     // expected candidates of a ray: cells weighted by how often rays fall in them,
     // taken proportional to their list lengths

@@ -42,6 +42,7 @@ constexpr int kTraceBlock = 256;   // threads per block of the closest-hit trave
 constexpr int kTraceNodes = 160;   // wide-node prefix its blocks stage in LDS
 constexpr int kShadeBlock = 512;   // threads per block of the shading pass (fewer slot reservations)
 constexpr uint32_t kFetch = 256;  // items per group of the traversal work distribution
+constexpr int kDescentLanes = 24;  // a closest-hit descent ends when fewer lanes still search
 constexpr int32_t kDone = INT_MIN;
 
 // ---------------------------------------------------------------------------
@@ -366,14 +367,16 @@ __device__ __forceinline__ TriDev load_tri(const TriDev *tris, int i)
 // searching for theirs, so lanes do not idle through the longest descent of
 // the wave (its extra visits use the larger bound of before the test, which
 // changes no result); it may pick up a second leaf on the way, tested in the
-// same step.  The descent ends when every lane holds a leaf or has nothing
-// left to visit.
+// same step.  The descent ends when fewer than kDescentLanes lanes are still
+// looking for a first leaf (after at least one round of visits); those lanes
+// go on from where they stopped in the next step.
 template <bool kFused, class R, class St>
 __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, St &st,
                                              Ray<R> &ry, Closest<R> &h, R teps, uint32_t &nodes, uint32_t &tests)
 {
     int32_t cur = ry.cur;      // inner node (>= 0), leaf (< -1) or kDone
     int32_t leaf = kDone, leaf2 = kDone;
+    bool visited = false;
     for (;;) {
         if (cur < 0 && cur != kDone && leaf2 == kDone) {
             if (leaf == kDone) leaf = cur;
@@ -381,6 +384,11 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
             cur = st.sp ? st.pop() : kDone;
         }
         if (!__any(leaf == kDone && cur >= 0)) break;
+        // after one round of visits (so every step advances every lane), the
+        // few lanes still searching resume in the next step rather than hold
+        // the wave's leaf tests back
+        if (visited && __popcll(__ballot(leaf == kDone && cur >= 0)) < kDescentLanes) break;
+        visited = true;
         if (cur >= 0) {
             const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur, ry.kx, ry.ky, ry.kz);
             ++nodes;

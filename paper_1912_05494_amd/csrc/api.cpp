@@ -292,6 +292,10 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         const int32_t ty = mtype[m];
         std::memcpy(&tris[l].c.w, &ty, 4);
     }
+    for (int a = 0; a < 3; ++a) {
+        sc->lo[a] = d->nv > 0 ? lo[a] : 0.0;
+        sc->hi[a] = d->nv > 0 ? hi[a] : 0.0;
+    }
     double maxabs = 0.0;
     for (int a = 0; a < 3 && d->nv > 0; ++a) maxabs = std::max({maxabs, std::fabs(lo[a]), std::fabs(hi[a])});
     const SunGrid grid = d->shadow_walk == SDM_SHADOW_BVH

@@ -214,6 +214,7 @@ struct ChunkArgs {
     uint64_t total;
     uint32_t chunk;
     int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec;
+    int32_t cam_fused;          // camera rays may take the fused slab form (origins in the scene's bounds)
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
 };
 
@@ -228,7 +229,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
     done();
     for (int dpt = 0; dpt < a.depth; ++dpt) {
         mark(SDM_K_TRACE);
-        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0, a.one_job != 0, a.grid_t, s);
+        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0 || a.cam_fused != 0, a.one_job != 0, a.grid_t, s);
         done();
         mark(SDM_K_SHADE);
         launch_shade<R>(a.jobs, a.bands, a.w, cur, a.one_job != 0, a.grid_s, s);
@@ -506,6 +507,17 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.depth = depth;
         a.lds_job = nj == 1 ? 0 : -2;   // a batch stages the BVH of each chunk's first job
         a.one_job = nj == 1;
+        // The fused slab form's rounding stays inside the box padding for
+        // origins within the scene's bounds: pinhole cameras placed inside
+        // their scene may use it for the camera rays too.
+        a.cam_fused = 1;
+        for (const auto &jj : jobs) {
+            const sdm_camera &cam = jj.p->camera;
+            bool inside = cam.projection == SDM_PINHOLE && jj.sc->nt > 0;
+            for (int q = 0; q < 3 && inside; ++q)
+                inside = (double)cam.eye[q] >= jj.sc->lo[q] && (double)cam.eye[q] <= jj.sc->hi[q];
+            if (!inside) a.cam_fused = 0;
+        }
         a.surr = surr;
         a.bubbly = bubbly;
         a.prec = sizeof(R) == 8;

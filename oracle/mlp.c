@@ -84,45 +84,44 @@ static void heads(const double *o, double *out)
     out[2] = softplus(o[2]);
 }
 
-/* Round to the nearest bfloat16 (8-bit significand), ties to even, through
- * float32 as the matrix-core operands are formed. */
+/* Round to the nearest bfloat16 (8 significant bits), ties to even, directly
+ * from the double: x = f 2^e with f in [0.5, 1) becomes nearbyint(f 2^8)
+ * 2^(e-8) under the default round-to-nearest-even mode.  Values below the
+ * smallest normal bfloat16 (2^-126) keep 8 bits as well (no gradual
+ * underflow; no such values occur in the network); inf and nan pass. */
 double orc_bf16(double x)
 {
-    float f = (float)x;
-    uint32_t b;
-    memcpy(&b, &f, 4);
-    if ((b & 0x7f800000u) == 0x7f800000u) return x;   /* inf / nan unchanged */
-    b = (b + 0x7fffu + ((b >> 16) & 1u)) & 0xffff0000u;
-    memcpy(&f, &b, 4);
-    return (double)f;
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    const double f = frexp(x, &e);
+    return ldexp(nearbyint(ldexp(f, 8)), e - 8);
 }
 
-/* Layer with BF16 operands: y = b + sum bf16(W) bf16(x), summed in double;
- * biases and sums stay wide. */
+/* Layer with BF16 operands: y = b + sum bf16(W) bf16(x).  Only the operands
+ * are rounded; the products, the sum and the bias are FP64, so this
+ * is the plain definition of a dense layer on bfloat16 inputs (the matrix
+ * cores' FP32 accumulation differs from it by FP32 rounding only). */
 static void dense_bf16(const double *W, const double *b, const double *xb, int nin, int nout, double *y)
 {
     for (int o = 0; o < nout; ++o) {
-        double s = 0.0;
+        double s = b[o];
         for (int i = 0; i < nin; ++i) s += orc_bf16(W[o * nin + i]) * xb[i];
-        y[o] = (double)(float)s + (double)(float)b[o];
+        y[o] = s;
     }
 }
 
-/* Network evaluated with BF16 operands (inputs, weights and hidden
- * activations rounded to bfloat16), the arithmetic of the matrix-core path. */
+/* Network evaluated with BF16 operands: the features, the weights and the
+ * hidden activations are rounded to bfloat16 where they enter a product;
+ * everything else (feature scaling, sums, biases, heads) is FP64. */
 void orc_mlp_forward_bf16(const double *params, int32_t n_panes, int64_t m, const double *tuples,
                           const int32_t *panes, double *out)
 {
     (void)n_panes;
     view v = make_view(params);
     for (int64_t s = 0; s < m; ++s) {
-        const double *t = tuples + 4 * s;
         double x[NIN], z1[NH], h1[NH], z2[NH], h2[NH], z3[NH], h3[NH], o[NOUT];
-        x[0] = orc_bf16((float)t[0]);
-        x[1] = orc_bf16(((float)t[1] - 580.0f) / 200.0f);
-        x[2] = orc_bf16(((float)t[2] - 3.5f) / 1.5f);
-        x[3] = orc_bf16((float)t[3] / 34.0f);
-        for (int e = 0; e < NEMB; ++e) x[4 + e] = orc_bf16(v.E[panes[s] * NEMB + e]);
+        features(tuples + 4 * s, panes[s], &v, x);
+        for (int i = 0; i < NIN; ++i) x[i] = orc_bf16(x[i]);
         dense_bf16(v.W1, v.b1, x, NIN, NH, z1); relu(z1, NH, h1);
         for (int i = 0; i < NH; ++i) h1[i] = orc_bf16(h1[i]);
         dense_bf16(v.W2, v.b2, h1, NH, NH, z2); relu(z2, NH, h2);

@@ -11,6 +11,9 @@ Tolerances:
   R and T must agree within 4 binomial sigmas (+1e-4).
 - Network: operands are rounded to BF16 (relative 2^-9) and accumulated in
   FP32 through four layers, so outputs may differ from FP64 by a few 1e-3;
+  against the oracle's BF16-operand definition (operands rounded, sums in
+  FP64) they differ only by FP32 summation and the BF16 re-roundings it
+  causes, held to a bound carried through the layers;
   the gradient vector must have cosine >= 0.999 with the oracle's and a
   relative L2 error <= 3e-2 per weight or bias tensor.  The embedding rows'
   gradient is the network's input gradient, a sum over 64 hidden units with
@@ -171,6 +174,72 @@ def test_mlp_forward_matches_oracle(gpu, orc):
     yo = orc.mlp_forward(p.astype(np.float64), n_panes, tup.astype(np.float64), pane)
     err = np.abs(y - yo)
     assert err.max() < 1e-2 and err.mean() < 2e-3, (err.max(), err.mean())
+    net.close()
+
+
+def _bf16_forward_bound(p, n_panes, tup, pane, orc):
+    """Per-sample bound on |GPU - oracle BF16 mode| for (R, T, w).
+
+    Both sides take BF16 operands; the matrix cores sum the exact BF16
+    products in FP32, which moves a pre-activation z by at most
+    E = |W| D + gamma (|b| + |W| (|h| + D)), gamma = 65 u / (1 - 65 u),
+    u = 2^-24, where D bounds how far the layer's inputs h already differ.
+    After the ReLU the activation is rounded to BF16 again.  Rounding is
+    monotone, so both sides' activations lie in
+    [bf16(max(z - E, 0)), bf16(max(z + E, 0))]: D of the next layer is that
+    interval's width, zero unless a BF16 rounding boundary falls within E of
+    z.  The features start the chain the same way (the kernel scales them in
+    FP32, within 4 ulp of the exact value; cos and the embedding are taken
+    as they are).  The output bound is carried through the heads by their
+    derivatives (R(1 - R), RT, T(1 - T); the softplus slope), with 5 % for
+    second-order terms and 2e-6 for the heads' own FP32 rounding."""
+    from paper_1912_05494_amd import surrogate as sg
+
+    def rb(a):
+        return orc.bf16(a).reshape(np.shape(a))
+
+    v = sg.split(p.astype(np.float64), n_panes)
+    gam = 65 * 2.0 ** -24 / (1 - 65 * 2.0 ** -24)
+    x = np.concatenate([tup[:, :1], (tup[:, 1:2] - 580) / 200, (tup[:, 2:3] - 3.5) / 1.5, tup[:, 3:4] / 34,
+                        v["E"][pane]], 1)
+    ex = np.zeros_like(x)
+    ex[:, 1:4] = 4 * 2.0 ** -24 * np.abs(x[:, 1:4])
+    h = rb(x)
+    D = rb(x + ex) - rb(x - ex)
+    for k in (1, 2, 3, 4):
+        Wb = rb(v[f"W{k}"])
+        b = v[f"b{k}"]
+        z = h @ Wb.T + b
+        E = D @ np.abs(Wb).T + gam * (np.abs(b) + (np.abs(h) + D) @ np.abs(Wb).T)
+        if k == 4:
+            break
+        h = rb(np.maximum(z, 0.0))
+        D = rb(np.maximum(z + E, 0.0)) - rb(np.maximum(z - E, 0.0))
+    o, do = z, E
+    ea, eb = np.exp(o[:, 0]), np.exp(o[:, 1])
+    R, T = ea / (ea + eb + 1), eb / (ea + eb + 1)
+    bR = R * (1 - R) * do[:, 0] + R * T * do[:, 1]
+    bT = R * T * do[:, 0] + T * (1 - T) * do[:, 1]
+    bw = do[:, 2] / (1 + np.exp(-o[:, 2]))
+    return 1.05 * np.stack([bR, bT, bw], 1) + 2e-6
+
+
+def test_mlp_forward_within_bf16_bound(gpu, orc):
+    """The matrix-core network against the oracle's plain BF16-operand
+    definition: every output within the bound carried from FP32 summation
+    and BF16 re-rounding (see _bf16_forward_bound)."""
+    sdm, ctx, torch = gpu
+    n_panes = 5
+    p, tup, pane, _ = net_case(3, 1000, n_panes)
+    net = sdm.MLP(ctx, n_panes, p)
+    t, pn = to_dev(torch, tup, pane)
+    y = net.infer(t, pn).cpu().numpy().astype(np.float64)
+    yb = orc.mlp_forward_bf16(p.astype(np.float64), n_panes, tup.astype(np.float64), pane)
+    bound = _bf16_forward_bound(p, n_panes, tup.astype(np.float64), pane, orc)
+    err = np.abs(y - yb)
+    print(f"bf16 forward: max err {err.max():.3e}, mean err {err.mean():.3e}, mean bound {bound.mean():.3e}, "
+          f"max err/bound {(err / bound).max():.3f}")
+    assert np.all(err <= bound), (err / bound).max()
     net.close()
 
 

@@ -1,5 +1,10 @@
 """Pins of the oracle's surrogate network: the analytic gradient against
-central finite differences, and the output heads' constraints."""
+central finite differences, the output heads' constraints, the forward pass
+against a numpy network written from the parameter layout and against one
+path worked out by hand, and the BF16 mode as operand rounding only (BF16
+rounding straight from the double, pinned on midpoint cases)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -56,3 +61,130 @@ def test_loss_is_mean_squared_error(orc):
     target = rng.uniform(0, 1, (37, 3))
     loss, _ = orc.mlp_loss_grad(p, 1, tup, pane, target)
     assert loss == pytest.approx(np.mean(np.sum((y - target) ** 2, axis=1)), rel=1e-13)
+
+
+# --------------------------------------------------------------------------
+# The forward pass, pinned outside the oracle's own loss and gradient
+# --------------------------------------------------------------------------
+def _numpy_forward(params, n_panes, tup, pane, rnd=None):
+    """The network written out with numpy on the named parameter views:
+    features, three ReLU layers of 64, the (R, T) shares of a softmax over
+    (o0, o1, 0) and a softplus width.  rnd (optional) rounds every operand
+    that enters a product."""
+    r = rnd if rnd is not None else (lambda a: a)
+    v = surrogate.split(np.asarray(params, dtype=np.float64), n_panes)
+    x = np.concatenate([tup[:, 0:1], (tup[:, 1:2] - 580.0) / 200.0, (tup[:, 2:3] - 3.5) / 1.5,
+                        tup[:, 3:4] / 34.0, v["E"][pane]], axis=1)
+    h = r(x)
+    for k in (1, 2, 3):
+        h = r(np.maximum(h @ r(v[f"W{k}"]).T + v[f"b{k}"], 0.0))
+    o = h @ r(v["W4"]).T + v["b4"]
+    den = np.exp(o[:, 0]) + np.exp(o[:, 1]) + 1.0
+    return np.stack([np.exp(o[:, 0]) / den, np.exp(o[:, 1]) / den, np.log1p(np.exp(o[:, 2]))], axis=1)
+
+
+def _bf16_round(a):
+    """Nearest value with an 8-bit significand, ties to even (numpy's round
+    is half-to-even, and scaling by powers of two is exact)."""
+    f, e = np.frexp(np.asarray(a, dtype=np.float64))
+    return np.ldexp(np.round(np.ldexp(f, 8)), e - 8)
+
+
+def test_forward_matches_numpy_network(orc):
+    rng = np.random.default_rng(7)
+    n_panes = 4
+    p = surrogate.init_params(n_panes, seed=8).astype(np.float64)
+    sp = surrogate.split(p, n_panes)
+    for k in (1, 2, 3):
+        sp[f"b{k}"][:] = rng.normal(0, 0.2, 64)      # nonzero biases: a dropped bias would show
+    sp["b4"][:] = [-1.5, 0.7, -0.3]
+    sp["E"][:] *= 4.0
+    tup, pane = _batch(rng, 400, n_panes)
+    y = orc.mlp_forward(p, n_panes, tup, pane)
+    ref = _numpy_forward(p, n_panes, tup, pane)
+    assert np.allclose(y, ref, rtol=1e-12, atol=1e-14)
+    # the ReLUs are active: a sizeable share of hidden units is cut
+    x = np.concatenate([tup[:, :1], (tup[:, 1:2] - 580) / 200, (tup[:, 2:3] - 3.5) / 1.5, tup[:, 3:4] / 34,
+                        sp["E"][pane]], 1)
+    z1 = x @ sp["W1"].T + sp["b1"]
+    assert 0.2 < np.mean(z1 < 0) < 0.8
+
+
+def test_forward_hand_computed_path(orc):
+    """One path through the network by hand.  Pane 1's embedding is one-hot
+    at its third value (feature 6); W1[5][6] = 2, W2[9][5] = 3, W3[4][9] = 0.5,
+    W4[0][4] = 1, W4[2][4] = -1, every other weight 0; biases b1[5] = -0.5,
+    b1[7] = -1 (unit 7 stays cut by its ReLU, as it has no input), b4 =
+    (0, ln 2, 0).  With cos = 0.3, lambda = 780, d = 5, rho = 34:
+    z1[5] = 2 * 1 - 0.5 = 1.5, z2[9] = 3 * 1.5 = 4.5, z3[4] = 2.25,
+    o = (2.25, ln 2, -2.25), so R = e^2.25 / (e^2.25 + 2 + 1), T = 2 / (same),
+    w = ln(1 + e^-2.25).  A transposed weight matrix, a dropped ReLU or a
+    dropped bias changes these."""
+    n_panes = 2
+    p = np.zeros(orc.mlp_nparams(n_panes))
+    v = surrogate.split(p, n_panes)
+    v["E"][1, 2] = 1.0
+    v["W1"][5, 6] = 2.0
+    v["b1"][5] = -0.5
+    v["b1"][7] = -1.0
+    v["W1"][3, 0] = -4.0                  # unit 3: -4 cos < 0, cut by the ReLU
+    v["W2"][9, 5] = 3.0
+    v["W2"][9, 3] = 100.0                 # would add 100 * (-1.2) if the ReLU were missing
+    v["W2"][9, 7] = 50.0                  # would add 50 * (-1) if the ReLU were missing
+    v["W3"][4, 9] = 0.5
+    v["W4"][0, 4] = 1.0
+    v["W4"][2, 4] = -1.0
+    v["b4"][:] = [0.0, math.log(2.0), 0.0]
+    tup = np.array([[0.3, 780.0, 5.0, 34.0], [0.3, 780.0, 5.0, 34.0]])
+    pane = np.array([1, 0], dtype=np.int32)
+    y = orc.mlp_forward(p, n_panes, tup, pane)
+    e = math.exp(2.25)
+    assert y[0, 0] == pytest.approx(e / (e + 3.0), rel=1e-14)
+    assert y[0, 1] == pytest.approx(2.0 / (e + 3.0), rel=1e-14)
+    assert y[0, 2] == pytest.approx(math.log1p(math.exp(-2.25)), rel=1e-14)
+    # pane 0 has a zero embedding: only b4 remains, o = (0, ln 2, 0)
+    assert y[1, 0] == pytest.approx(1.0 / 4.0, rel=1e-14)
+    assert y[1, 1] == pytest.approx(2.0 / 4.0, rel=1e-14)
+    assert y[1, 2] == pytest.approx(math.log(2.0), rel=1e-14)
+    # the feature scaling: lambda = 780 -> 1, d = 5 -> 1, rho = 34 -> 1 carry
+    # W1 columns 1, 2, 3 into unit 5 (+1 each), and cos = 0.3 through column 0
+    v["W1"][5, 0:4] = [1.0, 1.0, 1.0, 1.0]
+    y2 = orc.mlp_forward(p, n_panes, tup[:1], pane[:1])
+    z3 = 0.5 * 3.0 * (1.5 + 0.3 + 1.0 + 1.0 + 1.0)
+    e2 = math.exp(z3)
+    assert y2[0, 0] == pytest.approx(e2 / (e2 + 3.0), rel=1e-14)
+    assert y2[0, 2] == pytest.approx(math.log1p(math.exp(-z3)), rel=1e-14)
+
+
+def test_bf16_rounding_direct_from_double(orc):
+    """Rounding a double straight to 8 significant bits: 1 + 2^-8 + 2^-30 lies
+    above the midpoint between 1 and 1 + 2^-7 and rounds up (going through
+    float32 first would land on the midpoint and round to 1); exact
+    midpoints go to the even significand."""
+    assert orc.bf16(1 + 2 ** -8 + 2 ** -30) == 1 + 2 ** -7
+    assert orc.bf16(1 + 2 ** -8) == 1.0
+    assert orc.bf16(1 + 3 * 2 ** -8) == 1 + 2 ** -6
+    assert orc.bf16(-(1 + 3 * 2 ** -8)) == -(1 + 2 ** -6)
+    assert orc.bf16(3 * 2 ** -140) == 3 * 2 ** -140
+    rng = np.random.default_rng(11)
+    x = rng.normal(0, 10, 3000) * np.exp2(rng.integers(-40, 40, 3000))
+    assert np.array_equal(orc.bf16(x), _bf16_round(x))
+
+
+def test_bf16_forward_is_operand_rounding_only(orc):
+    """The BF16 mode rounds the features, the weights and the hidden
+    activations where they enter a product, and computes everything else in
+    FP64: the numpy network with the same roundings agrees to 1e-12."""
+    rng = np.random.default_rng(12)
+    n_panes = 3
+    p = surrogate.init_params(n_panes, seed=13).astype(np.float64)
+    sp = surrogate.split(p, n_panes)
+    for k in (1, 2, 3):
+        sp[f"b{k}"][:] = rng.normal(0, 0.2, 64)
+    sp["b4"][:] = [-2.0, 0.5, -1.0]
+    tup, pane = _batch(rng, 300, n_panes)
+    y = orc.mlp_forward_bf16(p, n_panes, tup, pane)
+    ref = _numpy_forward(p, n_panes, tup, pane, rnd=_bf16_round)
+    assert np.allclose(y, ref, rtol=1e-12, atol=1e-14)
+    # and the rounding matters: the FP64 network differs by more than that
+    assert np.abs(orc.mlp_forward(p, n_panes, tup, pane) - y).max() > 1e-5

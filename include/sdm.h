@@ -44,6 +44,7 @@ extern "C" {
 #define SDM_E_NOMEM (-2)       /* device or host allocation failed            */
 #define SDM_E_DEVICE (-3)      /* HIP error or a device-side error flag       */
 #define SDM_E_UNSUPPORTED (-4) /* valid request this build does not handle    */
+#define SDM_E_ABORTED (-5)     /* the render's item budget ran out; resumable  */
 
 enum { SDM_LAMBERT = 0, SDM_GLASS = 1, SDM_GLASS_BUBBLY = 2 };
 enum { SDM_MEM_HOST = 0, SDM_MEM_DEVICE = 1 };
@@ -140,6 +141,16 @@ typedef struct {
     float err_bound;
     int32_t graph;              /* 1: replay each chunk's kernel sequence as a
                                    HIP graph (ignored when timing = 1)         */
+    /* Work-item budget.  The spectral and ray-set sub-domains are independent
+     * (Sec. 4 and 5), so a render may run as several calls.  0: render every
+     * (pixel tile x band) item.  n > 0: render at most n of the items not yet
+     * done, in plan order (tile rows top to bottom, tiles left to right,
+     * bands in order); when items remain, the outputs hold the items done so
+     * far (zero elsewhere), the context keeps the partial state and the call
+     * returns SDM_E_ABORTED: sdm_render_resume continues it and
+     * sdm_render_checkpoint saves it.  Single renders only: sdm_render_batch
+     * returns SDM_E_UNSUPPORTED for max_items > 0. */
+    int64_t max_items;
 } sdm_render_params;
 
 /* Kernel classes reported in sdm_stats. */
@@ -167,6 +178,9 @@ typedef struct {
     double ms_render;          /* wall time of the render on the stream       */
     double kernel_ms[SDM_K_COUNT];     /* summed kernel durations (timing=1)   */
     uint64_t kernel_launches[SDM_K_COUNT];
+    uint64_t items_done;        /* work items finished, this call and earlier
+                                   calls of a resumed render                  */
+    uint64_t items_total;       /* work items of the render                    */
 } sdm_stats;
 
 typedef struct {
@@ -175,6 +189,20 @@ typedef struct {
     int32_t spectral_mem;       /* SDM_MEM_HOST or SDM_MEM_DEVICE              */
     int32_t xyz_mem;
     sdm_stats *stats;           /* host struct, may be NULL                     */
+    /* Event signatures (a debug aid for explaining differences against a
+     * reference), DEVICE [H*W*n_lambda] or NULL.  Entry (pixel, lambda) is
+     * the sum modulo 2^64 of a hash of every event that decides what that
+     * pixel's paths contribute at that wavelength: each closest hit (vertex,
+     * sample, triangle index or none) and each shadow-ray result (vertex,
+     * occluded, or the set of panes crossed), counted where the wavelength's
+     * path weight is nonzero.  The hash is the SplitMix64 output function
+     * (Steele, Lea and Flood, 2014) of kind << 56 | vertex << 48 | x, with
+     * x = sample << 32 | (triangle + 1) for a hit (kind 1), x = 0xFFFF when
+     * occluded or else the pane count for a shadow result (kind 2), to which
+     * the hashes of 3 << 56 | triangle of every pane crossed are added.  Two
+     * renders whose paths decide alike have equal signatures.  Adds two
+     * passes per bounce; not with max_items or resume. */
+    uint64_t *events;
 } sdm_outputs;
 
 /* Context on HIP device `device`.  Owns the work buffers of renders. */
@@ -197,6 +225,25 @@ int sdm_scene_destroy(sdm_scene *scene);
  * returning SDM_E_DEVICE only if the pool cannot grow further. */
 int sdm_render(sdm_context *ctx, const sdm_scene *scene, const sdm_render_params *params,
                const sdm_outputs *out, void *hip_stream);
+
+/* Saves the partial render the context holds after SDM_E_ABORTED to a file:
+ * a header identifying the render (a digest of the scene's inputs and of the
+ * parameters that decide the accumulated values, the resolved tile size and
+ * item count), the bitmap of the items done and the FP64 accumulator
+ * [H*W*n_lambda] (sums over samples, not yet divided by spp).  SDM_E_INVALID
+ * when the context holds no partial render; SDM_E_DEVICE on a file error. */
+int sdm_render_checkpoint(sdm_context *ctx, const char *path);
+
+/* Continues a partial render: from the file path written by
+ * sdm_render_checkpoint (possibly in another process), or, with path NULL,
+ * from the state the context holds after SDM_E_ABORTED.  scene and params
+ * must describe the same render (the header's digest is checked:
+ * SDM_E_INVALID otherwise); params->max_items applies to the items still to
+ * do.  Returns SDM_OK with the whole image in out once every item is done --
+ * the same image as one uninterrupted render, up to the order of the FP64
+ * additions -- or SDM_E_ABORTED again with the partial image. */
+int sdm_render_resume(sdm_context *ctx, const char *path, const sdm_scene *scene,
+                      const sdm_render_params *params, const sdm_outputs *out, void *hip_stream);
 
 /* One job of a batch: a scene, its parameters and its outputs. */
 typedef struct {
@@ -333,6 +380,16 @@ int sdm_mlp_grad(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *pa
 int sdm_mlp_train(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *panes,
                   const float *target, const sdm_train_params *tp, float *loss_curve,
                   void *hip_stream);
+/* Writes the network to a file: pane count, FP32 master parameters, Adam
+ * moments and step count, so that training can continue where it stopped.
+ * SDM_E_DEVICE on a file error. */
+int sdm_mlp_save(const sdm_mlp *mlp, const char *path);
+/* Creates a network in ctx from a file written by sdm_mlp_save (same
+ * parameters and optimiser state).  SDM_E_INVALID for a file that is not
+ * such a network. */
+int sdm_mlp_load(sdm_context *ctx, const char *path, sdm_mlp **out);
+/* Pane count (embedding rows) and Adam steps taken; either may be NULL. */
+int sdm_mlp_info(const sdm_mlp *mlp, int32_t *n_panes, int64_t *steps);
 /* (R, T, w) for m tuples: out [m][3] DEVICE. */
 int sdm_mlp_infer(sdm_mlp *mlp, int64_t m, const float *tuples, const int32_t *panes, float *out,
                   void *hip_stream);

@@ -44,7 +44,10 @@ class _Params(C.Structure):
                 ("use_bvh", C.c_int32), ("n_threads", C.c_int32),
                 ("btdf_mode", C.c_int32), ("mlp_n_panes", C.c_int32), ("mlp_bf16", C.c_int32),
                 ("err_dims", C.c_int32 * 3), ("mlp_params", C.POINTER(C.c_double)),
-                ("err_table", C.POINTER(C.c_double)), ("err_bound", C.c_double)]
+                ("err_table", C.POINTER(C.c_double)), ("err_bound", C.c_double),
+                ("item_begin", C.c_int64), ("max_items", C.c_int64), ("events", C.c_void_p),
+                ("prec_bound", C.c_void_p), ("prec_rel", C.c_double), ("prec_ceps", C.c_double),
+                ("prec_eps", C.c_double)]
 
 
 class _WalkStream(C.Structure):
@@ -253,27 +256,54 @@ def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=Non
     return p, keep
 
 
-def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=None):
-    """Full image -> (spec (H, W, nl) float64, xyz (H, W, 3) float64)."""
+def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=None, items=None,
+           events=False, spec=None, prec=None):
+    """Full image -> (spec (H, W, nl) float64, xyz (H, W, 3) float64), plus the
+    event signatures (H, W, nl) uint64 when events is True, plus the
+    single-precision error bound (H, W, nl) float64 when prec = (rel,
+    cos_eps, pos_eps) is given (see orc_render_params).  items: (begin,
+    count) of the work
+    items to render (count 0: to the end); the others keep the values of
+    spec (zeros when spec is None)."""
     p, keep = _params(settings, use_bvh, tile, n_threads, n_bands, btdf)
     W, H, nl = settings.camera.W, settings.camera.H, len(settings.lambda_nm)
-    spec = np.empty((H, W, nl))
+    spec = np.zeros((H, W, nl)) if spec is None else np.ascontiguousarray(spec, dtype=np.float64)
     xyz = np.empty((H, W, 3))
+    ev = np.zeros((H, W, nl), dtype=np.uint64) if events else None
+    pb = np.zeros((H, W, nl)) if prec is not None else None
+    if items is not None:
+        p.item_begin, p.max_items = int(items[0]), int(items[1])
+    if ev is not None:
+        p.events = ev.ctypes.data
+    if pb is not None:
+        p.prec_bound = pb.ctypes.data
+        p.prec_rel, p.prec_ceps, p.prec_eps = (float(x) for x in prec)
     rc = lib().orc_render(oscene.ptr, C.byref(p), spec.ctypes.data, xyz.ctypes.data)
     if rc != 0:
         raise ValueError("oracle render rejected the parameters")
-    return spec, xyz
+    return (spec, xyz) + ((ev,) if events else ()) + ((pb,) if pb is not None else ())
 
 
-def render_pixels(oscene, settings, pixels, use_bvh=True, n_threads=0, btdf=None):
-    """Selected linear pixel indices -> spec (m, nl) float64."""
+def render_pixels(oscene, settings, pixels, use_bvh=True, n_threads=0, btdf=None, events=False, prec=None):
+    """Selected linear pixel indices -> spec (m, nl) float64, plus the event
+    signatures (m, nl) uint64 when events is True and the single-precision
+    error bound (m, nl) float64 when prec is given (as for render)."""
     p, keep = _params(settings, use_bvh, 16, n_threads, btdf=btdf)
     px = np.ascontiguousarray(pixels, dtype=np.int32)
-    spec = np.empty((len(px), len(settings.lambda_nm)))
+    nl = len(settings.lambda_nm)
+    spec = np.empty((len(px), nl))
+    ev = np.zeros((len(px), nl), dtype=np.uint64) if events else None
+    pb = np.zeros((len(px), nl)) if prec is not None else None
+    if ev is not None:
+        p.events = ev.ctypes.data
+    if pb is not None:
+        p.prec_bound = pb.ctypes.data
+        p.prec_rel, p.prec_ceps, p.prec_eps = (float(x) for x in prec)
     rc = lib().orc_render_pixels(oscene.ptr, C.byref(p), len(px), px.ctypes.data, spec.ctypes.data)
     if rc != 0:
         raise ValueError("oracle render rejected the parameters")
-    return spec
+    extra = ((ev,) if events else ()) + ((pb,) if pb is not None else ())
+    return (spec,) + extra if extra else spec
 
 
 def camera_ray(settings, i, j, u0, u1):

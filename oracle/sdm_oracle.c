@@ -432,6 +432,48 @@ static ohit closest(const orc_scene *s, int use_bvh, const double *o, const doub
 static double interp_tab(const orc_scene *s, const double *ys, double x);
 
 /* Glass thickness at barycentric (u, v): the per-vertex distribution map. */
+/* Magnitude of the gradient of the interpolated thickness across triangle
+ * t (mm per metre; 0 without a thickness map).  With e1 = p1 - p0, e2 =
+ * p2 - p0 and N = e1 x e2, the barycentric gradients are (e2 x N) / |N|^2
+ * and (N x e1) / |N|^2. */
+static double thickness_grad(const orc_scene *s, int32_t t)
+{
+    if (!s->vthick) return 0.0;
+    const double *p0 = s->pos + 3 * s->idx[3 * t], *p1 = s->pos + 3 * s->idx[3 * t + 1],
+                 *p2 = s->pos + 3 * s->idx[3 * t + 2];
+    double e1[3], e2[3], N[3], gu[3], gv[3];
+    sub3(p1, p0, e1);
+    sub3(p2, p0, e2);
+    cross3(e1, e2, N);
+    double nn = dot3(N, N);
+    if (!(nn > 0.0)) return 0.0;
+    cross3(e2, N, gu);
+    cross3(N, e1, gv);
+    double d0 = s->vthick[s->idx[3 * t]], d1 = s->vthick[s->idx[3 * t + 1]], d2 = s->vthick[s->idx[3 * t + 2]];
+    double g[3];
+    for (int a = 0; a < 3; ++a) g[a] = ((d1 - d0) * gu[a] + (d2 - d0) * gv[a]) / nn;
+    return sqrt(dot3(g, g));
+}
+
+/* Hit error of the single-precision bound (see orc_render_params): a hit
+ * reached from an origin with error bound e over a distance dist at incidence
+ * cosine c, landing at x. */
+static double hit_error(const orc_render_params *p, double e, double dist, double c, const double *x)
+{
+    double ax = fmax(fmax(fabs(x[0]), fabs(x[1])), fabs(x[2]));
+    return (e + p->prec_eps * dist) / fmax(c, 1e-300) + p->prec_eps * ax;
+}
+
+/* Relative error bound of a glass factor at incidence cosine c with a hit
+ * error h on triangle t (see orc_render_params). */
+static double glass_sensitivity(const orc_render_params *p, const orc_scene *s, int32_t t, double h, double c,
+                                double n, double alpha)
+{
+    if (!(c > 0.0)) return INFINITY;
+    double st = sqrt(fmax(0.0, 1.0 - c * c)) / n, ct = sqrt(fmax(1e-300, 1.0 - st * st));
+    return p->prec_ceps / c + alpha * thickness_grad(s, t) * h / ct;
+}
+
 static double thickness_at(const orc_scene *s, int32_t t, double u, double v)
 {
     const omat *m = &s->mats[s->mat[t]];
@@ -450,10 +492,30 @@ typedef struct {
 /* Sun transmittance along x + t * sun (t > teps, t unbounded): zero if any
  * opaque triangle is crossed, else the product of the slab transmittances of
  * every pane crossed (Sec. 3.1 shadow rays; eq. (3)). */
+/* Event signatures (a debug aid, independent of the transport): the output
+ * function of SplitMix64 (Steele, Lea and Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014) applied to a packed event
+ * word kind << 56 | vertex << 48 | x. */
+static uint64_t event_hash(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Sun transmittance (below).  ev (may be NULL) receives, for the event
+ * signature, -1 if the ray is occluded, else the number of panes crossed,
+ * and ev_panes the sum of the hashes of 3 << 56 | triangle over them. */
 static double shadow_T(const orc_scene *s, const spectra *sp, int use_bvh, const double *x,
-                       int32_t skip, int li, double lambda_nm)
+                       int32_t skip, int li, double lambda_nm, int *ev, uint64_t *ev_panes,
+                       const orc_render_params *pb_p, double pb_e, double *pb_s)
 {
     double T = 1.0;
+    int n_panes = 0;
+    uint64_t pane_sum = 0;
+    if (ev) *ev = 0;
+    if (ev_panes) *ev_panes = 0;
     const double *d = s->sun;
     int32_t stack[256];
     int top = 0;
@@ -478,10 +540,23 @@ static double shadow_T(const orc_scene *s, const spectra *sp, int use_bvh, const
             double tt, u, v;
             if (!tri_hit(s, t, x, d, &tt, &u, &v) || !(tt > s->teps)) continue;
             const omat *m = &s->mats[s->mat[t]];
-            if (m->type == ORC_LAMBERT) return 0.0;
+            if (m->type == ORC_LAMBERT) {
+                if (ev) *ev = -1;
+                return 0.0;
+            }
+            ++n_panes;
+            pane_sum += event_hash(3ULL << 56 | (uint32_t)t);
             double R, Tr;
             double c = fabs(dot3(d, s->ng + 3 * t));
             int32_t mi = s->mat[t];
+            if (pb_s) {
+                double xh[3];
+                for (int a = 0; a < 3; ++a) xh[a] = x[a] + tt * d[a];
+                double alpha = 4.0 * PI * sp->k[mi * sp->nl + li] / (lambda_nm * 1e-6) + sp->tint[mi * sp->nl + li] +
+                               sp->sigma[mi];
+                *pb_s += pb_p->prec_rel + glass_sensitivity(pb_p, s, t, hit_error(pb_p, pb_e, tt, c, xh), c,
+                                                            sp->n[mi * sp->nl + li], alpha);
+            }
             /* Reading: toward the delta sun only the unscattered (ballistic)
              * light of a bubbly pane counts, so the bubbles' extinction adds
              * to the absorption of the slab. */
@@ -490,6 +565,8 @@ static double shadow_T(const orc_scene *s, const spectra *sp, int use_bvh, const
             T *= Tr;
         }
     }
+    if (ev) *ev = n_panes;
+    if (ev_panes) *ev_panes = pane_sum;
     return T;
 }
 
@@ -705,8 +782,11 @@ static void surrogate_eval(const orc_render_params *p, const omat *mm, double co
     else orc_mlp_forward(p->mlp_params, p->mlp_n_panes, 1, tup, &pane, out);
 }
 
-/* One (pixel, sample, wavelength) path estimate. */
-static double path_radiance(const rctx *c, int i, int j, int smp, int li)
+/* One (pixel, sample, wavelength) path estimate.  ev (may be NULL): the
+ * path's events are added to *ev (event signature); pb (may be NULL): the
+ * single-precision error bound of its contributions is added to *pb (see
+ * orc_render_params). */
+static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64_t *ev, double *pb)
 {
     const orc_scene *s = c->s;
     const orc_render_params *p = c->p;
@@ -718,14 +798,22 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li)
     double lambda = sp->lam[li];
     double beta = 1.0, L = 0.0;
     int32_t skip = -1;
+    /* single-precision bound: error of the current ray origin (a camera
+     * origin is rounded once) and relative error of the path weight */
+    double epos = p->prec_eps * fmax(fmax(fabs(o[0]), fabs(o[1])), fabs(o[2]));
+    double sbeta = 0.0;
     /* Reading: vertices 0 .. max_depth-1 are shaded; the last one does its
      * light sum but traces no continuation; no Russian roulette. */
     for (int vtx = 0; vtx < p->max_depth; ++vtx) {
         ohit h = closest(s, p->use_bvh, o, d, skip);
+        if (ev && beta != 0.0)
+            *ev += event_hash(1ULL << 56 | (uint64_t)vtx << 48 | (uint64_t)(uint32_t)smp << 32 |
+                              (uint32_t)(h.tri + 1));
         if (h.tri < 0) {
             /* Reading: every escaping ray sees the uniform sky; the sun is a
              * delta light reached only through the shadow rays. */
             L += beta * sp->Lsky[li];
+            if (pb) *pb += fabs(beta * sp->Lsky[li]) * (sbeta + p->prec_rel);
             break;
         }
         double x[3];
@@ -733,26 +821,42 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li)
         draw4(p->seed, p->job_id, pixel, (uint32_t)smp, vtx, 0, u);
         int32_t mi = s->mat[h.tri];
         const double *ng = s->ng + 3 * h.tri;
+        if (pb) epos = hit_error(p, epos, h.t, fabs(dot3(d, ng)), x);
         if (s->mats[mi].type == ORC_LAMBERT) {
             double ns[3] = {ng[0], ng[1], ng[2]};
             if (dot3(ns, d) > 0.0) { ns[0] = -ns[0]; ns[1] = -ns[1]; ns[2] = -ns[2]; }
             double rho = sp->rho[mi * sp->nl + li];
             double cs = dot3(ns, s->sun);
             if (cs > 0.0) {
-                double T = shadow_T(s, sp, p->use_bvh, x, h.tri, li, lambda);
+                int sev;
+                double s_sh = 0.0;
+                uint64_t spanes;
+                double T = shadow_T(s, sp, p->use_bvh, x, h.tri, li, lambda, &sev, &spanes, p, epos,
+                                    pb ? &s_sh : NULL);
+                if (ev && beta * rho != 0.0)
+                    *ev += event_hash(2ULL << 56 | (uint64_t)vtx << 48 | (sev < 0 ? 0xFFFFULL : (uint64_t)sev)) +
+                           (sev > 0 ? spanes : 0);
                 /* eq. (3): Lambert BRDF rho / pi times E_sun cos(theta). */
                 L += beta * rho / PI * sp->E[li] * cs * T;
+                if (pb)
+                    *pb += fabs(beta * rho / PI * sp->E[li] * cs * T) *
+                           (sbeta + 3.0 * p->prec_rel + p->prec_ceps / cs + s_sh);
             }
             if (vtx == p->max_depth - 1) break;
             /* The cosine/pdf ratio of the bounce cancels pi, so the path
              * weight is multiplied by the albedo. */
             cosine_dir(ns, u[1], u[2], d);
             beta *= rho;
+            sbeta += p->prec_rel;
         } else if (s->mats[mi].type == ORC_GLASS_BUBBLY) {
             /* Bubbly pane (air micro-particles, Sec. 1; scattering, Sec. 6). */
             if (vtx == p->max_depth - 1) break;
             const omat *mm = &s->mats[mi];
             double cos_i = fabs(dot3(d, ng));
+            if (pb) {
+                double alpha = 4.0 * PI * sp->k[mi * sp->nl + li] / (lambda * 1e-6) + sp->tint[mi * sp->nl + li];
+                sbeta += p->prec_rel + glass_sensitivity(p, s, h.tri, epos, cos_i, sp->n[mi * sp->nl + li], alpha);
+            }
             double thick = thickness_at(s, h.tri, h.u, h.v);
             if (bubbly_mode(p, mm, cos_i, thick) == ORC_BTDF_EXACT) {
                 /* Exact walk: entry interface at this wavelength (eq. (1)),
@@ -800,6 +904,10 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li)
              * through; the weight is R + T. */
             double cos_i = fabs(dot3(d, ng));
             double thick = thickness_at(s, h.tri, h.u, h.v);
+            if (pb && vtx < p->max_depth - 1) {
+                double alpha = 4.0 * PI * sp->k[mi * sp->nl + li] / (lambda * 1e-6) + sp->tint[mi * sp->nl + li];
+                sbeta += p->prec_rel + glass_sensitivity(p, s, h.tri, epos, cos_i, sp->n[mi * sp->nl + li], alpha);
+            }
             double R, T;
             orc_slab(cos_i, lambda, thick, sp->n[mi * sp->nl + li], sp->k[mi * sp->nl + li],
                      sp->tint[mi * sp->nl + li], &R, &T);
@@ -860,12 +968,16 @@ void orc_spec_to_xyz(int64_t npix, int32_t nl, const double *lam, const double *
     free(w);
 }
 
-static void pixel_spectrum(const rctx *c, int i, int j, int l0, int l1, double *out)
+static void pixel_spectrum(const rctx *c, int i, int j, int l0, int l1, double *out, uint64_t *ev, double *pb)
 {
     for (int li = l0; li < l1; ++li) {
-        double sum = 0.0;
-        for (int smp = 0; smp < c->p->spp; ++smp) sum += path_radiance(c, i, j, smp, li);
+        double sum = 0.0, bound = 0.0;
+        uint64_t e = 0;
+        for (int smp = 0; smp < c->p->spp; ++smp)
+            sum += path_radiance(c, i, j, smp, li, ev ? &e : NULL, pb ? &bound : NULL);
         out[li] = sum / c->p->spp;
+        if (ev) ev[li] = e;
+        if (pb) pb[li] = bound / c->p->spp;
     }
 }
 
@@ -881,6 +993,8 @@ int orc_render(const orc_scene *s, const orc_render_params *p, double *spec, dou
     int tile = p->tile > 0 ? p->tile : 16;
     int tx = (p->W + tile - 1) / tile, ty = (p->H + tile - 1) / tile;
     int64_t items = (int64_t)tx * ty * B;
+    int64_t it0 = p->item_begin < 0 ? 0 : (p->item_begin > items ? items : p->item_begin);
+    int64_t it1 = p->max_items > 0 && p->max_items < items - it0 ? it0 + p->max_items : items;
 #ifdef _OPENMP
     if (p->n_threads > 0) omp_set_num_threads(p->n_threads);
 #endif
@@ -888,7 +1002,7 @@ int orc_render(const orc_scene *s, const orc_render_params *p, double *spec, dou
      * dynamically by the threads (dynamic job balancing, Sec. 4).  Bands are
      * contiguous, the first nl mod B one wavelength larger. */
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t it = 0; it < items; ++it) {
+    for (int64_t it = it0; it < it1; ++it) {
         int band = (int)(it % B);
         int64_t tile_id = it / B;
         int bx = (int)(tile_id % tx), by = (int)(tile_id / tx);
@@ -897,7 +1011,9 @@ int orc_render(const orc_scene *s, const orc_render_params *p, double *spec, dou
         int l1 = l0 + base + (band < extra ? 1 : 0);
         for (int j = by * tile; j < (by + 1) * tile && j < p->H; ++j)
             for (int i = bx * tile; i < (bx + 1) * tile && i < p->W; ++i)
-                pixel_spectrum(&c, i, j, l0, l1, spec + ((int64_t)j * p->W + i) * nl);
+                pixel_spectrum(&c, i, j, l0, l1, spec + ((int64_t)j * p->W + i) * nl,
+                               p->events ? p->events + ((int64_t)j * p->W + i) * nl : NULL,
+                               p->prec_bound ? p->prec_bound + ((int64_t)j * p->W + i) * nl : NULL);
     }
     if (xyz && p->cmf_xyz) orc_spec_to_xyz((int64_t)p->W * p->H, nl, p->lambda_nm, p->cmf_xyz, spec, xyz);
     spectra_free(&sp);
@@ -918,7 +1034,9 @@ int orc_render_pixels(const orc_scene *s, const orc_render_params *p, int64_t m,
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < m; ++q) {
         int pix = pixels[q];
-        pixel_spectrum(&c, pix % p->W, pix / p->W, 0, p->n_lambda, spec + q * p->n_lambda);
+        pixel_spectrum(&c, pix % p->W, pix / p->W, 0, p->n_lambda, spec + q * p->n_lambda,
+                       p->events ? p->events + q * p->n_lambda : NULL,
+                       p->prec_bound ? p->prec_bound + q * p->n_lambda : NULL);
     }
     spectra_free(&sp);
     return 0;
@@ -934,6 +1052,7 @@ void orc_shadow(const orc_scene *s, int32_t use_bvh, int64_t m, const double *o,
     spectra sp;
     spectra_make(s, &p, &sp);
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < m; ++i) T[i] = shadow_T(s, &sp, use_bvh, o + 3 * i, skip ? skip[i] : -1, 0, lambda_nm);
+    for (int64_t i = 0; i < m; ++i)
+        T[i] = shadow_T(s, &sp, use_bvh, o + 3 * i, skip ? skip[i] : -1, 0, lambda_nm, NULL, NULL, NULL, 0.0, NULL);
     spectra_free(&sp);
 }

@@ -88,6 +88,36 @@ typedef struct {
     const double *mlp_params; /* network parameters (ORC_BTDF_SURROGATE / _FALLBACK) */
     const double *err_table;  /* [mlp_n_panes][err_dims[0]][err_dims[1]][err_dims[2]] */
     double err_bound;         /* a cell above this uses the exact walk */
+    /* Work items (pixel tile x band, tile rows top to bottom, tiles left to
+     * right, bands in order): orc_render renders items [item_begin,
+     * item_begin + max_items) only (max_items 0: every item from
+     * item_begin) and leaves the other entries of spec untouched. */
+    int64_t item_begin, max_items;
+    /* Event signatures or NULL: [H*W*n_lambda] for orc_render, [m*n_lambda]
+     * for orc_render_pixels.  Entry (pixel, lambda) = sum modulo 2^64, over
+     * the pixel's paths at that wavelength, of a hash of each closest hit
+     * (vertex, sample, triangle or none) and each shadow-ray result (vertex,
+     * occluded or the set of panes crossed), counted while the path's
+     * weight is nonzero; see event_hash in sdm_oracle.c. */
+    uint64_t *events;
+    /* Single-precision error bound or NULL (same layout as events): per
+     * spectral pixel, a first-order bound on how far an evaluation of the
+     * same paths (same decisions) in single precision can land from this
+     * one.  Each contribution to the pixel adds |contribution| times the
+     * relative error bound of its factors: prec_rel per factor, prec_ceps /
+     * cos for the cosine of a light sum, and for each glass factor (a glass hit on the path, or a pane its shadow ray
+     * crosses) prec_ceps / c + alpha |grad d| h / cos_t, where c is the
+     * incidence cosine, cos_t the refracted one, alpha = 4 pi k / lambda +
+     * alpha_tint (per mm), |grad d| the thickness gradient across the pane
+     * triangle (mm per m) and h the error bound of the hit within the pane.
+     * Hit errors follow the path: a hit reached from an origin with error e
+     * over a distance t at incidence cosine c has error (e + prec_eps t) / c
+     * + prec_eps |x| (the ray's offset moves the hit within the surface by
+     * that over c; the hit is then rounded); a camera origin has prec_eps
+     * |x|.  prec_eps bounds the relative rounding of positions and
+     * directions, prec_ceps the error of a cosine formed from them. */
+    double *prec_bound;
+    double prec_rel, prec_ceps, prec_eps;
 } orc_render_params;
 
 typedef struct orc_scene orc_scene;

@@ -198,6 +198,34 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     HIPCHK(ctx, hipSetDevice(ctx->device));
     auto *sc = new sdm_scene();
     sc->ctx = ctx;
+    {
+        // digest of every input that decides the rendered values (checkpoints)
+        Digest dg;
+        dg.add_value(d->nv);
+        dg.add_value(d->nt);
+        dg.add_value(d->n_mat);
+        dg.add_value(d->n_tab);
+        dg.add(d->pos, sizeof(float) * 3 * (size_t)d->nv);
+        if (d->vthick_mm) dg.add(d->vthick_mm, sizeof(float) * (size_t)d->nv);
+        dg.add(d->idx, sizeof(int32_t) * 3 * (size_t)d->nt);
+        dg.add(d->mat, sizeof(int32_t) * (size_t)d->nt);
+        dg.add(d->tab_lambda_nm, sizeof(float) * (size_t)d->n_tab);
+        dg.add(d->sun_dir, sizeof(d->sun_dir));
+        dg.add(d->sun_E, sizeof(float) * (size_t)d->n_tab);
+        dg.add(d->sky_L, sizeof(float) * (size_t)d->n_tab);
+        for (int32_t m = 0; m < d->n_mat; ++m) {
+            const sdm_material &mm = d->mats[m];
+            dg.add_value(mm.type);
+            dg.add_value(mm.thick_mm);
+            dg.add_value(mm.bubble_density_mm3);
+            dg.add_value(mm.bubble_rmin_um);
+            dg.add_value(mm.bubble_rmax_um);
+            dg.add_value(mm.pane_id);
+            for (const float *t : {mm.albedo, mm.n, mm.k, mm.alpha_tint})
+                if (t) dg.add(t, sizeof(float) * (size_t)d->n_tab);
+        }
+        sc->digest = dg.h;
+    }
     sc->n_tab = d->n_tab;
     sc->n_mat = d->n_mat;
     sc->nt = d->nt;
@@ -508,6 +536,71 @@ int sdm_mlp_get_params(const sdm_mlp *net, float *params)
     return SDM_OK;
 }
 
+
+static const char kMlpMagic[8] = {'S', 'D', 'M', 'M', 'L', 'P', '0', '1'};
+
+int sdm_mlp_save(const sdm_mlp *net, const char *path)
+{
+    if (!net) return SDM_E_INVALID;
+    if (!path) return fail(net->ctx, SDM_E_INVALID, "null path");
+    HIPCHK(net->ctx, hipSetDevice(net->ctx->device));
+    const size_t P = (size_t)net->P;
+    std::vector<float> buf(3 * P);
+    HIPCHK(net->ctx, hipMemcpy(buf.data(), net->params.p, P * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(net->ctx, hipMemcpy(buf.data() + P, net->m1.p, P * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(net->ctx, hipMemcpy(buf.data() + 2 * P, net->m2.p, P * sizeof(float), hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(net->ctx, SDM_E_DEVICE, "cannot open %s for writing", path);
+    const int64_t np = net->P, t = net->t;
+    bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(&net->n_panes, 4, 1, f) == 1 &&
+              std::fwrite(&np, 8, 1, f) == 1 && std::fwrite(&t, 8, 1, f) == 1 &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(net->ctx, SDM_E_DEVICE, "write error on %s", path);
+    return SDM_OK;
+}
+
+int sdm_mlp_load(sdm_context *ctx, const char *path, sdm_mlp **out)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!path || !out) return fail(ctx, SDM_E_INVALID, "null argument");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, SDM_E_INVALID, "cannot open %s", path);
+    char magic[8];
+    int32_t n_panes = 0;
+    int64_t np = 0, t = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+              std::fread(&n_panes, 4, 1, f) == 1 && std::fread(&np, 8, 1, f) == 1 && std::fread(&t, 8, 1, f) == 1 &&
+              n_panes >= 1 && n_panes <= kMaxPanes && np == sdm_mlp_nparams(n_panes) && t >= 0;
+    std::vector<float> buf;
+    if (ok) {
+        buf.resize(3 * (size_t)np);
+        ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    }
+    std::fclose(f);
+    if (!ok) return fail(ctx, SDM_E_INVALID, "%s is not a saved network", path);
+    sdm_mlp *net = nullptr;
+    if (int rc = sdm_mlp_create(ctx, n_panes, buf.data(), &net)) return rc;
+    const size_t pb = (size_t)np * sizeof(float);
+    hipError_t e = hipMemcpy(net->m1.p, buf.data() + np, pb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(net->m2.p, buf.data() + 2 * np, pb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        sdm_mlp_destroy(net);
+        return fail(ctx, SDM_E_DEVICE, "mlp load: %s", hipGetErrorString(e));
+    }
+    net->t = t;
+    *out = net;
+    return SDM_OK;
+}
+
+int sdm_mlp_info(const sdm_mlp *net, int32_t *n_panes, int64_t *steps)
+{
+    if (!net) return SDM_E_INVALID;
+    if (n_panes) *n_panes = net->n_panes;
+    if (steps) *steps = net->t;
+    return SDM_OK;
+}
 
 int sdm_mlp_grad(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *panes, const float *target,
                  float *grad, float *loss, void *hip_stream)

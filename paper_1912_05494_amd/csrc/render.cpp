@@ -231,6 +231,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         mark(SDM_K_TRACE);
         launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0 || a.cam_fused != 0, a.one_job != 0, a.grid_t, s);
         done();
+        if (a.w.sig) launch_sig_hits<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
         mark(SDM_K_SHADE);
         launch_shade<R>(a.jobs, a.bands, a.w, cur, a.one_job != 0, a.grid_s, s);
         done();
@@ -250,6 +251,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         mark(SDM_K_SHADOW);
         launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.one_job != 0, a.grid_st, s);
         done();
+        if (a.w.sig) launch_sig_shadow<R>(a.jobs, a.bands, a.w, a.grid_s, s);
         mark(SDM_K_SHADOW_ACCUM);
         launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.one_job != 0, a.grid_a, s);
         done();
@@ -314,8 +316,16 @@ TableLayout table_layout(size_t base, int nm, int nl, size_t rsize)
     return t;
 }
 
+// Item budget and resumption of a single render (max_items, checkpoints).
+struct Budget {
+    int64_t max_items = 0;      // 0: every item still to do
+    bool resume = false;        // continue ctx->partial (the accumulator holds its sums)
+    uint64_t digest = 0;        // render_digest of the job
+};
+
 template <class R>
-int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s)
+int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s,
+                const Budget &bud)
 {
     const int nj = (int)jobs.size();
     const sdm_render_params *p0 = jobs[0].p;
@@ -323,14 +333,66 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
     uint64_t chunk = 0;
     int depth = 0;
     std::vector<int64_t> acc_off(nj + 1, 0);
+    int tw0 = 0, th0 = 0;
     for (int j = 0; j < nj; ++j) {
         uint64_t ch;
         int tw, th;
         job_shape(ctx, jobs[j], ch, tw, th);
-        if (j == 0) chunk = ch;
+        if (bud.resume) {   // the partial render's items
+            tw = ctx->partial.tw;
+            th = ctx->partial.th;
+        }
+        if (j == 0) {
+            chunk = ch;
+            tw0 = tw;
+            th0 = th;
+        }
         if (int rc = plan_work(ctx, jobs[j].p, j, tw, th, plan)) return rc;
         depth = std::max(depth, jobs[j].p->max_depth);
         acc_off[j + 1] = acc_off[j] + (int64_t)jobs[j].p->camera.W * jobs[j].p->camera.H * jobs[j].p->n_lambda;
+    }
+    // Items of this call: those not done yet, in plan order, at most max_items
+    // (each item's paths are numbered afresh from 0).
+    const size_t n_all = plan.items.size();
+    std::vector<uint8_t> done;
+    if (bud.resume) {
+        if (ctx->partial.done.size() != n_all || ctx->partial.acc_elems != (size_t)acc_off[nj])
+            return fail(ctx, SDM_E_INVALID, "the partial render has another item plan");
+        done = ctx->partial.done;
+    } else {
+        done.assign(n_all, 0);
+    }
+    if (bud.resume || bud.max_items > 0) {
+        std::vector<ItemDev> sel;
+        uint64_t first = 0;
+        for (size_t i = 0; i < n_all; ++i) {
+            if (done[i]) continue;
+            if (bud.max_items > 0 && (int64_t)sel.size() >= bud.max_items) break;
+            ItemDev it = plan.items[i];
+            it.first = first;
+            first += (uint64_t)it.tw * it.th * it.ns;
+            sel.push_back(it);
+            done[i] = 1;
+        }
+        plan.items.swap(sel);
+        plan.total_rays = first;
+    } else {
+        std::fill(done.begin(), done.end(), 1);
+    }
+    uint64_t n_done = 0;
+    for (uint8_t x : done) n_done += x;
+    const bool complete = n_done == n_all;
+    // event signatures (debug)
+    bool want_sig = false;
+    for (const auto &j : jobs) want_sig = want_sig || j.out->events != nullptr;
+    if (want_sig && (bud.resume || bud.max_items > 0))
+        return fail(ctx, SDM_E_UNSUPPORTED, "event signatures need an uninterrupted render");
+    if (want_sig) HIPCHK(ctx, ctx->sig.ensure((size_t)acc_off[nj] * sizeof(uint64_t)));
+    if (bud.resume) {
+        // a retried attempt (pool overflow) starts again from these sums
+        HIPCHK(ctx, ctx->acc_base.ensure((size_t)acc_off[nj] * sizeof(double)));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->acc_base.p, ctx->acc.p, (size_t)acc_off[nj] * sizeof(double),
+                                   hipMemcpyDeviceToDevice, s));
     }
     // tables of every job
     std::vector<TableLayout> lay(nj);
@@ -424,7 +486,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
     HIPCHK(ctx, hipStreamSynchronize(s));
 
     const uint64_t total = plan.total_rays;
-    chunk = std::max<uint64_t>(1, std::min<uint64_t>(chunk, total));
+    chunk = std::max<uint64_t>(1, std::min<uint64_t>(chunk, std::max<uint64_t>(total, 1)));
     const bool timing = p0->timing != 0;
     const bool graph = p0->graph != 0 && !timing;
     int attempt = 0;
@@ -443,7 +505,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
         HIPCHK(ctx, ctx->hits.ensure(hit_b + 2048));
         HIPCHK(ctx, ctx->shadowq.ensure(sh_b + 2048));
-        HIPCHK(ctx, ctx->acc.ensure((size_t)acc_off[nj] * sizeof(double)));
+        if (!bud.resume) HIPCHK(ctx, ctx->acc.ensure((size_t)acc_off[nj] * sizeof(double)));
         HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
         ChunkArgs<R> a{};
         a.grid_t = ctx->num_cu * occupancy<R>(SDM_K_TRACE);
@@ -498,6 +560,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         w.cap = cap;
         w.nbmax = nb;
         w.gstack = ctx->gstack.as<int32_t>();
+        w.sig = want_sig ? ctx->sig.as<unsigned long long>() : nullptr;
         a.jobs = ctx->jobs.as<JobDev>();
         a.bands = ctx->bands.as<BandDev>();
         a.items = ctx->items.as<ItemDev>();
@@ -527,16 +590,23 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             a.params = net->params.as<float>();
             a.E = net->params.as<float>() + mlp_net_params();
         }
-        const uint64_t n_chunks = (total + chunk - 1) / chunk;
+        const uint64_t n_chunks = total == 0 ? 0 : (total + chunk - 1) / chunk;
 
         Timer tm{ctx, s, timing};
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         HIPCHK(ctx, hipEventCreate(&ev0));
         HIPCHK(ctx, hipEventCreate(&ev1));
         HIPCHK(ctx, hipEventRecord(ev0, s));
-        launch_zero_f64(w.acc, acc_off[nj], s);
+        if (bud.resume)
+            HIPCHK(ctx, hipMemcpyAsync(w.acc, ctx->acc_base.p, (size_t)acc_off[nj] * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s));
+        else
+            launch_zero_f64(w.acc, acc_off[nj], s);
+        if (want_sig) launch_zero_f64(reinterpret_cast<double *>(w.sig), acc_off[nj], s);
         launch_zero_counters(w.cnt, s);
-        if (graph) {
+        if (n_chunks == 0) {
+            // nothing left to trace: the outputs come from the accumulator
+        } else if (graph) {
             if (int rc = run_graph<R>(ctx, a, n_chunks, s)) return rc;
         } else {
             for (uint64_t c = 0; c < n_chunks; ++c) enqueue_chunk<R>(a, s, timing ? &tm : nullptr);
@@ -586,6 +656,9 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
                             reinterpret_cast<const double *>(tb + lay[j].off_w),
                             reinterpret_cast<const double *>(tb + lay[j].off_c), spec_d, xyz_d, s);
             if (timing) HIPCHK(ctx, tm.end());
+            if (out->events)
+                HIPCHK(ctx, hipMemcpyAsync(out->events, w.sig + acc_off[j], (size_t)npix * nl * sizeof(uint64_t),
+                                           hipMemcpyDeviceToDevice, s));
         }
         HIPCHK(ctx, hipEventRecord(ev1, s));
         HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, w.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -634,9 +707,23 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
                     st.kernel_ms[mk.first] += km;
                     st.kernel_launches[mk.first] += 1;
                 }
+            st.items_done = n_done;
+            st.items_total = n_all;
         }
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
+        if (bud.resume || bud.max_items > 0) {
+            sdm_context::Partial &pt = ctx->partial;
+            pt.valid = !complete;
+            pt.digest = bud.digest;
+            pt.tw = tw0;
+            pt.th = th0;
+            pt.done.swap(done);
+            pt.acc_elems = (size_t)acc_off[nj];
+            if (!complete)
+                return fail(ctx, SDM_E_ABORTED, "item budget reached: %llu of %llu items done",
+                            (unsigned long long)n_done, (unsigned long long)n_all);
+        }
         return SDM_OK;
     }
 }
@@ -651,18 +738,61 @@ int check_job(sdm_context *ctx, const JobIn &j)
         return fail(ctx, SDM_E_INVALID, "spectral output is not device memory");
     if (j.out->xyz && j.out->xyz_mem == SDM_MEM_DEVICE && !ptr_is_device(j.out->xyz))
         return fail(ctx, SDM_E_INVALID, "xyz output is not device memory");
+    if (j.out->events && !ptr_is_device(j.out->events))
+        return fail(ctx, SDM_E_INVALID, "events output is not device memory");
+    if (j.p->max_items < 0) return fail(ctx, SDM_E_INVALID, "max_items must be >= 0");
     return SDM_OK;
 }
 
-int render_any(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s)
+// Identifies a render for checkpoints: the scene's inputs and every
+// parameter that decides the accumulated sums (not the observer table, which
+// only enters the XYZ conversion, nor chunking, timing or graphs).
+uint64_t render_digest(const sdm_scene *sc, const sdm_render_params *p)
+{
+    Digest dg;
+    dg.add_value(sc->digest);
+    const sdm_camera &c = p->camera;
+    dg.add(c.eye, sizeof(c.eye));
+    dg.add(c.target, sizeof(c.target));
+    dg.add(c.up, sizeof(c.up));
+    dg.add_value(c.vfov_deg);
+    dg.add_value(c.ortho_height);
+    dg.add_value(c.W);
+    dg.add_value(c.H);
+    dg.add_value(c.projection);
+    dg.add_value(p->n_lambda);
+    dg.add(p->lambda_nm, sizeof(float) * (size_t)p->n_lambda);
+    dg.add_value(p->spp);
+    dg.add_value(p->max_depth);
+    dg.add_value(p->seed);
+    dg.add_value(p->job_id);
+    dg.add_value(p->n_bands);
+    if (p->band_edges) dg.add(p->band_edges, sizeof(int32_t) * ((size_t)p->n_bands + 1));
+    dg.add_value(p->beta_threshold);
+    dg.add_value(p->precision);
+    dg.add_value(p->btdf_mode);
+    if (sc->max_pane >= 0 && p->btdf_mode != SDM_BTDF_EXACT) {
+        dg.add_value(p->mlp);   // the network object (its weights may change between calls)
+        if (p->btdf_mode == SDM_BTDF_FALLBACK) {
+            dg.add(p->err_dims, sizeof(p->err_dims));
+            dg.add_value(p->err_bound);
+        }
+    }
+    return dg.h;
+}
+
+int render_any(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s,
+               const Budget &bud = Budget())
 {
     const int prec = jobs[0].p->precision;
     for (const auto &j : jobs)
         if (j.p->precision != prec) return fail(ctx, SDM_E_INVALID, "the jobs of a batch must share one precision");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    if (prec == SDM_PREC_FP64) return render_jobs<double>(ctx, jobs, stats, s);
-    return render_jobs<float>(ctx, jobs, stats, s);
+    if (prec == SDM_PREC_FP64) return render_jobs<double>(ctx, jobs, stats, s, bud);
+    return render_jobs<float>(ctx, jobs, stats, s, bud);
 }
+
+constexpr char kCkptMagic[8] = {'S', 'D', 'M', 'C', 'K', 'P', 'T', '1'};
 
 }  // namespace
 
@@ -675,7 +805,86 @@ int sdm_render(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p
     const JobIn j{sc, p, out};
     if (!p) return fail(ctx, SDM_E_INVALID, "null render parameters");
     if (int rc = check_job(ctx, j)) return rc;
-    return render_any(ctx, {j}, out->stats, (hipStream_t)hip_stream);
+    ctx->partial.valid = false;   // a new render replaces any partial one
+    Budget bud;
+    bud.max_items = p->max_items;
+    bud.digest = render_digest(sc, p);
+    return render_any(ctx, {j}, out->stats, (hipStream_t)hip_stream, bud);
+}
+
+int sdm_render_checkpoint(sdm_context *ctx, const char *path)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!path) return fail(ctx, SDM_E_INVALID, "null path");
+    const sdm_context::Partial &pt = ctx->partial;
+    if (!pt.valid) return fail(ctx, SDM_E_INVALID, "no partial render to save");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    std::vector<double> acc(pt.acc_elems);
+    HIPCHK(ctx, hipMemcpy(acc.data(), ctx->acc.p, acc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(ctx, SDM_E_DEVICE, "cannot open %s for writing", path);
+    const int64_t n_items = (int64_t)pt.done.size(), n_acc = (int64_t)pt.acc_elems;
+    bool ok = std::fwrite(kCkptMagic, 1, 8, f) == 8 && std::fwrite(&pt.digest, 8, 1, f) == 1 &&
+              std::fwrite(&n_items, 8, 1, f) == 1 && std::fwrite(&n_acc, 8, 1, f) == 1 &&
+              std::fwrite(&pt.tw, 4, 1, f) == 1 && std::fwrite(&pt.th, 4, 1, f) == 1 &&
+              std::fwrite(pt.done.data(), 1, pt.done.size(), f) == pt.done.size() &&
+              std::fwrite(acc.data(), sizeof(double), acc.size(), f) == acc.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(ctx, SDM_E_DEVICE, "write error on %s", path);
+    return SDM_OK;
+}
+
+int sdm_render_resume(sdm_context *ctx, const char *path, const sdm_scene *sc, const sdm_render_params *p,
+                      const sdm_outputs *out, void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (!p || !out) return fail(ctx, SDM_E_INVALID, "null render parameters or outputs");
+    const JobIn j{sc, p, out};
+    if (int rc = check_job(ctx, j)) return rc;
+    const uint64_t digest = render_digest(sc, p);
+    const size_t n_acc = (size_t)p->camera.W * p->camera.H * p->n_lambda;
+    if (path) {
+        FILE *f = std::fopen(path, "rb");
+        if (!f) return fail(ctx, SDM_E_INVALID, "cannot open %s", path);
+        char magic[8];
+        uint64_t dg = 0;
+        int64_t n_items = 0, na = 0;
+        int32_t tw = 0, th = 0;
+        bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kCkptMagic, 8) == 0 &&
+                  std::fread(&dg, 8, 1, f) == 1 && std::fread(&n_items, 8, 1, f) == 1 &&
+                  std::fread(&na, 8, 1, f) == 1 && std::fread(&tw, 4, 1, f) == 1 && std::fread(&th, 4, 1, f) == 1;
+        if (ok && (dg != digest || na != (int64_t)n_acc || n_items < 1 || n_items > (1ll << 31) || tw < 1 || th < 1)) {
+            std::fclose(f);
+            return fail(ctx, SDM_E_INVALID, "%s holds another render", path);
+        }
+        std::vector<uint8_t> done;
+        std::vector<double> acc;
+        if (ok) {
+            done.resize((size_t)n_items);
+            acc.resize(n_acc);
+            ok = std::fread(done.data(), 1, done.size(), f) == done.size() &&
+                 std::fread(acc.data(), sizeof(double), acc.size(), f) == acc.size();
+        }
+        std::fclose(f);
+        if (!ok) return fail(ctx, SDM_E_INVALID, "%s is not a complete checkpoint", path);
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        HIPCHK(ctx, ctx->acc.ensure(n_acc * sizeof(double)));
+        HIPCHK(ctx, hipMemcpy(ctx->acc.p, acc.data(), n_acc * sizeof(double), hipMemcpyHostToDevice));
+        sdm_context::Partial &pt = ctx->partial;
+        pt.valid = true;
+        pt.digest = digest;
+        pt.tw = tw;
+        pt.th = th;
+        pt.done.swap(done);
+        pt.acc_elems = n_acc;
+    } else if (!ctx->partial.valid || ctx->partial.digest != digest) {
+        return fail(ctx, SDM_E_INVALID, "the context holds no partial render of these parameters");
+    }
+    Budget bud;
+    bud.max_items = p->max_items;
+    bud.resume = true;
+    bud.digest = digest;
+    return render_any(ctx, {j}, out->stats, (hipStream_t)hip_stream, bud);
 }
 
 int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_stats *stats, void *hip_stream)
@@ -688,7 +897,10 @@ int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_
         if (!jobs[i].params) return fail(ctx, SDM_E_INVALID, "job %d has no parameters", i);
         js.push_back({jobs[i].scene, jobs[i].params, jobs[i].out});
         if (int rc = check_job(ctx, js.back())) return rc;
+        if (jobs[i].params->max_items > 0)
+            return fail(ctx, SDM_E_UNSUPPORTED, "item budgets apply to single renders");
     }
+    ctx->partial.valid = false;
     return render_any(ctx, js, stats, (hipStream_t)hip_stream);
 }
 
@@ -733,6 +945,8 @@ int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params 
         sdm_render_params q = *p;
         q.timing = 0;
         q.graph = 0;
+        q.max_items = 0;
+        ctx->partial.valid = false;
         sdm_outputs none{};
         sdm_stats st{};
         none.stats = &st;

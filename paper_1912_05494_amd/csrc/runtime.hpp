@@ -12,6 +12,21 @@
 
 namespace sdm_rt {
 
+// FNV-1a (64-bit) over byte ranges: identifies a render's inputs in a
+// checkpoint header.
+struct Digest {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void *p, size_t n)
+    {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    }
+    template <class T> void add_value(const T &v) { add(&v, sizeof(v)); }
+};
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -56,6 +71,17 @@ struct sdm_context {
     hipEvent_t join[2] = {nullptr, nullptr};
     hipGraphExec_t gexec = nullptr;
     std::vector<unsigned char> gkey;
+    // event signatures of a render (debug; sized like acc)
+    DevBuf sig;
+    // partial render after SDM_E_ABORTED: its accumulator stays in acc
+    struct Partial {
+        bool valid = false;
+        uint64_t digest = 0;          // render_digest of the scene and parameters
+        int32_t tw = 0, th = 0;       // resolved pixel tile
+        std::vector<uint8_t> done;    // per work item, in plan order
+        size_t acc_elems = 0;         // doubles of the accumulator
+    } partial;
+    DevBuf acc_base;                  // the accumulator a resumed render starts from
     // autotuned (chunk, tile) per scene and render shape
     struct Tuned {
         const sdm_scene *scene;
@@ -84,6 +110,7 @@ struct sdm_scene {
     int32_t stack = 0;          // most traversal stack entries a walk can hold
     int32_t max_pane = -1;      // largest pane type of a bubbly material (-1: none)
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // bounds of the vertices
+    uint64_t digest = 0;        // of the scene description's inputs
 };
 
 namespace sdm_rt {

@@ -228,8 +228,10 @@ __device__ __forceinline__ void slab_RT(R c, R lambda_nm, R d_mm, R n, R k, R ti
 }
 
 // ---------------------------------------------------------------------------
-// Ray-triangle (Moeller-Trumbore 1997): two-sided, edges inclusive.
+// Ray-triangle tests: two-sided, edges inclusive.
 // ---------------------------------------------------------------------------
+// Moeller-Trumbore (1997), the FP64 test (the same arithmetic as a plain
+// double-precision reference).
 template <class R>
 __device__ __forceinline__ bool tri_hit(V3<R> o, V3<R> d, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u, R &v)
 {
@@ -237,32 +239,92 @@ __device__ __forceinline__ bool tri_hit(V3<R> o, V3<R> d, V3<R> p0, V3<R> p1, V3
     const V3<R> pv = cross(d, e2);
     const R det = dot(e1, pv);
     if (det == R(0)) return false;
+    const R inv = R(1) / det;
     const V3<R> sv = o - p0;
-    if constexpr (sizeof(R) == 4) {
-        // FP32: the bounds are checked on the numerators against |det| (its
-        // sign folded in), so a rejected triangle costs no division; an
-        // accepted one gets the same u, v, t as below (1/det = s/|det|)
-        const R s = det < R(0) ? R(-1) : R(1), ad = fabs(det);
-        const R uu = s * dot(sv, pv);
-        if (uu < R(0) || uu > ad) return false;
-        const V3<R> qv = cross(sv, e1);
-        const R vv = s * dot(d, qv);
-        if (vv < R(0) || uu + vv > ad) return false;
-        const R ia = R(1) / ad;
-        u = uu * ia;
-        v = vv * ia;
-        t = (s * dot(e2, qv)) * ia;
-        return true;
-    } else {
-        const R inv = R(1) / det;
-        u = dot(sv, pv) * inv;
-        if (u < R(0) || u > R(1)) return false;
-        const V3<R> qv = cross(sv, e1);
-        v = dot(d, qv) * inv;
-        if (v < R(0) || u + v > R(1)) return false;
-        t = dot(e2, qv) * inv;
-        return true;
+    u = dot(sv, pv) * inv;
+    if (u < R(0) || u > R(1)) return false;
+    const V3<R> qv = cross(sv, e1);
+    v = dot(d, qv) * inv;
+    if (v < R(0) || u + v > R(1)) return false;
+    t = dot(e2, qv) * inv;
+    return true;
+}
+
+// Watertight test for FP32 (Woop, Benthin and Wald, "Watertight
+// Ray/Triangle Intersection", JCGT 2013).  The ray is sheared so that it
+// runs along +z through the origin: kz is the axis where |d| is largest, kx
+// and ky the two others (swapped when d[kz] < 0, which keeps the winding),
+// and a point p - o maps to (p[kx] - sx p[kz], p[ky] - sy p[kz], sz p[kz])
+// with (sx, sy, sz) = (d[kx], d[ky], 1) / d[kz].  A vertex maps to the same
+// floats in every triangle that holds it, and each edge function a.x b.y -
+// a.y b.x is evaluated without fused multiply-adds, so the triangle on the
+// other side of a shared edge computes exactly its negation: a ray is never
+// rejected by both (no crack between neighbours), and a ray on the edge
+// (value 0) is accepted by both, the closest-hit tie rule then picking one.
+// Rounding is monotone, so near a shared vertex the signs are those of an
+// exact point and one triangle of the fan accepts.
+template <class R>
+struct Shear {
+    R sx, sy, sz;
+    uint32_t kx, ky, kz;
+};
+
+template <class R>
+__device__ __forceinline__ R comp(V3<R> a, uint32_t k)
+{
+    return k == 0 ? a.x : (k == 1 ? a.y : a.z);
+}
+
+template <class R>
+__device__ __forceinline__ Shear<R> make_shear(V3<R> d)
+{
+    const R ax = fabs(d.x), ay = fabs(d.y), az = fabs(d.z);
+    Shear<R> s;
+    s.kz = (ax >= ay && ax >= az) ? 0u : (ay >= az ? 1u : 2u);
+    s.kx = s.kz == 2u ? 0u : s.kz + 1u;
+    s.ky = s.kx == 2u ? 0u : s.kx + 1u;
+    const R dz = comp(d, s.kz);
+    if (dz < R(0)) {
+        const uint32_t k = s.kx;
+        s.kx = s.ky;
+        s.ky = k;
     }
+    s.sz = R(1) / dz;
+    s.sx = comp(d, s.kx) * s.sz;
+    s.sy = comp(d, s.ky) * s.sz;
+    return s;
+}
+
+// a.x b.y - a.y b.x with both products rounded separately.
+__device__ __forceinline__ float edge_fn(float ax, float ay, float bx, float by)
+{
+#pragma clang fp contract(off)
+    return ax * by - ay * bx;
+}
+
+template <class R>
+__device__ __forceinline__ bool tri_hit_wt(V3<R> o, const Shear<R> &sh, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u,
+                                           R &v)
+{
+    static_assert(sizeof(R) == 4, "the watertight form is the FP32 test");
+    const V3<R> a = p0 - o, b = p1 - o, c = p2 - o;
+    const R az = comp(a, sh.kz), bz = comp(b, sh.kz), cz = comp(c, sh.kz);
+    const R ax = comp(a, sh.kx) - sh.sx * az, ay = comp(a, sh.ky) - sh.sy * az;
+    const R bx = comp(b, sh.kx) - sh.sx * bz, by = comp(b, sh.ky) - sh.sy * bz;
+    const R cx = comp(c, sh.kx) - sh.sx * cz, cy = comp(c, sh.ky) - sh.sy * cz;
+    // scaled barycentrics: U weighs p0 (edge p1 p2), V p1, W p2
+    const R U = edge_fn(cx, cy, bx, by);
+    const R V = edge_fn(ax, ay, cx, cy);
+    const R W = edge_fn(bx, by, ax, ay);
+    if ((U < R(0) || V < R(0) || W < R(0)) && (U > R(0) || V > R(0) || W > R(0))) return false;
+    const R det = U + V + W;
+    if (det == R(0)) return false;
+    const R T = U * (sh.sz * az) + V * (sh.sz * bz) + W * (sh.sz * cz);
+    const R sg = det < R(0) ? R(-1) : R(1), ia = R(1) / fabs(det);
+    u = sg * V * ia;
+    v = sg * W * ia;
+    t = sg * T * ia;
+    return true;
 }
 
 // Inverse direction for the slab tests.  FP32 takes the hardware reciprocal

@@ -216,6 +216,7 @@ struct Work {
     uint32_t cap;               // slots of each pool and of the record buffer
     int32_t nbmax;              // row length of the per-wavelength arrays (band size rounded up to 4)
     int32_t *gstack;            // traversal stack overflow (global)
+    unsigned long long *sig;    // event signatures per accumulator entry (debug), or null
 };
 
 constexpr int kAuxDepthBits = 8;

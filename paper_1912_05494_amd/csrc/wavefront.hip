@@ -249,7 +249,16 @@ struct Ray {
     V3<R> oi;            // o * inv, for the fused slab form
     uint32_t kx, ky, kz; // node word offsets of the near planes (see load_node)
     int32_t skip, cur;
+    Shear<R> sh;         // ray-space shear of the FP32 triangle test
 };
+
+// Triangle test of a ray: watertight in FP32, Moeller-Trumbore in FP64.
+template <class R>
+__device__ __forceinline__ bool ray_tri(const Ray<R> &ry, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u, R &v)
+{
+    if constexpr (sizeof(R) == 4) return tri_hit_wt(ry.o, ry.sh, p0, p1, p2, t, u, v);
+    else return tri_hit(ry.o, ry.d, p0, p1, p2, t, u, v);
+}
 
 template <class R>
 __device__ __forceinline__ void set_dir(Ray<R> &ry, V3<R> o, V3<R> d)
@@ -261,6 +270,7 @@ __device__ __forceinline__ void set_dir(Ray<R> &ry, V3<R> o, V3<R> d)
     ry.kx = signbit(ry.inv.x) ? 16u : 0u;
     ry.ky = signbit(ry.inv.y) ? 48u : 32u;
     ry.kz = signbit(ry.inv.z) ? 80u : 64u;
+    if constexpr (sizeof(R) == 4) ry.sh = make_shear(d);
 }
 
 // Distance to the plane x = b along one axis.  The fused form b * inv - o *
@@ -415,7 +425,7 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
             if (i == ry.skip) continue;
             const TriDev tr = load_tri(sc.tris, i);
             R t, u, v;
-            if (!tri_hit(ry.o, ry.d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
+            if (!ray_tri(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
             if (!(t > teps)) continue;
             const int32_t orig = __float_as_int(tr.a.w);
             if (t < h.tb || (t == h.tb && orig < h.orig_b)) {
@@ -471,7 +481,7 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
             if (i == ry.skip) continue;
             const TriDev tr = load_tri(sc.tris, i);
             R t, u, v;
-            if (!tri_hit(ry.o, ry.d, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
+            if (!ray_tri(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
             if (!(t > teps)) continue;
             const int mt = __float_as_int(tr.c.w);
             if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
@@ -530,7 +540,7 @@ __device__ __forceinline__ bool grid_step(const SceneDev &sc, const Ray<R> &ry, 
         if (R(B.w) < g.depth || leaf == ry.skip) continue;
         ++tests;
         R t, u, v;
-        if (!tri_hit(ry.o, ry.d, from4<R>(A), from4<R>(B), from4<R>(C), t, u, v)) continue;
+        if (!ray_tri(ry, from4<R>(A), from4<R>(B), from4<R>(C), t, u, v)) continue;
         if (!(t > teps)) continue;
         const int mt = __float_as_int(C.w);
         if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
@@ -1536,9 +1546,10 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
             const SceneDev &sc = jobs[job].sc;
             grid = sc.g_use != 0;
             const V3<R> o = {w.sx[s], w.sy[s], w.sz[s]}, d = {R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])};
-            if (grid) {   // the candidate walk needs no slab setup
+            if (grid) {   // the candidate walk needs no slab setup, only the triangle test's shear
                 ry.o = o;
                 ry.d = d;
+                if constexpr (sizeof(R) == 4) ry.sh = make_shear(d);
                 gr = grid_range(sc, o);
             } else {
                 set_dir(ry, o, d);
@@ -1821,6 +1832,72 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
 }
 
 // ---------------------------------------------------------------------------
+// Event signatures (debug): per spectral pixel, the sum modulo 2^64 of a hash
+// of every event that decides what its paths contribute -- each closest hit
+// (vertex, sample, triangle or none) and each shadow-ray result (vertex,
+// occluded or the set of panes crossed) -- counted for the wavelengths whose
+// weight is nonzero.  Renders whose paths take the same decisions give equal
+// sums, so a pixel whose sum differs from a reference's holds a path that
+// decided differently (a flip).  The hash is the output function of
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) on a packed event word:
+// kind << 56 | vertex << 48 | low 48 bits (sample << 32 | triangle + 1 for a
+// hit; 0xFFFF when occluded, else the pane count, for a shadow ray, plus the
+// hashes of kind 3 with each pane's triangle).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t ev_mix(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_sig_hits(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands,
+                                                     Work<R> w, int cur)
+{
+    const uint32_t count = min(w.cnt->count[cur], w.cap);
+    const Pool<R> P = w.p[cur];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const PathS<R> ps = rec_load(P.s + i);
+        if (ps.g == R(0)) continue;
+        const HitRec<R> hr = rec_load(w.hit + i);
+        const JobDev &jb = jobs[ps.aux >> kAuxJobShift];
+        const BandDev bd = bands[(ps.aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+        const int32_t caller = hr.tri >= 0 ? __float_as_int(load_tri(jb.sc.tris, hr.tri).a.w) : -1;
+        const uint64_t key = ev_mix(1ull << 56 | (uint64_t)(ps.aux & 0xffu) << 48 |
+                                    (uint64_t)(ps.smp & ~kSpectral) << 32 | (uint32_t)(caller + 1));
+        unsigned long long *row = w.sig + jb.acc_off + (uint64_t)ps.pix * jb.nl + bd.l0;
+        const bool spec = (ps.smp & kSpectral) != 0u;
+        for (int j = 0; j < bd.nb; ++j)
+            if (!spec || P.beta[aosoa(i, j, w.nbmax)] != R(0)) atomicAdd(row + j, (unsigned long long)key);
+    }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_sig_shadow(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands,
+                                                       Work<R> w)
+{
+    const uint32_t ns = min(w.cnt->scount, w.cap);
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < ns; r += gridDim.x * blockDim.x) {
+        if (w.scs[r] == R(0)) continue;
+        const uint32_t sp = w.spix[r], aux = w.saux[r];
+        const JobDev &jb = jobs[aux >> kAuxJobShift];
+        const BandDev bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+        const int occ = w.socc[r];
+        uint64_t key = ev_mix(2ull << 56 | (uint64_t)(aux & 0xffu) << 48 | (occ < 0 ? 0xFFFFull : (uint64_t)occ));
+        for (int q = 0; q < min(occ, kMaxGlass); ++q) {
+            const int leaf = w.sg_leaf[(size_t)r * kMaxGlass + q];
+            key += ev_mix(3ull << 56 | (uint32_t)__float_as_int(load_tri(jb.sc.tris, leaf).a.w));
+        }
+        unsigned long long *row = w.sig + jb.acc_off + (uint64_t)(sp & ~kSpectral) * jb.nl + bd.l0;
+        const bool spec = (sp & kSpectral) != 0u;
+        for (int j = 0; j < bd.nb; ++j)
+            if (!spec || w.contrib[aosoa(r, j, w.nbmax)] != R(0)) atomicAdd(row + j, (unsigned long long)key);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Accumulator -> mean spectral radiance (float) and XYZ (FP64):
 // XYZ = sum_i w_i L(lambda_i) cmf_i with trapezoid weights.
 // ---------------------------------------------------------------------------
@@ -2093,6 +2170,18 @@ void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R>
 }
 
 template <class R>
+void launch_sig_hits(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sig_hits<R>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
+}
+
+template <class R>
+void launch_sig_shadow(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sig_shadow<R>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w);
+}
+
+template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl,
                      int stride, R *out, hipStream_t s)
 {
@@ -2185,6 +2274,8 @@ int occupancy(int kernel_class, int lds_bytes)
     template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, bool, int, hipStream_t); \
     template void launch_resample<R>(const float *, int, const float *, int, const float *, int, int, R *,         \
                                      hipStream_t);                                                                 \
+    template void launch_sig_hits<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t);     \
+    template void launch_sig_shadow<R>(const JobDev *, const BandDev *, const Work<R> &, int, hipStream_t);       \
     template int occupancy<R>(int, int);
 
 SDM_INSTANTIATE(float)

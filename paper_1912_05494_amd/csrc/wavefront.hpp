@@ -31,6 +31,12 @@ void launch_shadow_trace(const JobDev *jobs, const BandDev *bands, const Work<R>
 template <class R>
 void launch_shadow_accum(const JobDev *jobs, const BandDev *bands, const Work<R> &w, bool one_job, int grid,
                          hipStream_t s);
+// Event signatures of the current pool's closest hits and of the shadow
+// records (debug; w.sig set).
+template <class R>
+void launch_sig_hits(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
+template <class R>
+void launch_sig_shadow(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int grid, hipStream_t s);
 template <class R>
 void launch_resample(const float *tab_x, int n_tab, const float *tab_y, int rows, const float *xs, int nl,
                      int stride, R *out, hipStream_t s);

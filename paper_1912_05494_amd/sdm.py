@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -54,7 +55,7 @@ class RenderParams(C.Structure):
                 ("tile_h", C.c_int32), ("beta_threshold", C.c_float), ("precision", C.c_int32),
                 ("chunk_paths", C.c_int64), ("timing", C.c_int32), ("btdf_mode", C.c_int32),
                 ("err_dims", C.c_int32 * 3), ("mlp", C.c_void_p), ("err_table", _FP),
-                ("err_bound", C.c_float), ("graph", C.c_int32)]
+                ("err_bound", C.c_float), ("graph", C.c_int32), ("max_items", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -64,7 +65,7 @@ class Stats(C.Structure):
                 ("tris_tested", C.c_uint64 * 2), ("bubbly_vertices", C.c_uint64),
                 ("spectral_paths", C.c_uint64), ("spectral_records", C.c_uint64),
                 ("glass_vertices", C.c_uint64 * 2), ("ms_render", C.c_double), ("kernel_ms", C.c_double * 9),
-                ("kernel_launches", C.c_uint64 * 9)]
+                ("kernel_launches", C.c_uint64 * 9), ("items_done", C.c_uint64), ("items_total", C.c_uint64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_[:6]}
@@ -77,12 +78,14 @@ class Stats(C.Structure):
         d["glass_vertices"] = {"all": int(self.glass_vertices[0]), "spectral": int(self.glass_vertices[1])}
         d["kernel_ms"] = {k: self.kernel_ms[i] for i, k in enumerate(KERNELS)}
         d["kernel_launches"] = {k: int(self.kernel_launches[i]) for i, k in enumerate(KERNELS)}
+        d["items_done"] = int(self.items_done)
+        d["items_total"] = int(self.items_total)
         return d
 
 
 class Outputs(C.Structure):
     _fields_ = [("spectral", C.c_void_p), ("xyz", C.c_void_p), ("spectral_mem", C.c_int32),
-                ("xyz_mem", C.c_int32), ("stats", C.POINTER(Stats))]
+                ("xyz_mem", C.c_int32), ("stats", C.POINTER(Stats)), ("events", C.c_void_p)]
 
 
 class Job(C.Structure):
@@ -140,6 +143,11 @@ def lib():
         L.sdm_mlp_error_table.argtypes = [vp, C.c_int64] + [vp] * 6
         L.sdm_render_batch.argtypes = [vp, C.c_int32, C.POINTER(Job), C.POINTER(Stats), vp]
         L.sdm_autotune.argtypes = [vp, vp, C.POINTER(RenderParams), C.c_char_p, C.POINTER(TuneResult), vp]
+        L.sdm_render_checkpoint.argtypes = [vp, C.c_char_p]
+        L.sdm_render_resume.argtypes = [vp, C.c_char_p, vp, C.POINTER(RenderParams), C.POINTER(Outputs), vp]
+        L.sdm_mlp_save.argtypes = [vp, C.c_char_p]
+        L.sdm_mlp_load.argtypes = [vp, C.c_char_p, C.POINTER(vp)]
+        L.sdm_mlp_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -149,7 +157,9 @@ EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_
             "sdm_debug_intersect", "sdm_debug_shadow", "sdm_slab_mc", "sdm_mlp_nparams",
             "sdm_mlp_create", "sdm_mlp_destroy", "sdm_mlp_get_params", "sdm_mlp_grad",
             "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table",
-            "sdm_render_batch", "sdm_autotune")
+            "sdm_render_batch", "sdm_autotune", "sdm_render_checkpoint", "sdm_render_resume", "sdm_mlp_save",
+            "sdm_mlp_load", "sdm_mlp_info")
+SDM_E_ABORTED = -5
 
 
 def _stream(stream=None):
@@ -173,6 +183,9 @@ class Context:
             raise SdmError("no GPU available")
         self.device = device
         self.ptr = C.c_void_p()
+        # scenes and networks of this context, destroyed before it (the C ABI
+        # requires that order)
+        self._owned = weakref.WeakSet()
         rc = lib().sdm_context_create(device, C.byref(self.ptr))
         if rc != SDM_OK:
             raise SdmError(f"sdm_context_create failed ({rc})")
@@ -184,6 +197,8 @@ class Context:
 
     def close(self):
         if self.ptr:
+            for obj in list(self._owned):
+                obj.close()
             lib().sdm_context_destroy(self.ptr)
             self.ptr = C.c_void_p()
 
@@ -223,6 +238,7 @@ class Scene:
                       fp(sE), fp(sL), SHADOW_WALKS[shadow_walk])
         self.ptr = C.c_void_p()
         ctx.check(lib().sdm_scene_create(ctx.ptr, C.byref(d), C.byref(self.ptr)), "sdm_scene_create")
+        ctx._owned.add(self)
         self.nt = int(scene.idx.shape[0])
 
     def info(self):
@@ -245,7 +261,7 @@ class Scene:
 
 
 def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision="fp32",
-                chunk_paths=0, timing=False, btdf=None, graph=False):
+                chunk_paths=0, timing=False, btdf=None, graph=False, max_items=0):
     """btdf: None (exact walks on bubbly panes) or a dict with mode ("exact",
     "surrogate", "fallback"), mlp (an MLP) and, for "fallback", err_table
     (array (n_panes, n_cos, n_d, n_rho)) and bound."""
@@ -269,6 +285,7 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
         int(tile[0]), int(tile[1]), float(settings.beta_threshold),
         SDM_PREC_FP64 if precision == "fp64" else SDM_PREC_FP32, int(chunk_paths), int(timing))
     p.graph = int(bool(graph))
+    p.max_items = int(max_items)
     if btdf is not None:
         p.btdf_mode = BTDF_MODES[btdf.get("mode", "exact")]
         if btdf.get("mlp") is not None:
@@ -285,21 +302,42 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
 
 def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, tile=(0, 0),
            precision="fp32", chunk_paths=0, timing=False, stream=None, spectral=True, xyz=True,
-           btdf=None, graph=False):
+           btdf=None, graph=False, max_items=0, events=None, resume=None):
     """Render into new device tensors: (spectral (H, W, nl) float32, xyz (H, W, 3) float64,
-    stats dict)."""
+    stats dict).
+
+    max_items > 0: at most that many work items this call; when items remain,
+    stats["aborted"] is True and the images hold the items done so far.
+    events: a device int64 tensor (H, W, nl) that receives the event
+    signatures (bit patterns of the library's uint64 values).
+    resume: continue a partial render -- True for the context's own state, or
+    the path of a checkpoint file."""
     import torch
     cam = settings.camera
     nl = len(settings.lambda_nm)
     dev = torch.device("cuda", ctx.device)
     spec_t = torch.empty((cam.H, cam.W, nl), dtype=torch.float32, device=dev) if spectral else None
     xyz_t = torch.empty((cam.H, cam.W, 3), dtype=torch.float64, device=dev) if xyz else None
-    p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing, btdf, graph)
+    p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing, btdf, graph,
+                          max_items)
     st = Stats()
-    out = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, C.pointer(st))
-    ctx.check(lib().sdm_render(ctx.ptr, scene.ptr, C.byref(p), C.byref(out), _stream(stream)),
-              "sdm_render")
-    return spec_t, xyz_t, st.as_dict()
+    out = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, C.pointer(st), _ptr(events))
+    if resume is None:
+        rc = lib().sdm_render(ctx.ptr, scene.ptr, C.byref(p), C.byref(out), _stream(stream))
+    else:
+        path = None if resume is True else str(resume).encode()
+        rc = lib().sdm_render_resume(ctx.ptr, path, scene.ptr, C.byref(p), C.byref(out), _stream(stream))
+    aborted = rc == SDM_E_ABORTED
+    if not aborted:
+        ctx.check(rc, "sdm_render" if resume is None else "sdm_render_resume")
+    d = st.as_dict()
+    d["aborted"] = aborted
+    return spec_t, xyz_t, d
+
+
+def checkpoint(ctx: Context, path):
+    """Saves the context's partial render (after an aborted render) to path."""
+    ctx.check(lib().sdm_render_checkpoint(ctx.ptr, str(path).encode()), "sdm_render_checkpoint")
 
 
 def render_into(ctx: Context, scene: Scene, params, spec_t, xyz_t, stream=None):
@@ -378,6 +416,7 @@ class MLP:
         h = C.c_void_p()
         ctx.check(lib().sdm_mlp_create(ctx.ptr, self.n_panes, p.ctypes.data, C.byref(h)), "sdm_mlp_create")
         self.ptr = h
+        ctx._owned.add(self)
 
     def params(self):
         p = np.empty(mlp_nparams(self.n_panes), dtype=np.float32)
@@ -421,6 +460,30 @@ class MLP:
                        "sdm_mlp_error_table")
         return tab
 
+    def save(self, path):
+        """Parameters and optimiser state to a file."""
+        self.ctx.check(lib().sdm_mlp_save(self.ptr, str(path).encode()), "sdm_mlp_save")
+
+    @classmethod
+    def load(cls, ctx: Context, path):
+        """A network created from a file written by save()."""
+        h = C.c_void_p()
+        ctx.check(lib().sdm_mlp_load(ctx.ptr, str(path).encode(), C.byref(h)), "sdm_mlp_load")
+        net = cls.__new__(cls)
+        net.ctx = ctx
+        net.ptr = h
+        ctx._owned.add(net)
+        n, t = C.c_int32(), C.c_int64()
+        ctx.check(lib().sdm_mlp_info(h, C.byref(n), C.byref(t)), "sdm_mlp_info")
+        net.n_panes = int(n.value)
+        return net
+
+    def steps(self):
+        """Adam steps taken so far."""
+        n, t = C.c_int32(), C.c_int64()
+        self.ctx.check(lib().sdm_mlp_info(self.ptr, C.byref(n), C.byref(t)), "sdm_mlp_info")
+        return int(t.value)
+
     def close(self):
         if getattr(self, "ptr", None):
             lib().sdm_mlp_destroy(self.ptr)
@@ -444,7 +507,8 @@ def debug_mfma(ctx: Context, A32, B32, A16, B16, stream=None):
     return C32, C16
 
 
-def render_batch(ctx: Context, jobs, precision="fp32", chunk_paths=0, graph=False, timing=False, stream=None):
+def render_batch(ctx: Context, jobs, precision="fp32", chunk_paths=0, graph=False, timing=False, stream=None,
+                 max_items=0):
     """jobs: list of (Scene, settings) or (Scene, settings, btdf); renders them
     in one wavefront.  Returns ([(spectral, xyz) device tensors], stats)."""
     import torch
@@ -459,7 +523,7 @@ def render_batch(ctx: Context, jobs, precision="fp32", chunk_paths=0, graph=Fals
         spec_t = torch.empty((cam.H, cam.W, nl), dtype=torch.float32, device=dev)
         xyz_t = torch.empty((cam.H, cam.W, 3), dtype=torch.float64, device=dev)
         p, k = make_params(settings, precision=precision, chunk_paths=chunk_paths if i == 0 else 0,
-                           timing=timing, btdf=btdf, graph=graph)
+                           timing=timing, btdf=btdf, graph=graph, max_items=max_items)
         o = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, None)
         keep += [p, k, o, scene]
         arr[i] = Job(scene.ptr, C.pointer(p), C.pointer(o))

@@ -343,6 +343,22 @@ int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *la
                 int32_t n_photons, uint64_t seed, uint32_t tuple0, int32_t precision, float *R,
                 float *T, float *A, float *w_lobe, void *hip_stream);
 
+/* sdm_slab_mc for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as sdm_slab_mc; the FP64 per-tuple
+ * sums live in a static device array of the library (2 MiB on each device
+ * it runs on, held until the process ends) instead of a context buffer, so
+ * m is limited to 65536 tuples (SDM_E_INVALID beyond).  The call allocates
+ * nothing and does not synchronise: the outputs are valid once hip_stream
+ * is synchronised.  Every call on a device shares that device's array: calls
+ * that overlap on one device (other streams, other contexts, other host
+ * threads) race and must be serialised by the caller. */
+int sdm_slab_mc_noalloc(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm,
+                        const float *d_mm, const float *rho_b, const float *n, const float *k,
+                        const float *alpha_tint, const float *n_ref, float rmin_um, float rmax_um,
+                        int32_t n_photons, uint64_t seed, uint32_t tuple0, int32_t precision, float *R,
+                        float *T, float *A, float *w_lobe, void *hip_stream);
+
 /* Surrogate network of the bubbly slab: 12 -> 64 -> 64 -> 64 -> 3 with ReLU.
  * Input of a tuple (cos_i, lambda_nm, d_mm, rho_b) on pane type p:
  * (cos_i, (lambda - 580) / 200, (d - 3.5) / 1.5, rho_b / 34, E[p][0..7]);

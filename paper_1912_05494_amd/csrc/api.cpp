@@ -108,6 +108,13 @@ int sdm_context_create(int device, sdm_context **out)
         return SDM_E_DEVICE;
     }
     ctx->num_cu = prop.multiProcessorCount;
+    // the allocation-free Monte Carlo entry point uses the device's static
+    // scratch: resolve its address now, with the device current (on failure
+    // that entry point reports an error; nothing else depends on it)
+    if (mc_scratch_address(device, &ctx->mc_scratch) != 0) {
+        ctx->mc_scratch = nullptr;
+        (void)hipGetLastError();
+    }
     if (hipHostMalloc((void **)&ctx->host_counters, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return SDM_E_NOMEM;
@@ -483,6 +490,40 @@ int sdm_slab_mc(sdm_context *ctx, int64_t m, const float *cos_i, const float *la
                               n_ref, r2, seed, tuple0, ctx->mc_acc.as<double>(), R, T, A, w_lobe, ctx->num_cu, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
+    return SDM_OK;
+}
+
+int sdm_slab_mc_noalloc(sdm_context *ctx, int64_t m, const float *cos_i, const float *lambda_nm, const float *d_mm,
+                        const float *rho_b, const float *n, const float *k, const float *alpha_tint,
+                        const float *n_ref, float rmin_um, float rmax_um, int32_t n_photons, uint64_t seed,
+                        uint32_t tuple0, int32_t precision, float *R, float *T, float *A, float *w_lobe,
+                        void *hip_stream)
+{
+    if (!ctx) return SDM_E_INVALID;
+    if (m < 0 || m > (int64_t)kMcScratchTuples)
+        return fail(ctx, SDM_E_INVALID, "tuple count %lld out of range [0, %u] (the static scratch holds %u tuples)",
+                    (long long)m, kMcScratchTuples, kMcScratchTuples);
+    if (n_photons < 1) return fail(ctx, SDM_E_INVALID, "n_photons must be >= 1");
+    if ((uint64_t)tuple0 + (uint64_t)m > 0x100000000ULL)
+        return fail(ctx, SDM_E_INVALID, "tuple0 + m exceeds the 32-bit counter word");
+    if (!(rmin_um >= 0.0f) || !(rmax_um >= rmin_um)) return fail(ctx, SDM_E_INVALID, "bad bubble radius range");
+    if (precision != SDM_PREC_FP32 && precision != SDM_PREC_FP64) return fail(ctx, SDM_E_INVALID, "bad precision");
+    if (m == 0) return SDM_OK;
+    if (!cos_i || !lambda_nm || !d_mm || !rho_b || !n || !k || !R || !T || !w_lobe)
+        return fail(ctx, SDM_E_INVALID, "null array");
+    if (!ctx->mc_scratch) return fail(ctx, SDM_E_DEVICE, "no static scratch on device %d", ctx->device);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double a = (double)rmin_um * 1e-3, b = (double)rmax_um * 1e-3;
+    const double r2 = (a * a + a * b + b * b) / 3.0;   // <r^2> in mm^2, r ~ U(a, b)
+    // the scratch sums start from zero: launch_slab_mc clears them with a kernel
+    if (precision == SDM_PREC_FP64)
+        launch_slab_mc<double>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint,
+                               n_ref, r2, seed, tuple0, ctx->mc_scratch, R, T, A, w_lobe, ctx->num_cu, s);
+    else
+        launch_slab_mc<float>((uint32_t)m, (uint32_t)n_photons, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint,
+                              n_ref, r2, seed, tuple0, ctx->mc_scratch, R, T, A, w_lobe, ctx->num_cu, s);
+    HIPCHK(ctx, hipGetLastError());
     return SDM_OK;
 }
 

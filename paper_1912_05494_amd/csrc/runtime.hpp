@@ -64,6 +64,7 @@ struct sdm_context {
     std::vector<hipEvent_t> events;
     DevBuf slab_tmp;
     DevBuf mc_acc, flag;
+    double *mc_scratch = nullptr;   // the device's static scratch (sdm_slab_mc_noalloc)
     DevBuf bubq, errtab;        // surrogate branch ratios and lobe widths; error table
     // graph replay of a chunk's kernel sequence (on a stream of the context,
     // default priority), cached while its launch arguments stay the same

@@ -10,6 +10,8 @@
 // Operands BF16, accumulation FP32, master weights FP32 (Adam).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "bubbly_dev.hpp"
 #include "mlp_dev.hpp"
 #include "surrogate.hpp"
@@ -410,6 +412,29 @@ void launch_mfma_probe(const float *A32, const float *B32, float *C32, const flo
                        hipStream_t s)
 {
     hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, A32, B32, C32, A16, B16, C16);
+}
+
+// FP64 per-tuple sums of the slab Monte Carlo for callers that cannot
+// allocate (sdm_slab_mc_noalloc): 4 doubles per tuple, kMcScratchTuples
+// tuples (2 MiB per device, held until the process ends).  Host code never
+// passes this name to a kernel: it resolves the device address once per
+// device (mc_scratch_address) and passes that.
+static __device__ __align__(256) double scratch[4 * (size_t)kMcScratchTuples];
+
+int mc_scratch_address(int device, double **out)
+{
+    static std::mutex mu;
+    static double *addr[kMcScratchDevices] = {};
+    if (device < 0 || device >= kMcScratchDevices) return -1;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        // the caller has made `device` current; each device holds its own copy
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+        addr[device] = static_cast<double *>(p);
+    }
+    *out = addr[device];
+    return 0;
 }
 
 template <class R>

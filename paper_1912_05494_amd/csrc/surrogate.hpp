@@ -11,6 +11,13 @@ constexpr int kMaxPanes = 64;   // embedding rows (glass types) a network can ho
 void launch_mfma_probe(const float *A32, const float *B32, float *C32, const float *A16, const float *B16, float *C16,
                        hipStream_t s);
 
+// Static device scratch of the allocation-free slab Monte Carlo: its
+// tuple capacity, the devices it is resolved for, and the device address on
+// `device` (which must be current); returns 0, or -1 on failure.
+constexpr uint32_t kMcScratchTuples = 1u << 16;
+constexpr int kMcScratchDevices = 64;
+int mc_scratch_address(int device, double **out);
+
 template <class R>
 void launch_slab_mc(uint32_t m, uint32_t nph, const float *cos_i, const float *lam, const float *d, const float *rho,
                     const float *n, const float *k, const float *tint, const float *n_ref, double r2_mm,

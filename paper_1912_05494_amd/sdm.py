@@ -131,6 +131,7 @@ def lib():
         L.sdm_debug_shadow.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_float, vp, vp]
         L.sdm_slab_mc.argtypes = ([vp, C.c_int64] + [vp] * 8 + [C.c_float, C.c_float, C.c_int32, C.c_uint64,
                                                                  C.c_uint32, C.c_int32] + [vp] * 5)
+        L.sdm_slab_mc_noalloc.argtypes = L.sdm_slab_mc.argtypes
         L.sdm_mlp_nparams.restype = C.c_int64
         L.sdm_mlp_nparams.argtypes = [C.c_int32]
         L.sdm_mlp_create.argtypes = [vp, C.c_int32, vp, C.POINTER(vp)]
@@ -158,7 +159,7 @@ EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_
             "sdm_mlp_create", "sdm_mlp_destroy", "sdm_mlp_get_params", "sdm_mlp_grad",
             "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table",
             "sdm_render_batch", "sdm_autotune", "sdm_render_checkpoint", "sdm_render_resume", "sdm_mlp_save",
-            "sdm_mlp_load", "sdm_mlp_info")
+            "sdm_mlp_load", "sdm_mlp_info", "sdm_slab_mc_noalloc")
 SDM_E_ABORTED = -5
 
 
@@ -385,17 +386,21 @@ PRECISION = {"fp32": 0, "fp64": 1}
 
 
 def slab_mc(ctx: Context, cos_i, lambda_nm, d_mm, rho_b, n, k, alpha_tint=None, rmin_um=10.0,
-            rmax_um=200.0, n_photons=64, seed=0, tuple0=0, precision="fp32", n_ref=None, stream=None):
+            rmax_um=200.0, n_photons=64, seed=0, tuple0=0, precision="fp32", n_ref=None, stream=None,
+            noalloc=False, out=None):
     """Bubbly-slab Monte Carlo on device float32 tensors of length m ->
-    (R, T, A, w_lobe) device tensors."""
+    (R, T, A, w_lobe) device tensors.  noalloc: the allocation-free entry
+    point (m <= 65536, outputs valid once the stream is synchronised); out:
+    four preallocated output tensors."""
     import torch
     m = cos_i.numel()
-    out = [torch.empty_like(cos_i) for _ in range(4)]
-    ctx.check(lib().sdm_slab_mc(ctx.ptr, m, _ptr(cos_i), _ptr(lambda_nm), _ptr(d_mm), _ptr(rho_b), _ptr(n),
-                                _ptr(k), _ptr(alpha_tint), _ptr(n_ref), float(rmin_um), float(rmax_um),
-                                int(n_photons),
-                                int(seed), int(tuple0), PRECISION[precision], *[_ptr(o) for o in out],
-                                _stream(stream)), "sdm_slab_mc")
+    out = list(out) if out is not None else [torch.empty_like(cos_i) for _ in range(4)]
+    fn = lib().sdm_slab_mc_noalloc if noalloc else lib().sdm_slab_mc
+    ctx.check(fn(ctx.ptr, m, _ptr(cos_i), _ptr(lambda_nm), _ptr(d_mm), _ptr(rho_b), _ptr(n),
+                 _ptr(k), _ptr(alpha_tint), _ptr(n_ref), float(rmin_um), float(rmax_um),
+                 int(n_photons),
+                 int(seed), int(tuple0), PRECISION[precision], *[_ptr(o) for o in out],
+                 _stream(stream)), "sdm_slab_mc_noalloc" if noalloc else "sdm_slab_mc")
     return tuple(out)
 
 

@@ -29,20 +29,32 @@ CHUNK_PATHS = 1 << 24
 TILE = 16
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
-# Plain VALU issue rate of FP32 arithmetic without packed math:
-# 256 CUs x 64 lanes x 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s.
-ALU_PEAK_TFLOPS = 78.6
-FLOPS_PER_NODE = 96     # four slab box tests per wide node (6 sub, 6 mul, 12 min/max each)
-FLOPS_PER_TRI = 50      # Moeller-Trumbore: edges, two cross products, four dots, reciprocal
-FLOPS_PER_CAND = 2      # sun-grid candidate: depth comparison and skip test
+# Published FP32 vector rate of MI355X (157.3 TFLOP/s: 256 CUs x 2.4 GHz x
+# 256 flop per clock, which counts packed FP32 issue).  This build keeps
+# packed FP32 instructions out of the device code, so the rate its kernels
+# can reach is half: 256 x 64 lanes x 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_TFLOPS = 78.6
+# Algorithmic work of a traversal step: a ray-box slab test is 16 flop (6
+# plane distances, 6 min/max, 2 comparisons against the interval, 2 for the
+# entry/exit), so a wide node (four boxes) is 64; a ray-triangle test is 30.
+FLOPS_PER_NODE = 64
+FLOPS_PER_TRI = 30
+# bytes a traversal reads for a node / triangle that is not cached
+NODE_BYTES, TRI_BYTES, CAND_BYTES = 128, 48, 48
 
 
-def kernel_models(stats, nb, npix, nl, sun_grid=False):
-    """Algorithmic work of each kernel class per render.  Weights are stored
-    as a scalar per path or shadow record plus nb per-wavelength factors only
-    for paths and records whose wavelengths differ (glass, coloured albedo):
+def kernel_models(stats, nb, npix, nl, sun_grid=False, launches=8):
+    """Algorithmic work of each kernel class per render: (bound, work) with
+    work in flop for "alu"/"mfma" kernels and bytes for "hbm" ones, plus the
+    bytes every kernel must move (for the whole-render HBM figure).  Weights
+    are stored as a scalar per path or shadow record plus nb per-wavelength
+    factors only for paths and records whose wavelengths differ (glass,
+    coloured albedo):
       generate      44 B per path written (origin, direction, pixel, sample,
                     depth/band/job word, skip, scalar factor)
+      trace         64 flop per wide node visited, 30 per triangle tested;
+                    moves 24 B of ray read and 16 B of hit written per ray
       shade         per closest segment 56 B read (ray 36, hit 16, factor 4)
                     and 44 B written for the continuing path, 28 B per shadow
                     record; 8 nb B per spectral path (read + write), 4 nb B
@@ -52,26 +64,34 @@ def kernel_models(stats, nb, npix, nl, sun_grid=False):
                     and its factors); 4 nb B read where the factors already
                     differed on arrival; a fork writes a second path and row,
                     44 + 4 nb B
+      shadow        a memory and latency walk: 20 B of record read (origin,
+                    skip, aux) and 4 B written per shadow ray, plus the 48-B
+                    grid candidates it examines (or the 128-B nodes and 48-B
+                    triangles of a BVH walk)
+      shadow_accum  16 B per record plus 4 nb B per spectral record, plus the
+                    FP64 accumulator's read-modify-write: 16 B per entry a
+                    launch adds to, at least min(records x nb, launches x
+                    pixels x wavelengths) entries (a pixel's records are
+                    summed before they are added)
       shade_bubbly  per bubbly vertex 60 B read, 44 + 4 nb B written, 4 nb B
                     read (factors or the network's reflectance ratios)
-      shadow_accum  16 B per record plus 4 nb B per spectral record
       finalize      12 nl + 24 B per pixel
-    Traversal (trace, shadow) counts 96 flop per wide node visited and 50 per
-    triangle tested; with a sun grid, shadow rays count 2 flop per candidate
-    examined instead of node visits; the network 2 x 9216 flop per (vertex,
-    wavelength)."""
+    The network: 2 x 9216 flop per (vertex, wavelength)."""
     Ng, Nc, Ns, F = stats["paths"], stats["closest_segments"], stats["shadow_segments"], stats["forks"]
     Nsp, Nsr = stats.get("spectral_paths", 0), stats.get("spectral_records", 0)
     gv = stats.get("glass_vertices", {"all": 0, "spectral": 0})
     Nb = stats.get("bubbly_vertices", 0)
+    nodes_s, tris_s = stats["nodes_visited"]["shadow"], stats["tris_tested"]["shadow"]
+    walk_bytes = (nodes_s * CAND_BYTES if sun_grid else nodes_s * NODE_BYTES + tris_s * TRI_BYTES)
+    acc_rmw = 16 * min(Ns * nb, launches * npix * nl)
+    trace_bytes = Nc * (24 + 16)
     m = {
         "generate": ("hbm", Ng * 44),
         "trace": ("alu", stats["nodes_visited"]["closest"] * FLOPS_PER_NODE
                   + stats["tris_tested"]["closest"] * FLOPS_PER_TRI),
         "shade": ("hbm", Nc * (56 + 44) + Ns * 28 + Nsp * 8 * nb + Nsr * 4 * nb),
-        "shadow": ("alu", stats["nodes_visited"]["shadow"] * (FLOPS_PER_CAND if sun_grid else FLOPS_PER_NODE)
-                   + stats["tris_tested"]["shadow"] * FLOPS_PER_TRI),
-        "shadow_accum": ("hbm", Ns * 16 + Nsr * 4 * nb),
+        "shadow": ("hbm", Ns * 24 + walk_bytes),
+        "shadow_accum": ("hbm", Ns * 16 + Nsr * 4 * nb + acc_rmw),
         "shade_glass": ("hbm", gv["all"] * (60 + 44 + 4 * nb) + gv["spectral"] * 4 * nb + F * (44 + 4 * nb)),
         "finalize": ("hbm", npix * nl * 12 + npix * 24),
         # network on the matrix cores: 2 x 9216 multiply-adds per (vertex, wavelength) tuple,
@@ -79,7 +99,9 @@ def kernel_models(stats, nb, npix, nl, sun_grid=False):
         "bubbly_eval": ("mfma", stats.get("bubbly_vertices", 0) * (nb + 1) * 2 * 9216),
         "shade_bubbly": ("hbm", Nb * (60 + 44 + 8 * nb)),
     }
-    return m
+    moved = {k: (w if bound == "hbm" else 0) for k, (bound, w) in m.items()}
+    moved["trace"] = trace_bytes
+    return m, moved
 
 
 def source_digest():
@@ -136,24 +158,29 @@ def profile_once():
     ctx.close()
 
 
-def cpu_baseline(scene, settings, budget_s=12.0, max_pixels=4096):
+def cpu_baseline(scene, settings, pixels_n=1024, pixels_1=48, reps=3):
+    """The oracle on the host's cores: the same workload on a bounded pixel
+    sample (every k-th pixel, all spp and wavelengths), best of `reps` runs,
+    at all threads (up to 16) and at one thread."""
     import oracle
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(threads, 16))
     W, H = settings.camera.W, settings.camera.H
-    step = max(1, (W * H) // max_pixels)
-    pixels = np.arange(0, W * H, step, dtype=np.int32)[:max_pixels]
-    os_ = oracle.OracleScene(scene)
-    done, t0 = 0, time.perf_counter()
-    while done < len(pixels):
-        batch = pixels[done:done + 256]
-        oracle.render_pixels(os_, settings, batch, n_threads=threads)
-        done += len(batch)
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
     nl = len(settings.lambda_nm)
-    value = done * settings.spp * nl / dt
+    os_ = oracle.OracleScene(scene)
+
+    def best(n_pix, n_threads):
+        step = max(1, (W * H) // n_pix)
+        pixels = np.arange(0, W * H, step, dtype=np.int32)[:n_pix]
+        dts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.render_pixels(os_, settings, pixels, n_threads=n_threads)
+            dts.append(time.perf_counter() - t0)
+        return len(pixels) * settings.spp * nl / min(dts), min(dts), step
+
+    value, dt, step = best(pixels_n, threads)
+    value1, dt1, step1 = best(pixels_1, 1)
     cpu = platform.processor() or "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -163,8 +190,31 @@ def cpu_baseline(scene, settings, budget_s=12.0, max_pixels=4096):
     except OSError:
         pass
     return {"value": value, "unit": "spectral ray samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} pixels (every {step}th of {W}x{H}), all {settings.spp} spp x {nl} "
-                      f"wavelengths, FP64, {dt:.1f} s on {threads} threads of {cpu}"}
+            "sample": f"{pixels_n} pixels (every {step}th of {W}x{H}), all {settings.spp} spp x {nl} "
+                      f"wavelengths, FP64, best of {reps} runs ({dt:.1f} s) on {threads} threads of {cpu}",
+            "value_1_thread": value1,
+            "sample_1_thread": f"{pixels_1} pixels (every {step1}th), best of {reps} runs ({dt1:.1f} s) on 1 thread",
+            "parallel_speedup": value / value1}
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=5):
+    """GB/s of a device-to-device copy of nbytes (read + write counted) in
+    this session: the HBM rate a streaming kernel can reach."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    return 2 * nbytes / best / 1e9
 
 
 def bubbly_bench(args):
@@ -347,6 +397,7 @@ def main():
     ap.add_argument("--bands", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-band-split", action="store_true", help="skip the 4- and 16-band timings")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch"],
@@ -419,7 +470,8 @@ def main():
     value = samples * args.steps / dt
     nb = -(-nl // args.bands)
     info = gs.info()
-    models = kernel_models(s, nb, W * H, nl, sun_grid=info["grid_cells"] > 0)
+    models, moved = kernel_models(s, nb, W * H, nl, sun_grid=info["grid_cells"] > 0,
+                                  launches=kl["shadow_accum"] // args.steps)
     kernels = {}
     for k in sdm.KERNELS:
         if kl[k] == 0:
@@ -432,10 +484,13 @@ def main():
         elif bound == "mfma":
             ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, MFMA_BF16_PEAK_TFLOPS, "TFLOP/s"
         else:
-            ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, ALU_PEAK_TFLOPS, "TFLOP/s"
+            ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
         kernels[k] = {"ms_per_step": kms[k] / args.steps, "launches_per_step": kl[k] // args.steps,
                       "avg_launch_ms": avg_ms, "bound": bound, "achieved": ach, "peak": peak,
                       "unit": unit, "frac": ach / peak}
+        traffic = measured_traffic(k)
+        if traffic is not None:
+            kernels[k]["counter_GBps"] = traffic / (avg_ms * 1e-3) / 1e9
     # the same render replayed as a graph per chunk (no per-kernel events)
     gparams, gkeep = sdm.make_params(st, precision=args.precision, graph=True, chunk_paths=chunk, tile=tile)
     sdm.render_into(ctx, gs, gparams, spec, xyz)
@@ -445,8 +500,44 @@ def main():
         sdm.render_into(ctx, gs, gparams, spec, xyz)
     torch.cuda.synchronize()
     graph_ms = (time.perf_counter() - tg) / max(1, args.steps // 2) * 1e3
+    # the same render split into 4 and 16 spectral sub-domains (bands)
+    band_split = {str(args.bands): dt / args.steps * 1e3}
+    if args.bands == 1 and not args.no_band_split:
+        for nbands in (4, 16):
+            stb = synth.nave_settings(W=512, H=512, spp=64, max_depth=8, n_bands=nbands)
+            bp, bkeep = sdm.make_params(stb, precision=args.precision, chunk_paths=chunk, tile=tile)
+            sdm.render_into(ctx, gs, bp, spec, xyz)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            for _ in range(3):
+                sdm.render_into(ctx, gs, bp, spec, xyz)
+            torch.cuda.synchronize()
+            band_split[str(nbands)] = (time.perf_counter() - tb) / 3 * 1e3
+            print(f"{nbands} bands: {band_split[str(nbands)]:.1f} ms", file=sys.stderr, flush=True)
+    # whole-render HBM rate: algorithmic bytes, and the counters' bytes where
+    # the committed rocprofv3 summary matches these sources
+    ms_step = dt / args.steps * 1e3
+    alg_bytes = sum(moved.values())
+    ctr = {k: measured_traffic(k) for k in sdm.KERNELS}
+    ctr_bytes = (sum(v * (kl[k] // args.steps) for k, v in ctr.items() if v is not None)
+                 if any(v is not None for v in ctr.values()) else None)
+    copy_gbps = copy_bandwidth()
+    hbm = {"ms_per_step": ms_step,
+           "algorithmic_bytes": alg_bytes, "algorithmic_GBps": alg_bytes / (ms_step * 1e-3) / 1e9,
+           "algorithmic_frac": alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "counter_bytes": ctr_bytes,
+           "counter_GBps": None if ctr_bytes is None else ctr_bytes / (ms_step * 1e-3) / 1e9,
+           "counter_frac": None if ctr_bytes is None else ctr_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "copy_kernel_GBps": copy_gbps, "copy_kernel_frac": copy_gbps / HBM_PEAK_GBS, "peak_GBps": HBM_PEAK_GBS}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     kd = kernels[dom]
+    roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
+            "unit": kd["unit"], "frac": kd["frac"], "traffic": measured_traffic(dom)}
+    if kd["bound"] == "alu":
+        roof["peak_note"] = ("published FP32 vector rate; the kernels are built without packed FP32 "
+                             f"instructions, whose rate is {FP32_UNPACKED_TFLOPS} TFLOP/s")
+        roof["frac_of_unpacked_rate"] = kd["achieved"] / FP32_UNPACKED_TFLOPS
+        roof["work_model"] = f"{FLOPS_PER_NODE} flop per wide node visited, {FLOPS_PER_TRI} per triangle tested"
     out = {
         "metric": "spectral ray samples/sec (plain form)",
         "value": value,
@@ -465,9 +556,10 @@ def main():
                                f"{st.max_depth}, {args.bands} spectral band(s)",
                    "W": W, "H": H, "spp": st.spp, "n_lambda": nl, "max_depth": st.max_depth,
                    "triangles": scene.nt, "bands": args.bands, "accumulation": "f64"},
-        "roofline": {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
-                     "unit": kd["unit"], "frac": kd["frac"], "traffic": measured_traffic(dom)},
+        "roofline": roof,
+        "hbm": hbm,
         "kernels": kernels,
+        "band_split_ms": band_split,
         "accel": {"bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"], "stack_bound": info["stack"],
                   "sun_grid_cells": info["grid_cells"], "sun_grid_candidates": info["grid_candidates"]},
         "segments_per_s": (s["closest_segments"] + s["shadow_segments"]) * args.steps / dt,

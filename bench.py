@@ -197,6 +197,43 @@ def cpu_baseline(scene, settings, pixels_n=1024, pixels_1=48, reps=3):
             "parallel_speedup": value / value1}
 
 
+def cpu_table1(threads=(1, 2, 4, 8, 16), bands=(1, 2, 4, 8), W=48, H=36, spp=4, reps=1, scene=None,
+               settings=None):
+    """The shape of the paper's Table 1 (speedup against threads x spectral
+    sub-domains) replayed with the oracle on the host's cores: one image of
+    the church nave (W x H, spp, 81 wavelengths, depth 8) rendered with
+    OpenMP over (pixel tile x band) items at each thread count and band
+    count; speedups are against 1 thread and 1 band (best of `reps`).  The
+    images of every cell are identical (the decomposition does not change
+    the result), which is checked."""
+    import oracle
+    from paper_1912_05494_amd import synth
+    sc = scene if scene is not None else synth.nave_scene(seed=1)
+    st = settings if settings is not None else synth.nave_settings(W=W, H=H, spp=spp)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = [t for t in threads if t <= max(1, avail)]
+    osc = oracle.OracleScene(sc)
+    times, ref = {}, None
+    for nb in bands:
+        for t in threads:
+            best = 1e30
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                img, _ = oracle.render(osc, st, n_threads=t, n_bands=nb)
+                best = min(best, time.perf_counter() - t0)
+            if ref is None:
+                ref = img
+            elif not np.array_equal(img, ref):
+                raise AssertionError(f"image differs at {t} threads, {nb} bands")
+            times[(nb, t)] = best
+    base = times[(bands[0], threads[0])]
+    return {"speedup": {str(nb): {str(t): base / times[(nb, t)] for t in threads} for nb in bands},
+            "seconds": {str(nb): {str(t): times[(nb, t)] for t in threads} for nb in bands},
+            "workload": f"church nave {st.camera.W}x{st.camera.H}, {st.spp} spp, {len(st.lambda_nm)} wavelengths, "
+                        f"depth {st.max_depth}, FP64 oracle, OpenMP over (16x16 tile x band) items",
+            "host_threads": avail}
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=5):
     """GB/s of a device-to-device copy of nbytes (read + write counted) in
     this session: the HBM rate a streaming kernel can reach."""
@@ -400,9 +437,10 @@ def main():
     ap.add_argument("--no-band-split", action="store_true", help="skip the 4- and 16-band timings")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
-    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch"],
+    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch", "table1"],
                     help="plain: the clear-glass nave (default); bubbly: bubbly panes in three forms; "
-                         "batch: the uneven 32-job batch in one wavefront")
+                         "batch: the uneven 32-job batch in one wavefront; table1: the oracle's speedup "
+                         "against threads x bands on the host (no GPU)")
     ap.add_argument("--batch-jobs", type=int, default=32)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--autotune", action="store_true",
@@ -423,6 +461,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.form == "table1":
+        # the oracle's speedup against threads x spectral sub-domains (CPU only)
+        out = {"metric": "oracle speedup against threads x spectral sub-domains (shape of the paper's Table 1)",
+               "cpu_baseline": cpu_table1()}
+        print(json.dumps(out), flush=True)
+        return
     if args.form == "bubbly":
         bubbly_bench(args)
         return

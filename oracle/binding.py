@@ -11,7 +11,7 @@ from .build import ensure_built
 __all__ = ["lib", "OracleScene", "philox", "u01", "fresnel", "slab", "snell_cos_t",
            "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir", "slab_mc",
            "fresnel_real", "bubble_dir", "mlp_nparams", "mlp_forward", "mlp_loss_grad", "walk_draw",
-           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "slab_to_world",
+           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "lobe_transmit", "slab_to_world",
            "BTDF_MODES"]
 
 _lib = None
@@ -112,6 +112,7 @@ def lib():
         L.orc_bf16.restype = C.c_double
         L.orc_bf16.argtypes = [C.c_double]
         L.orc_lobe_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.orc_lobe_transmit.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.orc_slab_to_world.argtypes = [C.c_void_p] * 4
         L.orc_fresnel_real.restype = C.c_double
         L.orc_fresnel_real.argtypes = [C.c_double] * 3 + [C.c_int]
@@ -377,6 +378,14 @@ def lobe_dir(d, w, u1, u2):
     d = np.ascontiguousarray(d, dtype=np.float64)
     out = np.empty(3)
     lib().orc_lobe_dir(d.ctypes.data, float(w), float(u1), float(u2), out.ctypes.data)
+    return out
+
+
+def lobe_transmit(d, ng, w, u1, u2):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    ng = np.ascontiguousarray(ng, dtype=np.float64)
+    out = np.empty(3)
+    lib().orc_lobe_transmit(d.ctypes.data, ng.ctypes.data, float(w), float(u1), float(u2), out.ctypes.data)
     return out
 
 

@@ -736,6 +736,19 @@ void orc_lobe_dir(const double d[3], double w, double u1, double u2, double out[
     normalize3(out);
 }
 
+/* Reading: a lobe sample that would leave through the entry side of the
+ * pane (the sign of its component along the face normal ng differs from the
+ * incoming ray's) is mirrored across the pane's plane, so that transmitted
+ * light always continues on the far side, as every transmitted exit of the
+ * photon walk does. */
+void orc_lobe_transmit(const double d[3], const double ng[3], double w, double u1, double u2, double out[3])
+{
+    orc_lobe_dir(d, w, u1, u2, out);
+    double dn = dot3(out, ng);
+    if (dn * dot3(d, ng) < 0.0)
+        for (int a = 0; a < 3; ++a) out[a] -= 2.0 * dn * ng[a];
+}
+
 /* Slab frame of a hit: z along the face normal on the far side of the
  * incoming ray, x along the ray's component in the face (the onb() axis
  * when the ray meets the face head-on), y = z x x. */
@@ -893,7 +906,7 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64
                     for (int a = 0; a < 3; ++a) d[a] -= 2.0 * dn * ng[a];
                 } else {
                     double nd[3];
-                    orc_lobe_dir(d, yr[2], u[1], u[2], nd);
+                    orc_lobe_transmit(d, ng, yr[2], u[1], u[2], nd);
                     for (int a = 0; a < 3; ++a) d[a] = nd[a];
                 }
                 beta *= y[0] + y[1];

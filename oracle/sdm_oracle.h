@@ -164,6 +164,10 @@ void orc_cosine_dir(const double n[3], double u1, double u2, double d[3]);
 /* Transmitted direction of the surrogate: d tilted by a 2-D Gaussian of
  * standard deviation w (radians, per tangent axis) from (u1, u2). */
 void orc_lobe_dir(const double d[3], double w, double u1, double u2, double out[3]);
+/* The transmitted direction the surrogate form takes at a pane of normal ng:
+ * orc_lobe_dir, mirrored across the pane's plane when it points back to the
+ * side the ray came from. */
+void orc_lobe_transmit(const double d[3], const double ng[3], double w, double u1, double u2, double out[3]);
 /* Direction a (slab frame of orc_bubbly_walk) in world space for a ray d
  * hitting a face of geometric normal ng. */
 void orc_slab_to_world(const double d[3], const double ng[3], const double a[3], double out[3]);

@@ -14,6 +14,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result"]
+# the render's surrogate evaluation keeps its matrix-core accumulators in
+# ordinary VGPRs (no accumulator-register reads between the layers)
+SOURCE_FLAGS = {"wavefront.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose=False, jobs=None):
@@ -22,7 +25,7 @@ def build(verbose=False, jobs=None):
         procs = []
         for src in SOURCES:
             obj = os.path.join(td, os.path.basename(src) + ".o")
-            cmd = ["hipcc", "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = ["hipcc", "-x", "hip", *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), file=sys.stderr)
             procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src))

@@ -209,11 +209,10 @@ struct ChunkArgs {
     const JobDev *jobs;
     const BandDev *bands;
     const ItemDev *items;
-    const void *wb;
-    const float *bb, *params, *E;
+    const float *params, *E;
     uint64_t total;
     uint32_t chunk;
-    int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec;
+    int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec, n_panes;
     int32_t cam_fused;          // camera rays may take the fused slab form (origins in the scene's bounds)
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
 };
@@ -240,7 +239,7 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         done();
         if (a.surr) {
             mark(SDM_K_BUBBLY_EVAL);
-            launch_bubbly_eval<R>(a.jobs, a.bands, a.w, cur, a.wb, a.bb, a.params, a.E, a.grid_e, s);
+            launch_bubbly_eval<R>(a.jobs, a.bands, a.w, cur, a.params, a.E, a.n_panes, a.grid_e, s);
             done();
         }
         if (a.bubbly) {
@@ -479,7 +478,6 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         }
     }
     HIPCHK(ctx, hipGetLastError());
-    if (surr) launch_mlp_pack(net->params.as<float>(), net->wb.p, net->bb.as<float>(), s);
     HIPCHK(ctx, upload(ctx->jobs, jd.data(), jd.size(), s));
     HIPCHK(ctx, upload(ctx->bands, plan.bands.data(), plan.bands.size(), s));
     HIPCHK(ctx, upload(ctx->items, plan.items.data(), plan.items.size(), s));
@@ -585,10 +583,9 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.bubbly = bubbly;
         a.prec = sizeof(R) == 8;
         if (surr) {
-            a.wb = net->wb.p;
-            a.bb = net->bb.as<float>();
             a.params = net->params.as<float>();
             a.E = net->params.as<float>() + mlp_net_params();
+            a.n_panes = net->n_panes;
         }
         const uint64_t n_chunks = total == 0 ? 0 : (total + chunk - 1) / chunk;
 

@@ -32,6 +32,7 @@
 #include "bubbly_dev.hpp"
 #include "mlp_dev.hpp"
 #include "sdm_dev.hpp"
+#include "surrogate.hpp"
 #include "wavefront.hpp"
 
 namespace sdm {
@@ -1264,59 +1265,223 @@ __device__ __forceinline__ BubblyVertex bubbly_vertex(const JobDev *jobs, const 
 // Surrogate at the bubbly vertices: for each vertex the network's (R, T) at
 // every wavelength of its band and its lobe width w at kLambdaRef.  The
 // weights are multiplied by R + T in place; R / (R + T) and w are kept for
-// k_shade_bubbly.  FP32 build: 16-tuple tiles on the matrix cores (BF16
-// operands, FP32 sums); tuple j of a vertex is its band's wavelength j, and
-// j = nb_max the reference wavelength.
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_bubbly_eval_mfma(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w,
-                                                            int cur, const __bf16 *wb, const float *bb,
-                                                            const float *E)
+// k_shade_bubbly.
+//
+// FP32 build, on the matrix cores (BF16 operands, FP32 sums).  A wave takes
+// 64 vertices, sets them up one per lane (the chain of dependent loads of a
+// vertex runs in parallel across the lanes) into LDS records, then runs each
+// vertex's band wavelengths (and the reference one) through the network 16
+// at a time.  Each layer is H' = W H^T on 16x16x32 tiles: the 16 samples are
+// the columns, so a lane ends a layer holding, for its sample c = lane % 16,
+// the outputs 16 t + 4 g + r (g = lane / 16, r = 0..3) of each output tile
+// t.  Those are exactly the operand rows the next layer needs if its input
+// index k = 32 s + 8 g + i (K step s, i = 0..7) stands for the previous
+// layer's output 16 (2 s + i / 4) + 4 g + i % 4: the layers' weight columns
+// are gathered in that order, and activations never leave the registers.
+// Every lane holds the A fragments of all four layers (W1 4, W2 8, W3 8, W4
+// 2 tiles of 8 BF16) for the whole launch; the biases enter as the
+// accumulators' initial values.  Layer 1 has 12 inputs and runs on the
+// 16x16x16 form (input k = 4 g + i).  Two tiles go through the layers
+// together, so each layer has eight independent products in flight.  The
+// three outputs of each sample go to LDS, and the heads and the weight
+// updates then run once per vertex over all 64 lanes.
+constexpr int kEvalBlock = 256;
+constexpr int kEvalMaxTiles = ((kMaxBand + 1 + 15) / 16 + 1) / 2 * 2;   // tiles run in pairs
+
+__device__ __forceinline__ int eval_in(int s, int g, int i)   // previous-layer output behind input k
 {
-    __shared__ NetLds net;
-    __shared__ WaveBuf wbuf[kBlock / 64];
-    load_net(net, wb, bb);
+    return 16 * (2 * s + (i >> 2)) + 4 * g + (i & 3);
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// relu(a), relu(b) rounded to BF16 and packed in one word.  A BF16 with its
+// sign bit set is a negative 16-bit integer, so the integer maximum with 0
+// after the rounding is the relu (and clears -0).
+__device__ __forceinline__ uint32_t pk_relu_bf16(float a, float b)
+{
+    const s16x2 h = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2){a, b}, bf16x2));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(h, (s16x2)0));
+}
+
+// A vertex as the evaluation needs it: its pool slot, pane, band size, mode
+// and spectral flag, the wavelength-independent features and its band's
+// wavelength row.
+struct EvalRec {
+    uint32_t i, pane, nb, flags;   // flags: 1 surrogate, 2 spectral weights
+    float f0, f2, f3;              // cos, (d - 3.5) / 1.5, rho / 34
+    uint32_t pad;
+    const void *lam;
+};
+
+template <class R>
+__global__ void __launch_bounds__(kEvalBlock) __attribute__((amdgpu_waves_per_eu(3))) k_bubbly_eval_mfma(const JobDev *__restrict__ jobs,
+                                                                const BandDev *__restrict__ bands, Work<R> w,
+                                                                int cur, const float *__restrict__ P,
+                                                                const float *__restrict__ E, int n_panes)
+{
+    constexpr int kW = kEvalBlock / 64, kS = kEvalMaxTiles * 16;
+    __shared__ f32x4 s_bias[49];   // b1 b2 b3 as 16 f32x4 each, then b4 padded
+    __shared__ float s_E[kMaxPanes * 8];
+    __shared__ EvalRec s_rec[kW][64];
+    __shared__ float s_lam[kW][kS];      // wavelength feature (lambda - 580) / 200 of sample j
+    __shared__ float s_out[kW][3][kS];
+    for (int i = threadIdx.x; i < 49; i += blockDim.x) {
+        const int layer = i >> 4, q = i & 15;
+        const int off = layer == 0 ? kOffB1 : layer == 1 ? kOffB2 : layer == 2 ? kOffB3 : kOffB4;
+        f32x4 v;
+        for (int r = 0; r < 4; ++r) v[r] = (layer == 3 && r >= 3) ? 0.0f : gld(P + off + 4 * q + r);
+        s_bias[i] = v;
+    }
+    for (int i = threadIdx.x; i < 8 * min(n_panes, kMaxPanes); i += blockDim.x) s_E[i] = gld(E + i);
+    __syncthreads();
+    const int l = (int)lane_id(), g = l >> 4, c = l & 15, wv = (int)(threadIdx.x >> 6);
+    float(*so)[kS] = s_out[wv];
+    float *sl = s_lam[wv];
+    // A fragments: lane (g, c) holds row c of each output tile and the
+    // inputs of its K slice
+    s16x4 A1[4];
+    bf16x8 A2[4][2], A3[4][2], A4[2];
+    for (int t = 0; t < 4; ++t) {
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            A1[t][i] = bits((__bf16)(k < 12 ? gld(P + kOffW1 + (16 * t + c) * 12 + k) : 0.0f));
+        }
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 8; ++i) {
+                const int k = eval_in(s, g, i);
+                A2[t][s][i] = (__bf16)gld(P + kOffW2 + (16 * t + c) * 64 + k);
+                A3[t][s][i] = (__bf16)gld(P + kOffW3 + (16 * t + c) * 64 + k);
+            }
+    }
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < 8; ++i)
+            A4[s][i] = (__bf16)(c < 3 ? gld(P + kOffW4 + c * 64 + eval_in(s, g, i)) : 0.0f);
+
     const Pool<R> Pi = w.p[cur];
-    WaveBuf &wv = wbuf[threadIdx.x >> 6];
-    const uint32_t l = lane_id();
     const uint32_t stride = (uint32_t)w.nbmax + 1u;          // band wavelengths + the reference one
-    const uint32_t per_v = (stride + 15u) / 16u;              // tiles per vertex
-    const uint64_t ntile = (uint64_t)min(w.cnt->bcount, w.cap) * per_v;
-    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t tile = wave; tile < ntile; tile += nw) {
-        // one tile = 16 consecutive wavelengths of one vertex, so the mode
-        // check is uniform across the wave and exact-walk vertices cost no
-        // matrix work
-        const uint32_t e = (uint32_t)(tile / per_v);
-        const uint32_t j = (uint32_t)(tile % per_v) * 16u + (l & 15u);
-        V3<R> d, ng;
-        R cos_i, thick;
-        const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, e, d, ng, cos_i, thick);
-        if (v.mode != kBtdfSurrogate) continue;
-        const bool valid = l < 16 && (j < (uint32_t)v.bd.nb || j == stride - 1u);
-        if (l < 16) {
-            if (valid) {
-                const float lam = j == stride - 1u ? kLambdaRef : (float)gld((const R *)v.jb->lam + v.bd.l0 + j);
-                features((float)cos_i, lam, (float)thick, (float)v.rho, E + 8 * v.pane, wv.X0 + l * 32);
-            } else {
-                for (int q = 0; q < 32; ++q) wv.X0[l * 32 + q] = (__bf16)0.0f;
+    const uint32_t per_v = ((stride + 15u) / 16u + 1u) & ~1u;   // tiles per vertex, even
+    const uint32_t nv = min(w.cnt->bcount, w.cap);
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+    const void *lam_cached = nullptr;
+    uint32_t nb_cached = 0;
+    for (uint32_t base = wave * 64u; base < nv; base += nw * 64u) {
+        {
+            EvalRec rc{};
+            const uint32_t e = base + (uint32_t)l;
+            if (e < nv) {
+                V3<R> d, ng;
+                R cos_i, thick;
+                const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, e, d, ng, cos_i, thick);
+                if (v.mode == kBtdfSurrogate) {
+                    rc.i = v.i;
+                    rc.pane = (uint32_t)v.pane;
+                    rc.nb = (uint32_t)v.bd.nb;
+                    rc.flags = 1u | ((rec_load(Pi.s + v.i).smp & kSpectral) ? 2u : 0u);
+                    rc.f0 = (float)cos_i;
+                    rc.f2 = ((float)thick - 3.5f) / 1.5f;
+                    rc.f3 = (float)v.rho / 34.0f;
+                    rc.lam = (const R *)v.jb->lam + v.bd.l0;
+                }
             }
+            s_rec[wv][l] = rc;
         }
         wave_sync();
-        forward_tile(net, wv);
-        if (valid) {
-            float Rr, Tt, wl;
-            heads(wv.O[l * 16], wv.O[l * 16 + 1], wv.O[l * 16 + 2], Rr, Tt, wl);
-            if (j == stride - 1u) {
-                w.bw[v.i] = R(wl);
-            } else {
-                const size_t q = aosoa(v.i, (int)j, w.nbmax);
-                const R b = (rec_load(Pi.s + v.i).smp & kSpectral) ? Pi.beta[q] : R(1);
-                Pi.beta[q] = b * R(Rr + Tt);
-                w.bratio[q] = R(Rr / (Rr + Tt));
+        const uint32_t nk = min(64u, nv - base);
+        for (uint32_t k = 0; k < nk; ++k) {
+            const EvalRec r = s_rec[wv][k];   // the same for every lane
+            if (!(r.flags & 1u)) continue;
+            // the weights this vertex scales, fetched while the network runs
+            R bq[(kS + 63) / 64];
+            for (int q = 0; q < (kS + 63) / 64; ++q) {
+                const uint32_t j = (uint32_t)(l + 64 * q);
+                bq[q] = ((r.flags & 2u) && j < r.nb) ? Pi.beta[aosoa(r.i, (int)j, w.nbmax)] : R(1);
             }
+            if (r.lam != lam_cached || r.nb != nb_cached) {   // most vertices share a band
+                for (uint32_t j = (uint32_t)l; j < per_v * 16u; j += 64u)
+                    sl[j] = ((j < r.nb ? (float)gld((const R *)r.lam + j) : kLambdaRef) - 580.0f) * 0.005f;
+                lam_cached = r.lam;
+                nb_cached = r.nb;
+                wave_sync();
+            }
+            // layer-1 operand of sample c: features 4 g .. 4 g + 3; only the
+            // wavelength (feature 1) changes from tile to tile
+            s16x4 x0;
+            {
+                const float *Ep = s_E + 8 * r.pane;
+                float f[4];
+                if (g == 0) {
+                    f[0] = r.f0;
+                    f[1] = 0.0f;
+                    f[2] = r.f2;
+                    f[3] = r.f3;
+                } else {
+                    for (int i = 0; i < 4; ++i) f[i] = g < 3 ? Ep[4 * (g - 1) + i] : 0.0f;
+                }
+                for (int i = 0; i < 4; ++i) x0[i] = bits((__bf16)f[i]);
+            }
+            for (uint32_t tile = 0; tile < per_v; tile += 2u) {
+                s16x4 x[2];
+                for (int u = 0; u < 2; ++u) {
+                    x[u] = x0;
+                    if (g == 0) x[u][1] = bits((__bf16)sl[(tile + u) * 16u + (uint32_t)c]);
+                }
+                bf16x8 H[2][2];
+                f32x4 acc[2][4];
+                auto epilogue = [&]() {
+                    for (int u = 0; u < 2; ++u)
+                        for (int s = 0; s < 2; ++s) {
+                            uint4 q;
+                            q.x = pk_relu_bf16(acc[u][2 * s][0], acc[u][2 * s][1]);
+                            q.y = pk_relu_bf16(acc[u][2 * s][2], acc[u][2 * s][3]);
+                            q.z = pk_relu_bf16(acc[u][2 * s + 1][0], acc[u][2 * s + 1][1]);
+                            q.w = pk_relu_bf16(acc[u][2 * s + 1][2], acc[u][2 * s + 1][3]);
+                            H[u][s] = __builtin_bit_cast(bf16x8, q);
+                        }
+                };
+                // the biases are read from LDS at each use rather than held
+                // in registers across the loop
+                int z = 0;
+                asm volatile("" : "+v"(z));
+                const f32x4 *sb = s_bias + z;
+                for (int t = 0; t < 4; ++t)
+                    for (int u = 0; u < 2; ++u) acc[u][t] = mfma16(A1[t], x[u], sb[4 * t + g]);
+                epilogue();
+                for (int t = 0; t < 4; ++t)
+                    for (int u = 0; u < 2; ++u)
+                        acc[u][t] = mfma32(A2[t][1], H[u][1], mfma32(A2[t][0], H[u][0], sb[16 + 4 * t + g]));
+                epilogue();
+                for (int t = 0; t < 4; ++t)
+                    for (int u = 0; u < 2; ++u)
+                        acc[u][t] = mfma32(A3[t][1], H[u][1], mfma32(A3[t][0], H[u][0], sb[32 + 4 * t + g]));
+                epilogue();
+                for (int u = 0; u < 2; ++u) {
+                    const f32x4 o = mfma32(A4[1], H[u][1], mfma32(A4[0], H[u][0], sb[48]));
+                    // outputs 0..2 of sample c sit in lanes g = 0
+                    if (g == 0)
+                        for (int q = 0; q < 3; ++q) so[q][(tile + u) * 16u + (uint32_t)c] = o[q];
+                }
+            }
+            wave_sync();
+            for (int q = 0; q < (kS + 63) / 64; ++q) {
+                const uint32_t j = (uint32_t)(l + 64 * q);
+                const bool ref = j == stride - 1u;
+                if (!(j < r.nb || ref)) continue;
+                float Rr, Tt, wl;
+                heads(so[0][j], so[1][j], so[2][j], Rr, Tt, wl);
+                if (ref) {
+                    w.bw[r.i] = R(wl);
+                } else {
+                    const size_t a = aosoa(r.i, (int)j, w.nbmax);
+                    Pi.beta[a] = bq[q] * R(Rr + Tt);
+                    w.bratio[a] = R(Rr / (Rr + Tt));
+                }
+            }
+            wave_sync();
         }
-        wave_sync();
     }
 }
 
@@ -1393,8 +1558,8 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *__res
 // wavelength (complex index, shared draw); the wavelengths that enter share
 // one walk inside (the pane's index at kLambdaRef) and are weighted by
 // exp(-alpha L).  Surrogate: reflect where u0 < R / (R + T), else the
-// transmitted lobe of width w.  Either way a band splits into at most a
-// reflected and a continuing packet.
+// transmitted lobe of width w, folded onto the far side of the pane.  Either
+// way a band splits into at most a reflected and a continuing packet.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
@@ -1490,6 +1655,11 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restric
                 const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
                 const R u0 = u01<R>(rr.x);
                 dnew = lobe_dir<R>(d, w.bw[i], u01<R>(rr.y), u01<R>(rr.z));
+                // a sample that points back through the entry side is
+                // mirrored across the pane's plane: transmitted light leaves
+                // on the far side
+                const R dn_out = dot(dnew, ng);
+                if (dn_out * dot(d, ng) < R(0)) dnew = dnew - (R(2) * dn_out) * ng;
                 for (int j = 0; j < bd.nb; ++j) {
                     const size_t q = aosoa(i, j, nbm);
                     R bn = Pi.beta[q];
@@ -2140,12 +2310,12 @@ void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> 
     else hipLaunchKernelGGL((k_shade_glass<R, false>), dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur);
 }
 template <class R>
-void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const void *wb,
-                        const float *bb, const float *params, const float *E, int grid, hipStream_t s)
+void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const float *params,
+                        const float *E, int n_panes, int grid, hipStream_t s)
 {
     if constexpr (sizeof(R) == 4)
-        hipLaunchKernelGGL(k_bubbly_eval_mfma<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur,
-                           (const __bf16 *)wb, bb, E);
+        hipLaunchKernelGGL(k_bubbly_eval_mfma<R>, dim3(grid), dim3(kEvalBlock), 0, s, jobs, bands, w, cur, params, E,
+                           n_panes);
     else
         hipLaunchKernelGGL(k_bubbly_eval_fp64, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, cur, params, E);
 }
@@ -2255,7 +2425,10 @@ int occupancy(int kernel_class, int lds_bytes)
     default: return 1;
     }
     int b = 0;
-    const int threads = kernel_class == SDM_K_SHADE ? kShadeBlock : kernel_class == SDM_K_TRACE ? kTraceBlock : kBlock;
+    const int threads = kernel_class == SDM_K_SHADE ? kShadeBlock
+                        : kernel_class == SDM_K_TRACE ? kTraceBlock
+                        : (kernel_class == SDM_K_BUBBLY_EVAL && sizeof(R) == 4) ? kEvalBlock
+                                                                                : kBlock;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, threads, lds_bytes) != hipSuccess) return 1;
     return std::max(1, b);
 }
@@ -2267,8 +2440,8 @@ int occupancy(int kernel_class, int lds_bytes)
     template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t);  \
     template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int,          \
                                         hipStream_t);                                                              \
-    template void launch_bubbly_eval<R>(const JobDev *, const BandDev *, const Work<R> &, int, const void *,       \
-                                        const float *, const float *, const float *, int, hipStream_t);            \
+    template void launch_bubbly_eval<R>(const JobDev *, const BandDev *, const Work<R> &, int, const float *,      \
+                                        const float *, int, int, hipStream_t);                                     \
     template void launch_shade_bubbly<R>(const JobDev *, const BandDev *, const Work<R> &, int, int, hipStream_t); \
     template void launch_shadow_trace<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t); \
     template void launch_shadow_accum<R>(const JobDev *, const BandDev *, const Work<R> &, bool, int, hipStream_t); \

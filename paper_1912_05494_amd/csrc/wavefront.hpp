@@ -21,8 +21,8 @@ template <class R>
 void launch_shade_glass(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
                         hipStream_t s);
 template <class R>
-void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const void *wb,
-                        const float *bb, const float *params, const float *E, int grid, hipStream_t s);
+void launch_bubbly_eval(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, const float *params,
+                        const float *E, int n_panes, int grid, hipStream_t s);
 template <class R>
 void launch_shade_bubbly(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, int grid, hipStream_t s);
 template <class R>

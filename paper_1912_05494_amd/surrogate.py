@@ -59,3 +59,49 @@ def random_tuples(n, n_panes, lambdas, seed=0, rho_max=RHO_MAX, d_range=(2.0, 5.
     tup[:, 3] = rng.uniform(0.0, rho_max, n)
     pane = rng.integers(0, n_panes, n).astype(np.int32)
     return tup, pane
+
+
+def scene_tuples(materials, tab_lambda, n, lambdas, seed=0, own=0.0, n_ref_nm=560.0):
+    """Training or validation inputs for the bubbly materials of a scene, pane
+    q being the q-th bubbly material: tuples (cos, lambda, d, rho) and pane
+    ids from random_tuples, and per tuple the pane's (n, k, tint) at lambda
+    and its n at n_ref_nm, interpolated linearly in the material tables.  A
+    fraction `own` of the tuples is moved to its pane's own bubble density."""
+    from .synth import GLASS_BUBBLY
+    panes = [m for m in materials if m.type == GLASS_BUBBLY]
+    n_panes = len(panes)
+    tup, pane = random_tuples(n, n_panes, lambdas, seed=seed)
+    if own > 0.0:
+        dens = np.array([m.bubble_density for m in panes], dtype=np.float32)
+        sel = np.random.default_rng(seed + 1).random(n) < own
+        tup[sel, 3] = dens[pane[sel]]
+    tab = np.asarray(tab_lambda, dtype=np.float64)
+    nk = np.empty((n, 4), dtype=np.float32)
+    for q, m in enumerate(panes):
+        sel = pane == q
+        lam = tup[sel, 1].astype(np.float64)
+        nk[sel, 0] = np.interp(lam, tab, m.n)
+        nk[sel, 1] = np.interp(lam, tab, m.k)
+        nk[sel, 2] = np.interp(lam, tab, m.alpha_tint)
+        nk[sel, 3] = np.interp(n_ref_nm, tab, m.n)
+    return tup, pane, nk
+
+
+def mc_targets(ctx, tup, nk, n_photons, seed, device):
+    """(R, T, lobe width) of each tuple from the library's slab Monte Carlo:
+    a device tensor [m, 3]."""
+    import torch
+    from . import sdm
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in
+         (tup[:, 0], tup[:, 1], tup[:, 2], tup[:, 3], nk[:, 0], nk[:, 1], nk[:, 2], nk[:, 3])]
+    R, T, A, Wl = sdm.slab_mc(ctx, *t[:7], n_ref=t[7], n_photons=n_photons, seed=seed)
+    return torch.stack([R, T, Wl], 1).contiguous()
+
+
+def train_stepped(net, tuples, panes, target, steps, batch=8192):
+    """Adam at a stepped learning rate: half the steps at 2e-3, a third at
+    5e-4, the rest at 1e-4.  Returns the loss curve."""
+    n1, n2 = steps // 2, steps // 3
+    curves = [net.train(tuples, panes, target, steps=s, batch=batch, lr=lr)
+              for s, lr in ((n1, 2e-3), (n2, 5e-4), (steps - n1 - n2, 1e-4)) if s > 0]
+    return np.concatenate(curves) if curves else np.zeros(0, dtype=np.float32)

@@ -247,12 +247,16 @@ def random_glass(rng, lam):
 
 
 def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=1,
-               pane_grid=10, bubbly=False, rho_max=34.0, sun_elev=35.0, sun_azim=15.0):
+               pane_grid=10, bubbly=False, rho_max=34.0, sun_elev=35.0, sun_azim=15.0, rho_min=0.0,
+               bubble_free=False):
     """Procedural church nave, 60 x 12 x 20 m: floor, side walls with window
     openings (1.5 x 4 m), semicircular barrel vault, end walls and two rows of
     ten cylindrical columns; glass panes fill the openings.  Opaque parts are
     gray Lambert groups with albedo in [0.3, 0.7].  Panes are quad grids with
-    per-vertex thickness in [2, 5] mm and per-pane optical constants."""
+    per-vertex thickness in [2, 5] mm and per-pane optical constants.
+    bubbly: panes carry air bubbles of density U(rho_min, rho_max) per mm^3;
+    bubble_free (with bubbly): the same scene with every pane a clear slab
+    (the draws are the same, the bubbles are left out)."""
     rng = np.random.default_rng(seed)
     lam = LAMBDA_81
     L, Wd, Hw, R = 60.0, 12.0, 14.0, 6.0
@@ -322,9 +326,10 @@ def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=
             h = (win_z1 - win_z0) / panes_per_window
             for q in range(panes_per_window):
                 nn, kk, tint = random_glass(rng, lam)
-                m = Material(GLASS_BUBBLY if bubbly else GLASS, n=nn, k=kk, alpha_tint=tint,
-                             thick_mm=3.5, pane_id=pane,
-                             bubble_density=float(rng.uniform(0.0, rho_max)) if bubbly else 0.0)
+                rho = float(rng.uniform(rho_min, rho_max)) if bubbly else 0.0
+                m = Material(GLASS_BUBBLY if bubbly and not bubble_free else GLASS, n=nn, k=kk,
+                             alpha_tint=tint, thick_mm=3.5, pane_id=pane,
+                             bubble_density=0.0 if bubble_free else rho)
                 mats.append(m)
                 v0 = mesh.nv
                 gu = pane_grid

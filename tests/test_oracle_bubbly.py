@@ -54,6 +54,32 @@ def test_lobe_sampler_statistics(orc):
     assert np.linalg.norm(mean - d) < 1e-4
 
 
+def test_lobe_transmit_stays_on_far_side(orc):
+    """The surrogate's transmitted direction: the lobe sample where it already
+    points through the pane, else its mirror image across the pane's plane
+    (tangential part kept, normal part negated), so always on the far side."""
+    rng = np.random.default_rng(9)
+    folded = 0
+    for _ in range(400):
+        ng = rng.normal(size=3)
+        ng /= np.linalg.norm(ng)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        w, u1, u2 = rng.uniform(0.0, 1.2), rng.random(), rng.random()
+        lobe = orc.lobe_dir(d, w, u1, u2)
+        out = orc.lobe_transmit(d, ng, w, u1, u2)
+        assert (out @ ng) * (d @ ng) >= 0.0
+        assert abs(np.linalg.norm(out) - 1) < 1e-12
+        if (lobe @ ng) * (d @ ng) >= 0.0:
+            assert np.array_equal(out, lobe)
+        else:
+            folded += 1
+            tang = lobe - (lobe @ ng) * ng
+            assert np.allclose(out - (out @ ng) * ng, tang, atol=1e-14)
+            assert out @ ng == pytest.approx(-(lobe @ ng), abs=1e-14)
+    assert folded > 20      # wide lobes at grazing incidence do cross the plane
+
+
 def test_slab_frame(orc):
     rng = np.random.default_rng(4)
     for _ in range(50):

@@ -397,6 +397,104 @@ def bubbly_bench(args):
     ctx.close()
 
 
+def large_bench(args):
+    """The large configuration: the ~1 M-triangle nave with 200 bubbly panes of
+    40 glass types at 1920 x 1080, 81 wavelengths, 256 spp, depth 12.  The
+    network is trained on MC tables of the 40 pane types, its error table
+    built from 10^4 tuples x 65,536 photons; the fallback form (surrogate,
+    exact walk where a cell's error exceeds the bound) is timed against the
+    plain form (exact walks) on the same GPU, with the surrogate form beside
+    them, and compared by CIEDE2000 on 16 x 16 pixel block means."""
+    import torch
+    from paper_1912_05494_amd import color, sdm, surrogate, synth
+
+    scene = synth.large_scene()
+    st = synth.large_settings(spp=args.large_spp)
+    W, H, nl = st.camera.W, st.camera.H, len(st.lambda_nm)
+    dev = torch.device("cuda", 0)
+    ctx = sdm.Context(0)
+    t0 = time.perf_counter()
+    gs = sdm.Scene(ctx, scene)
+    t_scene = time.perf_counter() - t0
+    n_types = 1 + max(m.pane_id for m in scene.materials if m.type == synth.GLASS_BUBBLY)
+    print(f"scene: {len(scene.idx)} triangles, built in {t_scene:.2f} s", file=sys.stderr, flush=True)
+    tup, pane, nk = surrogate.scene_tuples(scene.materials, scene.tab_lambda, args.bubbly_train, st.lambda_nm,
+                                           seed=101, own=0.5)
+    target = surrogate.mc_targets(ctx, tup, nk, 64, 7, dev)
+    net = sdm.MLP(ctx, n_types, surrogate.init_params(n_types, seed=0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    surrogate.train_stepped(net, torch.from_numpy(tup).to(dev), torch.from_numpy(pane).to(dev), target,
+                            args.bubbly_steps)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    vt, vp, vnk = surrogate.scene_tuples(scene.materials, scene.tab_lambda, args.bubbly_val, st.lambda_nm, seed=202)
+    vtarget = surrogate.mc_targets(ctx, vt, vnk, args.bubbly_val_photons, 9, dev)
+    table = net.error_table(torch.from_numpy(vt).to(dev), torch.from_numpy(vp).to(dev), vtarget,
+                            dims=(8, 3, 4)).cpu().numpy()
+    print(f"training: {args.bubbly_steps} steps in {t_train:.2f} s", file=sys.stderr, flush=True)
+    spec = torch.empty((H, W, nl), dtype=torch.float32, device=dev)
+    xyz = torch.empty((H, W, 3), dtype=torch.float64, device=dev)
+
+    def run(btdf, st_, steps):
+        params, keep = sdm.make_params(st_, timing=steps > 0, btdf=btdf)
+        s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+        dt = None
+        if steps > 0:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+        return xyz.cpu().numpy(), dt, s_
+
+    forms, images = {}, {}
+    for form, btdf in (("exact", {"mode": "exact"}),
+                       ("fallback", {"mode": "fallback", "mlp": net, "err_table": table, "bound": args.bubbly_bound}),
+                       ("surrogate", {"mode": "surrogate", "mlp": net})):
+        images[form], dt, s_ = run(btdf, st, args.large_steps)
+        forms[form] = {"value": W * H * st.spp * nl / dt, "ms_per_step": dt * 1e3,
+                       "bubbly_vertices": s_["bubbly_vertices"],
+                       "kernel_ms": {k: v for k, v in s_["kernel_ms"].items() if v > 0}}
+        print(f"{form}: {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    other, _, _ = run({"mode": "exact"}, synth.large_settings(spp=args.large_spp, seed=1), 0)
+
+    def blocks(x, b=20):
+        return x.reshape(H // b, b, W // b, b, 3).mean((1, 3))
+
+    def de(a, b):
+        return float(np.mean(color.image_delta_e(a, b, st.cmf, st.lambda_nm)))
+
+    de_blocks = {f: de(blocks(images["exact"]), blocks(images[f])) for f in ("fallback", "surrogate")}
+    de_blocks["exact_vs_exact_other_seed"] = de(blocks(images["exact"]), blocks(other))
+    out = {
+        "metric": "spectral ray samples/sec (large nave, fallback form at error bound "
+                  f"{args.bubbly_bound:g} against the plain form)",
+        "value": forms["fallback"]["value"],
+        "unit": "spectral ray samples/s",
+        "n_gpus": 1, "steps": args.large_steps, "warmup": 1,
+        "ms_per_step": forms["fallback"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"procedural church nave, {len(scene.idx)} triangles, 200 bubbly panes of 200 "
+                               f"triangles ({n_types} glass types, densities 0-34 per mm^3), {W}x{H}, {st.spp} spp, "
+                               f"{nl} wavelengths, depth {st.max_depth}",
+                   "surrogate": f"12-64-64-64-3 trained {args.bubbly_steps} Adam steps of 8192 on "
+                                f"{args.bubbly_train} MC tuples (64 photons)",
+                   "error_table": f"8x3x4 cells per pane type from {args.bubbly_val} tuples x "
+                                  f"{args.bubbly_val_photons} photons, bound {args.bubbly_bound}"},
+        "forms": forms,
+        "fallback_speed_vs_plain": forms["fallback"]["value"] / forms["exact"]["value"],
+        "mean_delta_e2000_vs_exact_20x20_blocks": de_blocks,
+        "flagged_cells": float((table > args.bubbly_bound).mean()),
+        "scene_build_s": t_scene,
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+    ctx.close()
+
+
 def batch_bench(args):
     """The uneven 32-job batch (square sides 128-1024, 10k-200k triangles,
     8-81 wavelengths, 16-128 spp; scene seed 2 + job) as one wavefront,
@@ -455,15 +553,18 @@ def main():
     ap.add_argument("--no-band-split", action="store_true", help="skip the 4- and 16-band timings")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
-    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch", "table1"],
-                    help="plain: the clear-glass nave (default); bubbly: bubbly panes in three forms; "
+    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch", "table1", "large"],
+                    help="plain: the clear-glass nave (default); bubbly: bubbly panes in four forms; "
                          "batch: the uneven 32-job batch in one wavefront; table1: the oracle's speedup "
-                         "against threads x bands on the host (no GPU)")
+                         "against threads x bands on the host (no GPU); large: the 1 M-triangle nave "
+                         "with 200 bubbly panes at 1920x1080, fallback against exact")
     ap.add_argument("--batch-jobs", type=int, default=32)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--autotune", action="store_true",
                     help="choose chunk size and tile with sdm_autotune before timing")
     ap.add_argument("--bubbly-spp", type=int, default=64)
+    ap.add_argument("--large-spp", type=int, default=256)
+    ap.add_argument("--large-steps", type=int, default=1, help="timed renders per form of --form large")
     ap.add_argument("--bubbly-train", type=int, default=10_000_000)
     ap.add_argument("--bubbly-steps", type=int, default=30000)
     ap.add_argument("--bubbly-val", type=int, default=10000, help="validation tuples")
@@ -490,6 +591,8 @@ def main():
                "cpu_baseline": cpu_table1()}
         print(json.dumps(out), flush=True)
         return
+    if args.form == "large":
+        return large_bench(args)
     if args.form == "bubbly":
         bubbly_bench(args)
         return

@@ -11,7 +11,7 @@ from .build import ensure_built
 __all__ = ["lib", "OracleScene", "philox", "u01", "fresnel", "slab", "snell_cos_t",
            "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir", "slab_mc",
            "fresnel_real", "bubble_dir", "mlp_nparams", "mlp_forward", "mlp_loss_grad", "walk_draw",
-           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "lobe_transmit", "slab_to_world",
+           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "lobe_transmit", "mlp_bf16_bound", "slab_to_world",
            "BTDF_MODES"]
 
 _lib = None
@@ -56,7 +56,7 @@ class _WalkStream(C.Structure):
 
 
 class _WalkOut(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("dir", C.c_double * 3), ("L", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("dir", C.c_double * 3), ("L", C.c_double), ("n_events", C.c_int32)]
 
 
 BTDF_MODES = {"exact": 0, "surrogate": 1, "fallback": 2}
@@ -113,6 +113,8 @@ def lib():
         L.orc_bf16.argtypes = [C.c_double]
         L.orc_lobe_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.orc_lobe_transmit.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.orc_mlp_bf16_bound.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p,
+                                         C.c_void_p]
         L.orc_slab_to_world.argtypes = [C.c_void_p] * 4
         L.orc_fresnel_real.restype = C.c_double
         L.orc_fresnel_real.argtypes = [C.c_double] * 3 + [C.c_int]
@@ -379,6 +381,17 @@ def lobe_dir(d, w, u1, u2):
     out = np.empty(3)
     lib().orc_lobe_dir(d.ctypes.data, float(w), float(u1), float(u2), out.ctypes.data)
     return out
+
+
+def mlp_bf16_bound(params, tup, pane, e_cos=0.0, e_d=0.0):
+    """One tuple's BF16-operand outputs (R, T, w) and the bound on their
+    distance from an FP32-sum evaluation with inputs off by e_cos, e_d."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    t = np.ascontiguousarray(tup, dtype=np.float64)
+    out, bnd = np.empty(3), np.empty(3)
+    lib().orc_mlp_bf16_bound(p.ctypes.data, t.ctypes.data, int(pane), float(e_cos), float(e_d), out.ctypes.data,
+                             bnd.ctypes.data)
+    return out, bnd
 
 
 def lobe_transmit(d, ng, w, u1, u2):

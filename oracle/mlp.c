@@ -133,6 +133,74 @@ void orc_mlp_forward_bf16(const double *params, int32_t n_panes, int64_t m, cons
     }
 }
 
+/* Test instrument: the BF16-operand network of one tuple (as
+ * orc_mlp_forward_bf16) and a bound on how far an evaluation that sums the
+ * same BF16 products in FP32 can lie from it, when its cos and thickness
+ * inputs may also be off by e_cos and e_d (absolute).  A layer's
+ * pre-activation z moves by at most E = |W| D + gamma (|b| + |W| (|h| + D)),
+ * gamma = 65 u / (1 - 65 u), u = 2^-24 (an FP32 sum of at most 65 terms),
+ * D bounding how far the layer's inputs h already differ.  The ReLU output
+ * is rounded to BF16 again, and rounding is monotone, so the next layer's D
+ * is the width of [bf16(max(z - E, 0)), bf16(max(z + E, 0))]: zero unless a
+ * BF16 rounding boundary lies within E of z.  The scaled features start
+ * within 4 u of their exact values.  The output bound is carried through
+ * the heads by their derivatives (R(1 - R), RT, T(1 - T); the softplus
+ * slope), with 5 % for second-order terms and 2e-6 for the heads' own FP32
+ * rounding. */
+static void layer_bound(const double *W, const double *b, const double *h, const double *D, int nin, int nout,
+                        double gam, double *z, double *E)
+{
+    for (int o = 0; o < nout; ++o) {
+        double s = b[o], a = fabs(b[o]), dd = 0.0;
+        for (int i = 0; i < nin; ++i) {
+            double wb = orc_bf16(W[o * nin + i]);
+            s += wb * h[i];
+            a += fabs(wb) * (fabs(h[i]) + D[i]);
+            dd += fabs(wb) * D[i];
+        }
+        z[o] = s;
+        E[o] = dd + gam * a;
+    }
+}
+
+static void relu_bf16_interval(const double *z, const double *E, int n, double *h, double *D)
+{
+    for (int i = 0; i < n; ++i) {
+        h[i] = orc_bf16(z[i] > 0.0 ? z[i] : 0.0);
+        double hi = z[i] + E[i], lo = z[i] - E[i];
+        D[i] = orc_bf16(hi > 0.0 ? hi : 0.0) - orc_bf16(lo > 0.0 ? lo : 0.0);
+    }
+}
+
+void orc_mlp_bf16_bound(const double *params, const double *tup, int32_t pane, double e_cos, double e_d,
+                        double out[3], double bound[3])
+{
+    view v = make_view(params);
+    const double u = ldexp(1.0, -24), gam = 65.0 * u / (1.0 - 65.0 * u);
+    double x[NIN], h0[NIN], D0[NIN], z[NH], E[NH], h[NH], D[NH], o[NOUT], eo[NOUT];
+    features(tup, pane, &v, x);
+    for (int i = 0; i < NIN; ++i) {
+        double ex = 0.0;
+        if (i == 0) ex = e_cos;
+        else if (i == 1 || i == 3) ex = 4.0 * u * fabs(x[i]);
+        else if (i == 2) ex = e_d / 1.5 + 4.0 * u * fabs(x[i]);
+        h0[i] = orc_bf16(x[i]);
+        D0[i] = orc_bf16(x[i] + ex) - orc_bf16(x[i] - ex);
+    }
+    layer_bound(v.W1, v.b1, h0, D0, NIN, NH, gam, z, E);
+    relu_bf16_interval(z, E, NH, h, D);
+    layer_bound(v.W2, v.b2, h, D, NH, NH, gam, z, E);
+    relu_bf16_interval(z, E, NH, h, D);
+    layer_bound(v.W3, v.b3, h, D, NH, NH, gam, z, E);
+    relu_bf16_interval(z, E, NH, h, D);
+    layer_bound(v.W4, v.b4, h, D, NH, NOUT, gam, o, eo);
+    heads(o, out);
+    double R = out[0], T = out[1];
+    bound[0] = 1.05 * (R * (1.0 - R) * eo[0] + R * T * eo[1]) + 2e-6;
+    bound[1] = 1.05 * (R * T * eo[0] + T * (1.0 - T) * eo[1]) + 2e-6;
+    bound[2] = 1.05 * eo[2] / (1.0 + exp(-o[2])) + 2e-6;
+}
+
 /* tuples: m x 4 (cos, lambda_nm, d_mm, rho_b); panes: m; out: m x 3 (R, T, w) */
 void orc_mlp_forward(const double *params, int32_t n_panes, int64_t m, const double *tuples,
                      const int32_t *panes, double *out)

@@ -786,12 +786,15 @@ static int bubbly_mode(const orc_render_params *p, const omat *mm, double cos_i,
     return e > p->err_bound ? ORC_BTDF_EXACT : ORC_BTDF_SURROGATE;
 }
 
+/* The network at one vertex; with bnd (BF16 mode only), also the bound of
+ * orc_mlp_bf16_bound for cos and thickness inputs off by e_cos and e_d. */
 static void surrogate_eval(const orc_render_params *p, const omat *mm, double cos_i, double lambda, double d,
-                           double out[3])
+                           double out[3], double e_cos, double e_d, double *bnd)
 {
     double tup[4] = {cos_i, lambda, d, mm->density};
     int32_t pane = mm->pane_id;
-    if (p->mlp_bf16) orc_mlp_forward_bf16(p->mlp_params, p->mlp_n_panes, 1, tup, &pane, out);
+    if (p->mlp_bf16 && bnd) orc_mlp_bf16_bound(p->mlp_params, tup, pane, e_cos, e_d, out, bnd);
+    else if (p->mlp_bf16) orc_mlp_forward_bf16(p->mlp_params, p->mlp_n_panes, 1, tup, &pane, out);
     else orc_mlp_forward(p->mlp_params, p->mlp_n_panes, 1, tup, &pane, out);
 }
 
@@ -815,6 +818,9 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64
      * origin is rounded once) and relative error of the path weight */
     double epos = p->prec_eps * fmax(fmax(fabs(o[0]), fabs(o[1])), fabs(o[2]));
     double sbeta = 0.0;
+    /* extra error of the current direction (radians) beyond its rounding, set
+     * where a bubbly vertex chose it: moves the next hit by edir * t */
+    double edir = 0.0;
     /* Reading: vertices 0 .. max_depth-1 are shaded; the last one does its
      * light sum but traces no continuation; no Russian roulette. */
     for (int vtx = 0; vtx < p->max_depth; ++vtx) {
@@ -834,7 +840,10 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64
         draw4(p->seed, p->job_id, pixel, (uint32_t)smp, vtx, 0, u);
         int32_t mi = s->mat[h.tri];
         const double *ng = s->ng + 3 * h.tri;
-        if (pb) epos = hit_error(p, epos, h.t, fabs(dot3(d, ng)), x);
+        if (pb) {
+            epos = hit_error(p, epos + edir * h.t, h.t, fabs(dot3(d, ng)), x);
+            edir = 0.0;
+        }
         if (s->mats[mi].type == ORC_LAMBERT) {
             double ns[3] = {ng[0], ng[1], ng[2]};
             if (dot3(ns, d) > 0.0) { ns[0] = -ns[0]; ns[1] = -ns[1]; ns[2] = -ns[2]; }
@@ -892,15 +901,26 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64
                     orc_slab_to_world(d, ng, wo.dir, nd);
                     for (int a = 0; a < 3; ++a) d[a] = nd[a];
                     beta *= exp(-alpha * wo.L);
+                    if (pb) {
+                        /* FP32 walk: each free flight's length and the running
+                         * sums carry a few roundings (2 prec_rel per flight);
+                         * every length scales with the thickness, which is
+                         * off by |grad d| epos; the exit direction carries the
+                         * flights' rounding, magnified near grazing exit */
+                        double nf = (double)(wo.n_events + 1);
+                        sbeta += alpha * wo.L * (2.0 * nf * p->prec_rel + thickness_grad(s, h.tri) * epos / thick);
+                        edir += 4.0 * nf * p->prec_rel / fmax(fabs(wo.dir[2]), 1e-3);
+                    }
                 }
             } else {
                 /* Surrogate: (R, T) at this wavelength; reflect with
                  * probability R / (R + T), else leave through the
                  * transmitted lobe, whose width is taken at 560 nm so that
                  * every wavelength of the path keeps one direction. */
-                double y[3], yr[3];
-                surrogate_eval(p, mm, cos_i, lambda, thick, y);
-                surrogate_eval(p, mm, cos_i, 560.0, thick, yr);
+                double y[3], yr[3], by[3], byr[3];
+                const double e_d = pb ? thickness_grad(s, h.tri) * epos : 0.0;
+                surrogate_eval(p, mm, cos_i, lambda, thick, y, p->prec_ceps, e_d, pb ? by : NULL);
+                surrogate_eval(p, mm, cos_i, 560.0, thick, yr, p->prec_ceps, e_d, pb ? byr : NULL);
                 if (u[0] < y[0] / (y[0] + y[1])) {
                     double dn = dot3(d, ng);
                     for (int a = 0; a < 3; ++a) d[a] -= 2.0 * dn * ng[a];
@@ -908,8 +928,11 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64
                     double nd[3];
                     orc_lobe_transmit(d, ng, yr[2], u[1], u[2], nd);
                     for (int a = 0; a < 3; ++a) d[a] = nd[a];
+                    /* the lobe offset is w g with g = sqrt(-2 ln(1 - u1)) */
+                    if (pb && p->mlp_bf16) edir += byr[2] * sqrt(-2.0 * log1p(-u[1]));
                 }
                 beta *= y[0] + y[1];
+                if (pb && p->mlp_bf16) sbeta += (by[0] + by[1]) / (y[0] + y[1]) + p->prec_rel;
             }
         } else {
             /* Glass pane as a thin slab (Sec. 6 thickness map): the path

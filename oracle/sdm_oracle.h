@@ -196,6 +196,7 @@ typedef struct {
     int32_t kind;   /* 0 absorbed (event cap), 1 out through the entry face, 2 through the far face */
     double dir[3];  /* direction in air, slab frame (x in the plane of incidence, z into the slab) */
     double L;       /* geometric length travelled in glass (mm) */
+    int32_t n_events; /* free flights taken (bubbles met and faces reached) */
 } orc_walk_out;
 
 /* The four uniforms of draw (event, sub) of a walk stream. */
@@ -214,6 +215,11 @@ void orc_mlp_forward(const double *params, int32_t n_panes, int64_t m, const dou
 double orc_mlp_loss_grad(const double *params, int32_t n_panes, int64_t m, const double *tuples,
                          const int32_t *panes, const double *target, double *grad);
 /* The same network with BF16 operands (matrix-core arithmetic). */
+/* Test instrument: one tuple's BF16-operand outputs (R, T, w) and a bound on
+ * their distance from an evaluation with FP32 sums whose cos and thickness
+ * inputs are off by up to e_cos and e_d (see mlp.c). */
+void orc_mlp_bf16_bound(const double *params, const double *tup, int32_t pane, double e_cos, double e_d,
+                        double out[3], double bound[3]);
 void orc_mlp_forward_bf16(const double *params, int32_t n_panes, int64_t m, const double *tuples,
                           const int32_t *panes, double *out);
 double orc_bf16(double x);

@@ -137,7 +137,9 @@ void orc_bubbly_walk(const orc_walk_stream *st, double cos_i, double d, double s
     double z = 0.0, L = 0.0;
     out->kind = 0;
     out->dir[0] = out->dir[1] = out->dir[2] = 0.0;
+    out->n_events = 0;
     for (uint32_t e = 1; e <= MC_MAX_EVENTS; ++e) {
+        out->n_events = (int32_t)e;
         orc_walk_draw(st, e, 0, u);
         double sb = dir[2] > 0.0 ? (d - z) / dir[2] : (dir[2] < 0.0 ? -z / dir[2] : INFINITY);
         double l = sigma > 0.0 ? -log1p(-u[0]) / sigma : INFINITY;

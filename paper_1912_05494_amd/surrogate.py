@@ -62,22 +62,32 @@ def random_tuples(n, n_panes, lambdas, seed=0, rho_max=RHO_MAX, d_range=(2.0, 5.
 
 
 def scene_tuples(materials, tab_lambda, n, lambdas, seed=0, own=0.0, n_ref_nm=560.0):
-    """Training or validation inputs for the bubbly materials of a scene, pane
-    q being the q-th bubbly material: tuples (cos, lambda, d, rho) and pane
-    ids from random_tuples, and per tuple the pane's (n, k, tint) at lambda
-    and its n at n_ref_nm, interpolated linearly in the material tables.  A
-    fraction `own` of the tuples is moved to its pane's own bubble density."""
+    """Training or validation inputs for the bubbly materials of a scene, by
+    pane type (a material's pane_id; the materials of one type share n, k and
+    tint): tuples (cos, lambda, d, rho) and pane types from random_tuples,
+    and per tuple the type's (n, k, tint) at lambda and its n at n_ref_nm,
+    interpolated linearly in the material tables.  A fraction `own` of the
+    tuples is moved to the density of one of its type's panes."""
     from .synth import GLASS_BUBBLY
-    panes = [m for m in materials if m.type == GLASS_BUBBLY]
-    n_panes = len(panes)
-    tup, pane = random_tuples(n, n_panes, lambdas, seed=seed)
+    by_type = {}
+    for m in materials:
+        if m.type == GLASS_BUBBLY:
+            by_type.setdefault(int(m.pane_id), []).append(m)
+    n_types = max(by_type) + 1
+    if sorted(by_type) != list(range(n_types)):
+        raise ValueError("pane types of the bubbly materials must be 0 .. n-1")
+    tup, pane = random_tuples(n, n_types, lambdas, seed=seed)
     if own > 0.0:
-        dens = np.array([m.bubble_density for m in panes], dtype=np.float32)
-        sel = np.random.default_rng(seed + 1).random(n) < own
-        tup[sel, 3] = dens[pane[sel]]
+        sel = np.flatnonzero(np.random.default_rng(seed + 1).random(n) < own)
+        pick = np.random.default_rng(seed + 2).random(len(sel))
+        for q in range(n_types):
+            dq = np.array([m.bubble_density for m in by_type[q]], dtype=np.float32)
+            s = sel[pane[sel] == q]
+            tup[s, 3] = dq[np.minimum((pick[pane[sel] == q] * len(dq)).astype(np.int64), len(dq) - 1)]
     tab = np.asarray(tab_lambda, dtype=np.float64)
     nk = np.empty((n, 4), dtype=np.float32)
-    for q, m in enumerate(panes):
+    for q in range(n_types):
+        m = by_type[q][0]
         sel = pane == q
         lam = tup[sel, 1].astype(np.float64)
         nk[sel, 0] = np.interp(lam, tab, m.n)

@@ -248,7 +248,7 @@ def random_glass(rng, lam):
 
 def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=1,
                pane_grid=10, bubbly=False, rho_max=34.0, sun_elev=35.0, sun_azim=15.0, rho_min=0.0,
-               bubble_free=False):
+               bubble_free=False, glass_types=None):
     """Procedural church nave, 60 x 12 x 20 m: floor, side walls with window
     openings (1.5 x 4 m), semicircular barrel vault, end walls and two rows of
     ten cylindrical columns; glass panes fill the openings.  Opaque parts are
@@ -256,7 +256,11 @@ def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=
     per-vertex thickness in [2, 5] mm and per-pane optical constants.
     bubbly: panes carry air bubbles of density U(rho_min, rho_max) per mm^3;
     bubble_free (with bubbly): the same scene with every pane a clear slab
-    (the draws are the same, the bubbles are left out)."""
+    (the draws are the same, the bubbles are left out).  glass_types: None
+    gives every pane its own glass (n, k, tint); an integer draws that many
+    glasses and pane p takes glass p mod glass_types (its pane type), keeping
+    its own density and thickness map.  Each pane is a pane_grid x pane_grid
+    quad grid."""
     rng = np.random.default_rng(seed)
     lam = LAMBDA_81
     L, Wd, Hw, R = 60.0, 12.0, 14.0, 6.0
@@ -321,19 +325,24 @@ def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=
     n_opaque = sum(len(t) for t in mesh.idx)
     vthick_parts = [np.zeros(mesh.nv)]
     pane = 0
+    glasses = [random_glass(rng, lam) for _ in range(glass_types)] if glass_types else None
     for y in (0.0, Wd):
         for xc in centres:
             h = (win_z1 - win_z0) / panes_per_window
             for q in range(panes_per_window):
-                nn, kk, tint = random_glass(rng, lam)
+                if glasses is None:
+                    nn, kk, tint = random_glass(rng, lam)
+                    ptype = pane
+                else:
+                    ptype = pane % glass_types
+                    nn, kk, tint = glasses[ptype]
                 rho = float(rng.uniform(rho_min, rho_max)) if bubbly else 0.0
                 m = Material(GLASS_BUBBLY if bubbly and not bubble_free else GLASS, n=nn, k=kk,
-                             alpha_tint=tint, thick_mm=3.5, pane_id=pane,
+                             alpha_tint=tint, thick_mm=3.5, pane_id=ptype,
                              bubble_density=0.0 if bubble_free else rho)
                 mats.append(m)
                 v0 = mesh.nv
-                gu = pane_grid
-                gv = max(1, pane_grid // panes_per_window) if panes_per_window > 1 else pane_grid
+                gu = gv = pane_grid
                 mesh.grid((xc - win_w / 2, y, win_z0 + q * h), (win_w, 0, 0), (0, 0, h),
                           gu, gv, pane_mat0 + pane)
                 vthick_parts.append(rng.uniform(2.0, 5.0, size=mesh.nv - v0))
@@ -346,6 +355,20 @@ def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=
                   sky_L=sky_radiance(lam), vthick=vthick)
     scene.n_opaque = n_opaque
     return scene
+
+
+def large_scene(seed=5, bubbly=True, bubble_free=False):
+    """The large nave: about 1 M triangles; 25 windows a side of 4 panes,
+    200 bubbly panes of 200 triangles (10 x 10 quads) with per-vertex
+    thickness in [2, 5] mm, each with its own bubble density U(0, 34) per
+    mm^3 and one of 40 glass types."""
+    return nave_scene(seed=seed, target_tris=1_000_000, windows_per_side=25, panes_per_window=4, pane_grid=10,
+                      bubbly=bubbly, bubble_free=bubble_free, glass_types=40)
+
+
+def large_settings(spp=256, max_depth=12, seed=0):
+    """1920 x 1080, 81 wavelengths, 256 spp, depth 12."""
+    return nave_settings(W=1920, H=1080, spp=spp, max_depth=max_depth, seed=seed)
 
 
 def nave_settings(W=512, H=512, spp=64, max_depth=8, n_bands=1, seed=0, n_lambda=81):

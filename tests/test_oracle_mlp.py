@@ -188,3 +188,62 @@ def test_bf16_forward_is_operand_rounding_only(orc):
     assert np.allclose(y, ref, rtol=1e-12, atol=1e-14)
     # and the rounding matters: the FP64 network differs by more than that
     assert np.abs(orc.mlp_forward(p, n_panes, tup, pane) - y).max() > 1e-5
+
+
+def _fp32_sum_forward(orc, p, n_panes, tup, pane, perm):
+    """The network as a matrix-core evaluation computes it, emulated: features
+    scaled in FP32, BF16 operands, each dot product summed in FP32 in the
+    order `perm` (a permutation of the inputs, bias first), ReLU, BF16
+    re-rounding; heads in FP64."""
+    sp = surrogate.split(p.astype(np.float64), n_panes)
+    f32 = np.float32
+    x = [f32(tup[0]), (f32(tup[1]) - f32(580)) * f32(0.005), (f32(tup[2]) - f32(3.5)) / f32(1.5),
+         f32(tup[3]) / f32(34)] + [f32(e) for e in sp["E"][pane]]
+    h = np.asarray(orc.bf16(np.array([float(v) for v in x])), dtype=np.float64).reshape(-1)
+    for k in (1, 2, 3, 4):
+        W = orc.bf16(sp[f"W{k}"].ravel()).reshape(sp[f"W{k}"].shape)
+        b = sp[f"b{k}"].astype(np.float32)
+        z = np.empty(W.shape[0])
+        order = [int(i) for i in perm if i < W.shape[1]]
+        for o in range(W.shape[0]):
+            s = f32(b[o])
+            for i in order:
+                s = f32(s + f32(W[o, i] * h[i]))
+            z[o] = s
+        if k < 4:
+            h = np.asarray(orc.bf16(np.maximum(z, 0.0)), dtype=np.float64).reshape(-1)
+    ea, eb = math.exp(z[0]), math.exp(z[1])
+    return np.array([ea / (ea + eb + 1), eb / (ea + eb + 1), z[2] if z[2] > 30 else math.log1p(math.exp(z[2]))])
+
+
+def test_bf16_bound_covers_fp32_summation(orc):
+    """orc_mlp_bf16_bound: its outputs are the BF16-mode forward's exactly,
+    and an FP32-sum evaluation (emulated in numpy, two summation orders, with
+    the cos and thickness inputs moved by up to the stated input errors) lies
+    within the bound; the bound is not vacuous (typically a few 1e-6; larger
+    only where a BF16 re-rounding may go either way)."""
+    rng = np.random.default_rng(12)
+    n_panes = 3
+    p = surrogate.init_params(n_panes, seed=4).astype(np.float64)
+    sp = surrogate.split(p, n_panes)
+    sp["b4"][:] = [-1.0, 0.5, -2.0]
+    sp["E"][:] *= 8.0
+    tup, pane = _batch(rng, 40, n_panes)
+    worst, bounds = 0.0, []
+    for s in range(len(tup)):
+        e_cos, e_d = 3e-7, 2e-6
+        out, bnd = orc.mlp_bf16_bound(p, tup[s], pane[s], e_cos, e_d)
+        ref = orc.mlp_forward_bf16(p, n_panes, tup[s:s + 1], pane[s:s + 1])[0]
+        assert np.array_equal(out, ref)
+        bounds.append(bnd)
+        for perm in (np.arange(64), rng.permutation(64)):
+            for dc, dd in ((0.0, 0.0), (e_cos, -e_d), (-e_cos, e_d)):
+                t = tup[s].copy()
+                t[0] += dc
+                t[2] += dd
+                got = _fp32_sum_forward(orc, p, n_panes, t, pane[s], perm)
+                err = np.abs(got - out)
+                assert np.all(err <= bnd), (s, err, bnd)
+                worst = max(worst, float((err / bnd).max()))
+    assert worst > 1e-3        # the emulation does differ from the FP64 sums
+    assert np.median(bounds) < 1e-4

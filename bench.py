@@ -495,6 +495,51 @@ def large_bench(args):
     ctx.close()
 
 
+def maps_bench(args):
+    """Distribution maps: the benchmark nave with every pane's optical
+    constants and thickness taken from its own stained-glass map (6 x 16
+    texels, six tile glasses and a yellow edging) against the same nave with
+    per-pane glass, both at 512 x 512, 64 spp, 81 wavelengths, depth 8."""
+    import torch
+    from paper_1912_05494_amd import sdm, synth
+
+    ctx = sdm.Context(0)
+    st = synth.nave_settings()
+    W, H, nl = st.camera.W, st.camera.H, len(st.lambda_nm)
+    dev = torch.device("cuda", 0)
+    spec = torch.empty((H, W, nl), dtype=torch.float32, device=dev)
+    xyz = torch.empty((H, W, 3), dtype=torch.float64, device=dev)
+    forms = {}
+    for form, scene in (("per_pane_glass", synth.nave_scene()), ("distribution_maps", synth.nave_scene(dist_maps=True))):
+        gs = sdm.Scene(ctx, scene)
+        params, keep = sdm.make_params(st, timing=True)
+        for _ in range(args.warmup):
+            s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        forms[form] = {"value": W * H * st.spp * nl / dt, "ms_per_step": dt * 1e3,
+                       "kernel_ms": {k: v for k, v in s_["kernel_ms"].items() if v > 0}}
+        print(f"{form}: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        gs.close()
+    out = {
+        "metric": "spectral ray samples/sec (nave with stained-glass distribution maps)",
+        "value": forms["distribution_maps"]["value"], "unit": "spectral ray samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": forms["distribution_maps"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "procedural church nave, 24 panes each with a 6x16-texel map of 7 glasses and "
+                               "per-texel thickness, 512x512, 64 spp, 81 wavelengths, depth 8"},
+        "forms": forms,
+        "maps_speed_vs_per_pane_glass": forms["distribution_maps"]["value"] / forms["per_pane_glass"]["value"],
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def batch_bench(args):
     """The uneven 32-job batch (square sides 128-1024, 10k-200k triangles,
     8-81 wavelengths, 16-128 spp; scene seed 2 + job) as one wavefront,
@@ -553,11 +598,12 @@ def main():
     ap.add_argument("--no-band-split", action="store_true", help="skip the 4- and 16-band timings")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
-    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch", "table1", "large"],
+    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch", "table1", "large", "maps"],
                     help="plain: the clear-glass nave (default); bubbly: bubbly panes in four forms; "
                          "batch: the uneven 32-job batch in one wavefront; table1: the oracle's speedup "
                          "against threads x bands on the host (no GPU); large: the 1 M-triangle nave "
-                         "with 200 bubbly panes at 1920x1080, fallback against exact")
+                         "with 200 bubbly panes at 1920x1080, fallback against exact; maps: the nave with "
+                         "stained-glass distribution maps against per-pane glass")
     ap.add_argument("--batch-jobs", type=int, default=32)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--autotune", action="store_true",
@@ -593,6 +639,8 @@ def main():
         return
     if args.form == "large":
         return large_bench(args)
+    if args.form == "maps":
+        return maps_bench(args)
     if args.form == "bubbly":
         bubbly_bench(args)
         return

@@ -79,7 +79,29 @@ typedef struct {
     float bubble_density_mm3;   /* bubbly glass: air bubbles per mm^3, >= 0     */
     float bubble_rmin_um, bubble_rmax_um;   /* radius range (micrometres)      */
     int32_t pane_id;            /* bubbly glass: the network's pane type       */
+    /* Clear glass only: 0, or k > 0 to take the optical constants and the
+     * thickness at a hit from the scene's distribution map k - 1 (Sec. 6:
+     * distribution maps of optical constants and of thickness over the
+     * geometry, looked up through the hit's texture coordinates, Sec. 3.1). */
+    int32_t dist_map;
 } sdm_material;
+
+/* Distribution map (Sec. 6): a W x H grid of texels over texture space
+ * [0, 1]^2, row 0 at t = 0, column 0 at s = 0.  A hit at barycentric (u, v)
+ * of triangle (i0, i1, i2) has texture coordinates
+ * (s, t) = (1 - u - v) uv[i0] + u uv[i1] + v uv[i2].
+ * Optical constants: the material of texel (clamp(floor(s W), 0, W - 1),
+ * clamp(floor(t H), 0, H - 1)) -- an index of a clear-glass material of the
+ * scene, whose n, k and alpha_tint tables apply at that hit.
+ * Thickness: NULL keeps the triangle's thickness (vthick_mm, else the
+ * material's thick_mm); otherwise the bilinear interpolation of thick_mm
+ * with texel centres at ((x + 0.5) / W, (y + 0.5) / H), clamped at the
+ * edges.  Arrays are host memory, row-major, copied by sdm_scene_create. */
+typedef struct {
+    int32_t W, H;               /* texels, 1 .. 4096 each                     */
+    const int32_t *material;    /* [W*H] clear-glass material indices          */
+    const float *thick_mm;      /* [W*H] thickness (> 0), or NULL              */
+} sdm_dist_map;
 
 /* Scene.  Triangles are two-sided.  Units: metres, thickness in mm. */
 typedef struct {
@@ -97,6 +119,10 @@ typedef struct {
     const float *sun_E;         /* [n_tab] sun irradiance                       */
     const float *sky_L;         /* [n_tab] uniform sky radiance                 */
     int32_t shadow_walk;        /* SDM_SHADOW_AUTO or SDM_SHADOW_BVH            */
+    const float *uv;            /* [nv*2] texture coordinates, or NULL (required
+                                   when a material has a distribution map)     */
+    int32_t n_maps;
+    const sdm_dist_map *maps;   /* [n_maps]                                    */
 } sdm_scene_desc;
 
 typedef struct {

@@ -11,7 +11,7 @@ from .build import ensure_built
 __all__ = ["lib", "OracleScene", "philox", "u01", "fresnel", "slab", "snell_cos_t",
            "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir", "slab_mc",
            "fresnel_real", "bubble_dir", "mlp_nparams", "mlp_forward", "mlp_loss_grad", "walk_draw",
-           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "lobe_transmit", "mlp_bf16_bound", "slab_to_world",
+           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "lobe_transmit", "mlp_bf16_bound", "pane_at", "slab_to_world",
            "BTDF_MODES"]
 
 _lib = None
@@ -22,7 +22,13 @@ class _Material(C.Structure):
                 ("bubble_rmin_um", C.c_double), ("bubble_rmax_um", C.c_double),
                 ("pane_id", C.c_int32),
                 ("albedo", C.POINTER(C.c_double)), ("n", C.POINTER(C.c_double)),
-                ("k", C.POINTER(C.c_double)), ("alpha_tint", C.POINTER(C.c_double))]
+                ("k", C.POINTER(C.c_double)), ("alpha_tint", C.POINTER(C.c_double)),
+                ("dist_map", C.c_int32)]
+
+
+class _DistMap(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("material", C.POINTER(C.c_int32)),
+                ("thick_mm", C.POINTER(C.c_double))]
 
 
 class _SceneDesc(C.Structure):
@@ -31,7 +37,8 @@ class _SceneDesc(C.Structure):
                 ("idx", C.POINTER(C.c_int32)), ("mat", C.POINTER(C.c_int32)),
                 ("n_mat", C.c_int32), ("mats", C.POINTER(_Material)), ("n_tab", C.c_int32),
                 ("tab_lambda_nm", C.POINTER(C.c_double)), ("sun_dir", C.c_double * 3),
-                ("sun_E", C.POINTER(C.c_double)), ("sky_L", C.POINTER(C.c_double))]
+                ("sun_E", C.POINTER(C.c_double)), ("sky_L", C.POINTER(C.c_double)),
+                ("uv", C.POINTER(C.c_double)), ("n_maps", C.c_int32), ("maps", C.POINTER(_DistMap))]
 
 
 class _Params(C.Structure):
@@ -113,6 +120,7 @@ def lib():
         L.orc_bf16.argtypes = [C.c_double]
         L.orc_lobe_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.orc_lobe_transmit.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.orc_pane_at.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
         L.orc_mlp_bf16_bound.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p,
                                          C.c_void_p]
         L.orc_slab_to_world.argtypes = [C.c_void_p] * 4
@@ -181,12 +189,21 @@ class OracleScene:
             self._keep += arrs
             mats[i] = _Material(m.type, float(m.thick_mm), float(m.bubble_density),
                                 float(m.bubble_rmin_um), float(m.bubble_rmax_um), int(m.pane_id),
-                                *[_dp(a) for a in arrs])
+                                *[_dp(a) for a in arrs], int(getattr(m, "dist_map", 0)))
         sunE, skyL = f64(scene.sun_E), f64(scene.sky_L)
-        self._keep += [pos, vth, idx, mat, tab, mats, sunE, skyL]
+        uv = f64(None if getattr(scene, "uv", None) is None else np.asarray(scene.uv).reshape(-1))
+        smaps = list(getattr(scene, "maps", []) or [])
+        maps = (_DistMap * max(1, len(smaps)))()
+        for i, dm in enumerate(smaps):
+            tm = np.ascontiguousarray(np.asarray(dm.material).reshape(-1), dtype=np.int32)
+            th = f64(None if dm.thick_mm is None else np.asarray(dm.thick_mm).reshape(-1))
+            self._keep += [tm, th]
+            maps[i] = _DistMap(int(dm.W), int(dm.H), _ip(tm), _dp(th))
+        self._keep += [pos, vth, idx, mat, tab, mats, sunE, skyL, uv, maps]
         d = _SceneDesc(len(scene.pos), _dp(pos), _dp(vth), int(scene.idx.shape[0]), _ip(idx),
                        _ip(mat), len(scene.materials), mats, len(tab), _dp(tab),
-                       (C.c_double * 3)(*[float(x) for x in scene.sun_dir]), _dp(sunE), _dp(skyL))
+                       (C.c_double * 3)(*[float(x) for x in scene.sun_dir]), _dp(sunE), _dp(skyL),
+                       _dp(uv), len(smaps), maps)
         self.ptr = lib().orc_scene_create(C.byref(d))
         if not self.ptr:
             raise ValueError("oracle rejected the scene description")
@@ -392,6 +409,14 @@ def mlp_bf16_bound(params, tup, pane, e_cos=0.0, e_d=0.0):
     lib().orc_mlp_bf16_bound(p.ctypes.data, t.ctypes.data, int(pane), float(e_cos), float(e_d), out.ctypes.data,
                              bnd.ctypes.data)
     return out, bnd
+
+
+def pane_at(oscene, t, u, v):
+    """(material, thickness mm) of the pane of triangle t at barycentric (u, v)."""
+    m = C.c_int32()
+    d = C.c_double()
+    lib().orc_pane_at(oscene.ptr, int(t), float(u), float(v), C.byref(m), C.byref(d))
+    return int(m.value), float(d.value)
 
 
 def lobe_transmit(d, ng, w, u1, u2):

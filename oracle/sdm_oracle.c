@@ -155,7 +155,15 @@ typedef struct {
     double *albedo, *n, *k, *tint; /* owned copies [n_tab] */
     double density, rmin_um, rmax_um; /* bubbly glass */
     int32_t pane_id;
+    int32_t map;                       /* distribution map index, -1 none */
 } omat;
+
+typedef struct {
+    int32_t W, H;
+    int32_t *material;                 /* owned [W*H] */
+    double *thick;                     /* owned [W*H] or NULL */
+    double gthick;                     /* largest thickness change per unit of s or t */
+} omap;
 
 struct orc_scene {
     int32_t nv, nt, n_mat, n_tab;
@@ -169,6 +177,9 @@ struct orc_scene {
     int32_t n_nodes;
     int32_t *order; /* triangle ids in leaf order */
     int32_t depth;
+    double *uv;     /* [nv*2] or NULL */
+    int32_t n_maps;
+    omap *maps;
 };
 
 static double *dup_d(const double *p, int64_t n)
@@ -270,6 +281,18 @@ orc_scene *orc_scene_create(const orc_scene_desc *d)
         const orc_material *mm = &d->mats[m];
         if (mm->type == ORC_LAMBERT && !mm->albedo) return NULL;
         if (mm->type != ORC_LAMBERT && (!mm->n || !mm->k)) return NULL;
+        if (mm->dist_map != 0 && (mm->type != ORC_GLASS || mm->dist_map < 0 || mm->dist_map > d->n_maps || !d->uv))
+            return NULL;
+    }
+    if (d->n_maps < 0 || (d->n_maps > 0 && !d->maps)) return NULL;
+    for (int32_t q = 0; q < d->n_maps; ++q) {
+        const orc_dist_map *dm = &d->maps[q];
+        if (dm->W < 1 || dm->H < 1 || !dm->material) return NULL;
+        for (int64_t x = 0; x < (int64_t)dm->W * dm->H; ++x) {
+            int32_t tm = dm->material[x];
+            if (tm < 0 || tm >= d->n_mat || d->mats[tm].type != ORC_GLASS || d->mats[tm].dist_map != 0) return NULL;
+            if (dm->thick_mm && !(dm->thick_mm[x] > 0.0)) return NULL;
+        }
     }
     orc_scene *s = (orc_scene *)calloc(1, sizeof(orc_scene));
     s->nv = d->nv; s->nt = d->nt; s->n_mat = d->n_mat; s->n_tab = d->n_tab;
@@ -294,6 +317,30 @@ orc_scene *orc_scene_create(const orc_scene_desc *d)
         s->mats[m].rmin_um = mm->bubble_rmin_um;
         s->mats[m].rmax_um = mm->bubble_rmax_um;
         s->mats[m].pane_id = mm->pane_id;
+        s->mats[m].map = mm->dist_map - 1;
+    }
+    s->uv = dup_d(d->uv, 2 * (int64_t)d->nv);
+    s->n_maps = d->n_maps;
+    s->maps = (omap *)calloc((size_t)(d->n_maps + 1), sizeof(omap));
+    for (int32_t q = 0; q < d->n_maps; ++q) {
+        const orc_dist_map *dm = &d->maps[q];
+        omap *M = &s->maps[q];
+        size_t n = (size_t)dm->W * dm->H;
+        M->W = dm->W;
+        M->H = dm->H;
+        M->material = (int32_t *)malloc(sizeof(int32_t) * n);
+        memcpy(M->material, dm->material, sizeof(int32_t) * n);
+        M->thick = dup_d(dm->thick_mm, (int64_t)n);
+        /* the bilinear surface's slope is at most the largest difference of
+         * neighbouring texels times texels per unit */
+        M->gthick = 0.0;
+        if (M->thick)
+            for (int32_t y = 0; y < M->H; ++y)
+                for (int32_t x = 0; x < M->W; ++x) {
+                    double t0 = M->thick[y * M->W + x];
+                    if (x + 1 < M->W) M->gthick = fmax(M->gthick, fabs(M->thick[y * M->W + x + 1] - t0) * M->W);
+                    if (y + 1 < M->H) M->gthick = fmax(M->gthick, fabs(M->thick[(y + 1) * M->W + x] - t0) * M->H);
+                }
     }
     s->tab_lambda = dup_d(d->tab_lambda_nm, d->n_tab);
     s->sun_E = dup_d(d->sun_E, d->n_tab);
@@ -340,6 +387,8 @@ void orc_scene_destroy(orc_scene *s)
     }
     free(s->mats); free(s->pos); free(s->vthick); free(s->ng); free(s->idx); free(s->mat);
     free(s->tab_lambda); free(s->sun_E); free(s->sky_L); free(s->nodes); free(s->order);
+    for (int32_t q = 0; q < s->n_maps; ++q) { free(s->maps[q].material); free(s->maps[q].thick); }
+    free(s->maps); free(s->uv);
     free(s);
 }
 
@@ -474,12 +523,105 @@ static double glass_sensitivity(const orc_render_params *p, const orc_scene *s, 
     return p->prec_ceps / c + alpha * thickness_grad(s, t) * h / ct;
 }
 
+static void tex_at(const orc_scene *s, int32_t t, double u, double v, double st[2]);
+
+/* As glass_sensitivity, for the pane of triangle t hit at barycentric (u, v)
+ * with hit error h, whose optical constants or thickness may come from a
+ * distribution map.  The texture coordinates move by the hit error through
+ * the barycentric gradients, plus a few roundings of their interpolation; a
+ * hit whose coordinates may cross a texel edge may take another texel's
+ * material, and the bound then covers any value (1e30); a thickness table
+ * moves by its slope times that error. */
+static double pane_sensitivity(const orc_render_params *p, const orc_scene *s, int32_t t, double u, double v,
+                               double h, double c, double n, double alpha)
+{
+    int32_t mp = s->mats[s->mat[t]].map;
+    if (mp < 0) return glass_sensitivity(p, s, t, h, c, n, alpha);
+    if (!(c > 0.0)) return 1e30;
+    const omap *M = &s->maps[mp];
+    const double *p0 = s->pos + 3 * s->idx[3 * t], *p1 = s->pos + 3 * s->idx[3 * t + 1],
+                 *p2 = s->pos + 3 * s->idx[3 * t + 2];
+    double e1[3], e2[3], N[3], gu[3], gv[3];
+    sub3(p1, p0, e1);
+    sub3(p2, p0, e2);
+    cross3(e1, e2, N);
+    double nn = dot3(N, N);
+    if (!(nn > 0.0)) return 1e30;
+    cross3(e2, N, gu);
+    cross3(N, e1, gv);
+    const double *q0 = s->uv + 2 * s->idx[3 * t], *q1 = s->uv + 2 * s->idx[3 * t + 1],
+                 *q2 = s->uv + 2 * s->idx[3 * t + 2];
+    double st[2], es[2];
+    tex_at(s, t, u, v, st);
+    const double ulp = 0.5 * p->prec_eps;
+    for (int a = 0; a < 2; ++a) {
+        double g[3];
+        for (int k = 0; k < 3; ++k) g[k] = ((q1[a] - q0[a]) * gu[k] + (q2[a] - q0[a]) * gv[k]) / nn;
+        es[a] = sqrt(dot3(g, g)) * h +
+                8.0 * ulp * (fabs(q0[a]) + fabs(q1[a]) + fabs(q2[a]) + fabs(st[a]) + 1.0);
+    }
+    const int32_t dims[2] = {M->W, M->H};
+    for (int a = 0; a < 2; ++a) {
+        double x = st[a] * dims[a], ke = nearbyint(x);
+        if (ke >= 1.0 && ke <= (double)(dims[a] - 1) && fabs(x - ke) <= es[a] * dims[a] * 1.01 + 8.0 * ulp * fabs(x))
+            return 1e30;
+    }
+    int32_t me;
+    double d;
+    orc_pane_at(s, t, u, v, &me, &d);
+    double dd = M->thick ? M->gthick * fmax(es[0], es[1]) : thickness_grad(s, t) * h;
+    dd += 8.0 * ulp * d;
+    double sn = sqrt(fmax(0.0, 1.0 - c * c)) / n, ct = sqrt(fmax(1e-300, 1.0 - sn * sn));
+    return p->prec_ceps / c + alpha * dd / ct;
+}
+
 static double thickness_at(const orc_scene *s, int32_t t, double u, double v)
 {
     const omat *m = &s->mats[s->mat[t]];
     if (!s->vthick) return m->thick_mm;
     return (1.0 - u - v) * s->vthick[s->idx[3 * t]] + u * s->vthick[s->idx[3 * t + 1]] +
            v * s->vthick[s->idx[3 * t + 2]];
+}
+
+/* Texture coordinates of barycentric (u, v) on triangle t. */
+static void tex_at(const orc_scene *s, int32_t t, double u, double v, double st[2])
+{
+    const double *q0 = s->uv + 2 * s->idx[3 * t], *q1 = s->uv + 2 * s->idx[3 * t + 1],
+                 *q2 = s->uv + 2 * s->idx[3 * t + 2];
+    for (int a = 0; a < 2; ++a) st[a] = (1.0 - u - v) * q0[a] + u * q1[a] + v * q2[a];
+}
+
+static int32_t clampi(double x, int32_t n)
+{
+    return x < 0.0 ? 0 : (x > (double)(n - 1) ? n - 1 : (int32_t)x);
+}
+
+/* Distribution maps (Sec. 6; texture coordinates of the hit, Sec. 3.1): the
+ * texel under the hit gives the material; the thickness table, when there
+ * is one, is interpolated bilinearly between texel centres. */
+void orc_pane_at(const orc_scene *s, int32_t t, double u, double v, int32_t *material, double *thick_mm)
+{
+    int32_t m = s->mat[t];
+    *material = m;
+    int32_t mp = s->mats[m].map;
+    if (mp < 0) {
+        *thick_mm = thickness_at(s, t, u, v);
+        return;
+    }
+    const omap *M = &s->maps[mp];
+    double st[2];
+    tex_at(s, t, u, v, st);
+    *material = M->material[clampi(floor(st[1] * M->H), M->H) * M->W + clampi(floor(st[0] * M->W), M->W)];
+    if (!M->thick) {
+        *thick_mm = thickness_at(s, t, u, v);
+        return;
+    }
+    double xs = st[0] * M->W - 0.5, ys = st[1] * M->H - 0.5;
+    double x0 = floor(xs), y0 = floor(ys), fx = xs - x0, fy = ys - y0;
+    int32_t xa = clampi(x0, M->W), xb = clampi(x0 + 1.0, M->W), ya = clampi(y0, M->H), yb = clampi(y0 + 1.0, M->H);
+    const double *T = M->thick;
+    *thick_mm = (1.0 - fy) * ((1.0 - fx) * T[ya * M->W + xa] + fx * T[ya * M->W + xb]) +
+                fy * ((1.0 - fx) * T[yb * M->W + xa] + fx * T[yb * M->W + xb]);
 }
 
 /* Per-render material values at the render wavelengths. */
@@ -548,20 +690,22 @@ static double shadow_T(const orc_scene *s, const spectra *sp, int use_bvh, const
             pane_sum += event_hash(3ULL << 56 | (uint32_t)t);
             double R, Tr;
             double c = fabs(dot3(d, s->ng + 3 * t));
-            int32_t mi = s->mat[t];
+            int32_t mi;
+            double thick;
+            orc_pane_at(s, t, u, v, &mi, &thick);
             if (pb_s) {
                 double xh[3];
                 for (int a = 0; a < 3; ++a) xh[a] = x[a] + tt * d[a];
                 double alpha = 4.0 * PI * sp->k[mi * sp->nl + li] / (lambda_nm * 1e-6) + sp->tint[mi * sp->nl + li] +
                                sp->sigma[mi];
-                *pb_s += pb_p->prec_rel + glass_sensitivity(pb_p, s, t, hit_error(pb_p, pb_e, tt, c, xh), c,
-                                                            sp->n[mi * sp->nl + li], alpha);
+                *pb_s += pb_p->prec_rel + pane_sensitivity(pb_p, s, t, u, v, hit_error(pb_p, pb_e, tt, c, xh), c,
+                                                           sp->n[mi * sp->nl + li], alpha);
             }
             /* Reading: toward the delta sun only the unscattered (ballistic)
              * light of a bubbly pane counts, so the bubbles' extinction adds
              * to the absorption of the slab. */
-            orc_slab(c, lambda_nm, thickness_at(s, t, u, v), sp->n[mi * sp->nl + li],
-                     sp->k[mi * sp->nl + li], sp->tint[mi * sp->nl + li] + sp->sigma[mi], &R, &Tr);
+            orc_slab(c, lambda_nm, thick, sp->n[mi * sp->nl + li], sp->k[mi * sp->nl + li],
+                     sp->tint[mi * sp->nl + li] + sp->sigma[mi], &R, &Tr);
             T *= Tr;
         }
     }
@@ -939,14 +1083,17 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64
              * reflects with probability R/(R+T), else passes straight
              * through; the weight is R + T. */
             double cos_i = fabs(dot3(d, ng));
-            double thick = thickness_at(s, h.tri, h.u, h.v);
+            int32_t me;
+            double thick;
+            orc_pane_at(s, h.tri, h.u, h.v, &me, &thick);
             if (pb && vtx < p->max_depth - 1) {
-                double alpha = 4.0 * PI * sp->k[mi * sp->nl + li] / (lambda * 1e-6) + sp->tint[mi * sp->nl + li];
-                sbeta += p->prec_rel + glass_sensitivity(p, s, h.tri, epos, cos_i, sp->n[mi * sp->nl + li], alpha);
+                double alpha = 4.0 * PI * sp->k[me * sp->nl + li] / (lambda * 1e-6) + sp->tint[me * sp->nl + li];
+                sbeta += p->prec_rel + pane_sensitivity(p, s, h.tri, h.u, h.v, epos, cos_i, sp->n[me * sp->nl + li],
+                                                        alpha);
             }
             double R, T;
-            orc_slab(cos_i, lambda, thick, sp->n[mi * sp->nl + li], sp->k[mi * sp->nl + li],
-                     sp->tint[mi * sp->nl + li], &R, &T);
+            orc_slab(cos_i, lambda, thick, sp->n[me * sp->nl + li], sp->k[me * sp->nl + li],
+                     sp->tint[me * sp->nl + li], &R, &T);
             if (vtx == p->max_depth - 1) break;
             if (R + T > 0.0 && u[0] < R / (R + T)) {
                 double dn = dot3(d, ng);

@@ -47,7 +47,19 @@ typedef struct {
     const double *n;          /* [n_tab] or NULL */
     const double *k;          /* [n_tab] or NULL */
     const double *alpha_tint; /* [n_tab] mm^-1 or NULL */
+    int32_t dist_map;         /* clear glass: 1 + index of its distribution map, 0 none */
 } orc_material;
+
+/* Distribution map (Sec. 6): W x H texels over texture space [0, 1]^2, row 0
+ * at t = 0.  At texture coordinates (s, t) a pane takes the material of
+ * texel (clamp(floor(s W), 0, W - 1), clamp(floor(t H), 0, H - 1)) and, with
+ * a thickness table, the bilinear interpolation of the texel thicknesses with
+ * texel centres at ((x + 0.5) / W, (y + 0.5) / H), clamped at the edges. */
+typedef struct {
+    int32_t W, H;
+    const int32_t *material;  /* [W*H] clear-glass material indices */
+    const double *thick_mm;   /* [W*H] or NULL (the triangle's own thickness) */
+} orc_dist_map;
 
 typedef struct {
     int32_t nv;
@@ -63,6 +75,9 @@ typedef struct {
     double sun_dir[3];        /* unit vector toward the sun */
     const double *sun_E;      /* [n_tab] */
     const double *sky_L;      /* [n_tab] */
+    const double *uv;         /* [nv*2] texture coordinates, or NULL */
+    int32_t n_maps;
+    const orc_dist_map *maps; /* [n_maps] */
 } orc_scene_desc;
 
 typedef struct {
@@ -129,6 +144,10 @@ double orc_u01(uint32_t x);
 
 /* Interface Fresnel reflectance, air -> n + ik, per polarisation. */
 void orc_fresnel(double cos_i, double n, double k, double *Rs, double *Rp);
+/* Material and thickness of the pane of triangle t at barycentric (u, v):
+ * with a distribution map, its texel's material and thickness (see
+ * orc_dist_map); otherwise the triangle's material and thickness. */
+void orc_pane_at(const orc_scene *s, int32_t t, double u, double v, int32_t *material, double *thick_mm);
 /* Thin slab: incoherent multiple reflection with Beer-Lambert attenuation. */
 void orc_slab(double cos_i, double lambda_nm, double d_mm, double n, double k,
               double alpha_tint, double *R, double *T);

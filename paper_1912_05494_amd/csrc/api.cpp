@@ -202,6 +202,38 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
             return fail(ctx, SDM_E_INVALID, "material %d has an unknown type %d", m, mm.type);
         }
     }
+    // distribution maps
+    if (d->n_maps < 0 || (d->n_maps > 0 && !d->maps)) return fail(ctx, SDM_E_INVALID, "bad distribution map list");
+    bool any_map = false;
+    for (int32_t m = 0; m < d->n_mat; ++m) {
+        const sdm_material &mm = d->mats[m];
+        if (mm.dist_map == 0) continue;
+        if (mm.type != SDM_GLASS)
+            return fail(ctx, SDM_E_UNSUPPORTED, "material %d: distribution maps apply to clear glass only", m);
+        if (mm.dist_map < 0 || mm.dist_map > d->n_maps)
+            return fail(ctx, SDM_E_INVALID, "material %d names distribution map %d of %d", m, mm.dist_map - 1,
+                        d->n_maps);
+        any_map = true;
+    }
+    if (any_map && !d->uv) return fail(ctx, SDM_E_INVALID, "distribution maps need per-vertex uv");
+    for (int32_t q = 0; q < d->n_maps; ++q) {
+        const sdm_dist_map &dm = d->maps[q];
+        if (dm.W < 1 || dm.H < 1 || dm.W > 4096 || dm.H > 4096 || !dm.material)
+            return fail(ctx, SDM_E_INVALID, "distribution map %d needs 1 <= W, H <= 4096 and materials", q);
+        for (int64_t x = 0; x < (int64_t)dm.W * dm.H; ++x) {
+            const int32_t tm = dm.material[x];
+            if (tm < 0 || tm >= d->n_mat || d->mats[tm].type != SDM_GLASS || d->mats[tm].dist_map != 0)
+                return fail(ctx, SDM_E_INVALID,
+                            "distribution map %d: texel %lld must name a clear-glass material without a map", q,
+                            (long long)x);
+            if (dm.thick_mm && !(dm.thick_mm[x] > 0.0f && dm.thick_mm[x] < 1e6f))
+                return fail(ctx, SDM_E_INVALID, "distribution map %d: texel %lld thickness must be > 0", q,
+                            (long long)x);
+        }
+    }
+    if (d->uv)
+        for (int64_t i = 0; i < 2 * (int64_t)d->nv; ++i)
+            if (!std::isfinite(d->uv[i])) return fail(ctx, SDM_E_INVALID, "uv must be finite");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     auto *sc = new sdm_scene();
     sc->ctx = ctx;
@@ -230,6 +262,16 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
             dg.add_value(mm.pane_id);
             for (const float *t : {mm.albedo, mm.n, mm.k, mm.alpha_tint})
                 if (t) dg.add(t, sizeof(float) * (size_t)d->n_tab);
+            dg.add_value(mm.dist_map);
+        }
+        if (d->uv) dg.add(d->uv, sizeof(float) * 2 * (size_t)d->nv);
+        dg.add_value(d->n_maps);
+        for (int32_t q = 0; q < d->n_maps; ++q) {
+            const sdm_dist_map &dm = d->maps[q];
+            dg.add_value(dm.W);
+            dg.add_value(dm.H);
+            dg.add(dm.material, sizeof(int32_t) * (size_t)dm.W * dm.H);
+            if (dm.thick_mm) dg.add(dm.thick_mm, sizeof(float) * (size_t)dm.W * dm.H);
         }
         sc->digest = dg.h;
     }
@@ -349,6 +391,35 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     chk(upload(sc->mat_type, mtype.data(), mtype.size()));
     chk(upload(sc->mat_thick, mthick.data(), mthick.size()));
     chk(upload(sc->mat_bub, mbub.data(), mbub.size()));
+    if (any_map) {
+        std::vector<int32_t> mmap(d->n_mat);
+        for (int32_t m = 0; m < d->n_mat; ++m) mmap[m] = d->mats[m].dist_map - 1;
+        std::vector<int4> hdr(d->n_maps);
+        std::vector<int32_t> tmat;
+        std::vector<float> tthick;
+        for (int32_t q = 0; q < d->n_maps; ++q) {
+            const sdm_dist_map &dm = d->maps[q];
+            const size_t n = (size_t)dm.W * dm.H;
+            hdr[q] = make_int4(dm.W, dm.H, (int)tmat.size(), dm.thick_mm ? 1 : 0);
+            tmat.insert(tmat.end(), dm.material, dm.material + n);
+            if (dm.thick_mm) tthick.insert(tthick.end(), dm.thick_mm, dm.thick_mm + n);
+            else tthick.insert(tthick.end(), n, 0.0f);
+        }
+        std::vector<float4> tuv(2 * (size_t)d->nt);
+        for (int32_t l = 0; l < d->nt; ++l) {
+            const int32_t t = bvh.order[l];
+            const float *q0 = d->uv + 2 * (size_t)d->idx[3 * (size_t)t];
+            const float *q1 = d->uv + 2 * (size_t)d->idx[3 * (size_t)t + 1];
+            const float *q2 = d->uv + 2 * (size_t)d->idx[3 * (size_t)t + 2];
+            tuv[2 * (size_t)l] = make_float4(q0[0], q0[1], q1[0], q1[1]);
+            tuv[2 * (size_t)l + 1] = make_float4(q2[0], q2[1], 0.0f, 0.0f);
+        }
+        chk(upload(sc->mat_map, mmap.data(), mmap.size()));
+        chk(upload(sc->map_hdr, hdr.data(), hdr.size()));
+        chk(upload(sc->map_mat, tmat.data(), tmat.size()));
+        chk(upload(sc->map_thick, tthick.data(), tthick.size()));
+        chk(upload(sc->tri_uv, tuv.data(), tuv.size()));
+    }
     chk(upload(sc->tab_x, d->tab_lambda_nm, (size_t)d->n_tab));
     chk(upload(sc->tab_mat, tabm.data(), tabm.size()));
     chk(upload(sc->tab_sun, d->sun_E, (size_t)d->n_tab));
@@ -389,6 +460,12 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     sc->grid_cands = (int64_t)grid.cand.size();
     sd.teps_d = 1e-6 * diag;
     sd.teps_f = (float)sd.teps_d;
+    sd.n_maps = any_map ? d->n_maps : 0;
+    sd.mat_map = any_map ? sc->mat_map.as<int32_t>() : nullptr;
+    sd.map_hdr = any_map ? sc->map_hdr.as<int4>() : nullptr;
+    sd.map_mat = any_map ? sc->map_mat.as<int32_t>() : nullptr;
+    sd.map_thick = any_map ? sc->map_thick.as<float>() : nullptr;
+    sd.tri_uv = any_map ? sc->tri_uv.as<float4>() : nullptr;
     *out = sc;
     return SDM_OK;
 }

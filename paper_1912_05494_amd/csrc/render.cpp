@@ -499,7 +499,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
                               (size_t)cap * nb * sizeof(R) + 8 * 256;
         const size_t hit_b = (size_t)cap * sizeof(HitRec<R>) + (size_t)cap * 4 + (size_t)cap * sizeof(GlassRec<R>) + 256;
         const size_t sh_b = 4 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
-                            (size_t)cap * kMaxGlass * (4 + 2 * sizeof(R)) + 12 * 256;
+                            (size_t)cap * kMaxGlass * (8 + sizeof(R)) + 12 * 256;
         HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
         HIPCHK(ctx, ctx->hits.ensure(hit_b + 2048));
         HIPCHK(ctx, ctx->shadowq.ensure(sh_b + 2048));
@@ -551,8 +551,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         w.scs = (R *)take(plane);
         w.contrib = (R *)take((size_t)cap * nb * sizeof(R));
         w.sg_leaf = (int32_t *)take((size_t)cap * kMaxGlass * 4);
-        w.sg_u = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
-        w.sg_v = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
+        w.sg_d = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
+        w.sg_m = (int32_t *)take((size_t)cap * kMaxGlass * sizeof(int32_t));
         w.acc = ctx->acc.as<double>();
         w.cnt = ctx->counters.as<Counters>();
         w.cap = cap;

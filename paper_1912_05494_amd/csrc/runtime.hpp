@@ -106,6 +106,7 @@ struct sdm_scene {
     sdm::SceneDev dev{};
     DevBuf nodes, tris, thick, mat_type, mat_thick, mat_bub, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
     DevBuf g_start, g_cand;     // sun grid (empty when shadow rays walk the BVH)
+    DevBuf mat_map, map_hdr, map_mat, map_thick, tri_uv;   // distribution maps
     int64_t grid_cells = 0, grid_cands = 0;
     int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
     int32_t stack = 0;          // most traversal stack entries a walk can hold

@@ -58,6 +58,16 @@ struct SceneDev {
     int32_t g_nx, g_ny, g_use;
     float teps_f;
     double teps_d;
+    // distribution maps (n_maps = 0: none): per material the map index or
+    // -1; per map (W, H, first texel, has thickness); texel materials and
+    // thicknesses; per leaf-order triangle its vertices' texture coordinates
+    // (s0, t0, s1, t1), (s2, t2, 0, 0)
+    const int32_t *mat_map;
+    const int4 *map_hdr;
+    const int32_t *map_mat;
+    const float *map_thick;
+    const float4 *tri_uv;
+    int32_t n_maps;
 };
 
 // One render job (an image of one scene).  Spectral tables are in the
@@ -209,8 +219,9 @@ struct Work {
     R *scs;                     // [record] scalar factor of the contributions
     R *contrib;                 // AoSoA [record][j] per-wavelength factors (kSpectral records)
     int32_t *socc;              // panes crossed (0..kMaxGlass), -1 occluded
-    int32_t *sg_leaf;           // [record][kMaxGlass]
-    R *sg_u, *sg_v;
+    int32_t *sg_leaf;           // [record][kMaxGlass] panes crossed, and at each crossing
+    R *sg_d;                    //   the pane's thickness and
+    int32_t *sg_m;              //   its material (distribution maps resolved)
     double *acc;
     Counters *cnt;
     uint32_t cap;               // slots of each pool and of the record buffer

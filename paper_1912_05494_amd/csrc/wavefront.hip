@@ -56,6 +56,12 @@ __device__ __forceinline__ float4 gld4(const float4 *p)
     const f4v v = *(const __attribute__((address_space(1))) f4v *)p;
     return make_float4(v.x, v.y, v.z, v.w);
 }
+typedef int i4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 gld4(const int4 *p)
+{
+    const i4v v = *(const __attribute__((address_space(1))) i4v *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
 template <class T>
 __device__ __forceinline__ T gld(const T *p)
 {
@@ -602,6 +608,44 @@ __device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, R u, R
     return (R(1) - u - v) * R(th.x) + u * R(th.y) + v * R(th.z);
 }
 
+// Material and thickness of a pane at barycentric (u, v) of leaf-order
+// triangle `leaf` whose own material is `mat`: with a distribution map (Sec.
+// 6), the material of the texel under the hit's texture coordinates and, if
+// the map has one, the bilinear thickness of its texel centres (clamped at
+// the edges); otherwise `mat` and the triangle's thickness.
+template <class R>
+__device__ __forceinline__ void pane_at(const SceneDev &sc, int leaf, int mat, R u, R v, int &m_out, R &d_out)
+{
+    m_out = mat;
+    const int mp = sc.n_maps > 0 ? gld(sc.mat_map + mat) : -1;
+    if (mp < 0) {
+        d_out = pane_thickness<R>(sc, leaf, u, v);
+        return;
+    }
+    const int4 hdr = gld4(sc.map_hdr + mp);
+    const float4 q01 = gld4(sc.tri_uv + 2 * leaf), q2 = gld4(sc.tri_uv + 2 * leaf + 1);
+    const R w0 = R(1) - u - v;
+    const R s = w0 * R(q01.x) + u * R(q01.z) + v * R(q2.x);
+    const R t = w0 * R(q01.y) + u * R(q01.w) + v * R(q2.y);
+    const int W = hdr.x, H = hdr.y;
+    const R fs = floor(s * R(W)), ft = floor(t * R(H));
+    const int ix = fs < R(0) ? 0 : (fs > R(W - 1) ? W - 1 : (int)fs);
+    const int iy = ft < R(0) ? 0 : (ft > R(H - 1) ? H - 1 : (int)ft);
+    m_out = gld(sc.map_mat + hdr.z + iy * W + ix);
+    if (!hdr.w) {
+        d_out = pane_thickness<R>(sc, leaf, u, v);
+        return;
+    }
+    const R xs = s * R(W) - R(0.5), ys = t * R(H) - R(0.5);
+    const R x0 = floor(xs), y0 = floor(ys), fx = xs - x0, fy = ys - y0;
+    auto cl = [](R a, int n) { return a < R(0) ? 0 : (a > R(n - 1) ? n - 1 : (int)a); };
+    const int xa = cl(x0, W), xb = cl(x0 + R(1), W), ya = cl(y0, H), yb = cl(y0 + R(1), H);
+    const float *T = sc.map_thick + hdr.z;
+    const R t00 = R(gld(T + ya * W + xa)), t10 = R(gld(T + ya * W + xb));
+    const R t01 = R(gld(T + yb * W + xa)), t11 = R(gld(T + yb * W + xb));
+    d_out = (R(1) - fy) * ((R(1) - fx) * t00 + fx * t10) + fy * ((R(1) - fx) * t01 + fx * t11);
+}
+
 // ---------------------------------------------------------------------------
 // Camera rays (Sec. 3.1: a ray from each pixel).  Image point ((i + u0) / W,
 // (j + u1) / H), row j from the top; pinhole through the unit-distance image
@@ -1114,12 +1158,13 @@ __global__ void __launch_bounds__(kBlock) k_shade_glass(const JobDev *__restrict
             const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
             u0 = u01<R>(rr.x);
             cos_i = fabs(dot(d, ng));
-            thick = pane_thickness<R>(jb->sc, tri, gr.u, gr.v);
+            int me;
+            pane_at<R>(jb->sc, tri, mat, gr.u, gr.v, me, thick);
             dnew = d;
             drefl = d - (R(2) * dot(d, ng)) * ng;
             flags = (spec ? kRowSrc : 0u) | ((bd.l0 & 3) == 0 ? kRowAl : 0u) | (uint32_t)bd.nb << kRowNbShift |
                     (uint32_t)bd.l0 << 16;
-            mo = (uint32_t)(mat * jb->ms + bd.l0);
+            mo = (uint32_t)(me * jb->ms + bd.l0);
         }
         // Per wavelength: the new factor b (R + T) goes back to the input
         // slot's row (a path without per-wavelength factors gets them here),
@@ -1743,9 +1788,13 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
                     over = true;
                     return;
                 }
+                const SceneDev &scj = jobs[job].sc;
+                int m;
+                R dd;
+                pane_at<R>(scj, leaf, __float_as_int(load_tri(scj.tris, leaf).b.w), u, v, m, dd);
                 w.sg_leaf[(size_t)rec * kMaxGlass + ng] = leaf;
-                w.sg_u[(size_t)rec * kMaxGlass + ng] = u;
-                w.sg_v[(size_t)rec * kMaxGlass + ng] = v;
+                w.sg_d[(size_t)rec * kMaxGlass + ng] = dd;
+                w.sg_m[(size_t)rec * kMaxGlass + ng] = m;
                 ++ng;
             };
             bool fin;
@@ -1806,8 +1855,8 @@ __device__ __forceinline__ void pane_geometry(const JobDev *jb, const Work<R> &w
     const int leaf = w.sg_leaf[(size_t)rec * kMaxGlass + g];
     const TriDev tr = load_tri(jb->sc.tris, leaf);
     c = fabs(dot(sun, tri_normal<R>(tr)));
-    d = pane_thickness<R>(jb->sc, leaf, w.sg_u[(size_t)rec * kMaxGlass + g], w.sg_v[(size_t)rec * kMaxGlass + g]);
-    m = __float_as_int(tr.b.w);
+    d = w.sg_d[(size_t)rec * kMaxGlass + g];
+    m = w.sg_m[(size_t)rec * kMaxGlass + g];
     // toward the delta sun a bubbly pane passes its unscattered light: the
     // bubbles' extinction adds to the absorption
     sig = R(gld(jb->sc.mat_bub + 4 * m));
@@ -2254,10 +2303,12 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
         if (item >= 0) {
             auto on_glass = [&](int leaf, float u, float v) {
                 const TriDev tr = load_tri(sc.tris, leaf);
-                const int mt = __float_as_int(tr.b.w);
+                int mt;
+                float dm;
+                pane_at<float>(sc, leaf, __float_as_int(tr.b.w), u, v, mt, dm);
                 float Rr, Tt;
-                slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm, pane_thickness<float>(sc, leaf, u, v),
-                               n_at[mt], k_at[mt], t_at[mt] + (float)gld(sc.mat_bub + 4 * mt), Rr, Tt);
+                slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm, dm, n_at[mt], k_at[mt],
+                               t_at[mt] + (float)gld(sc.mat_bub + 4 * mt), Rr, Tt);
                 prod *= Tt;
             };
             // the walk of the render: the sun grid where the scene has one (test

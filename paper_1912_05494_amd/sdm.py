@@ -30,7 +30,11 @@ class Material(C.Structure):
     _fields_ = [("type", C.c_int32), ("albedo", _FP), ("n", _FP), ("k", _FP), ("alpha_tint", _FP),
                 ("thick_mm", C.c_float), ("bubble_density_mm3", C.c_float),
                 ("bubble_rmin_um", C.c_float), ("bubble_rmax_um", C.c_float),
-                ("pane_id", C.c_int32)]
+                ("pane_id", C.c_int32), ("dist_map", C.c_int32)]
+
+
+class DistMapDesc(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("material", C.POINTER(C.c_int32)), ("thick_mm", _FP)]
 
 
 class SceneDesc(C.Structure):
@@ -38,7 +42,8 @@ class SceneDesc(C.Structure):
                 ("idx", C.POINTER(C.c_int32)), ("mat", C.POINTER(C.c_int32)),
                 ("n_mat", C.c_int32), ("mats", C.POINTER(Material)), ("n_tab", C.c_int32),
                 ("tab_lambda_nm", _FP), ("sun_dir", C.c_float * 3), ("sun_E", _FP),
-                ("sky_L", _FP), ("shadow_walk", C.c_int32)]
+                ("sky_L", _FP), ("shadow_walk", C.c_int32), ("uv", _FP), ("n_maps", C.c_int32),
+                ("maps", C.POINTER(DistMapDesc))]
 
 
 class Camera(C.Structure):
@@ -229,14 +234,22 @@ class Scene:
             keep += arrs
             mats[i] = Material(int(m.type), *[fp(a) for a in arrs], float(m.thick_mm),
                                float(m.bubble_density), float(m.bubble_rmin_um),
-                               float(m.bubble_rmax_um), int(m.pane_id))
+                               float(m.bubble_rmax_um), int(m.pane_id), int(getattr(m, "dist_map", 0)))
         sE, sL = _f32(scene.sun_E), _f32(scene.sky_L)
-        keep += [pos, vth, idx, mat, tab, sE, sL]
+        uv = _f32(None if getattr(scene, "uv", None) is None else np.asarray(scene.uv).reshape(-1))
+        smaps = list(getattr(scene, "maps", []) or [])
+        maps = (DistMapDesc * max(1, len(smaps)))()
+        for i, dm in enumerate(smaps):
+            tm = np.ascontiguousarray(np.asarray(dm.material).reshape(-1), dtype=np.int32)
+            th = _f32(None if dm.thick_mm is None else np.asarray(dm.thick_mm).reshape(-1))
+            keep += [tm, th]
+            maps[i] = DistMapDesc(int(dm.W), int(dm.H), tm.ctypes.data_as(C.POINTER(C.c_int32)), fp(th))
+        keep += [pos, vth, idx, mat, tab, sE, sL, uv, maps]
         d = SceneDesc(len(scene.pos), fp(pos), fp(vth), int(scene.idx.shape[0]),
                       idx.ctypes.data_as(C.POINTER(C.c_int32)),
                       mat.ctypes.data_as(C.POINTER(C.c_int32)), len(scene.materials), mats,
                       len(tab), fp(tab), (C.c_float * 3)(*[float(x) for x in scene.sun_dir]),
-                      fp(sE), fp(sL), SHADOW_WALKS[shadow_walk])
+                      fp(sE), fp(sL), SHADOW_WALKS[shadow_walk], fp(uv), len(smaps), maps)
         self.ptr = C.c_void_p()
         ctx.check(lib().sdm_scene_create(ctx.ptr, C.byref(d), C.byref(self.ptr)), "sdm_scene_create")
         ctx._owned.add(self)

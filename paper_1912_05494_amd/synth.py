@@ -97,6 +97,18 @@ class Material:
     bubble_rmin_um: float = 10.0
     bubble_rmax_um: float = 200.0
     pane_id: int = 0
+    dist_map: int = 0                   # clear glass: 1 + index of its distribution map, 0 none
+
+
+@dataclasses.dataclass
+class DistMap:
+    """Distribution map (Sec. 6): W x H texels over texture space [0, 1]^2,
+    row 0 at t = 0; per texel a clear-glass material index and optionally a
+    thickness (mm)."""
+    W: int
+    H: int
+    material: np.ndarray                # (H, W) int32
+    thick_mm: Optional[np.ndarray] = None   # (H, W) float32 or None
 
 
 @dataclasses.dataclass
@@ -110,6 +122,8 @@ class Scene:
     sun_E: np.ndarray          # (n_tab,) float32
     sky_L: np.ndarray          # (n_tab,) float32
     vthick: Optional[np.ndarray] = None  # (nv,) float32 mm, or None
+    uv: Optional[np.ndarray] = None      # (nv, 2) float32 texture coordinates, or None
+    maps: list = dataclasses.field(default_factory=list)   # DistMap
 
     @property
     def nt(self):
@@ -150,7 +164,7 @@ def flat_table(value, n=81):
 # ----------------------------------------------------------------------------
 class _Mesh:
     def __init__(self):
-        self.pos, self.idx, self.mat = [], [], []
+        self.pos, self.idx, self.mat, self.uv = [], [], [], []
         self.nv = 0
 
     def grid(self, origin, ax_u, ax_v, nu, nv_, material, keep=None):
@@ -160,6 +174,7 @@ class _Mesh:
         p = o + ii[..., None] / nu * a + jj[..., None] / nv_ * b
         base = self.nv
         self.pos.append(p.reshape(-1, 3))
+        self.uv.append(np.stack([ii / nu, jj / nv_], -1).reshape(-1, 2))
         self.nv += (nu + 1) * (nv_ + 1)
         vid = lambda i, j: base + i * (nv_ + 1) + j
         tris = []
@@ -183,6 +198,7 @@ class _Mesh:
         p = fn(ss, tt)
         base = self.nv
         self.pos.append(p.reshape(-1, 3))
+        self.uv.append(np.stack([ss, tt], -1).reshape(-1, 2))
         self.nv += (nu + 1) * (nv_ + 1)
         i, j = np.meshgrid(np.arange(nu), np.arange(nv_), indexing="ij")
         a0 = base + i * (nv_ + 1) + j
@@ -200,6 +216,11 @@ class _Mesh:
         idx = np.concatenate(self.idx).astype(np.int32)
         mat = np.concatenate(self.mat).astype(np.int32)
         return pos, idx, mat
+
+    def uv_array(self):
+        """Texture coordinates of every vertex: a grid's or a parametric
+        surface's own (s, t) in [0, 1]^2."""
+        return np.concatenate(self.uv).astype(np.float32)
 
 
 # ----------------------------------------------------------------------------
@@ -246,9 +267,38 @@ def random_glass(rng, lam):
     return cauchy_n(lam, n0, b), flat_table(k, len(lam)), tint
 
 
+def stained_glass_palette(rng, lam, n_tiles=6):
+    """Glasses of a Cistercian window (Sec. 6): nearly clear tile glasses (n0
+    in [1.50, 1.56], weak tints) and one yellow glass for the edgings (a
+    strong absorption band at 440 nm).  Returns a list of (n, k, tint)."""
+    lam64 = lam.astype(np.float64)
+    out = []
+    for _ in range(n_tiles):
+        n0 = rng.uniform(1.50, 1.56)
+        k = 10.0 ** rng.uniform(-7.0, -6.0)
+        a, mu, sg = rng.uniform(0.0, 0.15), rng.uniform(400.0, 700.0), rng.uniform(40.0, 120.0)
+        out.append((cauchy_n(lam, n0, 0.0042), flat_table(k, len(lam)),
+                    (a * np.exp(-0.5 * ((lam64 - mu) / sg) ** 2)).astype(np.float32)))
+    yellow = (2.5 * np.exp(-0.5 * ((lam64 - 440.0) / 45.0) ** 2)).astype(np.float32)
+    out.append((cauchy_n(lam, 1.53, 0.0042), flat_table(1e-6, len(lam)), yellow))
+    return out
+
+
+def stained_glass_map(rng, first_material, n_tiles, W=6, H=16, thick=(2.0, 5.0)):
+    """One pane's distribution map: a border of yellow-edging texels around
+    tiles drawn from the n_tiles tile glasses (materials first_material ..
+    first_material + n_tiles - 1; the yellow glass follows them), each texel
+    with its own thickness."""
+    mat = first_material + rng.integers(0, n_tiles, size=(H, W))
+    mat[0, :] = mat[-1, :] = first_material + n_tiles
+    mat[:, 0] = mat[:, -1] = first_material + n_tiles
+    th = rng.uniform(*thick, size=(H, W)).astype(np.float32)
+    return DistMap(W=W, H=H, material=mat.astype(np.int32), thick_mm=th)
+
+
 def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=1,
                pane_grid=10, bubbly=False, rho_max=34.0, sun_elev=35.0, sun_azim=15.0, rho_min=0.0,
-               bubble_free=False, glass_types=None):
+               bubble_free=False, glass_types=None, dist_maps=False):
     """Procedural church nave, 60 x 12 x 20 m: floor, side walls with window
     openings (1.5 x 4 m), semicircular barrel vault, end walls and two rows of
     ten cylindrical columns; glass panes fill the openings.  Opaque parts are
@@ -260,7 +310,10 @@ def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=
     gives every pane its own glass (n, k, tint); an integer draws that many
     glasses and pane p takes glass p mod glass_types (its pane type), keeping
     its own density and thickness map.  Each pane is a pane_grid x pane_grid
-    quad grid."""
+    quad grid.  dist_maps (clear glass): every pane takes its optical
+    constants and thickness from its own stained-glass distribution map
+    (tiles of six nearly clear glasses with a yellow edging, Sec. 6), looked
+    up through the pane's texture coordinates; the other draws are unchanged."""
     rng = np.random.default_rng(seed)
     lam = LAMBDA_81
     L, Wd, Hw, R = 60.0, 12.0, 14.0, 6.0
@@ -301,6 +354,7 @@ def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=
         tp = np.asarray(tris_pos, dtype=np.float64).reshape(-1, 3)
         base = mesh.nv
         mesh.pos.append(tp)
+        mesh.uv.append(np.zeros((len(tp), 2)))      # opaque walls carry no map
         mesh.nv += len(tp)
         mesh.idx.append(base + np.arange(len(tp)).reshape(-1, 3))
         mesh.mat.append(np.full(len(tp) // 3, 1))
@@ -353,6 +407,17 @@ def nave_scene(seed=1, target_tris=40000, windows_per_side=12, panes_per_window=
     scene = Scene(pos=pos, idx=idx, mat=mat, materials=mats, tab_lambda=lam.copy(),
                   sun_dir=direction(sun_elev, 180.0 - sun_azim), sun_E=sun_irradiance(lam),
                   sky_L=sky_radiance(lam), vthick=vthick)
+    if dist_maps and not bubbly:
+        # a separate stream, so that the scene's other draws stay as they are
+        mrng = np.random.default_rng(seed + 7919)
+        first = len(mats)
+        palette = stained_glass_palette(mrng, lam)
+        for nn, kk, tint in palette:
+            mats.append(Material(GLASS, n=nn, k=kk, alpha_tint=tint, thick_mm=3.5))
+        for q in range(pane):
+            scene.maps.append(stained_glass_map(mrng, first, len(palette) - 1))
+            mats[pane_mat0 + q].dist_map = q + 1
+        scene.uv = mesh.uv_array()
     scene.n_opaque = n_opaque
     return scene
 

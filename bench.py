@@ -540,6 +540,60 @@ def maps_bench(args):
     ctx.close()
 
 
+def subdomains_bench(args):
+    """Geometric sub-domains (Sec. 5): the benchmark nave (512 x 512, 64 spp)
+    and the large nave (1920 x 1080, --subdomain-large-spp spp, depth 12)
+    rendered whole and cut into grids of cells; per cut the render time, the
+    closest-hit pass time, the rays handed across interfaces and the cells'
+    triangle references.  The images are identical to the uncut ones (the
+    sub-domain tests check it)."""
+    import torch
+    from paper_1912_05494_amd import sdm, synth
+
+    ctx = sdm.Context(0)
+    dev = torch.device("cuda", 0)
+    cases = [("nave", synth.nave_scene(), synth.nave_settings(), [(1, 1, 1), (4, 1, 1), (8, 2, 2), (16, 4, 4)]),
+             ("large", synth.large_scene(bubbly=False), synth.large_settings(spp=args.subdomain_large_spp),
+              [(1, 1, 1), (8, 2, 2), (16, 4, 4), (32, 8, 8)])]
+    results = {}
+    for name, scene, st, cuts in cases:
+        W, H, nl = st.camera.W, st.camera.H, len(st.lambda_nm)
+        spec = torch.empty((H, W, nl), dtype=torch.float32, device=dev)
+        xyz = torch.empty((H, W, 3), dtype=torch.float64, device=dev)
+        rows = []
+        for cut, handoff in [(c, m) for c in cuts for m in (("queue", "march") if c != (1, 1, 1) else ("queue",))]:
+            gs = sdm.Scene(ctx, scene, subdomains=cut, handoff=handoff)
+            params, keep = sdm.make_params(st, timing=True)
+            s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+            steps = args.steps if name == "nave" else 1
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            cells, refs, nodes = gs.subdomains()
+            rows.append({"cells": list(cells), "handoff": handoff, "ms_per_step": dt * 1e3, "value": W * H * st.spp * nl / dt,
+                         "trace_ms": s_["kernel_ms"]["trace"], "interface_rays": s_["interface_rays"],
+                         "closest_segments": s_["closest_segments"], "tri_refs": refs, "nodes": nodes,
+                         "nodes_visited": s_["nodes_visited"]["closest"],
+                         "tris_tested": s_["tris_tested"]["closest"]})
+            print(f"{name} {cut} {handoff}: {dt * 1e3:.2f} ms, trace {s_['kernel_ms']['trace']:.2f} ms, "
+                  f"{s_['interface_rays']} interface rays", file=sys.stderr, flush=True)
+            gs.close()
+        results[name] = {"workload": f"{len(scene.idx)} triangles, {W}x{H}, {st.spp} spp, {nl} wavelengths, "
+                                     f"depth {st.max_depth}", "cuts": rows}
+    best = min(results["large"]["cuts"][1:], key=lambda r: r["ms_per_step"])
+    out = {"metric": "spectral ray samples/sec (large nave, geometric sub-domains)", "value": best["value"],
+           "unit": "spectral ray samples/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic", "config": {"workload": results["large"]["workload"],
+                                                         "cells": best["cells"], "handoff": best["handoff"]},
+           "results": results}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def batch_bench(args):
     """The uneven 32-job batch (square sides 128-1024, 10k-200k triangles,
     8-81 wavelengths, 16-128 spp; scene seed 2 + job) as one wavefront,
@@ -598,18 +652,21 @@ def main():
     ap.add_argument("--no-band-split", action="store_true", help="skip the 4- and 16-band timings")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
-    ap.add_argument("--form", default="plain", choices=["plain", "bubbly", "batch", "table1", "large", "maps"],
+    ap.add_argument("--form", default="plain",
+                    choices=["plain", "bubbly", "batch", "table1", "large", "maps", "subdomains"],
                     help="plain: the clear-glass nave (default); bubbly: bubbly panes in four forms; "
                          "batch: the uneven 32-job batch in one wavefront; table1: the oracle's speedup "
                          "against threads x bands on the host (no GPU); large: the 1 M-triangle nave "
                          "with 200 bubbly panes at 1920x1080, fallback against exact; maps: the nave with "
-                         "stained-glass distribution maps against per-pane glass")
+                         "stained-glass distribution maps against per-pane glass; subdomains: geometric "
+                         "sub-domain cuts of the nave and the large nave")
     ap.add_argument("--batch-jobs", type=int, default=32)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--autotune", action="store_true",
                     help="choose chunk size and tile with sdm_autotune before timing")
     ap.add_argument("--bubbly-spp", type=int, default=64)
     ap.add_argument("--large-spp", type=int, default=256)
+    ap.add_argument("--subdomain-large-spp", type=int, default=64)
     ap.add_argument("--large-steps", type=int, default=1, help="timed renders per form of --form large")
     ap.add_argument("--bubbly-train", type=int, default=10_000_000)
     ap.add_argument("--bubbly-steps", type=int, default=30000)
@@ -641,6 +698,8 @@ def main():
         return large_bench(args)
     if args.form == "maps":
         return maps_bench(args)
+    if args.form == "subdomains":
+        return subdomains_bench(args)
     if args.form == "bubbly":
         bubbly_bench(args)
         return

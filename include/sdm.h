@@ -58,6 +58,9 @@ enum { SDM_SHADOW_AUTO = 0, SDM_SHADOW_BVH = 1 };
 /* Evaluation of path vertices on bubbly panes (SDM_GLASS_BUBBLY). */
 enum { SDM_BTDF_EXACT = 0, SDM_BTDF_SURROGATE = 1, SDM_BTDF_FALLBACK = 2 };
 
+/* Interface hand-off of geometric sub-domains (sdm_scene_desc). */
+enum { SDM_HANDOFF_QUEUE = 0, SDM_HANDOFF_MARCH = 1 };
+
 /* Largest number of wavelengths one spectral band (sub-domain) may hold. */
 #define SDM_MAX_BAND 128
 
@@ -123,6 +126,19 @@ typedef struct {
                                    when a material has a distribution map)     */
     int32_t n_maps;
     const sdm_dist_map *maps;   /* [n_maps]                                    */
+    /* Geometric sub-domains (Sec. 5): the scene's bounds cut into a grid of
+     * subdomains[0] x [1] x [2] cells (0 or 1 along an axis: no cut; at most
+     * 64 along an axis, 4096 cells), each with its own BVH over the triangles
+     * that overlap it.  Closest hits of a single render are then found cell
+     * by cell along each ray, rays crossing an interface being handed to the
+     * neighbouring cell with their state; the image is the same as without
+     * the cut.  Batches (sdm_render_batch) do not take such scenes. */
+    int32_t subdomains[3];
+    /* How a ray crosses an interface: SDM_HANDOFF_QUEUE, it waits in the
+     * neighbouring cell's queue for the next pass (passes per bounce: the
+     * most cells a ray can cross); SDM_HANDOFF_MARCH, the thread that traced
+     * it goes on in the neighbour. */
+    int32_t subdomain_handoff;
 } sdm_scene_desc;
 
 typedef struct {
@@ -207,6 +223,7 @@ typedef struct {
     uint64_t items_done;        /* work items finished, this call and earlier
                                    calls of a resumed render                  */
     uint64_t items_total;       /* work items of the render                    */
+    uint64_t interface_rays;    /* rays handed across sub-domain interfaces     */
 } sdm_stats;
 
 typedef struct {
@@ -240,6 +257,11 @@ const char *sdm_last_error(const sdm_context *ctx);
 /* Copies the scene, builds its BVH on the host (binned SAH) and uploads it. */
 int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *desc, sdm_scene **out);
 int sdm_scene_destroy(sdm_scene *scene);
+/* Geometric sub-domains of a scene: cells along x, y, z (1 1 1 without a
+ * cut), the triangle references of all cells (a triangle overlapping several
+ * cells counts once per cell) and their BVH nodes.  SDM_E_INVALID for a
+ * NULL scene; output pointers may be NULL. */
+int sdm_scene_subdomains(const sdm_scene *scene, int32_t cells[3], int64_t *tri_refs, int64_t *nodes);
 
 /* Renders one image: spectral radiance (mean over spp) per pixel and
  * wavelength, and XYZ = sum_i w_i L(lambda_i) cmf(lambda_i) with trapezoid

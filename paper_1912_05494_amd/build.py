@@ -7,7 +7,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libsdm.so")
-SOURCES = ["api.cpp", "render.cpp", "bvh_build.cpp", "sun_grid.cpp", "wavefront.hip", "surrogate.hip"]
+SOURCES = ["api.cpp", "render.cpp", "bvh_build.cpp", "sun_grid.cpp", "subdomain.cpp", "wavefront.hip",
+           "surrogate.hip"]
 ARCH = os.environ.get("SDM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -11,6 +11,7 @@
 
 #include "../../include/sdm.h"
 #include "bvh_build.hpp"
+#include "subdomain.hpp"
 #include "sun_grid.hpp"
 #include "sdm_types.hpp"
 #include "surrogate.hpp"
@@ -234,6 +235,16 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     if (d->uv)
         for (int64_t i = 0; i < 2 * (int64_t)d->nv; ++i)
             if (!std::isfinite(d->uv[i])) return fail(ctx, SDM_E_INVALID, "uv must be finite");
+    int32_t dd_n[3];
+    for (int a = 0; a < 3; ++a) {
+        dd_n[a] = d->subdomains[a] < 1 ? 1 : d->subdomains[a];
+        if (d->subdomains[a] < 0 || dd_n[a] > kMaxCellsPerAxis)
+            return fail(ctx, SDM_E_INVALID, "subdomains must be in [0, %d] along each axis", kMaxCellsPerAxis);
+    }
+    if ((int64_t)dd_n[0] * dd_n[1] * dd_n[2] > 4096) return fail(ctx, SDM_E_INVALID, "at most 4096 sub-domains");
+    const bool use_dd = (int64_t)dd_n[0] * dd_n[1] * dd_n[2] > 1 && d->nt > 0;
+    if (d->subdomain_handoff != SDM_HANDOFF_QUEUE && d->subdomain_handoff != SDM_HANDOFF_MARCH)
+        return fail(ctx, SDM_E_INVALID, "unknown sub-domain hand-off %d", d->subdomain_handoff);
     HIPCHK(ctx, hipSetDevice(ctx->device));
     auto *sc = new sdm_scene();
     sc->ctx = ctx;
@@ -266,6 +277,8 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         }
         if (d->uv) dg.add(d->uv, sizeof(float) * 2 * (size_t)d->nv);
         dg.add_value(d->n_maps);
+        dg.add(d->subdomains, sizeof(d->subdomains));
+        dg.add_value(d->subdomain_handoff);
         for (int32_t q = 0; q < d->n_maps; ++q) {
             const sdm_dist_map &dm = d->maps[q];
             dg.add_value(dm.W);
@@ -420,6 +433,23 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         chk(upload(sc->map_thick, tthick.data(), tthick.size()));
         chk(upload(sc->tri_uv, tuv.data(), tuv.size()));
     }
+    SubdomainBuild sub;
+    if (use_dd) {
+        sub = build_subdomains(d->pos, d->nv, d->idx, d->nt, tris, o2l, dd_n, lo, hi);
+        if (!sub.ok) {
+            delete sc;
+            return fail(ctx, SDM_E_UNSUPPORTED, "a sub-domain's BVH has a leaf at the depth limit holding > %d triangles",
+                        kMaxLeafTris);
+        }
+        chk(upload(sc->dd_cells, sub.cells.data(), sub.cells.size()));
+        chk(upload(sc->dd_nodes, sub.nodes.data(), std::max<size_t>(1, sub.nodes.size())));
+        chk(upload(sc->dd_tris, sub.tris.data(), std::max<size_t>(1, sub.tris.size())));
+        chk(upload(sc->dd_leaf, sub.leaf.data(), std::max<size_t>(1, sub.leaf.size())));
+        for (int a = 0; a < 3; ++a) sc->dd_n[a] = dd_n[a];
+        sc->dd_refs = (int64_t)sub.tris.size();
+        sc->dd_nodes_n = (int64_t)sub.nodes.size();
+        sc->dd_stack = sub.stack;
+    }
     chk(upload(sc->tab_x, d->tab_lambda_nm, (size_t)d->n_tab));
     chk(upload(sc->tab_mat, tabm.data(), tabm.size()));
     chk(upload(sc->tab_sun, d->sun_E, (size_t)d->n_tab));
@@ -460,6 +490,21 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     sc->grid_cands = (int64_t)grid.cand.size();
     sd.teps_d = 1e-6 * diag;
     sd.teps_f = (float)sd.teps_d;
+    sd.dd = DdDev{};
+    if (use_dd) {
+        for (int a = 0; a < 3; ++a) {
+            sd.dd.n[a] = dd_n[a];
+            sd.dd.lo[a] = sub.lo[a];
+            sd.dd.size[a] = sub.size[a];
+        }
+        sd.dd.n_cells = dd_n[0] * dd_n[1] * dd_n[2];
+        sd.dd.sweeps = (dd_n[0] + dd_n[1] + dd_n[2] + 2) / 3 * 3;
+        sd.dd.march = d->subdomain_handoff == SDM_HANDOFF_MARCH ? 1 : 0;
+        sd.dd.cells = sc->dd_cells.as<CellDev>();
+        sd.dd.nodes = sc->dd_nodes.as<BvhNode>();
+        sd.dd.tris = sc->dd_tris.as<TriDev>();
+        sd.dd.leaf = sc->dd_leaf.as<int32_t>();
+    }
     sd.n_maps = any_map ? d->n_maps : 0;
     sd.mat_map = any_map ? sc->mat_map.as<int32_t>() : nullptr;
     sd.map_hdr = any_map ? sc->map_hdr.as<int4>() : nullptr;
@@ -467,6 +512,16 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     sd.map_thick = any_map ? sc->map_thick.as<float>() : nullptr;
     sd.tri_uv = any_map ? sc->tri_uv.as<float4>() : nullptr;
     *out = sc;
+    return SDM_OK;
+}
+
+int sdm_scene_subdomains(const sdm_scene *sc, int32_t cells[3], int64_t *tri_refs, int64_t *nodes)
+{
+    if (!sc) return SDM_E_INVALID;
+    if (cells)
+        for (int a = 0; a < 3; ++a) cells[a] = sc->dd_n[a];
+    if (tri_refs) *tri_refs = sc->dd_refs;
+    if (nodes) *nodes = sc->dd_nodes_n;
     return SDM_OK;
 }
 

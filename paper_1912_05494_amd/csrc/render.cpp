@@ -213,6 +213,8 @@ struct ChunkArgs {
     uint64_t total;
     uint32_t chunk;
     int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec, n_panes;
+    int32_t dd_sweeps;                  // > 0: closest hits by geometric sub-domains
+    int32_t dd_march;                   // the hand-off stays in the thread
     int32_t cam_fused;          // camera rays may take the fused slab form (origins in the scene's bounds)
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
 };
@@ -228,7 +230,11 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
     done();
     for (int dpt = 0; dpt < a.depth; ++dpt) {
         mark(SDM_K_TRACE);
-        launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0 || a.cam_fused != 0, a.one_job != 0, a.grid_t, s);
+        if (a.dd_sweeps > 0)
+            launch_dd_trace<R>(a.jobs, a.w, cur, dpt > 0 || a.cam_fused != 0, a.dd_sweeps, a.dd_march != 0, a.grid_t,
+                               s);
+        else
+            launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0 || a.cam_fused != 0, a.one_job != 0, a.grid_t, s);
         done();
         if (a.w.sig) launch_sig_hits<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
         mark(SDM_K_SHADE);
@@ -497,7 +503,9 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         const size_t plane = (size_t)cap * sizeof(R);
         const size_t pool_b = (size_t)cap * (sizeof(PathO<R>) + sizeof(PathD<R>) + sizeof(PathS<R>)) +
                               (size_t)cap * nb * sizeof(R) + 8 * 256;
-        const size_t hit_b = (size_t)cap * sizeof(HitRec<R>) + (size_t)cap * 4 + (size_t)cap * sizeof(GlassRec<R>) + 256;
+        const bool dd = nj == 1 && jobs[0].sc->dev.dd.n_cells > 0;
+        const size_t hit_b = (size_t)cap * sizeof(HitRec<R>) + (size_t)cap * 4 + (size_t)cap * sizeof(GlassRec<R>) +
+                             (dd ? 2 * (size_t)cap * sizeof(DdEntry<R>) + 512 : 0) + 256;
         const size_t sh_b = 4 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
                             (size_t)cap * kMaxGlass * (8 + sizeof(R)) + 12 * 256;
         HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
@@ -521,7 +529,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
         const size_t gthreads = std::max((size_t)a.grid_t * trace_block_size(), (size_t)a.grid_st * block_size());
         int stack = 0;
-        for (const auto &jj : jobs) stack = std::max(stack, jj.sc->stack);
+        for (const auto &jj : jobs) stack = std::max({stack, jj.sc->stack, jj.sc->dd_stack});
         HIPCHK(ctx, ctx->gstack.ensure(gthreads * global_stack_levels(stack) * sizeof(int32_t)));
         Work<R> &w = a.w;
         char *pb = nullptr;
@@ -538,6 +546,11 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         w.hit = (HitRec<R> *)take((size_t)cap * sizeof(HitRec<R>));
         w.gidx = (uint32_t *)take((size_t)cap * 4);
         w.grec = (GlassRec<R> *)take((size_t)cap * sizeof(GlassRec<R>));
+        w.ddq[0] = w.ddq[1] = nullptr;
+        if (dd) {
+            w.ddq[0] = (DdEntry<R> *)take((size_t)cap * sizeof(DdEntry<R>));
+            w.ddq[1] = (DdEntry<R> *)take((size_t)cap * sizeof(DdEntry<R>));
+        }
         if (surr) {
             HIPCHK(ctx, ctx->bubq.ensure((size_t)cap * nb * sizeof(R) + plane + 1024));
             pb = ctx->bubq.as<char>();
@@ -567,6 +580,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.chunk = (uint32_t)chunk;
         a.depth = depth;
         a.lds_job = nj == 1 ? 0 : -2;   // a batch stages the BVH of each chunk's first job
+        a.dd_sweeps = dd ? jobs[0].sc->dev.dd.sweeps : 0;
+        a.dd_march = dd ? jobs[0].sc->dev.dd.march : 0;
         a.one_job = nj == 1;
         // The fused slab form's rounding stays inside the box padding for
         // origins within the scene's bounds: pinhole cameras placed inside
@@ -667,6 +682,11 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             (void)hipEventDestroy(ev1);
             return fail(ctx, SDM_E_UNSUPPORTED, "a shadow ray crossed more than %d glass panes", kMaxGlass);
         }
+        if (c.overflow & 4u) {
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
+            return fail(ctx, SDM_E_DEVICE, "a ray crossed more sub-domains than the passes cover");
+        }
         if (c.overflow) {
             (void)hipEventDestroy(ev0);
             (void)hipEventDestroy(ev1);
@@ -694,6 +714,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
                 st.nodes_visited[q] = c.nodes[q];
                 st.tris_tested[q] = c.tris[q];
             }
+            st.interface_rays = c.interface_rays;
             float ms = 0;
             (void)hipEventElapsedTime(&ms, ev0, ev1);
             st.ms_render = ms;
@@ -896,6 +917,8 @@ int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_
         if (int rc = check_job(ctx, js.back())) return rc;
         if (jobs[i].params->max_items > 0)
             return fail(ctx, SDM_E_UNSUPPORTED, "item budgets apply to single renders");
+        if (jobs[i].scene->dev.dd.n_cells > 0)
+            return fail(ctx, SDM_E_UNSUPPORTED, "scenes cut into sub-domains render singly");
     }
     ctx->partial.valid = false;
     return render_any(ctx, js, stats, (hipStream_t)hip_stream);

@@ -107,6 +107,10 @@ struct sdm_scene {
     DevBuf nodes, tris, thick, mat_type, mat_thick, mat_bub, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
     DevBuf g_start, g_cand;     // sun grid (empty when shadow rays walk the BVH)
     DevBuf mat_map, map_hdr, map_mat, map_thick, tri_uv;   // distribution maps
+    DevBuf dd_cells, dd_nodes, dd_tris, dd_leaf;           // geometric sub-domains
+    int32_t dd_n[3] = {1, 1, 1};
+    int64_t dd_refs = 0, dd_nodes_n = 0;                   // triangle references and nodes of the cells
+    int32_t dd_stack = 0;
     int64_t grid_cells = 0, grid_cands = 0;
     int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
     int32_t stack = 0;          // most traversal stack entries a walk can hold

@@ -39,6 +39,27 @@ struct alignas(16) GridCand {
 };
 
 // Scene data resident on the device.
+// Geometric sub-domains (Sec. 5): a grid of cells over the scene's bounds,
+// each with its own 4-wide BVH over the triangles that overlap it.  The
+// cells' triangles are copies (a.w the caller's index, b.w the material, c.w
+// the material type) in each cell's leaf order; leaf maps a copy back to the
+// scene's leaf-order triangle.
+struct CellDev {
+    float lo[3], hi[3];
+    int32_t node_base, tri_base;    // into DdDev::nodes, and DdDev::tris / leaf
+    int32_t n_nodes, n_tris;
+};
+struct DdDev {
+    int32_t n[3], n_cells;          // cells along x, y, z (n_cells = 0: no sub-domains)
+    float lo[3], size[3];           // grid origin and cell extent
+    int32_t sweeps;                 // passes per bounce: a multiple of 3, >= n[0] + n[1] + n[2]
+    int32_t march;                  // 1: a ray goes on into the next cell in the same thread
+    const CellDev *cells;
+    const BvhNode *nodes;
+    const TriDev *tris;
+    const int32_t *leaf;
+};
+
 struct SceneDev {
     const BvhNode *nodes;
     const TriDev *tris;
@@ -68,6 +89,7 @@ struct SceneDev {
     const float *map_thick;
     const float4 *tri_uv;
     int32_t n_maps;
+    DdDev dd;
 };
 
 // One render job (an image of one scene).  Spectral tables are in the
@@ -122,14 +144,18 @@ struct alignas(256) Counters {
     uint32_t pad_b[kCounterPad - 1];
     uint32_t kcount;            // sky records (escaped paths), from the back of the record buffer
     uint32_t pad_k[kCounterPad - 1];
+    uint32_t ddn[3];            // sub-domain interface queues: entries (see k_dd_sweep)
+    uint32_t pad_d[kCounterPad - 3];
     uint32_t overflow;          // bit 0: a pool or record buffer was full;
-                                // bit 1: a shadow ray crossed more than kMaxGlass panes
+                                // bit 1: a shadow ray crossed more than kMaxGlass panes;
+                                // bit 2: a ray crossed more sub-domains than the sweeps cover
     int32_t lds_job;            // job whose BVH prefix the traversal kernels stage in LDS
     unsigned long long r0;      // first primary path of the current chunk (advanced per chunk)
     unsigned long long closest, shadow, forks, bubbly;
     unsigned long long spec_paths, spec_records;   // kSpectral paths shaded / shadow records made
     unsigned long long glass[2];   // glass vertices shaded [all, arriving with per-wavelength factors]
     unsigned long long nodes[2], tris[2];   // traversal work [closest, shadow]
+    unsigned long long interface_rays;      // rays handed from a sub-domain to its neighbour
 };
 
 // Per-wavelength arrays are slot-major: the nb_max values of a slot are
@@ -183,6 +209,16 @@ constexpr int kMaxGlass = 8;    // panes a shadow ray may cross (more: SDM_E_UNS
 
 // Closest hit of a pool slot (tri < 0: no hit), one record so that it is
 // written and read with one or two 16-byte accesses.
+// A ray handed across a sub-domain interface: its pool slot, the cell it
+// enters and the ray parameter where it enters (Sec. 5: the ray's state is
+// continuous across the interface; origin and direction stay in the pool).
+template <class R>
+struct alignas(16) DdEntry {
+    R t;
+    uint32_t slot;
+    int32_t cell;
+};
+
 template <class R>
 struct alignas(16) HitRec {
     R t, u, v;                  // distance and barycentric coordinates
@@ -207,6 +243,7 @@ template <class R>
 struct Work {
     Pool<R> p[2];
     HitRec<R> *hit;             // closest hit per slot of the current pool
+    DdEntry<R> *ddq[2];         // sub-domain interface queues (ping-pong)
     uint32_t *gidx;             // slots of the current pool at a bubbly-glass vertex, from the
                                 // back: gidx[cap - 1 - b]
     GlassRec<R> *grec;          // clear-glass vertices [0, gcount)

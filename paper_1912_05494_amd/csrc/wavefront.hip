@@ -387,7 +387,9 @@ __device__ __forceinline__ TriDev load_tri(const TriDev *tris, int i)
 // same step.  The descent ends when fewer than kDescentLanes lanes are still
 // looking for a first leaf (after at least one round of visits); those lanes
 // go on from where they stopped in the next step.
-template <bool kFused, class R, class St>
+// kSkipCaller: ry.skip holds the caller index of the triangle to skip (the
+// tree's triangles are copies, as in a sub-domain's cell), not its position.
+template <bool kFused, class R, class St, bool kSkipCaller = false>
 __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, St &st,
                                              Ray<R> &ry, Closest<R> &h, R teps, uint32_t &nodes, uint32_t &tests)
 {
@@ -429,12 +431,13 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
         tests += (uint32_t)(na + nb);
         for (int k = 0; k < na + nb; ++k) {
             const int i = k < na ? fa + k : fb + (k - na);
-            if (i == ry.skip) continue;
+            if (!kSkipCaller && i == ry.skip) continue;
             const TriDev tr = load_tri(sc.tris, i);
+            const int32_t orig = __float_as_int(tr.a.w);
+            if (kSkipCaller && orig == ry.skip) continue;
             R t, u, v;
             if (!ray_tri(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
             if (!(t > teps)) continue;
-            const int32_t orig = __float_as_int(tr.a.w);
             if (t < h.tb || (t == h.tb && orig < h.orig_b)) {
                 h.tb = t; h.trib = i; h.ub = u; h.vb = v; h.orig_b = orig;
             }
@@ -670,6 +673,7 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *__restrict__ 
             w.cnt->lds_job = bands[items[lo].band].job;
         }
         w.cnt->count[0] = n;
+        w.cnt->ddn[1] = 0;      // the first sub-domain pass's output queue
         w.cnt->count[1] = 0;
         w.cnt->scount = 0;
     }
@@ -778,6 +782,201 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(const JobDev *__restrict_
         atomicAdd(&w.cnt->nodes[0], (unsigned long long)n_nodes);
         atomicAdd(&w.cnt->tris[0], (unsigned long long)n_tests);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Closest hit by geometric sub-domains (Sec. 5).  The scene's bounds are cut
+// into a grid of cells, each with its own BVH over the triangles that overlap
+// it.  A ray is traced in one cell at a time, over its segment inside the
+// cell: a hit before the ray's exit from the cell is the closest hit, since
+// every nearer point of the ray lies in cells already searched.  A ray that
+// leaves the cell without a hit crosses the interface to the next cell
+// along its direction, carrying its state (pool slot, entry parameter;
+// origin and direction stay in the pool).  Each pass takes the rays queued
+// at the interfaces; the first takes every path of the pool and finds its
+// cell.  Pass k reads queue counter ddn[k mod 3], appends to ddn[(k + 1)
+// mod 3] and clears ddn[(k + 2) mod 3] for the pass after next; the passes
+// per bounce are a multiple of 3, so the last one leaves ddn[1] clear for
+// the next bounce's first pass (k_generate clears it before a chunk).
+// ---------------------------------------------------------------------------
+// Parameter range [t0, t1] of the ray inside the box, and the axis through
+// whose face it leaves.
+template <class R>
+__device__ __forceinline__ bool dd_box(const float lo[3], const float hi[3], const Ray<R> &ry, R &t0, R &t1,
+                                       int &axis)
+{
+    const R o[3] = {ry.o.x, ry.o.y, ry.o.z}, iv[3] = {ry.inv.x, ry.inv.y, ry.inv.z};
+    t0 = R(0);
+    t1 = R(INFINITY);
+    axis = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R ta = (R(lo[a]) - o[a]) * iv[a], tb = (R(hi[a]) - o[a]) * iv[a];
+        const R n = fmin(ta, tb), f = fmax(ta, tb);
+        t0 = fmax(t0, n);
+        if (f < t1) {
+            t1 = f;
+            axis = a;
+        }
+    }
+    return t0 <= t1;
+}
+
+// kMarch: a ray that leaves a cell goes on in the neighbouring cell in the
+// same thread (the hand-off stays in registers; one pass per bounce).
+template <class R, bool kSurface, bool kFirst, bool kMarch>
+__global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restrict__ jobs, Work<R> w, int cur,
+                                                          int pass, int last)
+{
+    __shared__ int32_t s_stack[kLdsStack * kTraceBlock];
+    const SceneDev &sc = jobs[0].sc;
+    const DdDev &dd = sc.dd;
+    const Pool<R> P = w.p[cur];
+    uint32_t n_in;
+    if (kFirst) {
+        n_in = min(w.cnt->count[cur], w.cap);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            w.cnt->count[cur ^ 1] = 0;
+            w.cnt->scount = 0;
+            w.cnt->kcount = 0;
+            w.cnt->gcount = 0;
+            w.cnt->bcount = 0;
+            w.cnt->closest += n_in;
+            w.cnt->ddn[2] = 0;
+        }
+    } else {
+        n_in = min(w.cnt->ddn[pass % 3], w.cap);
+        if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->ddn[(pass + 2) % 3] = 0;
+    }
+    const DdEntry<R> *qin = w.ddq[(pass + 1) & 1];
+    DdEntry<R> *qout = w.ddq[pass & 1];
+    uint32_t *nout = &w.cnt->ddn[(pass + 1) % 3];
+    StackT<kTraceBlock> st = make_stack<kTraceBlock>(s_stack, w.gstack);
+    WaveFeed feed{0, 0, false, 0};
+    Ray<R> ry;
+    Closest<R> h;
+    SceneDev cv = sc;            // the current cell's tree in the scene's place
+    int64_t item = -1;
+    uint32_t slot = 0;
+    int32_t cell = -1;
+    int axis = 0;
+    const R teps = teps_of<R>(sc);
+    uint32_t n_nodes = 0, n_tests = 0, n_cross = 0;
+    for (;;) {
+        const int64_t got = feed.next(item < 0, n_in);
+        if (got >= 0) {
+            item = got;
+            if (kFirst) {
+                slot = (uint32_t)got;
+            } else {
+                const DdEntry<R> e = qin[got];
+                slot = e.slot;
+                cell = e.cell;
+            }
+            const PathO<R> po = rec_load(P.o + slot);
+            const PathD<R> pd = rec_load(P.d + slot);
+            set_dir(ry, V3<R>{po.x, po.y, po.z}, V3<R>{pd.x, pd.y, pd.z});
+            ry.skip = po.skip >= 0 ? __float_as_int(load_tri(sc.tris, po.skip).a.w) : -1;
+            if (kFirst) {
+                // the cell of the origin, or of the point where the ray
+                // enters the grid
+                const float glo[3] = {dd.lo[0], dd.lo[1], dd.lo[2]};
+                const float ghi[3] = {dd.lo[0] + dd.size[0] * dd.n[0], dd.lo[1] + dd.size[1] * dd.n[1],
+                                      dd.lo[2] + dd.size[2] * dd.n[2]};
+                R g0, g1;
+                int ax;
+                cell = -1;
+                if (dd_box(glo, ghi, ry, g0, g1, ax)) {
+                    const R p[3] = {ry.o.x + g0 * ry.d.x, ry.o.y + g0 * ry.d.y, ry.o.z + g0 * ry.d.z};
+                    int k[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const R f = floor((p[a] - R(dd.lo[a])) / R(dd.size[a]));
+                        k[a] = f < R(0) ? 0 : (f > R(dd.n[a] - 1) ? dd.n[a] - 1 : (int)f);
+                    }
+                    cell = (k[2] * dd.n[1] + k[1]) * dd.n[0] + k[0];
+                }
+            }
+            h.tb = R(INFINITY); h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
+            st.sp = 0;
+            ry.cur = kDone;
+            if (cell >= 0) {
+                const CellDev c = dd.cells[cell];
+                R t0, t1;
+                dd_box(c.lo, c.hi, ry, t0, t1, axis);
+                h.tb = t1;     // only hits before the ray leaves the cell
+                cv.nodes = dd.nodes + c.node_base;
+                cv.tris = dd.tris + c.tri_base;
+                cv.n_nodes = c.n_nodes;
+                ry.cur = c.n_nodes > 0 ? 0 : kDone;
+            }
+        }
+        if (!__ballot(item >= 0)) {
+            if (feed.done) break;
+            continue;
+        }
+        if (item >= 0) {
+            const bool fin = ry.cur == kDone ||
+                             closest_step<kSurface, R, StackT<kTraceBlock>, true>(cv, nullptr, 0, st, ry, h, teps,
+                                                                                 n_nodes, n_tests);
+            if (fin) {
+                HitRec<R> hr;
+                hr.t = R(INFINITY); hr.u = hr.v = R(0); hr.tri = -1;
+                int next = -1;
+                if (h.trib >= 0) {
+                    hr.t = h.tb; hr.u = h.ub; hr.v = h.vb;
+                    hr.tri = gld(dd.leaf + dd.cells[cell].tri_base + h.trib);
+                } else if (cell >= 0) {
+                    // across the face of the exit axis, toward the ray's direction
+                    int k[3] = {cell % dd.n[0], (cell / dd.n[0]) % dd.n[1], cell / (dd.n[0] * dd.n[1])};
+                    const R da = axis == 0 ? ry.d.x : (axis == 1 ? ry.d.y : ry.d.z);
+                    k[axis] += da > R(0) ? 1 : -1;
+                    if (k[axis] >= 0 && k[axis] < dd.n[axis]) next = (k[2] * dd.n[1] + k[1]) * dd.n[0] + k[0];
+                }
+                if (kMarch && next >= 0) {
+                    // continue in the neighbour from the interface
+                    cell = next;
+                    const CellDev c = dd.cells[cell];
+                    R t0, t1;
+                    dd_box(c.lo, c.hi, ry, t0, t1, axis);
+                    h.tb = t1;
+                    h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
+                    cv.nodes = dd.nodes + c.node_base;
+                    cv.tris = dd.tris + c.tri_base;
+                    cv.n_nodes = c.n_nodes;
+                    st.sp = 0;
+                    ry.cur = c.n_nodes > 0 ? 0 : kDone;
+                    ++n_cross;
+                    continue;
+                }
+                if (next >= 0 && last) {
+                    atomicOr(&w.cnt->overflow, 4u);   // more cells than the passes cover
+                    next = -1;
+                }
+                if (next >= 0) {
+                    const uint32_t q = atomicAdd(nout, 1u);
+                    if (q < w.cap) {
+                        DdEntry<R> e;
+                        e.t = h.tb;
+                        e.slot = slot;
+                        e.cell = next;
+                        qout[q] = e;
+                    } else {
+                        atomicOr(&w.cnt->overflow, 1u);
+                    }
+                    ++n_cross;
+                } else {
+                    rec_store(w.hit + slot, hr);
+                }
+                item = -1;
+            }
+        }
+    }
+    if (n_nodes) {
+        atomicAdd(&w.cnt->nodes[0], (unsigned long long)n_nodes);
+        atomicAdd(&w.cnt->tris[0], (unsigned long long)n_tests);
+    }
+    if (n_cross) atomicAdd(&w.cnt->interface_rays, (unsigned long long)n_cross);
 }
 
 // ---------------------------------------------------------------------------
@@ -2176,6 +2375,8 @@ __global__ void k_zero_counters(Counters *c)
         c->spec_paths = c->spec_records = 0;
         c->glass[0] = c->glass[1] = 0;
         c->nodes[0] = c->nodes[1] = c->tris[0] = c->tris[1] = 0;
+        c->interface_rays = 0;
+        c->ddn[0] = c->ddn[1] = c->ddn[2] = 0;
     }
 }
 
@@ -2347,6 +2548,27 @@ void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bo
     }
 }
 template <class R>
+void launch_dd_trace(const JobDev *jobs, const Work<R> &w, int cur, bool surface, int sweeps, bool march, int grid,
+                     hipStream_t s)
+{
+    const dim3 g(grid), b(kTraceBlock);
+    if (march) {
+        if (surface) hipLaunchKernelGGL((k_dd_sweep<R, true, true, true>), g, b, 0, s, jobs, w, cur, 0, 1);
+        else hipLaunchKernelGGL((k_dd_sweep<R, false, true, true>), g, b, 0, s, jobs, w, cur, 0, 1);
+        return;
+    }
+    for (int k = 0; k < sweeps; ++k) {
+        const int last = k == sweeps - 1;
+        if (k == 0) {
+            if (surface) hipLaunchKernelGGL((k_dd_sweep<R, true, true, false>), g, b, 0, s, jobs, w, cur, k, last);
+            else hipLaunchKernelGGL((k_dd_sweep<R, false, true, false>), g, b, 0, s, jobs, w, cur, k, last);
+        } else {
+            if (surface) hipLaunchKernelGGL((k_dd_sweep<R, true, false, false>), g, b, 0, s, jobs, w, cur, k, last);
+            else hipLaunchKernelGGL((k_dd_sweep<R, false, false, false>), g, b, 0, s, jobs, w, cur, k, last);
+        }
+    }
+}
+template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
                   hipStream_t s)
 {
@@ -2488,6 +2710,7 @@ int occupancy(int kernel_class, int lds_bytes)
     template void launch_generate<R>(const JobDev *, const BandDev *, const ItemDev *, int, const Work<R> &,       \
                                      uint64_t, uint32_t, int, hipStream_t);                                        \
     template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, bool, bool, int, hipStream_t);        \
+    template void launch_dd_trace<R>(const JobDev *, const Work<R> &, int, bool, int, bool, int, hipStream_t);    \
     template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t);  \
     template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int,          \
                                         hipStream_t);                                                              \

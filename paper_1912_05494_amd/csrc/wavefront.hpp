@@ -15,6 +15,9 @@ template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, bool one_job, int grid,
                   hipStream_t s);
 template <class R>
+void launch_dd_trace(const JobDev *jobs, const Work<R> &w, int cur, bool surface, int sweeps, bool march, int grid,
+                     hipStream_t s);
+template <class R>
 void launch_shade(const JobDev *jobs, const BandDev *bands, const Work<R> &w, int cur, bool one_job, int grid,
                   hipStream_t s);
 template <class R>

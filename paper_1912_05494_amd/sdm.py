@@ -43,7 +43,8 @@ class SceneDesc(C.Structure):
                 ("n_mat", C.c_int32), ("mats", C.POINTER(Material)), ("n_tab", C.c_int32),
                 ("tab_lambda_nm", _FP), ("sun_dir", C.c_float * 3), ("sun_E", _FP),
                 ("sky_L", _FP), ("shadow_walk", C.c_int32), ("uv", _FP), ("n_maps", C.c_int32),
-                ("maps", C.POINTER(DistMapDesc))]
+                ("maps", C.POINTER(DistMapDesc)), ("subdomains", C.c_int32 * 3),
+                ("subdomain_handoff", C.c_int32)]
 
 
 class Camera(C.Structure):
@@ -70,7 +71,8 @@ class Stats(C.Structure):
                 ("tris_tested", C.c_uint64 * 2), ("bubbly_vertices", C.c_uint64),
                 ("spectral_paths", C.c_uint64), ("spectral_records", C.c_uint64),
                 ("glass_vertices", C.c_uint64 * 2), ("ms_render", C.c_double), ("kernel_ms", C.c_double * 9),
-                ("kernel_launches", C.c_uint64 * 9), ("items_done", C.c_uint64), ("items_total", C.c_uint64)]
+                ("kernel_launches", C.c_uint64 * 9), ("items_done", C.c_uint64), ("items_total", C.c_uint64),
+                ("interface_rays", C.c_uint64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_[:6]}
@@ -85,6 +87,7 @@ class Stats(C.Structure):
         d["kernel_launches"] = {k: int(self.kernel_launches[i]) for i, k in enumerate(KERNELS)}
         d["items_done"] = int(self.items_done)
         d["items_total"] = int(self.items_total)
+        d["interface_rays"] = int(self.interface_rays)
         return d
 
 
@@ -128,6 +131,7 @@ def lib():
         L.sdm_last_error.argtypes = [vp]
         L.sdm_scene_create.argtypes = [vp, C.POINTER(SceneDesc), C.POINTER(vp)]
         L.sdm_scene_destroy.argtypes = [vp]
+        L.sdm_scene_subdomains.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sdm_scene_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sdm_render.argtypes = [vp, vp, C.POINTER(RenderParams), C.POINTER(Outputs), vp]
@@ -159,7 +163,7 @@ def lib():
 
 
 EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_scene_create",
-            "sdm_scene_destroy", "sdm_scene_info", "sdm_render", "sdm_slab_eval",
+            "sdm_scene_destroy", "sdm_scene_info", "sdm_scene_subdomains", "sdm_render", "sdm_slab_eval",
             "sdm_debug_intersect", "sdm_debug_shadow", "sdm_slab_mc", "sdm_mlp_nparams",
             "sdm_mlp_create", "sdm_mlp_destroy", "sdm_mlp_get_params", "sdm_mlp_grad",
             "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table",
@@ -218,8 +222,11 @@ class Context:
 class Scene:
     """Uploads a ``synth.Scene``-like object (pos, idx, mat, materials, tables)."""
 
-    def __init__(self, ctx: Context, scene, shadow_walk="auto"):
-        """shadow_walk: "auto" (sun grid where it is compact) or "bvh"."""
+    def __init__(self, ctx: Context, scene, shadow_walk="auto", subdomains=None, handoff="queue"):
+        """shadow_walk: "auto" (sun grid where it is compact) or "bvh".
+        subdomains: (nx, ny, nz) cells of geometric sub-domains, or None;
+        handoff: "queue" (interface queues, one pass per cell crossed) or
+        "march" (the thread goes on in the next cell)."""
         self.ctx = ctx
         keep = []
         pos = _f32(scene.pos.reshape(-1))
@@ -249,7 +256,9 @@ class Scene:
                       idx.ctypes.data_as(C.POINTER(C.c_int32)),
                       mat.ctypes.data_as(C.POINTER(C.c_int32)), len(scene.materials), mats,
                       len(tab), fp(tab), (C.c_float * 3)(*[float(x) for x in scene.sun_dir]),
-                      fp(sE), fp(sL), SHADOW_WALKS[shadow_walk], fp(uv), len(smaps), maps)
+                      fp(sE), fp(sL), SHADOW_WALKS[shadow_walk], fp(uv), len(smaps), maps,
+                      (C.c_int32 * 3)(*[int(x) for x in (subdomains or (0, 0, 0))]),
+                      {"queue": 0, "march": 1}[handoff])
         self.ptr = C.c_void_p()
         ctx.check(lib().sdm_scene_create(ctx.ptr, C.byref(d), C.byref(self.ptr)), "sdm_scene_create")
         ctx._owned.add(self)
@@ -261,6 +270,13 @@ class Scene:
         lib().sdm_scene_info(self.ptr, C.byref(n), C.byref(dep), C.byref(stk), C.byref(cells), C.byref(cands))
         return {"n_nodes": n.value, "depth": dep.value, "stack": stk.value, "grid_cells": cells.value,
                 "grid_candidates": cands.value}
+
+    def subdomains(self):
+        """(cells along x, y, z; triangle references of the cells; their BVH nodes)."""
+        n = (C.c_int32 * 3)()
+        refs, nodes = C.c_int64(), C.c_int64()
+        self.ctx.check(lib().sdm_scene_subdomains(self.ptr, n, C.byref(refs), C.byref(nodes)), "sdm_scene_subdomains")
+        return tuple(int(x) for x in n), int(refs.value), int(nodes.value)
 
     def close(self):
         if self.ptr:

@@ -382,9 +382,17 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         const int32_t ty = mtype[m];
         std::memcpy(&tris[l].c.w, &ty, 4);
     }
+    // bounds of the triangles (vertices no triangle uses do not count): the
+    // region the BVH padding and the sub-domain grid are sized for
+    double tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < 3 * (int64_t)d->nt; ++i)
+        for (int a = 0; a < 3; ++a) {
+            tlo[a] = std::min(tlo[a], (double)d->pos[3 * (size_t)d->idx[i] + a]);
+            thi[a] = std::max(thi[a], (double)d->pos[3 * (size_t)d->idx[i] + a]);
+        }
     for (int a = 0; a < 3; ++a) {
-        sc->lo[a] = d->nv > 0 ? lo[a] : 0.0;
-        sc->hi[a] = d->nv > 0 ? hi[a] : 0.0;
+        sc->lo[a] = d->nt > 0 ? tlo[a] : 0.0;
+        sc->hi[a] = d->nt > 0 ? thi[a] : 0.0;
     }
     double maxabs = 0.0;
     for (int a = 0; a < 3 && d->nv > 0; ++a) maxabs = std::max({maxabs, std::fabs(lo[a]), std::fabs(hi[a])});
@@ -435,7 +443,7 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     }
     SubdomainBuild sub;
     if (use_dd) {
-        sub = build_subdomains(d->pos, d->nv, d->idx, d->nt, tris, o2l, dd_n, lo, hi);
+        sub = build_subdomains(d->pos, d->nv, d->idx, d->nt, tris, o2l, dd_n, sc->lo, sc->hi);
         if (!sub.ok) {
             delete sc;
             return fail(ctx, SDM_E_UNSUPPORTED, "a sub-domain's BVH has a leaf at the depth limit holding > %d triangles",

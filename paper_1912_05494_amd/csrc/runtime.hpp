@@ -115,7 +115,7 @@ struct sdm_scene {
     int32_t n_tab = 0, n_mat = 0, depth = 0, n_nodes = 0, nt = 0;
     int32_t stack = 0;          // most traversal stack entries a walk can hold
     int32_t max_pane = -1;      // largest pane type of a bubbly material (-1: none)
-    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // bounds of the vertices
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // bounds of the triangles
     uint64_t digest = 0;        // of the scene description's inputs
 };
 

@@ -284,8 +284,10 @@ __device__ __forceinline__ void set_dir(Ray<R> &ry, V3<R> o, V3<R> d)
 // inv saves a subtraction per plane; its rounding error, about |o| u in
 // distance (u = 2^-24 in FP32), stays far inside the box padding (1e-5 of
 // the scene diagonal plus 1e-5 of the box coordinates) when the origin lies
-// in the scene's bounds, as it does for rays leaving a surface.  Rays from
-// elsewhere (the camera, test rays) use (b - o) * inv.
+// in the scene's bounds, as it does for rays leaving a surface and for
+// pinhole camera rays whose eye lies within the bounds of the scene's
+// triangles (the render checks it per job).  Other rays (cameras elsewhere,
+// orthographic cameras, test rays) use (b - o) * inv.
 template <bool kFused, class R>
 __device__ __forceinline__ R slab_t(float b, R o, R inv, R oi)
 {
@@ -717,8 +719,10 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *__restrict__ 
 // ---------------------------------------------------------------------------
 // Closest hit of every path of pool `cur`.
 // ---------------------------------------------------------------------------
-// kSurface: every ray of the pool leaves a surface (after the first bounce),
-// so the fused slab form applies; camera rays take the plain form.  kOne: the
+// kSurface: every ray of the pool starts inside the scene's bounds (after
+// the first bounce, or camera rays of pinhole eyes within the bounds of the
+// scene's triangles), so the fused slab form applies; other camera rays take
+// the plain form.  kOne: the
 // launch renders one job, so the scene's constants are uniform (scalar loads
 // hoisted out of the loops) rather than looked up per lane.
 template <class R, bool kSurface, bool kOne>

@@ -594,6 +594,56 @@ def subdomains_bench(args):
     ctx.close()
 
 
+def photons_bench(args):
+    """Caustic photon map (photon mapping, Sec. 3.2): the bubbly nave (24
+    panes, exact walks) at 512 x 512, 64 spp, 81 wavelengths, depth 8, with
+    0 and 2^20 .. 2^24 sun photons, radius --photon-radius; per count the
+    render time, the photon pass and gather times and the photons stored."""
+    import torch
+    from paper_1912_05494_amd import sdm, synth
+
+    ctx = sdm.Context(0)
+    st = synth.nave_settings()
+    W, H, nl = st.camera.W, st.camera.H, len(st.lambda_nm)
+    dev = torch.device("cuda", 0)
+    spec = torch.empty((H, W, nl), dtype=torch.float32, device=dev)
+    xyz = torch.empty((H, W, 3), dtype=torch.float64, device=dev)
+    gs = sdm.Scene(ctx, synth.nave_scene(seed=1, bubbly=True))
+    rows = []
+    for n in (0, 1 << 20, 1 << 22, 1 << 24):
+        params, keep = sdm.make_params(st, timing=True, btdf={"mode": "exact"}, photons=n,
+                                       photon_radius=args.photon_radius)
+        for _ in range(args.warmup):
+            s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s_ = sdm.render_into(ctx, gs, params, spec, xyz)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        km = s_["kernel_ms"]
+        rows.append({"photons": n, "ms_per_step": dt * 1e3, "value": W * H * st.spp * nl / dt,
+                     "photons_stored": s_["photons_stored"], "photon_ms": km["photon"], "caustic_ms": km["caustic"],
+                     "photons_per_s": n / (km["photon"] * 1e-3) if n and km["photon"] > 0 else None,
+                     "kernel_ms": {k: v for k, v in km.items() if v > 0}})
+        print(f"{n} photons: {dt * 1e3:.2f} ms, stored {s_['photons_stored']}, photon pass {km['photon']:.2f} ms, "
+              f"gather {km['caustic']:.2f} ms", file=sys.stderr, flush=True)
+    gs.close()
+    main_row = rows[2]
+    out = {
+        "metric": "spectral ray samples/sec (bubbly nave with the caustic photon map, 2^22 photons)",
+        "value": main_row["value"], "unit": "spectral ray samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_row["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "procedural church nave, 24 bubbly panes (exact walks), 512x512, 64 spp, "
+                               f"81 wavelengths, depth 8, photon radius {args.photon_radius} m"},
+        "counts": rows,
+        "map_cost_vs_no_map": main_row["ms_per_step"] / rows[0]["ms_per_step"],
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def batch_bench(args):
     """The uneven 32-job batch (square sides 128-1024, 10k-200k triangles,
     8-81 wavelengths, 16-128 spp; scene seed 2 + job) as one wavefront,
@@ -653,13 +703,15 @@ def main():
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--form", default="plain",
-                    choices=["plain", "bubbly", "batch", "table1", "large", "maps", "subdomains"],
+                    choices=["plain", "bubbly", "batch", "table1", "large", "maps", "subdomains", "photons"],
                     help="plain: the clear-glass nave (default); bubbly: bubbly panes in four forms; "
                          "batch: the uneven 32-job batch in one wavefront; table1: the oracle's speedup "
                          "against threads x bands on the host (no GPU); large: the 1 M-triangle nave "
                          "with 200 bubbly panes at 1920x1080, fallback against exact; maps: the nave with "
                          "stained-glass distribution maps against per-pane glass; subdomains: geometric "
-                         "sub-domain cuts of the nave and the large nave")
+                         "sub-domain cuts of the nave and the large nave; photons: the bubbly nave with "
+                         "the caustic photon map at 2^20 to 2^24 photons")
+    ap.add_argument("--photon-radius", type=float, default=0.1, help="gather radius of --form photons (m)")
     ap.add_argument("--batch-jobs", type=int, default=32)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--autotune", action="store_true",
@@ -700,6 +752,8 @@ def main():
         return maps_bench(args)
     if args.form == "subdomains":
         return subdomains_bench(args)
+    if args.form == "photons":
+        return photons_bench(args)
     if args.form == "bubbly":
         bubbly_bench(args)
         return

@@ -193,12 +193,28 @@ typedef struct {
      * sdm_render_checkpoint saves it.  Single renders only: sdm_render_batch
      * returns SDM_E_UNSUPPORTED for max_items > 0. */
     int64_t max_items;
+    /* Caustic photon map (photon mapping, Sec. 3.2).  0: off.  n > 0: before
+     * the render, n sun photons of one render wavelength each leave a square
+     * across the sun's direction covering the scene's bounding sphere
+     * (centred two radii toward the sun; its axes h x s and s x (h x s)
+     * normalised, s the sun direction, h = (1, 2, 3) / sqrt(14)) and follow
+     * the panes (clear glass: reflect with probability R / (R + T), weight
+     * R + T; bubbly glass: the exact walk) for up to max_depth vertices; a
+     * photon that a pane has turned (reflected or scattered by bubbles) is
+     * stored where it first meets a Lambert surface, with power
+     * E_sun(lambda) x square area x n_lambda / n.  Every Lambert vertex of
+     * the render then adds g b_j rho_j / pi x sum Phi / (pi r^2) over the
+     * stored photons of its wavelength j within photon_radius r (metres)
+     * whose arrival side's normal is within 0.9 (cosine) of its own.  Single
+     * renders only; not with max_items. */
+    int64_t photons;
+    float photon_radius;
 } sdm_render_params;
 
 /* Kernel classes reported in sdm_stats. */
 enum { SDM_K_GENERATE = 0, SDM_K_TRACE = 1, SDM_K_SHADE = 2, SDM_K_SHADOW = 3,
        SDM_K_FINALIZE = 4, SDM_K_SHADOW_ACCUM = 5, SDM_K_SHADE_GLASS = 6, SDM_K_BUBBLY_EVAL = 7,
-       SDM_K_SHADE_BUBBLY = 8, SDM_K_COUNT = 9 };
+       SDM_K_SHADE_BUBBLY = 8, SDM_K_PHOTON = 9, SDM_K_CAUSTIC = 10, SDM_K_COUNT = 11 };
 
 typedef struct {
     uint64_t spectral_samples;  /* W*H*spp*n_lambda                            */
@@ -224,6 +240,7 @@ typedef struct {
                                    calls of a resumed render                  */
     uint64_t items_total;       /* work items of the render                    */
     uint64_t interface_rays;    /* rays handed across sub-domain interfaces     */
+    uint64_t photons_stored;    /* photons of the caustic map                   */
 } sdm_stats;
 
 typedef struct {

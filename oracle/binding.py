@@ -11,7 +11,7 @@ from .build import ensure_built
 __all__ = ["lib", "OracleScene", "philox", "u01", "fresnel", "slab", "snell_cos_t",
            "render", "render_pixels", "spec_to_xyz", "camera_ray", "cosine_dir", "slab_mc",
            "fresnel_real", "bubble_dir", "mlp_nparams", "mlp_forward", "mlp_loss_grad", "walk_draw",
-           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "lobe_transmit", "mlp_bf16_bound", "pane_at", "slab_to_world",
+           "bubbly_walk", "bubble_sigma", "bf16", "mlp_forward_bf16", "lobe_dir", "lobe_transmit", "mlp_bf16_bound", "pane_at", "photon_map", "slab_to_world",
            "BTDF_MODES"]
 
 _lib = None
@@ -54,7 +54,7 @@ class _Params(C.Structure):
                 ("err_table", C.POINTER(C.c_double)), ("err_bound", C.c_double),
                 ("item_begin", C.c_int64), ("max_items", C.c_int64), ("events", C.c_void_p),
                 ("prec_bound", C.c_void_p), ("prec_rel", C.c_double), ("prec_ceps", C.c_double),
-                ("prec_eps", C.c_double)]
+                ("prec_eps", C.c_double), ("photons", C.c_int64), ("photon_radius", C.c_double)]
 
 
 class _WalkStream(C.Structure):
@@ -63,7 +63,8 @@ class _WalkStream(C.Structure):
 
 
 class _WalkOut(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("dir", C.c_double * 3), ("L", C.c_double), ("n_events", C.c_int32)]
+    _fields_ = [("kind", C.c_int32), ("dir", C.c_double * 3), ("L", C.c_double), ("n_events", C.c_int32),
+                ("bubbles", C.c_int32)]
 
 
 BTDF_MODES = {"exact": 0, "surrogate": 1, "fallback": 2}
@@ -121,6 +122,8 @@ def lib():
         L.orc_lobe_dir.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.orc_lobe_transmit.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.orc_pane_at.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
+        L.orc_photon_map.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_photon_map.restype = C.c_int64
         L.orc_mlp_bf16_bound.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_void_p,
                                          C.c_void_p]
         L.orc_slab_to_world.argtypes = [C.c_void_p] * 4
@@ -245,7 +248,7 @@ class OracleScene:
         return T
 
 
-def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=None):
+def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=None, photons=0, photon_radius=0.05):
     """btdf: None (exact walks on bubbly panes) or a dict with keys mode
     ("exact" / "surrogate" / "fallback"), params, n_panes, bf16 (bool) and,
     for "fallback", err_table (n_panes, n_cos, n_d, n_rho) and bound."""
@@ -259,6 +262,8 @@ def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=Non
                 int(settings.n_bands if n_bands is None else n_bands), int(tile),
                 float(settings.beta_threshold), int(use_bvh), int(n_threads))
     keep = [lam, cmf]
+    p.photons = int(photons)
+    p.photon_radius = float(photon_radius)
     if btdf is not None:
         p.btdf_mode = BTDF_MODES[btdf.get("mode", "exact")]
         if btdf.get("params") is not None:
@@ -277,7 +282,7 @@ def _params(settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=Non
 
 
 def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, btdf=None, items=None,
-           events=False, spec=None, prec=None):
+           events=False, spec=None, prec=None, photons=0, photon_radius=0.05):
     """Full image -> (spec (H, W, nl) float64, xyz (H, W, 3) float64), plus the
     event signatures (H, W, nl) uint64 when events is True, plus the
     single-precision error bound (H, W, nl) float64 when prec = (rel,
@@ -285,7 +290,7 @@ def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, b
     count) of the work
     items to render (count 0: to the end); the others keep the values of
     spec (zeros when spec is None)."""
-    p, keep = _params(settings, use_bvh, tile, n_threads, n_bands, btdf)
+    p, keep = _params(settings, use_bvh, tile, n_threads, n_bands, btdf, photons, photon_radius)
     W, H, nl = settings.camera.W, settings.camera.H, len(settings.lambda_nm)
     spec = np.zeros((H, W, nl)) if spec is None else np.ascontiguousarray(spec, dtype=np.float64)
     xyz = np.empty((H, W, 3))
@@ -304,11 +309,12 @@ def render(oscene, settings, use_bvh=True, tile=16, n_threads=0, n_bands=None, b
     return (spec, xyz) + ((ev,) if events else ()) + ((pb,) if pb is not None else ())
 
 
-def render_pixels(oscene, settings, pixels, use_bvh=True, n_threads=0, btdf=None, events=False, prec=None):
+def render_pixels(oscene, settings, pixels, use_bvh=True, n_threads=0, btdf=None, events=False, prec=None,
+                  photons=0, photon_radius=0.05):
     """Selected linear pixel indices -> spec (m, nl) float64, plus the event
     signatures (m, nl) uint64 when events is True and the single-precision
     error bound (m, nl) float64 when prec is given (as for render)."""
-    p, keep = _params(settings, use_bvh, 16, n_threads, btdf=btdf)
+    p, keep = _params(settings, use_bvh, 16, n_threads, btdf=btdf, photons=photons, photon_radius=photon_radius)
     px = np.ascontiguousarray(pixels, dtype=np.int32)
     nl = len(settings.lambda_nm)
     spec = np.empty((len(px), nl))
@@ -409,6 +415,18 @@ def mlp_bf16_bound(params, tup, pane, e_cos=0.0, e_d=0.0):
     lib().orc_mlp_bf16_bound(p.ctypes.data, t.ctypes.data, int(pane), float(e_cos), float(e_d), out.ctypes.data,
                              bnd.ctypes.data)
     return out, bnd
+
+
+def photon_map(oscene, settings, photons, photon_radius=0.05, use_bvh=True):
+    """Stored photons of the caustic map: (n, 8) rows (x, y, z, nx, ny, nz,
+    power, wavelength index)."""
+    p, keep = _params(settings, use_bvh, photons=photons, photon_radius=photon_radius)
+    n = lib().orc_photon_map(oscene.ptr, C.byref(p), None)
+    if n < 0:
+        raise ValueError("oracle rejected the parameters")
+    out = np.empty((max(n, 0), 8))
+    lib().orc_photon_map(oscene.ptr, C.byref(p), out.ctypes.data if n > 0 else None)
+    return out
 
 
 def pane_at(oscene, t, u, v):

@@ -838,11 +838,27 @@ static void onb(const double *n, double *t1, double *t2)
     cross3(n, t1, t2);
 }
 
+/* A stored photon of the caustic map, and the map hashed by cells of side r. */
+typedef struct {
+    double x[3], n[3], phi;
+    int32_t j;
+} ophot;
+
+typedef struct {
+    int64_t n;
+    ophot *ph;
+    uint32_t mask;
+    int64_t *start;   /* [buckets + 1] */
+    int64_t *idx;     /* photon indices by bucket */
+    double r, lo[3];
+} ophmap;
+
 typedef struct {
     const orc_scene *s;
     const orc_render_params *p;
     const spectra *sp;
     camera cam;
+    const ophmap *ph;
 } rctx;
 
 void orc_camera_ray(const orc_render_params *p, int32_t i, int32_t j, double u0, double u1,
@@ -942,6 +958,238 @@ static void surrogate_eval(const orc_render_params *p, const omat *mm, double co
     else orc_mlp_forward(p->mlp_params, p->mlp_n_panes, 1, tup, &pane, out);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Caustic photon map (photon mapping, Sec. 3.2)                              */
+/* ------------------------------------------------------------------------- */
+#define PHOTON_TAG 0xFFFFFFF0u   /* sample word of the photons' draws */
+
+static uint32_t ph_hash(int64_t ix, int64_t iy, int64_t iz, uint32_t mask)
+{
+    return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) & mask;
+}
+
+static void ph_cell(const ophmap *m, const double *x, int64_t c[3])
+{
+    for (int a = 0; a < 3; ++a) c[a] = (int64_t)floor((x[a] - m->lo[a]) / m->r);
+}
+
+/* One photon: the sun's photon pid leaves the emission square (centre c,
+ * half sides e1 and e2) toward -sun with one render wavelength, follows the
+ * panes for up to max_depth vertices, and is stored (returns 1) where it
+ * first meets a Lambert surface if a pane has turned it: a reflection at
+ * clear glass (probability R / (R + T), weight R + T), or at a bubbly pane an
+ * entry reflection, an exit back through the entry face or a bubble met on
+ * the walk (weight exp(-alpha L)).  Light that goes straight through (clear
+ * transmission, unscattered bubbly transmission) is the shadow rays'. */
+static int trace_photon(const rctx *c, uint32_t pid, const double cen[3], const double e1[3], const double e2[3],
+                        double power, ophot *out)
+{
+    const orc_scene *s = c->s;
+    const orc_render_params *p = c->p;
+    const spectra *sp = c->sp;
+    double u[4], o[3], d[3];
+    draw4(p->seed, p->job_id, pid, PHOTON_TAG, -1, 0, u);
+    double a = 2.0 * u[0] - 1.0, b = 2.0 * u[1] - 1.0;
+    int j = (int)(u[2] * sp->nl);
+    if (j > sp->nl - 1) j = sp->nl - 1;
+    for (int q = 0; q < 3; ++q) {
+        o[q] = cen[q] + a * e1[q] + b * e2[q];
+        d[q] = -s->sun[q];
+    }
+    double lambda = sp->lam[j];
+    double phi = sp->E[j] * power;
+    int turned = 0;
+    int32_t skip = -1;
+    for (int vtx = 0; vtx < p->max_depth; ++vtx) {
+        ohit h = closest(s, p->use_bvh, o, d, skip);
+        if (h.tri < 0 || !(phi > 0.0)) return 0;
+        double x[3];
+        for (int q = 0; q < 3; ++q) x[q] = o[q] + h.t * d[q];
+        const double *ng = s->ng + 3 * h.tri;
+        double cos_i = fabs(dot3(d, ng));
+        int32_t mi = s->mat[h.tri];
+        const omat *mm = &s->mats[mi];
+        if (mm->type == ORC_LAMBERT) {
+            if (!turned) return 0;
+            double sg = dot3(ng, d) > 0.0 ? -1.0 : 1.0;
+            for (int q = 0; q < 3; ++q) {
+                out->x[q] = x[q];
+                out->n[q] = sg * ng[q];
+            }
+            out->phi = phi;
+            out->j = j;
+            return 1;
+        }
+        if (mm->type == ORC_GLASS) {
+            int32_t me;
+            double thick, R, T;
+            orc_pane_at(s, h.tri, h.u, h.v, &me, &thick);
+            orc_slab(cos_i, lambda, thick, sp->n[me * sp->nl + j], sp->k[me * sp->nl + j], sp->tint[me * sp->nl + j],
+                     &R, &T);
+            draw4(p->seed, p->job_id, pid, PHOTON_TAG, vtx, 0, u);
+            if (R + T > 0.0 && u[0] < R / (R + T)) {
+                double dn = dot3(d, ng);
+                for (int q = 0; q < 3; ++q) d[q] -= 2.0 * dn * ng[q];
+                turned = 1;
+            }
+            phi *= R + T;
+        } else {
+            double thick = thickness_at(s, h.tri, h.u, h.v);
+            orc_walk_stream st = {p->seed, pid, PHOTON_TAG, p->job_id, (uint32_t)vtx, 1};
+            double ue[4], Rs, Rp;
+            orc_walk_draw(&st, 0, 0, ue);
+            int pol = ue[1] < 0.5 ? 0 : 1;
+            orc_fresnel(cos_i, sp->n[mi * sp->nl + j], sp->k[mi * sp->nl + j], &Rs, &Rp);
+            if (ue[0] < (pol == 0 ? Rs : Rp)) {
+                double dn = dot3(d, ng);
+                for (int q = 0; q < 3; ++q) d[q] -= 2.0 * dn * ng[q];
+                turned = 1;
+            } else {
+                orc_walk_out wo;
+                orc_bubbly_walk(&st, cos_i, thick, sp->sigma[mi], sp->nref[mi], pol, &wo);
+                if (wo.kind == 0) return 0;
+                double nd[3];
+                orc_slab_to_world(d, ng, wo.dir, nd);
+                for (int q = 0; q < 3; ++q) d[q] = nd[q];
+                if (wo.kind == 1 || wo.bubbles > 0) turned = 1;
+                double alpha = 4.0 * PI * sp->k[mi * sp->nl + j] / (lambda * 1e-6) + sp->tint[mi * sp->nl + j];
+                phi *= exp(-alpha * wo.L);
+            }
+        }
+        for (int q = 0; q < 3; ++q) o[q] = x[q];
+        skip = h.tri;
+    }
+    return 0;
+}
+
+/* The first pass: every photon traced, the stored ones kept in photon order
+ * and hashed by the cells of side r. */
+static void photon_map_build(const rctx *c, ophmap *m)
+{
+    const orc_scene *s = c->s;
+    const orc_render_params *p = c->p;
+    memset(m, 0, sizeof(*m));
+    if (p->photons <= 0) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < 3 * (int64_t)s->nt; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double x = s->pos[3 * s->idx[i] + a];
+            lo[a] = fmin(lo[a], x);
+            hi[a] = fmax(hi[a], x);
+        }
+    double cen[3], rad = 0.0, e1[3], e2[3], h[3] = {0.2672612419124244, 0.5345224838248488, 0.8017837257372732};
+    for (int a = 0; a < 3; ++a) {
+        cen[a] = 0.5 * (lo[a] + hi[a]);
+        rad += 0.25 * (hi[a] - lo[a]) * (hi[a] - lo[a]);
+    }
+    rad = sqrt(rad) + 1e-6;
+    cross3(h, s->sun, e1);
+    normalize3(e1);
+    cross3(s->sun, e1, e2);
+    double c0[3], a1[3], a2[3];
+    for (int a = 0; a < 3; ++a) {
+        c0[a] = cen[a] + 2.0 * rad * s->sun[a];
+        a1[a] = rad * e1[a];
+        a2[a] = rad * e2[a];
+    }
+    double power = 4.0 * rad * rad * (double)c->sp->nl / (double)p->photons;
+    int64_t N = p->photons;
+    ophot *all = (ophot *)malloc(sizeof(ophot) * (size_t)N);
+    char *kept = (char *)calloc((size_t)N, 1);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t q = 0; q < N; ++q) kept[q] = (char)trace_photon(c, (uint32_t)q, c0, a1, a2, power, &all[q]);
+    int64_t n = 0;
+    for (int64_t q = 0; q < N; ++q)
+        if (kept[q]) all[n++] = all[q];
+    free(kept);
+    m->n = n;
+    m->ph = all;
+    m->r = p->photon_radius;
+    for (int a = 0; a < 3; ++a) m->lo[a] = lo[a];
+    uint32_t buckets = 1024;
+    while (buckets < 2 * (uint64_t)n && buckets < (1u << 24)) buckets <<= 1;
+    m->mask = buckets - 1;
+    m->start = (int64_t *)calloc((size_t)buckets + 1, sizeof(int64_t));
+    m->idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t cc[3];
+    for (int64_t q = 0; q < n; ++q) {
+        ph_cell(m, m->ph[q].x, cc);
+        m->start[ph_hash(cc[0], cc[1], cc[2], m->mask) + 1]++;
+    }
+    for (uint32_t b = 0; b < buckets; ++b) m->start[b + 1] += m->start[b];
+    int64_t *fill = (int64_t *)calloc((size_t)buckets, sizeof(int64_t));
+    for (int64_t q = 0; q < n; ++q) {
+        ph_cell(m, m->ph[q].x, cc);
+        uint32_t b = ph_hash(cc[0], cc[1], cc[2], m->mask);
+        m->idx[m->start[b] + fill[b]++] = q;
+    }
+    free(fill);
+}
+
+static void photon_map_free(ophmap *m)
+{
+    free(m->ph);
+    free(m->start);
+    free(m->idx);
+}
+
+/* Density estimate of the caustic light at x (surface side normal ns) for
+ * wavelength j: the stored power of the photons of that wavelength within r
+ * whose arrival side's normal is within 0.9 (cosine) of ns, over pi r^2.
+ * Each cell of the 27 around x is read once (cells may share a bucket). */
+static double photon_gather(const ophmap *m, const double *x, const double *ns, int j)
+{
+    int64_t cc[3];
+    ph_cell(m, x, cc);
+    uint32_t seen[27];
+    int n_seen = 0;
+    double sum = 0.0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                uint32_t b = ph_hash(cc[0] + dx, cc[1] + dy, cc[2] + dz, m->mask);
+                int dup = 0;
+                for (int q = 0; q < n_seen; ++q) dup |= seen[q] == b;
+                if (dup) continue;
+                seen[n_seen++] = b;
+                for (int64_t k = m->start[b]; k < m->start[b + 1]; ++k) {
+                    const ophot *ph = &m->ph[m->idx[k]];
+                    if (ph->j != j) continue;
+                    double e[3];
+                    sub3(ph->x, x, e);
+                    if (!(dot3(e, e) < m->r * m->r)) continue;
+                    if (!(dot3(ph->n, ns) > 0.9)) continue;
+                    sum += ph->phi;
+                }
+            }
+    return sum / (PI * m->r * m->r);
+}
+
+static int params_ok(const orc_scene *s, const orc_render_params *p);
+
+int64_t orc_photon_map(const orc_scene *s, const orc_render_params *p, double *out)
+{
+    if (!params_ok(s, p)) return -1;
+    spectra sp;
+    spectra_make(s, p, &sp);
+    rctx c = {s, p, &sp, {{0}}, NULL};
+    ophmap m;
+    photon_map_build(&c, &m);
+    if (out)
+        for (int64_t q = 0; q < m.n; ++q) {
+            for (int a = 0; a < 3; ++a) {
+                out[8 * q + a] = m.ph[q].x[a];
+                out[8 * q + 3 + a] = m.ph[q].n[a];
+            }
+            out[8 * q + 6] = m.ph[q].phi;
+            out[8 * q + 7] = m.ph[q].j;
+        }
+    int64_t n = m.n;
+    photon_map_free(&m);
+    spectra_free(&sp);
+    return n;
+}
+
 /* One (pixel, sample, wavelength) path estimate.  ev (may be NULL): the
  * path's events are added to *ev (event signature); pb (may be NULL): the
  * single-precision error bound of its contributions is added to *pb (see
@@ -1007,6 +1255,13 @@ static double path_radiance(const rctx *c, int i, int j, int smp, int li, uint64
                 if (pb)
                     *pb += fabs(beta * rho / PI * sp->E[li] * cs * T) *
                            (sbeta + 3.0 * p->prec_rel + p->prec_ceps / cs + s_sh);
+            }
+            if (c->ph) {
+                /* caustic photon map: rho / pi times the density estimate of
+                 * the turned sunlight arriving on this side */
+                double Lc = beta * rho / PI * photon_gather(c->ph, x, ns, li);
+                L += Lc;
+                if (pb) *pb += fabs(Lc) * (sbeta + 3.0 * p->prec_rel);
             }
             if (vtx == p->max_depth - 1) break;
             /* The cosine/pdf ratio of the bounce cancels pi, so the path
@@ -1115,6 +1370,7 @@ static int params_ok(const orc_scene *s, const orc_render_params *p)
         !p->lambda_nm)
         return 0;
     if (p->btdf_mode < ORC_BTDF_EXACT || p->btdf_mode > ORC_BTDF_FALLBACK) return 0;
+    if (p->photons < 0 || (p->photons > 0 && !(p->photon_radius > 0.0))) return 0;
     for (int m = 0; m < s->n_mat; ++m) {
         const omat *mm = &s->mats[m];
         if (mm->type != ORC_GLASS_BUBBLY || p->btdf_mode == ORC_BTDF_EXACT) continue;
@@ -1169,8 +1425,11 @@ int orc_render(const orc_scene *s, const orc_render_params *p, double *spec, dou
     if (!params_ok(s, p) || !spec) return -1;
     spectra sp;
     spectra_make(s, p, &sp);
-    rctx c = {s, p, &sp, {{0}}};
+    rctx c = {s, p, &sp, {{0}}, NULL};
     camera_make(p, &c.cam);
+    ophmap phm;
+    photon_map_build(&c, &phm);
+    if (p->photons > 0) c.ph = &phm;
     int nl = p->n_lambda;
     int B = p->n_bands < 1 ? 1 : (p->n_bands > nl ? nl : p->n_bands);
     int tile = p->tile > 0 ? p->tile : 16;
@@ -1199,6 +1458,7 @@ int orc_render(const orc_scene *s, const orc_render_params *p, double *spec, dou
                                p->prec_bound ? p->prec_bound + ((int64_t)j * p->W + i) * nl : NULL);
     }
     if (xyz && p->cmf_xyz) orc_spec_to_xyz((int64_t)p->W * p->H, nl, p->lambda_nm, p->cmf_xyz, spec, xyz);
+    photon_map_free(&phm);
     spectra_free(&sp);
     return 0;
 }
@@ -1209,8 +1469,11 @@ int orc_render_pixels(const orc_scene *s, const orc_render_params *p, int64_t m,
     if (!params_ok(s, p) || !spec || !pixels) return -1;
     spectra sp;
     spectra_make(s, p, &sp);
-    rctx c = {s, p, &sp, {{0}}};
+    rctx c = {s, p, &sp, {{0}}, NULL};
     camera_make(p, &c.cam);
+    ophmap phm;
+    photon_map_build(&c, &phm);
+    if (p->photons > 0) c.ph = &phm;
 #ifdef _OPENMP
     if (p->n_threads > 0) omp_set_num_threads(p->n_threads);
 #endif
@@ -1221,6 +1484,7 @@ int orc_render_pixels(const orc_scene *s, const orc_render_params *p, int64_t m,
                        p->events ? p->events + q * p->n_lambda : NULL,
                        p->prec_bound ? p->prec_bound + q * p->n_lambda : NULL);
     }
+    photon_map_free(&phm);
     spectra_free(&sp);
     return 0;
 }

@@ -133,6 +133,12 @@ typedef struct {
      * directions, prec_ceps the error of a cosine formed from them. */
     double *prec_bound;
     double prec_rel, prec_ceps, prec_eps;
+    /* Caustic photon map (photon mapping, Sec. 3.2; 0 photons: off): photons
+     * shot from the sun and stored where a pane has turned them; every
+     * Lambert vertex adds rho / pi times the stored power of its wavelength
+     * within photon_radius (metres) divided by pi r^2 (see orc_photon_map). */
+    int64_t photons;
+    double photon_radius;
 } orc_render_params;
 
 typedef struct orc_scene orc_scene;
@@ -144,6 +150,10 @@ double orc_u01(uint32_t x);
 
 /* Interface Fresnel reflectance, air -> n + ik, per polarisation. */
 void orc_fresnel(double cos_i, double n, double k, double *Rs, double *Rp);
+/* The caustic photon map of a render (test instrument view of the first
+ * pass): the photons stored, as rows (x, y, z, nx, ny, nz, power, j);
+ * returns the count, or -1.  out may be NULL to count only. */
+int64_t orc_photon_map(const orc_scene *s, const orc_render_params *p, double *out);
 /* Material and thickness of the pane of triangle t at barycentric (u, v):
  * with a distribution map, its texel's material and thickness (see
  * orc_dist_map); otherwise the triangle's material and thickness. */
@@ -216,6 +226,7 @@ typedef struct {
     double dir[3];  /* direction in air, slab frame (x in the plane of incidence, z into the slab) */
     double L;       /* geometric length travelled in glass (mm) */
     int32_t n_events; /* free flights taken (bubbles met and faces reached) */
+    int32_t bubbles;  /* bubbles met (0: the light left unscattered) */
 } orc_walk_out;
 
 /* The four uniforms of draw (event, sub) of a walk stream. */

@@ -138,6 +138,7 @@ void orc_bubbly_walk(const orc_walk_stream *st, double cos_i, double d, double s
     out->kind = 0;
     out->dir[0] = out->dir[1] = out->dir[2] = 0.0;
     out->n_events = 0;
+    out->bubbles = 0;
     for (uint32_t e = 1; e <= MC_MAX_EVENTS; ++e) {
         out->n_events = (int32_t)e;
         orc_walk_draw(st, e, 0, u);
@@ -162,6 +163,7 @@ void orc_bubbly_walk(const orc_walk_stream *st, double cos_i, double d, double s
         }
         L += l;
         z += l * dir[2];
+        ++out->bubbles;
         /* bubble: impact ratio sqrt(u2), azimuth 2 pi u3 about dir; the
          * polarisation label relative to the bubble is drawn afresh */
         double t1[3], t2[3], ep[3];

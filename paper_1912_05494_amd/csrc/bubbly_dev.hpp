@@ -67,6 +67,7 @@ struct WalkOut {
     int kind;     // 0 absorbed (event cap), 1 out through the entry face, 2 through the far face
     V3<R> a;      // direction in air, slab frame: x in the plane of incidence, z into the slab
     R L;          // length travelled in glass (mm)
+    int bubbles;  // bubbles met (0: the light left unscattered)
 };
 
 // The walk after the photon has entered (label pol drawn at entry).
@@ -75,6 +76,7 @@ __device__ WalkOut<R> bubbly_walk(const WalkStream &s, R cos_i, R d, R sigma, R 
 {
     WalkOut<R> out;
     out.kind = 0;
+    out.bubbles = 0;
     out.a = {R(0), R(0), R(0)};
     R u[4], v[4];
     const R sin_i = sqrt(fmax(R(1) - cos_i * cos_i, R(0)));
@@ -102,6 +104,7 @@ __device__ WalkOut<R> bubbly_walk(const WalkStream &s, R cos_i, R d, R sigma, R 
         }
         L += l;
         z += l * dir.z;
+        ++out.bubbles;
         V3<R> t1, t2;
         onb(dir, t1, t2);
         R sphi, cphi;

@@ -215,6 +215,8 @@ struct ChunkArgs {
     int32_t n_items, depth, lds_job, one_job, surr, bubbly, prec, n_panes;
     int32_t dd_sweeps;                  // > 0: closest hits by geometric sub-domains
     int32_t dd_march;                   // the hand-off stays in the thread
+    int32_t caustic;                    // gather the photon map after each bounce
+    PhotonWork<R> pw;
     int32_t cam_fused;          // camera rays may take the fused slab form (origins in the scene's bounds)
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
 };
@@ -260,6 +262,11 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
         mark(SDM_K_SHADOW_ACCUM);
         launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.one_job != 0, a.grid_a, s);
         done();
+        if (a.caustic) {
+            mark(SDM_K_CAUSTIC);
+            launch_caustic<R>(a.jobs, a.bands, a.w, a.pw, a.grid_a, s);
+            done();
+        }
         cur ^= 1;
     }
     launch_advance_cursor(a.w.cnt, a.chunk, s);
@@ -327,6 +334,69 @@ struct Budget {
     bool resume = false;        // continue ctx->partial (the accumulator holds its sums)
     uint64_t digest = 0;        // render_digest of the job
 };
+
+// Photon pass set-up (see sdm_render_params.photons): buffers, the hash grid
+// of cells of side r over the scene's bounds, and the emission square: half
+// sides along e1 = normalize(h x s) and e2 = s x e1 (h = (1, 2, 3) / sqrt(14),
+// s the sun direction) scaled by the bounding sphere's radius rho, centred at
+// the sphere's centre plus 2 rho s, area (2 rho)^2.
+template <class R>
+int photon_setup(sdm_context *ctx, const JobIn &j, ChunkArgs<R> &a, hipStream_t s)
+{
+    (void)s;
+    const sdm_scene *sc = j.sc;
+    PhotonWork<R> &pw = a.pw;
+    pw.n = (uint32_t)j.p->photons;
+    pw.cap = pw.n;
+    // At most 2^23 buckets: the bucket offsets (buckets + 1 values) are
+    // scanned in blocks of 4096 and the block totals by one block of 4096,
+    // which covers up to 2^24 values.  Which photons a gather finds does not
+    // depend on the bucket count (the radius test drops colliding cells).
+    uint32_t buckets = 1024;
+    while (buckets < 2u * pw.n && buckets < (1u << 23)) buckets <<= 1;
+    pw.mask = buckets - 1u;
+    pw.nblk = (buckets + 1u + 4095u) / 4096u;
+    HIPCHK(ctx, ctx->ph_rec.ensure((size_t)pw.cap * sizeof(PhotonRec<R>)));
+    HIPCHK(ctx, ctx->ph_sorted.ensure((size_t)pw.cap * sizeof(PhotonRec<R>)));
+    HIPCHK(ctx, ctx->ph_start.ensure((size_t)(buckets + 1) * sizeof(uint32_t)));
+    HIPCHK(ctx, ctx->ph_cursor.ensure((size_t)buckets * sizeof(uint32_t)));
+    HIPCHK(ctx, ctx->ph_part.ensure((size_t)pw.nblk * sizeof(uint32_t)));
+    // one occupancy bit per bucket up to 2^20 buckets (128 KiB, resident in
+    // L2); above, bit b & (2^20 - 1) stands for every bucket that shares it
+    pw.occ_mask = std::min<uint32_t>(buckets, 1u << 20) - 1u;
+    HIPCHK(ctx, ctx->ph_occ.ensure((size_t)(pw.occ_mask + 1u) / 8u));
+    pw.rec = ctx->ph_rec.as<PhotonRec<R>>();
+    pw.sorted = ctx->ph_sorted.as<PhotonRec<R>>();
+    pw.start = ctx->ph_start.as<uint32_t>();
+    pw.cursor = ctx->ph_cursor.as<uint32_t>();
+    pw.part = ctx->ph_part.as<uint32_t>();
+    pw.occ = ctx->ph_occ.as<uint32_t>();
+    pw.gstack = a.w.gstack;
+    pw.cnt = a.w.cnt;
+    pw.r = j.p->photon_radius;
+    double cen[3], rad = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        pw.lo[q] = sc->lo[q];
+        cen[q] = 0.5 * (sc->lo[q] + sc->hi[q]);
+        rad += 0.25 * (sc->hi[q] - sc->lo[q]) * (sc->hi[q] - sc->lo[q]);
+    }
+    rad = std::sqrt(rad) + 1e-6;
+    double sn[3] = {sc->dev.sun[0], sc->dev.sun[1], sc->dev.sun[2]};
+    const double sl = std::sqrt(sn[0] * sn[0] + sn[1] * sn[1] + sn[2] * sn[2]);
+    for (double &x : sn) x /= sl;
+    const double hh[3] = {0.2672612419124244, 0.5345224838248488, 0.8017837257372732};
+    double e1[3] = {hh[1] * sn[2] - hh[2] * sn[1], hh[2] * sn[0] - hh[0] * sn[2], hh[0] * sn[1] - hh[1] * sn[0]};
+    const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (double &x : e1) x /= l1;
+    const double e2[3] = {sn[1] * e1[2] - sn[2] * e1[1], sn[2] * e1[0] - sn[0] * e1[2], sn[0] * e1[1] - sn[1] * e1[0]};
+    for (int q = 0; q < 3; ++q) {
+        pw.c[q] = cen[q] + 2.0 * rad * sn[q];
+        pw.e1[q] = rad * e1[q];
+        pw.e2[q] = rad * e2[q];
+    }
+    pw.power = 4.0 * rad * rad * (double)j.p->n_lambda / (double)std::max<uint32_t>(pw.n, 1u);
+    return SDM_OK;
+}
 
 template <class R>
 int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s,
@@ -473,6 +543,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         jb.beta_thr = p->beta_threshold;
         jb.btdf_mode = p->btdf_mode;
         jb.err_bound = p->err_bound;
+        jb.caustic = p->photons > 0 ? 1 : 0;
         if (sc->max_pane >= 0 && p->btdf_mode == SDM_BTDF_FALLBACK) {
             const size_t ncell = (size_t)net->n_panes * p->err_dims[0] * p->err_dims[1] * p->err_dims[2];
             HIPCHK(ctx, hipMemcpyAsync(ctx->errtab.as<float>() + err_pos, p->err_table, ncell * sizeof(float),
@@ -506,7 +577,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         const bool dd = nj == 1 && jobs[0].sc->dev.dd.n_cells > 0;
         const size_t hit_b = (size_t)cap * sizeof(HitRec<R>) + (size_t)cap * 4 + (size_t)cap * sizeof(GlassRec<R>) +
                              (dd ? 2 * (size_t)cap * sizeof(DdEntry<R>) + 512 : 0) + 256;
-        const size_t sh_b = 4 * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
+        const bool caustic = nj == 1 && jobs[0].p->photons > 0;
+        const size_t sh_b = (caustic ? 8 : 4) * plane + 4 * (size_t)cap * 4 + (size_t)cap * nb * sizeof(R) +
                             (size_t)cap * kMaxGlass * (8 + sizeof(R)) + 12 * 256;
         HIPCHK(ctx, ctx->pool.ensure(2 * pool_b + 1024));
         HIPCHK(ctx, ctx->hits.ensure(hit_b + 2048));
@@ -562,6 +634,11 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         w.sskip = (int32_t *)take((size_t)cap * 4); w.spix = (uint32_t *)take((size_t)cap * 4);
         w.saux = (uint32_t *)take((size_t)cap * 4); w.socc = (int32_t *)take((size_t)cap * 4);
         w.scs = (R *)take(plane);
+        w.sgr = w.snx = w.sny = w.snz = nullptr;
+        if (caustic) {
+            w.sgr = (R *)take(plane);
+            w.snx = (R *)take(plane); w.sny = (R *)take(plane); w.snz = (R *)take(plane);
+        }
         w.contrib = (R *)take((size_t)cap * nb * sizeof(R));
         w.sg_leaf = (int32_t *)take((size_t)cap * kMaxGlass * 4);
         w.sg_d = (R *)take((size_t)cap * kMaxGlass * sizeof(R));
@@ -616,6 +693,13 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             launch_zero_f64(w.acc, acc_off[nj], s);
         if (want_sig) launch_zero_f64(reinterpret_cast<double *>(w.sig), acc_off[nj], s);
         launch_zero_counters(w.cnt, s);
+        a.caustic = caustic ? 1 : 0;
+        if (caustic) {
+            if (int rc = photon_setup<R>(ctx, jobs[0], a, s)) return rc;
+            (void)tm.begin(SDM_K_PHOTON);
+            launch_photon_pass<R>(a.jobs, a.pw, a.grid_t, ctx->num_cu, s);
+            (void)tm.end();
+        }
         if (n_chunks == 0) {
             // nothing left to trace: the outputs come from the accumulator
         } else if (graph) {
@@ -715,6 +799,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
                 st.tris_tested[q] = c.tris[q];
             }
             st.interface_rays = c.interface_rays;
+            st.photons_stored = caustic ? std::min<uint64_t>(c.phcount, a.pw.cap) : 0;
             float ms = 0;
             (void)hipEventElapsedTime(&ms, ev0, ev1);
             st.ms_render = ms;
@@ -759,6 +844,12 @@ int check_job(sdm_context *ctx, const JobIn &j)
     if (j.out->events && !ptr_is_device(j.out->events))
         return fail(ctx, SDM_E_INVALID, "events output is not device memory");
     if (j.p->max_items < 0) return fail(ctx, SDM_E_INVALID, "max_items must be >= 0");
+    if (j.p->photons < 0 || j.p->photons > (int64_t)1 << 30)
+        return fail(ctx, SDM_E_INVALID, "photons must be in [0, 2^30]");
+    if (j.p->photons > 0 && !(j.p->photon_radius > 0.0f && std::isfinite(j.p->photon_radius)))
+        return fail(ctx, SDM_E_INVALID, "photon_radius must be > 0");
+    if (j.p->photons > 0 && j.p->max_items > 0)
+        return fail(ctx, SDM_E_UNSUPPORTED, "the photon map is built for whole renders (no max_items)");
     return SDM_OK;
 }
 
@@ -919,6 +1010,8 @@ int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_
             return fail(ctx, SDM_E_UNSUPPORTED, "item budgets apply to single renders");
         if (jobs[i].scene->dev.dd.n_cells > 0)
             return fail(ctx, SDM_E_UNSUPPORTED, "scenes cut into sub-domains render singly");
+        if (jobs[i].params->photons > 0)
+            return fail(ctx, SDM_E_UNSUPPORTED, "the photon map applies to single renders");
     }
     ctx->partial.valid = false;
     return render_any(ctx, js, stats, (hipStream_t)hip_stream);

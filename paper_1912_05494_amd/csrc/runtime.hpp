@@ -83,6 +83,7 @@ struct sdm_context {
         size_t acc_elems = 0;         // doubles of the accumulator
     } partial;
     DevBuf acc_base;                  // the accumulator a resumed render starts from
+    DevBuf ph_rec, ph_sorted, ph_start, ph_cursor, ph_part, ph_occ;   // caustic photon map
     // autotuned (chunk, tile) per scene and render shape
     struct Tuned {
         const sdm_scene *scene;

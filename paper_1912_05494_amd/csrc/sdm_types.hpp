@@ -110,7 +110,20 @@ struct JobDev {
     int32_t err_dims[3];        // error-table cells along cos, thickness, density
     const float *err_table;     // [n_panes][err_dims] (fallback mode)
     float err_bound;            // a cell above this uses the exact walk
+    // caustic photon map (photon mapping, Sec. 3.2)
+    int32_t caustic;            // 1: every Lambert vertex keeps a record for the gather
     int32_t pad1;
+};
+
+constexpr uint32_t kPhotonTag = 0xFFFFFFF0u;   // sample word of photon draws (camera samples stay below 2^31)
+
+// A photon of the caustic map, at rest on a Lambert surface: position, the
+// normal of the side it arrived on, its wavelength index and power.
+template <class R>
+struct alignas(16) PhotonRec {
+    R x, y, z, phi;
+    R nx, ny, nz;
+    int32_t j;
 };
 
 constexpr int kBtdfExact = 0, kBtdfSurrogate = 1, kBtdfFallback = 2;
@@ -146,6 +159,8 @@ struct alignas(256) Counters {
     uint32_t pad_k[kCounterPad - 1];
     uint32_t ddn[3];            // sub-domain interface queues: entries (see k_dd_sweep)
     uint32_t pad_d[kCounterPad - 3];
+    uint32_t phcount;           // photons stored in the caustic map
+    uint32_t pad_p[kCounterPad - 1];
     uint32_t overflow;          // bit 0: a pool or record buffer was full;
                                 // bit 1: a shadow ray crossed more than kMaxGlass panes;
                                 // bit 2: a ray crossed more sub-domains than the sweeps cover
@@ -254,6 +269,8 @@ struct Work {
     int32_t *sskip;
     uint32_t *spix, *saux;      // spix: pixel | kSpectral
     R *scs;                     // [record] scalar factor of the contributions
+    R *sgr;                     // [record] g rho / pi without the sun's cosine (caustic gather)
+    R *snx, *sny, *snz;         // [record] normal on the side the path arrived (caustic gather)
     R *contrib;                 // AoSoA [record][j] per-wavelength factors (kSpectral records)
     int32_t *socc;              // panes crossed (0..kMaxGlass), -1 occluded
     int32_t *sg_leaf;           // [record][kMaxGlass] panes crossed, and at each crossing
@@ -281,5 +298,26 @@ __host__ __device__ inline uint32_t pack_aux(int depth, int band, int job)
 {
     return (uint32_t)depth | ((uint32_t)band << kAuxBandShift) | ((uint32_t)job << kAuxJobShift);
 }
+
+// The photon pass's buffers and emission square (see k_photon).
+template <class R>
+struct PhotonWork {
+    uint32_t n;                     // photons shot
+    uint32_t cap;                   // photons that can be stored
+    uint32_t mask;                  // hash buckets - 1
+    uint32_t nblk;                  // scan blocks
+    PhotonRec<R> *rec, *sorted;
+    uint32_t *start;                // [buckets + 1]: counts, then first photon of each bucket
+    uint32_t *cursor;               // [buckets]
+    uint32_t *part;                 // [nblk] scan block sums
+    uint32_t *occ;                  // occupancy bits: bit (b & occ_mask) set when bucket b holds a photon
+    uint32_t occ_mask;              // occupancy bits - 1 (a power of two, at least 32)
+    int32_t *gstack;
+    Counters *cnt;
+    double r;                       // cell side and gather radius
+    double lo[3];                   // hash grid origin
+    double c[3], e1[3], e2[3];      // emission square: centre and half-side axes
+    double power;                   // E(lambda) factor: square area x wavelengths / photons
+};
 
 }  // namespace sdm

@@ -984,6 +984,277 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
 }
 
 // ---------------------------------------------------------------------------
+// Caustic photon map (photon mapping, Sec. 3.2: a pass before the render
+// shoots photons from the light and stores where they land; the render
+// estimates the light they carry from their density).  Sun photons, each of
+// one render wavelength, leave a square across the sun's direction that
+// covers the scene and follow the panes' optics: clear glass reflects with
+// probability R / (R + T) (weight R + T), bubbly glass takes the exact walk.
+// A photon is stored where it first meets a Lambert surface if a pane has
+// turned it (a reflection, or light scattered by bubbles): the straight,
+// unscattered sunlight is the render's own shadow-ray estimate.  The stored
+// photons are hashed by the cell of side r they lie in.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t ph_hash(int ix, int iy, int iz, uint32_t mask)
+{
+    return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) & mask;
+}
+
+template <class R>
+__device__ __forceinline__ void ph_cell(const V3<R> &x, const double lo[3], double r, int &ix, int &iy, int &iz)
+{
+    const R ir = R(1.0 / r);
+    ix = (int)floor((x.x - R(lo[0])) * ir);
+    iy = (int)floor((x.y - R(lo[1])) * ir);
+    iz = (int)floor((x.z - R(lo[2])) * ir);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kTraceBlock) k_photon(const JobDev *__restrict__ jobs, PhotonWork<R> pw)
+{
+    __shared__ int32_t s_stack[kLdsStack * kTraceBlock];
+    const JobDev &jb = jobs[0];
+    const SceneDev &sc = jb.sc;
+    StackT<kTraceBlock> st = make_stack<kTraceBlock>(s_stack, pw.gstack);
+    WaveFeed feed{0, 0, false, 0};
+    Ray<R> ry;
+    Closest<R> h;
+    int64_t item = -1;
+    uint32_t pid = 0;
+    int vtx = 0, j = 0;
+    bool turned = false;
+    R phi = R(0);
+    const R teps = teps_of<R>(sc);
+    const V3<R> sun = {R(sc.sun[0]), R(sc.sun[1]), R(sc.sun[2])};
+    uint32_t n_nodes = 0, n_tests = 0;
+    for (;;) {
+        const int64_t got = feed.next(item < 0, pw.n);
+        if (got >= 0) {
+            item = got;
+            pid = (uint32_t)got;
+            const uint4 e = vertex_draws(jb.seed, jb.job_word, pid, kPhotonTag, -1, 0);
+            const R a = R(2) * u01<R>(e.x) - R(1), b = R(2) * u01<R>(e.y) - R(1);
+            j = min((int)(u01<R>(e.z) * R(jb.nl)), jb.nl - 1);
+            const V3<R> o = {R(pw.c[0]) + a * R(pw.e1[0]) + b * R(pw.e2[0]),
+                             R(pw.c[1]) + a * R(pw.e1[1]) + b * R(pw.e2[1]),
+                             R(pw.c[2]) + a * R(pw.e1[2]) + b * R(pw.e2[2])};
+            set_dir(ry, o, R(-1) * sun);
+            ry.skip = -1;
+            phi = gld((const R *)jb.E + j) * R(pw.power);
+            vtx = 0;
+            turned = false;
+            h.tb = R(INFINITY); h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
+            st.sp = 0;
+            ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+        }
+        if (!__ballot(item >= 0)) {
+            if (feed.done) break;
+            continue;
+        }
+        if (item >= 0) {
+            const bool fin = ry.cur == kDone || closest_step<false>(sc, nullptr, 0, st, ry, h, teps, n_nodes, n_tests);
+            if (fin) {
+                bool go = false;
+                V3<R> x = ry.o, dn = ry.d;
+                if (h.trib >= 0 && vtx < jb.max_depth && phi > R(0)) {
+                    const TriDev tr = load_tri(sc.tris, h.trib);
+                    const int mat = __float_as_int(tr.b.w), mt = __float_as_int(tr.c.w);
+                    const V3<R> d = ry.d, ng = tri_normal<R>(tr);
+                    x = ry.o + h.tb * d;
+                    const R cos_i = fabs(dot(d, ng));
+                    const R lam = gld((const R *)jb.lam + j);
+                    if (mt == 0 || mt == 3) {
+                        if (turned) {
+                            const uint32_t q = atomicAdd(&pw.cnt->phcount, 1u);
+                            if (q < pw.cap) {
+                                const V3<R> ns = dot(ng, d) > R(0) ? R(-1) * ng : ng;
+                                PhotonRec<R> pr;
+                                pr.x = x.x; pr.y = x.y; pr.z = x.z; pr.phi = phi;
+                                pr.nx = ns.x; pr.ny = ns.y; pr.nz = ns.z; pr.j = j;
+                                pw.rec[q] = pr;
+                            }
+                        }
+                    } else if (mt == 1) {
+                        int me;
+                        R thick;
+                        pane_at<R>(sc, h.trib, mat, h.ub, h.vb, me, thick);
+                        const size_t mo = (size_t)me * jb.ms + j;
+                        R Rr, Tt;
+                        slab_RT<R>(cos_i, lam, thick, gld((const R *)jb.n + mo), gld((const R *)jb.k + mo),
+                                   gld((const R *)jb.tint + mo), Rr, Tt);
+                        const R u = u01<R>(vertex_draws(jb.seed, jb.job_word, pid, kPhotonTag, vtx, 0).x);
+                        if (Rr + Tt > R(0) && u < Rr / (Rr + Tt)) {
+                            dn = d - (R(2) * dot(d, ng)) * ng;
+                            turned = true;
+                        }
+                        phi *= Rr + Tt;
+                        go = true;
+                    } else {
+                        // bubbly pane: the exact walk at the photon's wavelength
+                        const R thick = pane_thickness<R>(sc, h.trib, h.ub, h.vb);
+                        const double *bub = sc.mat_bub + 4 * (size_t)mat;
+                        const size_t mo = (size_t)mat * jb.ms + j;
+                        const R nn = gld((const R *)jb.n + mo), kk = gld((const R *)jb.k + mo);
+                        const WalkStream ws = {jb.seed, pid, kPhotonTag, jb.job_word, (uint32_t)vtx, true};
+                        R ue[4];
+                        walk_draw<R>(ws, 0, 0, ue);
+                        const int pol = ue[1] < R(0.5) ? 0 : 1;
+                        R Rs, Rp;
+                        fresnel_sp<R>(cos_i, nn, kk, Rs, Rp);
+                        if (ue[0] < (pol == 0 ? Rs : Rp)) {
+                            dn = d - (R(2) * dot(d, ng)) * ng;
+                            turned = true;
+                            go = true;
+                        } else {
+                            const WalkOut<R> wo = bubbly_walk<R>(ws, cos_i, thick, R(gld(bub)), R(gld(bub + 1)), pol);
+                            if (wo.kind != 0) {
+                                dn = slab_to_world<R>(d, ng, wo.a);
+                                turned = turned || wo.kind == 1 || wo.bubbles > 0;
+                                const R alpha = R(12.566370614359172) * kk / (lam * R(1e-6)) +
+                                                gld((const R *)jb.tint + mo);
+                                phi *= exp(-alpha * wo.L);
+                                go = true;
+                            }
+                        }
+                    }
+                    ++vtx;
+                }
+                if (go && vtx < jb.max_depth) {
+                    set_dir(ry, x, dn);
+                    ry.skip = h.trib;
+                    h.tb = R(INFINITY); h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
+                    st.sp = 0;
+                    ry.cur = sc.n_nodes > 0 ? 0 : kDone;
+                } else {
+                    item = -1;
+                }
+            }
+        }
+    }
+}
+
+// Hash grid: clear the counts and cursors, count the photons per bucket,
+// scan (blocks of 4096, then the block sums), and place each photon.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_ph_clear(PhotonWork<R> pw)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= pw.mask + 1u; i += gridDim.x * blockDim.x) {
+        pw.start[i] = 0u;
+        if (i <= pw.mask) pw.cursor[i] = 0u;
+        if (i <= pw.occ_mask >> 5) pw.occ[i] = 0u;
+    }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_ph_count(PhotonWork<R> pw)
+{
+    const uint32_t n = min(pw.cnt->phcount, pw.cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const PhotonRec<R> p = pw.rec[i];
+        int ix, iy, iz;
+        ph_cell<R>(V3<R>{p.x, p.y, p.z}, pw.lo, pw.r, ix, iy, iz);
+        const uint32_t b = ph_hash(ix, iy, iz, pw.mask);
+        atomicAdd(pw.start + b, 1u);
+        atomicOr(pw.occ + ((b & pw.occ_mask) >> 5), 1u << (b & 31u));
+    }
+}
+
+constexpr int kScanBlock = 1024, kScanPer = 4;   // 4096 values per block
+
+// Exclusive scan of v[0, n) in blocks of 4096; each block's total to part.
+__global__ void __launch_bounds__(kScanBlock) k_scan_blocks(uint32_t *v, uint32_t n, uint32_t *part)
+{
+    __shared__ uint32_t s[kScanBlock];
+    const uint32_t base = blockIdx.x * (kScanBlock * kScanPer) + threadIdx.x * kScanPer;
+    uint32_t x[kScanPer], sum = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        x[k] = base + k < n ? v[base + k] : 0u;
+        sum += x[k];
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {    // inclusive scan of the thread sums
+        const uint32_t t = threadIdx.x >= (uint32_t)off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - sum;
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) v[base + k] = run;
+        run += x[k];
+    }
+    if (part && threadIdx.x == kScanBlock - 1) part[blockIdx.x] = s[kScanBlock - 1];
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_add(uint32_t *v, uint32_t n, const uint32_t *part)
+{
+    const uint32_t add = part[blockIdx.x];
+    const uint32_t base = blockIdx.x * (kScanBlock * kScanPer) + threadIdx.x * kScanPer;
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n) v[base + k] += add;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_ph_place(PhotonWork<R> pw)
+{
+    const uint32_t n = min(pw.cnt->phcount, pw.cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const PhotonRec<R> p = pw.rec[i];
+        int ix, iy, iz;
+        ph_cell<R>(V3<R>{p.x, p.y, p.z}, pw.lo, pw.r, ix, iy, iz);
+        const uint32_t b = ph_hash(ix, iy, iz, pw.mask);
+        pw.sorted[pw.start[b] + atomicAdd(pw.cursor + b, 1u)] = p;
+    }
+}
+
+// Caustic gather at the Lambert vertices of the chunk (their shadow records):
+// L_j += g b_j rho_j / pi * sum of Phi / (pi r^2) over the photons of
+// wavelength j within r that arrived on the same side (normals within 0.9).
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_caustic(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands,
+                                                    Work<R> w, PhotonWork<R> pw)
+{
+    const uint32_t ns = min(w.cnt->scount, w.cap);
+    const JobDev &jb = jobs[0];
+    const R r2 = R(pw.r * pw.r), inv_area = R(1.0 / (3.14159265358979323846 * pw.r * pw.r));
+    const PhotonRec<R> *P = pw.sorted;
+    for (uint32_t rec = blockIdx.x * blockDim.x + threadIdx.x; rec < ns; rec += gridDim.x * blockDim.x) {
+        const uint32_t sp = w.spix[rec], aux = w.saux[rec];
+        const BandDev bd = bands[(aux >> kAuxBandShift) & ((1u << kAuxBandBits) - 1u)];
+        const bool spec = (sp & kSpectral) != 0u;
+        const R gr = w.sgr[rec];
+        if (gr == R(0)) continue;
+        const V3<R> x = {w.sx[rec], w.sy[rec], w.sz[rec]}, n = {w.snx[rec], w.sny[rec], w.snz[rec]};
+        double *row = w.acc + jb.acc_off + (uint64_t)(sp & ~kSpectral) * jb.nl;
+        int cx, cy, cz;
+        ph_cell<R>(x, pw.lo, pw.r, cx, cy, cz);
+        uint32_t seen[27];
+        int n_seen = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const uint32_t b = ph_hash(cx + dx, cy + dy, cz + dz, pw.mask);
+                    if (!((pw.occ[(b & pw.occ_mask) >> 5] >> (b & 31u)) & 1u)) continue;   // no photon there
+                    bool dup = false;
+                    for (int q = 0; q < n_seen; ++q) dup = dup || seen[q] == b;
+                    if (dup) continue;
+                    seen[n_seen++] = b;
+                    for (uint32_t k = pw.start[b]; k < pw.start[b + 1]; ++k) {
+                        const PhotonRec<R> p = P[k];
+                        if (p.j < bd.l0 || p.j >= bd.l0 + bd.nb) continue;
+                        const R ex = p.x - x.x, ey = p.y - x.y, ez = p.z - x.z;
+                        if (!(ex * ex + ey * ey + ez * ez < r2)) continue;
+                        if (!(p.nx * n.x + p.ny * n.y + p.nz * n.z > R(0.9))) continue;
+                        const R f = spec ? w.contrib[aosoa(rec, p.j - bd.l0, w.nbmax)] : R(1);
+                        unsafeAtomicAdd(row + p.j, (double)(gr * f * p.phi * inv_area));
+                    }
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-wavelength rows handled by the whole wave.  Each lane whose flag is set
 // owns a task on rows of nbm values (nbm a multiple of 4); the wave works
 // through the tasks ng at a time, gl = nbm / 4 lanes per task and four
@@ -1097,7 +1368,7 @@ __global__ void __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_e
         int32_t tri = -1;
         int kind = -1;            // 0 miss, 1 Lambert, 2 glass, 3 bubbly glass (both queued)
         bool want_shadow = false, keep = false, spec = false, gray = false;
-        V3<R> x = {R(0), R(0), R(0)}, dnew = x;
+        V3<R> x = {R(0), R(0), R(0)}, dnew = x, nrm = x;
         R cs = R(0), g = R(0), rho_g = R(1);
         int mat = 0;
         const JobDev *jb = nullptr;
@@ -1133,7 +1404,10 @@ __global__ void __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_e
                     const V3<R> ns = dot(ng, d) > R(0) ? R(-1) * ng : ng;
                     const V3<R> sun = {R(jb->sc.sun[0]), R(jb->sc.sun[1]), R(jb->sc.sun[2])};
                     cs = dot(ns, sun);
-                    want_shadow = cs > R(0);
+                    // with the caustic map, every Lambert vertex keeps a record for
+                    // its gather (the sun's term is zero where it faces away)
+                    want_shadow = cs > R(0) || jb->caustic;
+                    nrm = ns;
                     keep = !last;
                     if (!last) {
                         const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
@@ -1190,7 +1464,11 @@ __global__ void __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_e
                 w.sskip[sslot] = tri;
                 w.spix[sslot] = pix | (out_spec ? kSpectral : 0u);
                 w.saux[sslot] = aux;
-                w.scs[sslot] = gn * inv_pi * cs;
+                w.scs[sslot] = cs > R(0) ? gn * inv_pi * cs : R(0);
+                if (jb->caustic) {
+                    w.sgr[sslot] = gn * inv_pi;
+                    w.snx[sslot] = nrm.x; w.sny[sslot] = nrm.y; w.snz[sslot] = nrm.z;
+                }
             }
             if (keep) {
                 // the energy threshold of a gray path acts on g
@@ -1952,7 +2230,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
     GridRange<R> gr{0, 0, R(0)};
     int64_t item = -1;
     int job = 0, ng = 0;
-    bool occ = false, over = false, grid = false;
+    bool occ = false, over = false, grid = false, away = false;
     R teps = R(0);
     uint32_t n_nodes = 0, n_tests = 0;
     for (;;) {
@@ -1976,6 +2254,9 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
             ry.cur = !grid && sc.n_nodes > 0 ? 0 : kDone;
             teps = teps_of<R>(sc);
             ng = 0;
+            // a record whose sun term is zero (a surface facing away from the
+            // sun, kept for the caustic gather) needs no walk
+            away = w.scs[s] == R(0);
             occ = false;
             over = false;
             st.sp = 0;
@@ -2001,7 +2282,10 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
                 ++ng;
             };
             bool fin;
-            if (grid)
+            if (away) {
+                fin = true;
+                occ = true;
+            } else if (grid)
                 fin = grid_step(jobs[job].sc, ry, gr, occ, teps, on_glass, n_nodes, n_tests);
             else
                 fin = ry.cur == kDone || shadow_step<true>(jobs[job].sc, s_nodes, job == lds_job ? n_lds : 0, st, ry,
@@ -2381,6 +2665,7 @@ __global__ void k_zero_counters(Counters *c)
         c->nodes[0] = c->nodes[1] = c->tris[0] = c->tris[1] = 0;
         c->interface_rays = 0;
         c->ddn[0] = c->ddn[1] = c->ddn[2] = 0;
+        c->phcount = 0;
     }
 }
 
@@ -2552,6 +2837,26 @@ void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bo
     }
 }
 template <class R>
+void launch_photon_pass(const JobDev *jobs, const PhotonWork<R> &pw, int grid_trace, int num_cu, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ph_clear<R>, dim3(4 * num_cu), dim3(kBlock), 0, s, pw);
+    hipLaunchKernelGGL(k_photon<R>, dim3(grid_trace), dim3(kTraceBlock), 0, s, jobs, pw);
+    hipLaunchKernelGGL(k_ph_count<R>, dim3(4 * num_cu), dim3(kBlock), 0, s, pw);
+    // the buckets' counts and a final 0 (start[buckets] = total); at most
+    // 2^23 + 1 values, so the block totals (pw.nblk <= 4096) fit one block
+    const uint32_t nv = pw.mask + 2u;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(pw.nblk), dim3(kScanBlock), 0, s, pw.start, nv, pw.part);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, s, pw.part, pw.nblk, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_scan_add, dim3(pw.nblk), dim3(kScanBlock), 0, s, pw.start, nv, (const uint32_t *)pw.part);
+    hipLaunchKernelGGL(k_ph_place<R>, dim3(4 * num_cu), dim3(kBlock), 0, s, pw);
+}
+template <class R>
+void launch_caustic(const JobDev *jobs, const BandDev *bands, const Work<R> &w, const PhotonWork<R> &pw, int grid,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_caustic<R>, dim3(grid), dim3(kBlock), 0, s, jobs, bands, w, pw);
+}
+template <class R>
 void launch_dd_trace(const JobDev *jobs, const Work<R> &w, int cur, bool surface, int sweeps, bool march, int grid,
                      hipStream_t s)
 {
@@ -2715,6 +3020,9 @@ int occupancy(int kernel_class, int lds_bytes)
                                      uint64_t, uint32_t, int, hipStream_t);                                        \
     template void launch_trace<R>(const JobDev *, const Work<R> &, int, int, bool, bool, int, hipStream_t);        \
     template void launch_dd_trace<R>(const JobDev *, const Work<R> &, int, bool, int, bool, int, hipStream_t);    \
+    template void launch_photon_pass<R>(const JobDev *, const PhotonWork<R> &, int, int, hipStream_t);            \
+    template void launch_caustic<R>(const JobDev *, const BandDev *, const Work<R> &, const PhotonWork<R> &, int,  \
+                                    hipStream_t);                                                                 \
     template void launch_shade<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int, hipStream_t);  \
     template void launch_shade_glass<R>(const JobDev *, const BandDev *, const Work<R> &, int, bool, int,          \
                                         hipStream_t);                                                              \

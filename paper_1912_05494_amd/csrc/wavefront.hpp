@@ -15,6 +15,11 @@ template <class R>
 void launch_trace(const JobDev *jobs, const Work<R> &w, int cur, int lds_job, bool surface, bool one_job, int grid,
                   hipStream_t s);
 template <class R>
+void launch_photon_pass(const JobDev *jobs, const PhotonWork<R> &pw, int grid_trace, int num_cu, hipStream_t s);
+template <class R>
+void launch_caustic(const JobDev *jobs, const BandDev *bands, const Work<R> &w, const PhotonWork<R> &pw, int grid,
+                    hipStream_t s);
+template <class R>
 void launch_dd_trace(const JobDev *jobs, const Work<R> &w, int cur, bool surface, int sweeps, bool march, int grid,
                      hipStream_t s);
 template <class R>

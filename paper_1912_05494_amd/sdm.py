@@ -19,7 +19,7 @@ SDM_OK = 0
 SDM_MEM_HOST, SDM_MEM_DEVICE = 0, 1
 SDM_PREC_FP32, SDM_PREC_FP64 = 0, 1
 KERNELS = ("generate", "trace", "shade", "shadow", "finalize", "shadow_accum", "shade_glass", "bubbly_eval",
-           "shade_bubbly")
+           "shade_bubbly", "photon", "caustic")
 BTDF_MODES = {"exact": 0, "surrogate": 1, "fallback": 2}
 SHADOW_WALKS = {"auto": 0, "bvh": 1}
 
@@ -61,7 +61,8 @@ class RenderParams(C.Structure):
                 ("tile_h", C.c_int32), ("beta_threshold", C.c_float), ("precision", C.c_int32),
                 ("chunk_paths", C.c_int64), ("timing", C.c_int32), ("btdf_mode", C.c_int32),
                 ("err_dims", C.c_int32 * 3), ("mlp", C.c_void_p), ("err_table", _FP),
-                ("err_bound", C.c_float), ("graph", C.c_int32), ("max_items", C.c_int64)]
+                ("err_bound", C.c_float), ("graph", C.c_int32), ("max_items", C.c_int64),
+                ("photons", C.c_int64), ("photon_radius", C.c_float)]
 
 
 class Stats(C.Structure):
@@ -70,9 +71,9 @@ class Stats(C.Structure):
                 ("forks", C.c_uint64), ("chunks", C.c_uint64), ("nodes_visited", C.c_uint64 * 2),
                 ("tris_tested", C.c_uint64 * 2), ("bubbly_vertices", C.c_uint64),
                 ("spectral_paths", C.c_uint64), ("spectral_records", C.c_uint64),
-                ("glass_vertices", C.c_uint64 * 2), ("ms_render", C.c_double), ("kernel_ms", C.c_double * 9),
-                ("kernel_launches", C.c_uint64 * 9), ("items_done", C.c_uint64), ("items_total", C.c_uint64),
-                ("interface_rays", C.c_uint64)]
+                ("glass_vertices", C.c_uint64 * 2), ("ms_render", C.c_double), ("kernel_ms", C.c_double * 11),
+                ("kernel_launches", C.c_uint64 * 11), ("items_done", C.c_uint64), ("items_total", C.c_uint64),
+                ("interface_rays", C.c_uint64), ("photons_stored", C.c_uint64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_[:6]}
@@ -88,6 +89,7 @@ class Stats(C.Structure):
         d["items_done"] = int(self.items_done)
         d["items_total"] = int(self.items_total)
         d["interface_rays"] = int(self.interface_rays)
+        d["photons_stored"] = int(self.photons_stored)
         return d
 
 
@@ -169,6 +171,7 @@ EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_
             "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table",
             "sdm_render_batch", "sdm_autotune", "sdm_render_checkpoint", "sdm_render_resume", "sdm_mlp_save",
             "sdm_mlp_load", "sdm_mlp_info", "sdm_slab_mc_noalloc")
+SDM_E_UNSUPPORTED = -4
 SDM_E_ABORTED = -5
 
 
@@ -291,7 +294,7 @@ class Scene:
 
 
 def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision="fp32",
-                chunk_paths=0, timing=False, btdf=None, graph=False, max_items=0):
+                chunk_paths=0, timing=False, btdf=None, graph=False, max_items=0, photons=0, photon_radius=0.05):
     """btdf: None (exact walks on bubbly panes) or a dict with mode ("exact",
     "surrogate", "fallback"), mlp (an MLP) and, for "fallback", err_table
     (array (n_panes, n_cos, n_d, n_rho)) and bound."""
@@ -316,6 +319,8 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
         SDM_PREC_FP64 if precision == "fp64" else SDM_PREC_FP32, int(chunk_paths), int(timing))
     p.graph = int(bool(graph))
     p.max_items = int(max_items)
+    p.photons = int(photons)
+    p.photon_radius = float(photon_radius)
     if btdf is not None:
         p.btdf_mode = BTDF_MODES[btdf.get("mode", "exact")]
         if btdf.get("mlp") is not None:
@@ -332,7 +337,7 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
 
 def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, tile=(0, 0),
            precision="fp32", chunk_paths=0, timing=False, stream=None, spectral=True, xyz=True,
-           btdf=None, graph=False, max_items=0, events=None, resume=None):
+           btdf=None, graph=False, max_items=0, events=None, resume=None, photons=0, photon_radius=0.05):
     """Render into new device tensors: (spectral (H, W, nl) float32, xyz (H, W, 3) float64,
     stats dict).
 
@@ -349,7 +354,7 @@ def render(ctx: Context, scene: Scene, settings, n_bands=None, band_edges=None, 
     spec_t = torch.empty((cam.H, cam.W, nl), dtype=torch.float32, device=dev) if spectral else None
     xyz_t = torch.empty((cam.H, cam.W, 3), dtype=torch.float64, device=dev) if xyz else None
     p, keep = make_params(settings, n_bands, band_edges, tile, precision, chunk_paths, timing, btdf, graph,
-                          max_items)
+                          max_items, photons, photon_radius)
     st = Stats()
     out = Outputs(_ptr(spec_t), _ptr(xyz_t), SDM_MEM_DEVICE, SDM_MEM_DEVICE, C.pointer(st), _ptr(events))
     if resume is None:

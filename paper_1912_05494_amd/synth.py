@@ -141,6 +141,17 @@ class Camera:
     projection: int = 0        # 0 = pinhole, 1 = orthographic
     ortho_height: float = 1.0  # view height in metres for orthographic
 
+    def __post_init__(self):
+        # the library's camera is single precision: hold the values it will
+        # see, so that every consumer (the library in FP32 or FP64, a
+        # reference in double) starts from the same camera
+        f32 = lambda v: float(np.float32(v))
+        self.eye = tuple(f32(v) for v in self.eye)
+        self.target = tuple(f32(v) for v in self.target)
+        self.up = tuple(f32(v) for v in self.up)
+        self.vfov_deg = f32(self.vfov_deg)
+        self.ortho_height = f32(self.ortho_height)
+
 
 @dataclasses.dataclass
 class RenderSettings:

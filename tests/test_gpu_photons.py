@@ -1,0 +1,178 @@
+"""Caustic photon map (photon mapping, Sec. 3.2): sunlight that a pane turns
+(a reflection at clear glass; at a bubbly pane an entry reflection, an exit
+back through the entry face or a bubble met on the walk) is traced from the
+sun, stored where it first meets a Lambert surface, and gathered at the
+camera paths' Lambert vertices as rho / pi times the density estimate.
+
+- FP64 kernels: the stored photon count equals the oracle's photon map, and
+  every spectral pixel matches the oracle render with the same photons and
+  radius (a mirror pane that throws the sun onto a wall; the bubbly nave,
+  whose bubbles scatter sunlight into the interior).
+- The caustic is there: the wall's beam footprint is brighter with the map
+  than without it, by the closed form's order (R E / pi on the footprint).
+- Where no pane turns light, the render with the map equals the render
+  without it, bit for bit (FP32).
+- FP32 kernels against FP64 kernels: the stored count within 0.1 % and the
+  image mean within 1 %; per pixel they agree to the FP32 tolerance on at
+  least 99 % of the spectral pixels (a photon within rounding of the radius
+  or of the normal test may be counted on one side only).
+  The same at 2^24 photons, the largest hash grid.
+- Batches, item budgets and bad parameters are rejected.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1912_05494_amd import synth
+from scenes_for_tests import assemble, glass, lambert, settings
+
+pytestmark = pytest.mark.gpu
+
+SQ2 = math.sqrt(2.0)
+RADIUS = 0.125          # exact in binary: the FP64 kernels and the oracle see the same radius
+
+
+def mirror_scene(half=0.5):
+    """Floor z = 0, a wall at x = 2 and a clear pane centred at (0, 0, 1)
+    whose normal is (1, 0, 1) / sqrt(2); sun overhead, dark sky."""
+    fl = np.array([[-2, -2, 0], [2, -2, 0], [2, 2, 0], [-2, 2, 0]], dtype=np.float32)
+    wall = np.array([[2, -2, 0], [2, 2, 0], [2, 2, 3], [2, -2, 3]], dtype=np.float32)
+    a = half / SQ2
+    pane = np.array([[-a, -half, 1 + a], [a, -half, 1 - a], [a, half, 1 - a], [-a, half, 1 + a]], dtype=np.float32)
+    t = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    g = glass(n=1.52, k=1e-7, tint=0.0, thick=3.0, dispersive=True)
+    return assemble([(fl, t, 0), (wall, t, 0), (pane, t, 1)], [lambert(0.6), g], sun_dir=(0.0, 0.0, 1.0),
+                    sun_E=1.0, sky_L=0.0)
+
+
+def mirror_settings(W=48, H=48, spp=4):
+    cam = synth.Camera(eye=(0.6, -1.4, 1.5), target=(2.0, 0.0, 1.0), W=W, H=H, vfov_deg=60.0)
+    return settings(cam, spp=spp, max_depth=4)
+
+
+def tol_ok(g, o):
+    return np.abs(g - o) <= 1e-4 * np.maximum(np.abs(o), 1e-3 * np.abs(o).mean())
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    from paper_1912_05494_amd import sdm
+    assert torch.cuda.is_available()
+    ctx = sdm.Context(0)
+    yield sdm, ctx, torch
+    ctx.close()
+
+
+def render(gpu, scene, st, **kw):
+    sdm, ctx, torch = gpu
+    gs = sdm.Scene(ctx, scene)
+    spec, _, stats = sdm.render(ctx, gs, st, **kw)
+    torch.cuda.synchronize()
+    gs.close()
+    return spec.cpu().numpy().astype(np.float64), stats
+
+
+def test_mirror_caustic_fp64_matches_oracle(gpu, orc):
+    sc = mirror_scene()
+    st = mirror_settings()
+    N = 1 << 20
+    osc = orc.OracleScene(sc)
+    stored = orc.photon_map(osc, st, N, RADIUS)
+    ref, _ = orc.render(osc, st, photons=N, photon_radius=RADIUS)
+    g, s = render(gpu, sc, st, precision="fp64", photons=N, photon_radius=RADIUS)
+    print(f"stored photons: gpu {s['photons_stored']}, oracle {len(stored)}")
+    assert len(stored) > 1000
+    assert s["photons_stored"] == len(stored)
+    assert tol_ok(g, ref).all(), np.argwhere(~tol_ok(g, ref))[:5]
+    # the caustic: the footprint on the wall gains about rho R E / pi per wavelength
+    g0, s0 = render(gpu, sc, st, precision="fp64")
+    assert s0["photons_stored"] == 0
+    gain = (g - g0).mean(axis=2)
+    assert gain.min() >= 0.0
+    lam = st.lambda_nm.astype(np.float64)
+    gm = sc.materials[1]
+    R, _ = orc.slab(math.cos(math.pi / 4), lam, 3.0, np.interp(lam, synth.LAMBDA_81, gm.n),
+                    np.interp(lam, synth.LAMBDA_81, gm.k), np.interp(lam, synth.LAMBDA_81, gm.alpha_tint))
+    expect = 0.6 * R.mean() / math.pi          # irradiance R E on the footprint, E = 1
+    lit = gain > 0.25 * expect
+    assert lit.mean() > 0.05
+    assert 0.7 * expect < np.median(gain[lit]) < 1.3 * expect
+
+
+def test_mirror_caustic_fp64_most_photons(gpu, orc):
+    """2^24 photons, the most the benchmark shoots: the hash grid has its
+    largest bucket count (2^23) and the two-level scan its most blocks."""
+    sc = mirror_scene()
+    st = mirror_settings(W=32, H=32, spp=2)
+    N = 1 << 24
+    osc = orc.OracleScene(sc)
+    stored = orc.photon_map(osc, st, N, RADIUS)
+    ref, _ = orc.render(osc, st, photons=N, photon_radius=RADIUS)
+    g, s = render(gpu, sc, st, precision="fp64", photons=N, photon_radius=RADIUS)
+    assert s["photons_stored"] == len(stored)
+    assert tol_ok(g, ref).all()
+
+
+def test_bubbly_nave_fp64_matches_oracle(gpu, orc):
+    sc = synth.nave_scene(seed=1, bubbly=True)
+    st = synth.nave_settings(W=40, H=32, spp=2, max_depth=5)
+    N = 1 << 18
+    osc = orc.OracleScene(sc)
+    stored = orc.photon_map(osc, st, N, RADIUS)
+    ref, _ = orc.render(osc, st, photons=N, photon_radius=RADIUS)
+    g, s = render(gpu, sc, st, precision="fp64", photons=N, photon_radius=RADIUS)
+    g0, _ = render(gpu, sc, st, precision="fp64")
+    print(f"nave stored photons: gpu {s['photons_stored']}, oracle {len(stored)}; caustic share of the image "
+          f"{(g.sum() - g0.sum()) / g.sum():.4f}")
+    assert len(stored) > 100
+    assert s["photons_stored"] == len(stored)
+    assert tol_ok(g, ref).all()
+    assert g.sum() > g0.sum()
+
+
+def test_nothing_turned_equals_no_map(gpu):
+    fl = np.array([[-2, -2, 0], [2, -2, 0], [2, 2, 0], [-2, 2, 0]], dtype=np.float32)
+    p = np.array([[-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float32)
+    t = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    sc = assemble([(fl, t, 0), (p, t, 1)], [lambert(0.5), glass(n=1.5, k=1e-6, tint=0.3)],
+                  sun_dir=(0.0, 0.0, 1.0), sun_E=2.0, sky_L=0.5)
+    st = settings(synth.Camera(eye=(0.3, -3, 2), target=(0, 0, 0.3), W=32, H=32), spp=4, max_depth=4)
+    a, _ = render(gpu, sc, st)
+    b, s = render(gpu, sc, st, photons=100000, photon_radius=RADIUS)
+    assert s["photons_stored"] == 0
+    assert np.array_equal(a, b)
+
+
+def test_fp32_agrees_with_fp64(gpu):
+    sc = mirror_scene()
+    st = mirror_settings(W=64, H=64, spp=4)
+    N = 1 << 20
+    g64, s64 = render(gpu, sc, st, precision="fp64", photons=N, photon_radius=RADIUS)
+    g32, s32 = render(gpu, sc, st, photons=N, photon_radius=RADIUS)
+    ok = tol_ok(g32, g64)
+    print(f"stored fp32 {s32['photons_stored']} fp64 {s64['photons_stored']}; {ok.mean():.5f} of the spectral "
+          f"pixels within tolerance")
+    assert abs(s32["photons_stored"] - s64["photons_stored"]) <= 1e-3 * s64["photons_stored"]
+    assert abs(g32.mean() / g64.mean() - 1.0) < 0.01
+    assert ok.mean() >= 0.99
+
+
+def test_photon_rejections(gpu):
+    sdm, ctx, torch = gpu
+    sc = mirror_scene()
+    st = mirror_settings(W=8, H=8, spp=1)
+    gs = sdm.Scene(ctx, sc)
+    for kw in ({"photons": -1}, {"photons": 10, "photon_radius": 0.0}, {"photons": 10, "max_items": 1}):
+        with pytest.raises(sdm.SdmError):
+            sdm.render(ctx, gs, st, **kw)
+    # a batch of two jobs, the first asking for the map, through the C ABI
+    import ctypes as C
+    params = [sdm.make_params(st, photons=10 if i == 0 else 0, photon_radius=RADIUS) for i in range(2)]
+    imgs = [torch.empty((8, 8, len(st.lambda_nm)), dtype=torch.float32, device="cuda") for _ in range(2)]
+    outs = [sdm.Outputs(sdm._ptr(im), None, sdm.SDM_MEM_DEVICE, sdm.SDM_MEM_DEVICE, None) for im in imgs]
+    arr = (sdm.Job * 2)(*[sdm.Job(gs.ptr, C.pointer(params[i][0]), C.pointer(outs[i])) for i in range(2)])
+    rc = sdm.lib().sdm_render_batch(ctx.ptr, 2, arr, None, sdm._stream())
+    assert rc == sdm.SDM_E_UNSUPPORTED
+    gs.close()

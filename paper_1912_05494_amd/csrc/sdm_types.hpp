@@ -35,7 +35,7 @@ struct alignas(16) TriDev {
 struct alignas(16) GridCand {
     float4 a;   // vertex 0, leaf
     float4 b;   // vertex 1, largest depth
-    float4 c;   // vertex 2, material type
+    float4 c;   // vertex 2, material type | material index << 2
 };
 
 // Scene data resident on the device.

@@ -139,7 +139,9 @@ SunGrid build_sun_grid(const TriDev *tris, int32_t nt, const int32_t *mat_type, 
         const float sm = std::nextafter((float)smax[i], INFINITY);
         int32_t mi;
         std::memcpy(&mi, &tris[i].b.w, 4);
-        const int32_t mt = mat_type[mi];
+        // type in the low two bits, material index above: the walk reports a
+        // pane's material without loading its triangle
+        const int32_t mt = mat_type[mi] | mi << 2;
         float fl, fm;
         std::memcpy(&fl, &i, 4);
         std::memcpy(&fm, &mt, 4);

@@ -452,7 +452,7 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
 // One step of an any-hit walk toward +infinity: visit nodes until a leaf is
 // due (speculatively, as in the closest-hit step) and test it.  An opaque
 // triangle ends the walk (occluded); each pane crossed is reported to
-// on_glass(leaf, u, v).
+// on_glass(leaf, material, u, v).
 template <bool kFused, class R, class St, class F>
 __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *lds_nodes, int n_lds, St &st,
                                             Ray<R> &ry, bool &occluded, R teps, F &&on_glass, uint32_t &nodes,
@@ -501,7 +501,7 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
                 ry.cur = kDone;
                 return true;
             }
-            on_glass(i, u, v);
+            on_glass(i, __float_as_int(tr.b.w), u, v);
         }
     }
     ry.cur = cur;
@@ -554,13 +554,13 @@ __device__ __forceinline__ bool grid_step(const SceneDev &sc, const Ray<R> &ry, 
         R t, u, v;
         if (!ray_tri(ry, from4<R>(A), from4<R>(B), from4<R>(C), t, u, v)) continue;
         if (!(t > teps)) continue;
-        const int mt = __float_as_int(C.w);
+        const int mw = __float_as_int(C.w), mt = mw & 3;
         if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
             occluded = true;
             g.cur = g.end;
             return true;
         }
-        on_glass(leaf, u, v);
+        on_glass(leaf, mw >> 2, u, v);
     }
     return g.cur >= g.end;
 }
@@ -606,9 +606,9 @@ __device__ __forceinline__ V3<R> tri_normal(const TriDev &tr)
 }
 
 template <class R>
-__device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, R u, R v)
+__device__ __forceinline__ R pane_thickness(const SceneDev &sc, int leaf, int mat, R u, R v)
 {
-    if (!sc.has_vthick) return R(gld(sc.mat_thick + __float_as_int(load_tri(sc.tris, leaf).b.w)));
+    if (!sc.has_vthick) return R(gld(sc.mat_thick + mat));
     const float4 th = gld4(sc.thick + leaf);
     return (R(1) - u - v) * R(th.x) + u * R(th.y) + v * R(th.z);
 }
@@ -624,7 +624,7 @@ __device__ __forceinline__ void pane_at(const SceneDev &sc, int leaf, int mat, R
     m_out = mat;
     const int mp = sc.n_maps > 0 ? gld(sc.mat_map + mat) : -1;
     if (mp < 0) {
-        d_out = pane_thickness<R>(sc, leaf, u, v);
+        d_out = pane_thickness<R>(sc, leaf, mat, u, v);
         return;
     }
     const int4 hdr = gld4(sc.map_hdr + mp);
@@ -638,7 +638,7 @@ __device__ __forceinline__ void pane_at(const SceneDev &sc, int leaf, int mat, R
     const int iy = ft < R(0) ? 0 : (ft > R(H - 1) ? H - 1 : (int)ft);
     m_out = gld(sc.map_mat + hdr.z + iy * W + ix);
     if (!hdr.w) {
-        d_out = pane_thickness<R>(sc, leaf, u, v);
+        d_out = pane_thickness<R>(sc, leaf, mat, u, v);
         return;
     }
     const R xs = s * R(W) - R(0.5), ys = t * R(H) - R(0.5);
@@ -1092,7 +1092,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_photon(const JobDev *__restrict
                         go = true;
                     } else {
                         // bubbly pane: the exact walk at the photon's wavelength
-                        const R thick = pane_thickness<R>(sc, h.trib, h.ub, h.vb);
+                        const R thick = pane_thickness<R>(sc, h.trib, mat, h.ub, h.vb);
                         const double *bub = sc.mat_bub + 4 * (size_t)mat;
                         const size_t mo = (size_t)mat * jb.ms + j;
                         const R nn = gld((const R *)jb.n + mo), kk = gld((const R *)jb.k + mo);
@@ -1774,7 +1774,7 @@ __device__ __forceinline__ BubblyVertex bubbly_vertex(const JobDev *jobs, const 
     d = {pd.x, pd.y, pd.z};
     ng = tri_normal<R>(tr);
     cos_i = fabs(dot(d, ng));
-    thick = pane_thickness<R>(v.jb->sc, v.tri, hr.u, hr.v);
+    thick = pane_thickness<R>(v.jb->sc, v.tri, v.mat, hr.u, hr.v);
     const double *b = v.jb->sc.mat_bub + 4 * (size_t)v.mat;
     v.sigma = gld(b);
     v.n_ref = gld(b + 1);
@@ -2256,7 +2256,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
             ng = 0;
             // a record whose sun term is zero (a surface facing away from the
             // sun, kept for the caustic gather) needs no walk
-            away = w.scs[s] == R(0);
+            away = jobs[job].caustic && w.scs[s] == R(0);
             occ = false;
             over = false;
             st.sp = 0;
@@ -2267,7 +2267,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
         }
         if (item >= 0) {
             const uint32_t rec = (uint32_t)item;
-            auto on_glass = [&](int leaf, R u, R v) {
+            auto on_glass = [&](int leaf, int mat, R u, R v) {
                 if (ng == kMaxGlass) {
                     over = true;
                     return;
@@ -2275,7 +2275,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
                 const SceneDev &scj = jobs[job].sc;
                 int m;
                 R dd;
-                pane_at<R>(scj, leaf, __float_as_int(load_tri(scj.tris, leaf).b.w), u, v, m, dd);
+                pane_at<R>(scj, leaf, mat, u, v, m, dd);
                 w.sg_leaf[(size_t)rec * kMaxGlass + ng] = leaf;
                 w.sg_d[(size_t)rec * kMaxGlass + ng] = dd;
                 w.sg_m[(size_t)rec * kMaxGlass + ng] = m;
@@ -2791,11 +2791,11 @@ __global__ void __launch_bounds__(kBlock) k_debug_shadow(SceneDev sc, uint32_t m
             continue;
         }
         if (item >= 0) {
-            auto on_glass = [&](int leaf, float u, float v) {
+            auto on_glass = [&](int leaf, int mat, float u, float v) {
                 const TriDev tr = load_tri(sc.tris, leaf);
                 int mt;
                 float dm;
-                pane_at<float>(sc, leaf, __float_as_int(tr.b.w), u, v, mt, dm);
+                pane_at<float>(sc, leaf, mat, u, v, mt, dm);
                 float Rr, Tt;
                 slab_RT<float>(fabsf(dot(sun, tri_normal<float>(tr))), lambda_nm, dm, n_at[mt], k_at[mt],
                                t_at[mt] + (float)gld(sc.mat_bub + 4 * mt), Rr, Tt);

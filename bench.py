@@ -644,6 +644,59 @@ def photons_bench(args):
     ctx.close()
 
 
+# useful multiply-adds of one training sample, x2 for flops: forward
+# 12x64 + 64x64 + 64x64 + 64x3, the input gradients of the four layers and
+# the weight gradients the same again (the padded tile entries not counted)
+TRAIN_FLOP_PER_SAMPLE = 3 * 2 * (12 * 64 + 64 * 64 + 64 * 64 + 64 * 3)
+
+
+def train_bench(args):
+    """Surrogate training on the matrix cores: Adam steps of the 12-64-64-64-3
+    network with 24 pane embeddings, batches of 8192 and 65536 drawn from
+    2^20 synthetic tuples (cos U(0, 1], the 81-wavelength grid, thickness
+    U(2, 5) mm, density U(0, 34)) with uniform targets; the step time does
+    not depend on the values.  Per step: the gradient pass and the fused
+    sum / Adam / repack pass."""
+    import torch
+    from paper_1912_05494_amd import sdm, surrogate, synth
+
+    ctx = sdm.Context(0)
+    dev = torch.device("cuda", 0)
+    n_panes = 24
+    tup, pane = surrogate.random_tuples(1 << 20, n_panes, synth.LAMBDA_81, seed=4)
+    t, pn = torch.from_numpy(tup).to(dev), torch.from_numpy(pane).to(dev)
+    target = torch.rand((len(tup), 3), dtype=torch.float32, device=dev, generator=torch.Generator(dev).manual_seed(5))
+    net = sdm.MLP(ctx, n_panes, surrogate.init_params(n_panes, seed=0))
+    rows = {}
+    for batch, steps in ((8192, 20 * args.steps), (65536, 5 * args.steps)):
+        net.train(t, pn, target, steps=max(args.warmup, 1) * 10, batch=batch, lr=1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.train(t, pn, target, steps=steps, batch=batch, lr=1e-3)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        sps = batch / dt
+        rows[batch] = {"us_per_step": dt * 1e6, "samples_per_s": sps,
+                       "tflops": sps * TRAIN_FLOP_PER_SAMPLE / 1e12,
+                       "frac_bf16_peak": sps * TRAIN_FLOP_PER_SAMPLE / 2.5e15}
+        print(f"batch {batch}: {dt * 1e6:.1f} us per step, {sps / 1e6:.1f} M samples/s", file=sys.stderr, flush=True)
+    net.close()
+    ctx.close()
+    r = rows[8192]
+    out = {"metric": "surrogate training samples/sec (batch 8192)", "value": r["samples_per_s"],
+           "unit": "samples/s", "n_gpus": 1, "steps": 20 * args.steps, "warmup": args.warmup,
+           "ms_per_step": r["us_per_step"] / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "Adam steps of the 12-64-64-64-3 surrogate, 24 pane embeddings, batch 8192 "
+                                  "(and 65536) from 2^20 synthetic tuples"},
+           "roofline": {"bound": "mfma", "achieved": r["tflops"], "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": r["frac_bf16_peak"], "traffic": None,
+                        "work_model": f"{TRAIN_FLOP_PER_SAMPLE} flop per sample (forward, input and weight "
+                                      "gradients)"},
+           "batches": rows}
+    print(json.dumps(out), flush=True)
+
+
 def batch_bench(args):
     """The uneven 32-job batch (square sides 128-1024, 10k-200k triangles,
     8-81 wavelengths, 16-128 spp; scene seed 2 + job) as one wavefront,
@@ -703,14 +756,14 @@ def main():
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--form", default="plain",
-                    choices=["plain", "bubbly", "batch", "table1", "large", "maps", "subdomains", "photons"],
+                    choices=["plain", "bubbly", "batch", "table1", "large", "maps", "subdomains", "photons", "train"],
                     help="plain: the clear-glass nave (default); bubbly: bubbly panes in four forms; "
                          "batch: the uneven 32-job batch in one wavefront; table1: the oracle's speedup "
                          "against threads x bands on the host (no GPU); large: the 1 M-triangle nave "
                          "with 200 bubbly panes at 1920x1080, fallback against exact; maps: the nave with "
                          "stained-glass distribution maps against per-pane glass; subdomains: geometric "
                          "sub-domain cuts of the nave and the large nave; photons: the bubbly nave with "
-                         "the caustic photon map at 2^20 to 2^24 photons")
+                         "the caustic photon map at 2^20 to 2^24 photons; train: surrogate training steps")
     ap.add_argument("--photon-radius", type=float, default=0.1, help="gather radius of --form photons (m)")
     ap.add_argument("--batch-jobs", type=int, default=32)
     ap.add_argument("--batch-scale", type=float, default=1.0)
@@ -754,6 +807,8 @@ def main():
         return subdomains_bench(args)
     if args.form == "photons":
         return photons_bench(args)
+    if args.form == "train":
+        return train_bench(args)
     if args.form == "bubbly":
         bubbly_bench(args)
         return

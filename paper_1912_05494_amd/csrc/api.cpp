@@ -685,7 +685,6 @@ int sdm_mlp_create(sdm_context *ctx, int32_t n_panes, const float *params, sdm_m
     hipError_t e = upload(net->params, params, (size_t)net->P);
     if (e == hipSuccess) e = net->m1.ensure(pb);
     if (e == hipSuccess) e = net->m2.ensure(pb);
-    if (e == hipSuccess) e = net->grad.ensure(pb);
     if (e == hipSuccess) e = net->wb.ensure((size_t)mlp_wb_elems() * 2);
     if (e == hipSuccess) e = net->bb.ensure((size_t)mlp_bb_elems() * sizeof(float));
     if (e == hipSuccess) e = hipMemset(net->m1.p, 0, pb);
@@ -822,16 +821,25 @@ int sdm_mlp_train(sdm_mlp *net, int64_t m, const float *tuples, const int32_t *p
     HIPCHK(ctx, net->loss.ensure((size_t)tp->steps * sizeof(float)));
     launch_zero_i32(ctx->flag.as<int>(), 1, s);
     const int64_t nb = m / tp->batch;
+    // two launches per step: the gradient pass (block rows) and the fused sum,
+    // Adam step and repacking of the weights the next pass reads
+    const int nblk = mlp_grad_blocks(net, tp->batch);
+    HIPCHK(ctx, net->partial.ensure((size_t)nblk * net->P * sizeof(float)));
+    HIPCHK(ctx, net->loss_partial.ensure((size_t)nblk * sizeof(float)));
+    launch_mlp_pack(net->params.as<float>(), net->wb.p, net->bb.as<float>(), s);
+    const float inv_n = 1.0f / (float)tp->batch;
     for (int32_t step = 0; step < tp->steps; ++step) {
         const int64_t off = (step % nb) * (int64_t)tp->batch;
-        if (int rc = mlp_enqueue_grad(net, tp->batch, tuples + 4 * off, panes + off, target + 3 * off,
-                                      net->grad.as<float>(), net->loss.as<float>() + step, s))
-            return rc;
+        launch_mlp_grad((uint32_t)tp->batch, net->n_panes, tuples + 4 * off, panes + off, target + 3 * off, net->wb.p,
+                        net->bb.as<float>(), net->params.as<float>() + mlp_net_params(), inv_n,
+                        net->partial.as<float>(), net->loss_partial.as<float>(), ctx->flag.as<int>(), nblk, s);
         ++net->t;
         const float c1 = (float)(1.0 - std::pow((double)tp->beta1, (double)net->t));
         const float c2 = (float)(1.0 - std::pow((double)tp->beta2, (double)net->t));
-        launch_mlp_adam((int)net->P, net->grad.as<float>(), net->params.as<float>(), net->m1.as<float>(),
-                        net->m2.as<float>(), tp->lr, tp->beta1, tp->beta2, tp->eps, c1, c2, s);
+        launch_mlp_reduce_adam(nblk, (int)net->P, net->partial.as<float>(), net->loss_partial.as<float>(), inv_n,
+                               net->loss.as<float>() + step, net->params.as<float>(), net->m1.as<float>(),
+                               net->m2.as<float>(), tp->lr, tp->beta1, tp->beta2, tp->eps, c1, c2, net->wb.p,
+                               net->bb.as<float>(), s);
     }
     HIPCHK(ctx, hipGetLastError());
     if (int rc = check_flag(ctx, s, "sdm_mlp_train")) return rc;

@@ -40,13 +40,20 @@ constexpr int kOffW1 = 0, kOffB1 = 768, kOffW2 = 832, kOffB2 = 4928, kOffW3 = 49
 constexpr int kWb = 64 * 32 + 64 * 64 + 64 * 64 + 16 * 64;   // 11264 BF16
 constexpr int kBb = 64 + 64 + 64 + 16;                       // 208 FP32
 
+// LDS row strides (BF16 elements) of the staged weights and the per-wave
+// activations: rows padded by 8, so consecutive rows start 16 bytes apart
+// modulo the 128-byte bank cycle (80 and 144 bytes; 48 for the 16-wide
+// output gradients) and a column read by 16 lanes does not fall in one bank.
+constexpr int kLd32 = 40, kLd64 = 72, kLd16 = 24;
+
 struct alignas(16) NetLds {
-    __bf16 W1[64 * 32], W2[64 * 64], W3[64 * 64], W4[16 * 64];
+    __bf16 W1[64 * kLd32], W2[64 * kLd64], W3[64 * kLd64], W4[16 * kLd64];
     float b1[64], b2[64], b3[64], b4[16];
 };
 
 struct alignas(16) WaveBuf {   // per wave, 16 samples
-    __bf16 X0[16 * 32], H1[16 * 64], H2[16 * 64], H3[16 * 64], Z0[16 * 64], Z1[16 * 64], dO[16 * 16];
+    __bf16 X0[16 * kLd32], H1[16 * kLd64], H2[16 * kLd64], H3[16 * kLd64], Z0[16 * kLd64], Z1[16 * kLd64],
+        dO[16 * kLd16];
     float O[16 * 16];
 };
 
@@ -56,13 +63,23 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Stages the weights (rows of 8-value chunks into the padded rows) and the
+// biases in LDS with 16-byte copies; the device copies are allocation-aligned.
+static_assert(kWb * 2 % 16 == 0 && kBb * 4 % 16 == 0, "16-byte staging");
 __device__ __forceinline__ void load_net(NetLds &net, const __bf16 *wb, const float *bb)
 {
-    const __bf16 *src = wb;
-    __bf16 *dst = net.W1;
-    for (int i = threadIdx.x; i < kWb; i += blockDim.x) dst[i] = src[i];
-    float *bd = net.b1;
-    for (int i = threadIdx.x; i < kBb; i += blockDim.x) bd[i] = bb[i];
+    const uint4 *src = reinterpret_cast<const uint4 *>(wb);
+    for (int q = threadIdx.x; q < kWb * 2 / 16; q += blockDim.x) {
+        __bf16 *d;
+        if (q < 256) d = net.W1 + (q / 4) * kLd32 + 8 * (q % 4);                       // W1p [64][32]
+        else if (q < 768) d = net.W2 + ((q - 256) / 8) * kLd64 + 8 * ((q - 256) % 8);  // W2 [64][64]
+        else if (q < 1280) d = net.W3 + ((q - 768) / 8) * kLd64 + 8 * ((q - 768) % 8); // W3 [64][64]
+        else d = net.W4 + ((q - 1280) / 8) * kLd64 + 8 * ((q - 1280) % 8);             // W4p [16][64]
+        *reinterpret_cast<uint4 *>(d) = src[q];
+    }
+    const uint4 *bs = reinterpret_cast<const uint4 *>(bb);
+    uint4 *bd = reinterpret_cast<uint4 *>(net.b1);
+    for (int i = threadIdx.x; i < kBb * 4 / 16; i += blockDim.x) bd[i] = bs[i];
     __syncthreads();
 }
 
@@ -78,9 +95,10 @@ __device__ __forceinline__ void features(float cosv, float lam, float d, float r
     for (int e = 12; e < 32; ++e) row[e] = (__bf16)0.0f;
 }
 
-// Y[16][64] = relu(X[16][K] W[64][K]^T + b), K = 32 * ksteps, stored BF16.
+// Y[16][64] = relu(X[16][K] W[64][K]^T + b), K = 32 * ksteps, stored BF16
+// with row stride ldy.
 __device__ __forceinline__ void dense_relu(const __bf16 *X, int ldx, const __bf16 *W, int ldw, const float *b,
-                                           int ksteps, __bf16 *Y)
+                                           int ksteps, __bf16 *Y, int ldy)
 {
     const int l = lane_id(), g = l / 16, c = l % 16;
     for (int t = 0; t < 4; ++t) {
@@ -92,24 +110,24 @@ __device__ __forceinline__ void dense_relu(const __bf16 *X, int ldx, const __bf1
         }
         for (int r = 0; r < 4; ++r) {
             const float z = acc[r] + b[16 * t + c];
-            Y[(4 * g + r) * 64 + 16 * t + c] = (__bf16)(z > 0.0f ? z : 0.0f);
+            Y[(4 * g + r) * ldy + 16 * t + c] = (__bf16)(z > 0.0f ? z : 0.0f);
         }
     }
 }
 
 __device__ __forceinline__ void forward_tile(const NetLds &net, WaveBuf &wb)
 {
-    dense_relu(wb.X0, 32, net.W1, 32, net.b1, 1, wb.H1);
+    dense_relu(wb.X0, kLd32, net.W1, kLd32, net.b1, 1, wb.H1, kLd64);
     wave_sync();
-    dense_relu(wb.H1, 64, net.W2, 64, net.b2, 2, wb.H2);
+    dense_relu(wb.H1, kLd64, net.W2, kLd64, net.b2, 2, wb.H2, kLd64);
     wave_sync();
-    dense_relu(wb.H2, 64, net.W3, 64, net.b3, 2, wb.H3);
+    dense_relu(wb.H2, kLd64, net.W3, kLd64, net.b3, 2, wb.H3, kLd64);
     wave_sync();
     const int l = lane_id(), g = l / 16, c = l % 16;
     f32x4 acc = {0, 0, 0, 0};
     for (int ks = 0; ks < 2; ++ks) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(wb.H3 + c * 64 + 32 * ks + 8 * g);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(net.W4 + c * 64 + 32 * ks + 8 * g);
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(wb.H3 + c * kLd64 + 32 * ks + 8 * g);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(net.W4 + c * kLd64 + 32 * ks + 8 * g);
         acc = mfma32(a, bv, acc);
     }
     for (int r = 0; r < 4; ++r) wb.O[(4 * g + r) * 16 + c] = acc[r] + net.b4[c];

@@ -99,7 +99,7 @@ struct sdm_mlp {
     int32_t n_panes = 0;
     int64_t P = 0;
     int64_t t = 0;   // Adam steps taken
-    DevBuf params, m1, m2, grad, wb, bb, partial, loss_partial, loss;
+    DevBuf params, m1, m2, wb, bb, partial, loss_partial, loss;
 };
 
 struct sdm_scene {

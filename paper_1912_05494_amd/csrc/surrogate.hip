@@ -145,63 +145,75 @@ __global__ void k_zero_f64s(double *a, size_t n)
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = 0.0;
 }
 
-// dW[out][in] += sum_s dZ[s][out] H[s][in] over the 16 samples (k = 16),
-// for out tiles [0, nto) and in tiles [0, nti); atomically into LDS.
-__device__ __forceinline__ void accum_dw(const __bf16 *dZ, int ldz, int nto, const __bf16 *H, int ldh, int nti,
-                                         float *gW, int ldg, int out_max, int in_max)
-{
-    const int l = lane_id(), g = l / 16, c = l % 16;
-    for (int to = 0; to < nto; ++to) {
-        s16x4 a;
-        for (int j = 0; j < 4; ++j) a[j] = bits(dZ[(4 * g + j) * ldz + 16 * to + c]);
-        for (int ti = 0; ti < nti; ++ti) {
-            s16x4 bv;
-            for (int j = 0; j < 4; ++j) bv[j] = bits(H[(4 * g + j) * ldh + 16 * ti + c]);
-            f32x4 acc = {0, 0, 0, 0};
-            acc = mfma16(a, bv, acc);
-            for (int r = 0; r < 4; ++r) {
-                const int o = 16 * to + 4 * g + r, i = 16 * ti + c;
-                if (o < out_max && i < in_max) atomicAdd(gW + o * ldg + i, acc[r]);
-            }
-        }
-    }
-}
-
 // dH[16][nti*16] = dZ[16][K] W[K][nti*16] with K = 16 * kq (W row-major
-// [K][ldw]); then ReLU mask from Hm (> 0) into Zout (BF16); bias sums into gb.
+// [K][ldw]); then the ReLU mask from Hm (> 0) into Zout (BF16), or, with
+// dx_out, the raw products (FP32, 16 columns) for the input gradients.
 __device__ __forceinline__ void back_dense(const __bf16 *dZ, int ldz, int kq, const __bf16 *W, int ldw, int nti,
-                                           const __bf16 *Hm, int ldm, __bf16 *Zout, int ldo, float *gb, float *dx_out)
+                                           const __bf16 *Hm, int ldm, __bf16 *Zout, int ldo, float *dx_out)
 {
     const int l = lane_id(), g = l / 16, c = l % 16;
     for (int ti = 0; ti < nti; ++ti) {
         f32x4 acc = {0, 0, 0, 0};
         for (int kk = 0; kk < kq; ++kk) {
-            s16x4 a, bv;
-            for (int j = 0; j < 4; ++j) {
-                a[j] = bits(dZ[c * ldz + 16 * kk + 4 * g + j]);
-                bv[j] = bits(W[(16 * kk + 4 * g + j) * ldw + 16 * ti + c]);
-            }
+            // dZ[c][16 kk + 4 g .. + 3]: one 8-byte read (row strides are multiples of 8 bytes)
+            const s16x4 a = *reinterpret_cast<const s16x4 *>(dZ + c * ldz + 16 * kk + 4 * g);
+            s16x4 bv;
+            for (int j = 0; j < 4; ++j) bv[j] = bits(W[(16 * kk + 4 * g + j) * ldw + 16 * ti + c]);
             acc = mfma16(a, bv, acc);
         }
-        float colsum = 0.0f;
         for (int r = 0; r < 4; ++r) {
             const int s = 4 * g + r, i = 16 * ti + c;
             if (dx_out) {
                 dx_out[s * 16 + c] = acc[r];
                 continue;
             }
-            const float z = (float)Hm[s * ldm + i] > 0.0f ? acc[r] : 0.0f;
-            Zout[s * ldo + i] = (__bf16)z;
-            colsum += z;
+            Zout[s * ldo + i] = (__bf16)((float)Hm[s * ldm + i] > 0.0f ? acc[r] : 0.0f);
         }
-        if (gb) atomicAdd(gb + 16 * ti + c, colsum);
     }
 }
 
-// Gradient of the mean loss over a batch of m samples (inv_n = 1 / m).  Each
-// wave takes 16-sample tiles through the forward and backward passes; weight,
-// bias and embedding gradients are summed per block in LDS (ds_add) and
-// written as one row of P = 9347 + 8 n_panes values per block.
+// One 16x16 tile of a block's weight gradient dW[out][in] = sum over the
+// block's 64 samples of dZ[s][out] H[s][in]: the samples are the products'
+// K dimension, 16 from each wave's buffers (wave q's at A0 + q * as and
+// B0 + q * bs), chained into the accumulator.
+__device__ __forceinline__ f32x4 dw_tile(f32x4 acc, const __bf16 *A0, int lda, int as, int to, const __bf16 *B0,
+                                        int ldb, int bs, int ti)
+{
+    const int l = lane_id(), g = l / 16, c = l % 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const __bf16 *A = A0 + q * as, *B = B0 + q * bs;
+        s16x4 a, bv;
+        for (int j = 0; j < 4; ++j) {
+            a[j] = bits(A[(4 * g + j) * lda + 16 * to + c]);
+            bv[j] = bits(B[(4 * g + j) * ldb + 16 * ti + c]);
+        }
+        acc = mfma16(a, bv, acc);
+    }
+    return acc;
+}
+
+// The 40 weight-gradient tiles of the network: W4 (3 x 64, one padded row
+// tile), W3 and W2 (16 tiles each), W1 (64 x 12, one padded column tile).
+struct DwTile {
+    int layer, to, ti;
+};
+__device__ __forceinline__ DwTile dw_tile_of(int k)
+{
+    if (k < 4) return {4, 0, k};
+    if (k < 20) return {3, (k - 4) / 4, (k - 4) % 4};
+    if (k < 36) return {2, (k - 20) / 4, (k - 20) % 4};
+    return {1, k - 36, 0};
+}
+
+// Gradient of the mean loss over a batch of m samples (inv_n = 1 / m).  A
+// block takes groups of 64 samples, one 16-sample tile per wave: each wave
+// runs its tile forward and backward and leaves every layer's dZ and input
+// in LDS; the block then forms the weight gradients as matrix-core products
+// over the 64 samples (ten tiles per wave, accumulated in registers over all
+// the block's groups), and bias, embedding and loss sums in a fixed order.
+// Each block writes one row of P = 9347 + 8 n_panes values once, with no
+// atomics, so the gradient does not depend on scheduling.
 __global__ void __launch_bounds__(256) k_mlp_grad(uint32_t m, int n_panes, const float *tup, const int32_t *pane,
                                                   const float *target, const __bf16 *wb, const float *bb,
                                                   const float *E, float inv_n, float *partial, float *loss_partial,
@@ -209,82 +221,133 @@ __global__ void __launch_bounds__(256) k_mlp_grad(uint32_t m, int n_panes, const
 {
     __shared__ NetLds net;
     __shared__ WaveBuf wbuf[4];
-    __shared__ float gacc[kNetParams + 8 * kMaxPanes];
+    __shared__ __bf16 zd1[4][16 * kLd64];   // dZ of layer 1, per wave
+    __shared__ float gO[4][16 * 4];       // d loss / d o of each sample (FP32)
+    __shared__ int32_t spane[64];         // pane of each sample of the group (-1: none)
     __shared__ float lsum[4];
     const int P = kNetParams + 8 * n_panes;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) gacc[i] = 0.0f;
+    const int wv = threadIdx.x >> 6, l = lane_id(), t = threadIdx.x;
+    const uint32_t ngrp = (m + 63) / 64;
+    // this lane's sample of a group (lanes 0-15): pane, inputs and target,
+    // fetched ahead of use (the first group's before the weights are staged)
+    int my_pane = -1;
+    bool have = false;   // the lane has a sample (not padding)
+    float fin[4] = {0, 0, 0, 0}, tg[3] = {0, 0, 0};
+    auto fetch = [&](uint32_t grp) {
+        const uint32_t s = grp * 64 + 16 * wv + l;
+        have = l < 16 && grp < ngrp && s < m;
+        if (have) {
+            my_pane = pane[s];
+            for (int q = 0; q < 4; ++q) fin[q] = tup[4 * s + q];
+            for (int q = 0; q < 3; ++q) tg[q] = target[3 * s + q];
+        }
+    };
+    fetch(blockIdx.x);
     load_net(net, wb, bb);
-    WaveBuf &w = wbuf[threadIdx.x >> 6];
-    const int l = lane_id();
-    float my_loss = 0.0f;
-    const uint32_t ntile = (m + 15) / 16;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t tile = wave; tile < ntile; tile += nw) {
-        const uint32_t s0 = tile * 16;
-        int my_pane = -1;   // -1: padding or an invalid pane index (reported in *bad)
+    WaveBuf &w = wbuf[wv];
+    const int ws = (int)(sizeof(WaveBuf) / sizeof(__bf16));
+    f32x4 acc[10];
+#pragma unroll
+    for (int u = 0; u < 10; ++u) acc[u] = f32x4{0, 0, 0, 0};
+    float bsum = 0.0f, esum0 = 0.0f, esum1 = 0.0f, my_loss = 0.0f;
+    const int pe0 = t, pe1 = t + 256;   // (pane, embedding) pairs of this thread: p = pe / 8, e = pe % 8
+    for (uint32_t grp = blockIdx.x; grp < ngrp; grp += gridDim.x) {
+        // -1: padding or an invalid pane index (reported in *bad)
+        if (!have) my_pane = -1;
+        else if ((unsigned)my_pane >= (unsigned)n_panes) {
+            atomicOr(bad, 1);
+            my_pane = -1;
+        }
         if (l < 16) {
-            const uint32_t s = s0 + l;
-            if (s < m) {
-                my_pane = pane[s];
-                if ((unsigned)my_pane >= (unsigned)n_panes) {
-                    atomicOr(bad, 1);
-                    my_pane = -1;
-                }
-            }
-            if (my_pane >= 0) features(tup[4 * s], tup[4 * s + 1], tup[4 * s + 2], tup[4 * s + 3], E + 8 * my_pane,
-                                       w.X0 + l * 32);
-            else for (int e = 0; e < 32; ++e) w.X0[l * 32 + e] = (__bf16)0.0f;
+            if (my_pane >= 0) features(fin[0], fin[1], fin[2], fin[3], E + 8 * my_pane, w.X0 + l * kLd32);
+            else for (int e = 0; e < 32; ++e) w.X0[l * kLd32 + e] = (__bf16)0.0f;
+            spane[16 * wv + l] = my_pane;
         }
         wave_sync();
         forward_tile(net, w);
         // heads, loss and d loss / d o; padded samples get a zero gradient
         if (l < 16) {
-            const uint32_t s = s0 + l;
             float go0 = 0, go1 = 0, go2 = 0;
             if (my_pane >= 0) {
                 const float o0 = w.O[l * 16], o1 = w.O[l * 16 + 1], o2 = w.O[l * 16 + 2];
                 float R, T, wl;
                 heads(o0, o1, o2, R, T, wl);
-                const float e0 = R - target[3 * s], e1 = T - target[3 * s + 1], e2 = wl - target[3 * s + 2];
+                const float e0 = R - tg[0], e1 = T - tg[1], e2 = wl - tg[2];
                 my_loss += e0 * e0 + e1 * e1 + e2 * e2;
                 const float gR = 2.0f * e0 * inv_n, gT = 2.0f * e1 * inv_n, gw = 2.0f * e2 * inv_n;
                 go0 = gR * R * (1.0f - R) - gT * T * R;
                 go1 = -gR * R * T + gT * T * (1.0f - T);
                 go2 = gw / (1.0f + expf(-o2));
-                atomicAdd(gacc + kOffB4, go0);
-                atomicAdd(gacc + kOffB4 + 1, go1);
-                atomicAdd(gacc + kOffB4 + 2, go2);
             }
-            for (int q = 0; q < 16; ++q) w.dO[l * 16 + q] = (__bf16)(q == 0 ? go0 : q == 1 ? go1 : q == 2 ? go2 : 0.0f);
+            gO[wv][l * 4] = go0;
+            gO[wv][l * 4 + 1] = go1;
+            gO[wv][l * 4 + 2] = go2;
+            for (int q = 0; q < 16; ++q)
+                w.dO[l * kLd16 + q] = (__bf16)(q == 0 ? go0 : q == 1 ? go1 : q == 2 ? go2 : 0.0f);
         }
         wave_sync();
-        // output layer: dW4 (3 x 64) and dZ3 = (dO W4) masked by H3
-        accum_dw(w.dO, 16, 1, w.H3, 64, 4, gacc + kOffW4, 64, 3, 64);
-        back_dense(w.dO, 16, 1, net.W4, 64, 4, w.H3, 64, w.Z0, 64, gacc + kOffB3, nullptr);
+        // dZ3 = (dO W4) masked by H3, dZ2, dZ1, then the inputs' gradients
+        back_dense(w.dO, kLd16, 1, net.W4, kLd64, 4, w.H3, kLd64, w.Z0, kLd64, nullptr);
         wave_sync();
-        // layer 3: dW3 and dZ2
-        accum_dw(w.Z0, 64, 4, w.H2, 64, 4, gacc + kOffW3, 64, 64, 64);
-        back_dense(w.Z0, 64, 4, net.W3, 64, 4, w.H2, 64, w.Z1, 64, gacc + kOffB2, nullptr);
+        back_dense(w.Z0, kLd64, 4, net.W3, kLd64, 4, w.H2, kLd64, w.Z1, kLd64, nullptr);
         wave_sync();
-        // layer 2: dW2 and dZ1
-        accum_dw(w.Z1, 64, 4, w.H1, 64, 4, gacc + kOffW2, 64, 64, 64);
-        back_dense(w.Z1, 64, 4, net.W2, 64, 4, w.H1, 64, w.Z0, 64, gacc + kOffB1, nullptr);
+        back_dense(w.Z1, kLd64, 4, net.W2, kLd64, 4, w.H1, kLd64, zd1[wv], kLd64, nullptr);
         wave_sync();
-        // layer 1: dW1 (64 x 12) and the gradients of the 12 inputs
-        accum_dw(w.Z0, 64, 4, w.X0, 32, 1, gacc + kOffW1, 12, 64, 12);
-        back_dense(w.Z0, 64, 4, net.W1, 32, 1, nullptr, 0, nullptr, 0, nullptr, w.O);
-        wave_sync();
-        if (l < 16) {
-            if (my_pane >= 0)
-                for (int e = 0; e < 8; ++e) atomicAdd(gacc + kOffE + 8 * my_pane + e, w.O[l * 16 + 4 + e]);
+        back_dense(zd1[wv], kLd64, 4, net.W1, kLd32, 1, nullptr, 0, nullptr, 0, w.O);
+        fetch(grp + gridDim.x);   // the next group's samples, while the block finishes this one
+        __syncthreads();
+        // weight gradients over the group's 64 samples: tiles wv, wv + 4, ...
+#pragma unroll
+        for (int u = 0; u < 10; ++u) {
+            const DwTile d = dw_tile_of(wv + 4 * u);
+            if (d.layer == 4) acc[u] = dw_tile(acc[u], wbuf[0].dO, kLd16, ws, d.to, wbuf[0].H3, kLd64, ws, d.ti);
+            else if (d.layer == 3) acc[u] = dw_tile(acc[u], wbuf[0].Z0, kLd64, ws, d.to, wbuf[0].H2, kLd64, ws, d.ti);
+            else if (d.layer == 2) acc[u] = dw_tile(acc[u], wbuf[0].Z1, kLd64, ws, d.to, wbuf[0].H1, kLd64, ws, d.ti);
+            else acc[u] = dw_tile(acc[u], zd1[0], kLd64, 16 * kLd64, d.to, wbuf[0].X0, kLd32, ws, d.ti);
         }
-        wave_sync();
+        // bias sums: threads 0-63 layer 1, 64-127 layer 2, 128-191 layer 3, 192-194 the outputs
+        if (t < 192) {
+            const int col = t & 63;
+            for (int q = 0; q < 4; ++q)
+                for (int r = 0; r < 16; ++r) {
+                    const __bf16 *D = t < 64 ? zd1[q] : (t < 128 ? wbuf[q].Z1 : wbuf[q].Z0);
+                    bsum += (float)D[r * kLd64 + col];
+                }
+        } else if (t < 195) {
+            for (int q = 0; q < 4; ++q)
+                for (int r = 0; r < 16; ++r) bsum += gO[q][r * 4 + (t - 192)];
+        }
+        // embedding rows: the inputs' gradients 4..11 of the samples of each pane
+        if (pe0 < 8 * n_panes)
+            for (int s = 0; s < 64; ++s)
+                if (spane[s] == pe0 / 8) esum0 += wbuf[s / 16].O[(s % 16) * 16 + 4 + pe0 % 8];
+        if (pe1 < 8 * n_panes)
+            for (int s = 0; s < 64; ++s)
+                if (spane[s] == pe1 / 8) esum1 += wbuf[s / 16].O[(s % 16) * 16 + 4 + pe1 % 8];
+        __syncthreads();
     }
+    float *row = partial + (size_t)blockIdx.x * P;
+    const int g = l / 16, c = l % 16;
+#pragma unroll
+    for (int u = 0; u < 10; ++u) {
+        const DwTile d = dw_tile_of(wv + 4 * u);
+        const int off = d.layer == 4 ? kOffW4 : d.layer == 3 ? kOffW3 : d.layer == 2 ? kOffW2 : kOffW1;
+        const int ldd = d.layer == 1 ? 12 : 64, out_max = d.layer == 4 ? 3 : 64, in_max = d.layer == 1 ? 12 : 64;
+        for (int r = 0; r < 4; ++r) {
+            const int o = 16 * d.to + 4 * g + r, i = 16 * d.ti + c;
+            if (o < out_max && i < in_max) row[off + o * ldd + i] = acc[u][r];
+        }
+    }
+    if (t < 64) row[kOffB1 + t] = bsum;
+    else if (t < 128) row[kOffB2 + t - 64] = bsum;
+    else if (t < 192) row[kOffB3 + t - 128] = bsum;
+    else if (t < 195) row[kOffB4 + t - 192] = bsum;
+    if (pe0 < 8 * n_panes) row[kOffE + pe0] = esum0;
+    if (pe1 < 8 * n_panes) row[kOffE + pe1] = esum1;
     for (int off = 32; off > 0; off >>= 1) my_loss += __shfl_xor(my_loss, off);
-    if (l == 0) lsum[threadIdx.x >> 6] = my_loss;
+    if (l == 0) lsum[wv] = my_loss;
     __syncthreads();
-    for (int i = threadIdx.x; i < P; i += blockDim.x) partial[(size_t)blockIdx.x * P + i] = gacc[i];
-    if (threadIdx.x == 0) loss_partial[blockIdx.x] = lsum[0] + lsum[1] + lsum[2] + lsum[3];
+    if (t == 0) loss_partial[blockIdx.x] = (lsum[0] + lsum[1]) + (lsum[2] + lsum[3]);
 }
 
 // Sum of the block rows into the canonical gradient vector (length P), and of
@@ -304,18 +367,84 @@ __global__ void k_mlp_reduce(int nblk, int P, const float *partial, const float 
     }
 }
 
-// Adam step on the FP32 master parameters (bias corrections c1 = 1 - b1^t,
-// c2 = 1 - b2^t).
-__global__ void k_mlp_adam(int P, const float *grad, float *params, float *m1, float *m2, float lr, float b1, float b2,
-                           float eps, float c1, float c2)
+// Where canonical parameter i lives in the kernels' layout: the BF16 weight
+// index (*is_w = true) or the FP32 bias index; -1 for the embedding, which
+// the kernels read from the FP32 parameters.
+__device__ __forceinline__ int packed_index(int i, bool *is_w)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
-        const float gi = grad[i];
-        const float a = b1 * m1[i] + (1.0f - b1) * gi;
-        const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    *is_w = true;
+    if (i < kOffB1) return (i / 12) * 32 + i % 12;
+    if (i < kOffW2) { *is_w = false; return i - kOffB1; }
+    if (i < kOffB2) return 2048 + (i - kOffW2);
+    if (i < kOffW3) { *is_w = false; return 64 + (i - kOffB2); }
+    if (i < kOffB3) return 6144 + (i - kOffW3);
+    if (i < kOffW4) { *is_w = false; return 128 + (i - kOffB3); }
+    if (i < kOffB4) return 10240 + i - kOffW4;   // W4 rows 0..2 of the 16-row padded block
+    if (i < kOffE) { *is_w = false; return 192 + (i - kOffB4); }
+    return -1;
+}
+
+// One training step after the gradient pass: the block rows summed in a fixed
+// order (eight interleaved partial sums per parameter, combined pairwise),
+// the Adam step on the FP32 master parameters (bias corrections c1 = 1 - b1^t,
+// c2 = 1 - b2^t), and the new parameters' BF16 / FP32 copies that the next
+// gradient pass reads.  Block 0 also writes the mean loss.
+constexpr int kRaPar = 32;   // parameters per block, 8 threads each
+__global__ void __launch_bounds__(256) k_mlp_reduce_adam(int nblk, int P, const float *partial,
+                                                         const float *loss_partial, float inv_n, float *loss,
+                                                         float *params, float *m1, float *m2, float lr, float b1,
+                                                         float b2, float eps, float c1, float c2, __bf16 *wb,
+                                                         float *bb)
+{
+    __shared__ float s[8][kRaPar];
+    const int c = threadIdx.x % kRaPar, q = threadIdx.x / kRaPar;
+    const int i = blockIdx.x * kRaPar + c;
+    float sum = 0.0f;
+    if (i < P) {
+        // rows q, q + 8, q + 16, ... in order; eight loads in flight per round
+        const float *col = partial + i;
+        int b = q;
+        for (; b + 56 < nblk; b += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(b + 8 * u) * P];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sum += v[u];
+        }
+        for (; b < nblk; b += 8) sum += col[(size_t)b * P];
+    }
+    // the state the update needs, loaded while the sums complete
+    float m1i = 0.0f, m2i = 0.0f, pi = 0.0f;
+    if (q == 0 && i < P) {
+        m1i = m1[i];
+        m2i = m2[i];
+        pi = params[i];
+    }
+    s[q][c] = sum;
+    __syncthreads();
+    if (q == 0 && i < P) {
+        const float gi = ((s[0][c] + s[1][c]) + (s[2][c] + s[3][c])) + ((s[4][c] + s[5][c]) + (s[6][c] + s[7][c]));
+        const float a = b1 * m1i + (1.0f - b1) * gi;
+        const float v = b2 * m2i + (1.0f - b2) * gi * gi;
         m1[i] = a;
         m2[i] = v;
-        params[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+        const float p = pi - lr * (a / c1) / (sqrtf(v / c2) + eps);
+        params[i] = p;
+        bool is_w;
+        const int k = packed_index(i, &is_w);
+        if (k >= 0) {
+            if (is_w) wb[k] = (__bf16)p;
+            else bb[k] = p;
+        }
+    }
+    if (loss && blockIdx.x == 0 && threadIdx.x >= 64 && threadIdx.x < 128) {
+        // the block losses over one wave: lane l sums l, l + 64, ...; then a
+        // fixed butterfly
+        const int ln = threadIdx.x - 64;
+        float t = 0.0f;
+        for (int b = ln; b < nblk; b += 64) t += loss_partial[b];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        if (ln == 0) *loss = t * inv_n;
     }
 }
 
@@ -370,8 +499,8 @@ __global__ void __launch_bounds__(256) k_mlp_infer(uint32_t m, int n_panes, cons
                 }
             }
             if (my_pane >= 0) features(tup[4 * s], tup[4 * s + 1], tup[4 * s + 2], tup[4 * s + 3], E + 8 * my_pane,
-                                       w.X0 + l * 32);
-            else for (int e = 0; e < 32; ++e) w.X0[l * 32 + e] = (__bf16)0.0f;
+                                       w.X0 + l * kLd32);
+            else for (int e = 0; e < 32; ++e) w.X0[l * kLd32 + e] = (__bf16)0.0f;
         }
         wave_sync();
         forward_tile(net, w);
@@ -479,10 +608,12 @@ void launch_mlp_reduce(int nblk, int P, const float *partial, const float *loss_
     hipLaunchKernelGGL(k_mlp_reduce, dim3(40), dim3(256), 0, s, nblk, P, partial, loss_partial, inv_n, grad, loss);
 }
 
-void launch_mlp_adam(int P, const float *grad, float *params, float *m1, float *m2, float lr, float b1, float b2,
-                     float eps, float c1, float c2, hipStream_t s)
+void launch_mlp_reduce_adam(int nblk, int P, const float *partial, const float *loss_partial, float inv_n, float *loss,
+                            float *params, float *m1, float *m2, float lr, float b1, float b2, float eps, float c1,
+                            float c2, void *wb, float *bb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_adam, dim3(40), dim3(256), 0, s, P, grad, params, m1, m2, lr, b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((P + kRaPar - 1) / kRaPar), dim3(256), 0, s, nblk, P, partial,
+                       loss_partial, inv_n, loss, params, m1, m2, lr, b1, b2, eps, c1, c2, (__bf16 *)wb, bb);
 }
 
 void launch_mlp_infer(uint32_t m, int n_panes, const float *tup, const int32_t *pane, const void *wb, const float *bb,

@@ -30,8 +30,11 @@ void launch_mlp_grad(uint32_t m, int n_panes, const float *tup, const int32_t *p
                      int *bad, int nblk, hipStream_t s);
 void launch_mlp_reduce(int nblk, int P, const float *partial, const float *loss_partial, float inv_n, float *grad,
                        float *loss, hipStream_t s);
-void launch_mlp_adam(int P, const float *grad, float *params, float *m1, float *m2, float lr, float b1, float b2,
-                     float eps, float c1, float c2, hipStream_t s);
+// Sum of the gradient pass's block rows, Adam step and the new parameters'
+// kernel copies (wb, bb) in one launch; loss receives the mean loss.
+void launch_mlp_reduce_adam(int nblk, int P, const float *partial, const float *loss_partial, float inv_n, float *loss,
+                            float *params, float *m1, float *m2, float lr, float b1, float b2, float eps, float c1,
+                            float c2, void *wb, float *bb, hipStream_t s);
 void launch_mlp_infer(uint32_t m, int n_panes, const float *tup, const int32_t *pane, const void *wb, const float *bb,
                       const float *E, float *out, int *bad, int num_cu, hipStream_t s);
 void launch_zero_i32(int *p, int n, hipStream_t s);

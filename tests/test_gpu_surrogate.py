@@ -269,6 +269,27 @@ def test_mlp_gradient_matches_oracle(gpu, orc):
         net.close()
 
 
+def test_mlp_training_is_reproducible(gpu):
+    """The gradient pass writes each block's sums without atomics and the
+    step sums the blocks in a fixed order: two trainings from the same state
+    give the same parameters bit for bit, at a batch with one 64-sample group
+    per block and at one with several groups per block and a ragged tail."""
+    sdm, ctx, torch = gpu
+    n_panes = 7
+    p, tup, pane, target = net_case(21, 1 << 16, n_panes)
+    t, pn, tg = to_dev(torch, tup, pane, target)
+    for batch in (8192, 40000 + 37):
+        runs = []
+        for _ in range(2):
+            net = sdm.MLP(ctx, n_panes, p)
+            curve = net.train(t, pn, tg, steps=12, batch=batch, lr=2e-3)
+            runs.append((net.params(), curve))
+            net.close()
+        assert np.array_equal(runs[0][0], runs[1][0]), batch
+        assert np.array_equal(runs[0][1], runs[1][1]), batch
+        assert not np.array_equal(runs[0][0], p)
+
+
 def test_mlp_adam_first_step(gpu, orc):
     """With zero moments, Adam's first step is lr * g / (|g| + eps): each
     parameter with a clear gradient moves by lr against the gradient's sign."""

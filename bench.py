@@ -699,8 +699,10 @@ def train_bench(args):
 
 def batch_bench(args):
     """The uneven 32-job batch (square sides 128-1024, 10k-200k triangles,
-    8-81 wavelengths, 16-128 spp; scene seed 2 + job) as one wavefront,
-    against the same jobs rendered one after the other."""
+    8-81 wavelengths, 16-128 spp; scene seed 2 + job) through the batch
+    scheduler (jobs that fill the device alone, the others in shared
+    wavefronts), against the same jobs rendered one after the other; then
+    the same for 64 small jobs (sides 32-256)."""
     import torch
     from paper_1912_05494_amd import sdm, synth
 
@@ -726,6 +728,25 @@ def batch_bench(args):
         sdm.render(ctx, g, st, graph=True)
     torch.cuda.synchronize()
     dt_seq = time.perf_counter() - t0
+    # a batch of small jobs (sides 32-256, 2k-12.5k triangles), most of which
+    # share wavefronts
+    small = synth.batch_jobs(n_jobs=64, seed=3, scale=0.25)
+    sscenes = [sdm.Scene(ctx, sc) for sc, _ in small]
+    sbatch = [(g, st) for g, (_, st) in zip(sscenes, small)]
+    ssamples = sum(st.camera.W * st.camera.H * st.spp * len(st.lambda_nm) for _, st in small)
+    sdm.render_batch(ctx, sbatch, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sdm.render_batch(ctx, sbatch, graph=True)
+    torch.cuda.synchronize()
+    dts = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for g, st in sbatch:
+        sdm.render(ctx, g, st, graph=True)
+    torch.cuda.synchronize()
+    dts_seq = time.perf_counter() - t0
+    print(f"small-job batch: {dts * 1e3:.1f} ms, one by one {dts_seq * 1e3:.1f} ms", file=sys.stderr, flush=True)
     out = {
         "metric": "spectral ray samples/sec (32-job batch)",
         "value": samples / dt,
@@ -739,6 +760,10 @@ def batch_bench(args):
                    "spectral_samples_per_step": samples},
         "sequential_single_renders": {"value": samples / dt_seq, "ms": dt_seq * 1e3},
         "batch_speedup_over_sequential": dt_seq / dt,
+        "small_jobs": {"jobs": len(small), "spectral_samples": ssamples, "value": ssamples / dts, "ms": dts * 1e3,
+                       "sequential_ms": dts_seq * 1e3, "speedup_over_sequential": dts_seq / dts,
+                       "workload": "64 procedural naves, square sides 32-256, 2k-12.5k triangles, 8-81 "
+                                   "wavelengths, 16-128 spp, depth 8"},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

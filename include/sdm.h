@@ -317,15 +317,18 @@ typedef struct {
     const sdm_outputs *out;
 } sdm_job;
 
-/* Renders n_jobs images in one wavefront: the (job x band x tile) work items
- * of every job share one path pool and one kernel sequence per chunk, with a
- * job table giving each path its scene, camera, spectra and accumulator
- * (Sec. 4: dynamic balancing of sub-domains).  Each image equals what
- * sdm_render gives for its job alone.  All jobs must use the same precision,
- * and the jobs that need a network must share one.  Chunking, graph replay
- * and the pool headroom follow jobs[0].params.  The per-job outputs are as
- * for sdm_render; job statistics are not filled; stats (host, may be NULL)
- * receives the totals.  Synchronises the stream. */
+/* Renders n_jobs images.  A job of at least half a chunk of paths (W x H x
+ * spp x bands; the chunk of jobs[0].params, by default 2^23) fills the
+ * device and renders alone; smaller jobs, in their order, are grouped into
+ * wavefronts of up to one chunk: the (job x band x tile) work items of a
+ * group share one path pool and one kernel sequence per chunk, with a job
+ * table giving each path its scene, camera, spectra and accumulator (Sec. 4:
+ * dynamic balancing of sub-domains).  Each image equals what sdm_render
+ * gives for its job alone.  All jobs must use the same precision, and the
+ * jobs of a group that need a network must share one.  A group's chunking,
+ * graph replay and pool headroom follow its first job's parameters.  The
+ * per-job outputs are as for sdm_render; job statistics are not filled;
+ * stats (host, may be NULL) receives the totals.  Synchronises the stream. */
 int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_stats *stats,
                      void *hip_stream);
 

@@ -890,6 +890,34 @@ uint64_t render_digest(const sdm_scene *sc, const sdm_render_params *p)
     return dg.h;
 }
 
+// Adds the counts and times of one render to a total (batch statistics).
+void add_stats(sdm_stats &t, const sdm_stats &a)
+{
+    t.spectral_samples += a.spectral_samples;
+    t.paths += a.paths;
+    t.closest_segments += a.closest_segments;
+    t.shadow_segments += a.shadow_segments;
+    t.forks += a.forks;
+    t.chunks += a.chunks;
+    for (int q = 0; q < 2; ++q) {
+        t.nodes_visited[q] += a.nodes_visited[q];
+        t.tris_tested[q] += a.tris_tested[q];
+        t.glass_vertices[q] += a.glass_vertices[q];
+    }
+    t.bubbly_vertices += a.bubbly_vertices;
+    t.spectral_paths += a.spectral_paths;
+    t.spectral_records += a.spectral_records;
+    t.ms_render += a.ms_render;
+    for (int k = 0; k < SDM_K_COUNT; ++k) {
+        t.kernel_ms[k] += a.kernel_ms[k];
+        t.kernel_launches[k] += a.kernel_launches[k];
+    }
+    t.items_done += a.items_done;
+    t.items_total += a.items_total;
+    t.interface_rays += a.interface_rays;
+    t.photons_stored += a.photons_stored;
+}
+
 int render_any(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *stats, hipStream_t s,
                const Budget &bud = Budget())
 {
@@ -1014,7 +1042,42 @@ int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_
             return fail(ctx, SDM_E_UNSUPPORTED, "the photon map applies to single renders");
     }
     ctx->partial.valid = false;
-    return render_any(ctx, js, stats, (hipStream_t)hip_stream);
+    // Scheduling: a job of at least half a chunk of paths fills the device on
+    // its own and renders alone, through the one-job kernels (scene constants
+    // uniform across the wave); smaller jobs, in their order, share
+    // wavefronts of up to one chunk of paths, whose job table gives each path
+    // its scene.  Every image is the same either way.
+    const hipStream_t s = (hipStream_t)hip_stream;
+    uint64_t chunk;
+    int tw, th;
+    job_shape(ctx, js[0], chunk, tw, th);
+    sdm_stats total{};
+    std::vector<JobIn> group;
+    uint64_t gpaths = 0;
+    auto run = [&](const std::vector<JobIn> &g) -> int {
+        sdm_stats st{};
+        if (int rc = render_any(ctx, g, &st, s)) return rc;
+        add_stats(total, st);
+        return SDM_OK;
+    };
+    for (const JobIn &j : js) {
+        const uint64_t paths = (uint64_t)j.p->camera.W * j.p->camera.H * j.p->spp * j.p->n_bands;
+        if (paths >= chunk / 2) {
+            if (int rc = run({j})) return rc;
+            continue;
+        }
+        if (!group.empty() && gpaths + paths > chunk) {
+            if (int rc = run(group)) return rc;
+            group.clear();
+            gpaths = 0;
+        }
+        group.push_back(j);
+        gpaths += paths;
+    }
+    if (!group.empty())
+        if (int rc = run(group)) return rc;
+    if (stats) *stats = total;
+    return SDM_OK;
 }
 
 int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params *p, const char *cache_path,

@@ -45,16 +45,24 @@ def close(a, b, rtol=1e-9):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_batch_equals_single_renders(gpu, precision):
+    """Chunks of 2^15 paths: every job but the tiny one renders alone, over
+    several chunks; chunks of 2^18: the three smallest jobs share one
+    wavefront (jobs of half a chunk or more render alone)."""
     sdm, ctx, torch = gpu
     jobs = small_batch()
+    paths = [st.camera.W * st.camera.H * st.spp * st.n_bands for _, st in jobs]
+    assert sum(p < 1 << 17 for p in paths) >= 3 and sum(p >= 1 << 17 for p in paths) >= 1, paths
     scenes = [sdm.Scene(ctx, sc) for sc, _ in jobs]
-    images, stats = sdm.render_batch(ctx, [(g, st) for g, (_, st) in zip(scenes, jobs)], precision=precision,
-                                     chunk_paths=1 << 15)
-    assert stats["chunks"] > 1
-    for g, (sc, st), (spec, xyz) in zip(scenes, jobs, images):
-        s1, x1, _ = sdm.render(ctx, g, st, precision=precision, chunk_paths=1 << 15)
-        assert close(np64(spec), np64(s1)), st.camera.W
-        assert close(np64(xyz), np64(x1))
+    for chunk in (1 << 15, 1 << 18):
+        images, stats = sdm.render_batch(ctx, [(g, st) for g, (_, st) in zip(scenes, jobs)], precision=precision,
+                                         chunk_paths=chunk)
+        assert stats["paths"] == sum(paths)
+        if chunk == 1 << 15:
+            assert stats["chunks"] > len(jobs)
+        for g, (sc, st), (spec, xyz) in zip(scenes, jobs, images):
+            s1, x1, _ = sdm.render(ctx, g, st, precision=precision, chunk_paths=1 << 15)
+            assert close(np64(spec), np64(s1)), (chunk, st.camera.W)
+            assert close(np64(xyz), np64(x1))
 
 
 def test_batch_matches_oracle_sampled(gpu, orc):

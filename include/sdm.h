@@ -209,6 +209,12 @@ typedef struct {
      * renders only; not with max_items. */
     int64_t photons;
     float photon_radius;
+    /* Resident blocks per compute unit of the persistent closest-hit and
+     * shadow-walk passes: 0 takes the library's choice (what sdm_autotune
+     * chose for this render shape, else the most that fit, four for
+     * sun-grid walks); n > 0 is capped at the most that fit.  The image
+     * does not depend on it. */
+    int32_t trace_blocks_per_cu, shadow_blocks_per_cu;
 } sdm_render_params;
 
 /* Kernel classes reported in sdm_stats. */
@@ -334,17 +340,20 @@ int sdm_render_batch(sdm_context *ctx, int32_t n_jobs, const sdm_job *jobs, sdm_
 
 /* Tuning of the wavefront for a scene and parameters: renders twice with
  * each candidate chunk size (2^22, 2^23, 2^24 paths) and pixel tile (8x8,
- * 16x16, 32x32), keeps the fastest, and uses it in later
- * renders of this context with the same scene, image size, wavelength
- * count, depth and precision whose chunk_paths, tile_w and tile_h are 0.
+ * 16x16, 32x32), keeps the fastest, then with those the resident blocks
+ * per CU of the closest-hit pass and then of the shadow walk (from the most
+ * that fit down to half of it), and uses the choice in later renders of
+ * this context with the same scene, image size, wavelength count, depth
+ * and precision whose chunk_paths, tile_w, tile_h and blocks per CU are 0.
  * cache_path (may be NULL): a text file of earlier results; a matching entry
  * is taken without measuring, a new result is appended.  The image does not
  * depend on the choice. */
 typedef struct {
     int64_t chunk_paths;
     int32_t tile_w, tile_h;
-    double ms;                  /* measured time of the reduced render         */
+    double ms;                  /* measured time of the chosen render          */
     int32_t from_cache;         /* 1: taken from cache_path                    */
+    int32_t trace_blocks_per_cu, shadow_blocks_per_cu;
 } sdm_tune_result;
 
 int sdm_autotune(sdm_context *ctx, const sdm_scene *scene, const sdm_render_params *params,

@@ -182,20 +182,26 @@ struct JobIn {
 };
 
 // Tuned (chunk, tile) of the context for a job, or the library defaults.
-void job_shape(const sdm_context *ctx, const JobIn &j, uint64_t &chunk, int &tw, int &th)
+void job_shape(const sdm_context *ctx, const JobIn &j, uint64_t &chunk, int &tw, int &th, int *trace_bpc = nullptr,
+               int *shadow_bpc = nullptr)
 {
     const sdm_render_params *p = j.p;
     chunk = p->chunk_paths > 0 ? (uint64_t)p->chunk_paths : 0;
     tw = p->tile_w;
     th = p->tile_h;
-    if (chunk == 0 && tw <= 0 && th <= 0)
+    int tb = p->trace_blocks_per_cu, sb = p->shadow_blocks_per_cu;
+    if (chunk == 0 && tw <= 0 && th <= 0 && tb <= 0 && sb <= 0)
         for (const auto &t : ctx->tuned)
             if (t.scene == j.sc && t.W == p->camera.W && t.H == p->camera.H && t.nl == p->n_lambda &&
                 t.depth == p->max_depth && t.precision == p->precision) {
                 chunk = (uint64_t)t.chunk;
                 tw = t.tw;
                 th = t.th;
+                tb = t.trace_bpc;
+                sb = t.shadow_bpc;
             }
+    if (trace_bpc) *trace_bpc = std::max(tb, 0);
+    if (shadow_bpc) *shadow_bpc = std::max(sb, 0);
     if (chunk == 0) chunk = (uint64_t)1 << 23;
     if (tw <= 0) tw = 16;
     if (th <= 0) th = 16;
@@ -409,10 +415,11 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
     int depth = 0;
     std::vector<int64_t> acc_off(nj + 1, 0);
     int tw0 = 0, th0 = 0;
+    int trace_bpc = 0, shadow_bpc = 0;   // resident blocks per CU of the traversal passes (0: default)
     for (int j = 0; j < nj; ++j) {
         uint64_t ch;
-        int tw, th;
-        job_shape(ctx, jobs[j], ch, tw, th);
+        int tw, th, tb, sb;
+        job_shape(ctx, jobs[j], ch, tw, th, &tb, &sb);
         if (bud.resume) {   // the partial render's items
             tw = ctx->partial.tw;
             th = ctx->partial.th;
@@ -421,6 +428,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             chunk = ch;
             tw0 = tw;
             th0 = th;
+            trace_bpc = tb;
+            shadow_bpc = sb;
         }
         if (int rc = plan_work(ctx, jobs[j].p, j, tw, th, plan)) return rc;
         depth = std::max(depth, jobs[j].p->max_depth);
@@ -586,7 +595,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         if (!bud.resume) HIPCHK(ctx, ctx->acc.ensure((size_t)acc_off[nj] * sizeof(double)));
         HIPCHK(ctx, ctx->counters.ensure(sizeof(Counters)));
         ChunkArgs<R> a{};
-        a.grid_t = ctx->num_cu * occupancy<R>(SDM_K_TRACE);
+        const int occ_t = occupancy<R>(SDM_K_TRACE), occ_s = occupancy<R>(SDM_K_SHADOW);
+        a.grid_t = ctx->num_cu * (trace_bpc > 0 ? std::min(trace_bpc, occ_t) : occ_t);
         a.grid_s = ctx->num_cu * occupancy<R>(SDM_K_SHADE);
         a.grid_gl = ctx->num_cu * occupancy<R>(SDM_K_SHADE_GLASS);
         a.grid_e = ctx->num_cu * occupancy<R>(SDM_K_BUBBLY_EVAL);
@@ -596,7 +606,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         // keep the pass faster (measured on the nave: 5.33 -> 4.93 ms)
         bool grid_walk = false;
         for (const auto &jj : jobs) grid_walk = grid_walk || jj.sc->dev.g_use != 0;
-        a.grid_st = ctx->num_cu * (grid_walk ? std::min(4, occupancy<R>(SDM_K_SHADOW)) : occupancy<R>(SDM_K_SHADOW));
+        a.grid_st = ctx->num_cu * (shadow_bpc > 0 ? std::min(shadow_bpc, occ_s) : grid_walk ? std::min(4, occ_s) : occ_s);
         a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM);
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
         const size_t gthreads = std::max((size_t)a.grid_t * trace_block_size(), (size_t)a.grid_st * block_size());
@@ -1099,14 +1109,17 @@ int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params 
             char line[256];
             while (std::fgets(line, sizeof(line), f)) {
                 long long ch;
-                int tw, th;
+                int tw, th, tb, sb;
                 double ms;
                 const size_t kl = std::strlen(key);
                 if (std::strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
-                    std::sscanf(line + kl, " -> chunk=%lld tile=%dx%d ms=%lf", &ch, &tw, &th, &ms) == 4) {
+                    std::sscanf(line + kl, " -> chunk=%lld tile=%dx%d trace_bpc=%d shadow_bpc=%d ms=%lf", &ch, &tw,
+                                &th, &tb, &sb, &ms) == 6) {
                     res->chunk_paths = ch;
                     res->tile_w = tw;
                     res->tile_h = th;
+                    res->trace_blocks_per_cu = tb;
+                    res->shadow_blocks_per_cu = sb;
                     res->ms = ms;
                     res->from_cache = 1;
                     found = true;
@@ -1118,6 +1131,7 @@ int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params 
     if (!found) {
         // measure the render itself (a chunk size only matters relative to the
         // whole workload); outputs are not needed
+        HIPCHK(ctx, hipSetDevice(ctx->device));
         sdm_render_params q = *p;
         q.timing = 0;
         q.graph = 0;
@@ -1126,30 +1140,70 @@ int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params 
         sdm_outputs none{};
         sdm_stats st{};
         none.stats = &st;
+        auto time_it = [&](double &ms) -> int {
+            ms = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                const JobIn j{sc, &q, &none};
+                if (int rc = render_any(ctx, {j}, &st, (hipStream_t)hip_stream)) return rc;
+                ms = std::min(ms, st.ms_render);
+            }
+            return SDM_OK;
+        };
+        // 1. chunk size and tile at the default blocks per CU
         const long long chunks[3] = {1ll << 22, 1ll << 23, 1ll << 24};
         const int tiles[3] = {8, 16, 32};
         double best = 1e300;
+        const bool fp64 = p->precision == SDM_PREC_FP64;
+        const int occ_t = fp64 ? occupancy<double>(SDM_K_TRACE) : occupancy<float>(SDM_K_TRACE);
+        const int occ_s = fp64 ? occupancy<double>(SDM_K_SHADOW) : occupancy<float>(SDM_K_SHADOW);
+        const int def_s = sc->dev.g_use ? std::min(4, occ_s) : occ_s;
+        q.trace_blocks_per_cu = occ_t;
+        q.shadow_blocks_per_cu = def_s;
         for (long long ch : chunks)
             for (int t : tiles) {
                 q.chunk_paths = ch;
                 q.tile_w = q.tile_h = t;
-                double ms = 1e300;
-                for (int rep = 0; rep < 2; ++rep) {
-                    const JobIn j{sc, &q, &none};
-                    if (int rc = render_any(ctx, {j}, &st, (hipStream_t)hip_stream)) return rc;
-                    ms = std::min(ms, st.ms_render);
-                }
+                double ms;
+                if (int rc = time_it(ms)) return rc;
                 if (ms < best) {
                     best = ms;
                     res->chunk_paths = ch;
                     res->tile_w = res->tile_h = t;
-                    res->ms = ms;
                 }
             }
+        q.chunk_paths = res->chunk_paths;
+        q.tile_w = res->tile_w;
+        q.tile_h = res->tile_h;
+        // 2. resident blocks per CU of the closest-hit pass, then of the shadow
+        // walk, from the most that fit down to half
+        res->trace_blocks_per_cu = occ_t;
+        for (int b = occ_t - 1; b >= std::max(1, (occ_t + 1) / 2); --b) {
+            q.trace_blocks_per_cu = b;
+            double ms;
+            if (int rc = time_it(ms)) return rc;
+            if (ms < best) {
+                best = ms;
+                res->trace_blocks_per_cu = b;
+            }
+        }
+        q.trace_blocks_per_cu = res->trace_blocks_per_cu;
+        res->shadow_blocks_per_cu = def_s;
+        for (int b = occ_s; b >= std::max(1, (occ_s + 1) / 2); --b) {
+            if (b == def_s) continue;
+            q.shadow_blocks_per_cu = b;
+            double ms;
+            if (int rc = time_it(ms)) return rc;
+            if (ms < best) {
+                best = ms;
+                res->shadow_blocks_per_cu = b;
+            }
+        }
+        res->ms = best;
         if (cache_path)
             if (FILE *f = std::fopen(cache_path, "a")) {
-                std::fprintf(f, "%s -> chunk=%lld tile=%dx%d ms=%.4f\n", key, (long long)res->chunk_paths,
-                             res->tile_w, res->tile_h, res->ms);
+                std::fprintf(f, "%s -> chunk=%lld tile=%dx%d trace_bpc=%d shadow_bpc=%d ms=%.4f\n", key,
+                             (long long)res->chunk_paths, res->tile_w, res->tile_h, res->trace_blocks_per_cu,
+                             res->shadow_blocks_per_cu, res->ms);
                 std::fclose(f);
             }
     }
@@ -1160,7 +1214,8 @@ int sdm_autotune(sdm_context *ctx, const sdm_scene *sc, const sdm_render_params 
                                        t.depth == p->max_depth && t.precision == p->precision;
                             }),
              tv.end());
-    tv.push_back({sc, W, H, p->n_lambda, p->max_depth, p->precision, res->chunk_paths, res->tile_w, res->tile_h});
+    tv.push_back({sc, W, H, p->n_lambda, p->max_depth, p->precision, res->chunk_paths, res->tile_w, res->tile_h,
+                  res->trace_blocks_per_cu, res->shadow_blocks_per_cu});
     return SDM_OK;
 }
 

@@ -84,12 +84,13 @@ struct sdm_context {
     } partial;
     DevBuf acc_base;                  // the accumulator a resumed render starts from
     DevBuf ph_rec, ph_sorted, ph_start, ph_cursor, ph_part, ph_occ;   // caustic photon map
-    // autotuned (chunk, tile) per scene and render shape
+    // autotuned (chunk, tile, traversal blocks per CU) per scene and render shape
     struct Tuned {
         const sdm_scene *scene;
         int32_t W, H, nl, depth, precision;
         int64_t chunk;
         int32_t tw, th;
+        int32_t trace_bpc, shadow_bpc;
     };
     std::vector<Tuned> tuned;
 };

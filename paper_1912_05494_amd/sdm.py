@@ -62,7 +62,8 @@ class RenderParams(C.Structure):
                 ("chunk_paths", C.c_int64), ("timing", C.c_int32), ("btdf_mode", C.c_int32),
                 ("err_dims", C.c_int32 * 3), ("mlp", C.c_void_p), ("err_table", _FP),
                 ("err_bound", C.c_float), ("graph", C.c_int32), ("max_items", C.c_int64),
-                ("photons", C.c_int64), ("photon_radius", C.c_float)]
+                ("photons", C.c_int64), ("photon_radius", C.c_float),
+                ("trace_blocks_per_cu", C.c_int32), ("shadow_blocks_per_cu", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -104,7 +105,7 @@ class Job(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("chunk_paths", C.c_int64), ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("ms", C.c_double),
-                ("from_cache", C.c_int32)]
+                ("from_cache", C.c_int32), ("trace_blocks_per_cu", C.c_int32), ("shadow_blocks_per_cu", C.c_int32)]
 
 
 class TrainParams(C.Structure):
@@ -294,7 +295,8 @@ class Scene:
 
 
 def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision="fp32",
-                chunk_paths=0, timing=False, btdf=None, graph=False, max_items=0, photons=0, photon_radius=0.05):
+                chunk_paths=0, timing=False, btdf=None, graph=False, max_items=0, photons=0, photon_radius=0.05,
+                blocks_per_cu=(0, 0)):
     """btdf: None (exact walks on bubbly panes) or a dict with mode ("exact",
     "surrogate", "fallback"), mlp (an MLP) and, for "fallback", err_table
     (array (n_panes, n_cos, n_d, n_rho)) and bound."""
@@ -321,6 +323,7 @@ def make_params(settings, n_bands=None, band_edges=None, tile=(0, 0), precision=
     p.max_items = int(max_items)
     p.photons = int(photons)
     p.photon_radius = float(photon_radius)
+    p.trace_blocks_per_cu, p.shadow_blocks_per_cu = int(blocks_per_cu[0]), int(blocks_per_cu[1])
     if btdf is not None:
         p.btdf_mode = BTDF_MODES[btdf.get("mode", "exact")]
         if btdf.get("mlp") is not None:
@@ -581,4 +584,5 @@ def autotune(ctx: Context, scene: Scene, settings, precision="fp32", cache_path=
                                  None if cache_path is None else str(cache_path).encode(), C.byref(r),
                                  _stream(stream)), "sdm_autotune")
     return {"chunk_paths": int(r.chunk_paths), "tile": (int(r.tile_w), int(r.tile_h)), "ms": r.ms,
-            "from_cache": bool(r.from_cache)}
+            "from_cache": bool(r.from_cache), "trace_blocks_per_cu": int(r.trace_blocks_per_cu),
+            "shadow_blocks_per_cu": int(r.shadow_blocks_per_cu)}

@@ -87,9 +87,11 @@ int main(void) {
   P(sdm_render_params, err_table); P(sdm_render_params, err_bound);
   P(sdm_stats, bubbly_vertices); P(sdm_stats, kernel_ms); P(sdm_stats, spectral_records); P(sdm_stats, glass_vertices);
   P(sdm_render_params, graph);
+  P(sdm_render_params, trace_blocks_per_cu); P(sdm_render_params, shadow_blocks_per_cu);
   printf("sdm_job %zu\n", sizeof(sdm_job));
   printf("sdm_tune_result %zu\n", sizeof(sdm_tune_result));
   P(sdm_tune_result, ms); P(sdm_tune_result, from_cache);
+  P(sdm_tune_result, trace_blocks_per_cu); P(sdm_tune_result, shadow_blocks_per_cu);
   P(sdm_stats, ms_render); P(sdm_stats, kernel_launches);
   P(sdm_outputs, stats);
   return 0;

@@ -130,11 +130,60 @@ def test_autotune_choice_and_cache(gpu, tmp_path):
     cache = tmp_path / "tune.txt"
     r = sdm.autotune(ctx, g, st, precision="fp64", cache_path=cache)
     assert r["chunk_paths"] in (1 << 22, 1 << 23, 1 << 24) and r["tile"][0] in (8, 16, 32)
+    assert r["trace_blocks_per_cu"] >= 1 and r["shadow_blocks_per_cu"] >= 1
     assert not r["from_cache"] and r["ms"] > 0
     r2 = sdm.autotune(ctx, g, st, precision="fp64", cache_path=cache)
-    assert r2["from_cache"] and r2["chunk_paths"] == r["chunk_paths"] and r2["tile"] == r["tile"]
+    assert r2["from_cache"] and all(r2[k] == r[k] for k in ("chunk_paths", "tile", "trace_blocks_per_cu",
+                                                             "shadow_blocks_per_cu"))
     tuned, _, _ = sdm.render(ctx, g, st, precision="fp64")
     assert close(np64(tuned), np64(base))
+
+
+def test_blocks_per_cu_leave_the_image(gpu):
+    """Resident blocks per CU of the traversal passes (the tuner's second
+    stage) change the schedule, not the paths: FP64 images agree to the
+    accumulation order, with the sun grid and with BVH shadow walks."""
+    sdm, ctx, torch = gpu
+    sc = synth.nave_scene(seed=5, target_tris=6000)
+    st = synth.nave_settings(W=96, H=64, spp=8, max_depth=5, n_lambda=12)
+    for walk in ("auto", "bvh"):
+        g = sdm.Scene(ctx, sc, shadow_walk=walk)
+        base, _, _ = sdm.render(ctx, g, st, precision="fp64")
+        for bpc in ((1, 1), (2, 3), (64, 64)):
+            p, keep = sdm.make_params(st, precision="fp64", blocks_per_cu=bpc)
+            spec = torch.empty_like(base)
+            xyz = torch.empty((st.camera.H, st.camera.W, 3), dtype=torch.float64, device="cuda")
+            sdm.render_into(ctx, g, p, spec, xyz)
+            assert close(np64(spec), np64(base)), (walk, bpc)
+        g.close()
+
+
+def test_autotune_on_the_benchmark_nave(gpu):
+    """On the 512 x 512 nave (64 spp, 81 wavelengths) the chunk choice
+    matters: the tuner's pick renders no slower than the default (within the
+    run-to-run spread of 3 %)."""
+    import time
+    sdm, ctx, torch = gpu
+    sc = synth.nave_scene(seed=1)
+    st = synth.nave_settings()
+    g = sdm.Scene(ctx, sc)
+
+    def best_ms(params):
+        spec = torch.empty((st.camera.H, st.camera.W, len(st.lambda_nm)), dtype=torch.float32, device="cuda")
+        xyz = torch.empty((st.camera.H, st.camera.W, 3), dtype=torch.float64, device="cuda")
+        out = []
+        for _ in range(4):
+            out.append(sdm.render_into(ctx, g, params, spec, xyz)["ms_render"])
+        return min(out)
+
+    p0, k0 = sdm.make_params(st, chunk_paths=1 << 23, tile=(16, 16))
+    t_default = best_ms(p0)
+    r = sdm.autotune(ctx, g, st)
+    p1, k1 = sdm.make_params(st)
+    t_tuned = best_ms(p1)
+    print(f"default {t_default:.2f} ms, tuned {t_tuned:.2f} ms: {r}")
+    assert t_tuned <= 1.03 * t_default
+    g.close()
 
 
 def test_batch_invalid(gpu):

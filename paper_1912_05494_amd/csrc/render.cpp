@@ -371,12 +371,14 @@ int photon_setup(sdm_context *ctx, const JobIn &j, ChunkArgs<R> &a, hipStream_t 
     // L2); above, bit b & (2^20 - 1) stands for every bucket that shares it
     pw.occ_mask = std::min<uint32_t>(buckets, 1u << 20) - 1u;
     HIPCHK(ctx, ctx->ph_occ.ensure((size_t)(pw.occ_mask + 1u) / 8u));
+    HIPCHK(ctx, ctx->ph_cocc.ensure((size_t)kPhCoarseWords * 4u));
     pw.rec = ctx->ph_rec.as<PhotonRec<R>>();
     pw.sorted = ctx->ph_sorted.as<PhotonRec<R>>();
     pw.start = ctx->ph_start.as<uint32_t>();
     pw.cursor = ctx->ph_cursor.as<uint32_t>();
     pw.part = ctx->ph_part.as<uint32_t>();
     pw.occ = ctx->ph_occ.as<uint32_t>();
+    pw.cocc = ctx->ph_cocc.as<uint32_t>();
     pw.gstack = a.w.gstack;
     pw.cnt = a.w.cnt;
     pw.r = j.p->photon_radius;

@@ -83,7 +83,7 @@ struct sdm_context {
         size_t acc_elems = 0;         // doubles of the accumulator
     } partial;
     DevBuf acc_base;                  // the accumulator a resumed render starts from
-    DevBuf ph_rec, ph_sorted, ph_start, ph_cursor, ph_part, ph_occ;   // caustic photon map
+    DevBuf ph_rec, ph_sorted, ph_start, ph_cursor, ph_part, ph_occ, ph_cocc;   // caustic photon map
     // autotuned (chunk, tile, traversal blocks per CU) per scene and render shape
     struct Tuned {
         const sdm_scene *scene;

@@ -115,7 +115,8 @@ struct JobDev {
     int32_t pad1;
 };
 
-constexpr uint32_t kPhotonTag = 0xFFFFFFF0u;   // sample word of photon draws (camera samples stay below 2^31)
+constexpr uint32_t kPhotonTag = 0xFFFFFFF0u;
+constexpr uint32_t kPhCoarseBits = 1u << 16, kPhCoarseWords = kPhCoarseBits / 32;   // 8 KiB, staged in LDS   // sample word of photon draws (camera samples stay below 2^31)
 
 // A photon of the caustic map, at rest on a Lambert surface: position, the
 // normal of the side it arrived on, its wavelength index and power.
@@ -312,6 +313,7 @@ struct PhotonWork {
     uint32_t *part;                 // [nblk] scan block sums
     uint32_t *occ;                  // occupancy bits: bit (b & occ_mask) set when bucket b holds a photon
     uint32_t occ_mask;              // occupancy bits - 1 (a power of two, at least 32)
+    uint32_t *cocc;                 // [kPhCoarseWords] coarse occupancy: cells of side 3 r, hashed
     int32_t *gstack;
     Counters *cnt;
     double r;                       // cell side and gather radius

@@ -1001,6 +1001,9 @@ __device__ __forceinline__ uint32_t ph_hash(int ix, int iy, int iz, uint32_t mas
     return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) & mask;
 }
 
+// Coarse cell (side 3 r) of a cell index: floor(i / 3), also below zero.
+__device__ __forceinline__ int ph_coarse(int i) { return i >= 0 ? i / 3 : -((2 - i) / 3); }
+
 template <class R>
 __device__ __forceinline__ void ph_cell(const V3<R> &x, const double lo[3], double r, int &ix, int &iy, int &iz)
 {
@@ -1139,10 +1142,12 @@ __global__ void __launch_bounds__(kTraceBlock) k_photon(const JobDev *__restrict
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_ph_clear(PhotonWork<R> pw)
 {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= pw.mask + 1u; i += gridDim.x * blockDim.x) {
-        pw.start[i] = 0u;
+    const uint32_t n = max(pw.mask + 2u, kPhCoarseWords);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (i <= pw.mask + 1u) pw.start[i] = 0u;
         if (i <= pw.mask) pw.cursor[i] = 0u;
         if (i <= pw.occ_mask >> 5) pw.occ[i] = 0u;
+        if (i < kPhCoarseWords) pw.cocc[i] = 0u;
     }
 }
 
@@ -1157,6 +1162,8 @@ __global__ void __launch_bounds__(kBlock) k_ph_count(PhotonWork<R> pw)
         const uint32_t b = ph_hash(ix, iy, iz, pw.mask);
         atomicAdd(pw.start + b, 1u);
         atomicOr(pw.occ + ((b & pw.occ_mask) >> 5), 1u << (b & 31u));
+        const uint32_t cb = ph_hash(ph_coarse(ix), ph_coarse(iy), ph_coarse(iz), kPhCoarseBits - 1u);
+        atomicOr(pw.cocc + (cb >> 5), 1u << (cb & 31u));
     }
 }
 
@@ -1216,6 +1223,9 @@ template <class R>
 __global__ void __launch_bounds__(kBlock) k_caustic(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands,
                                                     Work<R> w, PhotonWork<R> pw)
 {
+    __shared__ uint32_t s_cocc[kPhCoarseWords];
+    for (uint32_t i = threadIdx.x; i < kPhCoarseWords; i += blockDim.x) s_cocc[i] = pw.cocc[i];
+    __syncthreads();
     const uint32_t ns = min(w.cnt->scount, w.cap);
     const JobDev &jb = jobs[0];
     const R r2 = R(pw.r * pw.r), inv_area = R(1.0 / (3.14159265358979323846 * pw.r * pw.r));
@@ -1230,27 +1240,45 @@ __global__ void __launch_bounds__(kBlock) k_caustic(const JobDev *__restrict__ j
         double *row = w.acc + jb.acc_off + (uint64_t)(sp & ~kSpectral) * jb.nl;
         int cx, cy, cz;
         ph_cell<R>(x, pw.lo, pw.r, cx, cy, cz);
-        uint32_t seen[27];
-        int n_seen = 0;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const uint32_t b = ph_hash(cx + dx, cy + dy, cz + dz, pw.mask);
-                    if (!((pw.occ[(b & pw.occ_mask) >> 5] >> (b & 31u)) & 1u)) continue;   // no photon there
-                    bool dup = false;
-                    for (int q = 0; q < n_seen; ++q) dup = dup || seen[q] == b;
-                    if (dup) continue;
-                    seen[n_seen++] = b;
-                    for (uint32_t k = pw.start[b]; k < pw.start[b + 1]; ++k) {
-                        const PhotonRec<R> p = P[k];
-                        if (p.j < bd.l0 || p.j >= bd.l0 + bd.nb) continue;
-                        const R ex = p.x - x.x, ey = p.y - x.y, ez = p.z - x.z;
-                        if (!(ex * ex + ey * ey + ez * ez < r2)) continue;
-                        if (!(p.nx * n.x + p.ny * n.y + p.nz * n.z > R(0.9))) continue;
-                        const R f = spec ? w.contrib[aosoa(rec, p.j - bd.l0, w.nbmax)] : R(1);
-                        unsafeAtomicAdd(row + p.j, (double)(gr * f * p.phi * inv_area));
-                    }
+        // the 27 cells lie in at most 2 x 2 x 2 coarse cells: none holding a
+        // photon (the common case) ends the record with LDS lookups only
+        bool any = false;
+        for (int gz = ph_coarse(cz - 1); gz <= ph_coarse(cz + 1); ++gz)
+            for (int gy = ph_coarse(cy - 1); gy <= ph_coarse(cy + 1); ++gy)
+                for (int gx = ph_coarse(cx - 1); gx <= ph_coarse(cx + 1); ++gx) {
+                    const uint32_t cb = ph_hash(gx, gy, gz, kPhCoarseBits - 1u);
+                    any = any || ((s_cocc[cb >> 5] >> (cb & 31u)) & 1u);
                 }
+        if (!any) continue;
+        // occupancy of the 27 cells around x: every bitmap load issued before
+        // any is tested (most cells are empty: one L2 round trip, not 27)
+        auto cell_bucket = [&](int q) {
+            return ph_hash(cx + q % 3 - 1, cy + (q / 3) % 3 - 1, cz + q / 9 - 1, pw.mask);
+        };
+        uint32_t occ27 = 0;
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            const uint32_t b = cell_bucket(q);
+            occ27 |= ((pw.occ[(b & pw.occ_mask) >> 5] >> (b & 31u)) & 1u) << q;
+        }
+        // each bucket once (cells may share one): skip a cell whose bucket an
+        // earlier occupied cell has
+        for (uint32_t mq = occ27; mq; mq &= mq - 1u) {
+            const int q = __builtin_ctz(mq);
+            const uint32_t b = cell_bucket(q);
+            bool dup = false;
+            for (uint32_t me = occ27 & ((1u << q) - 1u); me; me &= me - 1u) dup = dup || cell_bucket(__builtin_ctz(me)) == b;
+            if (dup) continue;
+            for (uint32_t k = pw.start[b]; k < pw.start[b + 1]; ++k) {
+                const PhotonRec<R> p = P[k];
+                if (p.j < bd.l0 || p.j >= bd.l0 + bd.nb) continue;
+                const R ex = p.x - x.x, ey = p.y - x.y, ez = p.z - x.z;
+                if (!(ex * ex + ey * ey + ez * ez < r2)) continue;
+                if (!(p.nx * n.x + p.ny * n.y + p.nz * n.z > R(0.9))) continue;
+                const R f = spec ? w.contrib[aosoa(rec, p.j - bd.l0, w.nbmax)] : R(1);
+                unsafeAtomicAdd(row + p.j, (double)(gr * f * p.phi * inv_area));
+            }
+        }
     }
 }
 

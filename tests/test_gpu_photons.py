@@ -16,7 +16,8 @@ camera paths' Lambert vertices as rho / pi times the density estimate.
   image mean within 1 %; per pixel they agree to the FP32 tolerance on at
   least 99 % of the spectral pixels (a photon within rounding of the radius
   or of the normal test may be counted on one side only).
-  The same at 2^24 photons, the largest hash grid.
+  The same at 2^24 photons, the largest hash grid, with 4 spectral bands
+  (equal to one band) and with a distribution map on the pane.
 - Batches, item budgets and bad parameters are rejected.
 """
 import math
@@ -130,6 +131,41 @@ def test_bubbly_nave_fp64_matches_oracle(gpu, orc):
     assert s["photons_stored"] == len(stored)
     assert tol_ok(g, ref).all()
     assert g.sum() > g0.sum()
+
+
+def test_photons_band_split_and_maps_fp64(gpu, orc):
+    """Spectral sub-domains: with 4 bands each gather takes its band's
+    photons and the image equals the one-band image.  A distribution map on
+    the mirror pane (a checker of two glasses, thickness per texel): the
+    photons reflect off the texel's glass, and the render matches the
+    oracle."""
+    sc = mirror_scene()
+    st1 = mirror_settings(W=32, H=32, spp=2)
+    st4 = mirror_settings(W=32, H=32, spp=2)
+    st4.n_bands = 4
+    N = 1 << 20
+    g1, s1 = render(gpu, sc, st1, precision="fp64", photons=N, photon_radius=RADIUS)
+    g4, s4 = render(gpu, sc, st4, precision="fp64", photons=N, photon_radius=RADIUS)
+    assert s1["photons_stored"] == s4["photons_stored"] > 0
+    assert tol_ok(g4, g1).all()
+    mapped = mirror_scene()
+    pane = mapped.materials[1]
+    pane.dist_map = 1                              # 1 + index of its map
+    mapped.materials.append(glass(n=1.62, k=3e-7, tint=1.2, thick=3.0, dispersive=True))
+    mapped.materials.append(glass(n=1.50, k=1e-7, tint=0.2, thick=3.0))
+    checker = np.array([[2, 3, 2], [3, 2, 3]], dtype=np.int32)
+    mapped.maps = [synth.DistMap(W=3, H=2, material=checker,
+                                 thick_mm=np.array([[2.0, 3.0, 4.0], [5.0, 3.5, 2.5]], np.float32))]
+    uv = np.zeros((mapped.pos.shape[0], 2), np.float32)
+    uv[8:12] = [[0, 0], [1, 0], [1, 1], [0, 1]]   # the pane's corners
+    mapped.uv = uv
+    osc = orc.OracleScene(mapped)
+    stored = orc.photon_map(osc, st1, N, RADIUS)
+    ref, _ = orc.render(osc, st1, photons=N, photon_radius=RADIUS)
+    g, s = render(gpu, mapped, st1, precision="fp64", photons=N, photon_radius=RADIUS)
+    print(f"mapped mirror pane: {s['photons_stored']} photons stored (plain pane {s1['photons_stored']})")
+    assert s["photons_stored"] == len(stored) > 0 and s["photons_stored"] != s1["photons_stored"]
+    assert tol_ok(g, ref).all()
 
 
 def test_nothing_turned_equals_no_map(gpu):

@@ -271,7 +271,12 @@ typedef struct {
     uint64_t *events;
 } sdm_outputs;
 
-/* Context on HIP device `device`.  Owns the work buffers of renders. */
+/* Context on HIP device `device`.  Owns the work buffers of renders.
+ * Testing the error paths: with SDM_FAIL_ALLOC=n (n > 0) in the
+ * environment when a context is created, the n-th device allocation of the
+ * library from then on (any context or scene of the process) fails once,
+ * and the call that made it returns SDM_E_NOMEM, with no other effect: the
+ * buffer is released, and a later call allocates it again. */
 int sdm_context_create(int device, sdm_context **out);
 int sdm_context_destroy(sdm_context *ctx);
 /* Description of the last failure of a call on ctx (context-owned string). */

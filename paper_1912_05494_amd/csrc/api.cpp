@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -103,6 +104,7 @@ int sdm_context_create(int device, sdm_context **out)
     if (hipSetDevice(device) != hipSuccess) return SDM_E_DEVICE;
     auto *ctx = new sdm_context();
     ctx->device = device;
+    if (const char *fa = std::getenv("SDM_FAIL_ALLOC")) sdm_rt::fail_alloc_countdown().store(std::atol(fa));
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
         delete ctx;
@@ -767,7 +769,8 @@ int sdm_mlp_load(sdm_context *ctx, const char *path, sdm_mlp **out)
     if (e == hipSuccess) e = hipMemcpy(net->m2.p, buf.data() + 2 * np, pb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         sdm_mlp_destroy(net);
-        return fail(ctx, SDM_E_DEVICE, "mlp load: %s", hipGetErrorString(e));
+        return fail(ctx, e == hipErrorOutOfMemory ? SDM_E_NOMEM : SDM_E_DEVICE, "mlp load: %s",
+                    hipGetErrorString(e));
     }
     net->t = t;
     *out = net;

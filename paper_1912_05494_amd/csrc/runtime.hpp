@@ -2,6 +2,7 @@
 // network) and the error helpers shared by the API translation units.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <atomic>
 
 #include <algorithm>
 #include <string>
@@ -27,6 +28,15 @@ struct Digest {
     template <class T> void add_value(const T &v) { add(&v, sizeof(v)); }
 };
 
+// Allocation-failure injection for tests of the error paths: a positive
+// count n makes the n-th device allocation from then on fail as out of
+// memory, once (set from SDM_FAIL_ALLOC at sdm_context_create).
+inline std::atomic<long> &fail_alloc_countdown()
+{
+    static std::atomic<long> c{0};
+    return c;
+}
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -34,6 +44,7 @@ struct DevBuf {
     {
         if (b <= bytes && p) return hipSuccess;
         release();
+        if (fail_alloc_countdown().load() > 0 && fail_alloc_countdown().fetch_sub(1) == 1) return hipErrorOutOfMemory;
         hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
         if (e != hipSuccess) { p = nullptr; bytes = 0; return e; }
         bytes = std::max<size_t>(b, 256);

@@ -114,7 +114,12 @@ class TrainParams(C.Structure):
 
 
 class SdmError(RuntimeError):
-    pass
+    """A call of the library failed; code is its return value (SDM_E_*), or
+    None for errors raised by the binding itself."""
+
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 _lib = None
@@ -172,6 +177,7 @@ EXPORTED = ("sdm_context_create", "sdm_context_destroy", "sdm_last_error", "sdm_
             "sdm_mlp_train", "sdm_mlp_infer", "sdm_debug_mfma", "sdm_mlp_error_table",
             "sdm_render_batch", "sdm_autotune", "sdm_render_checkpoint", "sdm_render_resume", "sdm_mlp_save",
             "sdm_mlp_load", "sdm_mlp_info", "sdm_slab_mc_noalloc")
+SDM_E_INVALID, SDM_E_NOMEM, SDM_E_DEVICE = -1, -2, -3
 SDM_E_UNSUPPORTED = -4
 SDM_E_ABORTED = -5
 
@@ -202,12 +208,12 @@ class Context:
         self._owned = weakref.WeakSet()
         rc = lib().sdm_context_create(device, C.byref(self.ptr))
         if rc != SDM_OK:
-            raise SdmError(f"sdm_context_create failed ({rc})")
+            raise SdmError(f"sdm_context_create failed ({rc})", code=rc)
 
     def check(self, rc, what):
         if rc != SDM_OK:
             msg = lib().sdm_last_error(self.ptr).decode(errors="replace")
-            raise SdmError(f"{what} failed ({rc}): {msg}")
+            raise SdmError(f"{what} failed ({rc}): {msg}", code=rc)
 
     def close(self):
         if self.ptr:

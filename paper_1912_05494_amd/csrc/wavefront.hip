@@ -1591,36 +1591,6 @@ __device__ __forceinline__ void emit_paths(const Work<R> &w, const Pool<R> &Po, 
     if (fork) put_path<R>(Po, of, x, drefl, tri, pix, smp, aux + 1u, g);
 }
 
-template <class R>
-__device__ __forceinline__ void emit_split(const Work<R> &w, const Pool<R> &Pi, const Pool<R> &Po, int cur, bool keep,
-                                           bool fork, uint32_t i, V3<R> x, V3<R> dnew, V3<R> drefl, uint32_t pix,
-                                           uint32_t smp, uint32_t aux, int32_t tri, int nb, uint32_t m0, uint32_t m1,
-                                           uint32_t m2, uint32_t m3, R g, uint32_t *s_cnt, uint32_t *s_base)
-{
-    const int nbm = w.nbmax;
-    uint32_t om, of;
-    emit_paths<R>(w, Po, cur, keep, fork, x, dnew, drefl, pix, smp, aux, tri, g, om, of, s_cnt, s_base);
-    if (keep) {
-        const R *__restrict__ bin = Pi.beta + aosoa(i, 0, nbm);
-        R *__restrict__ bk = Po.beta + aosoa(om, 0, nbm);
-        R *__restrict__ bf = Po.beta + aosoa(fork ? of : om, 0, nbm);
-        for (int j = 0; j < nb; j += 4) {
-            const Vec4<R> b = row_load4(bin + j);
-            Vec4<R> k4 = b, f4 = b;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int jj = j + q;
-                const uint32_t word = jj < 32 ? m0 : jj < 64 ? m1 : jj < 96 ? m2 : m3;
-                const bool refl = (word >> (jj & 31)) & 1u;
-                k4.v[q] = (fork && refl) ? R(0) : b.v[q];
-                f4.v[q] = refl ? b.v[q] : R(0);
-            }
-            row_store4(bk + j, k4);
-            if (fork) row_store4(bf + j, f4);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Glass vertices (thin slab, Sec. 6 thickness map): per wavelength the path
 // reflects with probability R/(R+T) and otherwise passes straight through,
@@ -2114,8 +2084,18 @@ __global__ void __launch_bounds__(kBlock) k_bubbly_eval_fp64(const JobDev *__res
 // exp(-alpha L).  Surrogate: reflect where u0 < R / (R + T), else the
 // transmitted lobe of width w, folded onto the far side of the pane.  Either
 // way a band splits into at most a reflected and a continuing packet.
+//
+// One lane per vertex for the set-up and the walk; the per-wavelength rows
+// (weights, surrogate ratios, tables) are taken by the whole wave (see
+// RowTasks), with a row's weights written back signed: negative where the
+// wavelength reflects.  Exact vertices take two row passes around the walk
+// (the entry decisions, which tell whether the walk is needed, then the
+// weights after it); surrogate vertices one.
+constexpr uint32_t kRowExact = 64u;
+
+// FP32: four waves per SIMD (the walk is latency-bound)
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) k_shade_bubbly(const JobDev *__restrict__ jobs, const BandDev *__restrict__ bands, Work<R> w, int cur)
 {
     const uint32_t count = min(w.cnt->bcount, w.cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->bubbly += count;
@@ -2123,23 +2103,21 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restric
     const int nbm = w.nbmax;
     const uint32_t lane = lane_id();
     __shared__ uint32_t s_cnt[(kBlock / 64) * 2], s_base[2];
+    __shared__ uint32_t s_map_all[kBlock];
+    uint32_t *const s_map = s_map_all + (threadIdx.x & ~63u);
     uint32_t n_fork = 0;
     // block-strided: the block reserves its output slots together
     for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
         const bool active = base + threadIdx.x < count;
-        uint32_t i = 0, aux = 0, pix = 0, smp = 0;
+        uint32_t i = 0, aux = 0, pix = 0, smp = 0, flags = 0, mo = 0;
         int32_t tri = -1;
-        V3<R> x = {R(0), R(0), R(0)}, dnew = x, drefl = x;
-        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-        bool keep = false, fork = false;
-        R g = R(0);
-        BandDev bd = {0, 0, 0, 0};
+        V3<R> x = {R(0), R(0), R(0)}, dnew = x, d = x, ng = x;
+        R g = R(0), cos_i = R(0), thick = R(0), u0 = R(0), sigma = R(0), n_ref = R(0);
+        int pol = 0;
+        WalkStream ws = {0, 0, 0, 0, 0, true};
         if (active) {
-            V3<R> d, ng;
-            R cos_i, thick;
             const BubblyVertex v = bubbly_vertex<R>(jobs, bands, w, Pi, base + threadIdx.x, d, ng, cos_i, thick);
             i = v.i;
-            bd = v.bd;
             tri = v.tri;
             const PathS<R> ps = rec_load(Pi.s + i);
             aux = ps.aux;
@@ -2152,84 +2130,189 @@ __global__ void __launch_bounds__(kBlock) k_shade_bubbly(const JobDev *__restric
             const PathO<R> po = rec_load(Pi.o + i);
             x = V3<R>{po.x, po.y, po.z} + rec_load(w.hit + i).t * d;
             dnew = d;
-            drefl = d - (R(2) * dot(d, ng)) * ng;
-            const size_t mo = (size_t)v.mat * jb->ms + bd.l0;
-            const R *nn = (const R *)jb->n + mo;
-            const R *kk = (const R *)jb->k + mo;
-            const R *tt = (const R *)jb->tint + mo;
-            const R *lam = (const R *)jb->lam + bd.l0;
-            const R thr = R(jb->beta_thr);
-            bool anyR = false, anyT = false;
-            auto set_bit = [&](int j) {
-                const uint32_t bit = 1u << (j & 31);
-                if (j < 32) m0 |= bit; else if (j < 64) m1 |= bit; else if (j < 96) m2 |= bit; else m3 |= bit;
-            };
+            mo = (uint32_t)(v.mat * jb->ms + v.bd.l0);
+            flags = (spec ? kRowSrc : 0u) | ((v.bd.l0 & 3) == 0 ? kRowAl : 0u) | (uint32_t)v.bd.nb << kRowNbShift |
+                    (uint32_t)v.bd.l0 << 16;
             if (v.mode == kBtdfExact) {
-                const WalkStream ws = {jb->seed, pix, smp & ~kSpectral, jb->job_word, (uint32_t)depth, true};
+                flags |= kRowExact;
+                ws = {jb->seed, pix, smp & ~kSpectral, jb->job_word, (uint32_t)depth, true};
                 R ue[4];
                 walk_draw<R>(ws, 0, 0, ue);
-                const int pol = ue[1] < R(0.5) ? 0 : 1;
-                bool enter = false;
-                for (int j = 0; j < bd.nb; ++j) {
-                    if (spec && Pi.beta[aosoa(i, j, nbm)] == R(0)) continue;
-                    R Rs, Rp;
-                    fresnel_sp<R>(cos_i, gld(nn + j), gld(kk + j), Rs, Rp);
-                    if (ue[0] < (pol == 0 ? Rs : Rp)) set_bit(j);
-                    else enter = true;
-                }
-                WalkOut<R> wo;
-                wo.kind = 0;
-                wo.L = R(0);
-                if (enter) {
-                    wo = bubbly_walk<R>(ws, cos_i, thick, R(v.sigma), R(v.n_ref), pol);
-                    if (wo.kind != 0) dnew = slab_to_world<R>(d, ng, wo.a);
-                }
-                const uint32_t r0 = m0, r1 = m1, r2 = m2, r3 = m3;
-                m0 = m1 = m2 = m3 = 0;
-                for (int j = 0; j < bd.nb; ++j) {
-                    const size_t q = aosoa(i, j, nbm);
-                    const R b = spec ? Pi.beta[q] : R(1);
-                    if (b == R(0)) continue;
-                    const uint32_t word = j < 32 ? r0 : j < 64 ? r1 : j < 96 ? r2 : r3;
-                    const bool refl = (word >> (j & 31)) & 1u;
-                    R bn = R(0);
-                    if (refl) {
-                        bn = b;
-                    } else if (wo.kind != 0) {
-                        const R alpha = R(12.566370614359172) * gld(kk + j) / (gld(lam + j) * R(1e-6)) + gld(tt + j);
-                        bn = b * exp(-alpha * wo.L);
-                    }
-                    if (g * bn < thr) bn = R(0);
-                    Pi.beta[q] = bn;
-                    if (bn == R(0)) continue;
-                    if (refl) { anyR = true; set_bit(j); }
-                    else anyT = true;
-                }
+                pol = ue[1] < R(0.5) ? 0 : 1;
+                u0 = ue[0];
+                sigma = R(v.sigma);
+                n_ref = R(v.n_ref);
             } else {
                 const uint4 rr = vertex_draws(jb->seed, jb->job_word, pix, smp & ~kSpectral, depth, 0);
-                const R u0 = u01<R>(rr.x);
+                u0 = u01<R>(rr.x);
                 dnew = lobe_dir<R>(d, w.bw[i], u01<R>(rr.y), u01<R>(rr.z));
                 // a sample that points back through the entry side is
                 // mirrored across the pane's plane: transmitted light leaves
                 // on the far side
                 const R dn_out = dot(dnew, ng);
                 if (dn_out * dot(d, ng) < R(0)) dnew = dnew - (R(2) * dn_out) * ng;
-                for (int j = 0; j < bd.nb; ++j) {
-                    const size_t q = aosoa(i, j, nbm);
-                    R bn = Pi.beta[q];
-                    if (bn == R(0)) continue;
-                    if (g * bn < thr) { Pi.beta[q] = R(0); continue; }
-                    if (u0 < w.bratio[q]) { anyR = true; set_bit(j); }
-                    else anyT = true;
-                }
             }
-            keep = anyR || anyT;
-            fork = anyR && anyT;
-            if (anyR && !anyT) dnew = drefl;
         }
+        const RowTasks rt = row_tasks(active, nbm, s_map);
+        // Row pass 1.  Exact: per wavelength with a weight, reflect where the
+        // shared draw falls below the entry reflectance of the drawn
+        // polarisation, else enter; the row holds +-b (b = 1 for a path
+        // without per-wavelength factors).  Surrogate: the weights (already
+        // times R + T) below the threshold are cleared, the others signed by
+        // u0 < R / (R + T).
+        bool anyR = false, anyT = false, enter = false;
+        for (int b0 = 0; b0 < rt.n; b0 += rt.ng) {
+            const int src = rt.src(b0, s_map);
+            const uint32_t f = (uint32_t)__shfl((int)flags, src);
+            const uint32_t si = (uint32_t)__shfl((int)i, src), smo = (uint32_t)__shfl((int)mo, src);
+            const R sc = __shfl(cos_i, src), su = __shfl(u0, src), sg = __shfl(g, src);
+            const int spol = __shfl(pol, src);
+            const uint32_t sjob = (uint32_t)__shfl((int)(aux >> kAuxJobShift), src);
+            const int nb = (int)((f >> kRowNbShift) & 0xffu), j = rt.j;
+            bool lR = false, lT = false, lE = false;
+            if (rt.busy(b0) && j < nb) {
+                const JobDev *sj = &jobs[sjob];
+                const bool al = (f & kRowAl) != 0u;
+                R *__restrict__ brow = Pi.beta + aosoa(si, 0, nbm);
+                Vec4<R> o4;
+                if (f & kRowExact) {
+                    Vec4<R> b4;
+                    if (f & kRowSrc) b4 = row_load4(brow + j);
+                    else b4.v[0] = b4.v[1] = b4.v[2] = b4.v[3] = R(1);
+                    const Vec4<R> n4 = tab4((const R *)sj->n + smo, al, j, nb),
+                                  k4 = tab4((const R *)sj->k + smo, al, j, nb);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        o4.v[q] = R(0);
+                        if (j + q >= nb || b4.v[q] == R(0)) continue;
+                        R Rs, Rp;
+                        fresnel_sp<R>(sc, n4.v[q], k4.v[q], Rs, Rp);
+                        if (su < (spol == 0 ? Rs : Rp)) o4.v[q] = -b4.v[q];
+                        else {
+                            o4.v[q] = b4.v[q];
+                            lE = true;
+                        }
+                    }
+                } else {
+                    const Vec4<R> b4 = row_load4(brow + j), r4 = row_load4(w.bratio + aosoa(si, j, nbm));
+                    const R thr = R(sj->beta_thr);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        o4.v[q] = R(0);
+                        const R bn = b4.v[q];
+                        if (j + q >= nb || bn == R(0) || sg * bn < thr) continue;
+                        if (su < r4.v[q]) {
+                            o4.v[q] = -bn;
+                            lR = true;
+                        } else {
+                            o4.v[q] = bn;
+                            lT = true;
+                        }
+                    }
+                }
+                row_store4(brow + j, o4);
+            }
+            const uint64_t bR = __ballot(lR), bT = __ballot(lT), bE = __ballot(lE);
+            uint64_t mine;
+            if (rt.mine(active, b0, mine)) {
+                anyR = (bR & mine) != 0u;
+                anyT = (bT & mine) != 0u;
+                enter = (bE & mine) != 0u;
+            }
+        }
+        // the walk of an exact vertex whose light enters the pane
+        int wkind = 0;
+        R wL = R(0);
+        if (active && (flags & kRowExact) && enter) {
+            const WalkOut<R> wo = bubbly_walk<R>(ws, cos_i, thick, sigma, n_ref, pol);
+            wkind = wo.kind;
+            wL = wo.L;
+            if (wo.kind != 0) dnew = slab_to_world<R>(d, ng, wo.a);
+        }
+        // Row pass 2 (exact vertices): the reflected wavelengths keep their
+        // weight, the entering ones take exp(-alpha L) if the walk left the
+        // pane (zero if it was absorbed); then the energy threshold.
+        for (int b0 = 0; b0 < rt.n; b0 += rt.ng) {
+            const int src = rt.src(b0, s_map);
+            const uint32_t f = (uint32_t)__shfl((int)flags, src);
+            const uint32_t si = (uint32_t)__shfl((int)i, src), smo = (uint32_t)__shfl((int)mo, src);
+            const R sg = __shfl(g, src), sL = __shfl(wL, src);
+            const int sk = __shfl(wkind, src);
+            const uint32_t sjob = (uint32_t)__shfl((int)(aux >> kAuxJobShift), src);
+            const int nb = (int)((f >> kRowNbShift) & 0xffu), j = rt.j;
+            bool lR = false, lT = false;
+            if (rt.busy(b0) && j < nb && (f & kRowExact)) {
+                const JobDev *sj = &jobs[sjob];
+                const bool al = (f & kRowAl) != 0u;
+                R *__restrict__ brow = Pi.beta + aosoa(si, 0, nbm);
+                const Vec4<R> b4 = row_load4(brow + j);
+                const Vec4<R> l4 = tab4((const R *)sj->lam + (f >> 16), al, j, nb),
+                              k4 = tab4((const R *)sj->k + smo, al, j, nb),
+                              t4 = tab4((const R *)sj->tint + smo, al, j, nb);
+                const R thr = R(sj->beta_thr);
+                Vec4<R> o4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    o4.v[q] = R(0);
+                    const R b = b4.v[q];
+                    if (j + q >= nb || b == R(0)) continue;
+                    const bool refl = b < R(0);
+                    R bn = R(0);
+                    if (refl) {
+                        bn = -b;
+                    } else if (sk != 0) {
+                        const R alpha = R(12.566370614359172) * k4.v[q] / (l4.v[q] * R(1e-6)) + t4.v[q];
+                        bn = b * exp(-alpha * sL);
+                    }
+                    if (sg * bn < thr) bn = R(0);
+                    if (bn == R(0)) continue;
+                    if (refl) {
+                        o4.v[q] = -bn;
+                        lR = true;
+                    } else {
+                        o4.v[q] = bn;
+                        lT = true;
+                    }
+                }
+                row_store4(brow + j, o4);
+            }
+            const uint64_t bR = __ballot(lR), bT = __ballot(lT);
+            uint64_t mine;
+            if (rt.mine(active && (flags & kRowExact), b0, mine)) {
+                anyR = (bR & mine) != 0u;
+                anyT = (bT & mine) != 0u;
+            }
+        }
+        bool keep = anyR || anyT, fork = anyR && anyT;
+        const V3<R> drefl = d - (R(2) * dot(d, ng)) * ng;
+        if (anyR && !anyT) dnew = drefl;
         n_fork += fork ? 1u : 0u;
-        emit_split<R>(w, Pi, Po, cur, keep, fork, i, x, dnew, drefl, pix, smp, aux, tri, bd.nb, m0, m1, m2, m3, g,
-                      s_cnt, s_base);
+        uint32_t om, of;
+        emit_paths<R>(w, Po, cur, keep, fork, x, dnew, drefl, pix, smp, aux, tri, g, om, of, s_cnt, s_base);
+        // the rows of the outputs: the kept path takes the transmitted
+        // wavelengths (all of them without a fork), the forked path the
+        // reflected ones
+        const uint32_t ef = flags | (keep ? kRowKeep : 0u) | (fork ? kRowFork : 0u);
+        for (int b0 = 0; b0 < rt.n; b0 += rt.ng) {
+            const int src = rt.src(b0, s_map);
+            const uint32_t f = (uint32_t)__shfl((int)ef, src);
+            const uint32_t si = (uint32_t)__shfl((int)i, src), so = (uint32_t)__shfl((int)om, src),
+                           sf = (uint32_t)__shfl((int)of, src);
+            const int nb = (int)((f >> kRowNbShift) & 0xffu), j = rt.j;
+            if (!rt.busy(b0) || j >= nb || !(f & kRowKeep)) continue;
+            const bool fk = (f & kRowFork) != 0u;
+            const Vec4<R> b = row_load4(Pi.beta + aosoa(si, j, nbm));
+            Vec4<R> k4, f4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool refl = signbit(b.v[q]);
+                const R a = fabs(b.v[q]);
+                k4.v[q] = (fk && refl) ? R(0) : a;
+                f4.v[q] = refl ? a : R(0);
+            }
+            row_store4(Po.beta + aosoa(so, j, nbm), k4);
+            if (fk) row_store4(Po.beta + aosoa(sf, j, nbm), f4);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) n_fork += __shfl_xor(n_fork, off);
     if (lane == 0 && n_fork) atomicAdd(&w.cnt->forks, (unsigned long long)n_fork);

@@ -5,8 +5,11 @@ MI355X.  A step is one full render.
 
 Prints one JSON line with the throughput, a roofline entry for the dominant
 kernel (per-kernel durations from HIP events the library records on the
-launch stream during the timed steps) and the FP64 CPU oracle timed on a
-bounded pixel sample of the same workload.
+launch stream during the timed steps), the FP64 CPU oracle timed on a
+bounded pixel sample of the same workload, and (surrogate_form) the same
+nave with its panes bubbly: the plain form (exact walks) against the trained
+surrogate, with both forms' colour differences from a converged reference
+(the run of --form bubbly, summarised; --no-surrogate skips it).
 """
 import argparse
 import json
@@ -254,7 +257,7 @@ def copy_bandwidth(nbytes=2 << 30, reps=5):
     return 2 * nbytes / best / 1e9
 
 
-def bubbly_bench(args):
+def bubbly_bench(args, emit=True):
     """Bubbly panes on the nave: MC tables of the slab (GPU), network training
     (matrix cores), validation and error table, then four forms of the render:
     exact walks (the plain form for bubbly panes), surrogate, fallback, and
@@ -392,9 +395,11 @@ def bubbly_bench(args):
         "mc_tuple_photons_per_s": len(tup) * 64 / t_mc,
         "train_samples_per_s": args.bubbly_steps * 8192 / t_train,
     }
-    print(json.dumps(out), flush=True)
     net.close()
     ctx.close()
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def large_bench(args):
@@ -777,6 +782,8 @@ def main():
     ap.add_argument("--bands", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the bubbly nave's plain-against-surrogate comparison in the default line")
     ap.add_argument("--no-band-split", action="store_true", help="skip the 4- and 16-band timings")
     ap.add_argument("--profile-once", action="store_true",
                     help="one render plus a 256 MiB calibration copy (for rocprofv3 --pmc)")
@@ -985,8 +992,24 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, st)
-    print(json.dumps(out), flush=True)
     ctx.close()
+    if not args.no_surrogate:
+        # the other half of the metric: the same nave with its panes bubbly,
+        # plain form (exact walks) against the trained surrogate at a mean
+        # block dE2000 < 1 (the whole run of --form bubbly, summarised)
+        b = bubbly_bench(args, emit=False)
+        f = b["forms"]
+        out["surrogate_form"] = {
+            "metric": b["metric"], "workload": b["config"]["workload"], "surrogate": b["config"]["surrogate"],
+            "plain_value": f["exact"]["value"], "plain_ms": f["exact"]["ms_per_step"],
+            "surrogate_value": f["surrogate"]["value"], "surrogate_ms": f["surrogate"]["ms_per_step"],
+            "surrogate_vs_plain": f["surrogate"]["value"] / f["exact"]["value"],
+            "fallback_value": f["fallback"]["value"], "bubble_free_value": f["bubble_free"]["value"],
+            "reference": b["reference"],
+            "block_de2000_vs_reference": b["mean_delta_e2000_vs_reference_16x16_blocks"],
+            "pixel_de2000_vs_reference": b["mean_delta_e2000_vs_reference"],
+        }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

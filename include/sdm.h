@@ -271,7 +271,12 @@ typedef struct {
     uint64_t *events;
 } sdm_outputs;
 
-/* Context on HIP device `device`.  Owns the work buffers of renders.
+/* Context on HIP device `device`.  Owns the work buffers of renders and a
+ * second stream of its own (default priority), on which each bounce's
+ * shadow walk and accumulation run beside the next bounce's closest-hit
+ * pass; a render's results are complete on the caller's stream when the
+ * call's work there is.  SDM_SERIAL=1 in the environment when the context is
+ * created keeps every pass on the caller's stream (same results).
  * Testing the error paths: with SDM_FAIL_ALLOC=n (n > 0) in the
  * environment when a context is created, the n-th device allocation of the
  * library from then on (any context or scene of the process) fails once,

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -82,6 +83,39 @@ int mlp_enqueue_grad(sdm_mlp *net, int64_t m, const float *tuples, const int32_t
     return SDM_OK;
 }
 
+// Vertex p as (p[k + 1], p[k + 2], p[k]) (indices mod 3), w kept: the frame
+// of the FP32 triangle test of rays whose dominant axis is k.
+float4 rot_vertex(const float4 &p, int k)
+{
+    const float c[3] = {p.x, p.y, p.z};
+    return make_float4(c[(k + 1) % 3], c[(k + 2) % 3], c[k], p.w);
+}
+
+// Copies k = ks[0], ks[1], ... of n triangles (TriDev or GridCand), one after
+// the other.
+template <class T>
+std::vector<T> rotated_copies(const T *src, size_t n, std::initializer_list<int> ks)
+{
+    std::vector<T> out;
+    out.reserve(n * ks.size());
+    for (const int k : ks)
+        for (size_t i = 0; i < n; ++i) {
+            T t = src[i];
+            t.a = rot_vertex(t.a, k);
+            t.b = rot_vertex(t.b, k);
+            t.c = rot_vertex(t.c, k);
+            out.push_back(t);
+        }
+    return out;
+}
+
+// The dominant axis of a direction as the kernels' ray shear takes it.
+int dominant_axis(const float d[3])
+{
+    const float ax = std::fabs(d[0]), ay = std::fabs(d[1]), az = std::fabs(d[2]);
+    return (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+}
+
 int check_flag(sdm_context *ctx, hipStream_t s, const char *what)
 {
     int bad = 0;
@@ -125,11 +159,14 @@ int sdm_context_create(int device, sdm_context **out)
     // the stream graphs are captured on and replayed from (default priority)
     if (hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->join[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->join[1], hipEventDisableTiming) != hipSuccess) {
-        (void)hipHostFree(ctx->host_counters);
-        delete ctx;
+        hipEventCreateWithFlags(&ctx->join[1], hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->rejoin, hipEventDisableTiming) != hipSuccess) {
+        (void)sdm_context_destroy(ctx);
         return SDM_E_DEVICE;
     }
+    if (const char *ser = std::getenv("SDM_SERIAL")) ctx->overlap = std::atoi(ser) == 0;
     *out = ctx;
     return SDM_OK;
 }
@@ -143,7 +180,10 @@ int sdm_context_destroy(sdm_context *ctx)
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     for (auto e : ctx->join)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->rejoin) (void)hipEventDestroy(ctx->rejoin);
     if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
     delete ctx;
     return SDM_OK;
@@ -403,12 +443,19 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
                              : build_sun_grid(tris.data(), d->nt, mtype.data(), d->sun_dir, diag + maxabs);
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    const int sun_axis = dominant_axis(d->sun_dir);
     if (grid.use) {
         chk(upload(sc->g_start, grid.start.data(), grid.start.size()));
         chk(upload(sc->g_cand, grid.cand.data(), grid.cand.size()));
+        const std::vector<GridCand> rc = rotated_copies(grid.cand.data(), grid.cand.size(), {sun_axis});
+        chk(upload(sc->g_cand_rot, rc.data(), rc.size()));
     }
     chk(upload(sc->nodes, bvh.nodes.data(), bvh.nodes.size()));
     chk(upload(sc->tris, tris.data(), tris.size()));
+    {
+        const std::vector<TriDev> rt = rotated_copies(tris.data(), tris.size(), {0, 1, 2});
+        chk(upload(sc->tris_rot, rt.data(), rt.size()));
+    }
     chk(upload(sc->thick, thick.data(), thick.size()));
     chk(upload(sc->orig_to_leaf, o2l.data(), o2l.size()));
     chk(upload(sc->mat_type, mtype.data(), mtype.size()));
@@ -454,6 +501,8 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         chk(upload(sc->dd_cells, sub.cells.data(), sub.cells.size()));
         chk(upload(sc->dd_nodes, sub.nodes.data(), std::max<size_t>(1, sub.nodes.size())));
         chk(upload(sc->dd_tris, sub.tris.data(), std::max<size_t>(1, sub.tris.size())));
+        const std::vector<TriDev> rt = rotated_copies(sub.tris.data(), sub.tris.size(), {0, 1, 2});
+        chk(upload(sc->dd_tris_rot, rt.data(), rt.size()));
         chk(upload(sc->dd_leaf, sub.leaf.data(), std::max<size_t>(1, sub.leaf.size())));
         for (int a = 0; a < 3; ++a) sc->dd_n[a] = dd_n[a];
         sc->dd_refs = (int64_t)sub.tris.size();
@@ -473,6 +522,8 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     SceneDev &sd = sc->dev;
     sd.nodes = sc->nodes.as<BvhNode>();
     sd.tris = sc->tris.as<TriDev>();
+    sd.tris_rot = sc->tris_rot.as<TriDev>();
+    sd.rot_n = d->nt;
     sd.thick = sc->thick.as<float4>();
     sd.mat_type = sc->mat_type.as<int32_t>();
     sd.mat_thick = sc->mat_thick.as<float>();
@@ -485,6 +536,8 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
     sd.g_use = grid.use ? 1 : 0;
     sd.g_start = grid.use ? sc->g_start.as<int32_t>() : nullptr;
     sd.g_cand = grid.use ? sc->g_cand.as<GridCand>() : nullptr;
+    sd.g_cand_rot = grid.use ? sc->g_cand_rot.as<GridCand>() : nullptr;
+    sd.g_rot = sun_axis;
     for (int a = 0; a < 3; ++a) {
         sd.g_e1[a] = grid.e1[a];
         sd.g_e2[a] = grid.e2[a];
@@ -513,6 +566,8 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         sd.dd.cells = sc->dd_cells.as<CellDev>();
         sd.dd.nodes = sc->dd_nodes.as<BvhNode>();
         sd.dd.tris = sc->dd_tris.as<TriDev>();
+        sd.dd.tris_rot = sc->dd_tris_rot.as<TriDev>();
+        sd.dd.n_refs = (int32_t)sub.tris.size();
         sd.dd.leaf = sc->dd_leaf.as<int32_t>();
     }
     sd.n_maps = any_map ? d->n_maps : 0;

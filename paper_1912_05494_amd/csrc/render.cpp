@@ -152,9 +152,12 @@ struct Timer {
     bool on;
     size_t next = 0;
     std::vector<std::pair<int, size_t>> marks;  // (kernel class, event index of start)
-    hipError_t begin(int cls)
+    hipStream_t at = nullptr;                   // stream of the open mark
+    // brackets the next launch on stream on_s (default: s)
+    hipError_t begin(int cls, hipStream_t on_s = nullptr)
     {
         if (!on) return hipSuccess;
+        at = on_s ? on_s : s;
         if (next + 2 > ctx->events.size()) {
             for (int i = 0; i < 64; ++i) {
                 hipEvent_t e;
@@ -164,14 +167,14 @@ struct Timer {
             }
         }
         marks.push_back({cls, next});
-        hipError_t r = hipEventRecord(ctx->events[next], s);
+        hipError_t r = hipEventRecord(ctx->events[next], at);
         next += 2;
         return r;
     }
     hipError_t end()
     {
         if (!on) return hipSuccess;
-        return hipEventRecord(ctx->events[marks.back().second + 1], s);
+        return hipEventRecord(ctx->events[marks.back().second + 1], at);
     }
 };
 
@@ -225,19 +228,31 @@ struct ChunkArgs {
     PhotonWork<R> pw;
     int32_t cam_fused;          // camera rays may take the fused slab form (origins in the scene's bounds)
     int32_t grid_g, grid_t, grid_s, grid_gl, grid_e, grid_b, grid_st, grid_a;   // blocks per pass
+    int32_t overlap;            // 1: shadow walk and accumulation on the side stream
 };
 
+// One chunk: generate, then per bounce the closest-hit pass, shading, the
+// shadow walk and the accumulation.  With a.overlap, the shadow walk and
+// accumulation of bounce i (and the caustic gather) run on the side stream
+// while the closest-hit pass of bounce i + 1 runs on s: both read only what
+// the shading of bounce i wrote (the paths of the next pool; the records),
+// the walk has its own overflow stack, and the records' counters are reset
+// on the side stream after their last reader.  The shading of bounce i + 1,
+// which writes new records, waits for the side stream first.
 template <class R>
-void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
+void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t rejoin,
+                   Timer *tm)
 {
-    auto mark = [&](int cls) { if (tm) (void)tm->begin(cls); };
+    const bool ov = a.overlap != 0 && side != nullptr;
+    hipStream_t s2 = ov ? side : s;
+    auto mark = [&](int cls, hipStream_t on) { if (tm) (void)tm->begin(cls, on); };
     auto done = [&]() { if (tm) (void)tm->end(); };
     int cur = 0;
-    mark(SDM_K_GENERATE);
+    mark(SDM_K_GENERATE, s);
     launch_generate<R>(a.jobs, a.bands, a.items, a.n_items, a.w, a.total, a.chunk, a.grid_g, s);
     done();
     for (int dpt = 0; dpt < a.depth; ++dpt) {
-        mark(SDM_K_TRACE);
+        mark(SDM_K_TRACE, s);
         if (a.dd_sweeps > 0)
             launch_dd_trace<R>(a.jobs, a.w, cur, dpt > 0 || a.cam_fused != 0, a.dd_sweeps, a.dd_march != 0, a.grid_t,
                                s);
@@ -245,36 +260,44 @@ void enqueue_chunk(const ChunkArgs<R> &a, hipStream_t s, Timer *tm)
             launch_trace<R>(a.jobs, a.w, cur, a.lds_job, dpt > 0 || a.cam_fused != 0, a.one_job != 0, a.grid_t, s);
         done();
         if (a.w.sig) launch_sig_hits<R>(a.jobs, a.bands, a.w, cur, a.grid_s, s);
-        mark(SDM_K_SHADE);
+        if (ov && dpt > 0) (void)hipStreamWaitEvent(s, rejoin, 0);   // the previous bounce's records are read
+        mark(SDM_K_SHADE, s);
         launch_shade<R>(a.jobs, a.bands, a.w, cur, a.one_job != 0, a.grid_s, s);
         done();
-        mark(SDM_K_SHADE_GLASS);
+        mark(SDM_K_SHADE_GLASS, s);
         launch_shade_glass<R>(a.jobs, a.bands, a.w, cur, a.one_job != 0, a.grid_gl, s);
         done();
         if (a.surr) {
-            mark(SDM_K_BUBBLY_EVAL);
+            mark(SDM_K_BUBBLY_EVAL, s);
             launch_bubbly_eval<R>(a.jobs, a.bands, a.w, cur, a.params, a.E, a.n_panes, a.grid_e, s);
             done();
         }
         if (a.bubbly) {
-            mark(SDM_K_SHADE_BUBBLY);
+            mark(SDM_K_SHADE_BUBBLY, s);
             launch_shade_bubbly<R>(a.jobs, a.bands, a.w, cur, a.grid_b, s);
             done();
         }
-        mark(SDM_K_SHADOW);
-        launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.one_job != 0, a.grid_st, s);
+        if (ov) {
+            (void)hipEventRecord(fork, s);
+            (void)hipStreamWaitEvent(s2, fork, 0);
+        }
+        mark(SDM_K_SHADOW, s2);
+        launch_shadow_trace<R>(a.jobs, a.bands, a.w, a.lds_job, a.one_job != 0, a.grid_st, s2);
         done();
-        if (a.w.sig) launch_sig_shadow<R>(a.jobs, a.bands, a.w, a.grid_s, s);
-        mark(SDM_K_SHADOW_ACCUM);
-        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.one_job != 0, a.grid_a, s);
+        if (a.w.sig) launch_sig_shadow<R>(a.jobs, a.bands, a.w, a.grid_s, s2);
+        mark(SDM_K_SHADOW_ACCUM, s2);
+        launch_shadow_accum<R>(a.jobs, a.bands, a.w, a.one_job != 0, a.grid_a, s2);
         done();
         if (a.caustic) {
-            mark(SDM_K_CAUSTIC);
-            launch_caustic<R>(a.jobs, a.bands, a.w, a.pw, a.grid_a, s);
+            mark(SDM_K_CAUSTIC, s2);
+            launch_caustic<R>(a.jobs, a.bands, a.w, a.pw, a.grid_a, s2);
             done();
         }
+        if (dpt + 1 < a.depth) launch_reset_records(a.w.cnt, s2);
+        if (ov) (void)hipEventRecord(rejoin, s2);
         cur ^= 1;
     }
+    if (ov) (void)hipStreamWaitEvent(s, rejoin, 0);
     launch_advance_cursor(a.w.cnt, a.chunk, s);
 }
 
@@ -293,7 +316,7 @@ int run_graph(sdm_context *ctx, const ChunkArgs<R> &a, uint64_t n_chunks, hipStr
         }
         hipGraph_t g = nullptr;
         HIPCHK(ctx, hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
-        enqueue_chunk<R>(a, ctx->gstream, nullptr);
+        enqueue_chunk<R>(a, ctx->gstream, ctx->side, ctx->fork, ctx->rejoin, nullptr);
         HIPCHK(ctx, hipStreamEndCapture(ctx->gstream, &g));
         const hipError_t e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -611,10 +634,13 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         a.grid_st = ctx->num_cu * (shadow_bpc > 0 ? std::min(shadow_bpc, occ_s) : grid_walk ? std::min(4, occ_s) : occ_s);
         a.grid_a = ctx->num_cu * occupancy<R>(SDM_K_SHADOW_ACCUM);
         a.grid_g = (int)std::max<uint64_t>(1, std::min<uint64_t>((chunk + 255) / 256, 8ull * ctx->num_cu));
-        const size_t gthreads = std::max((size_t)a.grid_t * trace_block_size(), (size_t)a.grid_st * block_size());
+        // overflow stacks: the closest-hit passes' (and the photon pass's),
+        // then the shadow walk's, which may run beside them
+        const size_t gt_threads = (size_t)a.grid_t * trace_block_size(), gs_threads = (size_t)a.grid_st * block_size();
         int stack = 0;
         for (const auto &jj : jobs) stack = std::max({stack, jj.sc->stack, jj.sc->dd_stack});
-        HIPCHK(ctx, ctx->gstack.ensure(gthreads * global_stack_levels(stack) * sizeof(int32_t)));
+        const size_t levels = (size_t)global_stack_levels(stack);
+        HIPCHK(ctx, ctx->gstack.ensure((gt_threads + gs_threads) * levels * sizeof(int32_t)));
         Work<R> &w = a.w;
         char *pb = nullptr;
         auto take = [&](size_t bytes) { char *r = pb; pb += (bytes + 255) / 256 * 256; return r; };
@@ -660,6 +686,7 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         w.cap = cap;
         w.nbmax = nb;
         w.gstack = ctx->gstack.as<int32_t>();
+        w.gstack_sh = w.gstack + gt_threads * levels;
         w.sig = want_sig ? ctx->sig.as<unsigned long long>() : nullptr;
         a.jobs = ctx->jobs.as<JobDev>();
         a.bands = ctx->bands.as<BandDev>();
@@ -684,6 +711,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
             if (!inside) a.cam_fused = 0;
         }
         a.surr = surr;
+        // signatures read the hits a concurrent closest-hit pass would overwrite
+        a.overlap = ctx->overlap && !want_sig ? 1 : 0;
         a.bubbly = bubbly;
         a.prec = sizeof(R) == 8;
         if (surr) {
@@ -717,7 +746,8 @@ int render_jobs(sdm_context *ctx, const std::vector<JobIn> &jobs, sdm_stats *sta
         } else if (graph) {
             if (int rc = run_graph<R>(ctx, a, n_chunks, s)) return rc;
         } else {
-            for (uint64_t c = 0; c < n_chunks; ++c) enqueue_chunk<R>(a, s, timing ? &tm : nullptr);
+            for (uint64_t c = 0; c < n_chunks; ++c)
+                enqueue_chunk<R>(a, s, ctx->side, ctx->fork, ctx->rejoin, timing ? &tm : nullptr);
         }
         HIPCHK(ctx, hipGetLastError());
         // finalize every job into device outputs (or staging for host outputs)

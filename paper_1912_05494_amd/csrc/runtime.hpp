@@ -81,6 +81,12 @@ struct sdm_context {
     // default priority), cached while its launch arguments stay the same
     hipStream_t gstream = nullptr;
     hipEvent_t join[2] = {nullptr, nullptr};
+    // the second stream of a chunk's sequence: a bounce's shadow walk and
+    // accumulation run on it beside the next bounce's closest-hit pass
+    // (default priority); fork / rejoin order the two streams
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, rejoin = nullptr;
+    bool overlap = true;        // false with SDM_SERIAL=1 at context creation
     hipGraphExec_t gexec = nullptr;
     std::vector<unsigned char> gkey;
     // event signatures of a render (debug; sized like acc)
@@ -118,9 +124,10 @@ struct sdm_scene {
     sdm_context *ctx = nullptr;
     sdm::SceneDev dev{};
     DevBuf nodes, tris, thick, mat_type, mat_thick, mat_bub, orig_to_leaf, tab_x, tab_mat, tab_sun, tab_sky;
-    DevBuf g_start, g_cand;     // sun grid (empty when shadow rays walk the BVH)
+    DevBuf tris_rot;            // tris rotated into the three frames of the FP32 triangle test
+    DevBuf g_start, g_cand, g_cand_rot;   // sun grid (empty when shadow rays walk the BVH)
     DevBuf mat_map, map_hdr, map_mat, map_thick, tri_uv;   // distribution maps
-    DevBuf dd_cells, dd_nodes, dd_tris, dd_leaf;           // geometric sub-domains
+    DevBuf dd_cells, dd_nodes, dd_tris, dd_tris_rot, dd_leaf;   // geometric sub-domains
     int32_t dd_n[3] = {1, 1, 1};
     int64_t dd_refs = 0, dd_nodes_n = 0;                   // triangle references and nodes of the cells
     int32_t dd_stack = 0;

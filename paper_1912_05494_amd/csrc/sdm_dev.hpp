@@ -252,46 +252,50 @@ __device__ __forceinline__ bool tri_hit(V3<R> o, V3<R> d, V3<R> p0, V3<R> p1, V3
 
 // Watertight test for FP32 (Woop, Benthin and Wald, "Watertight
 // Ray/Triangle Intersection", JCGT 2013).  The ray is sheared so that it
-// runs along +z through the origin: kz is the axis where |d| is largest, kx
-// and ky the two others (swapped when d[kz] < 0, which keeps the winding),
-// and a point p - o maps to (p[kx] - sx p[kz], p[ky] - sy p[kz], sz p[kz])
-// with (sx, sy, sz) = (d[kx], d[ky], 1) / d[kz].  A vertex maps to the same
-// floats in every triangle that holds it, and each edge function a.x b.y -
-// a.y b.x is evaluated without fused multiply-adds, so the triangle on the
+// runs along +z through the origin: kz is the axis where |d| is largest and
+// (kx, ky) = (kz + 1, kz + 2) mod 3, and a point p - o maps to (p[kx] - sx
+// p[kz], p[ky] - sy p[kz], sz p[kz]) with (sx, sy, sz) = (d[kx], d[ky], 1) /
+// d[kz].  The published test swaps kx and ky when d[kz] < 0 to keep the
+// winding; that swap negates U, V, W, det and T exactly (each is a sum of
+// products of the swapped coordinates, and rounding is symmetric in sign), so
+// without it the accepted rays and t, u, v are the same.  A vertex maps to the
+// same floats in every triangle that holds it, and each edge function a.x b.y
+// - a.y b.x is evaluated without fused multiply-adds, so the triangle on the
 // other side of a shared edge computes exactly its negation: a ray is never
 // rejected by both (no crack between neighbours), and a ray on the edge
 // (value 0) is accepted by both, the closest-hit tie rule then picking one.
 // Rounding is monotone, so near a shared vertex the signs are those of an
 // exact point and one triangle of the fan accepts.
+//
+// The test reads vertices in the ray's frame, (p[kx], p[ky], p[kz]): the
+// traversal kernels read them so from a copy of the triangles rotated by kz
+// (rot_frame, applied once per scene), which spares the per-lane selection
+// of the three coordinates of each vertex; o is the ray origin in that frame.
 template <class R>
 struct Shear {
     R sx, sy, sz;
-    uint32_t kx, ky, kz;
+    uint32_t kz;
+    V3<R> o;
 };
 
+// p in the frame of axis kz: (p[kz + 1], p[kz + 2], p[kz]), indices mod 3.
 template <class R>
-__device__ __forceinline__ R comp(V3<R> a, uint32_t k)
+__device__ __forceinline__ V3<R> rot_frame(V3<R> p, uint32_t kz)
 {
-    return k == 0 ? a.x : (k == 1 ? a.y : a.z);
+    return kz == 0u ? V3<R>{p.y, p.z, p.x} : (kz == 1u ? V3<R>{p.z, p.x, p.y} : V3<R>{p.x, p.y, p.z});
 }
 
 template <class R>
-__device__ __forceinline__ Shear<R> make_shear(V3<R> d)
+__device__ __forceinline__ Shear<R> make_shear(V3<R> o, V3<R> d)
 {
     const R ax = fabs(d.x), ay = fabs(d.y), az = fabs(d.z);
     Shear<R> s;
     s.kz = (ax >= ay && ax >= az) ? 0u : (ay >= az ? 1u : 2u);
-    s.kx = s.kz == 2u ? 0u : s.kz + 1u;
-    s.ky = s.kx == 2u ? 0u : s.kx + 1u;
-    const R dz = comp(d, s.kz);
-    if (dz < R(0)) {
-        const uint32_t k = s.kx;
-        s.kx = s.ky;
-        s.ky = k;
-    }
-    s.sz = R(1) / dz;
-    s.sx = comp(d, s.kx) * s.sz;
-    s.sy = comp(d, s.ky) * s.sz;
+    const V3<R> dr = rot_frame(d, s.kz);
+    s.sz = R(1) / dr.z;
+    s.sx = dr.x * s.sz;
+    s.sy = dr.y * s.sz;
+    s.o = rot_frame(o, s.kz);
     return s;
 }
 
@@ -302,16 +306,15 @@ __device__ __forceinline__ float edge_fn(float ax, float ay, float bx, float by)
     return ax * by - ay * bx;
 }
 
+// p0, p1, p2 in the ray's frame (see rot_frame).
 template <class R>
-__device__ __forceinline__ bool tri_hit_wt(V3<R> o, const Shear<R> &sh, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u,
-                                           R &v)
+__device__ __forceinline__ bool tri_hit_wt(const Shear<R> &sh, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u, R &v)
 {
     static_assert(sizeof(R) == 4, "the watertight form is the FP32 test");
-    const V3<R> a = p0 - o, b = p1 - o, c = p2 - o;
-    const R az = comp(a, sh.kz), bz = comp(b, sh.kz), cz = comp(c, sh.kz);
-    const R ax = comp(a, sh.kx) - sh.sx * az, ay = comp(a, sh.ky) - sh.sy * az;
-    const R bx = comp(b, sh.kx) - sh.sx * bz, by = comp(b, sh.ky) - sh.sy * bz;
-    const R cx = comp(c, sh.kx) - sh.sx * cz, cy = comp(c, sh.ky) - sh.sy * cz;
+    const V3<R> a = p0 - sh.o, b = p1 - sh.o, c = p2 - sh.o;
+    const R ax = a.x - sh.sx * a.z, ay = a.y - sh.sy * a.z;
+    const R bx = b.x - sh.sx * b.z, by = b.y - sh.sy * b.z;
+    const R cx = c.x - sh.sx * c.z, cy = c.y - sh.sy * c.z;
     // scaled barycentrics: U weighs p0 (edge p1 p2), V p1, W p2
     const R U = edge_fn(cx, cy, bx, by);
     const R V = edge_fn(ax, ay, cx, cy);
@@ -319,7 +322,7 @@ __device__ __forceinline__ bool tri_hit_wt(V3<R> o, const Shear<R> &sh, V3<R> p0
     if ((U < R(0) || V < R(0) || W < R(0)) && (U > R(0) || V > R(0) || W > R(0))) return false;
     const R det = U + V + W;
     if (det == R(0)) return false;
-    const R T = U * (sh.sz * az) + V * (sh.sz * bz) + W * (sh.sz * cz);
+    const R T = U * (sh.sz * a.z) + V * (sh.sz * b.z) + W * (sh.sz * c.z);
     const R sg = det < R(0) ? R(-1) : R(1), ia = R(1) / fabs(det);
     u = sg * V * ia;
     v = sg * W * ia;
@@ -346,6 +349,10 @@ __device__ __forceinline__ V3<R> safe_inv(V3<R> d)
 // Wave-level compaction: one atomic per wave per queue.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Mask of the wave's active lanes whose pred is set (the vote on the bool
+// itself, without widening it to an integer first).
+__device__ __forceinline__ uint64_t wave_ballot(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 
 // All lanes of the wave must call this together.  Returns the slot of each
 // lane with pred set (undefined for the others).

@@ -57,12 +57,19 @@ struct DdDev {
     const CellDev *cells;
     const BvhNode *nodes;
     const TriDev *tris;
+    const TriDev *tris_rot;         // [3][n_refs]: tris with vertices rotated as in SceneDev::tris_rot
     const int32_t *leaf;
+    int32_t n_refs;                 // triangle copies of all cells
 };
 
 struct SceneDev {
     const BvhNode *nodes;
     const TriDev *tris;
+    // [3][rot_n]: copy k of tris with each vertex p stored as (p[k + 1],
+    // p[k + 2], p[k]) (indices mod 3), the frame of the FP32 triangle test of
+    // rays whose dominant axis is k; w words as in tris
+    const TriDev *tris_rot;
+    int32_t rot_n;
     const float4 *thick;        // per leaf-order triangle: vertex thickness (mm)
     const int32_t *mat_type;    // [n_mat]: 0 Lambert, 1 glass, 2 bubbly glass, 3 gray Lambert
     const float *mat_thick;     // [n_mat] default thickness
@@ -75,6 +82,8 @@ struct SceneDev {
     // g_cand[g_start[c] .. g_start[c + 1]) by increasing smallest depth o.sun
     const int32_t *g_start;
     const GridCand *g_cand;
+    const GridCand *g_cand_rot;   // g_cand with vertices rotated by g_rot, the sun's dominant axis
+    int32_t g_rot;
     float g_e1[3], g_e2[3], g_u0, g_v0, g_idu, g_idv, g_marg;
     int32_t g_nx, g_ny, g_use;
     float teps_f;
@@ -282,6 +291,7 @@ struct Work {
     uint32_t cap;               // slots of each pool and of the record buffer
     int32_t nbmax;              // row length of the per-wavelength arrays (band size rounded up to 4)
     int32_t *gstack;            // traversal stack overflow (global)
+    int32_t *gstack_sh;         // the shadow walk's own (it may run beside the closest-hit pass)
     unsigned long long *sig;    // event signatures per accumulator entry (debug), or null
 };
 

@@ -260,11 +260,31 @@ struct Ray {
 };
 
 // Triangle test of a ray: watertight in FP32, Moeller-Trumbore in FP64.
+// ray_tri takes the vertices in scene coordinates; ray_tri_frame takes them
+// as test_tris lists them (in FP32 already in the ray's shear frame).
 template <class R>
 __device__ __forceinline__ bool ray_tri(const Ray<R> &ry, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u, R &v)
 {
-    if constexpr (sizeof(R) == 4) return tri_hit_wt(ry.o, ry.sh, p0, p1, p2, t, u, v);
+    if constexpr (sizeof(R) == 4)
+        return tri_hit_wt(ry.sh, rot_frame(p0, ry.sh.kz), rot_frame(p1, ry.sh.kz), rot_frame(p2, ry.sh.kz), t, u, v);
     else return tri_hit(ry.o, ry.d, p0, p1, p2, t, u, v);
+}
+
+template <class R>
+__device__ __forceinline__ bool ray_tri_frame(const Ray<R> &ry, V3<R> p0, V3<R> p1, V3<R> p2, R &t, R &u, R &v)
+{
+    if constexpr (sizeof(R) == 4) return tri_hit_wt(ry.sh, p0, p1, p2, t, u, v);
+    else return tri_hit(ry.o, ry.d, p0, p1, p2, t, u, v);
+}
+
+// The triangles a ray's test reads: in FP32 the copy whose vertices are
+// rotated into the frame of the ray's dominant axis (same w words, same
+// order), in FP64 the scene's own.
+template <class R>
+__device__ __forceinline__ const TriDev *test_tris(const SceneDev &sc, const Ray<R> &ry)
+{
+    if constexpr (sizeof(R) == 4) return sc.tris_rot + (size_t)ry.sh.kz * (size_t)sc.rot_n;
+    else return sc.tris;
 }
 
 template <class R>
@@ -277,7 +297,7 @@ __device__ __forceinline__ void set_dir(Ray<R> &ry, V3<R> o, V3<R> d)
     ry.kx = signbit(ry.inv.x) ? 16u : 0u;
     ry.ky = signbit(ry.inv.y) ? 48u : 32u;
     ry.kz = signbit(ry.inv.z) ? 80u : 64u;
-    if constexpr (sizeof(R) == 4) ry.sh = make_shear(d);
+    if constexpr (sizeof(R) == 4) ry.sh = make_shear(o, d);
 }
 
 // Distance to the plane x = b along one axis.  The fused form b * inv - o *
@@ -301,6 +321,10 @@ __device__ __forceinline__ R slab_t(float b, R o, R inv, R oi)
 // rounded plane distance is monotonic in the plane coordinate, so each
 // near-plane distance is exactly the smaller of the axis's two (and the far
 // one the larger): the same values a min/max of the pair gives.
+// Empty child slots hold inverted boxes (lower planes +inf, upper -inf), whose
+// entry distance is +inf and exit -inf for every ray, so no test of the
+// child's entry is needed (a NaN ray that took one would find a leaf of no
+// triangles).
 template <bool kFused, class R>
 __device__ __forceinline__ void box4(const WideNode &nd, const Ray<R> &ry, R tlo, R thi, R (&tn)[4],
                                      bool (&hit)[4])
@@ -314,7 +338,7 @@ __device__ __forceinline__ void box4(const WideNode &nd, const Ray<R> &ry, R tlo
         const R a = fmax(fmax(ax, ay), fmax(az, tlo));
         const R b = fmin(fmin(bx, by), fmin(bz, thi));
         tn[c] = a;
-        hit[c] = child_at(nd, c) != kNoChild && a <= b;
+        hit[c] = a <= b;
     }
 }
 
@@ -404,11 +428,12 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
             else leaf2 = cur;
             cur = st.sp ? st.pop() : kDone;
         }
-        if (!__any(leaf == kDone && cur >= 0)) break;
+        const uint64_t searching = wave_ballot(leaf == kDone && cur >= 0);
+        if (!searching) break;
         // after one round of visits (so every step advances every lane), the
         // few lanes still searching resume in the next step rather than hold
         // the wave's leaf tests back
-        if (visited && __popcll(__ballot(leaf == kDone && cur >= 0)) < kDescentLanes) break;
+        if (visited && __popcll(searching) < kDescentLanes) break;
         visited = true;
         if (cur >= 0) {
             const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur, ry.kx, ry.ky, ry.kz);
@@ -431,14 +456,15 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
         const int32_t ca = leaf != kDone ? -1 - leaf : 0, cb = leaf2 != kDone ? -1 - leaf2 : 0;
         const int fa = ca >> 8, na = ca & 255, fb = cb >> 8, nb = cb & 255;
         tests += (uint32_t)(na + nb);
+        const TriDev *tt = test_tris(sc, ry);
         for (int k = 0; k < na + nb; ++k) {
             const int i = k < na ? fa + k : fb + (k - na);
             if (!kSkipCaller && i == ry.skip) continue;
-            const TriDev tr = load_tri(sc.tris, i);
+            const TriDev tr = load_tri(tt, i);
             const int32_t orig = __float_as_int(tr.a.w);
             if (kSkipCaller && orig == ry.skip) continue;
             R t, u, v;
-            if (!ray_tri(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
+            if (!ray_tri_frame(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
             if (!(t > teps)) continue;
             if (t < h.tb || (t == h.tb && orig < h.orig_b)) {
                 h.tb = t; h.trib = i; h.ub = u; h.vb = v; h.orig_b = orig;
@@ -466,7 +492,7 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
             leaf = cur;
             cur = st.sp ? st.pop() : kDone;
         }
-        if (!__any(leaf == kDone && cur >= 0)) break;
+        if (!wave_ballot(leaf == kDone && cur >= 0)) break;
         if (cur >= 0) {
             const WideNode nd = load_node(lds_nodes, n_lds, sc.nodes, cur, ry.kx, ry.ky, ry.kz);
             ++nodes;
@@ -489,11 +515,12 @@ __device__ __forceinline__ bool shadow_step(const SceneDev &sc, const float4 *ld
         const int32_t code = -1 - leaf;
         const int first = code >> 8, cnt = code & 255;
         tests += (uint32_t)cnt;
+        const TriDev *tt = test_tris(sc, ry);
         for (int i = first; i < first + cnt; ++i) {
             if (i == ry.skip) continue;
-            const TriDev tr = load_tri(sc.tris, i);
+            const TriDev tr = load_tri(tt, i);
             R t, u, v;
-            if (!ray_tri(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
+            if (!ray_tri_frame(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
             if (!(t > teps)) continue;
             const int mt = __float_as_int(tr.c.w);
             if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
@@ -544,15 +571,23 @@ __device__ __forceinline__ bool grid_step(const SceneDev &sc, const Ray<R> &ry, 
                                           R teps, F &&on_glass, uint32_t &cands, uint32_t &tests)
 {
     const uint32_t stop = min(g.end, g.cur + kGridBatch);
+    // FP32 reads the candidates rotated into the frame of the sun's dominant
+    // axis, the frame of every shadow ray's test (the scene's other rays
+    // never walk the grid)
+    bool framed = false;
+    if constexpr (sizeof(R) == 4) framed = ry.sh.kz == (uint32_t)sc.g_rot;
+    const GridCand *cand = framed ? sc.g_cand_rot : sc.g_cand;
     for (; g.cur < stop; ++g.cur) {
-        const float4 *cp = reinterpret_cast<const float4 *>(sc.g_cand) + 3 * (size_t)g.cur;
+        const float4 *cp = reinterpret_cast<const float4 *>(cand) + 3 * (size_t)g.cur;
         const float4 A = gld4(cp), B = gld4(cp + 1), C = gld4(cp + 2);
         ++cands;
         const int leaf = __float_as_int(A.w);
         if (R(B.w) < g.depth || leaf == ry.skip) continue;
         ++tests;
         R t, u, v;
-        if (!ray_tri(ry, from4<R>(A), from4<R>(B), from4<R>(C), t, u, v)) continue;
+        if (!(framed ? ray_tri_frame(ry, from4<R>(A), from4<R>(B), from4<R>(C), t, u, v)
+                     : ray_tri(ry, from4<R>(A), from4<R>(B), from4<R>(C), t, u, v)))
+            continue;
         if (!(t > teps)) continue;
         const int mw = __float_as_int(C.w), mt = mw & 3;
         if (mt == 0 || mt == 3) {   // Lambert (spectral or gray): opaque
@@ -677,7 +712,7 @@ __global__ void __launch_bounds__(kBlock) k_generate(const JobDev *__restrict__ 
         w.cnt->count[0] = n;
         w.cnt->ddn[1] = 0;      // the first sub-domain pass's output queue
         w.cnt->count[1] = 0;
-        w.cnt->scount = 0;
+        w.cnt->scount = w.cnt->kcount = w.cnt->gcount = w.cnt->bcount = 0;
     }
     const Pool<R> P = w.p[0];
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -734,10 +769,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(const JobDev *__restrict_
     const uint32_t count = min(w.cnt->count[cur], w.cap);   // the counter may pass cap on overflow
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.cnt->count[cur ^ 1] = 0;
-        w.cnt->scount = 0;
-        w.cnt->kcount = 0;
-        w.cnt->gcount = 0;
-        w.cnt->bcount = 0;
         w.cnt->closest += count;
     }
     const int n_lds = lds_job >= 0 ? stage_nodes(s_nodes, jobs[lds_job].sc, kTraceNodes) : 0;
@@ -841,10 +872,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
         n_in = min(w.cnt->count[cur], w.cap);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             w.cnt->count[cur ^ 1] = 0;
-            w.cnt->scount = 0;
-            w.cnt->kcount = 0;
-            w.cnt->gcount = 0;
-            w.cnt->bcount = 0;
             w.cnt->closest += n_in;
             w.cnt->ddn[2] = 0;
         }
@@ -860,6 +887,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
     Ray<R> ry;
     Closest<R> h;
     SceneDev cv = sc;            // the current cell's tree in the scene's place
+    cv.rot_n = dd.n_refs;        // the cells' rotated copies are dd.n_refs apart
     int64_t item = -1;
     uint32_t slot = 0;
     int32_t cell = -1;
@@ -911,6 +939,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
                 h.tb = t1;     // only hits before the ray leaves the cell
                 cv.nodes = dd.nodes + c.node_base;
                 cv.tris = dd.tris + c.tri_base;
+                cv.tris_rot = dd.tris_rot + c.tri_base;
                 cv.n_nodes = c.n_nodes;
                 ry.cur = c.n_nodes > 0 ? 0 : kDone;
             }
@@ -947,6 +976,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
                     h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
                     cv.nodes = dd.nodes + c.node_base;
                     cv.tris = dd.tris + c.tri_base;
+                    cv.tris_rot = dd.tris_rot + c.tri_base;
                     cv.n_nodes = c.n_nodes;
                     st.sp = 0;
                     ry.cur = c.n_nodes > 0 ? 0 : kDone;
@@ -2335,7 +2365,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
     if (blockIdx.x == 0 && threadIdx.x == 0) w.cnt->shadow += count;
     // a scene whose shadow rays use the sun grid needs no BVH prefix
     const int n_lds = lds_job >= 0 && !jobs[lds_job].sc.g_use ? stage_nodes(s_nodes, jobs[lds_job].sc) : 0;
-    Stack st = make_stack(s_stack, w.gstack);
+    Stack st = make_stack(s_stack, w.gstack_sh);
     WaveFeed feed{0, 0, false, 0};
     Ray<R> ry;
     GridRange<R> gr{0, 0, R(0)};
@@ -2356,7 +2386,7 @@ __global__ void __launch_bounds__(kBlock) k_shadow_trace(const JobDev *__restric
             if (grid) {   // the candidate walk needs no slab setup, only the triangle test's shear
                 ry.o = o;
                 ry.d = d;
-                if constexpr (sizeof(R) == 4) ry.sh = make_shear(d);
+                if constexpr (sizeof(R) == 4) ry.sh = make_shear(o, d);
                 gr = grid_range(sc, o);
             } else {
                 set_dir(ry, o, d);
@@ -2761,6 +2791,14 @@ __global__ void k_advance_cursor(Counters *c, uint32_t chunk)
     if (threadIdx.x == 0 && blockIdx.x == 0) c->r0 += chunk;
 }
 
+// The record queues of a bounce (shadow, sky, glass and bubbly vertices)
+// emptied for the next one, after their last reader: the closest-hit pass of
+// the next bounce may run meanwhile, so it cannot clear them itself.
+__global__ void k_reset_records(Counters *c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) c->scount = c->kcount = c->gcount = c->bcount = 0;
+}
+
 __global__ void k_zero_counters(Counters *c)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -3072,6 +3110,10 @@ void launch_advance_cursor(Counters *c, uint32_t chunk, hipStream_t s)
 void launch_zero_counters(Counters *c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, c);
+}
+void launch_reset_records(Counters *c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_records, dim3(1), dim3(64), 0, s, c);
 }
 void launch_slab_eval(int64_t m, const float *c, const float *lam, const float *d, const float *n, const float *k,
                       const float *tint, float *R, float *T, hipStream_t s)

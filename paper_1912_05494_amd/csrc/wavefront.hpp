@@ -58,6 +58,7 @@ void launch_finalize(const double *acc, int64_t npix, int nl, int spp, const dou
 void launch_zero_f64(double *a, int64_t n, hipStream_t s);
 void launch_zero_counters(Counters *c, hipStream_t s);
 void launch_advance_cursor(Counters *c, uint32_t chunk, hipStream_t s);
+void launch_reset_records(Counters *c, hipStream_t s);
 void launch_slab_eval(int64_t m, const float *c, const float *lam, const float *d, const float *n, const float *k,
                       const float *tint, float *R, float *T, hipStream_t s);
 void launch_debug_intersect(const SceneDev &sc, uint32_t m, const float *o, const float *d, const int32_t *skip,

@@ -501,8 +501,6 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         chk(upload(sc->dd_cells, sub.cells.data(), sub.cells.size()));
         chk(upload(sc->dd_nodes, sub.nodes.data(), std::max<size_t>(1, sub.nodes.size())));
         chk(upload(sc->dd_tris, sub.tris.data(), std::max<size_t>(1, sub.tris.size())));
-        const std::vector<TriDev> rt = rotated_copies(sub.tris.data(), sub.tris.size(), {0, 1, 2});
-        chk(upload(sc->dd_tris_rot, rt.data(), rt.size()));
         chk(upload(sc->dd_leaf, sub.leaf.data(), std::max<size_t>(1, sub.leaf.size())));
         for (int a = 0; a < 3; ++a) sc->dd_n[a] = dd_n[a];
         sc->dd_refs = (int64_t)sub.tris.size();
@@ -566,8 +564,6 @@ int sdm_scene_create(sdm_context *ctx, const sdm_scene_desc *d, sdm_scene **out)
         sd.dd.cells = sc->dd_cells.as<CellDev>();
         sd.dd.nodes = sc->dd_nodes.as<BvhNode>();
         sd.dd.tris = sc->dd_tris.as<TriDev>();
-        sd.dd.tris_rot = sc->dd_tris_rot.as<TriDev>();
-        sd.dd.n_refs = (int32_t)sub.tris.size();
         sd.dd.leaf = sc->dd_leaf.as<int32_t>();
     }
     sd.n_maps = any_map ? d->n_maps : 0;

@@ -127,7 +127,7 @@ struct sdm_scene {
     DevBuf tris_rot;            // tris rotated into the three frames of the FP32 triangle test
     DevBuf g_start, g_cand, g_cand_rot;   // sun grid (empty when shadow rays walk the BVH)
     DevBuf mat_map, map_hdr, map_mat, map_thick, tri_uv;   // distribution maps
-    DevBuf dd_cells, dd_nodes, dd_tris, dd_tris_rot, dd_leaf;   // geometric sub-domains
+    DevBuf dd_cells, dd_nodes, dd_tris, dd_leaf;           // geometric sub-domains
     int32_t dd_n[3] = {1, 1, 1};
     int64_t dd_refs = 0, dd_nodes_n = 0;                   // triangle references and nodes of the cells
     int32_t dd_stack = 0;

@@ -57,9 +57,7 @@ struct DdDev {
     const CellDev *cells;
     const BvhNode *nodes;
     const TriDev *tris;
-    const TriDev *tris_rot;         // [3][n_refs]: tris with vertices rotated as in SceneDev::tris_rot
     const int32_t *leaf;
-    int32_t n_refs;                 // triangle copies of all cells
 };
 
 struct SceneDev {

@@ -456,7 +456,11 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
         const int32_t ca = leaf != kDone ? -1 - leaf : 0, cb = leaf2 != kDone ? -1 - leaf2 : 0;
         const int fa = ca >> 8, na = ca & 255, fb = cb >> 8, nb = cb & 255;
         tests += (uint32_t)(na + nb);
-        const TriDev *tt = test_tris(sc, ry);
+        // a sub-domain cell's walk reads its cell's copies in scene coordinates:
+        // rotated copies of every cell's triangles would triple a footprint
+        // that is already spread over many cells, which costs more in cache
+        // misses than the per-lane coordinate selection saves
+        const TriDev *tt = kSkipCaller ? sc.tris : test_tris(sc, ry);
         for (int k = 0; k < na + nb; ++k) {
             const int i = k < na ? fa + k : fb + (k - na);
             if (!kSkipCaller && i == ry.skip) continue;
@@ -464,7 +468,9 @@ __device__ __forceinline__ bool closest_step(const SceneDev &sc, const float4 *l
             const int32_t orig = __float_as_int(tr.a.w);
             if (kSkipCaller && orig == ry.skip) continue;
             R t, u, v;
-            if (!ray_tri_frame(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)) continue;
+            if (!(kSkipCaller ? ray_tri(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)
+                              : ray_tri_frame(ry, from4<R>(tr.a), from4<R>(tr.b), from4<R>(tr.c), t, u, v)))
+                continue;
             if (!(t > teps)) continue;
             if (t < h.tb || (t == h.tb && orig < h.orig_b)) {
                 h.tb = t; h.trib = i; h.ub = u; h.vb = v; h.orig_b = orig;
@@ -887,7 +893,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
     Ray<R> ry;
     Closest<R> h;
     SceneDev cv = sc;            // the current cell's tree in the scene's place
-    cv.rot_n = dd.n_refs;        // the cells' rotated copies are dd.n_refs apart
     int64_t item = -1;
     uint32_t slot = 0;
     int32_t cell = -1;
@@ -939,7 +944,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
                 h.tb = t1;     // only hits before the ray leaves the cell
                 cv.nodes = dd.nodes + c.node_base;
                 cv.tris = dd.tris + c.tri_base;
-                cv.tris_rot = dd.tris_rot + c.tri_base;
                 cv.n_nodes = c.n_nodes;
                 ry.cur = c.n_nodes > 0 ? 0 : kDone;
             }
@@ -976,7 +980,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_dd_sweep(const JobDev *__restri
                     h.ub = h.vb = R(0); h.trib = -1; h.orig_b = INT_MAX;
                     cv.nodes = dd.nodes + c.node_base;
                     cv.tris = dd.tris + c.tri_base;
-                    cv.tris_rot = dd.tris_rot + c.tri_base;
                     cv.n_nodes = c.n_nodes;
                     st.sp = 0;
                     ry.cur = c.n_nodes > 0 ? 0 : kDone;

@@ -231,6 +231,7 @@ def cpu_table1(threads=(1, 2, 4, 8, 16), bands=(1, 2, 4, 8), W=48, H=36, spp=4, 
             elif not np.array_equal(img, ref):
                 raise AssertionError(f"image differs at {t} threads, {nb} bands")
             times[(nb, t)] = best
+            print(f"table1: {nb} band(s), {t} thread(s): {best:.2f} s", file=sys.stderr, flush=True)
     base = times[(bands[0], threads[0])]
     return {"speedup": {str(nb): {str(t): base / times[(nb, t)] for t in threads} for nb in bands},
             "seconds": {str(nb): {str(t): times[(nb, t)] for t in threads} for nb in bands},
